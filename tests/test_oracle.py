@@ -1,0 +1,368 @@
+"""Pins for the CPU oracle: each check comes from mathematics or physics that the oracle's
+own code does not restate (closed forms, quadrature, limits, invariances, brute force), so
+that a dropped term, a wrong sign, a wrong index or a transposed operand fails one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.special import erf
+
+from he_inputs import HE_STO3G_COEFS as C3, HE_STO3G_EXPS as E3, random_cluster, config_system
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+# ------------------------------------------------------------------ Boys function
+
+T_GRID = [0.0, 1e-12, 1e-8, 1e-3, 0.1, 0.5, 1.0, 2.5, 5.0, 10.0, 20.0, 33.0, 40.0, 60.0, 99.0, 150.0]
+
+
+def _boys_quad(m, t):
+    """F_m(t) = int_0^1 u^(2m) exp(-t u^2) du by adaptive quadrature."""
+    v, _ = integrate.quad(lambda u: u ** (2 * m) * math.exp(-t * u * u), 0.0, 1.0,
+                          epsabs=0.0, epsrel=2e-14, limit=200)
+    return v
+
+
+@pytest.mark.parametrize("m", [0, 1, 2, 3])
+def test_boys_series_matches_quadrature(oracle_lib, m):
+    for t in T_GRID:
+        ref = _boys_quad(m, t)
+        got = oracle_lib.boys_series(m, t)
+        assert abs(got - ref) <= 2e-14 * ref, (m, t, got, ref)
+
+
+def test_boys_at_zero(oracle_lib):
+    for m in range(6):
+        assert oracle_lib.boys_series(m, 0.0) == pytest.approx(1.0 / (2 * m + 1), rel=1e-16)
+    assert oracle_lib.boys0(0.0) == 1.0
+    assert oracle_lib.boys1(0.0) == pytest.approx(1.0 / 3.0, rel=1e-16)
+
+
+def test_boys0_closed_form_vs_series(oracle_lib):
+    # F0(t) = (1/2) sqrt(pi/t) erf(sqrt t) against the positive series.
+    for t in T_GRID[1:]:
+        s = oracle_lib.boys_series(0, t)
+        c = 0.5 * math.sqrt(math.pi / t) * math.erf(math.sqrt(t))
+        assert abs(oracle_lib.boys0(t) - s) <= 3e-15 * s
+        assert abs(c - s) <= 3e-15 * s
+
+
+def test_boys_downward_recursion(oracle_lib):
+    # (2m+1) F_m = 2 t F_{m+1} + exp(-t), from integrating u^(2m) exp(-t u^2) by parts.
+    for t in T_GRID:
+        for m in range(4):
+            lhs = (2 * m + 1) * oracle_lib.boys_series(m, t)
+            rhs = 2 * t * oracle_lib.boys_series(m + 1, t) + math.exp(-t)
+            assert abs(lhs - rhs) <= 1e-14 * lhs, (t, m)
+
+
+def test_boys1_hybrid_matches_series(oracle_lib):
+    for t in T_GRID + [0.99999, 1.0, 1.00001, 3.7, 12.3]:
+        s = oracle_lib.boys_series(1, t)
+        assert abs(oracle_lib.boys1(t) - s) <= 5e-15 * s, t
+
+
+def test_boys_large_t_limit(oracle_lib):
+    for t in (50.0, 100.0, 200.0, 1e4):
+        assert oracle_lib.boys0(t) == pytest.approx(0.5 * math.sqrt(math.pi / t), rel=1e-15)
+
+
+# ------------------------------------------------------------------ integrals
+
+def _norm_prim(a):
+    return (2.0 * a / math.pi) ** 0.75
+
+
+def test_overlap_matches_quadrature(oracle_lib):
+    """<phi_A|phi_B> factorises into three 1-D Gaussian integrals; integrate them numerically."""
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        A = rng.uniform(-2, 2, 3)
+        B = A + rng.uniform(-2, 2, 3)
+        ref = 0.0
+        for a, ca in zip(E3, C3):
+            for b, cb in zip(E3, C3):
+                prod = ca * cb * _norm_prim(a) * _norm_prim(b)
+                for x in range(3):
+                    v, _ = integrate.quad(lambda s: math.exp(-a * (s - A[x]) ** 2 - b * (s - B[x]) ** 2),
+                                          -40, 40, epsabs=0, epsrel=1e-13, limit=400,
+                                          points=[A[x], B[x]])
+                    prod *= v
+                ref += prod
+        assert oracle_lib.overlap(A, B, E3, C3) == pytest.approx(ref, rel=1e-12)
+
+
+def test_he_sto3g_self_overlap(oracle_lib):
+    # Normalised primitives, coefficients as given: S_ii is 1 to the basis' 8 printed digits.
+    assert oracle_lib.overlap(np.zeros(3), np.zeros(3), E3, C3) == pytest.approx(1.0, abs=1e-8)
+
+
+@pytest.mark.parametrize("alpha", [0.3, 1.0, 6.5])
+def test_single_gaussian_self_repulsion(oracle_lib, alpha):
+    """|g|^2 of a normalised s Gaussian is a unit Gaussian charge with exponent 2 alpha;
+    its Coulomb self energy is sqrt(2 * 2alpha / pi) = 2 sqrt(alpha / pi)."""
+    A = np.array([0.3, -1.2, 2.0])
+    got = oracle_lib.eri(A, A, A, A, [alpha], [1.0])
+    assert got == pytest.approx(2.0 * math.sqrt(alpha / math.pi), rel=1e-14)
+
+
+@pytest.mark.parametrize("R", [0.0, 1e-4, 0.3, 1.0, 2.0, 5.0, 9.0])
+@pytest.mark.parametrize("a", [0.4, 1.3])
+def test_two_gaussian_charges(oracle_lib, R, a):
+    """(AA|BB) for one normalised primitive of exponent a: g_a^2 is a unit Gaussian charge of
+    exponent 2a, and two such charges R apart interact as erf(sqrt(a) R) / R (reduced
+    exponent (2a)(2a)/(4a) = a), tending to 2 sqrt(a/pi) as R -> 0."""
+    A = np.array([0.1, 0.2, -0.4])
+    d = np.array([1.0, -2.0, 0.5])
+    B = A + R * d / np.linalg.norm(d)
+    ref = 2.0 * math.sqrt(a / math.pi) if R == 0 else erf(math.sqrt(a) * R) / R
+    got = oracle_lib.eri(A, A, B, B, [a], [1.0])
+    assert got == pytest.approx(ref, rel=1e-13, abs=1e-15)
+
+
+def test_contracted_far_field_limit(oracle_lib):
+    """Far apart, (ii|jj) -> S_ii S_jj / R (point charges)."""
+    A = np.zeros(3)
+    for R in (30.0, 60.0):
+        B = np.array([0.0, 0.0, R])
+        s = oracle_lib.overlap(A, A, E3, C3)
+        assert oracle_lib.eri(A, A, B, B, E3, C3) == pytest.approx(s * s / R, rel=1e-14)
+
+
+def test_contracted_coincident_value(oracle_lib):
+    # STO-3G He (ii|ii): every primitive quartet at T = 0.
+    ref = 0.0
+    w = C3 * (2 * E3 / math.pi) ** 0.75
+    for a in range(3):
+        for b in range(3):
+            for c in range(3):
+                for d in range(3):
+                    p = E3[a] + E3[b]
+                    q = E3[c] + E3[d]
+                    # charge of each Gaussian product times the self-energy kernel of two
+                    # spherical Gaussian charges at the same centre: 2 sqrt(rho/pi)
+                    sab = w[a] * w[b] * (math.pi / p) ** 1.5
+                    scd = w[c] * w[d] * (math.pi / q) ** 1.5
+                    rho = p * q / (p + q)
+                    ref += sab * scd * 2.0 * math.sqrt(rho / math.pi)
+    got = oracle_lib.eri(np.zeros(3), np.zeros(3), np.zeros(3), np.zeros(3), E3, C3)
+    assert got == pytest.approx(ref, rel=1e-14)
+    assert got == pytest.approx(1.0557129304699764, rel=1e-13)
+
+
+def test_gaussian_charge_form_general_quartet(oracle_lib):
+    """Each primitive (ab|cd) equals S_ab S_cd erf(sqrt(rho) |P-Q|) / |P-Q| (two spherical
+    Gaussian charge clouds); the oracle goes through 2 pi^(5/2)/(pq sqrt(p+q)) K K F0(T)."""
+    rng = np.random.default_rng(5)
+    w = C3 * (2 * E3 / math.pi) ** 0.75
+    for _ in range(5):
+        X = rng.uniform(-2.5, 2.5, (4, 3))
+        ref = 0.0
+        for a in range(3):
+            for b in range(3):
+                p = E3[a] + E3[b]
+                P = (E3[a] * X[0] + E3[b] * X[1]) / p
+                sab = w[a] * w[b] * (math.pi / p) ** 1.5 * math.exp(-E3[a] * E3[b] / p * np.sum((X[0] - X[1]) ** 2))
+                for c in range(3):
+                    for d in range(3):
+                        q = E3[c] + E3[d]
+                        Q = (E3[c] * X[2] + E3[d] * X[3]) / q
+                        scd = w[c] * w[d] * (math.pi / q) ** 1.5 * math.exp(-E3[c] * E3[d] / q * np.sum((X[2] - X[3]) ** 2))
+                        rho = p * q / (p + q)
+                        r = np.linalg.norm(P - Q)
+                        ref += sab * scd * (2 * math.sqrt(rho / math.pi) if r < 1e-12 else erf(math.sqrt(rho) * r) / r)
+        got = oracle_lib.eri(X[0], X[1], X[2], X[3], E3, C3)
+        assert got == pytest.approx(ref, rel=1e-13)
+
+
+def test_eightfold_symmetry(oracle_lib):
+    rng = np.random.default_rng(3)
+    A, B, C, D = rng.uniform(-2, 2, (4, 3))
+    ref = oracle_lib.eri(A, B, C, D, E3, C3)
+    for perm in [(B, A, C, D), (A, B, D, C), (B, A, D, C), (C, D, A, B), (D, C, A, B), (C, D, B, A), (D, C, B, A)]:
+        assert oracle_lib.eri(*perm, E3, C3) == pytest.approx(ref, rel=1e-14)
+    # and it is not symmetric under a swap across bra and ket (ik|jl)
+    assert abs(oracle_lib.eri(A, C, B, D, E3, C3) - ref) > 1e-6 * ref
+
+
+def test_schwarz_bounds_all_quartets(oracle_lib):
+    s = random_cluster(5, 21, box=5.0)
+    Q = oracle_lib.schwarz(s.xyz, E3, C3)
+    n = s.natoms
+    def q(i, j):
+        i, j = max(i, j), min(i, j)
+        return Q[i * (i + 1) // 2 + j]
+    for i in range(n):
+        for j in range(n):
+            assert q(i, j) ** 2 == pytest.approx(oracle_lib.eri(s.xyz[i], s.xyz[j], s.xyz[i], s.xyz[j], E3, C3), rel=1e-14)
+            for k in range(n):
+                for l in range(n):
+                    v = oracle_lib.eri(s.xyz[i], s.xyz[j], s.xyz[k], s.xyz[l], E3, C3)
+                    assert abs(v) <= q(i, j) * q(k, l) * (1 + 1e-13)
+
+
+# ------------------------------------------------------------------ Fock build
+
+@pytest.mark.parametrize("n,seed,box,tau", [(1, 1, 1.0, 0.0), (2, 2, 3.0, 0.0), (4, 3, 4.0, 0.0),
+                                            (5, 4, 4.0, 0.0), (6, 5, 9.0, 1e-4), (6, 6, 12.0, 1e-6)])
+def test_unique_scatter_equals_plain_definition(oracle_lib, n, seed, box, tau):
+    s = random_cluster(n, seed, box=box)
+    Fb, Eb = oracle_lib.fock_bruteforce(s.xyz, s.dens, E3, C3, tau)
+    Fu, Eu, ns = oracle_lib.fock(s.xyz, s.dens, E3, C3, tau)
+    scale = np.abs(Fb).max()
+    assert np.abs(Fu - Fb).max() <= 1e-14 * scale
+    assert Eu == pytest.approx(Eb, rel=1e-14)
+    assert np.array_equal(Fu, Fu.T)
+    P = n * (n + 1) // 2
+    Q = oracle_lib.schwarz(s.xyz, E3, C3)
+    kept = sum(1 for a in range(P) for b in range(a + 1) if Q[a] * Q[b] >= tau)
+    assert ns == kept
+    if tau > 0:
+        assert kept < P * (P + 1) // 2  # the screen removed something
+
+
+def test_screening_changes_result_consistently(oracle_lib):
+    s = random_cluster(6, 6, box=12.0)
+    F0, _, n0 = oracle_lib.fock(s.xyz, s.dens, E3, C3, 0.0)
+    F1, _, n1 = oracle_lib.fock(s.xyz, s.dens, E3, C3, 1e-6)
+    assert n1 < n0
+    assert 0 < np.abs(F1 - F0).max() < 1e-5
+
+
+def test_single_atom(oracle_lib):
+    # G_11 = D_11 [(11|11) - 1/2 (11|11)]
+    xyz = np.array([[0.2, 0.1, -0.3]])
+    D = np.array([[0.8]])
+    F, E2, _ = oracle_lib.fock(xyz, D, E3, C3, 0.0)
+    j = 1.0557129304699764
+    assert F[0, 0] == pytest.approx(0.5 * 0.8 * j, rel=1e-13)
+    assert E2 == pytest.approx(0.5 * 0.8 * 0.5 * 0.8 * j, rel=1e-13)
+
+
+def test_two_distant_atoms(oracle_lib):
+    """Two atoms 40 bohr apart: the overlap pair is screened away, leaving Coulomb between
+    the atoms as S^2/R point charges and the on-site halves."""
+    R = 40.0
+    xyz = np.array([[0.0, 0.0, 0.0], [0.0, R, 0.0]])
+    D = np.array([[1.0, 0.3], [0.3, 0.7]])
+    F, E2, _ = oracle_lib.fock(xyz, D, E3, C3, 1e-12)
+    j = 1.0557129304699764
+    s = oracle_lib.overlap(xyz[0], xyz[0], E3, C3)
+    jab = s * s / R
+    assert F[0, 0] == pytest.approx(0.5 * D[0, 0] * j + D[1, 1] * jab, rel=1e-13)
+    assert F[1, 1] == pytest.approx(0.5 * D[1, 1] * j + D[0, 0] * jab, rel=1e-13)
+    # off-diagonal: (01|kl) screened for all kl; exchange -1/2 D_10 (00|11)
+    assert F[0, 1] == pytest.approx(-0.5 * D[1, 0] * jab, rel=1e-12)
+
+
+def _rot(seed):
+    q, _ = np.linalg.qr(np.random.default_rng(seed).normal(size=(3, 3)))
+    return q
+
+
+def test_invariances(oracle_lib):
+    s = random_cluster(5, 9, box=5.0)
+    F, E2, _ = oracle_lib.fock(s.xyz, s.dens, E3, C3, 1e-9)
+    Ft, Et, _ = oracle_lib.fock(s.xyz + np.array([3.0, -7.0, 11.0]), s.dens, E3, C3, 1e-9)
+    Fr, Er, _ = oracle_lib.fock(s.xyz @ _rot(1).T, s.dens, E3, C3, 1e-9)
+    perm = np.array([3, 0, 4, 1, 2])
+    Fp, Ep, _ = oracle_lib.fock(s.xyz[perm], s.dens[np.ix_(perm, perm)], E3, C3, 1e-9)
+    sc = np.abs(F).max()
+    assert np.abs(Ft - F).max() < 1e-12 * sc
+    assert np.abs(Fr - F).max() < 1e-12 * sc
+    assert np.abs(Fp - F[np.ix_(perm, perm)]).max() < 1e-13 * sc
+    for e in (Et, Er, Ep):
+        assert e == pytest.approx(E2, rel=1e-12)
+
+
+def test_linearity_and_quadratic_energy(oracle_lib):
+    s = random_cluster(5, 10, box=6.0)
+    D2 = random_cluster(5, 99).dens
+    F1, E1, _ = oracle_lib.fock(s.xyz, s.dens, E3, C3, 1e-8)
+    F2, _, _ = oracle_lib.fock(s.xyz, D2, E3, C3, 1e-8)
+    F12, _, _ = oracle_lib.fock(s.xyz, s.dens + D2, E3, C3, 1e-8)
+    assert np.abs(F12 - F1 - F2).max() < 1e-13 * np.abs(F12).max()
+    for lam in (0.5, 2.0, -3.0):
+        _, El, _ = oracle_lib.fock(s.xyz, lam * s.dens, E3, C3, 1e-8)
+        assert El == pytest.approx(lam * lam * E1, rel=1e-13)
+
+
+def test_energy_derivative_wrt_density_is_G(oracle_lib):
+    s = random_cluster(4, 12, box=5.0)
+    G, E, _ = oracle_lib.fock(s.xyz, s.dens, E3, C3, 0.0)
+    h = 1e-3
+    for (i, j) in [(0, 0), (1, 0), (3, 2), (2, 2)]:
+        Dp = s.dens.copy(); Dm = s.dens.copy()
+        Dp[i, j] += h; Dm[i, j] -= h
+        if i != j:
+            Dp[j, i] += h; Dm[j, i] -= h
+        _, Ep, _ = oracle_lib.fock(s.xyz, Dp, E3, C3, 0.0)
+        _, Em, _ = oracle_lib.fock(s.xyz, Dm, E3, C3, 0.0)
+        fd = (Ep - Em) / (2 * h)
+        expect = G[i, j] * (1 if i == j else 2)
+        assert fd == pytest.approx(expect, rel=1e-10, abs=1e-12)
+
+
+def test_fock_element_equals_bruteforce(oracle_lib):
+    s = random_cluster(5, 13, box=7.0)
+    tau = 1e-7
+    Fb, _ = oracle_lib.fock_bruteforce(s.xyz, s.dens, E3, C3, tau)
+    Q = oracle_lib.schwarz(s.xyz, E3, C3)
+    for (i, j) in [(0, 0), (4, 1), (2, 3)]:
+        assert oracle_lib.fock_element(s.xyz, s.dens, E3, C3, tau, Q, i, j) == pytest.approx(Fb[i, j], rel=1e-14, abs=1e-16)
+
+
+def test_bra_range_partition_sums(oracle_lib):
+    """Splitting the bra loop into ranges and summing gives the full build (used by the CPU
+    baseline, which times a bounded bra range)."""
+    s = random_cluster(6, 14, box=5.0)
+    F, E, ns = oracle_lib.fock(s.xyz, s.dens, E3, C3, 1e-10)
+    Fa, _, na = oracle_lib.fock(s.xyz, s.dens, E3, C3, 1e-10, bra_range=(0, 9))
+    Fb, _, nb = oracle_lib.fock(s.xyz, s.dens, E3, C3, 1e-10, bra_range=(9, 21))
+    assert na + nb == ns
+    assert np.abs(Fa + Fb - F).max() < 1e-14 * np.abs(F).max()
+
+
+# ------------------------------------------------------------------ gradient
+
+def test_gradient_vs_finite_differences(oracle_lib):
+    s = random_cluster(4, 15, box=4.0)
+    g, Eg, _ = oracle_lib.grad(s.xyz, s.dens, E3, C3, 0.0)
+    _, E, _ = oracle_lib.fock(s.xyz, s.dens, E3, C3, 0.0)
+    assert Eg == pytest.approx(E, rel=1e-13)
+    h = 1e-4
+    fd = np.zeros_like(g)
+    for a in range(s.natoms):
+        for x in range(3):
+            xp = s.xyz.copy(); xm = s.xyz.copy()
+            xp[a, x] += h; xm[a, x] -= h
+            fd[a, x] = (oracle_lib.fock(xp, s.dens, E3, C3, 0.0)[1] - oracle_lib.fock(xm, s.dens, E3, C3, 0.0)[1]) / (2 * h)
+    assert np.abs(fd - g).max() < 1e-8 * max(1.0, np.abs(g).max())
+
+
+def test_gradient_net_force_and_torque(oracle_lib):
+    s = random_cluster(6, 16, box=6.0)
+    g, _, _ = oracle_lib.grad(s.xyz, s.dens, E3, C3, 1e-9)
+    sc = np.abs(g).max()
+    assert np.abs(g.sum(axis=0)).max() < 1e-13 * max(sc, 1)
+    c = s.xyz - s.xyz.mean(axis=0)
+    torque = np.cross(c, g).sum(axis=0)
+    assert np.abs(torque).max() < 1e-12 * max(sc, 1)
+
+
+def test_config_he64_matches_fixture(oracle_lib):
+    """The 64-atom build against the stored fixture written by tests/golden/make_golden.py."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "he64_fp64.txt")
+    lines = open(path).read().split("\n")
+    e2_ref = float([l for l in lines if l.startswith("# E2")][0].split()[2])
+    ns_ref = int([l for l in lines if l.startswith("# survivors")][0].split()[2])
+    s = config_system("he64_fp64")
+    F, E2, ns = oracle_lib.fock(s.xyz, s.dens, E3, C3, s.tau)
+    assert ns == ns_ref
+    assert E2 == pytest.approx(e2_ref, rel=1e-13)
+    Fref = np.loadtxt(path)
+    assert np.abs(F - Fref).max() <= 1e-13 * np.abs(Fref).max()
