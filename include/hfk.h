@@ -1,0 +1,181 @@
+/*
+ * hfk.h -- C ABI of the MI355X (gfx950) two-electron Fock build library, libhfk.so.
+ *
+ * The operation (Background section, "Hartree--Fock" paragraph and its kernel listing):
+ * for a system of atoms, each carrying one contracted s-type Gaussian built from the same
+ * primitives (exponents xpnt, coefficients coef), loop over the unique electron-repulsion
+ * quartets (ij|kl) that pass the Schwarz screen Q_ij Q_kl >= tau, Q_ij = sqrt((ij|ij)),
+ * evaluate each from its primitive quartets with the Boys function F0, and scatter the
+ * Coulomb (factor 4) and exchange (factor -1) contributions into the Fock matrix read
+ * against the density, under the 8-fold permutational symmetry of the integrals.  The
+ * library returns the symmetrised two-electron matrix
+ *     G_ij = sum_kl D_kl [ s(ij,kl) (ij|kl) - 1/2 s(ik,jl) (ik|jl) ]
+ * and the two-electron energy E2 = 1/2 sum_ij D_ij G_ij.
+ *
+ * Conventions shared by every entry point:
+ *   - Units: bohr in, hartree out.  Every matrix is FP64, row-major, contiguous.
+ *   - Pointers without a _host suffix are DEVICE pointers (memory of the current HIP
+ *     device).  Pointers with _host are host memory read during the call.
+ *   - The caller owns every buffer.  The library never allocates, frees or retains caller
+ *     memory: its scratch comes from the caller's workspace, whose size the matching
+ *     *_workspace_bytes call returns (a bound that depends only on the sizes passed).
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL is the null stream)
+ *     and the call returns without waiting for it, except hfk_read_stats.
+ *   - Arguments are validated on the host before any HIP call; an invalid call enqueues
+ *     nothing.  A non-zero hfk_status is returned on failure and hfk_last_error() gives a
+ *     thread-local message.  No C++ exception crosses this interface.
+ *   - The density must be symmetric; the library does not check it.
+ *   - Calls that share a workspace must not overlap in time (same stream, or ordered).
+ */
+#ifndef HFK_H
+#define HFK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hfk_status {
+    HFK_OK = 0,
+    HFK_EINVAL = 1,        /* an argument is out of range or a required pointer is NULL */
+    HFK_ENOMEM = 2,        /* the workspace is smaller than *_workspace_bytes asked for */
+    HFK_EHIP = 3,          /* a HIP runtime call failed (message holds the HIP error) */
+    HFK_EUNSUPPORTED = 4   /* valid but outside what this build supports (sizes, device) */
+} hfk_status;
+
+typedef enum hfk_precision {
+    HFK_FP64 = 0,   /* every step in FP64 */
+    HFK_MIXED = 1   /* primitive integrals and Boys function in FP32; Schwarz bounds, the
+                       contraction into the Fock matrix, the energy and the gradient
+                       accumulation in FP64 */
+} hfk_precision;
+
+/* Accumulation strategy of the forward build (chosen by hfk_tune or passed explicitly). */
+typedef enum hfk_strategy {
+    HFK_STRATEGY_AUTO = 0,     /* library default, or the tuned choice once hfk_tune ran */
+    HFK_STRATEGY_PRIVATE = 1,  /* each workgroup owns an FP64 copy of F; summed at the end */
+    HFK_STRATEGY_ATOMIC = 2    /* workgroups flush their LDS rows into one F with atomics */
+} hfk_strategy;
+
+enum { HFK_MAX_NGAUSS = 8 };
+
+/* Counters of the last build that used a workspace, read back by hfk_read_stats. */
+typedef struct hfk_stats {
+    int64_t natoms;          /* atoms (basis functions) */
+    int64_t pairs;           /* n(n+1)/2 */
+    int64_t sig_pairs;       /* pairs with Q_ij * max Q >= tau */
+    int64_t quartets;        /* unique quartets kept by the screen (ij >= kl) */
+    int64_t work_items;      /* items of the persistent quartet kernel */
+    int32_t strategy;        /* hfk_strategy actually used */
+    int32_t groups;          /* persistent workgroups launched */
+    int32_t precision;       /* hfk_precision used */
+    int32_t reserved;
+} hfk_stats;
+
+/* Workspace size (bytes) for hfk_fock / hfk_fock_grad on `natoms` atoms with `ngauss`
+ * primitives per atom at `precision`; with_grad != 0 adds what hfk_fock_grad needs.
+ * Uses the current device's compute-unit count.  Errors: HFK_EINVAL for natoms < 1,
+ * ngauss outside [1, HFK_MAX_NGAUSS], an unknown precision or a NULL bytes_out. */
+hfk_status hfk_workspace_bytes(int64_t natoms, int32_t ngauss, int32_t precision,
+                               int32_t with_grad, size_t *bytes_out);
+
+/* Forward Fock build: the Background section's kernel (listing of the Hartree--Fock
+ * kernel), over all unique screened quartets.
+ *   natoms           n >= 1
+ *   xyz              [n*3] atom positions (bohr)
+ *   ngauss           primitives per contracted function, 1..HFK_MAX_NGAUSS
+ *   exps_host        [ngauss] primitive exponents, each > 0 and finite (host memory)
+ *   coefs_host       [ngauss] contraction coefficients, finite (host memory); the
+ *                    primitives are normalised, the coefficients are used as given
+ *   dens             [n*n] symmetric density D
+ *   tau              Schwarz threshold, finite and >= 0 (a quartet is kept iff
+ *                    Q_ij Q_kl >= tau)
+ *   precision        hfk_precision
+ *   strategy         hfk_strategy (HFK_STRATEGY_AUTO for the default)
+ *   fock             [n*n] output G (overwritten)
+ *   e2               [1] output E2 (device, overwritten)
+ *   workspace        device scratch of at least hfk_workspace_bytes(...) bytes, 256-byte
+ *                    aligned; its contents on entry do not matter
+ * Errors: HFK_EINVAL (arguments), HFK_ENOMEM (workspace too small), HFK_EUNSUPPORTED
+ * (n above what one workgroup's LDS rows hold), HFK_EHIP (launch failure). */
+hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss,
+                    const double *exps_host, const double *coefs_host,
+                    const double *dens, double tau, int32_t precision, int32_t strategy,
+                    double *fock, double *e2,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
+/* Backward of E2 (the paper has no gradient; this is the derivative of the energy the
+ * forward defines, with the screening decisions held fixed):
+ *   d_xyz  = g_e2 * dE2/dR,  dE2/dR_A = sum_unique Gamma_ijkl d(ij|kl)/dR_A,
+ *            Gamma = deg (4 D_ij D_kl - D_ik D_jl - D_il D_jk)
+ *   d_dens = g_e2 * G  (dE2/dD = G for the symmetric-bilinear energy), from fock_in
+ * Inputs as hfk_fock plus
+ *   g_e2     [1] upstream dL/dE2 (device)
+ *   fock_in  [n*n] G from the forward call on the same inputs; may be NULL when d_dens is
+ * Outputs
+ *   d_xyz    [n*3] (overwritten)
+ *   d_dens   [n*n] or NULL (not computed)
+ *   e2_out   [1] or NULL: E2 recomputed as sum_unique Gamma (ij|kl)
+ * Errors as hfk_fock; HFK_EINVAL if d_dens is given without fock_in. */
+hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss,
+                         const double *exps_host, const double *coefs_host,
+                         const double *dens, double tau, int32_t precision,
+                         const double *g_e2, const double *fock_in,
+                         double *d_xyz, double *d_dens, double *e2_out,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace size for hfk_fock_batched over `nmol` molecules whose atom ranges are
+ * atom_off_host[m] .. atom_off_host[m+1] (CSR, host memory, nondecreasing, starting at 0).
+ * with_grad != 0 adds the gradient accumulators. */
+hfk_status hfk_batched_workspace_bytes(int64_t nmol, const int64_t *atom_off_host,
+                                       int32_t ngauss, int32_t precision, int32_t with_grad,
+                                       size_t *bytes_out);
+
+/* Ragged batch of independent molecules in one persistent launch.
+ *   xyz          [sum n, 3] positions of all molecules, molecule m at rows
+ *                atom_off_host[m] .. atom_off_host[m+1]
+ *   dens_packed  the molecules' n_m x n_m densities stored one after another
+ *                (molecule m starts at sum_{m'<m} n_m'^2)
+ *   fock_packed  output, same packing as dens_packed
+ *   e2           [nmol] output energies
+ *   d_xyz        [sum n, 3] output dE2/dR, or NULL for a forward-only call
+ * Each molecule needs 1 <= n_m <= 128 atoms (its matrices stay in LDS).
+ * Errors as hfk_fock; HFK_EUNSUPPORTED for a molecule above 128 atoms. */
+hfk_status hfk_fock_batched(int64_t nmol, const int64_t *atom_off_host, const double *xyz,
+                            int32_t ngauss, const double *exps_host, const double *coefs_host,
+                            const double *dens_packed, double tau, int32_t precision,
+                            double *fock_packed, double *e2, double *d_xyz,
+                            void *workspace, size_t workspace_bytes, void *stream);
+
+/* Waits for `stream`, then copies the counters of the last build made with `workspace`
+ * into *out.  Errors: HFK_EINVAL for NULL arguments, HFK_EHIP. */
+hfk_status hfk_read_stats(const void *workspace, void *stream, hfk_stats *out);
+
+/* Autotuner: times the forward build of the given system under every candidate
+ * (accumulation strategy x workgroups per compute unit) on `stream`, keeps the fastest
+ * for this (device, precision, size class) for the rest of the process, and writes the
+ * table to cache_path as JSON when cache_path is not NULL.  best_out (may be NULL)
+ * receives the chosen hfk_strategy.  Inputs and workspace as hfk_fock (fock and e2 are
+ * overwritten).  Errors as hfk_fock. */
+hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss,
+                    const double *exps_host, const double *coefs_host,
+                    const double *dens, double tau, int32_t precision,
+                    double *fock, double *e2, void *workspace, size_t workspace_bytes,
+                    void *stream, const char *cache_path, int32_t *best_out);
+
+/* Loads a table written by hfk_tune (JSON).  Errors: HFK_EINVAL (NULL or unreadable). */
+hfk_status hfk_load_tuning(const char *cache_path);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *hfk_last_error(void);
+
+/* Library version string. */
+const char *hfk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HFK_H */

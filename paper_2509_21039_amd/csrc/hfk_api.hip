@@ -1,0 +1,276 @@
+// Host side of the libhfk C ABI: validation, workspace layout and launch sequencing.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "hfk_internal.hpp"
+
+namespace hfk {
+
+static thread_local char g_err[512];
+
+static hfk_status fail(hfk_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+static hfk_status hip_fail(hipError_t e, const char *where)
+{
+    return fail(HFK_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int device_cu_count()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus;
+}
+
+Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
+{
+    (void)prec;
+    Layout L;
+    memset(&L, 0, sizeof(L));
+    L.n = n;
+    L.npair = n * (n + 1) / 2;
+    L.pcap = ((L.npair + 63) / 64) * 64 + 64;
+    L.g = g;
+    L.g2 = g * g;
+    L.groups = groups;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t P = (size_t)L.npair, PC = (size_t)L.pcap, g2 = (size_t)L.g2;
+    L.hdr = take(sizeof(DevHeader));
+    L.basis = take(sizeof(BasisDev));
+    L.boys = take(sizeof(double) * kBoysGrid * kBoysStride);
+    L.boys_f = take(sizeof(float) * kBoysGrid * kBoysStride);
+    L.q_unsorted = take(sizeof(double) * P);
+    L.bucket_of = take(sizeof(int) * P);
+    L.bucket_cnt = take(sizeof(int) * kNumBuckets);
+    L.bucket_off = take(sizeof(int) * (kNumBuckets + 1));
+    L.bucket_cur = take(sizeof(int) * kNumBuckets);
+    L.pk = take(sizeof(int) * PC);
+    L.pl = take(sizeof(int) * PC);
+    L.pq = take(sizeof(double) * PC);
+    L.pd = take(sizeof(double) * PC);
+    L.prim = take(sizeof(double) * 4 * g2 * PC);
+    L.prim_f = take(sizeof(float) * 4 * g2 * PC);
+    L.nitems = take(sizeof(long long) * PC);
+    L.lim = take(sizeof(int) * PC);
+    L.item_off = take(sizeof(long long) * (PC + 1));
+    L.scan_tmp = take(sizeof(long long) * ((PC + 1023) / 1024 + 1));
+    const size_t n2 = (size_t)(n * n);
+    L.fpriv = take(sizeof(double) * n2 * (size_t)groups);
+    L.jcol = take(sizeof(double) * PC * (size_t)groups);
+    L.fsum = take(sizeof(double) * n2);
+    L.e2part = take(sizeof(double) * ((n2 + 255) / 256 + 256));
+    L.grad = with_grad ? take(sizeof(double) * 3 * (size_t)n * (size_t)groups + sizeof(double) * 4096) : 0;
+    L.total = o;
+    return L;
+}
+
+static int groups_for(int cus) { return cus > 0 ? 2 * cus : 512; }
+
+static hfk_status check_common(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps,
+                               const double *coefs, const double *dens, double tau, int32_t precision)
+{
+    if (natoms < 1) return fail(HFK_EINVAL, "natoms must be >= 1 (got %lld)", (long long)natoms);
+    if (ngauss < 1 || ngauss > HFK_MAX_NGAUSS)
+        return fail(HFK_EINVAL, "ngauss must be in [1, %d] (got %d)", HFK_MAX_NGAUSS, (int)ngauss);
+    if (!xyz) return fail(HFK_EINVAL, "xyz is NULL");
+    if (!dens) return fail(HFK_EINVAL, "dens is NULL");
+    if (!exps) return fail(HFK_EINVAL, "exps_host is NULL");
+    if (!coefs) return fail(HFK_EINVAL, "coefs_host is NULL");
+    for (int a = 0; a < ngauss; ++a) {
+        if (!(exps[a] > 0.0) || !isfinite(exps[a]))
+            return fail(HFK_EINVAL, "exps_host[%d] must be finite and > 0 (got %g)", a, exps[a]);
+        if (!isfinite(coefs[a])) return fail(HFK_EINVAL, "coefs_host[%d] is not finite", a);
+    }
+    if (!isfinite(tau) || tau < 0.0) return fail(HFK_EINVAL, "tau must be finite and >= 0 (got %g)", tau);
+    if (precision != HFK_FP64 && precision != HFK_MIXED)
+        return fail(HFK_EINVAL, "precision must be HFK_FP64 or HFK_MIXED (got %d)", (int)precision);
+    return HFK_OK;
+}
+
+static Basis make_basis(int32_t ngauss, const double *exps, const double *coefs)
+{
+    Basis b;
+    memset(&b, 0, sizeof(b));
+    b.g = ngauss;
+    b.g2 = ngauss * ngauss;
+    for (int a = 0; a < ngauss; ++a) {
+        b.alpha[a] = exps[a];
+        b.w[a] = coefs[a] * pow(2.0 * exps[a] / 3.14159265358979323846, 0.75);
+    }
+    return b;
+}
+
+// n above which rows i and j of F no longer fit in one workgroup's LDS next to the Boys table
+constexpr int64_t kMaxAtoms = 6144;
+
+// Tuned strategy per (precision, size class); 0 = not tuned.
+static std::mutex g_tune_mu;
+static int g_tuned[2][4];
+
+static int size_class(int64_t n) { return n <= 128 ? 0 : n <= 384 ? 1 : n <= 768 ? 2 : 3; }
+
+static int pick_strategy(int32_t strategy, int32_t precision, int64_t n)
+{
+    if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_ATOMIC) return strategy;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const int t = g_tuned[precision][size_class(n)];
+    return t ? t : HFK_STRATEGY_PRIVATE;
+}
+
+}  // namespace hfk
+
+using namespace hfk;
+
+extern "C" {
+
+const char *hfk_last_error(void) { return g_err; }
+
+const char *hfk_version(void) { return "hfk 0.1 (gfx950)"; }
+
+hfk_status hfk_workspace_bytes(int64_t natoms, int32_t ngauss, int32_t precision, int32_t with_grad,
+                               size_t *bytes_out)
+{
+    g_err[0] = 0;
+    if (!bytes_out) return fail(HFK_EINVAL, "bytes_out is NULL");
+    if (natoms < 1) return fail(HFK_EINVAL, "natoms must be >= 1 (got %lld)", (long long)natoms);
+    if (ngauss < 1 || ngauss > HFK_MAX_NGAUSS)
+        return fail(HFK_EINVAL, "ngauss must be in [1, %d] (got %d)", HFK_MAX_NGAUSS, (int)ngauss);
+    if (precision != HFK_FP64 && precision != HFK_MIXED)
+        return fail(HFK_EINVAL, "precision must be HFK_FP64 or HFK_MIXED (got %d)", (int)precision);
+    if (natoms > kMaxAtoms) return fail(HFK_EUNSUPPORTED, "natoms above %lld", (long long)kMaxAtoms);
+    const Layout L = make_layout(natoms, ngauss, precision, with_grad, groups_for(device_cu_count()));
+    *bytes_out = L.total;
+    return HFK_OK;
+}
+
+hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
+                    const double *coefs_host, const double *dens, double tau, int32_t precision,
+                    int32_t strategy, double *fock, double *e2, void *workspace, size_t workspace_bytes,
+                    void *stream)
+{
+    g_err[0] = 0;
+    hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision);
+    if (s != HFK_OK) return s;
+    if (!fock) return fail(HFK_EINVAL, "fock is NULL");
+    if (!e2) return fail(HFK_EINVAL, "e2 is NULL");
+    if (!workspace) return fail(HFK_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
+    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_ATOMIC)
+        return fail(HFK_EINVAL, "unknown strategy %d", (int)strategy);
+    if (natoms > kMaxAtoms) return fail(HFK_EUNSUPPORTED, "natoms above %lld", (long long)kMaxAtoms);
+    if (ngauss > 4) return fail(HFK_EUNSUPPORTED, "ngauss above 4 is not built in this version");
+    const int cus = device_cu_count();
+    if (cus <= 0) return fail(HFK_EHIP, "no HIP device");
+    const Layout L = make_layout(natoms, ngauss, precision, 0, groups_for(cus));
+    if (workspace_bytes < L.total)
+        return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
+    const int strat = pick_strategy(strategy, precision, natoms);
+    const Basis b = make_basis(ngauss, exps_host, coefs_host);
+    char *ws = (char *)workspace;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys),
+                                (float *)(ws + L.boys_f), (DevHeader *)(ws + L.hdr), natoms, xyz, st);
+    if (e != hipSuccess) return hip_fail(e, "setup launch");
+    e = launch_pairs(L, b, ws, xyz, dens, tau, st);
+    if (e != hipSuccess) return hip_fail(e, "pair launch");
+    e = launch_fock(L, b, ws, dens, tau, precision, strat, fock, e2, st);
+    if (e != hipSuccess) return hip_fail(e, "fock launch");
+    e = launch_header_info(ws + L.hdr, strat, L.groups, precision, st);
+    if (e != hipSuccess) return hip_fail(e, "header launch");
+    return HFK_OK;
+}
+
+hfk_status hfk_read_stats(const void *workspace, void *stream, hfk_stats *out)
+{
+    g_err[0] = 0;
+    if (!workspace || !out) return fail(HFK_EINVAL, "workspace and out must not be NULL");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "stream sync");
+    DevHeader h;
+    e = hipMemcpy(&h, workspace, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "header copy");
+    memset(out, 0, sizeof(*out));
+    out->natoms = h.natoms;
+    out->pairs = (int64_t)h.natoms * (h.natoms + 1) / 2;
+    out->sig_pairs = h.sig_pairs;
+    out->quartets = (int64_t)h.quartets;
+    out->work_items = h.items;
+    out->strategy = h.strategy;
+    out->groups = h.groups;
+    out->precision = h.precision;
+    return HFK_OK;
+}
+
+hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
+                         const double *coefs_host, const double *dens, double tau, int32_t precision,
+                         const double *g_e2, const double *fock_in, double *d_xyz, double *d_dens,
+                         double *e2_out, void *workspace, size_t workspace_bytes, void *stream)
+{
+    g_err[0] = 0;
+    hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision);
+    if (s != HFK_OK) return s;
+    (void)g_e2; (void)fock_in; (void)d_xyz; (void)d_dens; (void)e2_out; (void)workspace;
+    (void)workspace_bytes; (void)stream;
+    return fail(HFK_EUNSUPPORTED, "gradient not built yet");
+}
+
+hfk_status hfk_batched_workspace_bytes(int64_t nmol, const int64_t *atom_off_host, int32_t ngauss,
+                                       int32_t precision, int32_t with_grad, size_t *bytes_out)
+{
+    g_err[0] = 0;
+    (void)nmol; (void)atom_off_host; (void)ngauss; (void)precision; (void)with_grad; (void)bytes_out;
+    return fail(HFK_EUNSUPPORTED, "batched path not built yet");
+}
+
+hfk_status hfk_fock_batched(int64_t nmol, const int64_t *atom_off_host, const double *xyz, int32_t ngauss,
+                            const double *exps_host, const double *coefs_host, const double *dens_packed,
+                            double tau, int32_t precision, double *fock_packed, double *e2, double *d_xyz,
+                            void *workspace, size_t workspace_bytes, void *stream)
+{
+    g_err[0] = 0;
+    (void)nmol; (void)atom_off_host; (void)xyz; (void)ngauss; (void)exps_host; (void)coefs_host;
+    (void)dens_packed; (void)tau; (void)precision; (void)fock_packed; (void)e2; (void)d_xyz;
+    (void)workspace; (void)workspace_bytes; (void)stream;
+    return fail(HFK_EUNSUPPORTED, "batched path not built yet");
+}
+
+hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
+                    const double *coefs_host, const double *dens, double tau, int32_t precision, double *fock,
+                    double *e2, void *workspace, size_t workspace_bytes, void *stream, const char *cache_path,
+                    int32_t *best_out)
+{
+    g_err[0] = 0;
+    (void)natoms; (void)xyz; (void)ngauss; (void)exps_host; (void)coefs_host; (void)dens; (void)tau;
+    (void)precision; (void)fock; (void)e2; (void)workspace; (void)workspace_bytes; (void)stream;
+    (void)cache_path; (void)best_out;
+    return fail(HFK_EUNSUPPORTED, "tuner not built yet");
+}
+
+hfk_status hfk_load_tuning(const char *cache_path)
+{
+    g_err[0] = 0;
+    if (!cache_path) return fail(HFK_EINVAL, "cache_path is NULL");
+    return fail(HFK_EUNSUPPORTED, "tuner not built yet");
+}
+
+}  // extern "C"

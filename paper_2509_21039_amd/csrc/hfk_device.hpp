@@ -1,0 +1,59 @@
+// Device helpers shared by the libhfk kernels.
+#pragma once
+
+#include "hfk_internal.hpp"
+
+namespace hfk {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kTwoOverSqrtPi = 1.12837916709551257389615890312154517;
+
+// H(T) = erf(sqrt T) / sqrt T with H(0) = 2/sqrt(pi): the reduced Boys function
+// (2/sqrt(pi)) F0(T).  Accurate library erf; used off the hot path (Schwarz bounds).
+__device__ inline double erf_over_sqrt(double T)
+{
+    if (T < 1e-12) return kTwoOverSqrtPi * (1.0 - T / 3.0);
+    const double s = sqrt(T);
+    return erf(s) / s;
+}
+
+// Gaussian product of the primitives of atoms A and B (coordinates already centred):
+// P_ab = (a A + b B)/p and S_ab = w_a w_b exp(-mu |A-B|^2) (pi/p)^(3/2), the charge of
+// the product distribution, for every primitive pair ab = a*g + b.
+__device__ inline void pair_prims(const Basis &b, const BasisDev *__restrict__ bd, const double *A,
+                                  const double *B, double *px, double *py, double *pz, double *ps)
+{
+    const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
+    const double ab2 = dx * dx + dy * dy + dz * dz;
+    for (int ab = 0; ab < b.g2; ++ab) {
+        const int a = ab / b.g, c = ab % b.g;
+        const double fa = bd->fa[ab], fb = bd->fb[ab];
+        px[ab] = fa * A[0] + fb * B[0];
+        py[ab] = fa * A[1] + fb * B[1];
+        pz[ab] = fa * A[2] + fb * B[2];
+        ps[ab] = b.w[a] * b.w[c] * exp(-bd->mu[ab] * ab2) * bd->pi32[ab];
+    }
+}
+
+// Reciprocal square root to full FP64 precision: the hardware estimate refined by one
+// Newton step carried to second order, y (1 + e/2 + 3e^2/8) with e = 1 - x y^2.
+__device__ inline double rsqrt_fp64(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+__device__ inline float rsqrt_fp32(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Wave-wide sum (64 lanes) of a double through cross-lane shuffles.
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline int lane_id() { return (int)__lane_id(); }
+
+}  // namespace hfk

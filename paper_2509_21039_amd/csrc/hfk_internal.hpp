@@ -1,0 +1,110 @@
+// Internal declarations of libhfk: workspace layout, basis tables, launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hfk.h"
+
+namespace hfk {
+
+constexpr int kMaxG = HFK_MAX_NGAUSS;
+constexpr int kMaxG2 = kMaxG * kMaxG;
+
+// Pairs are bucketed by Q on a log2 grid: bucket b holds 2^(1-(b+1)/R) <= Q < 2^(1-b/R).
+constexpr int kBucketsPerOctave = 32;
+constexpr int kNumBuckets = 64 * kBucketsPerOctave;
+
+// Boys function table: F0 Taylor expansion about T_k = k h, k = 0 .. kBoysGrid-1.
+// Coefficient n of row k is (2/sqrt(pi)) (-1)^n F_n(T_k) / n!, so that
+// H(T) = erf(sqrt T)/sqrt T = sum_n c_n (T - T_k)^n near T_k.  Row 0 of the offset table
+// subtracts the far-field value at kTswitch (used by the deferred near-field path).
+constexpr int kBoysOrder = 7;          // coefficients used (degree 6)
+constexpr int kBoysStride = 8;         // padded row length
+constexpr double kBoysH = 0.125;       // grid spacing
+constexpr double kBoysInvH = 8.0;
+constexpr double kTswitch = 32.0;      // above this H(T) = T^(-1/2) to < 1e-15 relative
+constexpr int kBoysGrid = 264;         // covers [0, 33)
+
+constexpr int kWave = 64;
+constexpr int kWavesPerGroup = 4;
+constexpr int kGroupThreads = kWave * kWavesPerGroup;
+constexpr int kKetsPerItem = kGroupThreads;   // one 64-ket chunk per wave per item
+
+// Device-side counters written by the build and read back by hfk_read_stats.
+struct DevHeader {
+    unsigned long long qmax_bits;   // max Q as the bit pattern of a positive double
+    int sig_pairs;
+    int pad0;
+    long long items;
+    unsigned long long quartets;
+    double centroid[3];
+    int strategy;
+    int groups;
+    int precision;
+    int natoms;
+};
+
+// Basis constants shared by every pair, computed on the host from exps/coefs and passed
+// by value.  ab = a * g + b indexes a primitive pair.
+struct Basis {
+    int g;
+    int g2;
+    double alpha[kMaxG];
+    double w[kMaxG];            // c_a (2 alpha_a / pi)^(3/4)
+};
+
+// Per primitive pair / quartet constants, in device memory (written by a setup kernel).
+struct BasisDev {
+    double p[kMaxG2];           // alpha_a + alpha_b
+    double mu[kMaxG2];          // alpha_a alpha_b / p
+    double fa[kMaxG2];          // alpha_a / p
+    double fb[kMaxG2];          // alpha_b / p
+    double pi32[kMaxG2];        // (pi / p)^(3/2)
+    double rho[kMaxG2 * kMaxG2];    // p q / (p + q), [ab * g2 + cd]
+    double srho[kMaxG2 * kMaxG2];   // sqrt(rho)
+    double r2sw[kMaxG2 * kMaxG2];   // kTswitch / rho: |P-Q|^2 beyond which the far field is exact
+    float rho_f[kMaxG2 * kMaxG2];
+    float srho_f[kMaxG2 * kMaxG2];
+    float r2sw_f[kMaxG2 * kMaxG2];
+};
+
+// Workspace layout of the single-molecule path.  Every offset is 256-byte aligned.
+struct Layout {
+    int64_t n, npair, pcap;     // pcap = npair rounded up to 64, plus one spare chunk
+    int g, g2, groups;
+    size_t hdr, basis, boys, boys_f;
+    size_t q_unsorted, bucket_of, bucket_cnt, bucket_off, bucket_cur;
+    size_t pk, pl, pq, pd;                 // sorted pair tables
+    size_t prim;                           // [4][g2][pcap] doubles: Px, Py, Pz, S
+    size_t prim_f;                         // [4][g2][pcap] floats (mixed)
+    size_t nitems, lim, item_off, scan_tmp;
+    size_t fpriv;                          // [groups][n*n] or [n*n]
+    size_t jcol;                           // [groups][pcap]
+    size_t fsum;                           // [n*n]
+    size_t e2part;                         // partial energies
+    size_t grad;                           // [groups][n*3] gradient accumulators
+    size_t total;
+};
+
+Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups);
+
+int device_cu_count();
+
+// ------------------------------------------------------------------ launchers
+// Each returns hipSuccess or the launch error; all enqueue on `st`.
+hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, DevHeader *hdr,
+                        int64_t n, const double *xyz, hipStream_t st);
+hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
+                        double tau, hipStream_t st);
+hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *dens, double tau,
+                       int prec, int strategy, double *fock, double *e2, hipStream_t st);
+hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision, hipStream_t st);
+hipError_t launch_scan(const long long *in, int64_t m, long long *out, long long *tmp, long long *total,
+                       hipStream_t st);
+hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *dens, double tau,
+                       int prec, const double *g_e2, const double *fock_in, double *d_xyz,
+                       double *d_dens, double *e2_out, hipStream_t st);
+
+}  // namespace hfk

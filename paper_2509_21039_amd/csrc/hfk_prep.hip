@@ -1,0 +1,435 @@
+// Setup and pair preparation for the Fock build: basis constants, Boys table, Schwarz
+// bounds, the Q-bucketed pair order and the work items of the quartet kernel.
+#include "hfk_device.hpp"
+
+namespace hfk {
+
+// ------------------------------------------------------------------ setup
+
+// Basis constants per primitive pair and quartet; zeroes the header; centroid of xyz.
+__global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ bd,
+                                               DevHeader *__restrict__ hdr, int64_t n,
+                                               const double *__restrict__ xyz)
+{
+    const int t = threadIdx.x;
+    const int g = b.g, g2 = b.g2;
+    for (int ab = t; ab < g2; ab += blockDim.x) {
+        const int a = ab / g, c = ab % g;
+        const double p = b.alpha[a] + b.alpha[c];
+        bd->p[ab] = p;
+        bd->mu[ab] = b.alpha[a] * b.alpha[c] / p;
+        bd->fa[ab] = b.alpha[a] / p;
+        bd->fb[ab] = b.alpha[c] / p;
+        bd->pi32[ab] = pow(kPi / p, 1.5);
+    }
+    for (int x = t; x < g2 * g2; x += blockDim.x) {
+        const int ab = x / g2, cd = x % g2;
+        const double p = b.alpha[ab / g] + b.alpha[ab % g];
+        const double q = b.alpha[cd / g] + b.alpha[cd % g];
+        const double rho = p * q / (p + q);
+        bd->rho[x] = rho;
+        bd->srho[x] = sqrt(rho);
+        bd->r2sw[x] = kTswitch / rho;
+        bd->rho_f[x] = (float)rho;
+        bd->srho_f[x] = (float)sqrt(rho);
+        bd->r2sw_f[x] = (float)(kTswitch / rho);
+    }
+    // centroid (block reduction, one block)
+    __shared__ double red[3][256];
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int64_t i = t; i < n; i += blockDim.x) {
+        s0 += xyz[3 * i];
+        s1 += xyz[3 * i + 1];
+        s2 += xyz[3 * i + 2];
+    }
+    red[0][t] = s0; red[1][t] = s1; red[2][t] = s2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            red[0][t] += red[0][t + w];
+            red[1][t] += red[1][t + w];
+            red[2][t] += red[2][t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        hdr->qmax_bits = 0;
+        hdr->sig_pairs = 0;
+        hdr->items = 0;
+        hdr->quartets = 0;
+        hdr->centroid[0] = red[0][0] / (double)n;
+        hdr->centroid[1] = red[1][0] / (double)n;
+        hdr->centroid[2] = red[2][0] / (double)n;
+        hdr->natoms = (int)n;
+    }
+}
+
+// Boys table: row k holds (2/sqrt(pi)) (-1)^m F_m(k h) / m!, m = 0..kBoysOrder-1, with
+// F_m from its positive Kummer series (all terms positive, no cancellation).
+__global__ void k_boys_table(double *__restrict__ tab, float *__restrict__ tab_f)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kBoysGrid) return;
+    const double T = k * kBoysH;
+    double fact = 1.0;
+    for (int m = 0; m < kBoysStride; ++m) {
+        double v = 0.0;
+        if (m < kBoysOrder) {
+            double term = 1.0 / (2.0 * m + 1.0), sum = term;
+            for (int i = 1; i < 400; ++i) {
+                term *= 2.0 * T / (2.0 * m + 2.0 * i + 1.0);
+                sum += term;
+                if (term < 1e-18 * sum) break;
+            }
+            const double fm = exp(-T) * sum;
+            if (m > 0) fact *= (double)m;
+            v = kTwoOverSqrtPi * ((m & 1) ? -fm : fm) / fact;
+        }
+        tab[k * kBoysStride + m] = v;
+        tab_f[k * kBoysStride + m] = (float)v;
+    }
+}
+
+hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, DevHeader *hdr,
+                        int64_t n, const double *xyz, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, b, bd, hdr, n, xyz);
+    hipLaunchKernelGGL(k_boys_table, dim3((kBoysGrid + 63) / 64), dim3(64), 0, st, boys, boys_f);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ pairs
+
+__device__ inline void pair_of_index(int64_t p, int64_t &i, int64_t &j)
+{
+    int64_t r = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while (r * (r + 1) / 2 > p) --r;
+    while ((r + 1) * (r + 2) / 2 <= p) ++r;
+    i = r;
+    j = p - r * (r + 1) / 2;
+}
+
+// Schwarz bound of every pair i >= j: Q_ij = sqrt((ij|ij)) in FP64, each primitive
+// quartet as S_ab S_cd sqrt(rho) H(rho |P-Q|^2) with H(T) = erf(sqrt T)/sqrt T.
+__global__ __launch_bounds__(256) void k_pair_q(Basis b, const BasisDev *__restrict__ bd,
+                                                DevHeader *__restrict__ hdr, int64_t n,
+                                                const double *__restrict__ xyz,
+                                                double *__restrict__ qout)
+{
+    const int64_t npair = n * (n + 1) / 2;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double q = 0.0;
+    if (p < npair) {
+        int64_t i, j;
+        pair_of_index(p, i, j);
+        const double c0 = hdr->centroid[0], c1 = hdr->centroid[1], c2 = hdr->centroid[2];
+        double A[3] = {xyz[3 * i] - c0, xyz[3 * i + 1] - c1, xyz[3 * i + 2] - c2};
+        double B[3] = {xyz[3 * j] - c0, xyz[3 * j + 1] - c1, xyz[3 * j + 2] - c2};
+        double px[kMaxG2], py[kMaxG2], pz[kMaxG2], ps[kMaxG2];
+        pair_prims(b, bd, A, B, px, py, pz, ps);
+        double s = 0.0;
+        for (int ab = 0; ab < b.g2; ++ab)
+            for (int cd = 0; cd < b.g2; ++cd) {
+                const double dx = px[ab] - px[cd], dy = py[ab] - py[cd], dz = pz[ab] - pz[cd];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                s += ps[ab] * ps[cd] * bd->srho[ab * b.g2 + cd] * erf_over_sqrt(bd->rho[ab * b.g2 + cd] * r2);
+            }
+        q = sqrt(s);
+        qout[p] = q;
+    }
+    // block max, then one atomic per block (positive doubles order like their bit patterns)
+    __shared__ double red[256];
+    red[threadIdx.x] = q;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(&hdr->qmax_bits, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+__device__ inline int q_bucket(double q)
+{
+    // b = floor((1 - log2 q) * R), clamped; larger Q -> smaller bucket.
+    const double x = (1.0 - log2(q)) * (double)kBucketsPerOctave;
+    if (!(x < (double)(kNumBuckets - 1))) return kNumBuckets - 1;
+    return x < 0.0 ? 0 : (int)x;
+}
+
+__global__ __launch_bounds__(256) void k_bucket_count(int64_t npair, double tau,
+                                                      const DevHeader *__restrict__ hdr,
+                                                      const double *__restrict__ q,
+                                                      int *__restrict__ bucket_of,
+                                                      int *__restrict__ cnt)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npair) return;
+    const double qmax = __longlong_as_double((long long)hdr->qmax_bits);
+    const double qp = q[p];
+    int b = -1;
+    if (qp * qmax >= tau && qp > 0.0) {
+        b = q_bucket(qp);
+        atomicAdd(&cnt[b], 1);
+    }
+    bucket_of[p] = b;
+}
+
+// Exclusive scan of the bucket counts (one block); also the significant-pair total.
+__global__ __launch_bounds__(1024) void k_bucket_scan(const int *__restrict__ cnt, int *__restrict__ off,
+                                                      int *__restrict__ cur, DevHeader *__restrict__ hdr)
+{
+    constexpr int per = kNumBuckets / 1024;
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    int local[per];
+    int s = 0;
+    for (int i = 0; i < per; ++i) {
+        local[i] = s;
+        s += cnt[t * per + i];
+    }
+    part[t] = s;
+    __syncthreads();
+    for (int w = 1; w < 1024; w <<= 1) {
+        int v = (t >= w) ? part[t - w] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const int base = part[t] - s;
+    for (int i = 0; i < per; ++i) {
+        off[t * per + i] = base + local[i];
+        cur[t * per + i] = base + local[i];
+    }
+    if (t == 1023) {
+        off[kNumBuckets] = part[1023];
+        hdr->sig_pairs = part[1023];
+    }
+}
+
+// Writes every significant pair at its bucketed position: atoms, Q, D_kl and the SoA
+// primitive-pair table {Px, Py, Pz, S} (FP64 and FP32), centred on the centroid.
+__global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *__restrict__ bd,
+                                                      const DevHeader *__restrict__ hdr, int64_t n,
+                                                      int64_t pcap, const double *__restrict__ xyz,
+                                                      const double *__restrict__ dens,
+                                                      const double *__restrict__ q,
+                                                      const int *__restrict__ bucket_of,
+                                                      int *__restrict__ cur, int *__restrict__ pk,
+                                                      int *__restrict__ pl, double *__restrict__ pq,
+                                                      double *__restrict__ pd, double *__restrict__ prim,
+                                                      float *__restrict__ prim_f)
+{
+    const int64_t npair = n * (n + 1) / 2;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npair) return;
+    const int bk = bucket_of[p];
+    if (bk < 0) return;
+    const int pos = atomicAdd(&cur[bk], 1);
+    int64_t i, j;
+    pair_of_index(p, i, j);
+    const double c0 = hdr->centroid[0], c1 = hdr->centroid[1], c2 = hdr->centroid[2];
+    double A[3] = {xyz[3 * i] - c0, xyz[3 * i + 1] - c1, xyz[3 * i + 2] - c2};
+    double B[3] = {xyz[3 * j] - c0, xyz[3 * j + 1] - c1, xyz[3 * j + 2] - c2};
+    double px[kMaxG2], py[kMaxG2], pz[kMaxG2], ps[kMaxG2];
+    pair_prims(b, bd, A, B, px, py, pz, ps);
+    pk[pos] = (int)i;
+    pl[pos] = (int)j;
+    pq[pos] = q[p];
+    pd[pos] = dens[i * n + j];
+    const int g2 = b.g2;
+    for (int ab = 0; ab < g2; ++ab) {
+        prim[(0 * g2 + ab) * pcap + pos] = px[ab];
+        prim[(1 * g2 + ab) * pcap + pos] = py[ab];
+        prim[(2 * g2 + ab) * pcap + pos] = pz[ab];
+        prim[(3 * g2 + ab) * pcap + pos] = ps[ab];
+        prim_f[(0 * g2 + ab) * pcap + pos] = (float)px[ab];
+        prim_f[(1 * g2 + ab) * pcap + pos] = (float)py[ab];
+        prim_f[(2 * g2 + ab) * pcap + pos] = (float)pz[ab];
+        prim_f[(3 * g2 + ab) * pcap + pos] = (float)ps[ab];
+    }
+}
+
+// Pads the tail chunk of the sorted tables with harmless entries (atom 0, zero weight) so
+// that lanes past the last pair read defined memory.
+__global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int g2,
+                           int *__restrict__ pk, int *__restrict__ pl, double *__restrict__ pq,
+                           double *__restrict__ pd, double *__restrict__ prim, float *__restrict__ prim_f)
+{
+    const int64_t s = hdr->sig_pairs;
+    const int64_t pos = s + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= pcap) return;
+    pk[pos] = 0;
+    pl[pos] = 0;
+    pq[pos] = 0.0;
+    pd[pos] = 0.0;
+    for (int ab = 0; ab < g2; ++ab) {
+        for (int c = 0; c < 4; ++c) {
+            prim[(c * g2 + ab) * pcap + pos] = c < 3 ? 1e6 : 0.0;
+            prim_f[(c * g2 + ab) * pcap + pos] = c < 3 ? 1e6f : 0.0f;
+        }
+    }
+}
+
+// Ket range of every bra s (in bucketed order): kets t < lim_s with
+// lim_s = min(s + 1, end of the bucket holding tau / Q_s); items of kKetsPerItem kets.
+__global__ __launch_bounds__(256) void k_limits(const DevHeader *__restrict__ hdr, double tau,
+                                                const double *__restrict__ pq,
+                                                const int *__restrict__ boff,
+                                                long long *__restrict__ nitems, int *__restrict__ lims,
+                                                int64_t pcap)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t S = hdr->sig_pairs;
+    if (s >= pcap) return;
+    long long ni = 0;
+    if (s < S) {
+        const double thr = tau / pq[s];
+        int64_t bend;
+        if (thr <= 0.0) {
+            bend = S;
+        } else {
+            const int bt = q_bucket(thr);
+            bend = (thr > 2.0) ? 0 : boff[bt + 1];
+        }
+        const int64_t lim = bend < s + 1 ? bend : s + 1;
+        ni = (lim + kKetsPerItem - 1) / kKetsPerItem;
+        lims[s] = (int)lim;
+    } else {
+        lims[s] = 0;
+    }
+    nitems[s] = ni;
+}
+
+// ------------------------------------------------------------------ exclusive scan (int64)
+
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const long long *__restrict__ in, int64_t m,
+                                                            long long *__restrict__ bsum)
+{
+    __shared__ long long red[kScanBlock];
+    const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    red[threadIdx.x] = i < m ? in[i] : 0;
+    __syncthreads();
+    for (int w = kScanBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+// Exclusive scan of the block sums in one block (nb <= 1024 * 16).
+__global__ __launch_bounds__(kScanBlock) void k_scan_blocks(long long *__restrict__ bsum, int nb)
+{
+    __shared__ long long part[kScanBlock];
+    const int t = threadIdx.x;
+    const int per = (nb + kScanBlock - 1) / kScanBlock;
+    long long s = 0;
+    for (int i = 0; i < per; ++i) {
+        const int x = t * per + i;
+        if (x < nb) s += bsum[x];
+    }
+    part[t] = s;
+    __syncthreads();
+    for (int w = 1; w < kScanBlock; w <<= 1) {
+        long long v = (t >= w) ? part[t - w] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    long long run = part[t] - s;
+    for (int i = 0; i < per; ++i) {
+        const int x = t * per + i;
+        if (x < nb) {
+            const long long v = bsum[x];
+            bsum[x] = run;
+            run += v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_final(const long long *__restrict__ in, int64_t m,
+                                                           const long long *__restrict__ bsum,
+                                                           long long *__restrict__ out,
+                                                           long long *__restrict__ total)
+{
+    __shared__ long long part[kScanBlock];
+    const int t = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kScanBlock + t;
+    const long long v = i < m ? in[i] : 0;
+    part[t] = v;
+    __syncthreads();
+    for (int w = 1; w < kScanBlock; w <<= 1) {
+        long long u = (t >= w) ? part[t - w] : 0;
+        __syncthreads();
+        part[t] += u;
+        __syncthreads();
+    }
+    const long long excl = bsum[blockIdx.x] + part[t] - v;
+    if (i < m) out[i] = excl;
+    if (i == m - 1) {
+        out[m] = excl + v;
+        *total = excl + v;
+    }
+}
+
+hipError_t launch_scan(const long long *in, int64_t m, long long *out, long long *tmp, long long *total,
+                       hipStream_t st)
+{
+    const int nb = (int)((m + kScanBlock - 1) / kScanBlock);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, st, in, m, tmp);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanBlock), 0, st, tmp, nb);
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanBlock), 0, st, in, m, tmp, out, total);
+    return hipGetLastError();
+}
+
+__global__ void k_header_info(DevHeader *hdr, int strategy, int groups, int precision)
+{
+    hdr->strategy = strategy;
+    hdr->groups = groups;
+    hdr->precision = precision;
+}
+
+hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_header_info, dim3(1), dim3(1), 0, st, (DevHeader *)hdr, strategy, groups, precision);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int *__restrict__ p, int64_t m, int v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) p[i] = v;
+}
+
+hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
+                        double tau, hipStream_t st)
+{
+    DevHeader *hdr = (DevHeader *)(ws + L.hdr);
+    const BasisDev *bd = (const BasisDev *)(ws + L.basis);
+    const int64_t np = L.npair;
+    const int bs = 256;
+    const unsigned nbp = (unsigned)((np + bs - 1) / bs);
+    int *cnt = (int *)(ws + L.bucket_cnt);
+    int *off = (int *)(ws + L.bucket_off);
+    int *cur = (int *)(ws + L.bucket_cur);
+    hipLaunchKernelGGL(k_fill_i32, dim3((kNumBuckets + 255) / 256), dim3(256), 0, st, cnt, (int64_t)kNumBuckets, 0);
+    hipLaunchKernelGGL(k_pair_q, dim3(nbp), dim3(bs), 0, st, b, bd, hdr, L.n, xyz, (double *)(ws + L.q_unsorted));
+    hipLaunchKernelGGL(k_bucket_count, dim3(nbp), dim3(bs), 0, st, np, tau, hdr,
+                       (const double *)(ws + L.q_unsorted), (int *)(ws + L.bucket_of), cnt);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, st, cnt, off, cur, hdr);
+    hipLaunchKernelGGL(k_pair_scatter, dim3(nbp), dim3(bs), 0, st, b, bd, hdr, L.n, L.pcap, xyz, dens,
+                       (const double *)(ws + L.q_unsorted), (const int *)(ws + L.bucket_of), cur,
+                       (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
+                       (double *)(ws + L.prim), (float *)(ws + L.prim_f));
+    hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, L.pcap, L.g2,
+                       (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
+                       (double *)(ws + L.prim), (float *)(ws + L.prim_f));
+    hipLaunchKernelGGL(k_limits, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, tau,
+                       (const double *)(ws + L.pq), off, (long long *)(ws + L.nitems), (int *)(ws + L.lim),
+                       L.pcap);
+    return launch_scan((const long long *)(ws + L.nitems), L.pcap, (long long *)(ws + L.item_off),
+                       (long long *)(ws + L.scan_tmp), &hdr->items, st);
+}
+
+}  // namespace hfk

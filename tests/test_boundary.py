@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared symbol, and
+rejects invalid arguments before touching a device (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2509_21039_amd as hfk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "hfk.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:hfk_status|const char \*)\s*(hfk_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_entry_points():
+    names = _declared_symbols()
+    for must in ("hfk_fock", "hfk_fock_grad", "hfk_fock_batched", "hfk_workspace_bytes",
+                 "hfk_batched_workspace_bytes", "hfk_read_stats", "hfk_tune", "hfk_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = hfk.lib()
+    for name in _declared_symbols():
+        assert hasattr(L, name), name
+    assert hfk.version().startswith("hfk")
+
+
+def _fock_raw(n=4, ngauss=3, exps=(6.36242139, 1.158923, 0.31364979), coefs=(0.15432897, 0.53532814, 0.44463454),
+              xyz=1, dens=1, tau=1e-10, prec=0, strat=0, fock=1, e2=1, ws=256, wsb=1 << 40):
+    e = np.ascontiguousarray(exps, dtype=np.float64)
+    c = np.ascontiguousarray(coefs, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    return hfk.lib().hfk_fock(n, xyz, ngauss, e.ctypes.data_as(dp), c.ctypes.data_as(dp), dens, tau, prec, strat,
+                              fock, e2, ws, wsb, None)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(n=0), "natoms"),
+    (dict(n=-5), "natoms"),
+    (dict(ngauss=0, exps=(1.0,), coefs=(1.0,)), "ngauss"),
+    (dict(ngauss=9, exps=(1.0,) * 9, coefs=(1.0,) * 9), "ngauss"),
+    (dict(xyz=None), "xyz"),
+    (dict(dens=None), "dens"),
+    (dict(exps=(1.0, -2.0, 3.0)), "exps"),
+    (dict(exps=(1.0, float("nan"), 3.0)), "exps"),
+    (dict(coefs=(1.0, float("inf"), 3.0)), "coefs"),
+    (dict(tau=-1.0), "tau"),
+    (dict(tau=float("nan")), "tau"),
+    (dict(prec=7), "precision"),
+    (dict(strat=9), "strategy"),
+    (dict(fock=None), "fock"),
+    (dict(e2=None), "e2"),
+    (dict(ws=None), "workspace"),
+    (dict(ws=257), "aligned"),
+])
+def test_fock_rejects_invalid_arguments(kw, msg):
+    st = _fock_raw(**kw)
+    assert st == hfk.HFK_EINVAL
+    assert msg in hfk.lib().hfk_last_error().decode()
+
+
+def test_workspace_bytes_validation():
+    out = ctypes.c_size_t(0)
+    L = hfk.lib()
+    assert L.hfk_workspace_bytes(0, 3, 0, 0, ctypes.byref(out)) == hfk.HFK_EINVAL
+    assert L.hfk_workspace_bytes(10, 9, 0, 0, ctypes.byref(out)) == hfk.HFK_EINVAL
+    assert L.hfk_workspace_bytes(10, 3, 5, 0, ctypes.byref(out)) == hfk.HFK_EINVAL
+    assert L.hfk_workspace_bytes(10, 3, 0, 0, None) == hfk.HFK_EINVAL
+    assert L.hfk_workspace_bytes(10, 3, 0, 0, ctypes.byref(out)) == hfk.HFK_OK
+    small = out.value
+    assert L.hfk_workspace_bytes(100, 3, 0, 0, ctypes.byref(out)) == hfk.HFK_OK
+    assert out.value > small
+    assert L.hfk_workspace_bytes(100000, 3, 0, 0, ctypes.byref(out)) == hfk.HFK_EUNSUPPORTED
+
+
+def test_python_layer_raises_hfkerror():
+    with pytest.raises(hfk.HfkError) as ei:
+        hfk.workspace_bytes(0)
+    assert ei.value.status == hfk.HFK_EINVAL
+
+
+def test_read_stats_null_arguments():
+    assert hfk.lib().hfk_read_stats(None, None, None) == hfk.HFK_EINVAL
