@@ -168,6 +168,14 @@ hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss,
 /* Loads a table written by hfk_tune (JSON).  Errors: HFK_EINVAL (NULL or unreadable). */
 hfk_status hfk_load_tuning(const char *cache_path);
 
+/* Kernel timing for measurement tools: while enabled, every build records a pair of HIP
+ * events on its stream around its quartet kernel (the dominant kernel).  hfk_profile_read
+ * waits for the recorded events, returns the summed duration in milliseconds and the
+ * number of launches timed, and clears the record.  Process-wide; not thread-safe against
+ * concurrent builds.  Errors: HFK_EINVAL (NULL outputs), HFK_EHIP. */
+hfk_status hfk_profile_enable(int32_t on);
+hfk_status hfk_profile_read(double *total_ms, int64_t *launches);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *hfk_last_error(void);
 

@@ -64,6 +64,8 @@ _SIGNATURES = {
     "hfk_tune": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
                  _vp, _vp, _vp, _sz, _vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)],
     "hfk_load_tuning": [ctypes.c_char_p],
+    "hfk_profile_enable": [ctypes.c_int32],
+    "hfk_profile_read": [ctypes.POINTER(ctypes.c_double), _i64p],
 }
 
 
@@ -295,6 +297,19 @@ def tune(xyz, dens, exps, coefs, tau, precision="fp64", cache_path: Optional[str
                           F.data_ptr(), E2.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream),
                           cache_path.encode() if cache_path else None, ctypes.byref(best)))
     return best.value
+
+
+def profile_enable(on: bool = True):
+    """Record HIP events around every quartet-kernel launch (measurement tools only)."""
+    _check(lib().hfk_profile_enable(int(bool(on))))
+
+
+def profile_read():
+    """(summed quartet-kernel milliseconds, launches) since the last read; waits for them."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(lib().hfk_profile_read(ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
 
 
 def load_tuning(cache_path: str):

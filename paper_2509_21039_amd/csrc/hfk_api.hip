@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <mutex>
+#include <utility>
+#include <vector>
 
 #include "hfk_internal.hpp"
 
@@ -137,6 +139,34 @@ static int pick_strategy(int32_t strategy, int32_t precision, int64_t n)
     return t ? t : HFK_STRATEGY_PRIVATE;
 }
 
+// ------------------------------------------------------------------ kernel timing
+
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
+static hipEvent_t g_prof_open = nullptr;
+
+void profile_begin(hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, st);
+    g_prof_open = e;
+}
+
+void profile_end(hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on || !g_prof_open) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, st);
+    g_prof_events.emplace_back(g_prof_open, e);
+    g_prof_open = nullptr;
+}
+
 }  // namespace hfk
 
 using namespace hfk;
@@ -144,6 +174,38 @@ using namespace hfk;
 extern "C" {
 
 const char *hfk_last_error(void) { return g_err; }
+
+hfk_status hfk_profile_enable(int32_t on)
+{
+    g_err[0] = 0;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return HFK_OK;
+}
+
+hfk_status hfk_profile_read(double *total_ms, int64_t *launches)
+{
+    g_err[0] = 0;
+    if (!total_ms || !launches) return fail(HFK_EINVAL, "total_ms and launches must not be NULL");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    double sum = 0.0;
+    int64_t cnt = 0;
+    hfk_status st = HFK_OK;
+    for (auto &p : g_prof_events) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(p.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.first, p.second);
+        if (e != hipSuccess && st == HFK_OK) st = hip_fail(e, "event timing");
+        sum += ms;
+        ++cnt;
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    g_prof_events.clear();
+    *total_ms = sum;
+    *launches = cnt;
+    return st;
+}
 
 const char *hfk_version(void) { return "hfk 0.1 (gfx950)"; }
 

@@ -332,7 +332,9 @@ __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ part,
 template <int G, typename R>
 static hipError_t launch_fock_t(const FockArgs &a, int groups, size_t smem, hipStream_t st)
 {
+    profile_begin(st);
     hipLaunchKernelGGL((k_fock<G, R>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+    profile_end(st);
     return hipGetLastError();
 }
 

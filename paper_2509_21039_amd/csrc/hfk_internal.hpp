@@ -100,6 +100,10 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
                         double tau, hipStream_t st);
 hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *dens, double tau,
                        int prec, int strategy, double *fock, double *e2, hipStream_t st);
+// Events around the quartet kernel when profiling is enabled (no-ops otherwise).
+void profile_begin(hipStream_t st);
+void profile_end(hipStream_t st);
+
 hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision, hipStream_t st);
 hipError_t launch_scan(const long long *in, int64_t m, long long *out, long long *tmp, long long *total,
                        hipStream_t st);
