@@ -71,7 +71,7 @@ typedef struct hfk_stats {
     int32_t strategy;        /* hfk_strategy actually used */
     int32_t groups;          /* persistent workgroups launched */
     int32_t precision;       /* hfk_precision used */
-    int32_t reserved;
+    int32_t variant;         /* quartet-kernel variant used (hfk_set_config) */
 } hfk_stats;
 
 /* Workspace size (bytes) for hfk_fock / hfk_fock_grad on `natoms` atoms with `ngauss`
@@ -167,6 +167,14 @@ hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss,
 
 /* Loads a table written by hfk_tune (JSON).  Errors: HFK_EINVAL (NULL or unreadable). */
 hfk_status hfk_load_tuning(const char *cache_path);
+
+/* Process-wide override of the launch configuration of hfk_fock, for tuning and tests:
+ *   variant          0 = every primitive quartet evaluates the Boys function in place,
+ *                    1 = near/far split with per-wave compaction of near-field quartets,
+ *                   -1 = library choice (default: tuned value, else 1)
+ *   groups_per_cu    persistent workgroups per compute unit, 1..6, or 0 for the default
+ * Errors: HFK_EINVAL for values outside these sets. */
+hfk_status hfk_set_config(int32_t variant, int32_t groups_per_cu);
 
 /* Kernel timing for measurement tools: while enabled, every build records a pair of HIP
  * events on its stream around its quartet kernel (the dominant kernel).  hfk_profile_read

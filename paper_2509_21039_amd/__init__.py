@@ -40,10 +40,10 @@ class HfkStats(ctypes.Structure):
     _fields_ = [("natoms", ctypes.c_int64), ("pairs", ctypes.c_int64), ("sig_pairs", ctypes.c_int64),
                 ("quartets", ctypes.c_int64), ("work_items", ctypes.c_int64),
                 ("strategy", ctypes.c_int32), ("groups", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -65,6 +65,7 @@ _SIGNATURES = {
                  _vp, _vp, _vp, _sz, _vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)],
     "hfk_load_tuning": [ctypes.c_char_p],
     "hfk_profile_enable": [ctypes.c_int32],
+    "hfk_set_config": [ctypes.c_int32, ctypes.c_int32],
     "hfk_profile_read": [ctypes.POINTER(ctypes.c_double), _i64p],
 }
 
@@ -297,6 +298,12 @@ def tune(xyz, dens, exps, coefs, tau, precision="fp64", cache_path: Optional[str
                           F.data_ptr(), E2.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream),
                           cache_path.encode() if cache_path else None, ctypes.byref(best)))
     return best.value
+
+
+def set_config(variant: int = -1, groups_per_cu: int = 0):
+    """Override the quartet-kernel variant (0 direct, 1 near/far split, -1 library choice)
+    and the persistent workgroups per compute unit (0 = default), process-wide."""
+    _check(lib().hfk_set_config(int(variant), int(groups_per_cu)))
 
 
 def profile_enable(on: bool = True):

@@ -39,12 +39,16 @@ int device_cu_count()
     return cus;
 }
 
+// Per-workgroup copies of F are used while they stay within this many bytes in total.
+constexpr double kPrivateBudget = 16.0e9;
+
 Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
 {
     (void)prec;
     Layout L;
     memset(&L, 0, sizeof(L));
     L.n = n;
+    L.private_ok = (double)groups * (double)n * (double)n * 8.0 <= kPrivateBudget;
     L.npair = n * (n + 1) / 2;
     L.pcap = ((L.npair + 63) / 64) * 64 + 64;
     L.g = g;
@@ -63,8 +67,8 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
     L.boys_f = take(sizeof(float) * kBoysGrid * kBoysStride);
     L.q_unsorted = take(sizeof(double) * P);
     L.bucket_of = take(sizeof(int) * P);
-    L.bucket_cnt = take(sizeof(int) * kNumBuckets);
-    L.bucket_off = take(sizeof(int) * (kNumBuckets + 1));
+    L.bucket_cnt = take(sizeof(long long) * kNumBuckets);
+    L.bucket_off = take(sizeof(long long) * (kNumBuckets + 1));
     L.bucket_cur = take(sizeof(int) * kNumBuckets);
     L.pk = take(sizeof(int) * PC);
     L.pl = take(sizeof(int) * PC);
@@ -72,12 +76,16 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
     L.pd = take(sizeof(double) * PC);
     L.prim = take(sizeof(double) * 4 * g2 * PC);
     L.prim_f = take(sizeof(float) * 4 * g2 * PC);
+    L.bra = take(sizeof(double) * 4 * g2 * PC);
+    L.bra_f = take(sizeof(float) * 4 * g2 * PC);
+    L.boys_off = take(sizeof(double) * kBoysGrid * kBoysStride);
+    L.boys_off_f = take(sizeof(float) * kBoysGrid * kBoysStride);
     L.nitems = take(sizeof(long long) * PC);
     L.lim = take(sizeof(int) * PC);
     L.item_off = take(sizeof(long long) * (PC + 1));
-    L.scan_tmp = take(sizeof(long long) * ((PC + 1023) / 1024 + 1));
+    L.scan_tmp = take(sizeof(long long) * (((PC > (size_t)kNumBuckets ? PC : (size_t)kNumBuckets) + 1023) / 1024 + 1));
     const size_t n2 = (size_t)(n * n);
-    L.fpriv = take(sizeof(double) * n2 * (size_t)groups);
+    L.fpriv = take(sizeof(double) * n2 * (size_t)(L.private_ok ? groups : 1));
     L.jcol = take(sizeof(double) * PC * (size_t)groups);
     L.fsum = take(sizeof(double) * n2);
     L.e2part = take(sizeof(double) * ((n2 + 255) / 256 + 256));
@@ -86,7 +94,12 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
     return L;
 }
 
-static int groups_for(int cus) { return cus > 0 ? 2 * cus : 512; }
+constexpr int kMaxGroupsPerCU = 6;
+static int g_cfg_variant = -1;
+static int g_cfg_gpc = 0;
+
+// Workgroups the buffers are sized for (the most any configuration launches).
+static int groups_cap(int cus) { return (cus > 0 ? cus : 256) * kMaxGroupsPerCU; }
 
 static hfk_status check_common(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps,
                                const double *coefs, const double *dens, double tau, int32_t precision)
@@ -127,16 +140,28 @@ constexpr int64_t kMaxAtoms = 6144;
 
 // Tuned strategy per (precision, size class); 0 = not tuned.
 static std::mutex g_tune_mu;
-static int g_tuned[2][4];
 
 static int size_class(int64_t n) { return n <= 128 ? 0 : n <= 384 ? 1 : n <= 768 ? 2 : 3; }
 
-static int pick_strategy(int32_t strategy, int32_t precision, int64_t n)
+struct TunedConfig {
+    int strategy;      // 0 = not tuned
+    int variant;
+    int gpc;
+};
+static TunedConfig g_tuned_cfg[2][4];
+
+static TunedConfig pick_config(int32_t strategy, int32_t precision, int64_t n)
 {
-    if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_ATOMIC) return strategy;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    const int t = g_tuned[precision][size_class(n)];
-    return t ? t : HFK_STRATEGY_PRIVATE;
+    TunedConfig c;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        c = g_tuned_cfg[precision][size_class(n)];
+    }
+    if (c.strategy == 0) c = TunedConfig{HFK_STRATEGY_PRIVATE, 1, 2};
+    if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_ATOMIC) c.strategy = strategy;
+    if (g_cfg_variant >= 0) c.variant = g_cfg_variant;
+    if (g_cfg_gpc > 0) c.gpc = g_cfg_gpc;
+    return c;
 }
 
 // ------------------------------------------------------------------ kernel timing
@@ -174,6 +199,17 @@ using namespace hfk;
 extern "C" {
 
 const char *hfk_last_error(void) { return g_err; }
+
+hfk_status hfk_set_config(int32_t variant, int32_t groups_per_cu)
+{
+    g_err[0] = 0;
+    if (variant < -1 || variant > 1) return fail(HFK_EINVAL, "variant must be -1, 0 or 1 (got %d)", (int)variant);
+    if (groups_per_cu < 0 || groups_per_cu > kMaxGroupsPerCU)
+        return fail(HFK_EINVAL, "groups_per_cu must be in [0, %d] (got %d)", kMaxGroupsPerCU, (int)groups_per_cu);
+    g_cfg_variant = variant;
+    g_cfg_gpc = groups_per_cu;
+    return HFK_OK;
+}
 
 hfk_status hfk_profile_enable(int32_t on)
 {
@@ -220,7 +256,7 @@ hfk_status hfk_workspace_bytes(int64_t natoms, int32_t ngauss, int32_t precision
     if (precision != HFK_FP64 && precision != HFK_MIXED)
         return fail(HFK_EINVAL, "precision must be HFK_FP64 or HFK_MIXED (got %d)", (int)precision);
     if (natoms > kMaxAtoms) return fail(HFK_EUNSUPPORTED, "natoms above %lld", (long long)kMaxAtoms);
-    const Layout L = make_layout(natoms, ngauss, precision, with_grad, groups_for(device_cu_count()));
+    const Layout L = make_layout(natoms, ngauss, precision, with_grad, groups_cap(device_cu_count()));
     *bytes_out = L.total;
     return HFK_OK;
 }
@@ -243,21 +279,25 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     if (ngauss > 4) return fail(HFK_EUNSUPPORTED, "ngauss above 4 is not built in this version");
     const int cus = device_cu_count();
     if (cus <= 0) return fail(HFK_EHIP, "no HIP device");
-    const Layout L = make_layout(natoms, ngauss, precision, 0, groups_for(cus));
+    Layout L = make_layout(natoms, ngauss, precision, 0, groups_cap(cus));
     if (workspace_bytes < L.total)
         return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
-    const int strat = pick_strategy(strategy, precision, natoms);
+    const TunedConfig cfg = pick_config(strategy, precision, natoms);
+    int strat = cfg.strategy;
+    if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
+    L.groups = cus * cfg.gpc;
     const Basis b = make_basis(ngauss, exps_host, coefs_host);
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys),
-                                (float *)(ws + L.boys_f), (DevHeader *)(ws + L.hdr), natoms, xyz, st);
+                                (float *)(ws + L.boys_f), (double *)(ws + L.boys_off),
+                                (float *)(ws + L.boys_off_f), (DevHeader *)(ws + L.hdr), natoms, xyz, st);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
     e = launch_pairs(L, b, ws, xyz, dens, tau, st);
     if (e != hipSuccess) return hip_fail(e, "pair launch");
-    e = launch_fock(L, b, ws, dens, tau, precision, strat, fock, e2, st);
+    e = launch_fock(L, b, ws, dens, tau, precision, strat, cfg.variant, fock, e2, st);
     if (e != hipSuccess) return hip_fail(e, "fock launch");
-    e = launch_header_info(ws + L.hdr, strat, L.groups, precision, st);
+    e = launch_header_info(ws + L.hdr, strat, L.groups, precision, cfg.variant, st);
     if (e != hipSuccess) return hip_fail(e, "header launch");
     return HFK_OK;
 }
@@ -280,6 +320,7 @@ hfk_status hfk_read_stats(const void *workspace, void *stream, hfk_stats *out)
     out->strategy = h.strategy;
     out->groups = h.groups;
     out->precision = h.precision;
+    out->variant = h.variant;
     return HFK_OK;
 }
 

@@ -25,12 +25,16 @@ struct FockArgs {
     const BasisDev *bd;
     const double *boys;
     const float *boys_f;
+    const double *boys_off;
+    const float *boys_off_f;
     const int *pk;
     const int *pl;
     const double *pq;
     const double *pd;
     const double *prim;
     const float *prim_f;
+    const double *bra;
+    const float *bra_f;
     const long long *item_off;
     const int *lim;
     const double *dens;
@@ -46,27 +50,40 @@ struct FockArgs {
 template <typename R> struct Prec;
 template <> struct Prec<double> {
     static __device__ const double *prim(const FockArgs &a) { return a.prim; }
+    static __device__ const double *bra(const FockArgs &a) { return a.bra; }
     static __device__ const double *boys(const FockArgs &a) { return a.boys; }
+    static __device__ const double *boys_off(const FockArgs &a) { return a.boys_off; }
     static __device__ const double *rho(const BasisDev *bd) { return bd->rho; }
     static __device__ const double *srho(const BasisDev *bd) { return bd->srho; }
+    static __device__ const double *r2sw(const BasisDev *bd) { return bd->r2sw; }
+    static __device__ const double *rs(const BasisDev *bd) { return bd->rs; }
     static __device__ double rsqrt(double x) { return rsqrt_fp64(x); }
+    // acc + s / sqrt(x): hardware estimate y, one Newton step folded into the product
+    static __device__ double far_acc(double acc, double s, double x)
+    {
+        const double y = __builtin_amdgcn_rsq(x);
+        const double e = fma(-x * y, y, 1.0);
+        return fma(s * y, fma(e, 0.5, 1.0), acc);
+    }
 };
 template <> struct Prec<float> {
     static __device__ const float *prim(const FockArgs &a) { return a.prim_f; }
+    static __device__ const float *bra(const FockArgs &a) { return a.bra_f; }
     static __device__ const float *boys(const FockArgs &a) { return a.boys_f; }
+    static __device__ const float *boys_off(const FockArgs &a) { return a.boys_off_f; }
     static __device__ const float *rho(const BasisDev *bd) { return bd->rho_f; }
     static __device__ const float *srho(const BasisDev *bd) { return bd->srho_f; }
+    static __device__ const float *r2sw(const BasisDev *bd) { return bd->r2sw_f; }
+    static __device__ const float *rs(const BasisDev *bd) { return bd->rs_f; }
     static __device__ float rsqrt(float x) { return rsqrt_fp32(x); }
+    static __device__ float far_acc(float acc, float s, float x) { return fmaf(s, rsqrt_fp32(x), acc); }
 };
 
-// H(T) = erf(sqrt T)/sqrt T: Taylor expansion about the nearest grid point below the
-// switch, T^(-1/2) above it (both evaluated, one selected: no divergence).
+// Taylor expansion of the table row nearest to T (T below the switch, so the row exists).
 template <typename R>
-__device__ inline R boys_h(R T, const R *__restrict__ tab)
+__device__ inline R boys_taylor(R T, const R *__restrict__ tab)
 {
-    const R far = Prec<R>::rsqrt(T > R(1e-30) ? T : R(1e-30));
-    const R Tc = T < R(kTswitch + 0.5) ? T : R(kTswitch + 0.5);
-    const int k = (int)(Tc * R(kBoysInvH) + R(0.5));
+    const int k = (int)(T * R(kBoysInvH) + R(0.5));
     const R d = T - (R)k * R(kBoysH);
     const R *c = tab + k * kBoysStride;
     R v = c[6];
@@ -76,38 +93,123 @@ __device__ inline R boys_h(R T, const R *__restrict__ tab)
     v = v * d + c[2];
     v = v * d + c[1];
     v = v * d + c[0];
+    return v;
+}
+
+// H(T) = erf(sqrt T)/sqrt T: Taylor row below the switch, T^(-1/2) above it (both
+// evaluated, one selected).
+template <typename R>
+__device__ inline R boys_h(R T, const R *__restrict__ tab)
+{
+    const R far = Prec<R>::rsqrt(fmax(T, R(1e-30)));
+    const R Tc = fmin(T, R(kTswitch + 0.5));
+    const R v = boys_taylor<R>(Tc, tab);
     return T < R(kTswitch) ? v : far;
 }
 
-// Contracted (bra | ket) for one lane: bra primitives are wave-uniform (LDS), the ket's
-// are the lane's own.  (ab|cd) = S_ab S_cd sqrt(rho) H(rho |P - Q|^2).
+// Wave-uniform tables are read through the constant address space so that they are
+// fetched with scalar loads into SGPRs (they are never written while the kernel runs).
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+
+// The lane's ket primitives are consumed in blocks of G (fixed c, all d), so only G of
+// them occupy registers at a time; the bra primitive pair ab runs in the middle loop.
+
+// Contracted (bra | ket) for one lane, every primitive quartet evaluated in place.
+// (ab|cd) = S_ab S_cd sqrt(rho) H(rho |P - Q|^2).
 template <int G, typename R>
-__device__ inline R quartet_eri(const R *__restrict__ bx, const R *__restrict__ by,
-                                const R *__restrict__ bz, const R *__restrict__ bs,
-                                const R (&kx)[G * G], const R (&ky)[G * G], const R (&kz)[G * G],
-                                const R (&ks)[G * G], const R *__restrict__ rho,
-                                const R *__restrict__ srho, const R *__restrict__ tab)
+__device__ inline R quartet_eri_direct(const R *__restrict__ lbra, const R *__restrict__ prim, int64_t pcap,
+                                       int64_t t, const R *__restrict__ lrs, const R *__restrict__ tab)
 {
     constexpr int G2 = G * G;
     R eri = R(0);
+#pragma unroll 1
+    for (int cb = 0; cb < G; ++cb) {
+        R kx[G], ky[G], kz[G], ks[G];
 #pragma unroll
-    for (int ab = 0; ab < G2; ++ab) {
-        const R px = bx[ab], py = by[ab], pz = bz[ab];
-        R acc = R(0);
-#pragma unroll
-        for (int cd = 0; cd < G2; ++cd) {
-            const R dx = px - kx[cd], dy = py - ky[cd], dz = pz - kz[cd];
-            const R r2 = dx * dx + dy * dy + dz * dz;
-            const R T = r2 * rho[ab * G2 + cd];
-            const R h = boys_h<R>(T, tab);
-            acc += (ks[cd] * srho[ab * G2 + cd]) * h;
+        for (int d = 0; d < G; ++d) {
+            const int cd = cb * G + d;
+            kx[d] = prim[(int64_t)(0 * G2 + cd) * pcap + t];
+            ky[d] = prim[(int64_t)(1 * G2 + cd) * pcap + t];
+            kz[d] = prim[(int64_t)(2 * G2 + cd) * pcap + t];
+            ks[d] = prim[(int64_t)(3 * G2 + cd) * pcap + t];
         }
-        eri += bs[ab] * acc;
+#pragma unroll 1
+        for (int ab = 0; ab < G2; ++ab) {
+            const R px = lbra[4 * ab], py = lbra[4 * ab + 1], pz = lbra[4 * ab + 2];
+            R acc = R(0);
+#pragma unroll
+            for (int d = 0; d < G; ++d) {
+                const int x = ab * G2 + cb * G + d;
+                const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R h = boys_h<R>(r2 * lrs[2 * x], tab);
+                acc += (ks[d] * lrs[2 * x + 1]) * h;
+            }
+            eri += lbra[4 * ab + 3] * acc;
+        }
     }
     return eri;
 }
 
+// Contracted (bra | ket) with a wave-uniform near/far branch per primitive quartet: when
+// no lane of the wave has rho |P-Q|^2 below the switch (the common case once kets are
+// spatially sorted), the lanes add the far-field value S_cd / |P-Q| (exact beyond the
+// switch); otherwise every lane evaluates H(T) from the Taylor table or its far-field
+// form.  Lanes without a kept quartet get ket centres far away, so they are never near.
+// Uniform data (bra primitives, rho and sqrt(rho) per primitive quartet) come through
+// scalar loads.
 template <int G, typename R>
+__device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, int64_t pcap, int64_t t,
+                                       bool valid, cptr<R> rs, const R *__restrict__ tab)
+{
+    constexpr int G2 = G * G;
+    R eri = R(0);
+#pragma unroll 1
+    for (int cb = 0; cb < G; ++cb) {
+        R kx[G], ky[G], kz[G], ks[G];
+#pragma unroll
+        for (int d = 0; d < G; ++d) {
+            const int cd = cb * G + d;
+            kx[d] = prim[(int64_t)(0 * G2 + cd) * pcap + t];
+            ky[d] = prim[(int64_t)(1 * G2 + cd) * pcap + t];
+            kz[d] = valid ? prim[(int64_t)(2 * G2 + cd) * pcap + t] : R(1e10);
+            ks[d] = prim[(int64_t)(3 * G2 + cd) * pcap + t];
+        }
+#pragma unroll 3
+        for (int ab = 0; ab < G2; ++ab) {
+            const R px = bra[4 * ab], py = bra[4 * ab + 1], pz = bra[4 * ab + 2];
+            R acc = R(0);
+#pragma unroll
+            for (int d = 0; d < G; ++d) {
+                const int x = ab * G2 + cb * G + d;
+                const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R T = r2 * rs[2 * x];
+                if (__builtin_amdgcn_ballot_w64(T < R(kTswitch))) {
+                    acc += (ks[d] * rs[2 * x + 1]) * boys_h<R>(T, tab);
+                } else {
+                    acc = Prec<R>::far_acc(acc, ks[d], r2);
+                }
+            }
+            eri += bra[4 * ab + 3] * acc;
+        }
+    }
+    return eri;
+}
+
+// LDS carve-up of the quartet kernel (bytes, 16-byte aligned pieces).
+template <typename R> struct FockSmem {
+    static constexpr int kCombos = kMaxG2 * kMaxG2 / 16;                    // g <= 4 here: 256 combos
+    static constexpr size_t tab_bytes = sizeof(R) * kBoysGrid * kBoysStride;
+    static constexpr size_t cw_bytes = 3 * sizeof(R) * kCombos;            // (rho, S_ab sqrt(rho), pad)
+    static constexpr size_t uni_bytes = 4 * sizeof(R) * 16 + 2 * sizeof(R) * kCombos;   // bra, (rho|thr, srho)
+    static size_t total(int n, bool split)
+    {
+        return sizeof(double) * 2 * (size_t)n + tab_bytes + (split ? 0 : cw_bytes + uni_bytes);
+    }
+};
+
+template <int G, typename R, bool kSplit>
 __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
 {
     constexpr int G2 = G * G;
@@ -115,8 +217,14 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     const int n = a.n;
     double *rowi = smem;
     double *rowj = smem + n;
-    R *tab = (R *)(smem + 2 * n);
-    __shared__ R bra_p[4][G2];
+    char *sp = (char *)(smem + 2 * n);
+    R *tab = (R *)sp;                       // direct: H table; split: offset table
+    sp += FockSmem<R>::tab_bytes;
+    R *cw = (R *)sp;                        // (rho, S_ab sqrt(rho)) per quartet combo of the current bra
+    sp += FockSmem<R>::cw_bytes;
+    R *lbra = (R *)sp;                      // [G2][4] Px, Py, Pz, S of the current bra
+    R *luni = lbra + 4 * 16;                // direct: (rho, sqrt rho) per combo; split: r2 switch per combo
+    sp += FockSmem<R>::uni_bytes;
     __shared__ int bra_at[2];
     __shared__ double bra_qd[2];
 
@@ -131,6 +239,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
 
     const R *gtab = Prec<R>::boys(a);
     for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) tab[x] = gtab[x];
+    if (!kSplit) {
+        for (int x = tid; x < G2 * G2; x += kGroupThreads) {
+            luni[2 * x] = Prec<R>::rho(bd)[x];
+            luni[2 * x + 1] = Prec<R>::srho(bd)[x];
+        }
+    }
+    const cptr<R> crs = (cptr<R>)Prec<R>::rs(bd);
     double *jcol = a.jcol + (int64_t)gid * a.pcap;
     double *fp = a.strategy == HFK_STRATEGY_PRIVATE ? a.fpriv + (int64_t)gid * n * n : a.fpriv;
     if (a.strategy == HFK_STRATEGY_PRIVATE) {
@@ -151,8 +266,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
         s = lo;
     }
     const R *prim = Prec<R>::prim(a);
-    const R *rho = Prec<R>::rho(bd);
-    const R *srho = Prec<R>::srho(bd);
     int cur = -1, bi = 0, bj = 0;
     double qs = 0.0, ds = 0.0, jb = 0.0;
     unsigned long long kept = 0;
@@ -169,8 +282,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
                 if (lane == 0 && w != 0.0) atomicAdd(&rowi[bj], 4.0 * w);
                 jb = 0.0;
                 __syncthreads();
+                double *fi = fp + (int64_t)bi * n, *fj = fp + (int64_t)bj * n;
                 if (a.strategy == HFK_STRATEGY_PRIVATE) {
-                    double *fi = fp + (int64_t)bi * n, *fj = fp + (int64_t)bj * n;
                     if (bi == bj) {
                         for (int c = tid; c < n; c += kGroupThreads) fi[c] += rowi[c] + rowj[c];
                     } else {
@@ -180,7 +293,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
                         }
                     }
                 } else {
-                    double *fi = fp + (int64_t)bi * n, *fj = fp + (int64_t)bj * n;
                     for (int c = tid; c < n; c += kGroupThreads) {
                         const double vi = rowi[c], vj = rowj[c];
                         if (vi != 0.0) atomicAdd(&fi[c], vi);
@@ -190,11 +302,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
                 __syncthreads();
             }
             if (m == m1) break;
-            // load the new bra
-            if (tid < 4 * G2) {
-                const int c = tid / G2, ab = tid % G2;
-                bra_p[c][ab] = prim[(int64_t)(c * G2 + ab) * a.pcap + s];
-            }
+            const R *br = Prec<R>::bra(a) + (int64_t)s * 4 * G2;
+            if (!kSplit && tid < 4 * G2) lbra[tid] = br[tid];
             if (tid == 0) {
                 bra_at[0] = a.pk[s];
                 bra_at[1] = a.pl[s];
@@ -219,15 +328,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
         const bool in = t < lim;
         const double qt = a.pq[t];
         const bool valid = in && (qs * qt >= a.tau);
-        R kx[G2], ky[G2], kz[G2], ks[G2];
-#pragma unroll
-        for (int cd = 0; cd < G2; ++cd) {
-            kx[cd] = prim[(int64_t)(0 * G2 + cd) * a.pcap + t];
-            ky[cd] = prim[(int64_t)(1 * G2 + cd) * a.pcap + t];
-            kz[cd] = prim[(int64_t)(2 * G2 + cd) * a.pcap + t];
-            ks[cd] = prim[(int64_t)(3 * G2 + cd) * a.pcap + t];
-        }
-        const R eri = quartet_eri<G, R>(bra_p[0], bra_p[1], bra_p[2], bra_p[3], kx, ky, kz, ks, rho, srho, tab);
+        R eri;
+        if (kSplit)
+            eri = quartet_eri_hybrid<G, R>((cptr<R>)(Prec<R>::bra(a) + (int64_t)s * 4 * G2), prim, a.pcap, t, valid,
+                                           crs, tab);
+        else
+            eri = quartet_eri_direct<G, R>(lbra, prim, a.pcap, t, luni, tab);
         const int k = a.pk[t], l = a.pl[t];
         double deg = 1.0;
         if (bi == bj) deg *= 0.5;
@@ -330,16 +436,27 @@ __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ part,
 }
 
 template <int G, typename R>
-static hipError_t launch_fock_t(const FockArgs &a, int groups, size_t smem, hipStream_t st)
+static hipError_t launch_fock_t(const FockArgs &a, int groups, int variant, hipStream_t st)
 {
+    const bool split = variant != 0;
+    const size_t smem = FockSmem<R>::total(a.n, split);
     profile_begin(st);
-    hipLaunchKernelGGL((k_fock<G, R>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+    if (split)
+        hipLaunchKernelGGL((k_fock<G, R, true>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+    else
+        hipLaunchKernelGGL((k_fock<G, R, false>), dim3(groups), dim3(kGroupThreads), smem, st, a);
     profile_end(st);
     return hipGetLastError();
 }
 
+size_t fock_smem_bytes(int64_t n, int prec, int variant)
+{
+    return prec == HFK_MIXED ? FockSmem<float>::total((int)n, variant != 0)
+                             : FockSmem<double>::total((int)n, variant != 0);
+}
+
 hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *dens, double tau, int prec,
-                       int strategy, double *fock, double *e2, hipStream_t st)
+                       int strategy, int variant, double *fock, double *e2, hipStream_t st)
 {
     DevHeader *hdr = (DevHeader *)(ws + L.hdr);
     FockArgs a;
@@ -347,12 +464,16 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.bd = (const BasisDev *)(ws + L.basis);
     a.boys = (const double *)(ws + L.boys);
     a.boys_f = (const float *)(ws + L.boys_f);
+    a.boys_off = (const double *)(ws + L.boys_off);
+    a.boys_off_f = (const float *)(ws + L.boys_off_f);
     a.pk = (const int *)(ws + L.pk);
     a.pl = (const int *)(ws + L.pl);
     a.pq = (const double *)(ws + L.pq);
     a.pd = (const double *)(ws + L.pd);
     a.prim = (const double *)(ws + L.prim);
     a.prim_f = (const float *)(ws + L.prim_f);
+    a.bra = (const double *)(ws + L.bra);
+    a.bra_f = (const float *)(ws + L.bra_f);
     a.item_off = (const long long *)(ws + L.item_off);
     a.lim = (const int *)(ws + L.lim);
     a.dens = dens;
@@ -367,23 +488,21 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     const unsigned nb2 = (unsigned)((n2 + 255) / 256);
     if (strategy == HFK_STRATEGY_ATOMIC)
         hipLaunchKernelGGL(k_fill, dim3(nb2), dim3(256), 0, st, a.fpriv, n2, 0.0);
-    const size_t smem = (size_t)(2 * L.n) * sizeof(double) +
-                        (size_t)kBoysGrid * kBoysStride * (prec == HFK_MIXED ? sizeof(float) : sizeof(double));
     hipError_t err = hipSuccess;
     const int g = b.g;
     if (prec == HFK_MIXED) {
         switch (g) {
-        case 1: err = launch_fock_t<1, float>(a, L.groups, smem, st); break;
-        case 2: err = launch_fock_t<2, float>(a, L.groups, smem, st); break;
-        case 3: err = launch_fock_t<3, float>(a, L.groups, smem, st); break;
-        default: err = launch_fock_t<4, float>(a, L.groups, smem, st); break;
+        case 1: err = launch_fock_t<1, float>(a, L.groups, variant, st); break;
+        case 2: err = launch_fock_t<2, float>(a, L.groups, variant, st); break;
+        case 3: err = launch_fock_t<3, float>(a, L.groups, variant, st); break;
+        default: err = launch_fock_t<4, float>(a, L.groups, variant, st); break;
         }
     } else {
         switch (g) {
-        case 1: err = launch_fock_t<1, double>(a, L.groups, smem, st); break;
-        case 2: err = launch_fock_t<2, double>(a, L.groups, smem, st); break;
-        case 3: err = launch_fock_t<3, double>(a, L.groups, smem, st); break;
-        default: err = launch_fock_t<4, double>(a, L.groups, smem, st); break;
+        case 1: err = launch_fock_t<1, double>(a, L.groups, variant, st); break;
+        case 2: err = launch_fock_t<2, double>(a, L.groups, variant, st); break;
+        case 3: err = launch_fock_t<3, double>(a, L.groups, variant, st); break;
+        default: err = launch_fock_t<4, double>(a, L.groups, variant, st); break;
         }
     }
     if (err != hipSuccess) return err;

@@ -12,16 +12,21 @@ namespace hfk {
 constexpr int kMaxG = HFK_MAX_NGAUSS;
 constexpr int kMaxG2 = kMaxG * kMaxG;
 
-// Pairs are bucketed by Q on a log2 grid: bucket b holds 2^(1-(b+1)/R) <= Q < 2^(1-b/R).
-constexpr int kBucketsPerOctave = 32;
-constexpr int kNumBuckets = 64 * kBucketsPerOctave;
+// Pairs are ordered by (Q band, spatial cell of the pair centre): band b holds
+// 2^(1-(b+1)/R) <= Q < 2^(1-b/R); within a band, cells follow a Morton curve over the
+// bounding box (kCellBits per axis), so 64 consecutive kets sit close together in space.
+constexpr int kBandsPerOctave = 2;
+constexpr int kNumBands = 64 * kBandsPerOctave;
+constexpr int kCellBits = 4;
+constexpr int kNumCells = 1 << (3 * kCellBits);
+constexpr int kNumBuckets = kNumBands * kNumCells;
 
 // Boys function table: F0 Taylor expansion about T_k = k h, k = 0 .. kBoysGrid-1.
 // Coefficient n of row k is (2/sqrt(pi)) (-1)^n F_n(T_k) / n!, so that
 // H(T) = erf(sqrt T)/sqrt T = sum_n c_n (T - T_k)^n near T_k.  Row 0 of the offset table
 // subtracts the far-field value at kTswitch (used by the deferred near-field path).
 constexpr int kBoysOrder = 7;          // coefficients used (degree 6)
-constexpr int kBoysStride = 8;         // padded row length
+constexpr int kBoysStride = 9;         // row length: odd in doubles, so rows start on 16 different LDS bank pairs
 constexpr double kBoysH = 0.125;       // grid spacing
 constexpr double kBoysInvH = 8.0;
 constexpr double kTswitch = 32.0;      // above this H(T) = T^(-1/2) to < 1e-15 relative
@@ -40,10 +45,14 @@ struct DevHeader {
     long long items;
     unsigned long long quartets;
     double centroid[3];
+    double bmin[3];
+    double bmax[3];
     int strategy;
     int groups;
     int precision;
     int natoms;
+    int variant;
+    int pad1;
 };
 
 // Basis constants shared by every pair, computed on the host from exps/coefs and passed
@@ -65,6 +74,8 @@ struct BasisDev {
     double rho[kMaxG2 * kMaxG2];    // p q / (p + q), [ab * g2 + cd]
     double srho[kMaxG2 * kMaxG2];   // sqrt(rho)
     double r2sw[kMaxG2 * kMaxG2];   // kTswitch / rho: |P-Q|^2 beyond which the far field is exact
+    double rs[2 * kMaxG2 * kMaxG2];     // (rho, sqrt(rho)) interleaved
+    float rs_f[2 * kMaxG2 * kMaxG2];
     float rho_f[kMaxG2 * kMaxG2];
     float srho_f[kMaxG2 * kMaxG2];
     float r2sw_f[kMaxG2 * kMaxG2];
@@ -73,12 +84,15 @@ struct BasisDev {
 // Workspace layout of the single-molecule path.  Every offset is 256-byte aligned.
 struct Layout {
     int64_t n, npair, pcap;     // pcap = npair rounded up to 64, plus one spare chunk
-    int g, g2, groups;
+    int g, g2, groups;          // groups: persistent workgroups the buffers are sized for
+    bool private_ok;            // per-workgroup copies of F fit the memory budget
     size_t hdr, basis, boys, boys_f;
     size_t q_unsorted, bucket_of, bucket_cnt, bucket_off, bucket_cur;
     size_t pk, pl, pq, pd;                 // sorted pair tables
     size_t prim;                           // [4][g2][pcap] doubles: Px, Py, Pz, S
     size_t prim_f;                         // [4][g2][pcap] floats (mixed)
+    size_t bra, bra_f;                     // [pcap][4][g2] (AoS copy read as wave-uniform bra data)
+    size_t boys_off, boys_off_f;           // Boys table with the far-field value at the switch removed
     size_t nitems, lim, item_off, scan_tmp;
     size_t fpriv;                          // [groups][n*n] or [n*n]
     size_t jcol;                           // [groups][pcap]
@@ -94,17 +108,19 @@ int device_cu_count();
 
 // ------------------------------------------------------------------ launchers
 // Each returns hipSuccess or the launch error; all enqueue on `st`.
-hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, DevHeader *hdr,
-                        int64_t n, const double *xyz, hipStream_t st);
+hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, double *boys_off,
+                        float *boys_off_f, DevHeader *hdr, int64_t n, const double *xyz, hipStream_t st);
 hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
                         double tau, hipStream_t st);
 hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *dens, double tau,
-                       int prec, int strategy, double *fock, double *e2, hipStream_t st);
+                       int prec, int strategy, int variant, double *fock, double *e2, hipStream_t st);
+size_t fock_smem_bytes(int64_t n, int prec, int variant);
 // Events around the quartet kernel when profiling is enabled (no-ops otherwise).
 void profile_begin(hipStream_t st);
 void profile_end(hipStream_t st);
 
-hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision, hipStream_t st);
+hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision, int variant,
+                              hipStream_t st);
 hipError_t launch_scan(const long long *in, int64_t m, long long *out, long long *tmp, long long *total,
                        hipStream_t st);
 hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *dens, double tau,

@@ -31,28 +31,47 @@ __global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ b
         bd->srho[x] = sqrt(rho);
         bd->r2sw[x] = kTswitch / rho;
         bd->rho_f[x] = (float)rho;
+        bd->rs[2 * x] = rho;
+        bd->rs[2 * x + 1] = sqrt(rho);
+        bd->rs_f[2 * x] = (float)rho;
+        bd->rs_f[2 * x + 1] = (float)sqrt(rho);
         bd->srho_f[x] = (float)sqrt(rho);
         bd->r2sw_f[x] = (float)(kTswitch / rho);
     }
-    // centroid (block reduction, one block)
-    __shared__ double red[3][256];
+    // centroid and bounding box (block reductions, one block)
+    __shared__ double red[3][256], rmin[3][256], rmax[3][256];
     double s0 = 0, s1 = 0, s2 = 0;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t i = t; i < n; i += blockDim.x) {
         s0 += xyz[3 * i];
         s1 += xyz[3 * i + 1];
         s2 += xyz[3 * i + 2];
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fmin(lo[c], xyz[3 * i + c]);
+            hi[c] = fmax(hi[c], xyz[3 * i + c]);
+        }
     }
     red[0][t] = s0; red[1][t] = s1; red[2][t] = s2;
+    for (int c = 0; c < 3; ++c) {
+        rmin[c][t] = lo[c];
+        rmax[c][t] = hi[c];
+    }
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) {
-            red[0][t] += red[0][t + w];
-            red[1][t] += red[1][t + w];
-            red[2][t] += red[2][t + w];
+            for (int c = 0; c < 3; ++c) {
+                red[c][t] += red[c][t + w];
+                rmin[c][t] = fmin(rmin[c][t], rmin[c][t + w]);
+                rmax[c][t] = fmax(rmax[c][t], rmax[c][t + w]);
+            }
         }
         __syncthreads();
     }
     if (t == 0) {
+        for (int c = 0; c < 3; ++c) {
+            hdr->bmin[c] = rmin[c][0];
+            hdr->bmax[c] = rmax[c][0];
+        }
         hdr->qmax_bits = 0;
         hdr->sig_pairs = 0;
         hdr->items = 0;
@@ -66,7 +85,8 @@ __global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ b
 
 // Boys table: row k holds (2/sqrt(pi)) (-1)^m F_m(k h) / m!, m = 0..kBoysOrder-1, with
 // F_m from its positive Kummer series (all terms positive, no cancellation).
-__global__ void k_boys_table(double *__restrict__ tab, float *__restrict__ tab_f)
+__global__ void k_boys_table(double *__restrict__ tab, float *__restrict__ tab_f, double *__restrict__ toff,
+                             float *__restrict__ toff_f)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= kBoysGrid) return;
@@ -87,14 +107,20 @@ __global__ void k_boys_table(double *__restrict__ tab, float *__restrict__ tab_f
         }
         tab[k * kBoysStride + m] = v;
         tab_f[k * kBoysStride + m] = (float)v;
+        // offset table: H(T) - kTswitch^(-1/2) (the far-field value the clamped fast path
+        // already added for a near-field quartet)
+        const double vo = m == 0 ? v - 1.0 / sqrt(kTswitch) : v;
+        toff[k * kBoysStride + m] = vo;
+        toff_f[k * kBoysStride + m] = (float)vo;
     }
 }
 
-hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, DevHeader *hdr,
-                        int64_t n, const double *xyz, hipStream_t st)
+hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, double *boys_off,
+                        float *boys_off_f, DevHeader *hdr, int64_t n, const double *xyz, hipStream_t st)
 {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, b, bd, hdr, n, xyz);
-    hipLaunchKernelGGL(k_boys_table, dim3((kBoysGrid + 63) / 64), dim3(64), 0, st, boys, boys_f);
+    hipLaunchKernelGGL(k_boys_table, dim3((kBoysGrid + 63) / 64), dim3(64), 0, st, boys, boys_f, boys_off,
+                       boys_off_f);
     return hipGetLastError();
 }
 
@@ -148,62 +174,57 @@ __global__ __launch_bounds__(256) void k_pair_q(Basis b, const BasisDev *__restr
     if (threadIdx.x == 0) atomicMax(&hdr->qmax_bits, (unsigned long long)__double_as_longlong(red[0]));
 }
 
-__device__ inline int q_bucket(double q)
+__device__ inline int q_band(double q)
 {
-    // b = floor((1 - log2 q) * R), clamped; larger Q -> smaller bucket.
-    const double x = (1.0 - log2(q)) * (double)kBucketsPerOctave;
-    if (!(x < (double)(kNumBuckets - 1))) return kNumBuckets - 1;
+    // b = floor((1 - log2 q) * R), clamped; larger Q -> smaller band.
+    const double x = (1.0 - log2(q)) * (double)kBandsPerOctave;
+    if (!(x < (double)(kNumBands - 1))) return kNumBands - 1;
     return x < 0.0 ? 0 : (int)x;
 }
 
-__global__ __launch_bounds__(256) void k_bucket_count(int64_t npair, double tau,
-                                                      const DevHeader *__restrict__ hdr,
-                                                      const double *__restrict__ q,
-                                                      int *__restrict__ bucket_of,
-                                                      int *__restrict__ cnt)
+// Morton index of the cell holding point c inside the bounding box.
+__device__ inline int morton_cell(const double *c, const DevHeader *__restrict__ hdr)
 {
+    constexpr int side = 1 << kCellBits;
+    int code = 0;
+    for (int d = 0; d < 3; ++d) {
+        const double ext = hdr->bmax[d] - hdr->bmin[d];
+        int u = ext > 0.0 ? (int)((c[d] - hdr->bmin[d]) / ext * side) : 0;
+        u = u < 0 ? 0 : (u >= side ? side - 1 : u);
+        for (int b = 0; b < kCellBits; ++b) code |= ((u >> b) & 1) << (3 * b + d);
+    }
+    return code;
+}
+
+__global__ __launch_bounds__(256) void k_bucket_count(int64_t n, double tau, const DevHeader *__restrict__ hdr,
+                                                      const double *__restrict__ xyz,
+                                                      const double *__restrict__ q, int *__restrict__ bucket_of,
+                                                      long long *__restrict__ cnt)
+{
+    const int64_t npair = n * (n + 1) / 2;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npair) return;
     const double qmax = __longlong_as_double((long long)hdr->qmax_bits);
     const double qp = q[p];
     int b = -1;
     if (qp * qmax >= tau && qp > 0.0) {
-        b = q_bucket(qp);
-        atomicAdd(&cnt[b], 1);
+        int64_t i, j;
+        pair_of_index(p, i, j);
+        const double c[3] = {0.5 * (xyz[3 * i] + xyz[3 * j]), 0.5 * (xyz[3 * i + 1] + xyz[3 * j + 1]),
+                             0.5 * (xyz[3 * i + 2] + xyz[3 * j + 2])};
+        b = q_band(qp) * kNumCells + morton_cell(c, hdr);
+        atomicAdd((unsigned long long *)&cnt[b], 1ULL);
     }
     bucket_of[p] = b;
 }
 
-// Exclusive scan of the bucket counts (one block); also the significant-pair total.
-__global__ __launch_bounds__(1024) void k_bucket_scan(const int *__restrict__ cnt, int *__restrict__ off,
-                                                      int *__restrict__ cur, DevHeader *__restrict__ hdr)
+// Bucket offsets -> cursors (int) and the significant-pair total.
+__global__ __launch_bounds__(256) void k_bucket_cursors(const long long *__restrict__ off, int *__restrict__ cur,
+                                                        DevHeader *__restrict__ hdr)
 {
-    constexpr int per = kNumBuckets / 1024;
-    __shared__ int part[1024];
-    const int t = threadIdx.x;
-    int local[per];
-    int s = 0;
-    for (int i = 0; i < per; ++i) {
-        local[i] = s;
-        s += cnt[t * per + i];
-    }
-    part[t] = s;
-    __syncthreads();
-    for (int w = 1; w < 1024; w <<= 1) {
-        int v = (t >= w) ? part[t - w] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    const int base = part[t] - s;
-    for (int i = 0; i < per; ++i) {
-        off[t * per + i] = base + local[i];
-        cur[t * per + i] = base + local[i];
-    }
-    if (t == 1023) {
-        off[kNumBuckets] = part[1023];
-        hdr->sig_pairs = part[1023];
-    }
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < kNumBuckets) cur[b] = (int)off[b];
+    if (b == 0) hdr->sig_pairs = (int)off[kNumBuckets];
 }
 
 // Writes every significant pair at its bucketed position: atoms, Q, D_kl and the SoA
@@ -217,7 +238,8 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
                                                       int *__restrict__ cur, int *__restrict__ pk,
                                                       int *__restrict__ pl, double *__restrict__ pq,
                                                       double *__restrict__ pd, double *__restrict__ prim,
-                                                      float *__restrict__ prim_f)
+                                                      float *__restrict__ prim_f, double *__restrict__ bra,
+                                                      float *__restrict__ bra_f)
 {
     const int64_t npair = n * (n + 1) / 2;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -246,6 +268,11 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
         prim_f[(1 * g2 + ab) * pcap + pos] = (float)py[ab];
         prim_f[(2 * g2 + ab) * pcap + pos] = (float)pz[ab];
         prim_f[(3 * g2 + ab) * pcap + pos] = (float)ps[ab];
+        double *ba = bra + (int64_t)pos * 4 * g2;
+        float *bf = bra_f + (int64_t)pos * 4 * g2;
+        ba[4 * ab] = px[ab]; ba[4 * ab + 1] = py[ab]; ba[4 * ab + 2] = pz[ab]; ba[4 * ab + 3] = ps[ab];
+        bf[4 * ab] = (float)px[ab]; bf[4 * ab + 1] = (float)py[ab]; bf[4 * ab + 2] = (float)pz[ab];
+        bf[4 * ab + 3] = (float)ps[ab];
     }
 }
 
@@ -271,10 +298,10 @@ __global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int 
 }
 
 // Ket range of every bra s (in bucketed order): kets t < lim_s with
-// lim_s = min(s + 1, end of the bucket holding tau / Q_s); items of kKetsPerItem kets.
+// lim_s = min(s + 1, end of the band holding tau / Q_s); items of kKetsPerItem kets.
 __global__ __launch_bounds__(256) void k_limits(const DevHeader *__restrict__ hdr, double tau,
                                                 const double *__restrict__ pq,
-                                                const int *__restrict__ boff,
+                                                const long long *__restrict__ boff,
                                                 long long *__restrict__ nitems, int *__restrict__ lims,
                                                 int64_t pcap)
 {
@@ -288,8 +315,8 @@ __global__ __launch_bounds__(256) void k_limits(const DevHeader *__restrict__ hd
         if (thr <= 0.0) {
             bend = S;
         } else {
-            const int bt = q_bucket(thr);
-            bend = (thr > 2.0) ? 0 : boff[bt + 1];
+            const int bt = q_band(thr);
+            bend = (thr > 2.0) ? 0 : (bt + 1 >= kNumBands ? S : boff[(bt + 1) * kNumCells]);
         }
         const int64_t lim = bend < s + 1 ? bend : s + 1;
         ni = (lim + kKetsPerItem - 1) / kKetsPerItem;
@@ -369,7 +396,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final(const long long *__re
     if (i < m) out[i] = excl;
     if (i == m - 1) {
         out[m] = excl + v;
-        *total = excl + v;
+        if (total) *total = excl + v;
     }
 }
 
@@ -383,23 +410,25 @@ hipError_t launch_scan(const long long *in, int64_t m, long long *out, long long
     return hipGetLastError();
 }
 
-__global__ void k_header_info(DevHeader *hdr, int strategy, int groups, int precision)
+__global__ void k_header_info(DevHeader *hdr, int strategy, int groups, int precision, int variant)
 {
     hdr->strategy = strategy;
     hdr->groups = groups;
     hdr->precision = precision;
+    hdr->variant = variant;
 }
 
-hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision, hipStream_t st)
+hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision, int variant, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_header_info, dim3(1), dim3(1), 0, st, (DevHeader *)hdr, strategy, groups, precision);
+    hipLaunchKernelGGL(k_header_info, dim3(1), dim3(1), 0, st, (DevHeader *)hdr, strategy, groups, precision,
+                       variant);
     return hipGetLastError();
 }
 
-__global__ void k_fill_i32(int *__restrict__ p, int64_t m, int v)
+__global__ void k_fill_i64(long long *__restrict__ p, int64_t m)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m) p[i] = v;
+    if (i < m) p[i] = 0;
 }
 
 hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
@@ -410,18 +439,21 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
     const int64_t np = L.npair;
     const int bs = 256;
     const unsigned nbp = (unsigned)((np + bs - 1) / bs);
-    int *cnt = (int *)(ws + L.bucket_cnt);
-    int *off = (int *)(ws + L.bucket_off);
+    long long *cnt = (long long *)(ws + L.bucket_cnt);
+    long long *off = (long long *)(ws + L.bucket_off);
     int *cur = (int *)(ws + L.bucket_cur);
-    hipLaunchKernelGGL(k_fill_i32, dim3((kNumBuckets + 255) / 256), dim3(256), 0, st, cnt, (int64_t)kNumBuckets, 0);
+    hipLaunchKernelGGL(k_fill_i64, dim3((kNumBuckets + 255) / 256), dim3(256), 0, st, cnt, (int64_t)kNumBuckets);
     hipLaunchKernelGGL(k_pair_q, dim3(nbp), dim3(bs), 0, st, b, bd, hdr, L.n, xyz, (double *)(ws + L.q_unsorted));
-    hipLaunchKernelGGL(k_bucket_count, dim3(nbp), dim3(bs), 0, st, np, tau, hdr,
+    hipLaunchKernelGGL(k_bucket_count, dim3(nbp), dim3(bs), 0, st, L.n, tau, hdr, xyz,
                        (const double *)(ws + L.q_unsorted), (int *)(ws + L.bucket_of), cnt);
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, st, cnt, off, cur, hdr);
+    hipError_t e = launch_scan(cnt, kNumBuckets, off, (long long *)(ws + L.scan_tmp), nullptr, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bucket_cursors, dim3((kNumBuckets + 255) / 256), dim3(256), 0, st, off, cur, hdr);
     hipLaunchKernelGGL(k_pair_scatter, dim3(nbp), dim3(bs), 0, st, b, bd, hdr, L.n, L.pcap, xyz, dens,
                        (const double *)(ws + L.q_unsorted), (const int *)(ws + L.bucket_of), cur,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
-                       (double *)(ws + L.prim), (float *)(ws + L.prim_f));
+                       (double *)(ws + L.prim), (float *)(ws + L.prim_f), (double *)(ws + L.bra),
+                       (float *)(ws + L.bra_f));
     hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, L.pcap, L.g2,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f));

@@ -19,34 +19,40 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
-def _run(torch_dev, s, precision="fp64", strategy=0):
+def _run(torch_dev, s, precision="fp64", strategy=0, variant=-1):
     import paper_2509_21039_amd as hfk
     torch, dev = torch_dev
+    hfk.set_config(variant, 0)
     xyz = torch.tensor(s.xyz, device=dev)
     D = torch.tensor(s.dens, device=dev)
     ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, len(s.exps), precision), dev)
     G, E2 = hfk.fock(xyz, D, s.exps, s.coefs, s.tau, precision=precision, strategy=strategy, workspace=ws)
     st = hfk.read_stats(ws)
+    hfk.set_config(-1, 0)
+    if variant >= 0:
+        assert st["variant"] == variant
     return G.cpu().numpy(), float(E2.item()), st
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("n,seed,box,tau", [(1, 1, 1.0, 0.0), (2, 2, 3.0, 0.0), (3, 3, 3.0, 0.0),
                                             (5, 4, 4.0, 0.0), (7, 5, 6.0, 1e-6), (8, 6, 12.0, 1e-8)])
-def test_tiny_vs_bruteforce(torch_dev, n, seed, box, tau):
+def test_tiny_vs_bruteforce(torch_dev, n, seed, box, tau, variant):
     s = random_cluster(n, seed, box=box, tau=tau)
-    announce("tiny n=%d seed=%d tau=%g" % (n, seed, tau))
-    G, E2, st = _run(torch_dev, s)
+    announce("tiny n=%d seed=%d tau=%g variant=%d" % (n, seed, tau, variant))
+    G, E2, st = _run(torch_dev, s, variant=variant)
     Gb, Eb = oracle.fock_bruteforce(s.xyz, s.dens, s.exps, s.coefs, tau)
     assert rel_fro(G, Gb) < FP64_TOL
     assert rel(E2, Eb) < FP64_TOL
     assert np.array_equal(G, G.T)
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("strategy", [1, 2])
-def test_he64_fp64_vs_oracle(torch_dev, strategy):
+def test_he64_fp64_vs_oracle(torch_dev, strategy, variant):
     s = config_system("he64_fp64")
-    announce("he64 fp64 strategy=%d" % strategy)
-    G, E2, st = _run(torch_dev, s, strategy=strategy)
+    announce("he64 fp64 strategy=%d variant=%d" % (strategy, variant))
+    G, E2, st = _run(torch_dev, s, strategy=strategy, variant=variant)
     Gr, Er, nsr = load_golden("he64_fp64")
     assert rel_fro(G, Gr) < FP64_TOL, rel_fro(G, Gr)
     assert rel(E2, Er) < FP64_TOL
@@ -57,10 +63,11 @@ def test_he64_fp64_vs_oracle(torch_dev, strategy):
     assert st["strategy"] == strategy
 
 
-def test_he64_mixed_vs_oracle(torch_dev):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_he64_mixed_vs_oracle(torch_dev, variant):
     s = config_system("he64_fp64")
-    announce("he64 mixed")
-    G, E2, st = _run(torch_dev, s, precision="mixed")
+    announce("he64 mixed variant=%d" % variant)
+    G, E2, st = _run(torch_dev, s, precision="mixed", variant=variant)
     Gr, Er, nsr = load_golden("he64_fp64")
     assert rel_fro(G, Gr) < MIXED_TOL, rel_fro(G, Gr)
     assert rel(E2, Er) < MIXED_TOL
