@@ -76,8 +76,8 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
     L.pd = take(sizeof(double) * PC);
     L.prim = take(sizeof(double) * 4 * g2 * PC);
     L.prim_f = take(sizeof(float) * 4 * g2 * PC);
-    L.bra = take(sizeof(double) * 4 * g2 * PC);
-    L.bra_f = take(sizeof(float) * 4 * g2 * PC);
+    L.bra = take(sizeof(double) * 8 * g2 * PC);
+    L.bra_f = take(sizeof(float) * 8 * g2 * PC);
     L.boys_off = take(sizeof(double) * kBoysGrid * kBoysStride);
     L.boys_off_f = take(sizeof(float) * kBoysGrid * kBoysStride);
     L.nitems = take(sizeof(long long) * PC);

@@ -156,17 +156,21 @@ __device__ inline R quartet_eri_direct(const R *__restrict__ lbra, const R *__re
 // spatially sorted), the lanes add the far-field value S_cd / |P-Q| (exact beyond the
 // switch); otherwise every lane evaluates H(T) from the Taylor table or its far-field
 // form.  Lanes without a kept quartet get ket centres far away, so they are never near.
-// Uniform data (bra primitives, rho and sqrt(rho) per primitive quartet) come through
-// scalar loads.
+// Uniform data come through scalar loads: per bra primitive (Px, Py, Pz, S, -2Px, -2Py,
+// -2Pz, |P|^2) and per primitive quartet (rho, sqrt(rho), switch radius^2).
+// FP64 forms |P-Q|^2 as |P|^2 + |Q|^2 - 2 P.Q (4 operations; with centroid-centred
+// coordinates the cancellation stays near 1e-13 bohr^2 absolute); FP32 subtracts the
+// centres directly, which its precision needs.
 template <int G, typename R>
 __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, int64_t pcap, int64_t t,
                                        bool valid, cptr<R> rs, const R *__restrict__ tab)
 {
     constexpr int G2 = G * G;
+    constexpr bool kExpand = sizeof(R) == 8;
     R eri = R(0);
 #pragma unroll 1
     for (int cb = 0; cb < G; ++cb) {
-        R kx[G], ky[G], kz[G], ks[G];
+        R kx[G], ky[G], kz[G], ks[G], kq[G];
 #pragma unroll
         for (int d = 0; d < G; ++d) {
             const int cd = cb * G + d;
@@ -174,24 +178,29 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
             ky[d] = prim[(int64_t)(1 * G2 + cd) * pcap + t];
             kz[d] = valid ? prim[(int64_t)(2 * G2 + cd) * pcap + t] : R(1e10);
             ks[d] = prim[(int64_t)(3 * G2 + cd) * pcap + t];
+            kq[d] = kx[d] * kx[d] + ky[d] * ky[d] + kz[d] * kz[d];
         }
-#pragma unroll 3
+#pragma unroll 1
         for (int ab = 0; ab < G2; ++ab) {
-            const R px = bra[4 * ab], py = bra[4 * ab + 1], pz = bra[4 * ab + 2];
+            cptr<R> b = bra + 8 * ab;
             R acc = R(0);
 #pragma unroll
             for (int d = 0; d < G; ++d) {
                 const int x = ab * G2 + cb * G + d;
-                const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
-                const R r2 = dx * dx + dy * dy + dz * dz;
-                const R T = r2 * rs[2 * x];
-                if (__builtin_amdgcn_ballot_w64(T < R(kTswitch))) {
-                    acc += (ks[d] * rs[2 * x + 1]) * boys_h<R>(T, tab);
+                R r2;
+                if (kExpand) {
+                    r2 = fma(b[4], kx[d], fma(b[5], ky[d], fma(b[6], kz[d], kq[d] + b[7])));
+                } else {
+                    const R dx = b[0] - kx[d], dy = b[1] - ky[d], dz = b[2] - kz[d];
+                    r2 = dx * dx + dy * dy + dz * dz;
+                }
+                if (__builtin_amdgcn_ballot_w64(r2 < rs[3 * x + 2])) {
+                    acc += (ks[d] * rs[3 * x + 1]) * boys_h<R>(r2 * rs[3 * x], tab);
                 } else {
                     acc = Prec<R>::far_acc(acc, ks[d], r2);
                 }
             }
-            eri += bra[4 * ab + 3] * acc;
+            eri += b[3] * acc;
         }
     }
     return eri;
@@ -302,8 +311,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
                 __syncthreads();
             }
             if (m == m1) break;
-            const R *br = Prec<R>::bra(a) + (int64_t)s * 4 * G2;
-            if (!kSplit && tid < 4 * G2) lbra[tid] = br[tid];
+            const R *br = Prec<R>::bra(a) + (int64_t)s * 8 * G2;
+            if (!kSplit && tid < 4 * G2) lbra[tid] = br[8 * (tid / 4) + tid % 4];
             if (tid == 0) {
                 bra_at[0] = a.pk[s];
                 bra_at[1] = a.pl[s];
@@ -330,7 +339,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
         const bool valid = in && (qs * qt >= a.tau);
         R eri;
         if (kSplit)
-            eri = quartet_eri_hybrid<G, R>((cptr<R>)(Prec<R>::bra(a) + (int64_t)s * 4 * G2), prim, a.pcap, t, valid,
+            eri = quartet_eri_hybrid<G, R>((cptr<R>)(Prec<R>::bra(a) + (int64_t)s * 8 * G2), prim, a.pcap, t, valid,
                                            crs, tab);
         else
             eri = quartet_eri_direct<G, R>(lbra, prim, a.pcap, t, luni, tab);

@@ -74,8 +74,8 @@ struct BasisDev {
     double rho[kMaxG2 * kMaxG2];    // p q / (p + q), [ab * g2 + cd]
     double srho[kMaxG2 * kMaxG2];   // sqrt(rho)
     double r2sw[kMaxG2 * kMaxG2];   // kTswitch / rho: |P-Q|^2 beyond which the far field is exact
-    double rs[2 * kMaxG2 * kMaxG2];     // (rho, sqrt(rho)) interleaved
-    float rs_f[2 * kMaxG2 * kMaxG2];
+    double rs[3 * kMaxG2 * kMaxG2];     // (rho, sqrt(rho), kTswitch / rho) interleaved
+    float rs_f[3 * kMaxG2 * kMaxG2];
     float rho_f[kMaxG2 * kMaxG2];
     float srho_f[kMaxG2 * kMaxG2];
     float r2sw_f[kMaxG2 * kMaxG2];
@@ -91,7 +91,7 @@ struct Layout {
     size_t pk, pl, pq, pd;                 // sorted pair tables
     size_t prim;                           // [4][g2][pcap] doubles: Px, Py, Pz, S
     size_t prim_f;                         // [4][g2][pcap] floats (mixed)
-    size_t bra, bra_f;                     // [pcap][4][g2] (AoS copy read as wave-uniform bra data)
+    size_t bra, bra_f;                     // [pcap][g2][8] Px Py Pz S -2Px -2Py -2Pz |P|^2 (wave-uniform bra data)
     size_t boys_off, boys_off_f;           // Boys table with the far-field value at the switch removed
     size_t nitems, lim, item_off, scan_tmp;
     size_t fpriv;                          // [groups][n*n] or [n*n]

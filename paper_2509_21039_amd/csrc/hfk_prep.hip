@@ -31,10 +31,12 @@ __global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ b
         bd->srho[x] = sqrt(rho);
         bd->r2sw[x] = kTswitch / rho;
         bd->rho_f[x] = (float)rho;
-        bd->rs[2 * x] = rho;
-        bd->rs[2 * x + 1] = sqrt(rho);
-        bd->rs_f[2 * x] = (float)rho;
-        bd->rs_f[2 * x + 1] = (float)sqrt(rho);
+        bd->rs[3 * x] = rho;
+        bd->rs[3 * x + 1] = sqrt(rho);
+        bd->rs[3 * x + 2] = kTswitch / rho;
+        bd->rs_f[3 * x] = (float)rho;
+        bd->rs_f[3 * x + 1] = (float)sqrt(rho);
+        bd->rs_f[3 * x + 2] = (float)(kTswitch / rho);
         bd->srho_f[x] = (float)sqrt(rho);
         bd->r2sw_f[x] = (float)(kTswitch / rho);
     }
@@ -268,11 +270,14 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
         prim_f[(1 * g2 + ab) * pcap + pos] = (float)py[ab];
         prim_f[(2 * g2 + ab) * pcap + pos] = (float)pz[ab];
         prim_f[(3 * g2 + ab) * pcap + pos] = (float)ps[ab];
-        double *ba = bra + (int64_t)pos * 4 * g2;
-        float *bf = bra_f + (int64_t)pos * 4 * g2;
-        ba[4 * ab] = px[ab]; ba[4 * ab + 1] = py[ab]; ba[4 * ab + 2] = pz[ab]; ba[4 * ab + 3] = ps[ab];
-        bf[4 * ab] = (float)px[ab]; bf[4 * ab + 1] = (float)py[ab]; bf[4 * ab + 2] = (float)pz[ab];
-        bf[4 * ab + 3] = (float)ps[ab];
+        double *ba = bra + ((int64_t)pos * g2 + ab) * 8;
+        float *bf = bra_f + ((int64_t)pos * g2 + ab) * 8;
+        const double pp = px[ab] * px[ab] + py[ab] * py[ab] + pz[ab] * pz[ab];
+        ba[0] = px[ab]; ba[1] = py[ab]; ba[2] = pz[ab]; ba[3] = ps[ab];
+        ba[4] = -2.0 * px[ab]; ba[5] = -2.0 * py[ab]; ba[6] = -2.0 * pz[ab]; ba[7] = pp;
+        bf[0] = (float)px[ab]; bf[1] = (float)py[ab]; bf[2] = (float)pz[ab]; bf[3] = (float)ps[ab];
+        bf[4] = (float)(-2.0 * px[ab]); bf[5] = (float)(-2.0 * py[ab]); bf[6] = (float)(-2.0 * pz[ab]);
+        bf[7] = (float)pp;
     }
 }
 
