@@ -222,7 +222,6 @@ def _autograd():
             ctx.basis = (np.asarray(exps, dtype=np.float64).copy(), np.asarray(coefs, dtype=np.float64).copy())
             ctx.tau = tau
             ctx.precision = precision
-            ctx.mark_non_differentiable(G)
             return G, E2
 
         @staticmethod

@@ -78,8 +78,8 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
     L.prim_f = take(sizeof(float) * 4 * g2 * PC);
     L.bra = take(sizeof(double) * 8 * g2 * PC);
     L.bra_f = take(sizeof(float) * 8 * g2 * PC);
-    L.boys_off = take(sizeof(double) * kBoysGrid * kBoysStride);
-    L.boys_off_f = take(sizeof(float) * kBoysGrid * kBoysStride);
+    L.boys_g = take(sizeof(double) * kBoysGrid * kBoysStride);
+    L.boys_g_f = take(sizeof(float) * kBoysGrid * kBoysStride);
     L.nitems = take(sizeof(long long) * PC);
     L.lim = take(sizeof(int) * PC);
     L.item_off = take(sizeof(long long) * (PC + 1));
@@ -137,6 +137,9 @@ static Basis make_basis(int32_t ngauss, const double *exps, const double *coefs)
 
 // n above which rows i and j of F no longer fit in one workgroup's LDS next to the Boys table
 constexpr int64_t kMaxAtoms = 6144;
+// n above which the gradient kernel's LDS copy of dE2/dR (n x 3) and its two tables no longer fit
+constexpr int64_t kMaxGradAtoms = 4096;
+constexpr int kGradGroupsPerCU = 2;
 
 // Tuned strategy per (precision, size class); 0 = not tuned.
 static std::mutex g_tune_mu;
@@ -290,8 +293,8 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys),
-                                (float *)(ws + L.boys_f), (double *)(ws + L.boys_off),
-                                (float *)(ws + L.boys_off_f), (DevHeader *)(ws + L.hdr), natoms, xyz, st);
+                                (float *)(ws + L.boys_f), (double *)(ws + L.boys_g),
+                                (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz, st);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
     e = launch_pairs(L, b, ws, xyz, dens, tau, st);
     if (e != hipSuccess) return hip_fail(e, "pair launch");
@@ -332,9 +335,34 @@ hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss, cons
     g_err[0] = 0;
     hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision);
     if (s != HFK_OK) return s;
-    (void)g_e2; (void)fock_in; (void)d_xyz; (void)d_dens; (void)e2_out; (void)workspace;
-    (void)workspace_bytes; (void)stream;
-    return fail(HFK_EUNSUPPORTED, "gradient not built yet");
+    if (!g_e2) return fail(HFK_EINVAL, "g_e2 is NULL");
+    if (!d_xyz) return fail(HFK_EINVAL, "d_xyz is NULL");
+    if (d_dens && !fock_in) return fail(HFK_EINVAL, "d_dens needs fock_in");
+    if (!workspace) return fail(HFK_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
+    if (natoms > kMaxGradAtoms)
+        return fail(HFK_EUNSUPPORTED, "gradient supports natoms <= %lld", (long long)kMaxGradAtoms);
+    if (ngauss > 4) return fail(HFK_EUNSUPPORTED, "ngauss above 4 is not built in this version");
+    const int cus = device_cu_count();
+    if (cus <= 0) return fail(HFK_EHIP, "no HIP device");
+    Layout L = make_layout(natoms, ngauss, precision, 1, groups_cap(cus));
+    if (workspace_bytes < L.total)
+        return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
+    L.groups = cus * kGradGroupsPerCU;
+    const Basis b = make_basis(ngauss, exps_host, coefs_host);
+    char *ws = (char *)workspace;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (float *)(ws + L.boys_f),
+                                (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr),
+                                natoms, xyz, st);
+    if (e != hipSuccess) return hip_fail(e, "setup launch");
+    e = launch_pairs(L, b, ws, xyz, dens, tau, st);
+    if (e != hipSuccess) return hip_fail(e, "pair launch");
+    e = launch_grad(L, b, ws, xyz, dens, tau, precision, g_e2, fock_in, d_xyz, d_dens, e2_out, st);
+    if (e != hipSuccess) return hip_fail(e, "gradient launch");
+    e = launch_header_info(ws + L.hdr, 0, L.groups, precision, -1, st);
+    if (e != hipSuccess) return hip_fail(e, "header launch");
+    return HFK_OK;
 }
 
 hfk_status hfk_batched_workspace_bytes(int64_t nmol, const int64_t *atom_off_host, int32_t ngauss,

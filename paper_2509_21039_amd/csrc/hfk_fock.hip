@@ -25,8 +25,6 @@ struct FockArgs {
     const BasisDev *bd;
     const double *boys;
     const float *boys_f;
-    const double *boys_off;
-    const float *boys_off_f;
     const int *pk;
     const int *pl;
     const double *pq;
@@ -52,7 +50,6 @@ template <> struct Prec<double> {
     static __device__ const double *prim(const FockArgs &a) { return a.prim; }
     static __device__ const double *bra(const FockArgs &a) { return a.bra; }
     static __device__ const double *boys(const FockArgs &a) { return a.boys; }
-    static __device__ const double *boys_off(const FockArgs &a) { return a.boys_off; }
     static __device__ const double *rho(const BasisDev *bd) { return bd->rho; }
     static __device__ const double *srho(const BasisDev *bd) { return bd->srho; }
     static __device__ const double *r2sw(const BasisDev *bd) { return bd->r2sw; }
@@ -70,7 +67,6 @@ template <> struct Prec<float> {
     static __device__ const float *prim(const FockArgs &a) { return a.prim_f; }
     static __device__ const float *bra(const FockArgs &a) { return a.bra_f; }
     static __device__ const float *boys(const FockArgs &a) { return a.boys_f; }
-    static __device__ const float *boys_off(const FockArgs &a) { return a.boys_off_f; }
     static __device__ const float *rho(const BasisDev *bd) { return bd->rho_f; }
     static __device__ const float *srho(const BasisDev *bd) { return bd->srho_f; }
     static __device__ const float *r2sw(const BasisDev *bd) { return bd->r2sw_f; }
@@ -473,8 +469,6 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.bd = (const BasisDev *)(ws + L.basis);
     a.boys = (const double *)(ws + L.boys);
     a.boys_f = (const float *)(ws + L.boys_f);
-    a.boys_off = (const double *)(ws + L.boys_off);
-    a.boys_off_f = (const float *)(ws + L.boys_off_f);
     a.pk = (const int *)(ws + L.pk);
     a.pl = (const int *)(ws + L.pl);
     a.pq = (const double *)(ws + L.pq);

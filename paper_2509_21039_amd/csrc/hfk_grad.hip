@@ -1,0 +1,376 @@
+// Backward of the two-electron energy: dE2/dR for every atom, contracting derivative
+// integrals with density products over the same screened unique quartets as the forward
+// build (screening decisions held fixed), and dE2/dD = G.
+//
+//   E2 = sum_unique Gamma (ij|kl),   Gamma = deg (4 D_ij D_kl - D_ik D_jl - D_il D_jk)
+//   (ab|cd) = S_ab S_cd E(r),  E(r) = erf(sqrt(rho) r)/r = sqrt(rho) H(T),  T = rho r^2,
+//   W(r) = E'(r)/r = rho^(3/2) g(T),  g(T) = -(4/sqrt(pi)) F1(T)
+//   d(ab|cd)/dA = S_ab S_cd [ -2 mu_ab (A-B) E + (a/p) (P-Q) W ]
+//   d(ab|cd)/dB = S_ab S_cd [ +2 mu_ab (A-B) E + (b/p) (P-Q) W ]
+//   d(ab|cd)/dC = S_ab S_cd [ -2 mu_cd (C-D) E - (c/q) (P-Q) W ]
+//   d(ab|cd)/dD = -(dA + dB + dC)            (translation invariance)
+// Beyond the switch E = 1/r and W = -1/r^3 exactly; below it both come from Taylor tables.
+//
+// Work decomposition as in the forward kernel (items of 256 kets of one bra, one contiguous
+// item range per workgroup, one 64-ket chunk per wave).  Bra-atom gradients accumulate in
+// registers and are reduced across the wave when the bra changes; ket-atom gradients go to
+// an LDS copy of the n x 3 gradient; each workgroup writes its copy out once.
+#include "hfk_device.hpp"
+
+namespace hfk {
+
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+
+struct GradArgs {
+    const DevHeader *hdr;
+    const BasisDev *bd;
+    const double *tabH;
+    const float *tabH_f;
+    const double *tabG;
+    const float *tabG_f;
+    const int *pk;
+    const int *pl;
+    const double *pq;
+    const double *pd;
+    const double *prim;
+    const float *prim_f;
+    const double *bra;
+    const float *bra_f;
+    const long long *item_off;
+    const int *lim;
+    const double *dens;
+    const double *xyz;
+    double *gpriv;      // [groups][n*3]
+    double *epart;      // [groups]
+    int64_t pcap;
+    double tau;
+    int n;
+};
+
+template <typename R> struct GPrec;
+template <> struct GPrec<double> {
+    static __device__ const double *prim(const GradArgs &a) { return a.prim; }
+    static __device__ const double *bra(const GradArgs &a) { return a.bra; }
+    static __device__ const double *tabH(const GradArgs &a) { return a.tabH; }
+    static __device__ const double *tabG(const GradArgs &a) { return a.tabG; }
+    static __device__ const double *rs(const BasisDev *bd) { return bd->rs; }
+    static __device__ double rsqrt(double x) { return rsqrt_fp64(x); }
+};
+template <> struct GPrec<float> {
+    static __device__ const float *prim(const GradArgs &a) { return a.prim_f; }
+    static __device__ const float *bra(const GradArgs &a) { return a.bra_f; }
+    static __device__ const float *tabH(const GradArgs &a) { return a.tabH_f; }
+    static __device__ const float *tabG(const GradArgs &a) { return a.tabG_f; }
+    static __device__ const float *rs(const BasisDev *bd) { return bd->rs_f; }
+    static __device__ float rsqrt(float x) { return rsqrt_fp32(x); }
+};
+
+// h = H(T), g = g(T): shared Taylor row below the switch, T^(-1/2) and -T^(-3/2) above it.
+template <typename R>
+__device__ inline void boys_hg(R T, const R *__restrict__ tH, const R *__restrict__ tG, R &h, R &g)
+{
+    const R y = GPrec<R>::rsqrt(fmax(T, R(1e-30)));
+    const R Tc = fmin(T, R(kTswitch + 0.5));
+    const int k = (int)(Tc * R(kBoysInvH) + R(0.5));
+    const R d = Tc - (R)k * R(kBoysH);
+    const R *c = tH + k * kBoysStride;
+    const R *e = tG + k * kBoysStride;
+    R vh = c[6], vg = e[6];
+#pragma unroll
+    for (int m = 5; m >= 0; --m) {
+        vh = vh * d + c[m];
+        vg = vg * d + e[m];
+    }
+    const bool near = T < R(kTswitch);
+    h = near ? vh : y;
+    g = near ? vg : -(y * y * y);
+}
+
+template <int G, typename R>
+__global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
+{
+    constexpr int G2 = G * G;
+    extern __shared__ double smem[];
+    const int n = a.n;
+    double *lg = smem;                                   // [n*3]
+    R *tH = (R *)(smem + 3 * n);
+    R *tG = tH + kBoysGrid * kBoysStride;
+    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    const int gid = blockIdx.x, ng = gridDim.x;
+    const long long M = a.hdr->items;
+    const int S = a.hdr->sig_pairs;
+    const long long m0 = M * gid / ng, m1 = M * (gid + 1) / ng;
+    const BasisDev *bd = a.bd;
+    for (int x = tid; x < 3 * n; x += kGroupThreads) lg[x] = 0.0;
+    for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) {
+        tH[x] = GPrec<R>::tabH(a)[x];
+        tG[x] = GPrec<R>::tabG(a)[x];
+    }
+    __syncthreads();
+
+    double eacc = 0.0;
+    if (m0 < m1) {
+        int s;
+        {
+            int lo = 0, hi = S - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.item_off[mid] <= m0) lo = mid; else hi = mid - 1;
+            }
+            s = lo;
+        }
+        const R *prim = GPrec<R>::prim(a);
+        const cptr<R> rs = (cptr<R>)GPrec<R>::rs(bd);
+        const cptr<double> cmu = (cptr<double>)bd->mu;
+        const cptr<double> cfa = (cptr<double>)bd->fa;
+        const cptr<double> cfb = (cptr<double>)bd->fb;
+        int cur = -1, bi = 0, bj = 0, lim = 0;
+        double qs = 0.0, ds = 0.0;
+        double ABx = 0.0, ABy = 0.0, ABz = 0.0;
+        double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
+        for (long long m = m0; m <= m1; ++m) {
+            if (m < m1) {
+                while (a.item_off[s + 1] <= m) ++s;
+            }
+            if (m == m1 || s != cur) {
+                if (cur >= 0) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double wa = wave_sum(gA[c]), wb = wave_sum(gB[c]);
+                        if (lane == 0) {
+                            atomicAdd(&lg[3 * bi + c], wa);
+                            atomicAdd(&lg[3 * bj + c], wb);
+                        }
+                        gA[c] = gB[c] = 0.0;
+                    }
+                }
+                if (m == m1) break;
+                cur = s;
+                bi = a.pk[s];
+                bj = a.pl[s];
+                qs = a.pq[s];
+                ds = a.pd[s];
+                lim = a.lim[s];
+                ABx = a.xyz[3 * bi] - a.xyz[3 * bj];
+                ABy = a.xyz[3 * bi + 1] - a.xyz[3 * bj + 1];
+                ABz = a.xyz[3 * bi + 2] - a.xyz[3 * bj + 2];
+            }
+            const long long t0 = (m - a.item_off[s]) * kKetsPerItem + (long long)wave * kWave;
+            if (t0 >= lim) continue;
+            const long long t = t0 + lane;
+            const bool valid = (t < lim) && (qs * a.pq[t] >= a.tau);
+            const cptr<R> bra = (cptr<R>)(GPrec<R>::bra(a) + (int64_t)s * 8 * G2);
+
+            R sX = R(0), eri = R(0);
+            R sYa[3] = {R(0), R(0), R(0)}, sYb[3] = {R(0), R(0), R(0)};
+            double kC[3] = {0.0, 0.0, 0.0};
+            const int k = a.pk[t], l = a.pl[t];
+            const double CDx = a.xyz[3 * k] - a.xyz[3 * l];
+            const double CDy = a.xyz[3 * k + 1] - a.xyz[3 * l + 1];
+            const double CDz = a.xyz[3 * k + 2] - a.xyz[3 * l + 2];
+#pragma unroll 1
+            for (int cb = 0; cb < G; ++cb) {
+                R kx[G], ky[G], kz[G], ks[G];
+                R Uc[G], Vc[G][3];
+#pragma unroll
+                for (int d = 0; d < G; ++d) {
+                    const int cd = cb * G + d;
+                    kx[d] = prim[(int64_t)(0 * G2 + cd) * a.pcap + t];
+                    ky[d] = prim[(int64_t)(1 * G2 + cd) * a.pcap + t];
+                    kz[d] = valid ? prim[(int64_t)(2 * G2 + cd) * a.pcap + t] : R(1e10);
+                    ks[d] = prim[(int64_t)(3 * G2 + cd) * a.pcap + t];
+                    Uc[d] = R(0);
+                    Vc[d][0] = Vc[d][1] = Vc[d][2] = R(0);
+                }
+#pragma unroll 1
+                for (int ab = 0; ab < G2; ++ab) {
+                    cptr<R> b = bra + 8 * ab;
+                    const R px = b[0], py = b[1], pz = b[2], sab = b[3];
+                    R U = R(0), V0 = R(0), V1 = R(0), V2 = R(0);
+#pragma unroll
+                    for (int d = 0; d < G; ++d) {
+                        const int x = ab * G2 + cb * G + d;
+                        const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
+                        const R r2 = dx * dx + dy * dy + dz * dz;
+                        R E, W;
+                        if (__builtin_amdgcn_ballot_w64(r2 < rs[3 * x + 2])) {
+                            R h, gg;
+                            const R rho = rs[3 * x], srho = rs[3 * x + 1];
+                            boys_hg<R>(r2 * rho, tH, tG, h, gg);
+                            E = srho * h;
+                            W = (rho * srho) * gg;
+                        } else {
+                            const R y = GPrec<R>::rsqrt(r2);
+                            E = y;
+                            W = -(y * y * y);
+                        }
+                        const R wk = ks[d] * W, wb = sab * W;
+                        U += ks[d] * E;
+                        V0 += wk * dx;
+                        V1 += wk * dy;
+                        V2 += wk * dz;
+                        Uc[d] += sab * E;
+                        Vc[d][0] += wb * dx;
+                        Vc[d][1] += wb * dy;
+                        Vc[d][2] += wb * dz;
+                    }
+                    const R su = sab * U;
+                    eri += su;
+                    sX += (R)cmu[ab] * su;
+                    const R fa = (R)cfa[ab] * sab, fb = (R)cfb[ab] * sab;
+                    sYa[0] += fa * V0; sYa[1] += fa * V1; sYa[2] += fa * V2;
+                    sYb[0] += fb * V0; sYb[1] += fb * V1; sYb[2] += fb * V2;
+                }
+#pragma unroll
+                for (int d = 0; d < G; ++d) {
+                    const int cd = cb * G + d;
+                    const double sc = (double)ks[d];
+                    const double mu2 = -2.0 * cmu[cd] * sc * (double)Uc[d];
+                    const double fc = cfa[cd] * sc;
+                    kC[0] += mu2 * CDx - fc * (double)Vc[d][0];
+                    kC[1] += mu2 * CDy - fc * (double)Vc[d][1];
+                    kC[2] += mu2 * CDz - fc * (double)Vc[d][2];
+                }
+            }
+            if (valid) {
+                double deg = 1.0;
+                if (bi == bj) deg *= 0.5;
+                if (k == l) deg *= 0.5;
+                if (t == s) deg *= 0.5;
+                const double *Di = a.dens + (int64_t)bi * n, *Dj = a.dens + (int64_t)bj * n;
+                const double gam = deg * (4.0 * ds * a.pd[t] - Di[k] * Dj[l] - Di[l] * Dj[k]);
+                const double AB[3] = {ABx, ABy, ABz};
+                double GA[3], GB[3], GC[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    GA[c] = gam * (-2.0 * AB[c] * (double)sX + (double)sYa[c]);
+                    GB[c] = gam * (2.0 * AB[c] * (double)sX + (double)sYb[c]);
+                    GC[c] = gam * kC[c];
+                    gA[c] += GA[c];
+                    gB[c] += GB[c];
+                    atomicAdd(&lg[3 * k + c], GC[c]);
+                    atomicAdd(&lg[3 * l + c], -(GA[c] + GB[c] + GC[c]));
+                }
+                eacc += gam * (double)eri;
+            }
+        }
+    }
+    // energy partial of the workgroup
+    __shared__ double ered[kWavesPerGroup];
+    const double ew = wave_sum(eacc);
+    if (lane == 0) ered[wave] = ew;
+    __syncthreads();
+    double *gp = a.gpriv + (int64_t)gid * 3 * n;
+    for (int x = tid; x < 3 * n; x += kGroupThreads) gp[x] = lg[x];
+    if (tid == 0) {
+        double e = 0.0;
+        for (int w = 0; w < kWavesPerGroup; ++w) e += ered[w];
+        a.epart[gid] = e;
+    }
+}
+
+// d_xyz = g_e2 * sum over workgroups; E2 = sum of partials (fixed order); d_dens = g_e2 * G.
+__global__ __launch_bounds__(256) void k_grad_reduce(const double *__restrict__ gpriv, int groups, int64_t m,
+                                                     const double *__restrict__ g_e2, double *__restrict__ d_xyz)
+{
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= m) return;
+    double s = 0.0;
+    for (int gph = 0; gph < groups; ++gph) s += gpriv[(int64_t)gph * m + x];
+    d_xyz[x] = g_e2[0] * s;
+}
+
+__global__ __launch_bounds__(256) void k_grad_energy(const double *__restrict__ epart, int groups,
+                                                     double *__restrict__ e2)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < groups; b += 256) s += epart[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *e2 = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_scale_copy(const double *__restrict__ src, int64_t m,
+                                                    const double *__restrict__ g_e2, double *__restrict__ dst)
+{
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < m) dst[x] = g_e2[0] * src[x];
+}
+
+size_t grad_smem_bytes(int64_t n, int prec)
+{
+    return sizeof(double) * 3 * (size_t)n +
+           2 * (size_t)kBoysGrid * kBoysStride * (prec == HFK_MIXED ? sizeof(float) : sizeof(double));
+}
+
+template <int G, typename R>
+static hipError_t launch_grad_t(const GradArgs &a, int groups, size_t smem, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_grad<G, R>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
+                       double tau, int prec, const double *g_e2, const double *fock_in, double *d_xyz,
+                       double *d_dens, double *e2_out, hipStream_t st)
+{
+    GradArgs a;
+    a.hdr = (const DevHeader *)(ws + L.hdr);
+    a.bd = (const BasisDev *)(ws + L.basis);
+    a.tabH = (const double *)(ws + L.boys);
+    a.tabH_f = (const float *)(ws + L.boys_f);
+    a.tabG = (const double *)(ws + L.boys_g);
+    a.tabG_f = (const float *)(ws + L.boys_g_f);
+    a.pk = (const int *)(ws + L.pk);
+    a.pl = (const int *)(ws + L.pl);
+    a.pq = (const double *)(ws + L.pq);
+    a.pd = (const double *)(ws + L.pd);
+    a.prim = (const double *)(ws + L.prim);
+    a.prim_f = (const float *)(ws + L.prim_f);
+    a.bra = (const double *)(ws + L.bra);
+    a.bra_f = (const float *)(ws + L.bra_f);
+    a.item_off = (const long long *)(ws + L.item_off);
+    a.lim = (const int *)(ws + L.lim);
+    a.dens = dens;
+    a.xyz = xyz;
+    a.gpriv = (double *)(ws + L.grad);
+    a.epart = (double *)(ws + L.grad) + (size_t)L.groups * 3 * L.n;
+    a.pcap = L.pcap;
+    a.tau = tau;
+    a.n = (int)L.n;
+    const size_t smem = grad_smem_bytes(L.n, prec);
+    hipError_t err;
+    if (prec == HFK_MIXED) {
+        switch (b.g) {
+        case 1: err = launch_grad_t<1, float>(a, L.groups, smem, st); break;
+        case 2: err = launch_grad_t<2, float>(a, L.groups, smem, st); break;
+        case 3: err = launch_grad_t<3, float>(a, L.groups, smem, st); break;
+        default: err = launch_grad_t<4, float>(a, L.groups, smem, st); break;
+        }
+    } else {
+        switch (b.g) {
+        case 1: err = launch_grad_t<1, double>(a, L.groups, smem, st); break;
+        case 2: err = launch_grad_t<2, double>(a, L.groups, smem, st); break;
+        case 3: err = launch_grad_t<3, double>(a, L.groups, smem, st); break;
+        default: err = launch_grad_t<4, double>(a, L.groups, smem, st); break;
+        }
+    }
+    if (err != hipSuccess) return err;
+    const int64_t m = 3 * L.n;
+    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, a.gpriv, L.groups, m,
+                       g_e2, d_xyz);
+    if (e2_out) hipLaunchKernelGGL(k_grad_energy, dim3(1), dim3(256), 0, st, a.epart, L.groups, e2_out);
+    if (d_dens) {
+        const int64_t n2 = L.n * L.n;
+        hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, fock_in, n2, g_e2,
+                           d_dens);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hfk

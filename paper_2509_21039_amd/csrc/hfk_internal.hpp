@@ -23,8 +23,8 @@ constexpr int kNumBuckets = kNumBands * kNumCells;
 
 // Boys function table: F0 Taylor expansion about T_k = k h, k = 0 .. kBoysGrid-1.
 // Coefficient n of row k is (2/sqrt(pi)) (-1)^n F_n(T_k) / n!, so that
-// H(T) = erf(sqrt T)/sqrt T = sum_n c_n (T - T_k)^n near T_k.  Row 0 of the offset table
-// subtracts the far-field value at kTswitch (used by the deferred near-field path).
+// H(T) = erf(sqrt T)/sqrt T = sum_n c_n (T - T_k)^n near T_k.  A second table holds the
+// expansion of g(T) = -(4/sqrt(pi)) F1(T) for the gradient.
 constexpr int kBoysOrder = 7;          // coefficients used (degree 6)
 constexpr int kBoysStride = 9;         // row length: odd in doubles, so rows start on 16 different LDS bank pairs
 constexpr double kBoysH = 0.125;       // grid spacing
@@ -92,7 +92,7 @@ struct Layout {
     size_t prim;                           // [4][g2][pcap] doubles: Px, Py, Pz, S
     size_t prim_f;                         // [4][g2][pcap] floats (mixed)
     size_t bra, bra_f;                     // [pcap][g2][8] Px Py Pz S -2Px -2Py -2Pz |P|^2 (wave-uniform bra data)
-    size_t boys_off, boys_off_f;           // Boys table with the far-field value at the switch removed
+    size_t boys_g, boys_g_f;               // Taylor table of g(T) = -(4/sqrt(pi)) F1(T) (gradient)
     size_t nitems, lim, item_off, scan_tmp;
     size_t fpriv;                          // [groups][n*n] or [n*n]
     size_t jcol;                           // [groups][pcap]
@@ -108,8 +108,8 @@ int device_cu_count();
 
 // ------------------------------------------------------------------ launchers
 // Each returns hipSuccess or the launch error; all enqueue on `st`.
-hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, double *boys_off,
-                        float *boys_off_f, DevHeader *hdr, int64_t n, const double *xyz, hipStream_t st);
+hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, double *boys_g,
+                        float *boys_g_f, DevHeader *hdr, int64_t n, const double *xyz, hipStream_t st);
 hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
                         double tau, hipStream_t st);
 hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *dens, double tau,
@@ -123,8 +123,9 @@ hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision
                               hipStream_t st);
 hipError_t launch_scan(const long long *in, int64_t m, long long *out, long long *tmp, long long *total,
                        hipStream_t st);
-hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *dens, double tau,
-                       int prec, const double *g_e2, const double *fock_in, double *d_xyz,
+hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
+                       double tau, int prec, const double *g_e2, const double *fock_in, double *d_xyz,
                        double *d_dens, double *e2_out, hipStream_t st);
+size_t grad_smem_bytes(int64_t n, int prec);
 
 }  // namespace hfk

@@ -85,44 +85,49 @@ __global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ b
     }
 }
 
-// Boys table: row k holds (2/sqrt(pi)) (-1)^m F_m(k h) / m!, m = 0..kBoysOrder-1, with
-// F_m from its positive Kummer series (all terms positive, no cancellation).
-__global__ void k_boys_table(double *__restrict__ tab, float *__restrict__ tab_f, double *__restrict__ toff,
-                             float *__restrict__ toff_f)
+// Boys tables.  Row k of `tab` holds (2/sqrt(pi)) (-1)^m F_m(k h) / m!, m = 0..kBoysOrder-1
+// (Taylor coefficients of H(T) = erf(sqrt T)/sqrt T about T_k), and row k of `tg` holds
+// -(4/sqrt(pi)) (-1)^m F_{m+1}(k h) / m! (Taylor coefficients of g(T) = -(4/sqrt(pi)) F1(T),
+// the radial derivative factor of the gradient).  F_m comes from its positive Kummer
+// series (no cancellation).
+__global__ void k_boys_table(double *__restrict__ tab, float *__restrict__ tab_f, double *__restrict__ tg,
+                             float *__restrict__ tg_f)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= kBoysGrid) return;
     const double T = k * kBoysH;
+    double fm[kBoysOrder + 1];
+    for (int m = 0; m <= kBoysOrder; ++m) {
+        double term = 1.0 / (2.0 * m + 1.0), sum = term;
+        for (int i = 1; i < 400; ++i) {
+            term *= 2.0 * T / (2.0 * m + 2.0 * i + 1.0);
+            sum += term;
+            if (term < 1e-18 * sum) break;
+        }
+        fm[m] = exp(-T) * sum;
+    }
     double fact = 1.0;
     for (int m = 0; m < kBoysStride; ++m) {
-        double v = 0.0;
+        double v = 0.0, w = 0.0;
         if (m < kBoysOrder) {
-            double term = 1.0 / (2.0 * m + 1.0), sum = term;
-            for (int i = 1; i < 400; ++i) {
-                term *= 2.0 * T / (2.0 * m + 2.0 * i + 1.0);
-                sum += term;
-                if (term < 1e-18 * sum) break;
-            }
-            const double fm = exp(-T) * sum;
             if (m > 0) fact *= (double)m;
-            v = kTwoOverSqrtPi * ((m & 1) ? -fm : fm) / fact;
+            const double sgn = (m & 1) ? -1.0 : 1.0;
+            v = kTwoOverSqrtPi * sgn * fm[m] / fact;
+            w = -2.0 * kTwoOverSqrtPi * sgn * fm[m + 1] / fact;
         }
         tab[k * kBoysStride + m] = v;
         tab_f[k * kBoysStride + m] = (float)v;
-        // offset table: H(T) - kTswitch^(-1/2) (the far-field value the clamped fast path
-        // already added for a near-field quartet)
-        const double vo = m == 0 ? v - 1.0 / sqrt(kTswitch) : v;
-        toff[k * kBoysStride + m] = vo;
-        toff_f[k * kBoysStride + m] = (float)vo;
+        tg[k * kBoysStride + m] = w;
+        tg_f[k * kBoysStride + m] = (float)w;
     }
 }
 
-hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, double *boys_off,
-                        float *boys_off_f, DevHeader *hdr, int64_t n, const double *xyz, hipStream_t st)
+hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, double *boys_g,
+                        float *boys_g_f, DevHeader *hdr, int64_t n, const double *xyz, hipStream_t st)
 {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, b, bd, hdr, n, xyz);
-    hipLaunchKernelGGL(k_boys_table, dim3((kBoysGrid + 63) / 64), dim3(64), 0, st, boys, boys_f, boys_off,
-                       boys_off_f);
+    hipLaunchKernelGGL(k_boys_table, dim3((kBoysGrid + 63) / 64), dim3(64), 0, st, boys, boys_f, boys_g,
+                       boys_g_f);
     return hipGetLastError();
 }
 

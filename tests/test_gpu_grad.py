@@ -1,0 +1,118 @@
+"""GPU parity of the backward kernel (dE2/dR, dE2/dD) against the CPU oracle and finite
+differences, through the C ABI and the autograd Function."""
+import numpy as np
+import pytest
+
+import oracle
+from he_inputs import config_system, random_cluster
+from gpu_util import announce, load_golden, rel, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda:0")
+
+
+def _grad(torch_dev, s, precision="fp64"):
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    xyz = torch.tensor(s.xyz, device=dev)
+    D = torch.tensor(s.dens, device=dev)
+    G, E2 = hfk.fock(xyz, D, s.exps, s.coefs, s.tau, precision=precision)
+    d_xyz, d_dens, E2g = hfk.fock_grad(xyz, D, s.exps, s.coefs, s.tau, precision=precision, fock_in=G)
+    torch.cuda.synchronize()
+    return d_xyz.cpu().numpy(), d_dens.cpu().numpy(), float(E2g.item()), G.cpu().numpy(), float(E2.item())
+
+
+@pytest.mark.parametrize("n,seed,box,tau", [(2, 1, 2.0, 0.0), (4, 2, 4.0, 0.0), (6, 3, 5.0, 0.0),
+                                            (8, 4, 9.0, 1e-8), (37, 5, 9.0, 1e-10)])
+def test_grad_vs_oracle(torch_dev, n, seed, box, tau):
+    s = random_cluster(n, seed, box=box, tau=tau)
+    announce("grad n=%d seed=%d tau=%g" % (n, seed, tau))
+    g, dD, E2g, G, E2 = _grad(torch_dev, s)
+    gr, Er, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, tau)
+    assert rel_fro(g, gr) < FP64_TOL, rel_fro(g, gr)
+    assert rel(E2g, Er) < FP64_TOL
+    assert rel(E2, Er) < FP64_TOL
+    assert np.abs(dD - G).max() == 0.0        # g_e2 = 1: dE2/dD is G itself
+    assert np.abs(g.sum(axis=0)).max() < 1e-12 * max(1.0, np.abs(g).max())
+
+
+def test_he128_grad_vs_oracle(torch_dev):
+    s = config_system("he128_grad")
+    announce("he128 grad fp64")
+    g, _, E2g, _, E2 = _grad(torch_dev, s)
+    gr, Er, _ = load_golden("he128_grad")
+    assert rel_fro(g, gr) < FP64_TOL, rel_fro(g, gr)
+    assert rel(E2g, Er) < FP64_TOL
+    assert rel(E2, Er) < FP64_TOL
+
+
+def test_he128_grad_mixed(torch_dev):
+    s = config_system("he128_grad")
+    announce("he128 grad mixed")
+    g, _, E2g, _, _ = _grad(torch_dev, s, precision="mixed")
+    gr, Er, _ = load_golden("he128_grad")
+    assert rel_fro(g, gr) < MIXED_TOL, rel_fro(g, gr)
+    assert rel(E2g, Er) < MIXED_TOL
+
+
+def test_grad_vs_central_differences(torch_dev):
+    """Central differences (h = 1e-4 bohr) of the GPU energy against the GPU gradient, tau = 0."""
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    s = random_cluster(10, 6, box=6.0, tau=0.0)
+    announce("grad fd n=10")
+    g, _, _, _, _ = _grad(torch_dev, s)
+    D = torch.tensor(s.dens, device=dev)
+    h = 1e-4
+    fd = np.zeros_like(g)
+    for a in range(s.natoms):
+        for c in range(3):
+            xp = s.xyz.copy(); xm = s.xyz.copy()
+            xp[a, c] += h; xm[a, c] -= h
+            ep = hfk.fock(torch.tensor(xp, device=dev), D, s.exps, s.coefs, 0.0)[1].item()
+            em = hfk.fock(torch.tensor(xm, device=dev), D, s.exps, s.coefs, 0.0)[1].item()
+            fd[a, c] = (ep - em) / (2 * h)
+    assert np.abs(fd - g).max() < 1e-7 * max(1.0, np.abs(g).max())
+
+
+def test_autograd_function(torch_dev):
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    s = random_cluster(7, 7, box=5.0, tau=1e-10)
+    announce("autograd n=7")
+    xyz = torch.tensor(s.xyz, device=dev, requires_grad=True)
+    D = torch.tensor(s.dens, device=dev, requires_grad=True)
+    G, E2 = hfk.FockEnergy.apply(xyz, D, s.exps, s.coefs, s.tau, "fp64")
+    (3.0 * E2.sum()).backward()
+    gr, _, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+    assert rel_fro(xyz.grad.cpu().numpy(), 3.0 * gr) < FP64_TOL
+    assert np.abs(D.grad.cpu().numpy() - 3.0 * G.detach().cpu().numpy()).max() < 1e-13 * np.abs(G.detach().cpu().numpy()).max()
+    # a gradient flowing into G itself is refused
+    xyz2 = torch.tensor(s.xyz, device=dev, requires_grad=True)
+    G2, E22 = hfk.FockEnergy.apply(xyz2, D.detach(), s.exps, s.coefs, s.tau, "fp64")
+    with pytest.raises((RuntimeError, NotImplementedError)):
+        (G2.sum() + E22.sum()).backward()
+
+
+def test_gradcheck_small(torch_dev):
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    s = random_cluster(4, 8, box=3.0, tau=0.0)
+    announce("gradcheck n=4")
+    xyz = torch.tensor(s.xyz, device=dev, requires_grad=True)
+    D = torch.tensor(s.dens, device=dev, requires_grad=True)
+
+    def f(x, d):
+        dd = 0.5 * (d + d.transpose(0, 1))
+        return hfk.FockEnergy.apply(x, dd.contiguous(), s.exps, s.coefs, 0.0, "fp64")[1]
+
+    assert torch.autograd.gradcheck(f, (xyz, D), eps=1e-6, atol=1e-7, rtol=1e-6)
