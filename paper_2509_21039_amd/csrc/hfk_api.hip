@@ -140,6 +140,10 @@ constexpr int64_t kMaxAtoms = 6144;
 // n above which the gradient kernel's LDS copy of dE2/dR (n x 3) and its two tables no longer fit
 constexpr int64_t kMaxGradAtoms = 4096;
 constexpr int kGradGroupsPerCU = 2;
+// Largest molecule of a batch (its triangle of F and its gradient stay in LDS).
+constexpr int kMaxBatchAtomsApi = 128;
+static int g_cfg_batch_gpc = 0;
+static int g_tuned_batch_gpc = 0;
 
 // Tuned strategy per (precision, size class); 0 = not tuned.
 static std::mutex g_tune_mu;
@@ -365,12 +369,34 @@ hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss, cons
     return HFK_OK;
 }
 
+static hfk_status check_batch(int64_t nmol, const int64_t *atom_off)
+{
+    if (nmol < 1) return fail(HFK_EINVAL, "nmol must be >= 1 (got %lld)", (long long)nmol);
+    if (!atom_off) return fail(HFK_EINVAL, "atom_off_host is NULL");
+    if (atom_off[0] != 0) return fail(HFK_EINVAL, "atom_off_host[0] must be 0");
+    for (int64_t m = 0; m < nmol; ++m) {
+        const int64_t n = atom_off[m + 1] - atom_off[m];
+        if (n < 1) return fail(HFK_EINVAL, "molecule %lld has %lld atoms (needs >= 1)", (long long)m, (long long)n);
+        if (n > kMaxBatchAtomsApi)
+            return fail(HFK_EUNSUPPORTED, "molecule %lld has %lld atoms; the batched path holds at most %d",
+                        (long long)m, (long long)n, kMaxBatchAtomsApi);
+    }
+    return HFK_OK;
+}
+
 hfk_status hfk_batched_workspace_bytes(int64_t nmol, const int64_t *atom_off_host, int32_t ngauss,
                                        int32_t precision, int32_t with_grad, size_t *bytes_out)
 {
     g_err[0] = 0;
-    (void)nmol; (void)atom_off_host; (void)ngauss; (void)precision; (void)with_grad; (void)bytes_out;
-    return fail(HFK_EUNSUPPORTED, "batched path not built yet");
+    if (!bytes_out) return fail(HFK_EINVAL, "bytes_out is NULL");
+    if (ngauss < 1 || ngauss > HFK_MAX_NGAUSS)
+        return fail(HFK_EINVAL, "ngauss must be in [1, %d] (got %d)", HFK_MAX_NGAUSS, (int)ngauss);
+    if (precision != HFK_FP64 && precision != HFK_MIXED)
+        return fail(HFK_EINVAL, "precision must be HFK_FP64 or HFK_MIXED (got %d)", (int)precision);
+    hfk_status s = check_batch(nmol, atom_off_host);
+    if (s != HFK_OK) return s;
+    *bytes_out = make_blayout(nmol, atom_off_host, ngauss, with_grad).total;
+    return HFK_OK;
 }
 
 hfk_status hfk_fock_batched(int64_t nmol, const int64_t *atom_off_host, const double *xyz, int32_t ngauss,
@@ -379,10 +405,33 @@ hfk_status hfk_fock_batched(int64_t nmol, const int64_t *atom_off_host, const do
                             void *workspace, size_t workspace_bytes, void *stream)
 {
     g_err[0] = 0;
-    (void)nmol; (void)atom_off_host; (void)xyz; (void)ngauss; (void)exps_host; (void)coefs_host;
-    (void)dens_packed; (void)tau; (void)precision; (void)fock_packed; (void)e2; (void)d_xyz;
-    (void)workspace; (void)workspace_bytes; (void)stream;
-    return fail(HFK_EUNSUPPORTED, "batched path not built yet");
+    hfk_status s = check_batch(nmol, atom_off_host);
+    if (s != HFK_OK) return s;
+    s = check_common(atom_off_host[nmol], xyz, ngauss, exps_host, coefs_host, dens_packed, tau, precision);
+    if (s != HFK_OK) return s;
+    if (!fock_packed) return fail(HFK_EINVAL, "fock_packed is NULL");
+    if (!e2) return fail(HFK_EINVAL, "e2 is NULL");
+    if (!workspace) return fail(HFK_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
+    if (ngauss > 4) return fail(HFK_EUNSUPPORTED, "ngauss above 4 is not built in this version");
+    const BLayout L = make_blayout(nmol, atom_off_host, ngauss, d_xyz != nullptr);
+    if (workspace_bytes < L.total)
+        return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
+    const int cus = device_cu_count();
+    if (cus <= 0) return fail(HFK_EHIP, "no HIP device");
+    const Basis b = make_basis(ngauss, exps_host, coefs_host);
+    char *ws = (char *)workspace;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (float *)(ws + L.boys_f),
+                                (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr),
+                                atom_off_host[nmol], xyz, st);
+    if (e != hipSuccess) return hip_fail(e, "setup launch");
+    const int gpc = g_cfg_batch_gpc > 0 ? g_cfg_batch_gpc : g_tuned_batch_gpc > 0 ? g_tuned_batch_gpc : 2;
+    e = launch_batched(L, b, ws, atom_off_host, xyz, dens_packed, tau, precision, fock_packed, e2, d_xyz, cus * gpc, st);
+    if (e != hipSuccess) return hip_fail(e, "batched launch");
+    e = launch_header_info(ws + L.hdr, 0, cus * gpc, precision, -1, st);
+    if (e != hipSuccess) return hip_fail(e, "header launch");
+    return HFK_OK;
 }
 
 hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,

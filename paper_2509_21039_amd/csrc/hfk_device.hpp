@@ -46,6 +46,53 @@ __device__ inline double rsqrt_fp64(double x)
 
 __device__ inline float rsqrt_fp32(float x) { return __builtin_amdgcn_rsqf(x); }
 
+__device__ inline double rsqrt_r(double x) { return rsqrt_fp64(x); }
+__device__ inline float rsqrt_r(float x) { return rsqrt_fp32(x); }
+
+// Wave-uniform tables read through the constant address space are fetched with scalar
+// loads (they are never written while a kernel runs).
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+
+// h = H(T) = erf(sqrt T)/sqrt T and g = g(T) = -(4/sqrt(pi)) F1(T): Taylor rows of the two
+// tables about the nearest grid point below the switch, T^(-1/2) and -T^(-3/2) above it.
+template <typename R>
+__device__ inline void boys_hg(R T, const R *__restrict__ tH, const R *__restrict__ tG, R &h, R &g)
+{
+    const R y = rsqrt_r(fmax(T, R(1e-30)));
+    const R Tc = fmin(T, R(kTswitch + 0.5));
+    const int k = (int)(Tc * R(kBoysInvH) + R(0.5));
+    const R d = Tc - (R)k * R(kBoysH);
+    const R *c = tH + k * kBoysStride;
+    const R *e = tG + k * kBoysStride;
+    R vh = c[6], vg = e[6];
+#pragma unroll
+    for (int m = 5; m >= 0; --m) {
+        vh = vh * d + c[m];
+        vg = vg * d + e[m];
+    }
+    const bool near = T < R(kTswitch);
+    h = near ? vh : y;
+    g = near ? vg : -(y * y * y);
+}
+
+// Pair index p = i(i+1)/2 + j (i >= j) back to (i, j).
+__device__ inline void pair_of_index(int64_t p, int64_t &i, int64_t &j)
+{
+    int64_t r = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while (r * (r + 1) / 2 > p) --r;
+    while ((r + 1) * (r + 2) / 2 <= p) ++r;
+    i = r;
+    j = p - r * (r + 1) / 2;
+}
+
+// Q band: floor((1 - log2 q) * bands per octave), clamped; larger Q -> smaller band.
+__device__ inline int q_band(double q)
+{
+    const double x = (1.0 - log2(q)) * (double)kBandsPerOctave;
+    if (!(x < (double)(kNumBands - 1))) return kNumBands - 1;
+    return x < 0.0 ? 0 : (int)x;
+}
+
 // Wave-wide sum (64 lanes) of a double through cross-lane shuffles.
 __device__ inline double wave_sum(double v)
 {

@@ -103,10 +103,6 @@ __device__ inline R boys_h(R T, const R *__restrict__ tab)
     return T < R(kTswitch) ? v : far;
 }
 
-// Wave-uniform tables are read through the constant address space so that they are
-// fetched with scalar loads into SGPRs (they are never written while the kernel runs).
-template <typename T> using cptr = const __attribute__((address_space(4))) T *;
-
 // The lane's ket primitives are consumed in blocks of G (fixed c, all d), so only G of
 // them occupy registers at a time; the bra primitive pair ab runs in the middle loop.
 

@@ -19,8 +19,6 @@
 
 namespace hfk {
 
-template <typename T> using cptr = const __attribute__((address_space(4))) T *;
-
 struct GradArgs {
     const DevHeader *hdr;
     const BasisDev *bd;
@@ -64,27 +62,6 @@ template <> struct GPrec<float> {
     static __device__ const float *rs(const BasisDev *bd) { return bd->rs_f; }
     static __device__ float rsqrt(float x) { return rsqrt_fp32(x); }
 };
-
-// h = H(T), g = g(T): shared Taylor row below the switch, T^(-1/2) and -T^(-3/2) above it.
-template <typename R>
-__device__ inline void boys_hg(R T, const R *__restrict__ tH, const R *__restrict__ tG, R &h, R &g)
-{
-    const R y = GPrec<R>::rsqrt(fmax(T, R(1e-30)));
-    const R Tc = fmin(T, R(kTswitch + 0.5));
-    const int k = (int)(Tc * R(kBoysInvH) + R(0.5));
-    const R d = Tc - (R)k * R(kBoysH);
-    const R *c = tH + k * kBoysStride;
-    const R *e = tG + k * kBoysStride;
-    R vh = c[6], vg = e[6];
-#pragma unroll
-    for (int m = 5; m >= 0; --m) {
-        vh = vh * d + c[m];
-        vg = vg * d + e[m];
-    }
-    const bool near = T < R(kTswitch);
-    h = near ? vh : y;
-    g = near ? vg : -(y * y * y);
-}
 
 template <int G, typename R>
 __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)

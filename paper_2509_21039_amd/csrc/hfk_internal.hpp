@@ -104,6 +104,27 @@ struct Layout {
 
 Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups);
 
+// Workspace layout of the batched path.
+struct BLayout {
+    int64_t nmol, ptot, ntot, pcap;
+    int g, g2, nmax;
+    size_t hdr, basis, boys, boys_f, boys_g, boys_g_f;
+    size_t mol_n, mol_aoff, mol_poff, mol_doff, mol_toff, cent, qmax;
+    size_t q, bucket_of, bcnt, boff, bcur;
+    size_t pk, pl, pm, pq, pd, prim, prim_f, bra, bra_f;
+    size_t nitems, lim, klo, item_off, scan_tmp;
+    size_t facc, gacc;
+    size_t total;
+};
+
+BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad);
+size_t batched_smem_bytes(int nmax, int prec);
+hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int64_t *atom_off_host, const double *xyz,
+                          const double *dens, double tau, int prec, double *fock, double *e2, double *d_xyz,
+                          int groups, hipStream_t st);
+hipError_t launch_pair_pad(const DevHeader *hdr, int64_t pcap, int g2, int *pk, int *pl, double *pq, double *pd,
+                           double *prim, float *prim_f, hipStream_t st);
+
 int device_cu_count();
 
 // ------------------------------------------------------------------ launchers

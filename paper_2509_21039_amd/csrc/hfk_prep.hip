@@ -133,15 +133,6 @@ hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_
 
 // ------------------------------------------------------------------ pairs
 
-__device__ inline void pair_of_index(int64_t p, int64_t &i, int64_t &j)
-{
-    int64_t r = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-    while (r * (r + 1) / 2 > p) --r;
-    while ((r + 1) * (r + 2) / 2 <= p) ++r;
-    i = r;
-    j = p - r * (r + 1) / 2;
-}
-
 // Schwarz bound of every pair i >= j: Q_ij = sqrt((ij|ij)) in FP64, each primitive
 // quartet as S_ab S_cd sqrt(rho) H(rho |P-Q|^2) with H(T) = erf(sqrt T)/sqrt T.
 __global__ __launch_bounds__(256) void k_pair_q(Basis b, const BasisDev *__restrict__ bd,
@@ -179,14 +170,6 @@ __global__ __launch_bounds__(256) void k_pair_q(Basis b, const BasisDev *__restr
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicMax(&hdr->qmax_bits, (unsigned long long)__double_as_longlong(red[0]));
-}
-
-__device__ inline int q_band(double q)
-{
-    // b = floor((1 - log2 q) * R), clamped; larger Q -> smaller band.
-    const double x = (1.0 - log2(q)) * (double)kBandsPerOctave;
-    if (!(x < (double)(kNumBands - 1))) return kNumBands - 1;
-    return x < 0.0 ? 0 : (int)x;
 }
 
 // Morton index of the cell holding point c inside the bounding box.
@@ -305,6 +288,14 @@ __global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int 
             prim_f[(c * g2 + ab) * pcap + pos] = c < 3 ? 1e6f : 0.0f;
         }
     }
+}
+
+hipError_t launch_pair_pad(const DevHeader *hdr, int64_t pcap, int g2, int *pk, int *pl, double *pq, double *pd,
+                           double *prim, float *prim_f, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((pcap + 255) / 256)), dim3(256), 0, st, hdr, pcap, g2, pk, pl, pq, pd,
+                       prim, prim_f);
+    return hipGetLastError();
 }
 
 // Ket range of every bra s (in bucketed order): kets t < lim_s with

@@ -1,0 +1,94 @@
+"""GPU parity of the ragged batched path (one persistent launch, forward + gradient)."""
+import numpy as np
+import pytest
+
+import oracle
+from he_inputs import cluster_batch, pack_batch, random_cluster
+from gpu_util import announce, rel, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda:0")
+
+
+def _run(torch_dev, systems, precision, with_grad=True):
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    off, xyz, dens = pack_batch(systems)
+    X = torch.tensor(xyz, device=dev)
+    Dp = torch.tensor(dens, device=dev)
+    F, E2, g = hfk.fock_batched(off, X, Dp, systems[0].exps, systems[0].coefs, systems[0].tau,
+                                precision=precision, with_grad=with_grad)
+    torch.cuda.synchronize()
+    return off, F.cpu().numpy(), E2.cpu().numpy(), (g.cpu().numpy() if g is not None else None)
+
+
+def _mol(off, F, g, m, n):
+    d0 = int(sum(int(off[k + 1] - off[k]) ** 2 for k in range(m)))
+    Fm = F[d0:d0 + n * n].reshape(n, n)
+    gm = g[off[m]:off[m + 1]] if g is not None else None
+    return Fm, gm
+
+
+def _small_batch(tau):
+    sizes = [1, 2, 5, 17, 3, 30, 9, 1, 24, 12, 40, 7]
+    return [random_cluster(n, 100 + i, box=1.2 * n ** (1 / 3) * 2.0, tau=tau) for i, n in enumerate(sizes)]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_small_batch_vs_oracle(torch_dev, precision, tol):
+    systems = _small_batch(1e-10)
+    announce("batched small %s" % precision)
+    off, F, E2, g = _run(torch_dev, systems, precision)
+    for m, s in enumerate(systems):
+        n = s.natoms
+        Fm, gm = _mol(off, F, g, m, n)
+        Fr, Er, _ = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+        gr, _, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+        assert rel_fro(Fm, Fr) < tol, (m, n, rel_fro(Fm, Fr))
+        assert rel(E2[m], Er) < tol, (m, n)
+        # a one-atom molecule has zero gradient (translation invariance): absolute floor
+        assert np.linalg.norm(gm - gr) <= tol * max(np.linalg.norm(gr), 1e-6), (m, n)
+
+
+def test_forward_only_matches_fused(torch_dev):
+    systems = _small_batch(1e-10)
+    announce("batched forward-only")
+    off, F1, E1, _ = _run(torch_dev, systems, "fp64", with_grad=False)
+    _, F2, E2, g2 = _run(torch_dev, systems, "fp64", with_grad=True)
+    assert np.abs(F1 - F2).max() <= 1e-13 * np.abs(F2).max()
+    assert np.abs(E1 - E2).max() <= 1e-12 * np.abs(E2).max()
+
+
+def test_cluster_batch_2000_sampled(torch_dev):
+    """The 2000-cluster workload (mixed precision + gradient, one launch); sampled molecules
+    are checked one by one against the FP64 oracle."""
+    systems = cluster_batch()
+    announce("batched 2000 clusters mixed+grad")
+    off, F, E2, g = _run(torch_dev, systems, "mixed")
+    counts = np.array([s.natoms for s in systems])
+    picks = [int(np.argmin(counts))]
+    for target in (20, 40, 60):
+        picks.append(int(np.argmin(np.abs(counts - target))))
+    for m in picks:
+        s = systems[m]
+        n = s.natoms
+        Fm, gm = _mol(off, F, g, m, n)
+        Fr, Er, _ = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+        gr, _, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+        assert rel_fro(Fm, Fr) < MIXED_TOL, (m, n)
+        assert rel(E2[m], Er) < MIXED_TOL, (m, n)
+        assert rel_fro(gm, gr) < MIXED_TOL, (m, n)
+    # properties over the whole batch: finite results, zero net force per molecule
+    assert np.isfinite(F).all() and np.isfinite(E2).all() and np.isfinite(g).all()
+    for m in range(len(systems)):
+        gm = g[off[m]:off[m + 1]]
+        assert np.abs(gm.sum(axis=0)).max() < 1e-5 * max(1.0, np.abs(gm).max())
