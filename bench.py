@@ -66,6 +66,61 @@ def time_builds(hfk, torch, s, precision, steps, warmup, ws):
             "e2": float(E2.item()), "F": F}
 
 
+def time_grad(hfk, torch, s, steps, warmup):
+    """Forward build followed by the backward (dE2/dR, dE2/dD) per step."""
+    dev = torch.device("cuda:0")
+    xyz = torch.tensor(s.xyz, device=dev)
+    D = torch.tensor(s.dens, device=dev)
+    ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, len(s.exps), "fp64", True), dev)
+    g_e2 = torch.ones((1,), dtype=torch.float64, device=dev)
+
+    def step():
+        G, E2 = hfk.fock(xyz, D, s.exps, s.coefs, s.tau, workspace=ws)
+        return hfk.fock_grad(xyz, D, s.exps, s.coefs, s.tau, g_e2=g_e2, fock_in=G, workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def time_batched(hfk, torch, systems, steps, warmup):
+    from he_inputs import pack_batch
+    dev = torch.device("cuda:0")
+    off, xyz, dens = pack_batch(systems)
+    X = torch.tensor(xyz, device=dev)
+    Dp = torch.tensor(dens, device=dev)
+    s0 = systems[0]
+    gpc = hfk.tune_batched(off, X, Dp, s0.exps, s0.coefs, s0.tau, precision="mixed", with_grad=True)
+    ws = hfk.new_workspace(hfk.batched_workspace_bytes(off, len(s0.exps), "mixed", True), dev)
+    for _ in range(warmup):
+        hfk.fock_batched(off, X, Dp, s0.exps, s0.coefs, s0.tau, precision="mixed", with_grad=True, workspace=ws)
+    torch.cuda.synchronize()
+    stats = hfk.read_stats(ws)
+    hfk.profile_read()
+    hfk.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        hfk.fock_batched(off, X, Dp, s0.exps, s0.coefs, s0.tau, precision="mixed", with_grad=True, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    hfk.profile_enable(False)
+    kms, nl = hfk.profile_read()
+    ms = e0.elapsed_time(e1) / steps
+    return {"molecules": len(systems), "atoms": int(off[-1]), "quartets": stats["quartets"],
+            "ms_per_batch": ms, "kernel_ms": kms / max(nl, 1), "quartets_per_s": stats["quartets"] / (ms / 1e3),
+            "groups_per_cu": gpc}
+
+
 def cpu_baseline(s, target_s=12.0):
     """Oracle on a bounded bra range of the same system, scaled to quartets/s."""
     import oracle
@@ -109,6 +164,11 @@ def main():
     s = config_system("he512_fp64")
     g = len(s.exps)
     ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, g, "fp64"), dev)
+    log("he512 fp64: autotune")
+    xyz_t = torch.tensor(s.xyz, device=dev)
+    D_t = torch.tensor(s.dens, device=dev)
+    hfk.tune(xyz_t, D_t, s.exps, s.coefs, s.tau, precision="fp64")
+    del xyz_t, D_t
     log("he512 fp64: warmup %d, steps %d" % (args.warmup, args.steps))
     r = time_builds(hfk, torch, s, "fp64", args.steps, args.warmup, ws)
     q = r["stats"]["quartets"]
@@ -132,7 +192,8 @@ def main():
                                "Schwarz tau 1e-10, FP64",
                    "natoms": s.natoms, "ngauss": g, "tau": s.tau, "quartets": q,
                    "primitive_quartets": q * g ** 4, "sig_pairs": r["stats"]["sig_pairs"],
-                   "parallelism": "single GPU"},
+                   "kernel_variant": r["stats"]["variant"], "accumulation": r["stats"]["strategy"],
+                   "workgroups": r["stats"]["groups"], "parallelism": "single GPU"},
         "pct_fp64_valu_peak_nominal": 100.0 * achieved / FP64_VALU_PEAK_TFLOPS,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
@@ -146,9 +207,14 @@ def main():
         try:
             s3 = config_system("he1024_mixed")
             ws3 = hfk.new_workspace(hfk.workspace_bytes(s3.natoms, g, "fp64"), dev)
-            log("he1024: fp64 and mixed")
-            a = time_builds(hfk, torch, s3, "fp64", 2, 1, ws3)
-            b = time_builds(hfk, torch, s3, "mixed", 2, 1, ws3)
+            log("he1024: autotune fp64 and mixed, then time")
+            x3 = torch.tensor(s3.xyz, device=dev)
+            d3 = torch.tensor(s3.dens, device=dev)
+            hfk.tune(x3, d3, s3.exps, s3.coefs, s3.tau, precision="fp64")
+            hfk.tune(x3, d3, s3.exps, s3.coefs, s3.tau, precision="mixed")
+            del x3, d3
+            a = time_builds(hfk, torch, s3, "fp64", 3, 1, ws3)
+            b = time_builds(hfk, torch, s3, "mixed", 3, 1, ws3)
             qa = a["stats"]["quartets"]
             Fa, Fb = a["F"], b["F"]
             extras["mixed_he1024"] = {
@@ -165,6 +231,28 @@ def main():
             torch.cuda.empty_cache()
         except hfk.HfkError as e:
             extras["mixed_he1024"] = {"error": str(e)}
+        try:
+            s4 = config_system("he128_grad")
+            log("he128: forward vs forward+gradient")
+            ws4 = hfk.new_workspace(hfk.workspace_bytes(s4.natoms, g, "fp64"), dev)
+            f4 = time_builds(hfk, torch, s4, "fp64", 10, 2, ws4)
+            fg = time_grad(hfk, torch, s4, 10, 2)
+            q4 = f4["stats"]["quartets"]
+            extras["fwd_grad_he128"] = {
+                "quartets": q4,
+                "fwd_ms": f4["ms_per_step"], "fwd_grad_ms": fg,
+                "fwd_quartets_per_s": q4 / (f4["ms_per_step"] / 1e3),
+                "fwd_grad_quartets_per_s": q4 / (fg / 1e3),
+                "fwd_grad_over_fwd_time": fg / f4["ms_per_step"],
+            }
+        except hfk.HfkError as e:
+            extras["fwd_grad_he128"] = {"error": str(e)}
+        try:
+            from he_inputs import cluster_batch
+            log("2000-cluster batch: mixed + gradient, one launch")
+            extras["batched_2000_mixed_grad"] = time_batched(hfk, torch, cluster_batch(), 5, 1)
+        except hfk.HfkError as e:
+            extras["batched_2000_mixed_grad"] = {"error": str(e)}
         out["extras"] = extras
     if not args.no_cpu:
         log("cpu oracle baseline (bounded sample)")

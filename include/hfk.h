@@ -154,18 +154,30 @@ hfk_status hfk_fock_batched(int64_t nmol, const int64_t *atom_off_host, const do
 hfk_status hfk_read_stats(const void *workspace, void *stream, hfk_stats *out);
 
 /* Autotuner: times the forward build of the given system under every candidate
- * (accumulation strategy x workgroups per compute unit) on `stream`, keeps the fastest
- * for this (device, precision, size class) for the rest of the process, and writes the
- * table to cache_path as JSON when cache_path is not NULL.  best_out (may be NULL)
- * receives the chosen hfk_strategy.  Inputs and workspace as hfk_fock (fock and e2 are
- * overwritten).  Errors as hfk_fock. */
+ * (accumulation strategy x quartet-kernel variant x persistent workgroups per compute
+ * unit) on `stream`, keeps the fastest for this (precision, size class) for the rest of the
+ * process, and writes the table to cache_path as JSON when cache_path is not NULL.
+ * best_out (may be NULL) receives the chosen hfk_strategy.  Inputs and workspace as
+ * hfk_fock (fock and e2 are overwritten).  Waits for `stream`.  Errors as hfk_fock. */
 hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss,
                     const double *exps_host, const double *coefs_host,
                     const double *dens, double tau, int32_t precision,
                     double *fock, double *e2, void *workspace, size_t workspace_bytes,
                     void *stream, const char *cache_path, int32_t *best_out);
 
-/* Loads a table written by hfk_tune (JSON).  Errors: HFK_EINVAL (NULL or unreadable). */
+/* Autotuner of the batched path: times hfk_fock_batched on the given batch for 1..3
+ * persistent workgroups per compute unit, keeps the fastest for the rest of the process
+ * (written to cache_path with the hfk_tune table when cache_path is not NULL) and returns it
+ * in best_gpc_out (may be NULL).  Arguments as hfk_fock_batched (outputs overwritten). */
+hfk_status hfk_tune_batched(int64_t nmol, const int64_t *atom_off_host, const double *xyz,
+                            int32_t ngauss, const double *exps_host, const double *coefs_host,
+                            const double *dens_packed, double tau, int32_t precision,
+                            double *fock_packed, double *e2, double *d_xyz,
+                            void *workspace, size_t workspace_bytes, void *stream,
+                            const char *cache_path, int32_t *best_gpc_out);
+
+/* Loads a table written by hfk_tune / hfk_tune_batched (JSON).  Errors: HFK_EINVAL (NULL,
+ * unreadable, or not such a table). */
 hfk_status hfk_load_tuning(const char *cache_path);
 
 /* Process-wide override of the launch configuration of hfk_fock, for tuning and tests:

@@ -64,6 +64,9 @@ _SIGNATURES = {
     "hfk_tune": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
                  _vp, _vp, _vp, _sz, _vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)],
     "hfk_load_tuning": [ctypes.c_char_p],
+    "hfk_tune_batched": [ctypes.c_int64, _i64p, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double,
+                         ctypes.c_int32, _vp, _vp, _vp, _vp, _sz, _vp, ctypes.c_char_p,
+                         ctypes.POINTER(ctypes.c_int32)],
     "hfk_profile_enable": [ctypes.c_int32],
     "hfk_set_config": [ctypes.c_int32, ctypes.c_int32],
     "hfk_profile_read": [ctypes.POINTER(ctypes.c_double), _i64p],
@@ -316,6 +319,28 @@ def profile_read():
     cnt = ctypes.c_int64(0)
     _check(lib().hfk_profile_read(ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+def tune_batched(atom_off, xyz, dens_packed, exps, coefs, tau, precision="mixed", with_grad=True,
+                 cache_path: Optional[str] = None, stream=None) -> int:
+    """Runs the batched autotuner; returns the chosen workgroups per compute unit."""
+    torch = _torch()
+    off = np.ascontiguousarray(np.asarray(atom_off, dtype=np.int64))
+    nmol = len(off) - 1
+    e = _host_f64(exps)
+    c = _host_f64(coefs)
+    prec = _PREC[precision]
+    ws = new_workspace(batched_workspace_bytes(off, len(e), prec, with_grad), xyz.device)
+    F = torch.empty_like(dens_packed)
+    E2 = torch.empty((nmol,), dtype=torch.float64, device=xyz.device)
+    g = torch.empty_like(xyz) if with_grad else None
+    best = ctypes.c_int32(0)
+    _check(lib().hfk_tune_batched(nmol, off.ctypes.data_as(_i64p), xyz.data_ptr(), len(e), _dptr(e), _dptr(c),
+                                  dens_packed.data_ptr(), float(tau), prec, F.data_ptr(), E2.data_ptr(),
+                                  g.data_ptr() if g is not None else None, ws.data_ptr(), ws.numel(),
+                                  _stream_handle(stream), cache_path.encode() if cache_path else None,
+                                  ctypes.byref(best)))
+    return best.value
 
 
 def load_tuning(cache_path: str):

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -164,7 +165,7 @@ static TunedConfig pick_config(int32_t strategy, int32_t precision, int64_t n)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         c = g_tuned_cfg[precision][size_class(n)];
     }
-    if (c.strategy == 0) c = TunedConfig{HFK_STRATEGY_PRIVATE, 1, 2};
+    if (c.strategy == 0) c = TunedConfig{HFK_STRATEGY_PRIVATE, 1, precision == HFK_MIXED ? 6 : 4};
     if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_ATOMIC) c.strategy = strategy;
     if (g_cfg_variant >= 0) c.variant = g_cfg_variant;
     if (g_cfg_gpc > 0) c.gpc = g_cfg_gpc;
@@ -434,23 +435,180 @@ hfk_status hfk_fock_batched(int64_t nmol, const int64_t *atom_off_host, const do
     return HFK_OK;
 }
 
+// ------------------------------------------------------------------ autotuner
+
+static double time_fock_ms(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps,
+                           const double *coefs, const double *dens, double tau, int32_t precision, int32_t strategy,
+                           double *fock, double *e2, void *ws, size_t wsb, hipStream_t st, int reps, hfk_status *err)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        *err = fail(HFK_EHIP, "event create");
+        return 0.0;
+    }
+    double best = 1e300;
+    for (int r = 0; r <= reps; ++r) {
+        (void)hipEventRecord(e0, st);
+        hfk_status s = hfk_fock(natoms, xyz, ngauss, exps, coefs, dens, tau, precision, strategy, fock, e2, ws, wsb, st);
+        (void)hipEventRecord(e1, st);
+        if (s != HFK_OK) {
+            *err = s;
+            break;
+        }
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            *err = fail(HFK_EHIP, "event timing");
+            break;
+        }
+        if (r > 0 && ms < best) best = ms;     // the first run warms up
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
+static hfk_status write_tuning(const char *path)
+{
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(HFK_EINVAL, "cannot write %s", path);
+    fprintf(f, "{\n  \"format\": \"hfk-tuning-1\",\n  \"entries\": [\n");
+    bool first = true;
+    for (int p = 0; p < 2; ++p)
+        for (int c = 0; c < 4; ++c) {
+            const TunedConfig &t = g_tuned_cfg[p][c];
+            if (!t.strategy) continue;
+            fprintf(f, "%s    {\"precision\": %d, \"size_class\": %d, \"strategy\": %d, \"variant\": %d, \"gpc\": %d}",
+                    first ? "" : ",\n", p, c, t.strategy, t.variant, t.gpc);
+            first = false;
+        }
+    fprintf(f, "\n  ],\n  \"batched_gpc\": %d\n}\n", g_tuned_batch_gpc);
+    fclose(f);
+    return HFK_OK;
+}
+
 hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
                     const double *coefs_host, const double *dens, double tau, int32_t precision, double *fock,
                     double *e2, void *workspace, size_t workspace_bytes, void *stream, const char *cache_path,
                     int32_t *best_out)
 {
     g_err[0] = 0;
-    (void)natoms; (void)xyz; (void)ngauss; (void)exps_host; (void)coefs_host; (void)dens; (void)tau;
-    (void)precision; (void)fock; (void)e2; (void)workspace; (void)workspace_bytes; (void)stream;
-    (void)cache_path; (void)best_out;
-    return fail(HFK_EUNSUPPORTED, "tuner not built yet");
+    hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision);
+    if (s != HFK_OK) return s;
+    const int save_var = g_cfg_variant, save_gpc = g_cfg_gpc;
+    const int strategies[2] = {HFK_STRATEGY_PRIVATE, HFK_STRATEGY_ATOMIC};
+    const int variants[2] = {1, 0};
+    const int gpcs[4] = {2, 3, 4, 6};
+    TunedConfig best{0, 1, 2};
+    double best_ms = 1e300;
+    hfk_status err = HFK_OK;
+    for (int si = 0; si < 2 && err == HFK_OK; ++si)
+        for (int vi = 0; vi < 2 && err == HFK_OK; ++vi)
+            for (int gi = 0; gi < 4 && err == HFK_OK; ++gi) {
+                g_cfg_variant = variants[vi];
+                g_cfg_gpc = gpcs[gi];
+                const double ms = time_fock_ms(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision,
+                                               strategies[si], fock, e2, workspace, workspace_bytes,
+                                               (hipStream_t)stream, 2, &err);
+                if (err == HFK_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best = TunedConfig{strategies[si], variants[vi], gpcs[gi]};
+                }
+            }
+    g_cfg_variant = save_var;
+    g_cfg_gpc = save_gpc;
+    if (err != HFK_OK) return err;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned_cfg[precision][size_class(natoms)] = best;
+    }
+    if (best_out) *best_out = best.strategy;
+    if (cache_path) return write_tuning(cache_path);
+    return HFK_OK;
+}
+
+hfk_status hfk_tune_batched(int64_t nmol, const int64_t *atom_off_host, const double *xyz, int32_t ngauss,
+                            const double *exps_host, const double *coefs_host, const double *dens_packed, double tau,
+                            int32_t precision, double *fock_packed, double *e2, double *d_xyz, void *workspace,
+                            size_t workspace_bytes, void *stream, const char *cache_path, int32_t *best_gpc_out)
+{
+    g_err[0] = 0;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(HFK_EHIP, "event create");
+    const int save = g_cfg_batch_gpc;
+    int best = 2;
+    double best_ms = 1e300;
+    hfk_status err = HFK_OK;
+    for (int gpc = 1; gpc <= 3 && err == HFK_OK; ++gpc) {
+        g_cfg_batch_gpc = gpc;
+        for (int r = 0; r < 3 && err == HFK_OK; ++r) {
+            (void)hipEventRecord(e0, st);
+            err = hfk_fock_batched(nmol, atom_off_host, xyz, ngauss, exps_host, coefs_host, dens_packed, tau,
+                                   precision, fock_packed, e2, d_xyz, workspace, workspace_bytes, stream);
+            (void)hipEventRecord(e1, st);
+            float ms = 0.f;
+            if (err == HFK_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                err = fail(HFK_EHIP, "event timing");
+            if (err == HFK_OK && r > 0 && ms < best_ms) {
+                best_ms = ms;
+                best = gpc;
+            }
+        }
+    }
+    g_cfg_batch_gpc = save;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != HFK_OK) return err;
+    g_tuned_batch_gpc = best;
+    if (best_gpc_out) *best_gpc_out = best;
+    if (cache_path) return write_tuning(cache_path);
+    return HFK_OK;
+}
+
+static bool json_int(const char *obj, const char *key, int *out)
+{
+    char pat[64];
+    snprintf(pat, sizeof(pat), "\"%s\"", key);
+    const char *p = strstr(obj, pat);
+    if (!p) return false;
+    p = strchr(p + strlen(pat), ':');
+    if (!p) return false;
+    return sscanf(p + 1, " %d", out) == 1;
 }
 
 hfk_status hfk_load_tuning(const char *cache_path)
 {
     g_err[0] = 0;
     if (!cache_path) return fail(HFK_EINVAL, "cache_path is NULL");
-    return fail(HFK_EUNSUPPORTED, "tuner not built yet");
+    FILE *f = fopen(cache_path, "r");
+    if (!f) return fail(HFK_EINVAL, "cannot read %s", cache_path);
+    std::vector<char> buf;
+    char tmp[4096];
+    size_t got;
+    while ((got = fread(tmp, 1, sizeof(tmp), f)) > 0) buf.insert(buf.end(), tmp, tmp + got);
+    fclose(f);
+    buf.push_back(0);
+    const char *txt = buf.data();
+    if (!strstr(txt, "\"hfk-tuning-1\"")) return fail(HFK_EINVAL, "%s is not an hfk tuning table", cache_path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const char *p = strchr(txt, '{'); p; p = strchr(p + 1, '{')) {
+        const char *end = strchr(p, '}');
+        if (!end) break;
+        std::string obj(p, end - p + 1);
+        int prec, cls, strat, var, gpc;
+        if (json_int(obj.c_str(), "precision", &prec) && json_int(obj.c_str(), "size_class", &cls) &&
+            json_int(obj.c_str(), "strategy", &strat) && json_int(obj.c_str(), "variant", &var) &&
+            json_int(obj.c_str(), "gpc", &gpc)) {
+            if (prec < 0 || prec > 1 || cls < 0 || cls > 3 || strat < 1 || strat > 2 || var < 0 || var > 1 ||
+                gpc < 1 || gpc > kMaxGroupsPerCU)
+                return fail(HFK_EINVAL, "bad entry in %s", cache_path);
+            g_tuned_cfg[prec][cls] = TunedConfig{strat, var, gpc};
+        }
+    }
+    int bg = 0;
+    if (json_int(txt, "batched_gpc", &bg) && bg >= 1 && bg <= 3) g_tuned_batch_gpc = bg;
+    return HFK_OK;
 }
 
 }  // extern "C"

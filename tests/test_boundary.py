@@ -87,3 +87,47 @@ def test_python_layer_raises_hfkerror():
 
 def test_read_stats_null_arguments():
     assert hfk.lib().hfk_read_stats(None, None, None) == hfk.HFK_EINVAL
+
+
+def test_load_tuning_rejects_missing_and_foreign_files(tmp_path):
+    with pytest.raises(hfk.HfkError):
+        hfk.load_tuning(str(tmp_path / "missing.json"))
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"something": 1}')
+    with pytest.raises(hfk.HfkError):
+        hfk.load_tuning(str(bad))
+    worse = tmp_path / "worse.json"
+    worse.write_text('{"format": "hfk-tuning-1", "entries": [{"precision": 0, "size_class": 1, "strategy": 7, '
+                     '"variant": 1, "gpc": 4}]}')
+    with pytest.raises(hfk.HfkError):
+        hfk.load_tuning(str(worse))
+
+
+def test_load_tuning_accepts_its_format(tmp_path):
+    good = tmp_path / "good.json"
+    good.write_text('{\n  "format": "hfk-tuning-1",\n  "entries": [\n    {"precision": 0, "size_class": 2, '
+                    '"strategy": 1, "variant": 1, "gpc": 4}\n  ],\n  "batched_gpc": 2\n}\n')
+    hfk.load_tuning(str(good))
+
+
+def test_set_config_validation():
+    L = hfk.lib()
+    assert L.hfk_set_config(2, 0) == hfk.HFK_EINVAL
+    assert L.hfk_set_config(-1, 9) == hfk.HFK_EINVAL
+    assert L.hfk_set_config(-1, 0) == hfk.HFK_OK
+
+
+def test_batched_validation():
+    import numpy as np
+    L = hfk.lib()
+    out = ctypes.c_size_t(0)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    off = np.array([0, 3, 3], dtype=np.int64)            # empty molecule
+    assert L.hfk_batched_workspace_bytes(2, off.ctypes.data_as(i64p), 3, 1, 1, ctypes.byref(out)) == hfk.HFK_EINVAL
+    off = np.array([1, 3], dtype=np.int64)               # must start at 0
+    assert L.hfk_batched_workspace_bytes(1, off.ctypes.data_as(i64p), 3, 1, 1, ctypes.byref(out)) == hfk.HFK_EINVAL
+    off = np.array([0, 200], dtype=np.int64)             # above the LDS limit
+    assert L.hfk_batched_workspace_bytes(1, off.ctypes.data_as(i64p), 3, 1, 1, ctypes.byref(out)) == hfk.HFK_EUNSUPPORTED
+    off = np.array([0, 4, 9], dtype=np.int64)
+    assert L.hfk_batched_workspace_bytes(2, off.ctypes.data_as(i64p), 3, 1, 1, ctypes.byref(out)) == hfk.HFK_OK
+    assert out.value > 0
