@@ -148,6 +148,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed / fwd+grad / batched comparisons")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="one he512 FP64 build (default configuration) and one plain 512 MiB device copy, for "
+                         "hardware-counter runs; prints the copy size")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the Fock build here is single-GPU (the multi-GPU "
@@ -163,6 +166,18 @@ def main():
     dev = torch.device("cuda:0")
     s = config_system("he512_fp64")
     g = len(s.exps)
+    if args.traffic_probe:
+        ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, g, "fp64"), dev)
+        xyz_t = torch.tensor(s.xyz, device=dev)
+        D_t = torch.tensor(s.dens, device=dev)
+        hfk.fock(xyz_t, D_t, s.exps, s.coefs, s.tau, workspace=ws)
+        nbytes = 512 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes}), flush=True)
+        return
     ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, g, "fp64"), dev)
     log("he512 fp64: autotune")
     xyz_t = torch.tensor(s.xyz, device=dev)
