@@ -84,3 +84,34 @@ def test_ragged_sizes_vs_oracle(torch_dev, n, seed):
     assert rel_fro(G, Gr) < FP64_TOL
     assert rel(E2, Er) < FP64_TOL
     assert abs(st["quartets"] - nsr) <= 2
+
+
+@pytest.mark.parametrize("exps,coefs", [
+    ([0.8], [1.0]),
+    ([3.0, 0.45], [0.4, 0.7]),
+    ([9.0, 2.1, 0.6, 0.19], [0.05, 0.25, 0.5, 0.3]),
+])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_other_basis_sizes(torch_dev, exps, coefs, variant):
+    """The kernels are instantiated for 1..4 primitives per function."""
+    s = random_cluster(23, 31, box=8.0, tau=1e-10)
+    s.exps = np.array(exps)
+    s.coefs = np.array(coefs)
+    announce("ngauss=%d variant=%d" % (len(exps), variant))
+    G, E2, st = _run(torch_dev, s, variant=variant)
+    Gr, Er, nsr = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+    assert rel_fro(G, Gr) < FP64_TOL
+    assert rel(E2, Er) < FP64_TOL
+    Gm, Em, _ = _run(torch_dev, s, precision="mixed", variant=variant)
+    assert rel_fro(Gm, Gr) < MIXED_TOL
+
+
+def test_unsupported_ngauss_raises(torch_dev):
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    s = random_cluster(4, 1)
+    xyz = torch.tensor(s.xyz, device=dev)
+    D = torch.tensor(s.dens, device=dev)
+    with pytest.raises(hfk.HfkError) as ei:
+        hfk.fock(xyz, D, [1.0] * 5, [0.2] * 5, 0.0)
+    assert ei.value.status == hfk.HFK_EUNSUPPORTED

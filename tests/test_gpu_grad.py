@@ -116,3 +116,16 @@ def test_gradcheck_small(torch_dev):
         return hfk.FockEnergy.apply(x, dd.contiguous(), s.exps, s.coefs, 0.0, "fp64")[1]
 
     assert torch.autograd.gradcheck(f, (xyz, D), eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+@pytest.mark.parametrize("exps,coefs", [([0.8], [1.0]), ([3.0, 0.45], [0.4, 0.7]),
+                                        ([9.0, 2.1, 0.6, 0.19], [0.05, 0.25, 0.5, 0.3])])
+def test_grad_other_basis_sizes(torch_dev, exps, coefs):
+    s = random_cluster(9, 41, box=5.0, tau=1e-10)
+    s.exps = np.array(exps)
+    s.coefs = np.array(coefs)
+    announce("grad ngauss=%d" % len(exps))
+    g, _, E2g, _, _ = _grad(torch_dev, s)
+    gr, Er, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+    assert rel_fro(g, gr) < FP64_TOL
+    assert rel(E2g, Er) < FP64_TOL
