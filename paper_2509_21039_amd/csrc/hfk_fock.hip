@@ -54,6 +54,7 @@ template <> struct Prec<double> {
     static __device__ const double *srho(const BasisDev *bd) { return bd->srho; }
     static __device__ const double *r2sw(const BasisDev *bd) { return bd->r2sw; }
     static __device__ const double *rs(const BasisDev *bd) { return bd->rs; }
+    static __device__ const double *rsn(const BasisDev *bd) { return bd->rsn; }
     static __device__ double rsqrt(double x) { return rsqrt_fp64(x); }
     // acc + s / sqrt(x): hardware estimate y, one Newton step folded into the product
     static __device__ double far_acc(double acc, double s, double x)
@@ -71,6 +72,7 @@ template <> struct Prec<float> {
     static __device__ const float *srho(const BasisDev *bd) { return bd->srho_f; }
     static __device__ const float *r2sw(const BasisDev *bd) { return bd->r2sw_f; }
     static __device__ const float *rs(const BasisDev *bd) { return bd->rs_f; }
+    static __device__ const float *rsn(const BasisDev *bd) { return bd->rsn_f; }
     static __device__ float rsqrt(float x) { return rsqrt_fp32(x); }
     static __device__ float far_acc(float acc, float s, float x) { return fmaf(s, rsqrt_fp32(x), acc); }
 };
@@ -143,19 +145,42 @@ __device__ inline R quartet_eri_direct(const R *__restrict__ lbra, const R *__re
     return eri;
 }
 
+// sqrt(h) H(T) from T' = T / h, the argument on the table grid (rows at integers): the
+// Taylor row nearest T' with coefficients pre-multiplied by h^m sqrt(h) where the lane
+// is near, T'^(-1/2) where it is not (T = 0 is always near, so needs no guard).
+template <typename R>
+__device__ inline R boys_grid(R Ts, bool near, const R *__restrict__ tab)
+{
+    const R far = Prec<R>::rsqrt(Ts);
+    const R Tc = fmin(Ts, R(kBoysGrid - 4));
+    const R kd = rint(Tc);
+    const R d = Tc - kd;
+    // 24-bit multiply (full rate) for the row address
+    const R *c = (const R *)((const char *)tab + __umul24((unsigned)(int)kd, (unsigned)(kBoysStride * sizeof(R))));
+    R v = c[6];
+    v = v * d + c[5];
+    v = v * d + c[4];
+    v = v * d + c[3];
+    v = v * d + c[2];
+    v = v * d + c[1];
+    v = v * d + c[0];
+    return near ? v : far;
+}
+
 // Contracted (bra | ket) with a wave-uniform near/far branch per primitive quartet: when
-// no lane of the wave has rho |P-Q|^2 below the switch (the common case once kets are
+// no lane of the wave has |P-Q|^2 below the switch radius (the common case once kets are
 // spatially sorted), the lanes add the far-field value S_cd / |P-Q| (exact beyond the
-// switch); otherwise every lane evaluates H(T) from the Taylor table or its far-field
-// form.  Lanes without a kept quartet get ket centres far away, so they are never near.
-// Uniform data come through scalar loads: per bra primitive (Px, Py, Pz, S, -2Px, -2Py,
-// -2Pz, |P|^2) and per primitive quartet (rho, sqrt(rho), switch radius^2).
+// switch); otherwise every lane evaluates S_cd sqrt(rho/h) * sqrt(h) H(T) through the
+// grid table or its far-field form.  Lanes without a kept quartet get ket centres far
+// away, so they are never near.  Uniform data come through scalar loads issued together
+// at the top of each bra primitive: (Px, Py, Pz, S, -2Px, -2Py, -2Pz, |P|^2) and, per
+// primitive quartet, (switch radius^2, rho/h, sqrt(rho/h)).
 // FP64 forms |P-Q|^2 as |P|^2 + |Q|^2 - 2 P.Q (4 operations; with centroid-centred
 // coordinates the cancellation stays near 1e-13 bohr^2 absolute); FP32 subtracts the
 // centres directly, which its precision needs.
 template <int G, typename R>
 __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, int64_t pcap, int64_t t,
-                                       bool valid, cptr<R> rs, const R *__restrict__ tab)
+                                       bool valid, cptr<R> rsn, const R *__restrict__ tab)
 {
     constexpr int G2 = G * G;
     constexpr bool kExpand = sizeof(R) == 8;
@@ -174,11 +199,19 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
         }
 #pragma unroll 1
         for (int ab = 0; ab < G2; ++ab) {
-            cptr<R> b = bra + 8 * ab;
+            const cptr<R> bp = bra + 8 * ab;
+            const cptr<R> up = rsn + 3 * (ab * G2 + cb * G);
+            R b[8], u[3 * G];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) b[c] = bp[c];
+#pragma unroll
+            for (int c = 0; c < 3 * G; ++c) u[c] = up[c];
+            // keep every uniform load in one batch at the top (not sunk into the branches)
+#pragma unroll
+            for (int c = 0; c < 3 * G; ++c) asm volatile("" ::"s"(u[c]));
             R acc = R(0);
 #pragma unroll
             for (int d = 0; d < G; ++d) {
-                const int x = ab * G2 + cb * G + d;
                 R r2;
                 if (kExpand) {
                     r2 = fma(b[4], kx[d], fma(b[5], ky[d], fma(b[6], kz[d], kq[d] + b[7])));
@@ -186,8 +219,9 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
                     const R dx = b[0] - kx[d], dy = b[1] - ky[d], dz = b[2] - kz[d];
                     r2 = dx * dx + dy * dy + dz * dz;
                 }
-                if (__builtin_amdgcn_ballot_w64(r2 < rs[3 * x + 2])) {
-                    acc += (ks[d] * rs[3 * x + 1]) * boys_h<R>(r2 * rs[3 * x], tab);
+                const bool near = r2 < u[3 * d];
+                if (__builtin_amdgcn_ballot_w64(near)) {
+                    acc = fma(ks[d] * u[3 * d + 2], boys_grid<R>(r2 * u[3 * d + 1], near, tab), acc);
                 } else {
                     acc = Prec<R>::far_acc(acc, ks[d], r2);
                 }
@@ -216,11 +250,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     constexpr int G2 = G * G;
     extern __shared__ double smem[];
     const int n = a.n;
-    double *rowi = smem;
-    double *rowj = smem + n;
-    char *sp = (char *)(smem + 2 * n);
-    R *tab = (R *)sp;                       // direct: H table; split: offset table
+    // the table first, so its row addresses need no base register
+    char *sp = (char *)smem;
+    R *tab = (R *)sp;                       // Boys table (grid-scaled for the hybrid form)
     sp += FockSmem<R>::tab_bytes;
+    double *rowi = (double *)sp;
+    double *rowj = rowi + n;
+    sp += sizeof(double) * 2 * (size_t)n;
     R *cw = (R *)sp;                        // (rho, S_ab sqrt(rho)) per quartet combo of the current bra
     sp += FockSmem<R>::cw_bytes;
     R *lbra = (R *)sp;                      // [G2][4] Px, Py, Pz, S of the current bra
@@ -239,14 +275,24 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     const BasisDev *bd = a.bd;
 
     const R *gtab = Prec<R>::boys(a);
-    for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) tab[x] = gtab[x];
+    if (kSplit) {
+        // grid-scaled rows: coefficient m times h^m sqrt(h)
+        for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) {
+            const int m = x % kBoysStride;
+            double sc = sqrt(kBoysH);
+            for (int e = 0; e < m; ++e) sc *= kBoysH;
+            tab[x] = (R)(a.boys[x] * sc);   // from the FP64 rows: one rounding for FP32
+        }
+    } else {
+        for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) tab[x] = gtab[x];
+    }
     if (!kSplit) {
         for (int x = tid; x < G2 * G2; x += kGroupThreads) {
             luni[2 * x] = Prec<R>::rho(bd)[x];
             luni[2 * x + 1] = Prec<R>::srho(bd)[x];
         }
     }
-    const cptr<R> crs = (cptr<R>)Prec<R>::rs(bd);
+    const cptr<R> crs = (cptr<R>)Prec<R>::rsn(bd);
     double *jcol = a.jcol + (int64_t)gid * a.pcap;
     double *fp = a.strategy == HFK_STRATEGY_PRIVATE ? a.fpriv + (int64_t)gid * n * n : a.fpriv;
     if (a.strategy == HFK_STRATEGY_PRIVATE) {

@@ -13,10 +13,13 @@ constexpr int kMaxG = HFK_MAX_NGAUSS;
 constexpr int kMaxG2 = kMaxG * kMaxG;
 
 // Pairs are ordered by (Q band, spatial cell of the pair centre): band b holds
-// 2^(1-(b+1)/R) <= Q < 2^(1-b/R); within a band, cells follow a Morton curve over the
-// bounding box (kCellBits per axis), so 64 consecutive kets sit close together in space.
-constexpr int kBandsPerOctave = 2;
-constexpr int kNumBands = 64 * kBandsPerOctave;
+// 2^(1-(b+1)/R) <= Q < 2^(1-b/R) with R bands per octave; within a band, cells follow a
+// Morton curve over the bounding box (kCellBits per axis), so 64 consecutive kets sit
+// close together in space.  Wide bands (two octaves) put more pairs in a band, so a
+// wave's kets are closer together and fewer waves straddle the near/far switch, for a
+// few more kets that fail the lane-level screen at the end of a bra's prefix.
+constexpr double kBandsPerOctave = 0.5;
+constexpr int kNumBands = 128;
 constexpr int kCellBits = 4;
 constexpr int kNumCells = 1 << (3 * kCellBits);
 constexpr int kNumBuckets = kNumBands * kNumCells;
@@ -76,6 +79,8 @@ struct BasisDev {
     double r2sw[kMaxG2 * kMaxG2];   // kTswitch / rho: |P-Q|^2 beyond which the far field is exact
     double rs[3 * kMaxG2 * kMaxG2];     // (rho, sqrt(rho), kTswitch / rho) interleaved
     float rs_f[3 * kMaxG2 * kMaxG2];
+    double rsn[3 * kMaxG2 * kMaxG2];    // (kTswitch / rho, rho / h, sqrt(rho / h)): T on the table grid
+    float rsn_f[3 * kMaxG2 * kMaxG2];
     float rho_f[kMaxG2 * kMaxG2];
     float srho_f[kMaxG2 * kMaxG2];
     float r2sw_f[kMaxG2 * kMaxG2];

@@ -37,6 +37,12 @@ __global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ b
         bd->rs_f[3 * x] = (float)rho;
         bd->rs_f[3 * x + 1] = (float)sqrt(rho);
         bd->rs_f[3 * x + 2] = (float)(kTswitch / rho);
+        bd->rsn[3 * x] = kTswitch / rho;
+        bd->rsn[3 * x + 1] = rho * kBoysInvH;
+        bd->rsn[3 * x + 2] = sqrt(rho * kBoysInvH);
+        bd->rsn_f[3 * x] = (float)(kTswitch / rho);
+        bd->rsn_f[3 * x + 1] = (float)(rho * kBoysInvH);
+        bd->rsn_f[3 * x + 2] = (float)sqrt(rho * kBoysInvH);
         bd->srho_f[x] = (float)sqrt(rho);
         bd->r2sw_f[x] = (float)(kTswitch / rho);
     }
