@@ -5,10 +5,13 @@
 // Work decomposition.  Significant pairs are stored in Q-bucketed order (t = 0 .. S-1),
 // so the kets kept by the screen for a bra s form a prefix t < lim_s (t <= s keeps each
 // unordered quartet once; a lane-level test Q_s Q_t >= tau handles the partial bucket).
-// An item is (bra s, 256 consecutive kets); items are numbered bra by bra and every
+// An item is (bra s, 1024 consecutive kets); items are numbered bra by bra and every
 // persistent workgroup takes one contiguous range of them, so a workgroup stays on one
-// bra for many items.  Each of its four waves takes 64 kets of an item, one per lane;
-// the bra's primitive data are wave-uniform.
+// bra for many items.  Each of its four waves takes 256 kets of an item and runs them as
+// 64-lane chunks, one ket per lane; the bra's primitive data are wave-uniform.  In the
+// hybrid form the wave first drops the kets that fail the screen and orders the rest by
+// distance from the bra (a counting sort over distance bins in LDS), so the near-field
+// kets share chunks and the chunks beyond them stay entirely far.
 //
 // Accumulation (replacing one global FP64 atomic per update):
 //   F_ij += 4 D_kl v   per-lane register, reduced across the wave when the bra changes
@@ -35,12 +38,15 @@ struct FockArgs {
     const float *bra_f;
     const long long *item_off;
     const int *lim;
+    const float4 *pcen;
     const double *dens;
     double *fpriv;
     double *jcol;
     unsigned long long *quartets;
+    unsigned long long *next_block;
     int64_t pcap;
     double tau;
+    float bin_inv;      // distance bins per bohr of the ket sort
     int n;
     int strategy;
 };
@@ -264,6 +270,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     sp += FockSmem<R>::uni_bytes;
     __shared__ int bra_at[2];
     __shared__ double bra_qd[2];
+    __shared__ int wcnt[kWavesPerGroup][kSortBins], woff[kWavesPerGroup][kSortBins];
+    __shared__ int wperm[kWavesPerGroup][kWaveKets];
 
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
@@ -271,7 +279,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     const int gid = blockIdx.x, ng = gridDim.x;
     const long long M = a.hdr->items;
     const int S = a.hdr->sig_pairs;
-    const long long m0 = M * gid / ng, m1 = M * (gid + 1) / ng;
     const BasisDev *bd = a.bd;
 
     const R *gtab = Prec<R>::boys(a);
@@ -300,7 +307,17 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     }
     for (int64_t x = tid; x < S; x += kGroupThreads) jcol[x] = 0.0;
     __syncthreads();
-    if (m0 >= m1) return;
+    const R *prim = Prec<R>::prim(a);
+    unsigned long long kept = 0;
+    __shared__ long long blk_at;
+    // blocks of kBlockItems consecutive items, fetched from a global counter until exhausted
+    for (;;) {
+    if (tid == 0) blk_at = (long long)atomicAdd(a.next_block, 1ULL);
+    __syncthreads();
+    const long long m0 = blk_at * kBlockItems;
+    __syncthreads();
+    if (m0 >= M) break;
+    const long long m1 = m0 + kBlockItems < M ? m0 + kBlockItems : M;
 
     // bra of the first item: the last s with item_off[s] <= m0
     int s;
@@ -312,11 +329,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
         }
         s = lo;
     }
-    const R *prim = Prec<R>::prim(a);
     int cur = -1, bi = 0, bj = 0;
     double qs = 0.0, ds = 0.0, jb = 0.0;
-    unsigned long long kept = 0;
     int lim = 0;
+    float4 bc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 
     for (long long m = m0; m <= m1; ++m) {
         if (m < m1) {
@@ -368,36 +384,94 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
             qs = bra_qd[0];
             ds = bra_qd[1];
             lim = a.lim[s];
+            bc = a.pcen[s];
         }
-        const long long t0 = (m - a.item_off[s]) * kKetsPerItem + (long long)wave * kWave;
-        if (t0 >= lim) continue;
-        const long long t = t0 + lane;   // < S + 64 <= pcap: padded tables
-        const bool in = t < lim;
-        const double qt = a.pq[t];
-        const bool valid = in && (qs * qt >= a.tau);
-        R eri;
-        if (kSplit)
-            eri = quartet_eri_hybrid<G, R>((cptr<R>)(Prec<R>::bra(a) + (int64_t)s * 8 * G2), prim, a.pcap, t, valid,
-                                           crs, tab);
-        else
-            eri = quartet_eri_direct<G, R>(lbra, prim, a.pcap, t, luni, tab);
-        const int k = a.pk[t], l = a.pl[t];
-        double deg = 1.0;
-        if (bi == bj) deg *= 0.5;
-        if (k == l) deg *= 0.5;
-        if (t == s) deg *= 0.5;
-        const double v = valid ? (double)eri * deg : 0.0;
-        jb = fma(a.pd[t], v, jb);
-        if (valid) {
-            ++kept;
-            jcol[t] += 4.0 * ds * v;
-            const double *Di = a.dens + (int64_t)bi * n;
-            const double *Dj = a.dens + (int64_t)bj * n;
-            atomicAdd(&rowi[k], -Dj[l] * v);
-            atomicAdd(&rowi[l], -Dj[k] * v);
-            atomicAdd(&rowj[k], -Di[l] * v);
-            atomicAdd(&rowj[l], -Di[k] * v);
+        const long long wbase = (m - a.item_off[s]) * kItemKets + (long long)wave * kWaveKets;
+        if (wbase >= lim) continue;
+        // one 64-lane chunk: ket t per lane (valid: kept by the screen), scatter of v
+        auto chunk = [&](int t, bool valid) {
+            R eri;
+            if (kSplit)
+                eri = quartet_eri_hybrid<G, R>((cptr<R>)(Prec<R>::bra(a) + (int64_t)s * 8 * G2), prim, a.pcap, t,
+                                               valid, crs, tab);
+            else
+                eri = quartet_eri_direct<G, R>(lbra, prim, a.pcap, t, luni, tab);
+            const int k = a.pk[t], l = a.pl[t];
+            double deg = 1.0;
+            if (bi == bj) deg *= 0.5;
+            if (k == l) deg *= 0.5;
+            if (t == s) deg *= 0.5;
+            const double v = valid ? (double)eri * deg : 0.0;
+            jb = fma(a.pd[t], v, jb);
+            if (valid) {
+                ++kept;
+                jcol[t] += 4.0 * ds * v;
+                const double *Di = a.dens + (int64_t)bi * n;
+                const double *Dj = a.dens + (int64_t)bj * n;
+                atomicAdd(&rowi[k], -Dj[l] * v);
+                atomicAdd(&rowi[l], -Dj[k] * v);
+                atomicAdd(&rowj[k], -Di[l] * v);
+                atomicAdd(&rowj[l], -Di[k] * v);
+            }
+        };
+        if (kSplit) {
+            // keep the screened kets of this wave's 256 and order them by distance bin
+            int *cnt = wcnt[wave], *off = woff[wave], *perm = wperm[wave];
+            if (lane < kSortBins) cnt[lane] = 0;
+            int tv[kSubChunks], bin[kSubChunks];
+            int nvalid = 0;
+#pragma unroll
+            for (int r = 0; r < kSubChunks; ++r) {
+                const long long t = wbase + r * kWave + lane;
+                bool ok = false;
+                int bn = kSortBins - 1;
+                if (t < lim) {
+                    ok = qs * a.pq[t] >= a.tau;
+                    if (ok) {
+                        const float4 c = a.pcen[t];
+                        const float dx = c.x - bc.x, dy = c.y - bc.y, dz = c.z - bc.z;
+                        const float dd = sqrtf(dx * dx + dy * dy + dz * dz);
+                        bn = min((int)(dd * a.bin_inv), kSortBins - 2);
+                    }
+                }
+                tv[r] = (int)t;
+                bin[r] = bn;
+                nvalid += (int)__popcll(__builtin_amdgcn_ballot_w64(ok));
+            }
+            if (nvalid == 0) continue;
+            __builtin_amdgcn_wave_barrier();
+            int slot[kSubChunks];
+#pragma unroll
+            for (int r = 0; r < kSubChunks; ++r) slot[r] = atomicAdd(&cnt[bin[r]], 1);
+            __builtin_amdgcn_wave_barrier();
+            // exclusive prefix of the bin counts across lanes 0 .. kSortBins-1
+            const int cv = lane < kSortBins ? cnt[lane] : 0;
+            int inc = cv;
+#pragma unroll
+            for (int o = 1; o < kSortBins; o <<= 1) {
+                const int y = __shfl_up(inc, o, kWave);
+                if (lane >= o) inc += y;
+            }
+            if (lane < kSortBins) off[lane] = inc - cv;
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int r = 0; r < kSubChunks; ++r)
+                if (bin[r] < kSortBins - 1) perm[off[bin[r]] + slot[r]] = tv[r];
+            __builtin_amdgcn_wave_barrier();
+            for (int c0 = 0; c0 < nvalid; c0 += kWave) {
+                const bool valid = c0 + lane < nvalid;
+                chunk(valid ? perm[c0 + lane] : s, valid);
+            }
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            for (int c = 0; c < kSubChunks; ++c) {
+                const long long t0 = wbase + c * kWave;
+                if (t0 >= lim) break;
+                const long long t = t0 + lane;   // < S + 64 <= pcap: padded tables
+                chunk((int)t, t < lim && qs * a.pq[t] >= a.tau);
+            }
         }
+    }
     }
     // survivors: one atomic per wave
     for (int off = 32; off > 0; off >>= 1) kept += __shfl_xor(kept, off, 64);
@@ -487,6 +561,8 @@ static hipError_t launch_fock_t(const FockArgs &a, int groups, int variant, hipS
 {
     const bool split = variant != 0;
     const size_t smem = FockSmem<R>::total(a.n, split);
+    const hipError_t ez = launch_zero_counter(a.next_block, st);
+    if (ez != hipSuccess) return ez;
     profile_begin(st);
     if (split)
         hipLaunchKernelGGL((k_fock<G, R, true>), dim3(groups), dim3(kGroupThreads), smem, st, a);
@@ -521,12 +597,20 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.bra_f = (const float *)(ws + L.bra_f);
     a.item_off = (const long long *)(ws + L.item_off);
     a.lim = (const int *)(ws + L.lim);
+    a.pcen = (const float4 *)(ws + L.pcen);
     a.dens = dens;
     a.fpriv = (double *)(ws + L.fpriv);
     a.jcol = (double *)(ws + L.jcol);
     a.quartets = &hdr->quartets;
+    a.next_block = &hdr->next_block;
     a.pcap = L.pcap;
     a.tau = tau;
+    {
+        // bins span 1.25 x the largest switch radius, sqrt(T_s / rho_min) with rho_min = alpha_min
+        double amin = b.alpha[0];
+        for (int i = 1; i < b.g; ++i) amin = b.alpha[i] < amin ? b.alpha[i] : amin;
+        a.bin_inv = (float)((kSortBins - 1) / (1.25 * sqrt(kTswitch / amin)));
+    }
     a.n = (int)L.n;
     a.strategy = strategy;
     const int64_t n2 = L.n * L.n;

@@ -132,103 +132,107 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                 ABy = a.xyz[3 * bi + 1] - a.xyz[3 * bj + 1];
                 ABz = a.xyz[3 * bi + 2] - a.xyz[3 * bj + 2];
             }
-            const long long t0 = (m - a.item_off[s]) * kKetsPerItem + (long long)wave * kWave;
-            if (t0 >= lim) continue;
-            const long long t = t0 + lane;
-            const bool valid = (t < lim) && (qs * a.pq[t] >= a.tau);
-            const cptr<R> bra = (cptr<R>)(GPrec<R>::bra(a) + (int64_t)s * 8 * G2);
+            const long long wbase = (m - a.item_off[s]) * kItemKets + (long long)wave * kWaveKets;
+            if (wbase >= lim) continue;
+            for (int sub = 0; sub < kSubChunks; ++sub) {
+                const long long t0 = wbase + sub * kWave;
+                if (t0 >= lim) break;
+                const long long t = t0 + lane;
+                const bool valid = (t < lim) && (qs * a.pq[t] >= a.tau);
+                const cptr<R> bra = (cptr<R>)(GPrec<R>::bra(a) + (int64_t)s * 8 * G2);
 
-            R sX = R(0), eri = R(0);
-            R sYa[3] = {R(0), R(0), R(0)}, sYb[3] = {R(0), R(0), R(0)};
-            double kC[3] = {0.0, 0.0, 0.0};
-            const int k = a.pk[t], l = a.pl[t];
-            const double CDx = a.xyz[3 * k] - a.xyz[3 * l];
-            const double CDy = a.xyz[3 * k + 1] - a.xyz[3 * l + 1];
-            const double CDz = a.xyz[3 * k + 2] - a.xyz[3 * l + 2];
-#pragma unroll 1
-            for (int cb = 0; cb < G; ++cb) {
-                R kx[G], ky[G], kz[G], ks[G];
-                R Uc[G], Vc[G][3];
-#pragma unroll
-                for (int d = 0; d < G; ++d) {
-                    const int cd = cb * G + d;
-                    kx[d] = prim[(int64_t)(0 * G2 + cd) * a.pcap + t];
-                    ky[d] = prim[(int64_t)(1 * G2 + cd) * a.pcap + t];
-                    kz[d] = valid ? prim[(int64_t)(2 * G2 + cd) * a.pcap + t] : R(1e10);
-                    ks[d] = prim[(int64_t)(3 * G2 + cd) * a.pcap + t];
-                    Uc[d] = R(0);
-                    Vc[d][0] = Vc[d][1] = Vc[d][2] = R(0);
-                }
-#pragma unroll 1
-                for (int ab = 0; ab < G2; ++ab) {
-                    cptr<R> b = bra + 8 * ab;
-                    const R px = b[0], py = b[1], pz = b[2], sab = b[3];
-                    R U = R(0), V0 = R(0), V1 = R(0), V2 = R(0);
+                R sX = R(0), eri = R(0);
+                R sYa[3] = {R(0), R(0), R(0)}, sYb[3] = {R(0), R(0), R(0)};
+                double kC[3] = {0.0, 0.0, 0.0};
+                const int k = a.pk[t], l = a.pl[t];
+                const double CDx = a.xyz[3 * k] - a.xyz[3 * l];
+                const double CDy = a.xyz[3 * k + 1] - a.xyz[3 * l + 1];
+                const double CDz = a.xyz[3 * k + 2] - a.xyz[3 * l + 2];
+    #pragma unroll 1
+                for (int cb = 0; cb < G; ++cb) {
+                    R kx[G], ky[G], kz[G], ks[G];
+                    R Uc[G], Vc[G][3];
 #pragma unroll
                     for (int d = 0; d < G; ++d) {
-                        const int x = ab * G2 + cb * G + d;
-                        const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
-                        const R r2 = dx * dx + dy * dy + dz * dz;
-                        R E, W;
-                        if (__builtin_amdgcn_ballot_w64(r2 < rs[3 * x + 2])) {
-                            R h, gg;
-                            const R rho = rs[3 * x], srho = rs[3 * x + 1];
-                            boys_hg<R>(r2 * rho, tH, tG, h, gg);
-                            E = srho * h;
-                            W = (rho * srho) * gg;
-                        } else {
-                            const R y = GPrec<R>::rsqrt(r2);
-                            E = y;
-                            W = -(y * y * y);
-                        }
-                        const R wk = ks[d] * W, wb = sab * W;
-                        U += ks[d] * E;
-                        V0 += wk * dx;
-                        V1 += wk * dy;
-                        V2 += wk * dz;
-                        Uc[d] += sab * E;
-                        Vc[d][0] += wb * dx;
-                        Vc[d][1] += wb * dy;
-                        Vc[d][2] += wb * dz;
+                        const int cd = cb * G + d;
+                        kx[d] = prim[(int64_t)(0 * G2 + cd) * a.pcap + t];
+                        ky[d] = prim[(int64_t)(1 * G2 + cd) * a.pcap + t];
+                        kz[d] = valid ? prim[(int64_t)(2 * G2 + cd) * a.pcap + t] : R(1e10);
+                        ks[d] = prim[(int64_t)(3 * G2 + cd) * a.pcap + t];
+                        Uc[d] = R(0);
+                        Vc[d][0] = Vc[d][1] = Vc[d][2] = R(0);
                     }
-                    const R su = sab * U;
-                    eri += su;
-                    sX += (R)cmu[ab] * su;
-                    const R fa = (R)cfa[ab] * sab, fb = (R)cfb[ab] * sab;
-                    sYa[0] += fa * V0; sYa[1] += fa * V1; sYa[2] += fa * V2;
-                    sYb[0] += fb * V0; sYb[1] += fb * V1; sYb[2] += fb * V2;
-                }
+    #pragma unroll 1
+                    for (int ab = 0; ab < G2; ++ab) {
+                        cptr<R> b = bra + 8 * ab;
+                        const R px = b[0], py = b[1], pz = b[2], sab = b[3];
+                        R U = R(0), V0 = R(0), V1 = R(0), V2 = R(0);
 #pragma unroll
-                for (int d = 0; d < G; ++d) {
-                    const int cd = cb * G + d;
-                    const double sc = (double)ks[d];
-                    const double mu2 = -2.0 * cmu[cd] * sc * (double)Uc[d];
-                    const double fc = cfa[cd] * sc;
-                    kC[0] += mu2 * CDx - fc * (double)Vc[d][0];
-                    kC[1] += mu2 * CDy - fc * (double)Vc[d][1];
-                    kC[2] += mu2 * CDz - fc * (double)Vc[d][2];
-                }
-            }
-            if (valid) {
-                double deg = 1.0;
-                if (bi == bj) deg *= 0.5;
-                if (k == l) deg *= 0.5;
-                if (t == s) deg *= 0.5;
-                const double *Di = a.dens + (int64_t)bi * n, *Dj = a.dens + (int64_t)bj * n;
-                const double gam = deg * (4.0 * ds * a.pd[t] - Di[k] * Dj[l] - Di[l] * Dj[k]);
-                const double AB[3] = {ABx, ABy, ABz};
-                double GA[3], GB[3], GC[3];
+                        for (int d = 0; d < G; ++d) {
+                            const int x = ab * G2 + cb * G + d;
+                            const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
+                            const R r2 = dx * dx + dy * dy + dz * dz;
+                            R E, W;
+                            if (__builtin_amdgcn_ballot_w64(r2 < rs[3 * x + 2])) {
+                                R h, gg;
+                                const R rho = rs[3 * x], srho = rs[3 * x + 1];
+                                boys_hg<R>(r2 * rho, tH, tG, h, gg);
+                                E = srho * h;
+                                W = (rho * srho) * gg;
+                            } else {
+                                const R y = GPrec<R>::rsqrt(r2);
+                                E = y;
+                                W = -(y * y * y);
+                            }
+                            const R wk = ks[d] * W, wb = sab * W;
+                            U += ks[d] * E;
+                            V0 += wk * dx;
+                            V1 += wk * dy;
+                            V2 += wk * dz;
+                            Uc[d] += sab * E;
+                            Vc[d][0] += wb * dx;
+                            Vc[d][1] += wb * dy;
+                            Vc[d][2] += wb * dz;
+                        }
+                        const R su = sab * U;
+                        eri += su;
+                        sX += (R)cmu[ab] * su;
+                        const R fa = (R)cfa[ab] * sab, fb = (R)cfb[ab] * sab;
+                        sYa[0] += fa * V0; sYa[1] += fa * V1; sYa[2] += fa * V2;
+                        sYb[0] += fb * V0; sYb[1] += fb * V1; sYb[2] += fb * V2;
+                    }
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    GA[c] = gam * (-2.0 * AB[c] * (double)sX + (double)sYa[c]);
-                    GB[c] = gam * (2.0 * AB[c] * (double)sX + (double)sYb[c]);
-                    GC[c] = gam * kC[c];
-                    gA[c] += GA[c];
-                    gB[c] += GB[c];
-                    atomicAdd(&lg[3 * k + c], GC[c]);
-                    atomicAdd(&lg[3 * l + c], -(GA[c] + GB[c] + GC[c]));
+                    for (int d = 0; d < G; ++d) {
+                        const int cd = cb * G + d;
+                        const double sc = (double)ks[d];
+                        const double mu2 = -2.0 * cmu[cd] * sc * (double)Uc[d];
+                        const double fc = cfa[cd] * sc;
+                        kC[0] += mu2 * CDx - fc * (double)Vc[d][0];
+                        kC[1] += mu2 * CDy - fc * (double)Vc[d][1];
+                        kC[2] += mu2 * CDz - fc * (double)Vc[d][2];
+                    }
                 }
-                eacc += gam * (double)eri;
+                if (valid) {
+                    double deg = 1.0;
+                    if (bi == bj) deg *= 0.5;
+                    if (k == l) deg *= 0.5;
+                    if (t == s) deg *= 0.5;
+                    const double *Di = a.dens + (int64_t)bi * n, *Dj = a.dens + (int64_t)bj * n;
+                    const double gam = deg * (4.0 * ds * a.pd[t] - Di[k] * Dj[l] - Di[l] * Dj[k]);
+                    const double AB[3] = {ABx, ABy, ABz};
+                    double GA[3], GB[3], GC[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        GA[c] = gam * (-2.0 * AB[c] * (double)sX + (double)sYa[c]);
+                        GB[c] = gam * (2.0 * AB[c] * (double)sX + (double)sYb[c]);
+                        GC[c] = gam * kC[c];
+                        gA[c] += GA[c];
+                        gB[c] += GB[c];
+                        atomicAdd(&lg[3 * k + c], GC[c]);
+                        atomicAdd(&lg[3 * l + c], -(GA[c] + GB[c] + GC[c]));
+                    }
+                    eacc += gam * (double)eri;
+                }
             }
         }
     }

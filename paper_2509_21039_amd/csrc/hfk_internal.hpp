@@ -39,6 +39,13 @@ constexpr int kWave = 64;
 constexpr int kWavesPerGroup = 4;
 constexpr int kGroupThreads = kWave * kWavesPerGroup;
 constexpr int kKetsPerItem = kGroupThreads;   // one 64-ket chunk per wave per item
+// Single-molecule items: (bra, kItemKets kets); each wave takes kWaveKets of them and runs
+// them as kSubChunks 64-lane chunks (after sorting them by distance to the bra).
+constexpr int kSubChunks = 4;
+constexpr int kWaveKets = kWave * kSubChunks;
+constexpr int kItemKets = kWavesPerGroup * kWaveKets;
+constexpr int kSortBins = 16;
+constexpr int kBlockItems = 16;  // items per dynamically fetched block of the quartet kernels   // distance bins of the per-wave ket sort; the last holds screened-out kets
 
 // Device-side counters written by the build and read back by hfk_read_stats.
 struct DevHeader {
@@ -56,6 +63,7 @@ struct DevHeader {
     int natoms;
     int variant;
     int pad1;
+    unsigned long long next_block;  // work counter of the quartet kernels (blocks of items)
 };
 
 // Basis constants shared by every pair, computed on the host from exps/coefs and passed
@@ -94,6 +102,7 @@ struct Layout {
     size_t hdr, basis, boys, boys_f;
     size_t q_unsorted, bucket_of, bucket_cnt, bucket_off, bucket_cur;
     size_t pk, pl, pq, pd;                 // sorted pair tables
+    size_t pcen;                           // [pcap] float4: pair centre (centroid frame), sort key source
     size_t prim;                           // [4][g2][pcap] doubles: Px, Py, Pz, S
     size_t prim_f;                         // [4][g2][pcap] floats (mixed)
     size_t bra, bra_f;                     // [pcap][g2][8] Px Py Pz S -2Px -2Py -2Pz |P|^2 (wave-uniform bra data)
@@ -136,6 +145,7 @@ int device_cu_count();
 // Each returns hipSuccess or the launch error; all enqueue on `st`.
 hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, double *boys_g,
                         float *boys_g_f, DevHeader *hdr, int64_t n, const double *xyz, hipStream_t st);
+hipError_t launch_zero_counter(unsigned long long *p, hipStream_t st);
 hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
                         double tau, hipStream_t st);
 hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *dens, double tau,

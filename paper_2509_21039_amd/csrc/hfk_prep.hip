@@ -224,7 +224,8 @@ __global__ __launch_bounds__(256) void k_bucket_cursors(const long long *__restr
 }
 
 // Writes every significant pair at its bucketed position: atoms, Q, D_kl and the SoA
-// primitive-pair table {Px, Py, Pz, S} (FP64 and FP32), centred on the centroid.
+// primitive-pair table {Px, Py, Pz, S} (FP64 and FP32), centred on the centroid, and the
+// pair centre (midpoint of the two atoms) as a float4.
 __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *__restrict__ bd,
                                                       const DevHeader *__restrict__ hdr, int64_t n,
                                                       int64_t pcap, const double *__restrict__ xyz,
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
                                                       int *__restrict__ pl, double *__restrict__ pq,
                                                       double *__restrict__ pd, double *__restrict__ prim,
                                                       float *__restrict__ prim_f, double *__restrict__ bra,
-                                                      float *__restrict__ bra_f)
+                                                      float *__restrict__ bra_f, float4 *__restrict__ pcen)
 {
     const int64_t npair = n * (n + 1) / 2;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -254,6 +255,8 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
     pl[pos] = (int)j;
     pq[pos] = q[p];
     pd[pos] = dens[i * n + j];
+    pcen[pos] = make_float4((float)(0.5 * (A[0] + B[0])), (float)(0.5 * (A[1] + B[1])), (float)(0.5 * (A[2] + B[2])),
+                            0.0f);
     const int g2 = b.g2;
     for (int ab = 0; ab < g2; ++ab) {
         prim[(0 * g2 + ab) * pcap + pos] = px[ab];
@@ -305,7 +308,7 @@ hipError_t launch_pair_pad(const DevHeader *hdr, int64_t pcap, int g2, int *pk, 
 }
 
 // Ket range of every bra s (in bucketed order): kets t < lim_s with
-// lim_s = min(s + 1, end of the band holding tau / Q_s); items of kKetsPerItem kets.
+// lim_s = min(s + 1, end of the band holding tau / Q_s); items of kItemKets kets.
 __global__ __launch_bounds__(256) void k_limits(const DevHeader *__restrict__ hdr, double tau,
                                                 const double *__restrict__ pq,
                                                 const long long *__restrict__ boff,
@@ -326,7 +329,7 @@ __global__ __launch_bounds__(256) void k_limits(const DevHeader *__restrict__ hd
             bend = (thr > 2.0) ? 0 : (bt + 1 >= kNumBands ? S : boff[(bt + 1) * kNumCells]);
         }
         const int64_t lim = bend < s + 1 ? bend : s + 1;
-        ni = (lim + kKetsPerItem - 1) / kKetsPerItem;
+        ni = (lim + kItemKets - 1) / kItemKets;
         lims[s] = (int)lim;
     } else {
         lims[s] = 0;
@@ -432,6 +435,18 @@ hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision
     return hipGetLastError();
 }
 
+__global__ void k_zero_u64(unsigned long long *__restrict__ p)
+{
+    if (threadIdx.x == 0) *p = 0ULL;
+}
+
+// Zeroes a work counter with a kernel (stream-ordered, no memset node).
+hipError_t launch_zero_counter(unsigned long long *p, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, p);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_i64(long long *__restrict__ p, int64_t m)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -460,7 +475,7 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
                        (const double *)(ws + L.q_unsorted), (const int *)(ws + L.bucket_of), cur,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f), (double *)(ws + L.bra),
-                       (float *)(ws + L.bra_f));
+                       (float *)(ws + L.bra_f), (float4 *)(ws + L.pcen));
     hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, L.pcap, L.g2,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f));
