@@ -74,7 +74,6 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
     L.pk = take(sizeof(int) * PC);
     L.pl = take(sizeof(int) * PC);
     L.pq = take(sizeof(double) * PC);
-    L.pcen = take(sizeof(float) * 4 * PC);
     L.pd = take(sizeof(double) * PC);
     L.prim = take(sizeof(double) * 4 * g2 * PC);
     L.prim_f = take(sizeof(float) * 4 * g2 * PC);

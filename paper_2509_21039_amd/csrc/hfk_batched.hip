@@ -3,11 +3,11 @@
 //
 // Pairs of every molecule are prepared in one pass and stored in (molecule, Q band) order;
 // a bra's kets are the molecule's pairs up to its screen limit (t <= s keeps each quartet
-// once).  Items of 256 kets are numbered molecule by molecule and every workgroup takes a
-// contiguous item range.  A workgroup keeps the current molecule's whole two-electron
-// matrix in LDS (lower triangle, the symmetrisation G = (F + F^T)/2 folded in: F_xy and F_yx
-// land in the same slot) and its n x 3 gradient, and flushes both with global atomics once
-// per molecule it worked on.  Per primitive quartet the loop forms E(r) (the integral) and
+// once).  Items of 256 kets are numbered molecule by molecule; workgroups fetch blocks of
+// consecutive items from a global counter.  A workgroup keeps the current molecule's whole
+// two-electron matrix in LDS (lower triangle, the symmetrisation G = (F + F^T)/2 folded in:
+// F_xy and F_yx land in the same slot) and its n x 3 gradient, and flushes both with
+// global atomics when the molecule or the block changes.  Per primitive quartet the loop forms E(r) (the integral) and
 // W(r) = E'(r)/r (its radial derivative) from the same r^2, so the forward result and the
 // gradient come out of one pass over the quartets.
 #include <string.h>
@@ -48,6 +48,7 @@ struct BArgs {
     double *facc;        // packed lower triangles, molecule m at mol_toff[m]
     double *gacc;        // [sum n][3]
     unsigned long long *quartets;
+    unsigned long long *next_block;
     int64_t pcap;
     double tau;
     int nmax;
@@ -258,14 +259,21 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
     const int gid = blockIdx.x, ng = gridDim.x;
     const long long M = a.hdr->items;
     const int S = a.hdr->sig_pairs;
-    const long long m0 = M * gid / ng, m1 = M * (gid + 1) / ng;
     const BasisDev *bd = a.bd;
     for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) {
         tH[x] = BPrec<R>::tabH(a)[x];
         tG[x] = BPrec<R>::tabG(a)[x];
     }
+    unsigned long long kept = 0;
+    __shared__ long long blk_at;
+    // blocks of kBlockItems consecutive items, fetched from a global counter until exhausted
+    for (;;) {
     __syncthreads();
-    if (m0 >= m1) return;
+    if (tid == 0) blk_at = (long long)atomicAdd(a.next_block, 1ULL);
+    __syncthreads();
+    const long long m0 = blk_at * kBlockItems;
+    if (m0 >= M) break;
+    const long long m1 = m0 + kBlockItems < M ? m0 + kBlockItems : M;
     int s;
     {
         int lo = 0, hi = S - 1;
@@ -286,7 +294,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
     int bi = 0, bj = 0, lim = 0, klo = 0;
     double qs = 0.0, ds = 0.0, ABx = 0.0, ABy = 0.0, ABz = 0.0;
     double jb = 0.0, gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
-    unsigned long long kept = 0;
 
     for (long long m = m0; m <= m1; ++m) {
         if (m < m1) {
@@ -465,6 +472,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
                 }
             }
         }
+    }
     }
     for (int off = 32; off > 0; off >>= 1) kept += __shfl_xor(kept, off, 64);
     if (lane == 0 && kept) atomicAdd(a.quartets, kept);
@@ -694,10 +702,15 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
     a.facc = (double *)(ws + L.facc);
     a.gacc = grad ? (double *)(ws + L.gacc) : nullptr;
     a.quartets = &hdr->quartets;
+    a.next_block = &hdr->next_block;
     a.pcap = L.pcap;
     a.tau = tau;
     a.nmax = L.nmax;
     const size_t smem = batched_smem_bytes(L.nmax, prec);
+    {
+        const hipError_t ez = launch_zero_counter(a.next_block, st);
+        if (ez != hipSuccess) return ez;
+    }
     profile_begin(st);
 #define HFK_B_LAUNCH(GG, RR, GR) \
     hipLaunchKernelGGL((k_batched<GG, RR, GR>), dim3(groups), dim3(kGroupThreads), smem, st, a)

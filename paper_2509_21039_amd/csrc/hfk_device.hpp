@@ -103,4 +103,25 @@ __device__ inline double wave_sum(double v)
 
 __device__ inline int lane_id() { return (int)__lane_id(); }
 
+// Packs this wave's kets t = base + r * 64 + lane (r < kSubChunks) for which keep(t) holds
+// into perm[0 .. count), in ascending order (ballot + lane count, no atomics), and returns
+// the wave-uniform count.
+template <typename Keep>
+__device__ inline int pack_kets(long long base, int lane, int *__restrict__ perm, Keep keep)
+{
+    int count = 0;
+#pragma unroll
+    for (int r = 0; r < kSubChunks; ++r) {
+        const long long t = base + r * kWave + lane;
+        const bool ok = keep(t);
+        const unsigned long long mk = __builtin_amdgcn_ballot_w64(ok);
+        if (ok)
+            perm[count + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u))] =
+                (int)t;
+        count += (int)__popcll(mk);
+    }
+    __builtin_amdgcn_wave_barrier();
+    return count;
+}
+
 }  // namespace hfk

@@ -5,13 +5,14 @@
 // Work decomposition.  Significant pairs are stored in Q-bucketed order (t = 0 .. S-1),
 // so the kets kept by the screen for a bra s form a prefix t < lim_s (t <= s keeps each
 // unordered quartet once; a lane-level test Q_s Q_t >= tau handles the partial bucket).
-// An item is (bra s, 1024 consecutive kets); items are numbered bra by bra and every
-// persistent workgroup takes one contiguous range of them, so a workgroup stays on one
-// bra for many items.  Each of its four waves takes 256 kets of an item and runs them as
+// An item is (bra s, 1024 consecutive kets); items are numbered bra by bra and persistent
+// workgroups fetch blocks of consecutive items, so a workgroup stays on one bra for
+// several items.  Each of its four waves takes 256 kets of an item and runs them as
 // 64-lane chunks, one ket per lane; the bra's primitive data are wave-uniform.  In the
-// hybrid form the wave first drops the kets that fail the screen and orders the rest by
-// distance from the bra (a counting sort over distance bins in LDS), so the near-field
-// kets share chunks and the chunks beyond them stay entirely far.
+// hybrid form the wave first packs the kets that pass the screen (ballot + lane count,
+// order kept so loads stay coalesced) into full chunks.  Items are handed out in blocks
+// of kBlockItems from a global counter: the cost per item varies with the bra's
+// surroundings, and static ranges left a long tail of slow workgroups.
 //
 // Accumulation (replacing one global FP64 atomic per update):
 //   F_ij += 4 D_kl v   per-lane register, reduced across the wave when the bra changes
@@ -38,7 +39,6 @@ struct FockArgs {
     const float *bra_f;
     const long long *item_off;
     const int *lim;
-    const float4 *pcen;
     const double *dens;
     double *fpriv;
     double *jcol;
@@ -46,7 +46,6 @@ struct FockArgs {
     unsigned long long *next_block;
     int64_t pcap;
     double tau;
-    float bin_inv;      // distance bins per bohr of the ket sort
     int n;
     int strategy;
 };
@@ -270,7 +269,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     sp += FockSmem<R>::uni_bytes;
     __shared__ int bra_at[2];
     __shared__ double bra_qd[2];
-    __shared__ int wcnt[kWavesPerGroup][kSortBins], woff[kWavesPerGroup][kSortBins];
     __shared__ int wperm[kWavesPerGroup][kWaveKets];
 
     const int tid = threadIdx.x;
@@ -332,7 +330,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     int cur = -1, bi = 0, bj = 0;
     double qs = 0.0, ds = 0.0, jb = 0.0;
     int lim = 0;
-    float4 bc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 
     for (long long m = m0; m <= m1; ++m) {
         if (m < m1) {
@@ -384,7 +381,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
             qs = bra_qd[0];
             ds = bra_qd[1];
             lim = a.lim[s];
-            bc = a.pcen[s];
         }
         const long long wbase = (m - a.item_off[s]) * kItemKets + (long long)wave * kWaveKets;
         if (wbase >= lim) continue;
@@ -415,49 +411,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
             }
         };
         if (kSplit) {
-            // keep the screened kets of this wave's 256 and order them by distance bin
-            int *cnt = wcnt[wave], *off = woff[wave], *perm = wperm[wave];
-            if (lane < kSortBins) cnt[lane] = 0;
-            int tv[kSubChunks], bin[kSubChunks];
-            int nvalid = 0;
-#pragma unroll
-            for (int r = 0; r < kSubChunks; ++r) {
-                const long long t = wbase + r * kWave + lane;
-                bool ok = false;
-                int bn = kSortBins - 1;
-                if (t < lim) {
-                    ok = qs * a.pq[t] >= a.tau;
-                    if (ok) {
-                        const float4 c = a.pcen[t];
-                        const float dx = c.x - bc.x, dy = c.y - bc.y, dz = c.z - bc.z;
-                        const float dd = sqrtf(dx * dx + dy * dy + dz * dz);
-                        bn = min((int)(dd * a.bin_inv), kSortBins - 2);
-                    }
-                }
-                tv[r] = (int)t;
-                bin[r] = bn;
-                nvalid += (int)__popcll(__builtin_amdgcn_ballot_w64(ok));
-            }
+            // keep the screened kets of this wave's 256, in order, packed into full chunks
+            int *perm = wperm[wave];
+            const int nvalid = pack_kets(wbase, lane, perm,
+                                         [&](long long t) { return t < lim && qs * a.pq[t] >= a.tau; });
             if (nvalid == 0) continue;
-            __builtin_amdgcn_wave_barrier();
-            int slot[kSubChunks];
-#pragma unroll
-            for (int r = 0; r < kSubChunks; ++r) slot[r] = atomicAdd(&cnt[bin[r]], 1);
-            __builtin_amdgcn_wave_barrier();
-            // exclusive prefix of the bin counts across lanes 0 .. kSortBins-1
-            const int cv = lane < kSortBins ? cnt[lane] : 0;
-            int inc = cv;
-#pragma unroll
-            for (int o = 1; o < kSortBins; o <<= 1) {
-                const int y = __shfl_up(inc, o, kWave);
-                if (lane >= o) inc += y;
-            }
-            if (lane < kSortBins) off[lane] = inc - cv;
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int r = 0; r < kSubChunks; ++r)
-                if (bin[r] < kSortBins - 1) perm[off[bin[r]] + slot[r]] = tv[r];
-            __builtin_amdgcn_wave_barrier();
             for (int c0 = 0; c0 < nvalid; c0 += kWave) {
                 const bool valid = c0 + lane < nvalid;
                 chunk(valid ? perm[c0 + lane] : s, valid);
@@ -597,7 +555,6 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.bra_f = (const float *)(ws + L.bra_f);
     a.item_off = (const long long *)(ws + L.item_off);
     a.lim = (const int *)(ws + L.lim);
-    a.pcen = (const float4 *)(ws + L.pcen);
     a.dens = dens;
     a.fpriv = (double *)(ws + L.fpriv);
     a.jcol = (double *)(ws + L.jcol);
@@ -605,12 +562,6 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.next_block = &hdr->next_block;
     a.pcap = L.pcap;
     a.tau = tau;
-    {
-        // bins span 1.25 x the largest switch radius, sqrt(T_s / rho_min) with rho_min = alpha_min
-        double amin = b.alpha[0];
-        for (int i = 1; i < b.g; ++i) amin = b.alpha[i] < amin ? b.alpha[i] : amin;
-        a.bin_inv = (float)((kSortBins - 1) / (1.25 * sqrt(kTswitch / amin)));
-    }
     a.n = (int)L.n;
     a.strategy = strategy;
     const int64_t n2 = L.n * L.n;

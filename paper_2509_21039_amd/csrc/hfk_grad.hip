@@ -11,8 +11,9 @@
 //   d(ab|cd)/dD = -(dA + dB + dC)            (translation invariance)
 // Beyond the switch E = 1/r and W = -1/r^3 exactly; below it both come from Taylor tables.
 //
-// Work decomposition as in the forward kernel (items of 256 kets of one bra, one contiguous
-// item range per workgroup, one 64-ket chunk per wave).  Bra-atom gradients accumulate in
+// Work decomposition as in the forward kernel (items of 1024 kets of one bra in blocks
+// fetched from a global counter, 256 kets per wave packed into full 64-lane chunks after
+// the screen).  Bra-atom gradients accumulate in
 // registers and are reduced across the wave when the bra changes; ket-atom gradients go to
 // an LDS copy of the n x 3 gradient; each workgroup writes its copy out once.
 #include "hfk_device.hpp"
@@ -40,6 +41,7 @@ struct GradArgs {
     const double *xyz;
     double *gpriv;      // [groups][n*3]
     double *epart;      // [groups]
+    unsigned long long *next_block;
     int64_t pcap;
     double tau;
     int n;
@@ -76,8 +78,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
     const int gid = blockIdx.x, ng = gridDim.x;
     const long long M = a.hdr->items;
     const int S = a.hdr->sig_pairs;
-    const long long m0 = M * gid / ng, m1 = M * (gid + 1) / ng;
     const BasisDev *bd = a.bd;
+    __shared__ int wperm[kWavesPerGroup][kWaveKets];
+    __shared__ long long blk_at;
     for (int x = tid; x < 3 * n; x += kGroupThreads) lg[x] = 0.0;
     for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) {
         tH[x] = GPrec<R>::tabH(a)[x];
@@ -86,7 +89,15 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
     __syncthreads();
 
     double eacc = 0.0;
-    if (m0 < m1) {
+    // blocks of kBlockItems consecutive items, fetched from a global counter until exhausted
+    for (;;) {
+    __syncthreads();
+    if (tid == 0) blk_at = (long long)atomicAdd(a.next_block, 1ULL);
+    __syncthreads();
+    const long long m0 = blk_at * kBlockItems;
+    if (m0 >= M) break;
+    const long long m1 = m0 + kBlockItems < M ? m0 + kBlockItems : M;
+    {
         int s;
         {
             int lo = 0, hi = S - 1;
@@ -134,11 +145,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
             }
             const long long wbase = (m - a.item_off[s]) * kItemKets + (long long)wave * kWaveKets;
             if (wbase >= lim) continue;
-            for (int sub = 0; sub < kSubChunks; ++sub) {
-                const long long t0 = wbase + sub * kWave;
-                if (t0 >= lim) break;
-                const long long t = t0 + lane;
-                const bool valid = (t < lim) && (qs * a.pq[t] >= a.tau);
+            int *perm = wperm[wave];
+            const int nvalid = pack_kets(wbase, lane, perm,
+                                         [&](long long t) { return t < lim && qs * a.pq[t] >= a.tau; });
+            if (nvalid == 0) continue;
+            for (int c0 = 0; c0 < nvalid; c0 += kWave) {
+                const bool valid = c0 + lane < nvalid;
+                const long long t = valid ? perm[c0 + lane] : s;
                 const cptr<R> bra = (cptr<R>)(GPrec<R>::bra(a) + (int64_t)s * 8 * G2);
 
                 R sX = R(0), eri = R(0);
@@ -234,7 +247,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                     eacc += gam * (double)eri;
                 }
             }
+            __builtin_amdgcn_wave_barrier();
         }
+    }
     }
     // energy partial of the workgroup
     __shared__ double ered[kWavesPerGroup];
@@ -292,6 +307,8 @@ size_t grad_smem_bytes(int64_t n, int prec)
 template <int G, typename R>
 static hipError_t launch_grad_t(const GradArgs &a, int groups, size_t smem, hipStream_t st)
 {
+    const hipError_t ez = launch_zero_counter(a.next_block, st);
+    if (ez != hipSuccess) return ez;
     hipLaunchKernelGGL((k_grad<G, R>), dim3(groups), dim3(kGroupThreads), smem, st, a);
     return hipGetLastError();
 }
@@ -321,6 +338,7 @@ hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *
     a.xyz = xyz;
     a.gpriv = (double *)(ws + L.grad);
     a.epart = (double *)(ws + L.grad) + (size_t)L.groups * 3 * L.n;
+    a.next_block = &((DevHeader *)(ws + L.hdr))->next_block;
     a.pcap = L.pcap;
     a.tau = tau;
     a.n = (int)L.n;

@@ -40,12 +40,11 @@ constexpr int kWavesPerGroup = 4;
 constexpr int kGroupThreads = kWave * kWavesPerGroup;
 constexpr int kKetsPerItem = kGroupThreads;   // one 64-ket chunk per wave per item
 // Single-molecule items: (bra, kItemKets kets); each wave takes kWaveKets of them and runs
-// them as kSubChunks 64-lane chunks (after sorting them by distance to the bra).
+// them as kSubChunks 64-lane chunks.
 constexpr int kSubChunks = 4;
 constexpr int kWaveKets = kWave * kSubChunks;
 constexpr int kItemKets = kWavesPerGroup * kWaveKets;
-constexpr int kSortBins = 16;
-constexpr int kBlockItems = 16;  // items per dynamically fetched block of the quartet kernels   // distance bins of the per-wave ket sort; the last holds screened-out kets
+constexpr int kBlockItems = 16;  // items per dynamically fetched block of the quartet kernels
 
 // Device-side counters written by the build and read back by hfk_read_stats.
 struct DevHeader {
@@ -102,7 +101,6 @@ struct Layout {
     size_t hdr, basis, boys, boys_f;
     size_t q_unsorted, bucket_of, bucket_cnt, bucket_off, bucket_cur;
     size_t pk, pl, pq, pd;                 // sorted pair tables
-    size_t pcen;                           // [pcap] float4: pair centre (centroid frame), sort key source
     size_t prim;                           // [4][g2][pcap] doubles: Px, Py, Pz, S
     size_t prim_f;                         // [4][g2][pcap] floats (mixed)
     size_t bra, bra_f;                     // [pcap][g2][8] Px Py Pz S -2Px -2Py -2Pz |P|^2 (wave-uniform bra data)

@@ -224,8 +224,7 @@ __global__ __launch_bounds__(256) void k_bucket_cursors(const long long *__restr
 }
 
 // Writes every significant pair at its bucketed position: atoms, Q, D_kl and the SoA
-// primitive-pair table {Px, Py, Pz, S} (FP64 and FP32), centred on the centroid, and the
-// pair centre (midpoint of the two atoms) as a float4.
+// primitive-pair table {Px, Py, Pz, S} (FP64 and FP32), centred on the centroid.
 __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *__restrict__ bd,
                                                       const DevHeader *__restrict__ hdr, int64_t n,
                                                       int64_t pcap, const double *__restrict__ xyz,
@@ -236,7 +235,7 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
                                                       int *__restrict__ pl, double *__restrict__ pq,
                                                       double *__restrict__ pd, double *__restrict__ prim,
                                                       float *__restrict__ prim_f, double *__restrict__ bra,
-                                                      float *__restrict__ bra_f, float4 *__restrict__ pcen)
+                                                      float *__restrict__ bra_f)
 {
     const int64_t npair = n * (n + 1) / 2;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -255,8 +254,6 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
     pl[pos] = (int)j;
     pq[pos] = q[p];
     pd[pos] = dens[i * n + j];
-    pcen[pos] = make_float4((float)(0.5 * (A[0] + B[0])), (float)(0.5 * (A[1] + B[1])), (float)(0.5 * (A[2] + B[2])),
-                            0.0f);
     const int g2 = b.g2;
     for (int ab = 0; ab < g2; ++ab) {
         prim[(0 * g2 + ab) * pcap + pos] = px[ab];
@@ -475,7 +472,7 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
                        (const double *)(ws + L.q_unsorted), (const int *)(ws + L.bucket_of), cur,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f), (double *)(ws + L.bra),
-                       (float *)(ws + L.bra_f), (float4 *)(ws + L.pcen));
+                       (float *)(ws + L.bra_f));
     hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, L.pcap, L.g2,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f));
