@@ -75,7 +75,7 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
     L.pl = take(sizeof(int) * PC);
     L.pq = take(sizeof(double) * PC);
     L.pd = take(sizeof(double) * PC);
-    L.prim = take(sizeof(double) * 4 * g2 * PC);
+    L.prim = take(sizeof(double) * 5 * g2 * PC);   // Px, Py, Pz, S, |P|^2
     L.prim_f = take(sizeof(float) * 4 * g2 * PC);
     L.bra = take(sizeof(double) * 8 * g2 * PC);
     L.bra_f = take(sizeof(float) * 8 * g2 * PC);

@@ -176,16 +176,16 @@ __device__ inline R boys_grid(R Ts, bool near, const R *__restrict__ tab)
 // no lane of the wave has |P-Q|^2 below the switch radius (the common case once kets are
 // spatially sorted), the lanes add the far-field value S_cd / |P-Q| (exact beyond the
 // switch); otherwise every lane evaluates S_cd sqrt(rho/h) * sqrt(h) H(T) through the
-// grid table or its far-field form.  Lanes without a kept quartet get ket centres far
-// away, so they are never near.  Uniform data come through scalar loads issued together
+// grid table or its far-field form.  Lanes without a kept quartet point at a pad entry
+// (centres 1e6 bohr away, zero weight), so they are never near and add nothing.  Uniform data come through scalar loads issued together
 // at the top of each bra primitive: (Px, Py, Pz, S, -2Px, -2Py, -2Pz, |P|^2) and, per
 // primitive quartet, (switch radius^2, rho/h, sqrt(rho/h)).
 // FP64 forms |P-Q|^2 as |P|^2 + |Q|^2 - 2 P.Q (4 operations; with centroid-centred
 // coordinates the cancellation stays near 1e-13 bohr^2 absolute); FP32 subtracts the
 // centres directly, which its precision needs.
 template <int G, typename R>
-__device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, int64_t pcap, int64_t t,
-                                       bool valid, cptr<R> rsn, const R *__restrict__ tab)
+__device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, int64_t pcap, unsigned t,
+                                       cptr<R> rsn, const R *__restrict__ tab)
 {
     constexpr int G2 = G * G;
     constexpr bool kExpand = sizeof(R) == 8;
@@ -193,14 +193,19 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
 #pragma unroll 1
     for (int cb = 0; cb < G; ++cb) {
         R kx[G], ky[G], kz[G], ks[G], kq[G];
+        // uniform base per component plus one 32-bit byte offset per lane (t < 2^29)
+        const unsigned tb = t * (unsigned)sizeof(R);
+        auto ld = [&](int c, int cd) {
+            return *(const R *)((const char *)(prim + (int64_t)(c * G2 + cd) * pcap) + tb);
+        };
 #pragma unroll
         for (int d = 0; d < G; ++d) {
             const int cd = cb * G + d;
-            kx[d] = prim[(int64_t)(0 * G2 + cd) * pcap + t];
-            ky[d] = prim[(int64_t)(1 * G2 + cd) * pcap + t];
-            kz[d] = valid ? prim[(int64_t)(2 * G2 + cd) * pcap + t] : R(1e10);
-            ks[d] = prim[(int64_t)(3 * G2 + cd) * pcap + t];
-            kq[d] = kx[d] * kx[d] + ky[d] * ky[d] + kz[d] * kz[d];
+            kx[d] = ld(0, cd);
+            ky[d] = ld(1, cd);
+            kz[d] = ld(2, cd);
+            ks[d] = ld(3, cd);
+            kq[d] = kExpand ? ld(4, cd) : R(0);
         }
 #pragma unroll 1
         for (int ab = 0; ab < G2; ++ab) {
@@ -388,8 +393,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
         auto chunk = [&](int t, bool valid) {
             R eri;
             if (kSplit)
-                eri = quartet_eri_hybrid<G, R>((cptr<R>)(Prec<R>::bra(a) + (int64_t)s * 8 * G2), prim, a.pcap, t,
-                                               valid, crs, tab);
+                eri = quartet_eri_hybrid<G, R>((cptr<R>)(Prec<R>::bra(a) + (int64_t)s * 8 * G2), prim, a.pcap,
+                                               (unsigned)t, crs, tab);
             else
                 eri = quartet_eri_direct<G, R>(lbra, prim, a.pcap, t, luni, tab);
             const int k = a.pk[t], l = a.pl[t];
@@ -418,7 +423,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
             if (nvalid == 0) continue;
             for (int c0 = 0; c0 < nvalid; c0 += kWave) {
                 const bool valid = c0 + lane < nvalid;
-                chunk(valid ? perm[c0 + lane] : s, valid);
+                chunk(valid ? perm[c0 + lane] : S, valid);   // S: first pad entry
             }
             __builtin_amdgcn_wave_barrier();
         } else {

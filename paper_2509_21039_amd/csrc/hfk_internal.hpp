@@ -101,7 +101,7 @@ struct Layout {
     size_t hdr, basis, boys, boys_f;
     size_t q_unsorted, bucket_of, bucket_cnt, bucket_off, bucket_cur;
     size_t pk, pl, pq, pd;                 // sorted pair tables
-    size_t prim;                           // [4][g2][pcap] doubles: Px, Py, Pz, S
+    size_t prim;                           // [5][g2][pcap] doubles: Px, Py, Pz, S, |P|^2
     size_t prim_f;                         // [4][g2][pcap] floats (mixed)
     size_t bra, bra_f;                     // [pcap][g2][8] Px Py Pz S -2Px -2Py -2Pz |P|^2 (wave-uniform bra data)
     size_t boys_g, boys_g_f;               // Taylor table of g(T) = -(4/sqrt(pi)) F1(T) (gradient)
@@ -134,6 +134,7 @@ size_t batched_smem_bytes(int nmax, int prec);
 hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int64_t *atom_off_host, const double *xyz,
                           const double *dens, double tau, int prec, double *fock, double *e2, double *d_xyz,
                           int groups, hipStream_t st);
+// Pads the batched pair tables (four-component FP64 ket table) past the last pair.
 hipError_t launch_pair_pad(const DevHeader *hdr, int64_t pcap, int g2, int *pk, int *pl, double *pq, double *pd,
                            double *prim, float *prim_f, hipStream_t st);
 

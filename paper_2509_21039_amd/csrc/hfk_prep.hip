@@ -260,6 +260,7 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
         prim[(1 * g2 + ab) * pcap + pos] = py[ab];
         prim[(2 * g2 + ab) * pcap + pos] = pz[ab];
         prim[(3 * g2 + ab) * pcap + pos] = ps[ab];
+        prim[(4 * g2 + ab) * pcap + pos] = px[ab] * px[ab] + py[ab] * py[ab] + pz[ab] * pz[ab];
         prim_f[(0 * g2 + ab) * pcap + pos] = (float)px[ab];
         prim_f[(1 * g2 + ab) * pcap + pos] = (float)py[ab];
         prim_f[(2 * g2 + ab) * pcap + pos] = (float)pz[ab];
@@ -275,9 +276,11 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
     }
 }
 
-// Pads the tail chunk of the sorted tables with harmless entries (atom 0, zero weight) so
-// that lanes past the last pair read defined memory.
-__global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int g2,
+// Pads the tail chunk of the sorted tables with harmless entries (atom 0, zero weight,
+// centres 1e6 bohr away) so that lanes past the last pair, or lanes pointed at the first
+// pad entry, read defined memory and land in the far branch with a zero integral.
+// ncomp: FP64 components of the ket table (4: Px Py Pz S; 5 adds |P|^2).
+__global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int g2, int ncomp,
                            int *__restrict__ pk, int *__restrict__ pl, double *__restrict__ pq,
                            double *__restrict__ pd, double *__restrict__ prim, float *__restrict__ prim_f)
 {
@@ -293,14 +296,16 @@ __global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int 
             prim[(c * g2 + ab) * pcap + pos] = c < 3 ? 1e6 : 0.0;
             prim_f[(c * g2 + ab) * pcap + pos] = c < 3 ? 1e6f : 0.0f;
         }
+        if (ncomp > 4) prim[(4 * g2 + ab) * pcap + pos] = 3e12;
     }
 }
 
 hipError_t launch_pair_pad(const DevHeader *hdr, int64_t pcap, int g2, int *pk, int *pl, double *pq, double *pd,
                            double *prim, float *prim_f, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((pcap + 255) / 256)), dim3(256), 0, st, hdr, pcap, g2, pk, pl, pq, pd,
-                       prim, prim_f);
+    // the batched tables hold the four-component FP64 ket table
+    hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((pcap + 255) / 256)), dim3(256), 0, st, hdr, pcap, g2, 4, pk, pl,
+                       pq, pd, prim, prim_f);
     return hipGetLastError();
 }
 
@@ -473,7 +478,7 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f), (double *)(ws + L.bra),
                        (float *)(ws + L.bra_f));
-    hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, L.pcap, L.g2,
+    hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, L.pcap, L.g2, 5,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f));
     hipLaunchKernelGGL(k_limits, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, tau,
