@@ -193,10 +193,17 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
 #pragma unroll 1
     for (int cb = 0; cb < G; ++cb) {
         R kx[G], ky[G], kz[G], ks[G], kq[G];
-        // uniform base per component plus one 32-bit byte offset per lane (t < 2^29)
+        // buffer loads: one resource per component (g2 * pcap values, < 4 GiB), the primitive
+        // pair as a scalar offset and the ket as a 32-bit lane offset (no 64-bit address math)
         const unsigned tb = t * (unsigned)sizeof(R);
         auto ld = [&](int c, int cd) {
-            return *(const R *)((const char *)(prim + (int64_t)(c * G2 + cd) * pcap) + tb);
+            const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(prim + (int64_t)c * G2 * pcap), (short)0, (int)(G2 * pcap * (int64_t)sizeof(R)), 0x00020000);
+            const int so = (int)((int64_t)cd * pcap * (int64_t)sizeof(R));
+            if constexpr (sizeof(R) == 8)
+                return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rc, (int)tb, so, 0));
+            else
+                return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)tb, so, 0));
         };
 #pragma unroll
         for (int d = 0; d < G; ++d) {
