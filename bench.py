@@ -24,8 +24,39 @@ sys.path.insert(0, ROOT)
 METRIC = "ERI quartets/s & % FP64 VALU peak; mixed-prec and fwd+grad vs plain FP64"
 FP64_VALU_PEAK_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, FP64 vector
 FP32_VALU_PEAK_TFLOPS = 157.3
-FLOP_PER_PRIM_QUARTET = 31        # nominal count of the general formulation
+FLOP_PER_PRIM_QUARTET = 31        # nominal flops per primitive quartet: the algorithmic work unit
 FLOP_SCATTER_PER_QUARTET = 14
+
+
+# Hardware-counter summary of the quartet kernel (FETCH_SIZE / WRITE_SIZE, scaled by the
+# same counters read on a plain copy of known size).  Used only while the kernel sources
+# and the launch configuration are the ones the counters were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fock_he512_fp64_traffic.json")
+KERNEL_SOURCES = ["paper_2509_21039_amd/csrc/hfk_fock.hip", "paper_2509_21039_amd/csrc/hfk_device.hpp",
+                  "paper_2509_21039_amd/csrc/hfk_internal.hpp"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stats):
+    """HBM bytes per launch from the committed counter summary, or None if it is stale."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    cfg = t.get("config", {})
+    if (t.get("source_sha256") != kernel_source_hash() or cfg.get("strategy") != stats["strategy"]
+            or cfg.get("variant") != stats["variant"] or cfg.get("groups") != stats["groups"]):
+        return None
+    return t.get("bytes_per_launch")
 
 
 def log(msg):
@@ -167,16 +198,22 @@ def main():
     s = config_system("he512_fp64")
     g = len(s.exps)
     if args.traffic_probe:
+        # the configuration the timed run uses: tune, then one build; then a plain copy
         ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, g, "fp64"), dev)
         xyz_t = torch.tensor(s.xyz, device=dev)
         D_t = torch.tensor(s.dens, device=dev)
+        hfk.tune(xyz_t, D_t, s.exps, s.coefs, s.tau, precision="fp64")
+        torch.cuda.synchronize()
         hfk.fock(xyz_t, D_t, s.exps, s.coefs, s.tau, workspace=ws)
+        torch.cuda.synchronize()
+        st = hfk.read_stats(ws)
         nbytes = 512 << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": nbytes}), flush=True)
+        print(json.dumps({"copy_bytes": nbytes, "strategy": st["strategy"], "variant": st["variant"],
+                          "groups": st["groups"], "source_sha256": kernel_source_hash()}), flush=True)
         return
     ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, g, "fp64"), dev)
     log("he512 fp64: autotune")
@@ -211,7 +248,7 @@ def main():
                    "workgroups": r["stats"]["groups"], "parallelism": "single GPU"},
         "pct_fp64_valu_peak_nominal": 100.0 * achieved / FP64_VALU_PEAK_TFLOPS,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": measured_traffic(r["stats"]),
                      "kernel": "k_fock<3,double>", "kernel_ms": r["kernel_ms"],
                      "flop_per_quartet": flop_per_quartet(g)},
         "e2": r["e2"],

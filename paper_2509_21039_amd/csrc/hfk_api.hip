@@ -165,7 +165,7 @@ static TunedConfig pick_config(int32_t strategy, int32_t precision, int64_t n)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         c = g_tuned_cfg[precision][size_class(n)];
     }
-    if (c.strategy == 0) c = TunedConfig{HFK_STRATEGY_PRIVATE, 1, precision == HFK_MIXED ? 6 : 4};
+    if (c.strategy == 0) c = TunedConfig{HFK_STRATEGY_PRIVATE, 1, 6};
     if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_ATOMIC) c.strategy = strategy;
     if (g_cfg_variant >= 0) c.variant = g_cfg_variant;
     if (g_cfg_gpc > 0) c.gpc = g_cfg_gpc;
@@ -497,7 +497,7 @@ hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     const int save_var = g_cfg_variant, save_gpc = g_cfg_gpc;
     const int strategies[2] = {HFK_STRATEGY_PRIVATE, HFK_STRATEGY_ATOMIC};
     const int variants[2] = {1, 0};
-    const int gpcs[4] = {2, 3, 4, 6};
+    const int gpcs[4] = {3, 4, 5, 6};
     TunedConfig best{0, 1, 2};
     double best_ms = 1e300;
     hfk_status err = HFK_OK;

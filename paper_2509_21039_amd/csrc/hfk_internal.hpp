@@ -29,7 +29,7 @@ constexpr int kNumBuckets = kNumBands * kNumCells;
 // H(T) = erf(sqrt T)/sqrt T = sum_n c_n (T - T_k)^n near T_k.  A second table holds the
 // expansion of g(T) = -(4/sqrt(pi)) F1(T) for the gradient.
 constexpr int kBoysOrder = 7;          // coefficients used (degree 6)
-constexpr int kBoysStride = 9;         // row length: odd in doubles, so rows start on 16 different LDS bank pairs
+constexpr int kBoysStride = 7;         // row length: odd in doubles, so rows start on 16 different LDS bank pairs
 constexpr double kBoysH = 0.125;       // grid spacing
 constexpr double kBoysInvH = 8.0;
 constexpr double kTswitch = 32.0;      // above this H(T) = T^(-1/2) to < 1e-15 relative
