@@ -42,6 +42,9 @@ int device_cu_count()
 
 // Per-workgroup copies of F are used while they stay within this many bytes in total.
 constexpr double kPrivateBudget = 16.0e9;
+// Ket-side Coulomb vectors: one per workgroup within this budget, else fewer copies that
+// workgroups share through atomics.
+constexpr double kJcolBudget = 8.0e9;
 
 Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
 {
@@ -87,7 +90,11 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
     L.scan_tmp = take(sizeof(long long) * (((PC > (size_t)kNumBuckets ? PC : (size_t)kNumBuckets) + 1023) / 1024 + 1));
     const size_t n2 = (size_t)(n * n);
     L.fpriv = take(sizeof(double) * n2 * (size_t)(L.private_ok ? groups : 1));
-    L.jcol = take(sizeof(double) * PC * (size_t)groups);
+    {
+        const double fit = kJcolBudget / (8.0 * (double)PC);
+        L.jcopies = fit >= (double)groups ? groups : (fit >= 1.0 ? (int)fit : 1);
+    }
+    L.jcol = take(sizeof(double) * PC * (size_t)L.jcopies);
     L.fsum = take(sizeof(double) * n2);
     L.e2part = take(sizeof(double) * ((n2 + 255) / 256 + 256));
     L.grad = with_grad ? take(sizeof(double) * 3 * (size_t)n * (size_t)groups + sizeof(double) * 4096) : 0;
@@ -293,7 +300,11 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     const TunedConfig cfg = pick_config(strategy, precision, natoms);
     int strat = cfg.strategy;
     if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
-    L.groups = cus * cfg.gpc;
+    {
+        // no more persistent workgroups than fit on a CU at once
+        const int fit = fock_resident_groups(ngauss, precision, cfg.variant, natoms);
+        L.groups = cus * (fit > 0 && cfg.gpc > fit ? fit : cfg.gpc);
+    }
     const Basis b = make_basis(ngauss, exps_host, coefs_host);
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;

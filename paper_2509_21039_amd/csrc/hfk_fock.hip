@@ -17,6 +17,7 @@
 // Accumulation (replacing one global FP64 atomic per update):
 //   F_ij += 4 D_kl v   per-lane register, reduced across the wave when the bra changes
 //   F_kl += 4 D_ij v   coalesced read-modify-write of a per-workgroup vector over kets
+//                      (atomics into shared copies when per-workgroup ones exceed the budget)
 //   F_ik, F_il, F_jk, F_jl -= ...   LDS atomics into copies of rows i and j of F, flushed
 //                      to a per-workgroup copy of F (or with global atomics) once per bra
 // and a final kernel sums the copies, symmetrises and forms E2.
@@ -41,13 +42,14 @@ struct FockArgs {
     const int *lim;
     const double *dens;
     double *fpriv;
-    double *jcol;
+    double *jcol;       // [jcopies][pcap]
     unsigned long long *quartets;
     unsigned long long *next_block;
     int64_t pcap;
     double tau;
     int n;
     int strategy;
+    int jcopies;        // ket vectors: one per workgroup if equal to the grid, else shared (atomics)
 };
 
 template <typename R> struct Prec;
@@ -310,12 +312,15 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
         }
     }
     const cptr<R> crs = (cptr<R>)Prec<R>::rsn(bd);
-    double *jcol = a.jcol + (int64_t)gid * a.pcap;
+    const bool jshared = a.jcopies < ng;
+    double *jcol = a.jcol + (int64_t)(gid % a.jcopies) * a.pcap;
     double *fp = a.strategy == HFK_STRATEGY_PRIVATE ? a.fpriv + (int64_t)gid * n * n : a.fpriv;
     if (a.strategy == HFK_STRATEGY_PRIVATE) {
         for (int64_t x = tid; x < (int64_t)n * n; x += kGroupThreads) fp[x] = 0.0;
     }
-    for (int64_t x = tid; x < S; x += kGroupThreads) jcol[x] = 0.0;
+    if (!jshared) {
+        for (int64_t x = tid; x < S; x += kGroupThreads) jcol[x] = 0.0;
+    }
     __syncthreads();
     const R *prim = Prec<R>::prim(a);
     unsigned long long kept = 0;
@@ -413,7 +418,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
             jb = fma(a.pd[t], v, jb);
             if (valid) {
                 ++kept;
-                jcol[t] += 4.0 * ds * v;
+                if (jshared)
+                    atomicAdd(&jcol[t], 4.0 * ds * v);
+                else
+                    jcol[t] += 4.0 * ds * v;
                 const double *Di = a.dens + (int64_t)bi * n;
                 const double *Dj = a.dens + (int64_t)bj * n;
                 atomicAdd(&rowi[k], -Dj[l] * v);
@@ -472,7 +480,7 @@ __global__ __launch_bounds__(256) void k_fill(double *__restrict__ p, int64_t m,
     if (x < m) p[x] = v;
 }
 
-// F_kl += sum over workgroups of the ket-side Coulomb vector (each t is a distinct pair).
+// F_kl += sum over the copies of the ket-side Coulomb vector (each t is a distinct pair).
 __global__ __launch_bounds__(256) void k_jcol_scatter(const DevHeader *__restrict__ hdr,
                                                       const double *__restrict__ jcol, int groups,
                                                       int64_t pcap, const int *__restrict__ pk,
@@ -542,6 +550,37 @@ static hipError_t launch_fock_t(const FockArgs &a, int groups, int variant, hipS
     return hipGetLastError();
 }
 
+template <int G, typename R>
+static int resident_t(bool split, size_t smem)
+{
+    int nb = 0;
+    const hipError_t e = split ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fock<G, R, true>, kGroupThreads, smem)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fock<G, R, false>, kGroupThreads, smem);
+    return e == hipSuccess ? nb : 0;
+}
+
+// Workgroups of the quartet kernel that fit on one CU at once (registers and LDS); 0 if
+// the runtime cannot tell.  Persistent workgroups beyond this would only queue.
+int fock_resident_groups(int g, int prec, int variant, int64_t n)
+{
+    const bool split = variant != 0;
+    const size_t smem = fock_smem_bytes(n, prec, variant);
+    if (prec == HFK_MIXED) {
+        switch (g) {
+        case 1: return resident_t<1, float>(split, smem);
+        case 2: return resident_t<2, float>(split, smem);
+        case 3: return resident_t<3, float>(split, smem);
+        default: return resident_t<4, float>(split, smem);
+        }
+    }
+    switch (g) {
+    case 1: return resident_t<1, double>(split, smem);
+    case 2: return resident_t<2, double>(split, smem);
+    case 3: return resident_t<3, double>(split, smem);
+    default: return resident_t<4, double>(split, smem);
+    }
+}
+
 size_t fock_smem_bytes(int64_t n, int prec, int variant)
 {
     return prec == HFK_MIXED ? FockSmem<float>::total((int)n, variant != 0)
@@ -576,6 +615,12 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.tau = tau;
     a.n = (int)L.n;
     a.strategy = strategy;
+    a.jcopies = L.jcopies < L.groups ? L.jcopies : L.groups;
+    if (a.jcopies < L.groups) {
+        // shared ket vectors are cleared before the launch (workgroups clear private ones)
+        const int64_t nj = (int64_t)a.jcopies * L.pcap;
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)((nj + 255) / 256)), dim3(256), 0, st, a.jcol, nj, 0.0);
+    }
     const int64_t n2 = L.n * L.n;
     const unsigned nb2 = (unsigned)((n2 + 255) / 256);
     if (strategy == HFK_STRATEGY_ATOMIC)
@@ -604,7 +649,7 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     else
         hipLaunchKernelGGL(k_copy, dim3(nb2), dim3(256), 0, st, a.fpriv, n2, fsum);
     hipLaunchKernelGGL(k_jcol_scatter, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, a.jcol,
-                       L.groups, L.pcap, a.pk, a.pl, a.n, fsum);
+                       a.jcopies, L.pcap, a.pk, a.pl, a.n, fsum);
     double *part = (double *)(ws + L.e2part);
     hipLaunchKernelGGL(k_symmetrise, dim3(nb2), dim3(256), 0, st, fsum, dens, a.n, fock, part);
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, st, part, (int)nb2, 0.5, e2);

@@ -107,7 +107,8 @@ struct Layout {
     size_t boys_g, boys_g_f;               // Taylor table of g(T) = -(4/sqrt(pi)) F1(T) (gradient)
     size_t nitems, lim, item_off, scan_tmp;
     size_t fpriv;                          // [groups][n*n] or [n*n]
-    size_t jcol;                           // [groups][pcap]
+    size_t jcol;                           // [jcopies][pcap] ket-side Coulomb vectors
+    int jcopies;                           // copies of the ket vector (one per workgroup while they fit)
     size_t fsum;                           // [n*n]
     size_t e2part;                         // partial energies
     size_t grad;                           // [groups][n*3] gradient accumulators
@@ -150,6 +151,7 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
 hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *dens, double tau,
                        int prec, int strategy, int variant, double *fock, double *e2, hipStream_t st);
 size_t fock_smem_bytes(int64_t n, int prec, int variant);
+int fock_resident_groups(int g, int prec, int variant, int64_t n);
 // Events around the quartet kernel when profiling is enabled (no-ops otherwise).
 void profile_begin(hipStream_t st);
 void profile_end(hipStream_t st);

@@ -115,3 +115,30 @@ def test_unsupported_ngauss_raises(torch_dev):
     with pytest.raises(hfk.HfkError) as ei:
         hfk.fock(xyz, D, [1.0] * 5, [0.2] * 5, 0.0)
     assert ei.value.status == hfk.HFK_EUNSUPPORTED
+
+
+def test_max_atoms_sparse_lattice(torch_dev):
+    """The largest accepted system (6144 atoms) on a sparse lattice (14 bohr spacing): only
+    the one-centre pairs pass the screen, so the kept quartets are the S(S+1)/2 pairs of
+    them, while the LDS rows (> 64 KiB), the shared ket vectors and the workspace run at
+    their maximum sizes.  Sampled elements against the oracle's element-wise definition;
+    E2 against 1/2 sum D o G of the returned G."""
+    from he_inputs import jittered_lattice
+    s = jittered_lattice((16, 16, 24), seed=11, tau=1e-10, spacing=14.0, jitter=0.5)
+    n = s.natoms
+    assert n == 6144
+    announce("max atoms 6144 sparse fp64")
+    G, E2, st = _run(torch_dev, s)
+    Q = oracle.schwarz(s.xyz, s.exps, s.coefs)
+    S = int((Q * Q.max() >= s.tau).sum())
+    assert S == n
+    assert st["quartets"] == S * (S + 1) // 2
+    rng = np.random.default_rng(3)
+    idx = [(int(i), int(i)) for i in rng.integers(0, n, 6)] + \
+          [(int(i), int(j)) for i, j in rng.integers(0, n, (6, 2))] + [(0, n - 1), (n - 1, n - 1)]
+    ref = [oracle.fock_element(s.xyz, s.dens, s.exps, s.coefs, s.tau, Q, i, j) for i, j in idx]
+    scale = max(abs(r) for r in ref)
+    for (i, j), r in zip(idx, ref):
+        assert abs(G[i, j] - r) <= FP64_TOL * scale, (i, j, G[i, j], r)
+    assert np.array_equal(G, G.T)
+    assert rel(E2, 0.5 * float(np.sum(s.dens * G))) < 1e-12
