@@ -53,7 +53,7 @@ template <> struct GPrec<double> {
     static __device__ const double *bra(const GradArgs &a) { return a.bra; }
     static __device__ const double *tabH(const GradArgs &a) { return a.tabH; }
     static __device__ const double *tabG(const GradArgs &a) { return a.tabG; }
-    static __device__ const double *rs(const BasisDev *bd) { return bd->rs; }
+    static __device__ const double *rsg(const BasisDev *bd) { return bd->rsg; }
     static __device__ double rsqrt(double x) { return rsqrt_fp64(x); }
 };
 template <> struct GPrec<float> {
@@ -61,7 +61,7 @@ template <> struct GPrec<float> {
     static __device__ const float *bra(const GradArgs &a) { return a.bra_f; }
     static __device__ const float *tabH(const GradArgs &a) { return a.tabH_f; }
     static __device__ const float *tabG(const GradArgs &a) { return a.tabG_f; }
-    static __device__ const float *rs(const BasisDev *bd) { return bd->rs_f; }
+    static __device__ const float *rsg(const BasisDev *bd) { return bd->rsg_f; }
     static __device__ float rsqrt(float x) { return rsqrt_fp32(x); }
 };
 
@@ -82,9 +82,14 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
     __shared__ int wperm[kWavesPerGroup][kWaveKets];
     __shared__ long long blk_at;
     for (int x = tid; x < 3 * n; x += kGroupThreads) lg[x] = 0.0;
+    // grid-scaled rows (argument T' = T / h): coefficient m of H times h^m sqrt(h), of g times
+    // h^m h^(3/2), built from the FP64 rows
     for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) {
-        tH[x] = GPrec<R>::tabH(a)[x];
-        tG[x] = GPrec<R>::tabG(a)[x];
+        const int m = x % kBoysStride;
+        double sc = sqrt(kBoysH);
+        for (int e = 0; e < m; ++e) sc *= kBoysH;
+        tH[x] = (R)(a.tabH[x] * sc);
+        tG[x] = (R)(a.tabG[x] * sc * kBoysH);
     }
     __syncthreads();
 
@@ -108,7 +113,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
             s = lo;
         }
         const R *prim = GPrec<R>::prim(a);
-        const cptr<R> rs = (cptr<R>)GPrec<R>::rs(bd);
+        const cptr<R> rsg = (cptr<R>)GPrec<R>::rsg(bd);
         const cptr<double> cmu = (cptr<double>)bd->mu;
         const cptr<double> cfa = (cptr<double>)bd->fa;
         const cptr<double> cfb = (cptr<double>)bd->fb;
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
             if (nvalid == 0) continue;
             for (int c0 = 0; c0 < nvalid; c0 += kWave) {
                 const bool valid = c0 + lane < nvalid;
-                const long long t = valid ? perm[c0 + lane] : s;
+                const long long t = valid ? perm[c0 + lane] : S;   // S: first pad entry
                 const cptr<R> bra = (cptr<R>)(GPrec<R>::bra(a) + (int64_t)s * 8 * G2);
 
                 R sX = R(0), eri = R(0);
@@ -165,33 +170,68 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                 for (int cb = 0; cb < G; ++cb) {
                     R kx[G], ky[G], kz[G], ks[G];
                     R Uc[G], Vc[G][3];
+                    // buffer loads of the ket table: component base, primitive pair as a
+                    // scalar offset, ket as a 32-bit lane offset
+                    const unsigned tb = (unsigned)t * (unsigned)sizeof(R);
+                    auto ld = [&](int c, int cd) {
+                        const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+                            (void *)(prim + (int64_t)c * G2 * a.pcap), (short)0,
+                            (int)(G2 * a.pcap * (int64_t)sizeof(R)), 0x00020000);
+                        const int so = (int)((int64_t)cd * a.pcap * (int64_t)sizeof(R));
+                        if constexpr (sizeof(R) == 8)
+                            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rc, (int)tb, so, 0));
+                        else
+                            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)tb, so, 0));
+                    };
 #pragma unroll
                     for (int d = 0; d < G; ++d) {
                         const int cd = cb * G + d;
-                        kx[d] = prim[(int64_t)(0 * G2 + cd) * a.pcap + t];
-                        ky[d] = prim[(int64_t)(1 * G2 + cd) * a.pcap + t];
-                        kz[d] = valid ? prim[(int64_t)(2 * G2 + cd) * a.pcap + t] : R(1e10);
-                        ks[d] = prim[(int64_t)(3 * G2 + cd) * a.pcap + t];
+                        kx[d] = ld(0, cd);
+                        ky[d] = ld(1, cd);
+                        kz[d] = ld(2, cd);
+                        ks[d] = ld(3, cd);
                         Uc[d] = R(0);
                         Vc[d][0] = Vc[d][1] = Vc[d][2] = R(0);
                     }
-    #pragma unroll 1
+#pragma unroll 1
                     for (int ab = 0; ab < G2; ++ab) {
-                        cptr<R> b = bra + 8 * ab;
+                        // every scalar of this bra primitive in one batch of scalar loads
+                        const cptr<R> bp = bra + 8 * ab;
+                        const cptr<R> up = rsg + 4 * (ab * G2 + cb * G);
+                        R b[4], u[4 * G];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) b[c] = bp[c];
+#pragma unroll
+                        for (int c = 0; c < 4 * G; ++c) u[c] = up[c];
+#pragma unroll
+                        for (int c = 0; c < 4 * G; ++c) asm volatile("" ::"s"(u[c]));
                         const R px = b[0], py = b[1], pz = b[2], sab = b[3];
                         R U = R(0), V0 = R(0), V1 = R(0), V2 = R(0);
 #pragma unroll
                         for (int d = 0; d < G; ++d) {
-                            const int x = ab * G2 + cb * G + d;
                             const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
                             const R r2 = dx * dx + dy * dy + dz * dz;
+                            const bool near = r2 < u[4 * d];
                             R E, W;
-                            if (__builtin_amdgcn_ballot_w64(r2 < rs[3 * x + 2])) {
-                                R h, gg;
-                                const R rho = rs[3 * x], srho = rs[3 * x + 1];
-                                boys_hg<R>(r2 * rho, tH, tG, h, gg);
-                                E = srho * h;
-                                W = (rho * srho) * gg;
+                            if (__builtin_amdgcn_ballot_w64(near)) {
+                                // T' = T / h on the table grid; sqrt(h) H and h^(3/2) g, or their
+                                // far forms T'^(-1/2) and -T'^(-3/2)
+                                const R Ts = r2 * u[4 * d + 1];
+                                const R y = GPrec<R>::rsqrt(Ts);
+                                const R Tc = fmin(Ts, R(kBoysGrid - 4));
+                                const R kd = rint(Tc);
+                                const R dd = Tc - kd;
+                                const unsigned off = __umul24((unsigned)(int)kd, (unsigned)(kBoysStride * sizeof(R)));
+                                const R *ch = (const R *)((const char *)tH + off);
+                                const R *cg = (const R *)((const char *)tG + off);
+                                R vh = ch[6], vg = cg[6];
+#pragma unroll
+                                for (int m = 5; m >= 0; --m) {
+                                    vh = vh * dd + ch[m];
+                                    vg = vg * dd + cg[m];
+                                }
+                                E = u[4 * d + 2] * (near ? vh : y);
+                                W = u[4 * d + 3] * (near ? vg : -(y * y * y));
                             } else {
                                 const R y = GPrec<R>::rsqrt(r2);
                                 E = y;

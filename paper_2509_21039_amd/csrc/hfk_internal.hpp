@@ -88,6 +88,8 @@ struct BasisDev {
     float rs_f[3 * kMaxG2 * kMaxG2];
     double rsn[3 * kMaxG2 * kMaxG2];    // (kTswitch / rho, rho / h, sqrt(rho / h)): T on the table grid
     float rsn_f[3 * kMaxG2 * kMaxG2];
+    double rsg[4 * kMaxG2 * kMaxG2];    // (kTswitch / rho, rho / h, sqrt(rho / h), (rho / h)^(3/2))
+    float rsg_f[4 * kMaxG2 * kMaxG2];
     float rho_f[kMaxG2 * kMaxG2];
     float srho_f[kMaxG2 * kMaxG2];
     float r2sw_f[kMaxG2 * kMaxG2];

@@ -43,6 +43,17 @@ __global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ b
         bd->rsn_f[3 * x] = (float)(kTswitch / rho);
         bd->rsn_f[3 * x + 1] = (float)(rho * kBoysInvH);
         bd->rsn_f[3 * x + 2] = (float)sqrt(rho * kBoysInvH);
+        {
+            const double r = rho * kBoysInvH, sr = sqrt(r);
+            bd->rsg[4 * x] = kTswitch / rho;
+            bd->rsg[4 * x + 1] = r;
+            bd->rsg[4 * x + 2] = sr;
+            bd->rsg[4 * x + 3] = r * sr;
+            bd->rsg_f[4 * x] = (float)(kTswitch / rho);
+            bd->rsg_f[4 * x + 1] = (float)r;
+            bd->rsg_f[4 * x + 2] = (float)sr;
+            bd->rsg_f[4 * x + 3] = (float)(r * sr);
+        }
         bd->srho_f[x] = (float)sqrt(rho);
         bd->r2sw_f[x] = (float)(kTswitch / rho);
     }
