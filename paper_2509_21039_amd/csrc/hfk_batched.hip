@@ -60,14 +60,14 @@ template <> struct BPrec<double> {
     static __device__ const double *bra(const BArgs &a) { return a.bra; }
     static __device__ const double *tabH(const BArgs &a) { return a.tabH; }
     static __device__ const double *tabG(const BArgs &a) { return a.tabG; }
-    static __device__ const double *rs(const BasisDev *bd) { return bd->rs; }
+    static __device__ const double *rsg(const BasisDev *bd) { return bd->rsg; }
 };
 template <> struct BPrec<float> {
     static __device__ const float *prim(const BArgs &a) { return a.prim_f; }
     static __device__ const float *bra(const BArgs &a) { return a.bra_f; }
     static __device__ const float *tabH(const BArgs &a) { return a.tabH_f; }
     static __device__ const float *tabG(const BArgs &a) { return a.tabG_f; }
-    static __device__ const float *rs(const BasisDev *bd) { return bd->rs_f; }
+    static __device__ const float *rsg(const BasisDev *bd) { return bd->rsg_f; }
 };
 
 __device__ inline int tri(int a, int b) { return a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a; }
@@ -260,9 +260,14 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
     const long long M = a.hdr->items;
     const int S = a.hdr->sig_pairs;
     const BasisDev *bd = a.bd;
+    // grid-scaled rows (argument T' = T / h): coefficient m of H times h^m sqrt(h), of g times
+    // h^m h^(3/2), built from the FP64 rows
     for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) {
-        tH[x] = BPrec<R>::tabH(a)[x];
-        tG[x] = BPrec<R>::tabG(a)[x];
+        const int m = x % kBoysStride;
+        double sc = sqrt(kBoysH);
+        for (int e = 0; e < m; ++e) sc *= kBoysH;
+        tH[x] = (R)(a.tabH[x] * sc);
+        tG[x] = (R)(a.tabG[x] * sc * kBoysH);
     }
     unsigned long long kept = 0;
     __shared__ long long blk_at;
@@ -284,7 +289,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
         s = lo;
     }
     const R *prim = BPrec<R>::prim(a);
-    const cptr<R> rs = (cptr<R>)BPrec<R>::rs(bd);
+    const cptr<R> rsg = (cptr<R>)BPrec<R>::rsg(bd);
     const cptr<double> cmu = (cptr<double>)bd->mu;
     const cptr<double> cfa = (cptr<double>)bd->fa;
     const cptr<double> cfb = (cptr<double>)bd->fb;
@@ -358,8 +363,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
         }
         const long long t0 = klo + (m - a.item_off[s]) * kKetsPerItem + (long long)wave * kWave;
         if (t0 >= lim) continue;
-        const long long t = t0 + lane;
-        const bool valid = (t < lim) && (qs * a.pq[t] >= a.tau);
+        const long long tk = t0 + lane;
+        const bool valid = (tk < lim) && (qs * a.pq[tk] >= a.tau);
+        const long long t = valid ? tk : S;   // lanes without a kept quartet read the first pad entry
         const cptr<R> bra = (cptr<R>)(BPrec<R>::bra(a) + (int64_t)s * 8 * G2);
         const int k = a.pk[t], l = a.pl[t];
 
@@ -375,33 +381,70 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
         for (int cb = 0; cb < G; ++cb) {
             R kx[G], ky[G], kz[G], ks[G];
             R Uc[G], Vc[G][3];
+            // buffer loads of the ket table: component base, primitive pair as a scalar
+            // offset, ket as a 32-bit lane offset
+            const unsigned tb = (unsigned)t * (unsigned)sizeof(R);
+            auto ld = [&](int c, int cd) {
+                const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)(prim + (int64_t)c * G2 * a.pcap), (short)0, (int)(G2 * a.pcap * (int64_t)sizeof(R)),
+                    0x00020000);
+                const int so = (int)((int64_t)cd * a.pcap * (int64_t)sizeof(R));
+                if constexpr (sizeof(R) == 8)
+                    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rc, (int)tb, so, 0));
+                else
+                    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)tb, so, 0));
+            };
 #pragma unroll
             for (int d = 0; d < G; ++d) {
                 const int cd = cb * G + d;
-                kx[d] = prim[(int64_t)(0 * G2 + cd) * a.pcap + t];
-                ky[d] = prim[(int64_t)(1 * G2 + cd) * a.pcap + t];
-                kz[d] = valid ? prim[(int64_t)(2 * G2 + cd) * a.pcap + t] : R(1e10);
-                ks[d] = prim[(int64_t)(3 * G2 + cd) * a.pcap + t];
+                kx[d] = ld(0, cd);
+                ky[d] = ld(1, cd);
+                kz[d] = ld(2, cd);
+                ks[d] = ld(3, cd);
                 Uc[d] = R(0);
                 Vc[d][0] = Vc[d][1] = Vc[d][2] = R(0);
             }
 #pragma unroll 1
             for (int ab = 0; ab < G2; ++ab) {
-                cptr<R> b = bra + 8 * ab;
+                // every scalar of this bra primitive in one batch of scalar loads
+                const cptr<R> bp = bra + 8 * ab;
+                const cptr<R> up = rsg + 4 * (ab * G2 + cb * G);
+                R b[4], u[4 * G];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) b[c] = bp[c];
+#pragma unroll
+                for (int c = 0; c < 4 * G; ++c) u[c] = up[c];
+#pragma unroll
+                for (int c = 0; c < 4 * G; ++c) asm volatile("" ::"s"(u[c]));
                 const R px = b[0], py = b[1], pz = b[2], sab = b[3];
                 R U = R(0), V0 = R(0), V1 = R(0), V2 = R(0);
 #pragma unroll
                 for (int d = 0; d < G; ++d) {
-                    const int x = ab * G2 + cb * G + d;
                     const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
                     const R r2 = dx * dx + dy * dy + dz * dz;
+                    const bool near = r2 < u[4 * d];
                     R E, W = R(0);
-                    if (__builtin_amdgcn_ballot_w64(r2 < rs[3 * x + 2])) {
-                        R h, gg;
-                        const R rho = rs[3 * x], srho = rs[3 * x + 1];
-                        boys_hg<R>(r2 * rho, tH, tG, h, gg);
-                        E = srho * h;
-                        if (kGrad) W = (rho * srho) * gg;
+                    if (__builtin_amdgcn_ballot_w64(near)) {
+                        // T' = T / h on the table grid; sqrt(h) H and h^(3/2) g, or their far
+                        // forms T'^(-1/2) and -T'^(-3/2)
+                        const R Ts = r2 * u[4 * d + 1];
+                        const R y = rsqrt_r(Ts);
+                        const R Tc = fmin(Ts, R(kBoysGrid - 4));
+                        const R kd = rint(Tc);
+                        const R dd = Tc - kd;
+                        const unsigned off = __umul24((unsigned)(int)kd, (unsigned)(kBoysStride * sizeof(R)));
+                        const R *ch = (const R *)((const char *)tH + off);
+                        R vh = ch[6];
+#pragma unroll
+                        for (int m = 5; m >= 0; --m) vh = vh * dd + ch[m];
+                        E = u[4 * d + 2] * (near ? vh : y);
+                        if (kGrad) {
+                            const R *cg = (const R *)((const char *)tG + off);
+                            R vg = cg[6];
+#pragma unroll
+                            for (int m = 5; m >= 0; --m) vg = vg * dd + cg[m];
+                            W = u[4 * d + 3] * (near ? vg : -(y * y * y));
+                        }
                     } else {
                         const R y = rsqrt_r(r2);
                         E = y;

@@ -53,28 +53,6 @@ __device__ inline float rsqrt_r(float x) { return rsqrt_fp32(x); }
 // loads (they are never written while a kernel runs).
 template <typename T> using cptr = const __attribute__((address_space(4))) T *;
 
-// h = H(T) = erf(sqrt T)/sqrt T and g = g(T) = -(4/sqrt(pi)) F1(T): Taylor rows of the two
-// tables about the nearest grid point below the switch, T^(-1/2) and -T^(-3/2) above it.
-template <typename R>
-__device__ inline void boys_hg(R T, const R *__restrict__ tH, const R *__restrict__ tG, R &h, R &g)
-{
-    const R y = rsqrt_r(fmax(T, R(1e-30)));
-    const R Tc = fmin(T, R(kTswitch + 0.5));
-    const int k = (int)(Tc * R(kBoysInvH) + R(0.5));
-    const R d = Tc - (R)k * R(kBoysH);
-    const R *c = tH + k * kBoysStride;
-    const R *e = tG + k * kBoysStride;
-    R vh = c[6], vg = e[6];
-#pragma unroll
-    for (int m = 5; m >= 0; --m) {
-        vh = vh * d + c[m];
-        vg = vg * d + e[m];
-    }
-    const bool near = T < R(kTswitch);
-    h = near ? vh : y;
-    g = near ? vg : -(y * y * y);
-}
-
 // Pair index p = i(i+1)/2 + j (i >= j) back to (i, j).
 __device__ inline void pair_of_index(int64_t p, int64_t &i, int64_t &j)
 {
