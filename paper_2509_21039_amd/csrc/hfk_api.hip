@@ -87,6 +87,9 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
     L.nitems = take(sizeof(long long) * PC);
     L.lim = take(sizeof(int) * PC);
     L.item_off = take(sizeof(long long) * (PC + 1));
+    L.ngroups = (L.pcap + kGroupBras - 1) / kGroupBras;
+    L.gcnt = take(sizeof(long long) * (size_t)(L.ngroups + 1));
+    L.goff = take(sizeof(long long) * (size_t)(L.ngroups + 1));
     L.scan_tmp = take(sizeof(long long) * (((PC > (size_t)kNumBuckets ? PC : (size_t)kNumBuckets) + 1023) / 1024 + 1));
     const size_t n2 = (size_t)(n * n);
     L.fpriv = take(sizeof(double) * n2 * (size_t)(L.private_ok ? groups : 1));

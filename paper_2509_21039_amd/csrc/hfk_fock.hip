@@ -5,14 +5,15 @@
 // Work decomposition.  Significant pairs are stored in Q-bucketed order (t = 0 .. S-1),
 // so the kets kept by the screen for a bra s form a prefix t < lim_s (t <= s keeps each
 // unordered quartet once; a lane-level test Q_s Q_t >= tau handles the partial bucket).
-// An item is (bra s, 1024 consecutive kets); items are numbered bra by bra and persistent
-// workgroups fetch blocks of consecutive items, so a workgroup stays on one bra for
-// several items.  Each of its four waves takes 256 kets of an item and runs them as
-// 64-lane chunks, one ket per lane; the bra's primitive data are wave-uniform.  In the
-// hybrid form the wave first packs the kets that pass the screen (ballot + lane count,
-// order kept so loads stay coalesced) into full chunks.  Items are handed out in blocks
-// of kBlockItems from a global counter: the cost per item varies with the bra's
-// surroundings, and static ranges left a long tail of slow workgroups.
+// An item is (bra s, 1024 consecutive kets).  Persistent workgroups fetch blocks of up to
+// kTileItems items of one bra from a global counter (the cost per item varies with the
+// bra's surroundings, and static ranges left a long tail of slow workgroups).  Blocks are
+// numbered ket-block-major within groups of kGroupBras bras, so the workgroups running
+// together read the same kets, which then come from L2.  Each of a workgroup's four waves
+// takes 256 kets of an item and runs them as 64-lane chunks, one ket per lane; the bra's
+// primitive data are wave-uniform.  In the hybrid form the wave first packs the kets that
+// pass the screen (ballot + lane count, order kept so loads stay coalesced) into full
+// chunks.
 //
 // Accumulation (replacing one global FP64 atomic per update):
 //   F_ij += 4 D_kl v   per-lane register, reduced across the wave when the bra changes
@@ -39,6 +40,8 @@ struct FockArgs {
     const double *bra;
     const float *bra_f;
     const long long *item_off;
+    const long long *goff;      // [ngroups + 1] block offsets of the bra groups
+    int64_t ngroups;
     const int *lim;
     const double *dens;
     double *fpriv;
@@ -325,24 +328,31 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     const R *prim = Prec<R>::prim(a);
     unsigned long long kept = 0;
     __shared__ long long blk_at;
-    // blocks of kBlockItems consecutive items, fetched from a global counter until exhausted
+    const long long NB = a.hdr->blocks;
+    (void)M;
+    // blocks (bra group, ket block K, bra) fetched from a global counter until exhausted
     for (;;) {
     if (tid == 0) blk_at = (long long)atomicAdd(a.next_block, 1ULL);
     __syncthreads();
-    const long long m0 = blk_at * kBlockItems;
+    const long long blk = blk_at;
     __syncthreads();
-    if (m0 >= M) break;
-    const long long m1 = m0 + kBlockItems < M ? m0 + kBlockItems : M;
-
-    // bra of the first item: the last s with item_off[s] <= m0
+    if (blk >= NB) break;
     int s;
+    long long m0, m1;
     {
-        int lo = 0, hi = S - 1;
+        // group: the last g with goff[g] <= blk; within it K-major over the group's bras
+        int64_t lo = 0, hi = a.ngroups - 1;
         while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.item_off[mid] <= m0) lo = mid; else hi = mid - 1;
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (a.goff[mid] <= blk) lo = mid; else hi = mid - 1;
         }
-        s = lo;
+        const long long local = blk - a.goff[lo];
+        s = (int)(lo * kGroupBras + local % kGroupBras);
+        if (s >= S) continue;
+        const long long i1 = a.item_off[s + 1];
+        m0 = a.item_off[s] + (local / kGroupBras) * kTileItems;
+        if (m0 >= i1) continue;   // this bra has fewer blocks than the group's longest
+        m1 = m0 + kTileItems < i1 ? m0 + kTileItems : i1;
     }
     int cur = -1, bi = 0, bj = 0;
     double qs = 0.0, ds = 0.0, jb = 0.0;
@@ -606,6 +616,8 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.bra_f = (const float *)(ws + L.bra_f);
     a.item_off = (const long long *)(ws + L.item_off);
     a.lim = (const int *)(ws + L.lim);
+    a.goff = (const long long *)(ws + L.goff);
+    a.ngroups = L.ngroups;
     a.dens = dens;
     a.fpriv = (double *)(ws + L.fpriv);
     a.jcol = (double *)(ws + L.jcol);

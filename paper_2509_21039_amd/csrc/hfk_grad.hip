@@ -11,9 +11,9 @@
 //   d(ab|cd)/dD = -(dA + dB + dC)            (translation invariance)
 // Beyond the switch E = 1/r and W = -1/r^3 exactly; below it both come from Taylor tables.
 //
-// Work decomposition as in the forward kernel (items of 1024 kets of one bra in blocks
-// fetched from a global counter, 256 kets per wave packed into full 64-lane chunks after
-// the screen).  Bra-atom gradients accumulate in
+// Work decomposition as in the forward kernel (items of 1024 kets of one bra, blocks of
+// items fetched from a global counter in the same bra-group order, 256 kets per wave packed
+// into full 64-lane chunks after the screen).  Bra-atom gradients accumulate in
 // registers and are reduced across the wave when the bra changes; ket-atom gradients go to
 // an LDS copy of the n x 3 gradient; each workgroup writes its copy out once.
 #include "hfk_device.hpp"
@@ -36,6 +36,8 @@ struct GradArgs {
     const double *bra;
     const float *bra_f;
     const long long *item_off;
+    const long long *goff;      // [ngroups + 1] block offsets of the bra groups
+    int64_t ngroups;
     const int *lim;
     const double *dens;
     const double *xyz;
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
     R *tH = (R *)(smem + 3 * n);
     R *tG = tH + kBoysGrid * kBoysStride;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    const int gid = blockIdx.x, ng = gridDim.x;
+    const int gid = blockIdx.x;
     const long long M = a.hdr->items;
     const int S = a.hdr->sig_pairs;
     const BasisDev *bd = a.bd;
@@ -94,23 +96,32 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
     __syncthreads();
 
     double eacc = 0.0;
-    // blocks of kBlockItems consecutive items, fetched from a global counter until exhausted
+    // blocks (bra group, ket block K, bra) fetched from a global counter until exhausted
+    const long long NB = a.hdr->blocks;
+    (void)M;
     for (;;) {
     __syncthreads();
     if (tid == 0) blk_at = (long long)atomicAdd(a.next_block, 1ULL);
     __syncthreads();
-    const long long m0 = blk_at * kBlockItems;
-    if (m0 >= M) break;
-    const long long m1 = m0 + kBlockItems < M ? m0 + kBlockItems : M;
+    const long long blk = blk_at;
+    if (blk >= NB) break;
     {
         int s;
+        long long m0, m1;
         {
-            int lo = 0, hi = S - 1;
+            // group: the last g with goff[g] <= blk; within it K-major over the group's bras
+            int64_t lo = 0, hi = a.ngroups - 1;
             while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (a.item_off[mid] <= m0) lo = mid; else hi = mid - 1;
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (a.goff[mid] <= blk) lo = mid; else hi = mid - 1;
             }
-            s = lo;
+            const long long local = blk - a.goff[lo];
+            s = (int)(lo * kGroupBras + local % kGroupBras);
+            if (s >= S) continue;
+            const long long i1 = a.item_off[s + 1];
+            m0 = a.item_off[s] + (local / kGroupBras) * kTileItems;
+            if (m0 >= i1) continue;
+            m1 = m0 + kTileItems < i1 ? m0 + kTileItems : i1;
         }
         const R *prim = GPrec<R>::prim(a);
         const cptr<R> rsg = (cptr<R>)GPrec<R>::rsg(bd);
@@ -374,6 +385,8 @@ hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *
     a.bra_f = (const float *)(ws + L.bra_f);
     a.item_off = (const long long *)(ws + L.item_off);
     a.lim = (const int *)(ws + L.lim);
+    a.goff = (const long long *)(ws + L.goff);
+    a.ngroups = L.ngroups;
     a.dens = dens;
     a.xyz = xyz;
     a.gpriv = (double *)(ws + L.grad);

@@ -45,6 +45,12 @@ constexpr int kSubChunks = 4;
 constexpr int kWaveKets = kWave * kSubChunks;
 constexpr int kItemKets = kWavesPerGroup * kWaveKets;
 constexpr int kBlockItems = 16;  // items per dynamically fetched block of the quartet kernels
+// Single-molecule blocks: kTileItems items of one bra.  Bras are taken kGroupBras at a time
+// and their blocks are numbered ket-block-major (block K of every bra of the group, then
+// block K+1), so the workgroups running at the same moment read the same few thousand
+// kets and the ket table is served from L2 instead of streaming past it.
+constexpr int kTileItems = 8;
+constexpr int kGroupBras = 1024;
 
 // Device-side counters written by the build and read back by hfk_read_stats.
 struct DevHeader {
@@ -63,6 +69,7 @@ struct DevHeader {
     int variant;
     int pad1;
     unsigned long long next_block;  // work counter of the quartet kernels (blocks of items)
+    long long blocks;               // blocks of the single-molecule kernels (empty ones included)
 };
 
 // Basis constants shared by every pair, computed on the host from exps/coefs and passed
@@ -108,6 +115,8 @@ struct Layout {
     size_t bra, bra_f;                     // [pcap][g2][8] Px Py Pz S -2Px -2Py -2Pz |P|^2 (wave-uniform bra data)
     size_t boys_g, boys_g_f;               // Taylor table of g(T) = -(4/sqrt(pi)) F1(T) (gradient)
     size_t nitems, lim, item_off, scan_tmp;
+    size_t gcnt, goff;                     // per bra group: blocks, and their exclusive prefix
+    int64_t ngroups;                       // bra groups of kGroupBras
     size_t fpriv;                          // [groups][n*n] or [n*n]
     size_t jcol;                           // [jcopies][pcap] ket-side Coulomb vectors
     int jcopies;                           // copies of the ket vector (one per workgroup while they fit)

@@ -466,6 +466,22 @@ __global__ void k_fill_i64(long long *__restrict__ p, int64_t m)
     if (i < m) p[i] = 0;
 }
 
+// Blocks of every bra group: kGroupBras x the largest block count of its bras (bras with
+// fewer blocks leave empty slots, skipped by the kernels).
+__global__ void k_group_blocks(const DevHeader *__restrict__ hdr, const long long *__restrict__ nitems,
+                               int64_t ngroups, long long *__restrict__ gcnt)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngroups) return;
+    const int64_t S = hdr->sig_pairs;
+    long long nb = 0;
+    for (int64_t s = g * kGroupBras; s < (g + 1) * kGroupBras && s < S; ++s) {
+        const long long b = (nitems[s] + kTileItems - 1) / kTileItems;
+        nb = b > nb ? b : nb;
+    }
+    gcnt[g] = nb * kGroupBras;
+}
+
 hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
                         double tau, hipStream_t st)
 {
@@ -495,8 +511,13 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
     hipLaunchKernelGGL(k_limits, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, tau,
                        (const double *)(ws + L.pq), off, (long long *)(ws + L.nitems), (int *)(ws + L.lim),
                        L.pcap);
-    return launch_scan((const long long *)(ws + L.nitems), L.pcap, (long long *)(ws + L.item_off),
-                       (long long *)(ws + L.scan_tmp), &hdr->items, st);
+    e = launch_scan((const long long *)(ws + L.nitems), L.pcap, (long long *)(ws + L.item_off),
+                    (long long *)(ws + L.scan_tmp), &hdr->items, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_group_blocks, dim3((unsigned)((L.ngroups + 255) / 256)), dim3(256), 0, st, hdr,
+                       (const long long *)(ws + L.nitems), L.ngroups, (long long *)(ws + L.gcnt));
+    return launch_scan((const long long *)(ws + L.gcnt), L.ngroups, (long long *)(ws + L.goff),
+                       (long long *)(ws + L.scan_tmp), &hdr->blocks, st);
 }
 
 }  // namespace hfk

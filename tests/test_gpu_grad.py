@@ -115,7 +115,9 @@ def test_gradcheck_small(torch_dev):
         dd = 0.5 * (d + d.transpose(0, 1))
         return hfk.FockEnergy.apply(x, dd.contiguous(), s.exps, s.coefs, 0.0, "fp64")[1]
 
-    assert torch.autograd.gradcheck(f, (xyz, D), eps=1e-6, atol=1e-7, rtol=1e-6)
+    # work is handed out dynamically, so per-workgroup partial sums, and with them the last
+    # bits of the FP64 result, differ between calls: allow that much nondeterminism
+    assert torch.autograd.gradcheck(f, (xyz, D), eps=1e-6, atol=1e-7, rtol=1e-6, nondet_tol=1e-12)
 
 
 @pytest.mark.parametrize("exps,coefs", [([0.8], [1.0]), ([3.0, 0.45], [0.4, 0.7]),
