@@ -52,11 +52,14 @@ def measured_traffic(stats):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    cfg = t.get("config", {})
-    if (t.get("source_sha256") != kernel_source_hash() or cfg.get("strategy") != stats["strategy"]
-            or cfg.get("variant") != stats["variant"] or cfg.get("groups") != stats["groups"]):
+    if t.get("source_sha256") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch")
+    for e in t.get("entries", []):
+        cfg = e.get("config", {})
+        if (cfg.get("strategy") == stats["strategy"] and cfg.get("variant") == stats["variant"]
+                and cfg.get("groups") == stats["groups"]):
+            return e.get("bytes_per_launch")
+    return None
 
 
 def log(msg):
@@ -180,8 +183,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed / fwd+grad / batched comparisons")
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="one he512 FP64 build (default configuration) and one plain 512 MiB device copy, for "
-                         "hardware-counter runs; prints the copy size")
+                    help="one he512 FP64 build (hybrid kernel, default workgroups, --probe-strategy) and one plain "
+                         "512 MiB device copy, for hardware-counter runs; prints the configuration")
+    ap.add_argument("--probe-strategy", type=int, default=2, choices=[1, 2],
+                    help="accumulation strategy of the traffic probe (1 private copies, 2 atomics)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the Fock build here is single-GPU (the multi-GPU "
@@ -198,13 +203,12 @@ def main():
     s = config_system("he512_fp64")
     g = len(s.exps)
     if args.traffic_probe:
-        # the configuration the timed run uses: tune, then one build; then a plain copy
+        # one build in a fixed configuration (hybrid kernel, default workgroups), then a copy
         ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, g, "fp64"), dev)
         xyz_t = torch.tensor(s.xyz, device=dev)
         D_t = torch.tensor(s.dens, device=dev)
-        hfk.tune(xyz_t, D_t, s.exps, s.coefs, s.tau, precision="fp64")
-        torch.cuda.synchronize()
-        hfk.fock(xyz_t, D_t, s.exps, s.coefs, s.tau, workspace=ws)
+        hfk.set_config(1, 0)
+        hfk.fock(xyz_t, D_t, s.exps, s.coefs, s.tau, strategy=args.probe_strategy, workspace=ws)
         torch.cuda.synchronize()
         st = hfk.read_stats(ws)
         nbytes = 512 << 20
