@@ -88,16 +88,24 @@ def time_builds(hfk, torch, s, precision, steps, warmup, ws):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     e0.record(stream)
-    for _ in range(steps):
+    marks[0].record(stream)
+    for k in range(steps):
         hfk.fock(xyz, D, s.exps, s.coefs, s.tau, precision=precision, workspace=ws, out=(F, E2))
+        marks[k + 1].record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
     hfk.profile_enable(False)
     kern_ms, launches = hfk.profile_read()
     total_ms = e0.elapsed_time(e1)
+    per = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(steps))
+
+    def pct(q):
+        return per[min(len(per) - 1, int(round(q * (len(per) - 1))))]
+
     return {"ms_per_step": total_ms / steps, "kernel_ms": kern_ms / max(launches, 1), "stats": stats,
-            "e2": float(E2.item()), "F": F}
+            "e2": float(E2.item()), "F": F, "step_ms": {"median": pct(0.5), "p10": pct(0.1), "p90": pct(0.9)}}
 
 
 def time_grad(hfk, torch, s, steps, warmup):
@@ -178,7 +186,7 @@ def cpu_baseline(s, target_s=12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed / fwd+grad / batched comparisons")
@@ -251,6 +259,8 @@ def main():
                    "kernel_variant": r["stats"]["variant"], "accumulation": r["stats"]["strategy"],
                    "workgroups": r["stats"]["groups"], "parallelism": "single GPU"},
         "pct_fp64_valu_peak_nominal": 100.0 * achieved / FP64_VALU_PEAK_TFLOPS,
+        "step_ms": r["step_ms"],
+        "primitive_quartets_per_s": q * g ** 4 / (r["ms_per_step"] / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": measured_traffic(r["stats"]),
                      "kernel": "k_fock<3,double>", "kernel_ms": r["kernel_ms"],
