@@ -106,23 +106,31 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss,
                     double *fock, double *e2,
                     void *workspace, size_t workspace_bytes, void *stream);
 
-/* Backward of E2 (the paper has no gradient; this is the derivative of the energy the
- * forward defines, with the screening decisions held fixed):
- *   d_xyz  = g_e2 * dE2/dR,  dE2/dR_A = sum_unique Gamma_ijkl d(ij|kl)/dR_A,
- *            Gamma = deg (4 D_ij D_kl - D_ik D_jl - D_il D_jk)
- *   d_dens = g_e2 * G  (dE2/dD = G for the symmetric-bilinear energy), from fock_in
+/* Backward of the forward outputs (G, E2) for upstream (g_fock, g_e2).  The paper has no
+ * gradient; this is the derivative of what the forward defines, with the screening
+ * decisions held fixed.  With W = (g_fock + g_fock^T)/2 (0 if g_fock is NULL) and
+ * X = W + (g_e2 / 2) D:
+ *   d_xyz  = sum_unique B_ijkl d(ij|kl)/dR,
+ *            B = deg (4 (X_ij D_kl + D_ij X_kl) - (X_ik D_jl + D_ik X_jl) - (X_il D_jk + D_il X_jk)),
+ *            which for g_fock = NULL is g_e2 * dE2/dR with Gamma = deg (4 D_ij D_kl - D_ik D_jl
+ *            - D_il D_jk)
+ *   d_dens = g_e2 G + G(W): dE2/dD = G (E2 is a symmetric bilinear form in D) and the map
+ *            D -> G is linear and self-adjoint, so the pull-back of W is a Fock build with W
+ *            as the density (run here when g_fock is given)
  * Inputs as hfk_fock plus
  *   g_e2     [1] upstream dL/dE2 (device)
+ *   g_fock   [n*n] upstream dL/dG (device) or NULL
  *   fock_in  [n*n] G from the forward call on the same inputs; may be NULL when d_dens is
  * Outputs
  *   d_xyz    [n*3] (overwritten)
  *   d_dens   [n*n] or NULL (not computed)
  *   e2_out   [1] or NULL: E2 recomputed as sum_unique Gamma (ij|kl)
- * Errors as hfk_fock; HFK_EINVAL if d_dens is given without fock_in. */
+ * The workspace must be sized with with_grad != 0.  Errors as hfk_fock; HFK_EINVAL if
+ * d_dens is given without fock_in. */
 hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss,
                          const double *exps_host, const double *coefs_host,
                          const double *dens, double tau, int32_t precision,
-                         const double *g_e2, const double *fock_in,
+                         const double *g_e2, const double *g_fock, const double *fock_in,
                          double *d_xyz, double *d_dens, double *e2_out,
                          void *workspace, size_t workspace_bytes, void *stream);
 

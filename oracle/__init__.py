@@ -71,6 +71,9 @@ def _load():
         lib.hfo_fock_bruteforce.restype = ctypes.c_int
         lib.hfo_fock_bruteforce.argtypes = [ctypes.c_int64, _dp, ctypes.c_int, _dp, _dp, _dp,
                                             ctypes.c_double, _dp, _dp]
+        lib.hfo_grad_pair.restype = ctypes.c_int
+        lib.hfo_grad_pair.argtypes = [ctypes.c_int64, _dp, ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_double,
+                                      _dp, ctypes.c_int, _dp]
         lib.hfo_grad.restype = ctypes.c_int
         lib.hfo_grad.argtypes = [ctypes.c_int64, _dp, ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
                                  _dp, ctypes.c_int, _dp, _dp, _i64p]
@@ -173,3 +176,18 @@ def grad(xyz, dens, exps, coefs, tau, Q=None, nthreads: int = 0):
     if rc != 0:
         raise MemoryError("oracle grad: out of memory")
     return g, e2.value, ns.value
+
+
+def grad_pair(xyz, dens, xdens, exps, coefs, tau, Q=None, nthreads: int = 0):
+    """sum_unique B(X, D) d(ij|kl)/dR (n, 3): the gradient of sum_ij W_ij G_ij for X = W, of E2
+    for X = D / 2."""
+    xyz, px = _c(xyz); d, pd = _c(dens); x, pxd = _c(xdens); e, pe = _c(exps); c, pc = _c(coefs)
+    n = xyz.shape[0]
+    g = np.zeros((n, 3))
+    qp = None
+    if Q is not None:
+        Q, qp = _c(Q)
+    rc = _load().hfo_grad_pair(n, px, len(e), pe, pc, pd, pxd, float(tau), qp, int(nthreads), g.ctypes.data_as(_dp))
+    if rc != 0:
+        raise MemoryError("oracle grad_pair: out of memory")
+    return g

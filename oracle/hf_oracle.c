@@ -33,7 +33,9 @@
  * The nuclear gradient (hfo_grad) differentiates E2 = sum_unique Gamma_ijkl (ij|kl),
  * Gamma = deg (4 D_ij D_kl - D_ik D_jl - D_il D_jk), with the screening decisions held
  * fixed; the derivative of one primitive integral uses F0 and F1 (dF0/dt = -F1).  The
- * paper has no gradient; this is the derivative of the functional above.
+ * paper has no gradient; this is the derivative of the functional above.  hfo_grad_pair is
+ * the same contraction for the pairing sum_ij W_ij G_ij with a fixed W (the derivative
+ * through the G output), with Gamma replaced by its polarisation B(X, D).
  *
  * Readings where the paper is silent: normalised primitives with the coefficients used as
  * given (no contraction renormalisation); contracted Schwarz bounds in FP64 with a
@@ -420,6 +422,74 @@ int hfo_grad(int64_t n, const double *xyz, int g, const double *exps, const doub
     if (e2) *e2 = energy;
     if (nsurv) *nsurv = count;
     return 0;
+}
+
+/* Gradient of the pairing L = sum_ij W_ij G_ij(R) of a fixed matrix W with the forward's G,
+ * the screening decisions held fixed (used for the derivative through the G output).  In
+ * unique-quartet form L = sum_unique B (ij|kl) with B the polarisation of 2 Gamma in which one
+ * density is replaced by X:
+ *   B = deg (4 (X_ij D_kl + D_ij X_kl) - (X_ik D_jl + D_ik X_jl) - (X_il D_jk + D_il X_jk)),
+ * so X = W gives dL/dR, X = D / 2 gives dE2/dR, and X = W + (g/2) D gives both at once. */
+int hfo_grad_pair(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                  const double *dens, const double *xdens, double tau, const double *Qin, int nthreads,
+                  double *grad)
+{
+    const int64_t npair = n * (n + 1) / 2;
+    double *Q = (double *)Qin;
+    int ownQ = 0;
+    if (!Q) {
+        Q = (double *)malloc(sizeof(double) * (size_t)npair);
+        if (!Q) return -1;
+        hfo_schwarz(n, xyz, g, exps, coefs, nthreads, Q);
+        ownQ = 1;
+    }
+    int64_t *pi = (int64_t *)malloc(sizeof(int64_t) * (size_t)npair * 2);
+    if (!pi) { if (ownQ) free(Q); return -1; }
+    for (int64_t i = 0, p = 0; i < n; ++i)
+        for (int64_t j = 0; j <= i; ++j, ++p) { pi[2 * p] = i; pi[2 * p + 1] = j; }
+    double w[16];
+    prim_weights(g, exps, coefs, w);
+    memset(grad, 0, sizeof(double) * (size_t)(3 * n));
+    int failed = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+    {
+        double *gp = (double *)calloc((size_t)(3 * n), sizeof(double));
+        if (!gp) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            failed = 1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+            for (int64_t ij = 0; ij < npair; ++ij) {
+                const int64_t i = pi[2 * ij], j = pi[2 * ij + 1];
+                for (int64_t kl = 0; kl <= ij; ++kl) {
+                    if (Q[ij] * Q[kl] < tau) continue;
+                    const int64_t k = pi[2 * kl], l = pi[2 * kl + 1];
+                    const double *X = xdens, *D = dens;
+                    const double b = quartet_deg(i, j, k, l, ij, kl) *
+                                     (4.0 * (X[i * n + j] * D[k * n + l] + D[i * n + j] * X[k * n + l]) -
+                                      (X[i * n + k] * D[j * n + l] + D[i * n + k] * X[j * n + l]) -
+                                      (X[i * n + l] * D[j * n + k] + D[i * n + l] * X[j * n + k]));
+                    const double *A = xyz + 3 * i, *B = xyz + 3 * j, *C = xyz + 3 * k, *E = xyz + 3 * l;
+                    eri_grad(A, B, C, E, g, exps, w, b, gp + 3 * i, gp + 3 * j, gp + 3 * k, gp + 3 * l);
+                }
+            }
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+            for (int64_t x = 0; x < 3 * n; ++x) grad[x] += gp[x];
+            free(gp);
+        }
+    }
+    free(pi);
+    if (ownQ) free(Q);
+    return failed ? -1 : 0;
 }
 
 int hfo_num_threads(void)

@@ -55,7 +55,7 @@ _SIGNATURES = {
     "hfk_fock": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
                  ctypes.c_int32, _vp, _vp, _vp, _sz, _vp],
     "hfk_fock_grad": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
-                      _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
+                      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
     "hfk_batched_workspace_bytes": [ctypes.c_int64, _i64p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.POINTER(_sz)],
     "hfk_fock_batched": [ctypes.c_int64, _i64p, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double,
@@ -178,8 +178,9 @@ def read_stats(workspace, stream=None) -> dict:
 
 
 def fock_grad(xyz, dens, exps, coefs, tau, precision="fp64", g_e2=None, fock_in=None, want_dens=True,
-              workspace=None, stream=None):
-    """(d_xyz, d_dens or None, E2) for upstream g_e2 (device scalar tensor; 1 if None)."""
+              workspace=None, stream=None, g_fock=None):
+    """(d_xyz, d_dens or None, E2) for upstream g_e2 (device scalar tensor; 1 if None) and
+    g_fock (device [n, n] tensor dL/dG, or None)."""
     torch = _torch()
     n = xyz.shape[0]
     _dev_f64(xyz, "xyz", (n, 3))
@@ -192,6 +193,8 @@ def fock_grad(xyz, dens, exps, coefs, tau, precision="fp64", g_e2=None, fock_in=
     _dev_f64(g_e2, "g_e2")
     if workspace is None:
         workspace = new_workspace(workspace_bytes(n, len(e), prec, True), xyz.device)
+    if g_fock is not None:
+        _dev_f64(g_fock, "g_fock", (n, n))
     d_xyz = torch.empty((n, 3), dtype=torch.float64, device=xyz.device)
     d_dens = None
     if want_dens:
@@ -201,7 +204,8 @@ def fock_grad(xyz, dens, exps, coefs, tau, precision="fp64", g_e2=None, fock_in=
         d_dens = torch.empty((n, n), dtype=torch.float64, device=xyz.device)
     E2 = torch.empty((1,), dtype=torch.float64, device=xyz.device)
     _check(lib().hfk_fock_grad(n, xyz.data_ptr(), len(e), _dptr(e), _dptr(c), dens.data_ptr(), float(tau), prec,
-                               g_e2.data_ptr(), fock_in.data_ptr() if fock_in is not None else None,
+                               g_e2.data_ptr(), g_fock.data_ptr() if g_fock is not None else None,
+                               fock_in.data_ptr() if fock_in is not None else None,
                                d_xyz.data_ptr(), d_dens.data_ptr() if d_dens is not None else None,
                                E2.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream_handle(stream)))
     return d_xyz, d_dens, E2
@@ -213,9 +217,9 @@ def _autograd():
     class FockEnergy(torch.autograd.Function):
         """E2 (and G) as a differentiable function of positions and density.
 
-        forward(xyz, dens, exps, coefs, tau, precision) -> (G, E2); backward gives
-        dL/dxyz = gE2 * dE2/dR from the library's gradient kernel and dL/ddens = gE2 * G.
-        A gradient flowing into G itself is not supported (raises)."""
+        forward(xyz, dens, exps, coefs, tau, precision) -> (G, E2); backward hands the
+        upstream (gG, gE2) to the library's gradient call: dL/dxyz from the two-density
+        contraction, dL/ddens = gE2 * G + G(sym(gG))."""
 
         @staticmethod
         def forward(ctx, xyz, dens, exps, coefs, tau, precision="fp64"):
@@ -229,14 +233,16 @@ def _autograd():
 
         @staticmethod
         def backward(ctx, gG, gE2):
-            if gG is not None:
-                raise NotImplementedError("gradient through G is not implemented; differentiate E2")
             xyz, dens, G = ctx.saved_tensors
-            if gE2 is None:
+            if gE2 is None and gG is None:
                 return None, None, None, None, None, None
+            if gE2 is None:
+                gE2 = torch.zeros((1,), dtype=torch.float64, device=xyz.device)
             e, c = ctx.basis
-            d_xyz, d_dens, _ = fock_grad(xyz, dens, e, c, ctx.tau, ctx.precision, g_e2=gE2.contiguous(),
-                                         fock_in=G, want_dens=ctx.needs_input_grad[1])
+            d_xyz, d_dens, _ = fock_grad(xyz, dens, e, c, ctx.tau, ctx.precision,
+                                         g_e2=gE2.reshape(1).to(torch.float64).contiguous(), fock_in=G,
+                                         want_dens=ctx.needs_input_grad[1],
+                                         g_fock=None if gG is None else gG.to(torch.float64).contiguous())
             return (d_xyz if ctx.needs_input_grad[0] else None, d_dens, None, None, None, None)
 
     return FockEnergy

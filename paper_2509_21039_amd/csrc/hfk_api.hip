@@ -101,6 +101,8 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
     L.fsum = take(sizeof(double) * n2);
     L.e2part = take(sizeof(double) * ((n2 + 255) / 256 + 256));
     L.grad = with_grad ? take(sizeof(double) * 3 * (size_t)n * (size_t)groups + sizeof(double) * 4096) : 0;
+    L.xw = with_grad ? take(sizeof(double) * 2 * n2) : 0;
+    L.e2tmp = take(sizeof(double));
     L.total = o;
     return L;
 }
@@ -348,8 +350,8 @@ hfk_status hfk_read_stats(const void *workspace, void *stream, hfk_stats *out)
 
 hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
                          const double *coefs_host, const double *dens, double tau, int32_t precision,
-                         const double *g_e2, const double *fock_in, double *d_xyz, double *d_dens,
-                         double *e2_out, void *workspace, size_t workspace_bytes, void *stream)
+                         const double *g_e2, const double *g_fock, const double *fock_in, double *d_xyz,
+                         double *d_dens, double *e2_out, void *workspace, size_t workspace_bytes, void *stream)
 {
     g_err[0] = 0;
     hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision);
@@ -377,8 +379,31 @@ hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss, cons
     if (e != hipSuccess) return hip_fail(e, "setup launch");
     e = launch_pairs(L, b, ws, xyz, dens, tau, st);
     if (e != hipSuccess) return hip_fail(e, "pair launch");
-    e = launch_grad(L, b, ws, xyz, dens, tau, precision, g_e2, fock_in, d_xyz, d_dens, e2_out, st);
+    const int64_t n2 = natoms * natoms;
+    double *xw = (double *)(ws + L.xw);
+    if (g_fock) {
+        e = launch_make_xw(natoms, dens, g_fock, g_e2, xw, st);
+        if (e != hipSuccess) return hip_fail(e, "W/X launch");
+    }
+    e = launch_grad(L, b, ws, xyz, dens, tau, precision, g_e2, g_fock ? xw + n2 : nullptr, fock_in, d_xyz,
+                    g_fock ? nullptr : d_dens, e2_out, st);
     if (e != hipSuccess) return hip_fail(e, "gradient launch");
+    if (g_fock && d_dens) {
+        // d_dens = G(W) + g_e2 G: a Fock build with W as the density (the pair tables are
+        // rebuilt around W; the screen depends on the geometry only), then the axpy
+        e = launch_pairs(L, b, ws, xyz, xw, tau, st);
+        if (e != hipSuccess) return hip_fail(e, "pair launch (W)");
+        const TunedConfig cfg = pick_config(HFK_STRATEGY_AUTO, precision, natoms);
+        int strat = cfg.strategy;
+        if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
+        Layout LF = L;
+        const int fit = fock_resident_groups(ngauss, precision, cfg.variant, natoms);
+        LF.groups = cus * (fit > 0 && cfg.gpc > fit ? fit : cfg.gpc);
+        e = launch_fock(LF, b, ws, xw, tau, precision, strat, cfg.variant, d_dens, (double *)(ws + L.e2tmp), st);
+        if (e != hipSuccess) return hip_fail(e, "Fock launch (W)");
+        e = launch_axpy_dev(n2, g_e2, fock_in, d_dens, st);
+        if (e != hipSuccess) return hip_fail(e, "axpy launch");
+    }
     e = launch_header_info(ws + L.hdr, 0, L.groups, precision, -1, st);
     if (e != hipSuccess) return hip_fail(e, "header launch");
     return HFK_OK;

@@ -40,6 +40,7 @@ struct GradArgs {
     int64_t ngroups;
     const int *lim;
     const double *dens;
+    const double *xdens;    // X of the two-density contraction, or NULL (Gamma from D alone)
     const double *xyz;
     double *gpriv;      // [groups][n*3]
     double *epart;      // [groups]
@@ -282,7 +283,16 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                     if (k == l) deg *= 0.5;
                     if (t == s) deg *= 0.5;
                     const double *Di = a.dens + (int64_t)bi * n, *Dj = a.dens + (int64_t)bj * n;
-                    const double gam = deg * (4.0 * ds * a.pd[t] - Di[k] * Dj[l] - Di[l] * Dj[k]);
+                    const double dt = a.pd[t];
+                    const double gE = deg * (4.0 * ds * dt - Di[k] * Dj[l] - Di[l] * Dj[k]);
+                    double gam = gE;
+                    if (a.xdens) {
+                        // B(X, D): the polarisation of 2 Gamma with one density replaced by X
+                        const double *Xi = a.xdens + (int64_t)bi * n, *Xj = a.xdens + (int64_t)bj * n;
+                        const double xs = Xi[bj], xt = a.xdens[(int64_t)k * n + l];
+                        gam = deg * (4.0 * (xs * dt + ds * xt) - (Xi[k] * Dj[l] + Di[k] * Xj[l]) -
+                                     (Xi[l] * Dj[k] + Di[l] * Xj[k]));
+                    }
                     const double AB[3] = {ABx, ABy, ABz};
                     double GA[3], GB[3], GC[3];
 #pragma unroll
@@ -295,7 +305,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                         atomicAdd(&lg[3 * k + c], GC[c]);
                         atomicAdd(&lg[3 * l + c], -(GA[c] + GB[c] + GC[c]));
                     }
-                    eacc += gam * (double)eri;
+                    eacc += gE * (double)eri;
                 }
             }
             __builtin_amdgcn_wave_barrier();
@@ -317,6 +327,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
 }
 
 // d_xyz = g_e2 * sum over workgroups; E2 = sum of partials (fixed order); d_dens = g_e2 * G.
+// d_xyz = scale * sum of the workgroup partials; scale = g_e2[0], or 1 when g_e2 is NULL
+// (the two-density contraction already carries it).
 __global__ __launch_bounds__(256) void k_grad_reduce(const double *__restrict__ gpriv, int groups, int64_t m,
                                                      const double *__restrict__ g_e2, double *__restrict__ d_xyz)
 {
@@ -324,7 +336,41 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double *__restrict__ 
     if (x >= m) return;
     double s = 0.0;
     for (int gph = 0; gph < groups; ++gph) s += gpriv[(int64_t)gph * m + x];
-    d_xyz[x] = g_e2[0] * s;
+    d_xyz[x] = g_e2 ? g_e2[0] * s : s;
+}
+
+__global__ __launch_bounds__(256) void k_make_xw(int64_t n, const double *__restrict__ dens,
+                                                 const double *__restrict__ gf, const double *__restrict__ g_e2,
+                                                 double *__restrict__ w, double *__restrict__ x)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n * n) return;
+    const int64_t i = p / n, j = p % n;
+    const double wv = 0.5 * (gf[p] + gf[j * n + i]);
+    w[p] = wv;
+    x[p] = wv + 0.5 * g_e2[0] * dens[p];
+}
+
+hipError_t launch_make_xw(int64_t n, const double *dens, const double *g_fock, const double *g_e2, double *xw,
+                          hipStream_t st)
+{
+    const int64_t n2 = n * n;
+    hipLaunchKernelGGL(k_make_xw, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, n, dens, g_fock, g_e2, xw,
+                       xw + n2);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_axpy_dev(int64_t m, const double *__restrict__ g_e2,
+                                                  const double *__restrict__ x, double *__restrict__ y)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m) y[p] += g_e2[0] * x[p];
+}
+
+hipError_t launch_axpy_dev(int64_t m, const double *g_e2, const double *x, double *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpy_dev, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, g_e2, x, y);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_grad_energy(const double *__restrict__ epart, int groups,
@@ -365,8 +411,8 @@ static hipError_t launch_grad_t(const GradArgs &a, int groups, size_t smem, hipS
 }
 
 hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
-                       double tau, int prec, const double *g_e2, const double *fock_in, double *d_xyz,
-                       double *d_dens, double *e2_out, hipStream_t st)
+                       double tau, int prec, const double *g_e2, const double *xdens, const double *fock_in,
+                       double *d_xyz, double *d_dens, double *e2_out, hipStream_t st)
 {
     GradArgs a;
     a.hdr = (const DevHeader *)(ws + L.hdr);
@@ -388,6 +434,7 @@ hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *
     a.goff = (const long long *)(ws + L.goff);
     a.ngroups = L.ngroups;
     a.dens = dens;
+    a.xdens = xdens;
     a.xyz = xyz;
     a.gpriv = (double *)(ws + L.grad);
     a.epart = (double *)(ws + L.grad) + (size_t)L.groups * 3 * L.n;
@@ -415,7 +462,7 @@ hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *
     if (err != hipSuccess) return err;
     const int64_t m = 3 * L.n;
     hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, a.gpriv, L.groups, m,
-                       g_e2, d_xyz);
+                       xdens ? nullptr : g_e2, d_xyz);
     if (e2_out) hipLaunchKernelGGL(k_grad_energy, dim3(1), dim3(256), 0, st, a.epart, L.groups, e2_out);
     if (d_dens) {
         const int64_t n2 = L.n * L.n;

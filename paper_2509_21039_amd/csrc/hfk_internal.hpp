@@ -122,6 +122,8 @@ struct Layout {
     int jcopies;                           // copies of the ket vector (one per workgroup while they fit)
     size_t fsum;                           // [n*n]
     size_t e2part;                         // partial energies
+    size_t xw;                             // gradient with dL/dG: W and X, [2][n*n]
+    size_t e2tmp;                          // one double of scratch
     size_t grad;                           // [groups][n*3] gradient accumulators
     size_t total;
 };
@@ -171,9 +173,17 @@ hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision
                               hipStream_t st);
 hipError_t launch_scan(const long long *in, int64_t m, long long *out, long long *tmp, long long *total,
                        hipStream_t st);
+// Gradient kernel and its reductions.  xdens: X of the two-density contraction (see
+// hfk_fock_grad), or NULL for g_e2 * dE2/dR.  d_dens here is g_e2 * fock_in only; the
+// caller adds G(W) for an upstream dL/dG.
 hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
-                       double tau, int prec, const double *g_e2, const double *fock_in, double *d_xyz,
-                       double *d_dens, double *e2_out, hipStream_t st);
+                       double tau, int prec, const double *g_e2, const double *xdens, const double *fock_in,
+                       double *d_xyz, double *d_dens, double *e2_out, hipStream_t st);
+// W = (gF + gF^T)/2 and X = W + (g_e2/2) D into xw[0 .. n*n) and xw[n*n .. 2 n*n).
+hipError_t launch_make_xw(int64_t n, const double *dens, const double *g_fock, const double *g_e2, double *xw,
+                          hipStream_t st);
+// y += g_e2 * x over m values.
+hipError_t launch_axpy_dev(int64_t m, const double *g_e2, const double *x, double *y, hipStream_t st);
 size_t grad_smem_bytes(int64_t n, int prec);
 
 }  // namespace hfk

@@ -65,6 +65,28 @@ def test_fock_rejects_invalid_arguments(kw, msg):
     assert msg in hfk.lib().hfk_last_error().decode()
 
 
+def _grad_raw(n=4, xyz=1, dens=1, g_e2=1, g_fock=None, fock_in=None, d_xyz=1, d_dens=None, ws=256):
+    e = np.ascontiguousarray((6.36242139, 1.158923, 0.31364979), dtype=np.float64)
+    c = np.ascontiguousarray((0.15432897, 0.53532814, 0.44463454), dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    return hfk.lib().hfk_fock_grad(n, xyz, 3, e.ctypes.data_as(dp), c.ctypes.data_as(dp), dens, 1e-10, 0, g_e2,
+                                   g_fock, fock_in, d_xyz, d_dens, None, ws, 1 << 40, None)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(n=0), "natoms"),
+    (dict(g_e2=None), "g_e2"),
+    (dict(d_xyz=None), "d_xyz"),
+    (dict(d_dens=1), "fock_in"),
+    (dict(d_dens=1, g_fock=1), "fock_in"),
+    (dict(ws=None), "workspace"),
+])
+def test_fock_grad_rejects_invalid_arguments(kw, msg):
+    st = _grad_raw(**kw)
+    assert st == hfk.HFK_EINVAL
+    assert msg in hfk.lib().hfk_last_error().decode()
+
+
 def test_workspace_bytes_validation():
     out = ctypes.c_size_t(0)
     L = hfk.lib()

@@ -1,5 +1,5 @@
-"""GPU parity of the backward kernel (dE2/dR, dE2/dD) against the CPU oracle and finite
-differences, through the C ABI and the autograd Function."""
+"""GPU parity of the backward kernel (dE2/dR, dE2/dD, and the pull-back of dL/dG) against
+the CPU oracle and finite differences, through the C ABI and the autograd Function."""
 import numpy as np
 import pytest
 
@@ -96,11 +96,68 @@ def test_autograd_function(torch_dev):
     gr, _, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
     assert rel_fro(xyz.grad.cpu().numpy(), 3.0 * gr) < FP64_TOL
     assert np.abs(D.grad.cpu().numpy() - 3.0 * G.detach().cpu().numpy()).max() < 1e-13 * np.abs(G.detach().cpu().numpy()).max()
-    # a gradient flowing into G itself is refused
-    xyz2 = torch.tensor(s.xyz, device=dev, requires_grad=True)
-    G2, E22 = hfk.FockEnergy.apply(xyz2, D.detach(), s.exps, s.coefs, s.tau, "fp64")
-    with pytest.raises((RuntimeError, NotImplementedError)):
-        (G2.sum() + E22.sum()).backward()
+
+
+def _vjp_reference(s, GF, ge2):
+    """Oracle pull-back of (dL/dG = GF, dL/dE2 = ge2): positions through the two-density
+    contraction with X = sym(GF) + (ge2/2) D, density through ge2 G + G(sym(GF))."""
+    W = 0.5 * (GF + GF.T)
+    gx = oracle.grad_pair(s.xyz, s.dens, W + 0.5 * ge2 * s.dens, s.exps, s.coefs, s.tau)
+    G = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)[0]
+    GW = oracle.fock(s.xyz, W, s.exps, s.coefs, s.tau)[0]
+    return gx, ge2 * G + GW
+
+
+@pytest.mark.parametrize("n,seed,box,tau,ge2", [(3, 21, 3.0, 0.0, 0.0), (8, 22, 7.0, 1e-10, 0.7),
+                                                (37, 23, 9.0, 1e-10, -1.3)])
+def test_fock_output_vjp_vs_oracle(torch_dev, n, seed, box, tau, ge2):
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    s = random_cluster(n, seed, box=box, tau=tau)
+    announce("vjp through G n=%d seed=%d ge2=%g" % (n, seed, ge2))
+    GF = np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n, n))   # not symmetric on purpose
+    xyz = torch.tensor(s.xyz, device=dev)
+    D = torch.tensor(s.dens, device=dev)
+    G, _ = hfk.fock(xyz, D, s.exps, s.coefs, s.tau)
+    g_e2 = torch.tensor([ge2], dtype=torch.float64, device=dev)
+    d_xyz, d_dens, _ = hfk.fock_grad(xyz, D, s.exps, s.coefs, s.tau, g_e2=g_e2, fock_in=G,
+                                     g_fock=torch.tensor(GF, device=dev))
+    gx, gd = _vjp_reference(s, GF, ge2)
+    assert rel_fro(d_xyz.cpu().numpy(), gx) < FP64_TOL, rel_fro(d_xyz.cpu().numpy(), gx)
+    assert rel_fro(d_dens.cpu().numpy(), gd) < FP64_TOL, rel_fro(d_dens.cpu().numpy(), gd)
+
+
+def test_fock_output_vjp_mixed(torch_dev):
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    s = random_cluster(20, 24, box=8.0, tau=1e-10)
+    announce("vjp through G mixed n=20")
+    GF = np.random.default_rng(24).uniform(-1.0, 1.0, size=(20, 20))
+    xyz = torch.tensor(s.xyz, device=dev)
+    D = torch.tensor(s.dens, device=dev)
+    G, _ = hfk.fock(xyz, D, s.exps, s.coefs, s.tau, precision="mixed")
+    g_e2 = torch.tensor([0.5], dtype=torch.float64, device=dev)
+    d_xyz, d_dens, _ = hfk.fock_grad(xyz, D, s.exps, s.coefs, s.tau, precision="mixed", g_e2=g_e2, fock_in=G,
+                                     g_fock=torch.tensor(GF, device=dev))
+    gx, gd = _vjp_reference(s, GF, 0.5)
+    assert rel_fro(d_xyz.cpu().numpy(), gx) < MIXED_TOL
+    assert rel_fro(d_dens.cpu().numpy(), gd) < MIXED_TOL
+
+
+def test_autograd_through_both_outputs(torch_dev):
+    """A loss on G and E2 together, through the autograd Function."""
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    s = random_cluster(9, 25, box=6.0, tau=1e-10)
+    announce("autograd through G and E2 n=9")
+    M = np.random.default_rng(25).uniform(-1.0, 1.0, size=(9, 9))
+    xyz = torch.tensor(s.xyz, device=dev, requires_grad=True)
+    D = torch.tensor(s.dens, device=dev, requires_grad=True)
+    G, E2 = hfk.FockEnergy.apply(xyz, D, s.exps, s.coefs, s.tau, "fp64")
+    ((G * torch.tensor(M, device=dev)).sum() + 2.5 * E2.sum()).backward()
+    gx, gd = _vjp_reference(s, M, 2.5)
+    assert rel_fro(xyz.grad.cpu().numpy(), gx) < FP64_TOL
+    assert rel_fro(D.grad.cpu().numpy(), gd) < FP64_TOL
 
 
 def test_gradcheck_small(torch_dev):
@@ -113,7 +170,7 @@ def test_gradcheck_small(torch_dev):
 
     def f(x, d):
         dd = 0.5 * (d + d.transpose(0, 1))
-        return hfk.FockEnergy.apply(x, dd.contiguous(), s.exps, s.coefs, 0.0, "fp64")[1]
+        return hfk.FockEnergy.apply(x, dd.contiguous(), s.exps, s.coefs, 0.0, "fp64")
 
     # work is handed out dynamically, so per-workgroup partial sums, and with them the last
     # bits of the FP64 result, differ between calls: allow that much nondeterminism

@@ -353,6 +353,52 @@ def test_gradient_net_force_and_torque(oracle_lib):
     assert np.abs(torque).max() < 1e-12 * max(sc, 1)
 
 
+def _sym_matrix(rng, n):
+    m = rng.uniform(-1.0, 1.0, size=(n, n))
+    return 0.5 * (m + m.T)
+
+
+def test_grad_pair_vs_finite_differences(oracle_lib):
+    """The pairing L(R) = sum W o G(R) with a fixed symmetric W: its gradient against
+    central differences of the forward oracle (tau = 0 and tau > 0, screen held fixed by a
+    geometry step far from any threshold)."""
+    rng = np.random.default_rng(31)
+    for tau in (0.0, 1e-9):
+        s = random_cluster(5, 32, box=4.5)
+        W = _sym_matrix(rng, s.natoms)
+        g = oracle_lib.grad_pair(s.xyz, s.dens, W, E3, C3, tau)
+        h = 1e-4
+        Q = oracle_lib.schwarz(s.xyz, E3, C3)
+        fd = np.zeros_like(g)
+        for a in range(s.natoms):
+            for x in range(3):
+                xp = s.xyz.copy(); xm = s.xyz.copy()
+                xp[a, x] += h; xm[a, x] -= h
+                # the screen is a property of the base geometry: pass its Q to both steps
+                Gp = oracle_lib.fock(xp, s.dens, E3, C3, tau, Q=Q)[0]
+                Gm = oracle_lib.fock(xm, s.dens, E3, C3, tau, Q=Q)[0]
+                fd[a, x] = (np.sum(W * Gp) - np.sum(W * Gm)) / (2 * h)
+        assert np.abs(fd - g).max() < 1e-8 * max(1.0, np.abs(g).max()), tau
+
+
+def test_grad_pair_special_cases(oracle_lib):
+    """X = D/2 reduces the pairing to E2 (same gradient as grad); linear in X; the pull-back
+    of W through D -> G is G(W) (sum W o G(D) = sum D o G(W): the map is self-adjoint)."""
+    rng = np.random.default_rng(33)
+    s = random_cluster(6, 34, box=5.0)
+    g, _, _ = oracle_lib.grad(s.xyz, s.dens, E3, C3, 1e-10)
+    gp = oracle_lib.grad_pair(s.xyz, s.dens, 0.5 * s.dens, E3, C3, 1e-10)
+    assert np.abs(gp - g).max() <= 1e-13 * np.abs(g).max()
+    W1, W2 = _sym_matrix(rng, s.natoms), _sym_matrix(rng, s.natoms)
+    a = oracle_lib.grad_pair(s.xyz, s.dens, W1, E3, C3, 1e-10)
+    b = oracle_lib.grad_pair(s.xyz, s.dens, W2, E3, C3, 1e-10)
+    c = oracle_lib.grad_pair(s.xyz, s.dens, 2.0 * W1 - 3.0 * W2, E3, C3, 1e-10)
+    assert np.abs(c - (2.0 * a - 3.0 * b)).max() <= 1e-12 * np.abs(c).max()
+    GD = oracle_lib.fock(s.xyz, s.dens, E3, C3, 1e-10)[0]
+    GW = oracle_lib.fock(s.xyz, W1, E3, C3, 1e-10)[0]
+    assert np.sum(W1 * GD) == pytest.approx(np.sum(s.dens * GW), rel=1e-13)
+
+
 def test_config_he64_matches_fixture(oracle_lib):
     """The 64-atom build against the stored fixture written by tests/golden/make_golden.py."""
     import os
