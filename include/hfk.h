@@ -59,7 +59,9 @@ typedef enum hfk_strategy {
     HFK_STRATEGY_ATOMIC = 2    /* workgroups flush their LDS rows into one F with atomics */
 } hfk_strategy;
 
-enum { HFK_MAX_NGAUSS = 8 };
+/* Arguments accept up to HFK_MAX_NGAUSS primitives per function; the kernels are built for
+ * up to HFK_BUILT_NGAUSS (more returns HFK_EUNSUPPORTED). */
+enum { HFK_MAX_NGAUSS = 8, HFK_BUILT_NGAUSS = 6 };
 
 /* Counters of the last build that used a workspace, read back by hfk_read_stats. */
 typedef struct hfk_stats {
@@ -99,7 +101,8 @@ hfk_status hfk_workspace_bytes(int64_t natoms, int32_t ngauss, int32_t precision
  *   workspace        device scratch of at least hfk_workspace_bytes(...) bytes, 256-byte
  *                    aligned; its contents on entry do not matter
  * Errors: HFK_EINVAL (arguments), HFK_ENOMEM (workspace too small), HFK_EUNSUPPORTED
- * (n above what one workgroup's LDS rows hold), HFK_EHIP (launch failure). */
+ * (n above what one workgroup's LDS rows hold, or ngauss above HFK_BUILT_NGAUSS),
+ * HFK_EHIP (launch failure). */
 hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss,
                     const double *exps_host, const double *coefs_host,
                     const double *dens, double tau, int32_t precision, int32_t strategy,

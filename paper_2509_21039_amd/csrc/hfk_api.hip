@@ -108,6 +108,8 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
 }
 
 constexpr int kMaxGroupsPerCU = 6;
+// Kernels are instantiated for 1 .. kMaxBuiltG primitives per atom.
+constexpr int kMaxBuiltG = HFK_BUILT_NGAUSS;
 static int g_cfg_variant = -1;
 static int g_cfg_gpc = 0;
 
@@ -170,7 +172,7 @@ struct TunedConfig {
 };
 static TunedConfig g_tuned_cfg[2][4];
 
-static TunedConfig pick_config(int32_t strategy, int32_t precision, int64_t n)
+static TunedConfig pick_config(int32_t strategy, int32_t precision, int64_t n, int32_t ngauss)
 {
     TunedConfig c;
     {
@@ -181,6 +183,7 @@ static TunedConfig pick_config(int32_t strategy, int32_t precision, int64_t n)
     if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_ATOMIC) c.strategy = strategy;
     if (g_cfg_variant >= 0) c.variant = g_cfg_variant;
     if (g_cfg_gpc > 0) c.gpc = g_cfg_gpc;
+    if (ngauss > 4) c.variant = 1;   // the direct form is built for g <= 4 only
     return c;
 }
 
@@ -296,13 +299,13 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_ATOMIC)
         return fail(HFK_EINVAL, "unknown strategy %d", (int)strategy);
     if (natoms > kMaxAtoms) return fail(HFK_EUNSUPPORTED, "natoms above %lld", (long long)kMaxAtoms);
-    if (ngauss > 4) return fail(HFK_EUNSUPPORTED, "ngauss above 4 is not built in this version");
+    if (ngauss > kMaxBuiltG) return fail(HFK_EUNSUPPORTED, "ngauss above %d is not built in this version", kMaxBuiltG);
     const int cus = device_cu_count();
     if (cus <= 0) return fail(HFK_EHIP, "no HIP device");
     Layout L = make_layout(natoms, ngauss, precision, 0, groups_cap(cus));
     if (workspace_bytes < L.total)
         return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
-    const TunedConfig cfg = pick_config(strategy, precision, natoms);
+    const TunedConfig cfg = pick_config(strategy, precision, natoms, ngauss);
     int strat = cfg.strategy;
     if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
     {
@@ -363,7 +366,7 @@ hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss, cons
     if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
     if (natoms > kMaxGradAtoms)
         return fail(HFK_EUNSUPPORTED, "gradient supports natoms <= %lld", (long long)kMaxGradAtoms);
-    if (ngauss > 4) return fail(HFK_EUNSUPPORTED, "ngauss above 4 is not built in this version");
+    if (ngauss > kMaxBuiltG) return fail(HFK_EUNSUPPORTED, "ngauss above %d is not built in this version", kMaxBuiltG);
     const int cus = device_cu_count();
     if (cus <= 0) return fail(HFK_EHIP, "no HIP device");
     Layout L = make_layout(natoms, ngauss, precision, 1, groups_cap(cus));
@@ -393,7 +396,7 @@ hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss, cons
         // rebuilt around W; the screen depends on the geometry only), then the axpy
         e = launch_pairs(L, b, ws, xyz, xw, tau, st);
         if (e != hipSuccess) return hip_fail(e, "pair launch (W)");
-        const TunedConfig cfg = pick_config(HFK_STRATEGY_AUTO, precision, natoms);
+        const TunedConfig cfg = pick_config(HFK_STRATEGY_AUTO, precision, natoms, ngauss);
         int strat = cfg.strategy;
         if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
         Layout LF = L;
@@ -453,7 +456,7 @@ hfk_status hfk_fock_batched(int64_t nmol, const int64_t *atom_off_host, const do
     if (!e2) return fail(HFK_EINVAL, "e2 is NULL");
     if (!workspace) return fail(HFK_EINVAL, "workspace is NULL");
     if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
-    if (ngauss > 4) return fail(HFK_EUNSUPPORTED, "ngauss above 4 is not built in this version");
+    if (ngauss > kMaxBuiltG) return fail(HFK_EUNSUPPORTED, "ngauss above %d is not built in this version", kMaxBuiltG);
     const BLayout L = make_blayout(nmol, atom_off_host, ngauss, d_xyz != nullptr);
     if (workspace_bytes < L.total)
         return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
@@ -541,7 +544,7 @@ hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     double best_ms = 1e300;
     hfk_status err = HFK_OK;
     for (int si = 0; si < 2 && err == HFK_OK; ++si)
-        for (int vi = 0; vi < 2 && err == HFK_OK; ++vi)
+        for (int vi = 0; vi < (ngauss > 4 ? 1 : 2) && err == HFK_OK; ++vi)
             for (int gi = 0; gi < 4 && err == HFK_OK; ++gi) {
                 g_cfg_variant = variants[vi];
                 g_cfg_gpc = gpcs[gi];

@@ -763,14 +763,18 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
             case 1: HFK_B_LAUNCH(1, float, true); break;
             case 2: HFK_B_LAUNCH(2, float, true); break;
             case 3: HFK_B_LAUNCH(3, float, true); break;
-            default: HFK_B_LAUNCH(4, float, true); break;
+            case 4: HFK_B_LAUNCH(4, float, true); break;
+            case 5: HFK_B_LAUNCH(5, float, true); break;
+            default: HFK_B_LAUNCH(6, float, true); break;
             }
         } else {
             switch (b.g) {
             case 1: HFK_B_LAUNCH(1, float, false); break;
             case 2: HFK_B_LAUNCH(2, float, false); break;
             case 3: HFK_B_LAUNCH(3, float, false); break;
-            default: HFK_B_LAUNCH(4, float, false); break;
+            case 4: HFK_B_LAUNCH(4, float, false); break;
+            case 5: HFK_B_LAUNCH(5, float, false); break;
+            default: HFK_B_LAUNCH(6, float, false); break;
             }
         }
     } else {
@@ -779,14 +783,18 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
             case 1: HFK_B_LAUNCH(1, double, true); break;
             case 2: HFK_B_LAUNCH(2, double, true); break;
             case 3: HFK_B_LAUNCH(3, double, true); break;
-            default: HFK_B_LAUNCH(4, double, true); break;
+            case 4: HFK_B_LAUNCH(4, double, true); break;
+            case 5: HFK_B_LAUNCH(5, double, true); break;
+            default: HFK_B_LAUNCH(6, double, true); break;
             }
         } else {
             switch (b.g) {
             case 1: HFK_B_LAUNCH(1, double, false); break;
             case 2: HFK_B_LAUNCH(2, double, false); break;
             case 3: HFK_B_LAUNCH(3, double, false); break;
-            default: HFK_B_LAUNCH(4, double, false); break;
+            case 4: HFK_B_LAUNCH(4, double, false); break;
+            case 5: HFK_B_LAUNCH(5, double, false); break;
+            default: HFK_B_LAUNCH(6, double, false); break;
             }
         }
     }

@@ -547,15 +547,20 @@ __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ part,
 template <int G, typename R>
 static hipError_t launch_fock_t(const FockArgs &a, int groups, int variant, hipStream_t st)
 {
-    const bool split = variant != 0;
+    // the direct form keeps a bra's primitive data in LDS slots sized for g <= 4
+    const bool split = G > 4 || variant != 0;
     const size_t smem = FockSmem<R>::total(a.n, split);
     const hipError_t ez = launch_zero_counter(a.next_block, st);
     if (ez != hipSuccess) return ez;
     profile_begin(st);
-    if (split)
+    if constexpr (G > 4) {
         hipLaunchKernelGGL((k_fock<G, R, true>), dim3(groups), dim3(kGroupThreads), smem, st, a);
-    else
-        hipLaunchKernelGGL((k_fock<G, R, false>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+    } else {
+        if (split)
+            hipLaunchKernelGGL((k_fock<G, R, true>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+        else
+            hipLaunchKernelGGL((k_fock<G, R, false>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+    }
     profile_end(st);
     return hipGetLastError();
 }
@@ -564,8 +569,14 @@ template <int G, typename R>
 static int resident_t(bool split, size_t smem)
 {
     int nb = 0;
-    const hipError_t e = split ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fock<G, R, true>, kGroupThreads, smem)
-                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fock<G, R, false>, kGroupThreads, smem);
+    hipError_t e;
+    if constexpr (G > 4) {
+        (void)split;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fock<G, R, true>, kGroupThreads, smem);
+    } else {
+        e = split ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fock<G, R, true>, kGroupThreads, smem)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fock<G, R, false>, kGroupThreads, smem);
+    }
     return e == hipSuccess ? nb : 0;
 }
 
@@ -580,14 +591,18 @@ int fock_resident_groups(int g, int prec, int variant, int64_t n)
         case 1: return resident_t<1, float>(split, smem);
         case 2: return resident_t<2, float>(split, smem);
         case 3: return resident_t<3, float>(split, smem);
-        default: return resident_t<4, float>(split, smem);
+        case 4: return resident_t<4, float>(split, smem);
+        case 5: return resident_t<5, float>(true, smem);
+        default: return resident_t<6, float>(true, smem);
         }
     }
     switch (g) {
     case 1: return resident_t<1, double>(split, smem);
     case 2: return resident_t<2, double>(split, smem);
     case 3: return resident_t<3, double>(split, smem);
-    default: return resident_t<4, double>(split, smem);
+    case 4: return resident_t<4, double>(split, smem);
+    case 5: return resident_t<5, double>(true, smem);
+    default: return resident_t<6, double>(true, smem);
     }
 }
 
@@ -644,14 +659,18 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
         case 1: err = launch_fock_t<1, float>(a, L.groups, variant, st); break;
         case 2: err = launch_fock_t<2, float>(a, L.groups, variant, st); break;
         case 3: err = launch_fock_t<3, float>(a, L.groups, variant, st); break;
-        default: err = launch_fock_t<4, float>(a, L.groups, variant, st); break;
+        case 4: err = launch_fock_t<4, float>(a, L.groups, variant, st); break;
+        case 5: err = launch_fock_t<5, float>(a, L.groups, 1, st); break;
+        default: err = launch_fock_t<6, float>(a, L.groups, 1, st); break;
         }
     } else {
         switch (g) {
         case 1: err = launch_fock_t<1, double>(a, L.groups, variant, st); break;
         case 2: err = launch_fock_t<2, double>(a, L.groups, variant, st); break;
         case 3: err = launch_fock_t<3, double>(a, L.groups, variant, st); break;
-        default: err = launch_fock_t<4, double>(a, L.groups, variant, st); break;
+        case 4: err = launch_fock_t<4, double>(a, L.groups, variant, st); break;
+        case 5: err = launch_fock_t<5, double>(a, L.groups, 1, st); break;
+        default: err = launch_fock_t<6, double>(a, L.groups, 1, st); break;
         }
     }
     if (err != hipSuccess) return err;

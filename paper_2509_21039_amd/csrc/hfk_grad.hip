@@ -449,14 +449,18 @@ hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *
         case 1: err = launch_grad_t<1, float>(a, L.groups, smem, st); break;
         case 2: err = launch_grad_t<2, float>(a, L.groups, smem, st); break;
         case 3: err = launch_grad_t<3, float>(a, L.groups, smem, st); break;
-        default: err = launch_grad_t<4, float>(a, L.groups, smem, st); break;
+        case 4: err = launch_grad_t<4, float>(a, L.groups, smem, st); break;
+        case 5: err = launch_grad_t<5, float>(a, L.groups, smem, st); break;
+        default: err = launch_grad_t<6, float>(a, L.groups, smem, st); break;
         }
     } else {
         switch (b.g) {
         case 1: err = launch_grad_t<1, double>(a, L.groups, smem, st); break;
         case 2: err = launch_grad_t<2, double>(a, L.groups, smem, st); break;
         case 3: err = launch_grad_t<3, double>(a, L.groups, smem, st); break;
-        default: err = launch_grad_t<4, double>(a, L.groups, smem, st); break;
+        case 4: err = launch_grad_t<4, double>(a, L.groups, smem, st); break;
+        case 5: err = launch_grad_t<5, double>(a, L.groups, smem, st); break;
+        default: err = launch_grad_t<6, double>(a, L.groups, smem, st); break;
         }
     }
     if (err != hipSuccess) return err;

@@ -92,3 +92,21 @@ def test_cluster_batch_2000_sampled(torch_dev):
     for m in range(len(systems)):
         gm = g[off[m]:off[m + 1]]
         assert np.abs(gm.sum(axis=0)).max() < 1e-5 * max(1.0, np.abs(gm).max())
+
+
+def test_six_primitive_batch(torch_dev):
+    """Six primitives per function in the batched launch, FP64 and mixed."""
+    systems = [random_cluster(n, 200 + i, box=1.2 * n ** (1 / 3) * 2.0, tau=1e-10) for i, n in enumerate([3, 11, 1, 19])]
+    for s in systems:
+        s.exps = np.array([30.0, 8.0, 2.5, 0.9, 0.35, 0.14])
+        s.coefs = np.array([0.02, 0.08, 0.25, 0.4, 0.3, 0.1])
+    for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+        announce("batched six primitives %s" % precision)
+        off, F, E2, g = _run(torch_dev, systems, precision)
+        for m, s in enumerate(systems):
+            Fm, gm = _mol(off, F, g, m, s.natoms)
+            Fr, Er, _ = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+            gr, _, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+            assert rel_fro(Fm, Fr) < tol, (precision, m)
+            assert rel(E2[m], Er) < tol, (precision, m)
+            assert np.linalg.norm(gm - gr) <= tol * max(np.linalg.norm(gr), 1e-6), (precision, m)

@@ -93,7 +93,7 @@ def test_ragged_sizes_vs_oracle(torch_dev, n, seed):
 ])
 @pytest.mark.parametrize("variant", [0, 1])
 def test_other_basis_sizes(torch_dev, exps, coefs, variant):
-    """The kernels are instantiated for 1..4 primitives per function."""
+    """1..4 primitives per function, both forms of the quartet kernel."""
     s = random_cluster(23, 31, box=8.0, tau=1e-10)
     s.exps = np.array(exps)
     s.coefs = np.array(coefs)
@@ -106,6 +106,29 @@ def test_other_basis_sizes(torch_dev, exps, coefs, variant):
     assert rel_fro(Gm, Gr) < MIXED_TOL
 
 
+# Five and six primitives per function (the paper's 1024-atom case uses six); made-up
+# exponents spanning the same range as a six-term He contraction.
+G5 = ([24.0, 6.5, 2.0, 0.7, 0.25], [0.03, 0.12, 0.35, 0.45, 0.2])
+G6 = ([30.0, 8.0, 2.5, 0.9, 0.35, 0.14], [0.02, 0.08, 0.25, 0.4, 0.3, 0.1])
+
+
+@pytest.mark.parametrize("exps,coefs", [G5, G6])
+def test_five_and_six_primitives(torch_dev, exps, coefs):
+    """g = 5, 6 run the hybrid form only (the direct form is built for g <= 4)."""
+    s = random_cluster(17, 33, box=7.0, tau=1e-10)
+    s.exps = np.array(exps)
+    s.coefs = np.array(coefs)
+    announce("ngauss=%d" % len(exps))
+    G, E2, st = _run(torch_dev, s)
+    assert st["variant"] == 1
+    Gr, Er, nsr = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+    assert st["quartets"] == nsr
+    assert rel_fro(G, Gr) < FP64_TOL
+    assert rel(E2, Er) < FP64_TOL
+    Gm, Em, _ = _run(torch_dev, s, precision="mixed")
+    assert rel_fro(Gm, Gr) < MIXED_TOL
+
+
 def test_unsupported_ngauss_raises(torch_dev):
     import paper_2509_21039_amd as hfk
     torch, dev = torch_dev
@@ -113,7 +136,7 @@ def test_unsupported_ngauss_raises(torch_dev):
     xyz = torch.tensor(s.xyz, device=dev)
     D = torch.tensor(s.dens, device=dev)
     with pytest.raises(hfk.HfkError) as ei:
-        hfk.fock(xyz, D, [1.0] * 5, [0.2] * 5, 0.0)
+        hfk.fock(xyz, D, [1.0] * 7, [0.2] * 7, 0.0)
     assert ei.value.status == hfk.HFK_EUNSUPPORTED
 
 
@@ -142,3 +165,21 @@ def test_max_atoms_sparse_lattice(torch_dev):
         assert abs(G[i, j] - r) <= FP64_TOL * scale, (i, j, G[i, j], r)
     assert np.array_equal(G, G.T)
     assert rel(E2, 0.5 * float(np.sum(s.dens * G))) < 1e-12
+
+
+def test_everything_screened(torch_dev):
+    """A threshold no pair product reaches: no quartet survives, G and E2 are exactly zero,
+    and the gradient is zero too."""
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    s = random_cluster(6, 51, box=4.0, tau=1e6)
+    announce("everything screened")
+    G, E2, st = _run(torch_dev, s)
+    assert st["quartets"] == 0 and st["sig_pairs"] == 0
+    assert not np.any(G) and E2 == 0.0
+    Gr, Er, nr = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+    assert nr == 0 and not np.any(Gr)
+    xyz = torch.tensor(s.xyz, device=dev)
+    D = torch.tensor(s.dens, device=dev)
+    d_xyz, _, E2g = hfk.fock_grad(xyz, D, s.exps, s.coefs, s.tau, want_dens=False)
+    assert not torch.any(d_xyz).item() and E2g.item() == 0.0

@@ -178,7 +178,9 @@ def test_gradcheck_small(torch_dev):
 
 
 @pytest.mark.parametrize("exps,coefs", [([0.8], [1.0]), ([3.0, 0.45], [0.4, 0.7]),
-                                        ([9.0, 2.1, 0.6, 0.19], [0.05, 0.25, 0.5, 0.3])])
+                                        ([9.0, 2.1, 0.6, 0.19], [0.05, 0.25, 0.5, 0.3]),
+                                        ([24.0, 6.5, 2.0, 0.7, 0.25], [0.03, 0.12, 0.35, 0.45, 0.2]),
+                                        ([30.0, 8.0, 2.5, 0.9, 0.35, 0.14], [0.02, 0.08, 0.25, 0.4, 0.3, 0.1])])
 def test_grad_other_basis_sizes(torch_dev, exps, coefs):
     s = random_cluster(9, 41, box=5.0, tau=1e-10)
     s.exps = np.array(exps)
