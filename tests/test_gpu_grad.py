@@ -190,3 +190,30 @@ def test_grad_other_basis_sizes(torch_dev, exps, coefs):
     gr, Er, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
     assert rel_fro(g, gr) < FP64_TOL
     assert rel(E2g, Er) < FP64_TOL
+
+
+def test_grad_max_atoms_sparse_lattice(torch_dev):
+    """The largest system the gradient accepts (4096 atoms) on a sparse lattice, where the
+    LDS gradient copy (3n doubles) and both tables are at their largest: sampled components
+    against central differences of the GPU energy, and zero net force."""
+    import paper_2509_21039_amd as hfk
+    from he_inputs import jittered_lattice
+    torch, dev = torch_dev
+    s = jittered_lattice((16, 16, 16), seed=12, tau=1e-10, spacing=14.0, jitter=0.5)
+    assert s.natoms == 4096
+    announce("grad max atoms 4096 sparse")
+    xyz = torch.tensor(s.xyz, device=dev)
+    D = torch.tensor(s.dens, device=dev)
+    ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, 3, "fp64", True), dev)
+    d_xyz, _, E2g = hfk.fock_grad(xyz, D, s.exps, s.coefs, s.tau, want_dens=False, workspace=ws)
+    g = d_xyz.cpu().numpy()
+    _, E2 = hfk.fock(xyz, D, s.exps, s.coefs, s.tau, workspace=ws)
+    assert rel(E2g.item(), E2.item()) < FP64_TOL
+    assert np.abs(g.sum(axis=0)).max() < 1e-10 * max(1.0, np.abs(g).max())
+    h = 1e-3
+    for a, c in [(0, 0), (1234, 1), (4095, 2)]:
+        xp = s.xyz.copy(); xm = s.xyz.copy()
+        xp[a, c] += h; xm[a, c] -= h
+        ep = hfk.fock(torch.tensor(xp, device=dev), D, s.exps, s.coefs, s.tau, workspace=ws)[1].item()
+        em = hfk.fock(torch.tensor(xm, device=dev), D, s.exps, s.coefs, s.tau, workspace=ws)[1].item()
+        assert abs((ep - em) / (2 * h) - g[a, c]) < 1e-6 * max(1.0, np.abs(g).max()), (a, c)
