@@ -183,3 +183,46 @@ def test_everything_screened(torch_dev):
     D = torch.tensor(s.dens, device=dev)
     d_xyz, _, E2g = hfk.fock_grad(xyz, D, s.exps, s.coefs, s.tau, want_dens=False)
     assert not torch.any(d_xyz).item() and E2g.item() == 0.0
+
+
+def test_he512_full_size_tuned(torch_dev):
+    """The 512-atom workload in the configuration the bench times (tuned first): survivors,
+    E2 and 64 sampled elements against the oracle's full build (stored fixture)."""
+    import os
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    s = config_system("he512_fp64")
+    announce("he512 fp64 tuned, full size")
+    rows, e2_ref, ns_ref = load_golden("he512_fp64_sample")
+    xyz = torch.tensor(s.xyz, device=dev)
+    D = torch.tensor(s.dens, device=dev)
+    hfk.tune(xyz, D, s.exps, s.coefs, s.tau, precision="fp64")
+    ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, 3, "fp64"), dev)
+    G, E2 = hfk.fock(xyz, D, s.exps, s.coefs, s.tau, workspace=ws)
+    st = hfk.read_stats(ws)
+    G = G.cpu().numpy()
+    assert st["quartets"] == ns_ref
+    assert rel(float(E2.item()), e2_ref) < FP64_TOL
+    scale = np.abs(rows[:, 2]).max()
+    for i, j, v in rows:
+        assert abs(G[int(i), int(j)] - v) <= FP64_TOL * scale, (i, j)
+
+
+def test_he1024_mixed_sampled(torch_dev):
+    """The 1024-atom mixed-precision workload: sampled elements of the mixed and FP64 builds
+    against the oracle's element-wise definition, and E2 mixed against E2 FP64."""
+    torch, dev = torch_dev
+    s = config_system("he1024_mixed")
+    announce("he1024 mixed and fp64 sampled")
+    G64, E64, st = _run(torch_dev, s)
+    Gm, Em, _ = _run(torch_dev, s, precision="mixed")
+    Q = oracle.schwarz(s.xyz, s.exps, s.coefs)
+    rng = np.random.default_rng(1024)
+    idx = [(0, 0), (1023, 5)] + [tuple(int(v) for v in p) for p in rng.integers(0, 1024, (4, 2))]
+    ref = [oracle.fock_element(s.xyz, s.dens, s.exps, s.coefs, s.tau, Q, i, j) for i, j in idx]
+    scale = max(abs(r) for r in ref)
+    for (i, j), r in zip(idx, ref):
+        assert abs(G64[i, j] - r) <= FP64_TOL * scale, (i, j)
+        assert abs(Gm[i, j] - r) <= MIXED_TOL * scale, (i, j)
+    assert rel(Em, E64) < MIXED_TOL
+    assert rel_fro(Gm, G64) < MIXED_TOL

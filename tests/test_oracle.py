@@ -412,3 +412,17 @@ def test_config_he64_matches_fixture(oracle_lib):
     assert E2 == pytest.approx(e2_ref, rel=1e-13)
     Fref = np.loadtxt(path)
     assert np.abs(F - Fref).max() <= 1e-13 * np.abs(Fref).max()
+
+
+def test_he512_fixture_elements_match_element_definition(oracle_lib):
+    """Sampled entries of the stored 512-atom build (written by the unique-quartet oracle)
+    against the element-wise plain definition, a separate code path."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "he512_fp64_sample.txt")
+    rows = np.loadtxt(path)
+    s = config_system("he512_fp64")
+    Q = oracle_lib.schwarz(s.xyz, E3, C3)
+    scale = np.abs(rows[:, 2]).max()
+    for i, j, v in rows[:8]:
+        e = oracle_lib.fock_element(s.xyz, s.dens, E3, C3, s.tau, Q, int(i), int(j))
+        assert abs(e - v) <= 1e-12 * scale, (i, j)
