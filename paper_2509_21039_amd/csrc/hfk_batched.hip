@@ -18,8 +18,6 @@
 
 namespace hfk {
 
-constexpr int kMaxBatchAtoms = 128;
-
 struct BArgs {
     const DevHeader *hdr;
     const BasisDev *bd;
@@ -256,7 +254,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
     R *tH = (R *)(lg + 3 * nmax);
     R *tG = tH + kBoysGrid * kBoysStride;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    const int gid = blockIdx.x, ng = gridDim.x;
     const long long M = a.hdr->items;
     const int S = a.hdr->sig_pairs;
     const BasisDev *bd = a.bd;

@@ -266,11 +266,10 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
 template <typename R> struct FockSmem {
     static constexpr int kCombos = kMaxG2 * kMaxG2 / 16;                    // g <= 4 here: 256 combos
     static constexpr size_t tab_bytes = sizeof(R) * kBoysGrid * kBoysStride;
-    static constexpr size_t cw_bytes = 3 * sizeof(R) * kCombos;            // (rho, S_ab sqrt(rho), pad)
-    static constexpr size_t uni_bytes = 4 * sizeof(R) * 16 + 2 * sizeof(R) * kCombos;   // bra, (rho|thr, srho)
+    static constexpr size_t uni_bytes = 4 * sizeof(R) * 16 + 2 * sizeof(R) * kCombos;   // bra, (rho, srho)
     static size_t total(int n, bool split)
     {
-        return sizeof(double) * 2 * (size_t)n + tab_bytes + (split ? 0 : cw_bytes + uni_bytes);
+        return sizeof(double) * 2 * (size_t)n + tab_bytes + (split ? 0 : uni_bytes);
     }
 };
 
@@ -287,11 +286,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     double *rowi = (double *)sp;
     double *rowj = rowi + n;
     sp += sizeof(double) * 2 * (size_t)n;
-    R *cw = (R *)sp;                        // (rho, S_ab sqrt(rho)) per quartet combo of the current bra
-    sp += FockSmem<R>::cw_bytes;
-    R *lbra = (R *)sp;                      // [G2][4] Px, Py, Pz, S of the current bra
-    R *luni = lbra + 4 * 16;                // direct: (rho, sqrt rho) per combo; split: r2 switch per combo
-    sp += FockSmem<R>::uni_bytes;
+    R *lbra = (R *)sp;                      // direct form: [G2][4] Px, Py, Pz, S of the current bra
+    R *luni = lbra + 4 * 16;                // direct form: (rho, sqrt rho) per primitive quartet
     __shared__ int bra_at[2];
     __shared__ double bra_qd[2];
     __shared__ int wperm[kWavesPerGroup][kWaveKets];
