@@ -67,6 +67,26 @@ def log(msg):
     sys.stderr.flush()
 
 
+def sample_sclk(delay_s: float, out: dict):
+    """Reads the shader clock once with rocm-smi, delay_s into the timed run (None if the tool
+    is missing or its output has no sclk figure)."""
+    import re
+    import subprocess
+    time.sleep(delay_s)
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
+        d = json.loads(r.stdout)
+        for card in d.values():
+            for k, v in card.items():
+                if "sclk" in k.lower():
+                    m = re.search(r"(\d+)\s*Mhz", str(v), re.I)
+                    if m:
+                        out["sclk_mhz"] = int(m.group(1))
+                        return
+    except Exception:
+        pass
+
+
 def flop_per_quartet(g: int) -> int:
     return g ** 4 * FLOP_PER_PRIM_QUARTET + FLOP_SCATTER_PER_QUARTET
 
@@ -89,6 +109,10 @@ def time_builds(hfk, torch, s, precision, steps, warmup, ws):
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    clock = {}
+    import threading
+    sampler = threading.Thread(target=sample_sclk, args=(0.3, clock), daemon=True)
+    sampler.start()
     e0.record(stream)
     marks[0].record(stream)
     for k in range(steps):
@@ -96,6 +120,7 @@ def time_builds(hfk, torch, s, precision, steps, warmup, ws):
         marks[k + 1].record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
+    sampler.join(timeout=30)
     hfk.profile_enable(False)
     kern_ms, launches = hfk.profile_read()
     total_ms = e0.elapsed_time(e1)
@@ -105,7 +130,8 @@ def time_builds(hfk, torch, s, precision, steps, warmup, ws):
         return per[min(len(per) - 1, int(round(q * (len(per) - 1))))]
 
     return {"ms_per_step": total_ms / steps, "kernel_ms": kern_ms / max(launches, 1), "stats": stats,
-            "e2": float(E2.item()), "F": F, "step_ms": {"median": pct(0.5), "p10": pct(0.1), "p90": pct(0.9)}}
+            "e2": float(E2.item()), "F": F, "step_ms": {"median": pct(0.5), "p10": pct(0.1), "p90": pct(0.9)},
+            "sclk_mhz": clock.get("sclk_mhz")}
 
 
 def time_grad(hfk, torch, s, steps, warmup):
@@ -260,6 +286,9 @@ def main():
                    "workgroups": r["stats"]["groups"], "parallelism": "single GPU"},
         "pct_fp64_valu_peak_nominal": 100.0 * achieved / FP64_VALU_PEAK_TFLOPS,
         "step_ms": r["step_ms"],
+        "sclk_mhz_sampled": r["sclk_mhz"],
+        "pct_fp64_valu_peak_at_sampled_clock": (100.0 * achieved / (FP64_VALU_PEAK_TFLOPS * r["sclk_mhz"] / 2400.0)
+                                                if r["sclk_mhz"] else None),
         "primitive_quartets_per_s": q * g ** 4 / (r["ms_per_step"] / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": measured_traffic(r["stats"]),
