@@ -226,3 +226,30 @@ def test_he1024_mixed_sampled(torch_dev):
         assert abs(Gm[i, j] - r) <= MIXED_TOL * scale, (i, j)
     assert rel(Em, E64) < MIXED_TOL
     assert rel_fro(Gm, G64) < MIXED_TOL
+
+
+def test_workspace_too_small_is_rejected(torch_dev):
+    """A workspace below hfk_workspace_bytes gives HFK_ENOMEM before any launch, for the
+    forward, gradient and batched calls."""
+    import paper_2509_21039_amd as hfk
+    from he_inputs import pack_batch
+    torch, dev = torch_dev
+    s = random_cluster(12, 61, box=5.0, tau=1e-10)
+    announce("workspace too small")
+    xyz = torch.tensor(s.xyz, device=dev)
+    D = torch.tensor(s.dens, device=dev)
+    small = hfk.new_workspace(4096, dev)
+    with pytest.raises(hfk.HfkError) as ei:
+        hfk.fock(xyz, D, s.exps, s.coefs, s.tau, workspace=small)
+    assert ei.value.status == hfk.HFK_ENOMEM
+    G, _ = hfk.fock(xyz, D, s.exps, s.coefs, s.tau)
+    # a forward-sized workspace is too small for the gradient
+    fwd_ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, 3, "fp64"), dev)
+    with pytest.raises(hfk.HfkError) as ei:
+        hfk.fock_grad(xyz, D, s.exps, s.coefs, s.tau, fock_in=G, workspace=fwd_ws)
+    assert ei.value.status == hfk.HFK_ENOMEM
+    off, bx, bd = pack_batch([s, random_cluster(3, 62)])
+    with pytest.raises(hfk.HfkError) as ei:
+        hfk.fock_batched(off, torch.tensor(bx, device=dev), torch.tensor(bd, device=dev), s.exps, s.coefs, s.tau,
+                         precision="fp64", with_grad=True, workspace=small)
+    assert ei.value.status == hfk.HFK_ENOMEM
