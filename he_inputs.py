@@ -13,6 +13,10 @@ Recipe (stated once, used everywhere):
     D = 0.1 * (M + M^T) / 2 with the diagonal then set to 1.0.
   * Basis: one contracted s function per atom with the STO-3G helium exponents and
     contraction coefficients below (the same three primitives on every atom).
+  * Per-atom bases (mixed H/He systems): after positions and density, one (n,) draw of
+    U[0, 1) marks atom i as hydrogen when below ``frac_h``; hydrogen carries the STO-3G
+    hydrogen exponents with the same coefficients.  Random contractions for brute-force
+    checks draw log-uniform exponents in [0.1, 10] and U(0.1, 1) coefficients.
 
 The paper measures on helium test systems (up to 256 atoms with three Gaussians per atom,
 and 1024 atoms with six; Methodology section and Table 4) whose input files are not
@@ -28,6 +32,8 @@ import numpy as np
 # STO-3G helium: exponents (bohr^-2) and contraction coefficients of the single s function.
 HE_STO3G_EXPS = np.array([6.36242139, 1.15892300, 0.31364979], dtype=np.float64)
 HE_STO3G_COEFS = np.array([0.15432897, 0.53532814, 0.44463454], dtype=np.float64)
+# STO-3G hydrogen: its own exponents, the same three contraction coefficients.
+H_STO3G_EXPS = np.array([3.42525091, 0.62391373, 0.16885540], dtype=np.float64)
 
 
 @dataclass
@@ -125,3 +131,27 @@ def random_cluster(n: int, seed: int, box: float = 4.0, tau: float = 0.0) -> Sys
     xyz = rng.uniform(0.0, box, size=(n, 3))
     dens = density_from(rng, n)
     return System(xyz=xyz, dens=dens, tau=tau)
+
+
+def mixed_lattice(shape, seed: int, tau: float, frac_h: float = 0.5, spacing: float = 2.0,
+                  jitter: float = 0.2) -> System:
+    """Jittered lattice of H and He atoms with per-atom bases: ``exps`` and ``coefs`` are
+    (n, 3), row i the contraction of atom i."""
+    rng = _rng(seed)
+    pts = lattice_points(shape, spacing)
+    n = pts.shape[0]
+    xyz = pts + rng.uniform(-jitter, jitter, size=(n, 3))
+    dens = density_from(rng, n)
+    is_h = rng.uniform(0.0, 1.0, size=n) < frac_h
+    exps = np.where(is_h[:, None], H_STO3G_EXPS[None, :], HE_STO3G_EXPS[None, :])
+    coefs = np.broadcast_to(HE_STO3G_COEFS, (n, 3)).copy()
+    return System(xyz=xyz, dens=dens, exps=exps, coefs=coefs, tau=tau)
+
+
+def random_basis_rows(n: int, g: int, seed: int):
+    """(n, g) exponents (log-uniform in [0.1, 10]) and coefficients (U(0.1, 1)), one
+    contraction per atom."""
+    rng = _rng(seed)
+    exps = np.exp(rng.uniform(math.log(0.1), math.log(10.0), size=(n, g)))
+    coefs = rng.uniform(0.1, 1.0, size=(n, g))
+    return exps, coefs

@@ -15,6 +15,12 @@ Parity status of each function (what pins it, in ``tests/test_oracle.py``):
                                 invariances, E2(lambda D) = lambda^2 E2, dE2/dD = G
   fock_element                  pinned: the plain definition itself, equals brute force
   grad                          pinned: central finite differences of E2, zero net force and torque
+  eri4                          pinned (per-centre contractions): two-centre Gaussian-charge closed
+                                form with unequal exponents, coincident-centre value, scaling law
+                                (exponents x l^2, lengths / l gives x l), 8-fold symmetry
+  *_atoms                       pinned: brute-force plain definition with per-atom bases, reduction
+                                to the one-basis build when every row is equal, atom-permutation
+                                equivariance, far-field S_ii S_kk / R, central differences of E2
 """
 from __future__ import annotations
 
@@ -77,6 +83,18 @@ def _load():
         lib.hfo_grad.restype = ctypes.c_int
         lib.hfo_grad.argtypes = [ctypes.c_int64, _dp, ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
                                  _dp, ctypes.c_int, _dp, _dp, _i64p]
+        lib.hfo_eri4.restype = ctypes.c_double
+        lib.hfo_eri4.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_int] + [_dp] * 8
+        lib.hfo_schwarz_atoms.restype = ctypes.c_int
+        lib.hfo_schwarz_atoms.argtypes = lib.hfo_schwarz.argtypes
+        lib.hfo_fock_atoms.restype = ctypes.c_int
+        lib.hfo_fock_atoms.argtypes = lib.hfo_fock.argtypes
+        lib.hfo_fock_element_atoms.restype = ctypes.c_double
+        lib.hfo_fock_element_atoms.argtypes = lib.hfo_fock_element.argtypes
+        lib.hfo_fock_bruteforce_atoms.restype = ctypes.c_int
+        lib.hfo_fock_bruteforce_atoms.argtypes = lib.hfo_fock_bruteforce.argtypes
+        lib.hfo_grad_atoms.restype = ctypes.c_int
+        lib.hfo_grad_atoms.argtypes = lib.hfo_grad.argtypes
         lib.hfo_num_threads.restype = ctypes.c_int
         lib.hfo_num_threads.argtypes = []
         _lib = lib
@@ -191,3 +209,95 @@ def grad_pair(xyz, dens, xdens, exps, coefs, tau, Q=None, nthreads: int = 0):
     if rc != 0:
         raise MemoryError("oracle grad_pair: out of memory")
     return g
+
+
+# ---------------------------------------------------------------- per-atom bases
+# exps and coefs are (n, g): row i is the contraction of atom i.
+
+def _atoms(xyz, exps, coefs):
+    xyz, px = _c(xyz)
+    e, pe = _c(exps)
+    c, pc = _c(coefs)
+    n = xyz.shape[0]
+    if e.shape != c.shape or e.ndim != 2 or e.shape[0] != n:
+        raise ValueError("per-atom exps and coefs must both be (natoms, ngauss)")
+    return xyz, px, e, pe, c, pc, n, e.shape[1]
+
+
+def eri4(A, B, C, D, basis_a, basis_b, basis_c, basis_d) -> float:
+    """(AB|CD) with a contraction (exps, coefs) of its own on each centre."""
+    pts = [_c(x) for x in (A, B, C, D)]
+    bs = []
+    g = len(basis_a[0])
+    for e, c in (basis_a, basis_b, basis_c, basis_d):
+        e, pe = _c(e)
+        c, pc = _c(c)
+        if len(e) != g or len(c) != g:
+            raise ValueError("every centre needs the same number of primitives")
+        bs += [(e, pe), (c, pc)]
+    return _load().hfo_eri4(*[p for _, p in pts], g, *[p for _, p in bs])
+
+
+def schwarz_atoms(xyz, exps, coefs, nthreads: int = 0) -> np.ndarray:
+    xyz, px, e, pe, c, pc, n, g = _atoms(xyz, exps, coefs)
+    Q = np.zeros(n * (n + 1) // 2)
+    if _load().hfo_schwarz_atoms(n, px, g, pe, pc, int(nthreads), Q.ctypes.data_as(_dp)) != 0:
+        raise MemoryError("oracle schwarz_atoms: out of memory")
+    return Q
+
+
+def fock_atoms(xyz, dens, exps, coefs, tau, Q=None, nthreads: int = 0, bra_range=None):
+    """Unique-quartet Fock build with per-atom bases.  Returns (G, E2, survivors)."""
+    xyz, px, e, pe, c, pc, n, g = _atoms(xyz, exps, coefs)
+    d, pd = _c(dens)
+    npair = n * (n + 1) // 2
+    b0, b1 = (0, npair) if bra_range is None else bra_range
+    F = np.zeros((n, n))
+    e2 = ctypes.c_double(0.0)
+    ns = ctypes.c_int64(0)
+    qp = None
+    if Q is not None:
+        Q, qp = _c(Q)
+    rc = _load().hfo_fock_atoms(n, px, g, pe, pc, pd, float(tau), qp, int(nthreads), int(b0), int(b1),
+                                F.ctypes.data_as(_dp), ctypes.byref(e2), ctypes.byref(ns))
+    if rc != 0:
+        raise MemoryError("oracle fock_atoms: out of memory")
+    return F, e2.value, ns.value
+
+
+def fock_element_atoms(xyz, dens, exps, coefs, tau, Q, i, j, nthreads: int = 0) -> float:
+    xyz, px, e, pe, c, pc, n, g = _atoms(xyz, exps, coefs)
+    d, pd = _c(dens)
+    Q, qp = _c(Q)
+    v = _load().hfo_fock_element_atoms(n, px, g, pe, pc, pd, float(tau), qp, int(nthreads), int(i), int(j))
+    if v != v:
+        raise MemoryError("oracle fock_element_atoms: out of memory")
+    return v
+
+
+def fock_bruteforce_atoms(xyz, dens, exps, coefs, tau):
+    xyz, px, e, pe, c, pc, n, g = _atoms(xyz, exps, coefs)
+    d, pd = _c(dens)
+    F = np.zeros((n, n))
+    e2 = ctypes.c_double(0.0)
+    if _load().hfo_fock_bruteforce_atoms(n, px, g, pe, pc, pd, float(tau), F.ctypes.data_as(_dp),
+                                         ctypes.byref(e2)) != 0:
+        raise MemoryError("oracle fock_bruteforce_atoms: out of memory")
+    return F, e2.value
+
+
+def grad_atoms(xyz, dens, exps, coefs, tau, Q=None, nthreads: int = 0):
+    """dE2/dR (n, 3) with per-atom bases, E2, survivors."""
+    xyz, px, e, pe, c, pc, n, g = _atoms(xyz, exps, coefs)
+    d, pd = _c(dens)
+    gr = np.zeros((n, 3))
+    e2 = ctypes.c_double(0.0)
+    ns = ctypes.c_int64(0)
+    qp = None
+    if Q is not None:
+        Q, qp = _c(Q)
+    rc = _load().hfo_grad_atoms(n, px, g, pe, pc, pd, float(tau), qp, int(nthreads),
+                                gr.ctypes.data_as(_dp), ctypes.byref(e2), ctypes.byref(ns))
+    if rc != 0:
+        raise MemoryError("oracle grad_atoms: out of memory")
+    return gr, e2.value, ns.value

@@ -37,6 +37,11 @@
  * the same contraction for the pairing sum_ij W_ij G_ij with a fixed W (the derivative
  * through the G output), with Gamma replaced by its polarisation B(X, D).
  *
+ * Per-atom bases (the *_atoms entry points and hfo_eri4) give every atom its own exponents
+ * and coefficients; the formulas above take each centre's own exponents (the kernel listing
+ * passes one exponent and one coefficient array for all atoms, which is the special case of
+ * identical rows).
+ *
  * Readings where the paper is silent: normalised primitives with the coefficients used as
  * given (no contraction renormalisation); contracted Schwarz bounds in FP64 with a
  * "keep iff >= tau" test and no primitive-level screening; G symmetrised as (F + F^T)/2;
@@ -93,9 +98,25 @@ double hfo_boys1(double t)
 
 /* ---------------------------------------------------------------- basis */
 
+/* A basis description is (g, exps, coefs, astride): atom i carries the contraction
+ * exps[i * astride + a], coefs[i * astride + a], a < g.  astride = 0 gives every atom the
+ * same contraction (the kernel listing's single exponent and coefficient arrays);
+ * astride = g gives each atom its own (per-atom bases).  The primitive formulas above hold
+ * for any exponent on any centre. */
+
 static void prim_weights(int g, const double *exps, const double *coefs, double *w)
 {
     for (int a = 0; a < g; ++a) w[a] = coefs[a] * pow(2.0 * exps[a] / HFO_PI, 0.75);
+}
+
+/* w for every atom of a basis description (one row when astride = 0); NULL when out of memory. */
+static double *atom_weights(int64_t n, int g, const double *exps, const double *coefs, int64_t astride)
+{
+    const int64_t rows = astride ? n : 1;
+    double *w = (double *)malloc(sizeof(double) * (size_t)(rows * g));
+    if (!w) return NULL;
+    for (int64_t i = 0; i < rows; ++i) prim_weights(g, exps + i * astride, coefs + i * astride, w + i * g);
+    return w;
 }
 
 /* Overlap <phi_A | phi_B> of two contracted s functions. */
@@ -114,12 +135,12 @@ double hfo_overlap(const double *A, const double *B, int g, const double *exps, 
     return s;
 }
 
-/* Contracted (AB|CD): the four nested primitive loops of the kernel listing. */
-double hfo_eri(const double *A, const double *B, const double *C, const double *D,
-               int g, const double *exps, const double *coefs)
+/* Contracted (AB|CD): the four nested primitive loops of the kernel listing, each centre
+ * with its own exponents e* and weights w*. */
+static double eri_core(const double *A, const double *B, const double *C, const double *D, int g,
+                       const double *eA, const double *wA, const double *eB, const double *wB,
+                       const double *eC, const double *wC, const double *eD, const double *wD)
 {
-    double w[16];
-    prim_weights(g, exps, coefs, w);
     double ab2 = 0.0, cd2 = 0.0;
     for (int x = 0; x < 3; ++x) {
         ab2 += (A[x] - B[x]) * (A[x] - B[x]);
@@ -128,17 +149,17 @@ double hfo_eri(const double *A, const double *B, const double *C, const double *
     double eri = 0.0;
     for (int a = 0; a < g; ++a)
         for (int b = 0; b < g; ++b) {
-            double p = exps[a] + exps[b];
-            double Kab = w[a] * w[b] * exp(-exps[a] * exps[b] / p * ab2);
+            double p = eA[a] + eB[b];
+            double Kab = wA[a] * wB[b] * exp(-eA[a] * eB[b] / p * ab2);
             double P[3];
-            for (int x = 0; x < 3; ++x) P[x] = (exps[a] * A[x] + exps[b] * B[x]) / p;
+            for (int x = 0; x < 3; ++x) P[x] = (eA[a] * A[x] + eB[b] * B[x]) / p;
             for (int c = 0; c < g; ++c)
                 for (int d = 0; d < g; ++d) {
-                    double q = exps[c] + exps[d];
-                    double Kcd = w[c] * w[d] * exp(-exps[c] * exps[d] / q * cd2);
+                    double q = eC[c] + eD[d];
+                    double Kcd = wC[c] * wD[d] * exp(-eC[c] * eD[d] / q * cd2);
                     double Q[3], pq2 = 0.0;
                     for (int x = 0; x < 3; ++x) {
-                        Q[x] = (exps[c] * C[x] + exps[d] * D[x]) / q;
+                        Q[x] = (eC[c] * C[x] + eD[d] * D[x]) / q;
                         pq2 += (P[x] - Q[x]) * (P[x] - Q[x]);
                     }
                     double rho = p * q / (p + q);
@@ -149,6 +170,28 @@ double hfo_eri(const double *A, const double *B, const double *C, const double *
     return eri;
 }
 
+/* Contracted (AB|CD) with one contraction on all four centres. */
+double hfo_eri(const double *A, const double *B, const double *C, const double *D,
+               int g, const double *exps, const double *coefs)
+{
+    double w[16];
+    prim_weights(g, exps, coefs, w);
+    return eri_core(A, B, C, D, g, exps, w, exps, w, exps, w, exps, w);
+}
+
+/* Contracted (AB|CD) with a contraction of its own on each centre (eX, cX: g values each). */
+double hfo_eri4(const double *A, const double *B, const double *C, const double *D, int g,
+                const double *eA, const double *cA, const double *eB, const double *cB,
+                const double *eC, const double *cC, const double *eD, const double *cD)
+{
+    double wA[16], wB[16], wC[16], wD[16];
+    prim_weights(g, eA, cA, wA);
+    prim_weights(g, eB, cB, wB);
+    prim_weights(g, eC, cC, wC);
+    prim_weights(g, eD, cD, wD);
+    return eri_core(A, B, C, D, g, eA, wA, eB, wB, eC, wC, eD, wD);
+}
+
 /* Gradient of one contracted (AB|CD) with respect to the four centres, each scaled by
  * gamma and added into gA, gB, gC, gD (3 components each).  Per primitive quartet, with
  * E = pref K_ab K_cd:
@@ -156,8 +199,9 @@ double hfo_eri(const double *A, const double *B, const double *C, const double *
  *   d/dB = E [ +2 mu_ab (A-B) F0 - 2 rho (b/p) (P-Q) F1 ]
  *   d/dC = E [ -2 mu_cd (C-D) F0 + 2 rho (c/q) (P-Q) F1 ]
  *   d/dD = E [ +2 mu_cd (C-D) F0 + 2 rho (d/q) (P-Q) F1 ]                                 */
-static void eri_grad(const double *A, const double *B, const double *C, const double *D,
-                     int g, const double *exps, const double *w, double gamma,
+static void eri_grad(const double *A, const double *B, const double *C, const double *D, int g,
+                     const double *eA, const double *wA, const double *eB, const double *wB,
+                     const double *eC, const double *wC, const double *eD, const double *wD, double gamma,
                      double *gA, double *gB, double *gC, double *gD)
 {
     double ab2 = 0.0, cd2 = 0.0;
@@ -167,19 +211,19 @@ static void eri_grad(const double *A, const double *B, const double *C, const do
     }
     for (int a = 0; a < g; ++a)
         for (int b = 0; b < g; ++b) {
-            double p = exps[a] + exps[b];
-            double muab = exps[a] * exps[b] / p;
-            double Kab = w[a] * w[b] * exp(-muab * ab2);
+            double p = eA[a] + eB[b];
+            double muab = eA[a] * eB[b] / p;
+            double Kab = wA[a] * wB[b] * exp(-muab * ab2);
             double P[3];
-            for (int x = 0; x < 3; ++x) P[x] = (exps[a] * A[x] + exps[b] * B[x]) / p;
+            for (int x = 0; x < 3; ++x) P[x] = (eA[a] * A[x] + eB[b] * B[x]) / p;
             for (int c = 0; c < g; ++c)
                 for (int d = 0; d < g; ++d) {
-                    double q = exps[c] + exps[d];
-                    double mucd = exps[c] * exps[d] / q;
-                    double Kcd = w[c] * w[d] * exp(-mucd * cd2);
+                    double q = eC[c] + eD[d];
+                    double mucd = eC[c] * eD[d] / q;
+                    double Kcd = wC[c] * wD[d] * exp(-mucd * cd2);
                     double Q[3], pq2 = 0.0;
                     for (int x = 0; x < 3; ++x) {
-                        Q[x] = (exps[c] * C[x] + exps[d] * D[x]) / q;
+                        Q[x] = (eC[c] * C[x] + eD[d] * D[x]) / q;
                         pq2 += (P[x] - Q[x]) * (P[x] - Q[x]);
                     }
                     double rho = p * q / (p + q);
@@ -188,13 +232,33 @@ static void eri_grad(const double *A, const double *B, const double *C, const do
                     double f0 = hfo_boys0(T), f1 = hfo_boys1(T);
                     for (int x = 0; x < 3; ++x) {
                         double pqx = P[x] - Q[x];
-                        gA[x] += E * (-2.0 * muab * (A[x] - B[x]) * f0 - 2.0 * rho * (exps[a] / p) * pqx * f1);
-                        gB[x] += E * (+2.0 * muab * (A[x] - B[x]) * f0 - 2.0 * rho * (exps[b] / p) * pqx * f1);
-                        gC[x] += E * (-2.0 * mucd * (C[x] - D[x]) * f0 + 2.0 * rho * (exps[c] / q) * pqx * f1);
-                        gD[x] += E * (+2.0 * mucd * (C[x] - D[x]) * f0 + 2.0 * rho * (exps[d] / q) * pqx * f1);
+                        gA[x] += E * (-2.0 * muab * (A[x] - B[x]) * f0 - 2.0 * rho * (eA[a] / p) * pqx * f1);
+                        gB[x] += E * (+2.0 * muab * (A[x] - B[x]) * f0 - 2.0 * rho * (eB[b] / p) * pqx * f1);
+                        gC[x] += E * (-2.0 * mucd * (C[x] - D[x]) * f0 + 2.0 * rho * (eC[c] / q) * pqx * f1);
+                        gD[x] += E * (+2.0 * mucd * (C[x] - D[x]) * f0 + 2.0 * rho * (eD[d] / q) * pqx * f1);
                     }
                 }
         }
+}
+
+/* (ij|kl) of atoms i, j, k, l under a basis description with weights W (atom_weights). */
+static double eri_atoms(const double *xyz, int g, const double *exps, const double *W, int64_t astride,
+                        int64_t i, int64_t j, int64_t k, int64_t l)
+{
+    const int64_t s = astride, sw = astride ? g : 0;
+    return eri_core(xyz + 3 * i, xyz + 3 * j, xyz + 3 * k, xyz + 3 * l, g,
+                    exps + i * s, W + i * sw, exps + j * s, W + j * sw,
+                    exps + k * s, W + k * sw, exps + l * s, W + l * sw);
+}
+
+static void eri_grad_atoms(const double *xyz, int g, const double *exps, const double *W, int64_t astride,
+                           int64_t i, int64_t j, int64_t k, int64_t l, double gamma, double *grad)
+{
+    const int64_t s = astride, sw = astride ? g : 0;
+    eri_grad(xyz + 3 * i, xyz + 3 * j, xyz + 3 * k, xyz + 3 * l, g,
+             exps + i * s, W + i * sw, exps + j * s, W + j * sw,
+             exps + k * s, W + k * sw, exps + l * s, W + l * sw, gamma,
+             grad + 3 * i, grad + 3 * j, grad + 3 * k, grad + 3 * l);
 }
 
 /* ---------------------------------------------------------------- Schwarz */
@@ -206,18 +270,32 @@ static inline int64_t pidx(int64_t i, int64_t j)
 }
 
 /* Q[ij] = sqrt((ij|ij)) for every pair i >= j, at index i(i+1)/2 + j. */
-void hfo_schwarz(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
-                 int nthreads, double *Q)
+static int schwarz_s(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                     int64_t astride, int nthreads, double *Q)
 {
+    double *W = atom_weights(n, g, exps, coefs, astride);
+    if (!W) return -1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 16)
 #endif
     for (int64_t i = 0; i < n; ++i)
-        for (int64_t j = 0; j <= i; ++j) {
-            const double *A = xyz + 3 * i, *B = xyz + 3 * j;
-            Q[pidx(i, j)] = sqrt(hfo_eri(A, B, A, B, g, exps, coefs));
-        }
+        for (int64_t j = 0; j <= i; ++j) Q[pidx(i, j)] = sqrt(eri_atoms(xyz, g, exps, W, astride, i, j, i, j));
+    free(W);
+    return 0;
+}
+
+void hfo_schwarz(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                 int nthreads, double *Q)
+{
+    (void)schwarz_s(n, xyz, g, exps, coefs, 0, nthreads, Q);
+}
+
+/* Per-atom bases: exps and coefs hold g values per atom (n * g). */
+int hfo_schwarz_atoms(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                      int nthreads, double *Q)
+{
+    return schwarz_s(n, xyz, g, exps, coefs, g, nthreads, Q);
 }
 
 static double quartet_deg(int64_t i, int64_t j, int64_t k, int64_t l, int64_t ij, int64_t kl)
@@ -229,29 +307,47 @@ static double quartet_deg(int64_t i, int64_t j, int64_t k, int64_t l, int64_t ij
     return deg;
 }
 
+/* Q from the caller, or computed (*own set when the caller must free it); NULL when out of memory. */
+static double *schwarz_or(const double *Qin, int64_t n, const double *xyz, int g, const double *exps,
+                          const double *coefs, int64_t astride, int nthreads, int *own)
+{
+    *own = 0;
+    if (Qin) return (double *)Qin;
+    double *Q = (double *)malloc(sizeof(double) * (size_t)(n * (n + 1) / 2));
+    if (!Q) return NULL;
+    if (schwarz_s(n, xyz, g, exps, coefs, astride, nthreads, Q) != 0) { free(Q); return NULL; }
+    *own = 1;
+    return Q;
+}
+
+/* (i, j) of every canonical pair index i(i+1)/2 + j. */
+static int64_t *pair_list(int64_t n)
+{
+    const int64_t npair = n * (n + 1) / 2;
+    int64_t *pi = (int64_t *)malloc(sizeof(int64_t) * (size_t)npair * 2);
+    if (!pi) return NULL;
+    for (int64_t i = 0, p = 0; i < n; ++i)
+        for (int64_t j = 0; j <= i; ++j, ++p) { pi[2 * p] = i; pi[2 * p + 1] = j; }
+    return pi;
+}
+
 /* ---------------------------------------------------------------- Fock build */
 
 /* Unique-quartet build over bra pairs with canonical index in [bra_begin, bra_end)
  * (the whole build when the range is [0, n(n+1)/2)).  F (n*n) receives G, e2 receives
  * E2 computed from that G, nsurv the number of quartets kept.  Q may be NULL (computed
  * here) or the array from hfo_schwarz.  Returns 0, or -1 when memory runs out. */
-int hfo_fock(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
-             const double *dens, double tau, const double *Qin, int nthreads,
-             int64_t bra_begin, int64_t bra_end, double *F, double *e2, int64_t *nsurv)
+static int fock_s(int64_t n, const double *xyz, int g, const double *exps, const double *coefs, int64_t astride,
+                  const double *dens, double tau, const double *Qin, int nthreads,
+                  int64_t bra_begin, int64_t bra_end, double *F, double *e2, int64_t *nsurv)
 {
     const int64_t npair = n * (n + 1) / 2;
-    double *Q = (double *)Qin;
     int ownQ = 0;
-    if (!Q) {
-        Q = (double *)malloc(sizeof(double) * (size_t)npair);
-        if (!Q) return -1;
-        hfo_schwarz(n, xyz, g, exps, coefs, nthreads, Q);
-        ownQ = 1;
-    }
-    int64_t *pi = (int64_t *)malloc(sizeof(int64_t) * (size_t)npair * 2);
-    if (!pi) { if (ownQ) free(Q); return -1; }
-    for (int64_t i = 0, p = 0; i < n; ++i)
-        for (int64_t j = 0; j <= i; ++j, ++p) { pi[2 * p] = i; pi[2 * p + 1] = j; }
+    double *Q = schwarz_or(Qin, n, xyz, g, exps, coefs, astride, nthreads, &ownQ);
+    if (!Q) return -1;
+    int64_t *pi = pair_list(n);
+    double *W = atom_weights(n, g, exps, coefs, astride);
+    if (!pi || !W) { free(pi); free(W); if (ownQ) free(Q); return -1; }
     if (bra_begin < 0) bra_begin = 0;
     if (bra_end > npair) bra_end = npair;
 
@@ -278,7 +374,7 @@ int hfo_fock(int64_t n, const double *xyz, int g, const double *exps, const doub
                 for (int64_t kl = 0; kl <= ij; ++kl) {
                     if (Q[ij] * Q[kl] < tau) continue;
                     const int64_t k = pi[2 * kl], l = pi[2 * kl + 1];
-                    double eri = hfo_eri(xyz + 3 * i, xyz + 3 * j, xyz + 3 * k, xyz + 3 * l, g, exps, coefs);
+                    double eri = eri_atoms(xyz, g, exps, W, astride, i, j, k, l);
                     double v = eri * quartet_deg(i, j, k, l, ij, kl);
                     Fp[i * n + j] += 4.0 * dens[k * n + l] * v;
                     Fp[k * n + l] += 4.0 * dens[i * n + j] * v;
@@ -297,6 +393,7 @@ int hfo_fock(int64_t n, const double *xyz, int g, const double *exps, const doub
         }
     }
     free(pi);
+    free(W);
     if (ownQ) free(Q);
     if (failed) return -1;
     /* G = (F + F^T) / 2 and E2 = 1/2 sum D o G */
@@ -313,13 +410,29 @@ int hfo_fock(int64_t n, const double *xyz, int g, const double *exps, const doub
     return 0;
 }
 
+int hfo_fock(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+             const double *dens, double tau, const double *Qin, int nthreads,
+             int64_t bra_begin, int64_t bra_end, double *F, double *e2, int64_t *nsurv)
+{
+    return fock_s(n, xyz, g, exps, coefs, 0, dens, tau, Qin, nthreads, bra_begin, bra_end, F, e2, nsurv);
+}
+
+int hfo_fock_atoms(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                   const double *dens, double tau, const double *Qin, int nthreads,
+                   int64_t bra_begin, int64_t bra_end, double *F, double *e2, int64_t *nsurv)
+{
+    return fock_s(n, xyz, g, exps, coefs, g, dens, tau, Qin, nthreads, bra_begin, bra_end, F, e2, nsurv);
+}
+
 /* One element of G straight from the plain definition:
  *   G_ij = sum_kl D_kl [ s(ij,kl) (ij|kl) - 1/2 s(ik,jl) (ik|jl) ].
- * Q is the array from hfo_schwarz. */
-double hfo_fock_element(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
-                        const double *dens, double tau, const double *Q, int nthreads,
-                        int64_t i, int64_t j)
+ * Q is the array from hfo_schwarz.  Returns NAN when out of memory. */
+static double fock_element_s(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                             int64_t astride, const double *dens, double tau, const double *Q, int nthreads,
+                             int64_t i, int64_t j)
 {
+    double *W = atom_weights(n, g, exps, coefs, astride);
+    if (!W) return NAN;
     double acc = 0.0;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -327,27 +440,41 @@ double hfo_fock_element(int64_t n, const double *xyz, int g, const double *exps,
 #endif
     for (int64_t k = 0; k < n; ++k)
         for (int64_t l = 0; l < n; ++l) {
-            const double *A = xyz + 3 * i, *B = xyz + 3 * j, *C = xyz + 3 * k, *D = xyz + 3 * l;
             if (Q[pidx(i, j)] * Q[pidx(k, l)] >= tau)
-                acc += dens[k * n + l] * hfo_eri(A, B, C, D, g, exps, coefs);
+                acc += dens[k * n + l] * eri_atoms(xyz, g, exps, W, astride, i, j, k, l);
             if (Q[pidx(i, k)] * Q[pidx(j, l)] >= tau)
-                acc -= 0.5 * dens[k * n + l] * hfo_eri(A, C, B, D, g, exps, coefs);
+                acc -= 0.5 * dens[k * n + l] * eri_atoms(xyz, g, exps, W, astride, i, k, j, l);
         }
+    free(W);
     return acc;
 }
 
+double hfo_fock_element(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                        const double *dens, double tau, const double *Q, int nthreads,
+                        int64_t i, int64_t j)
+{
+    return fock_element_s(n, xyz, g, exps, coefs, 0, dens, tau, Q, nthreads, i, j);
+}
+
+double hfo_fock_element_atoms(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                              const double *dens, double tau, const double *Q, int nthreads,
+                              int64_t i, int64_t j)
+{
+    return fock_element_s(n, xyz, g, exps, coefs, g, dens, tau, Q, nthreads, i, j);
+}
+
 /* Every element of G from the plain definition (O(n^4) integrals; for tiny n). */
-int hfo_fock_bruteforce(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
-                        const double *dens, double tau, double *F, double *e2)
+static int fock_bruteforce_s(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                             int64_t astride, const double *dens, double tau, double *F, double *e2)
 {
     const int64_t npair = n * (n + 1) / 2;
     double *Q = (double *)malloc(sizeof(double) * (size_t)npair);
     if (!Q) return -1;
-    hfo_schwarz(n, xyz, g, exps, coefs, 1, Q);
+    if (schwarz_s(n, xyz, g, exps, coefs, astride, 1, Q) != 0) { free(Q); return -1; }
     double e = 0.0;
     for (int64_t i = 0; i < n; ++i)
         for (int64_t j = 0; j < n; ++j) {
-            F[i * n + j] = hfo_fock_element(n, xyz, g, exps, coefs, dens, tau, Q, 1, i, j);
+            F[i * n + j] = fock_element_s(n, xyz, g, exps, coefs, astride, dens, tau, Q, 1, i, j);
         }
     for (int64_t x = 0; x < n * n; ++x) e += dens[x] * F[x];
     *e2 = 0.5 * e;
@@ -355,27 +482,31 @@ int hfo_fock_bruteforce(int64_t n, const double *xyz, int g, const double *exps,
     return 0;
 }
 
+int hfo_fock_bruteforce(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                        const double *dens, double tau, double *F, double *e2)
+{
+    return fock_bruteforce_s(n, xyz, g, exps, coefs, 0, dens, tau, F, e2);
+}
+
+int hfo_fock_bruteforce_atoms(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                              const double *dens, double tau, double *F, double *e2)
+{
+    return fock_bruteforce_s(n, xyz, g, exps, coefs, g, dens, tau, F, e2);
+}
+
 /* dE2/dR (n*3) over the unique quartets kept by the screen, also returning E2 and the
  * number of quartets kept.  Returns 0, or -1 when memory runs out. */
-int hfo_grad(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
-             const double *dens, double tau, const double *Qin, int nthreads,
-             double *grad, double *e2, int64_t *nsurv)
+static int grad_s(int64_t n, const double *xyz, int g, const double *exps, const double *coefs, int64_t astride,
+                  const double *dens, double tau, const double *Qin, int nthreads,
+                  double *grad, double *e2, int64_t *nsurv)
 {
     const int64_t npair = n * (n + 1) / 2;
-    double *Q = (double *)Qin;
     int ownQ = 0;
-    if (!Q) {
-        Q = (double *)malloc(sizeof(double) * (size_t)npair);
-        if (!Q) return -1;
-        hfo_schwarz(n, xyz, g, exps, coefs, nthreads, Q);
-        ownQ = 1;
-    }
-    int64_t *pi = (int64_t *)malloc(sizeof(int64_t) * (size_t)npair * 2);
-    if (!pi) { if (ownQ) free(Q); return -1; }
-    for (int64_t i = 0, p = 0; i < n; ++i)
-        for (int64_t j = 0; j <= i; ++j, ++p) { pi[2 * p] = i; pi[2 * p + 1] = j; }
-    double w[16];
-    prim_weights(g, exps, coefs, w);
+    double *Q = schwarz_or(Qin, n, xyz, g, exps, coefs, astride, nthreads, &ownQ);
+    if (!Q) return -1;
+    int64_t *pi = pair_list(n);
+    double *W = atom_weights(n, g, exps, coefs, astride);
+    if (!pi || !W) { free(pi); free(W); if (ownQ) free(Q); return -1; }
     memset(grad, 0, sizeof(double) * (size_t)(3 * n));
     double energy = 0.0;
     int64_t count = 0;
@@ -403,9 +534,8 @@ int hfo_grad(int64_t n, const double *xyz, int g, const double *exps, const doub
                     double gam = quartet_deg(i, j, k, l, ij, kl) *
                                  (4.0 * dens[i * n + j] * dens[k * n + l] - dens[i * n + k] * dens[j * n + l] -
                                   dens[i * n + l] * dens[j * n + k]);
-                    const double *A = xyz + 3 * i, *B = xyz + 3 * j, *C = xyz + 3 * k, *D = xyz + 3 * l;
-                    energy += gam * hfo_eri(A, B, C, D, g, exps, coefs);
-                    eri_grad(A, B, C, D, g, exps, w, gam, gp + 3 * i, gp + 3 * j, gp + 3 * k, gp + 3 * l);
+                    energy += gam * eri_atoms(xyz, g, exps, W, astride, i, j, k, l);
+                    eri_grad_atoms(xyz, g, exps, W, astride, i, j, k, l, gam, gp);
                     ++count;
                 }
             }
@@ -417,11 +547,26 @@ int hfo_grad(int64_t n, const double *xyz, int g, const double *exps, const doub
         }
     }
     free(pi);
+    free(W);
     if (ownQ) free(Q);
     if (failed) return -1;
     if (e2) *e2 = energy;
     if (nsurv) *nsurv = count;
     return 0;
+}
+
+int hfo_grad(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+             const double *dens, double tau, const double *Qin, int nthreads,
+             double *grad, double *e2, int64_t *nsurv)
+{
+    return grad_s(n, xyz, g, exps, coefs, 0, dens, tau, Qin, nthreads, grad, e2, nsurv);
+}
+
+int hfo_grad_atoms(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                   const double *dens, double tau, const double *Qin, int nthreads,
+                   double *grad, double *e2, int64_t *nsurv)
+{
+    return grad_s(n, xyz, g, exps, coefs, g, dens, tau, Qin, nthreads, grad, e2, nsurv);
 }
 
 /* Gradient of the pairing L = sum_ij W_ij G_ij(R) of a fixed matrix W with the forward's G,
@@ -435,20 +580,12 @@ int hfo_grad_pair(int64_t n, const double *xyz, int g, const double *exps, const
                   double *grad)
 {
     const int64_t npair = n * (n + 1) / 2;
-    double *Q = (double *)Qin;
     int ownQ = 0;
-    if (!Q) {
-        Q = (double *)malloc(sizeof(double) * (size_t)npair);
-        if (!Q) return -1;
-        hfo_schwarz(n, xyz, g, exps, coefs, nthreads, Q);
-        ownQ = 1;
-    }
-    int64_t *pi = (int64_t *)malloc(sizeof(int64_t) * (size_t)npair * 2);
-    if (!pi) { if (ownQ) free(Q); return -1; }
-    for (int64_t i = 0, p = 0; i < n; ++i)
-        for (int64_t j = 0; j <= i; ++j, ++p) { pi[2 * p] = i; pi[2 * p + 1] = j; }
-    double w[16];
-    prim_weights(g, exps, coefs, w);
+    double *Q = schwarz_or(Qin, n, xyz, g, exps, coefs, 0, nthreads, &ownQ);
+    if (!Q) return -1;
+    int64_t *pi = pair_list(n);
+    double *W = atom_weights(n, g, exps, coefs, 0);
+    if (!pi || !W) { free(pi); free(W); if (ownQ) free(Q); return -1; }
     memset(grad, 0, sizeof(double) * (size_t)(3 * n));
     int failed = 0;
 #ifdef _OPENMP
@@ -476,8 +613,7 @@ int hfo_grad_pair(int64_t n, const double *xyz, int g, const double *exps, const
                                      (4.0 * (X[i * n + j] * D[k * n + l] + D[i * n + j] * X[k * n + l]) -
                                       (X[i * n + k] * D[j * n + l] + D[i * n + k] * X[j * n + l]) -
                                       (X[i * n + l] * D[j * n + k] + D[i * n + l] * X[j * n + k]));
-                    const double *A = xyz + 3 * i, *B = xyz + 3 * j, *C = xyz + 3 * k, *E = xyz + 3 * l;
-                    eri_grad(A, B, C, E, g, exps, w, b, gp + 3 * i, gp + 3 * j, gp + 3 * k, gp + 3 * l);
+                    eri_grad_atoms(xyz, g, exps, W, 0, i, j, k, l, b, gp);
                 }
             }
 #ifdef _OPENMP
@@ -488,6 +624,7 @@ int hfo_grad_pair(int64_t n, const double *xyz, int g, const double *exps, const
         }
     }
     free(pi);
+    free(W);
     if (ownQ) free(Q);
     return failed ? -1 : 0;
 }

@@ -426,3 +426,177 @@ def test_he512_fixture_elements_match_element_definition(oracle_lib):
     for i, j, v in rows[:8]:
         e = oracle_lib.fock_element(s.xyz, s.dens, E3, C3, s.tau, Q, int(i), int(j))
         assert abs(e - v) <= 1e-12 * scale, (i, j)
+
+
+# ------------------------------------------------------------------ per-atom bases
+
+from he_inputs import H_STO3G_EXPS as EH, random_basis_rows  # noqa: E402
+
+
+@pytest.mark.parametrize("R", [0.0, 1e-4, 0.7, 2.0, 6.0])
+@pytest.mark.parametrize("a,b", [(0.4, 2.5), (3.0, 0.15)])
+def test_eri4_two_gaussian_charges_unequal(oracle_lib, R, a, b):
+    """One normalised primitive on A (exponent a) and one on B (exponent b): g_a^2 and g_b^2 are
+    unit Gaussian charges of exponents 2a and 2b, interacting as erf(sqrt(r) R) / R with the
+    reduced exponent r = (2a)(2b)/(2a + 2b), and 2 sqrt(r/pi) at R = 0."""
+    A = np.array([0.2, -0.1, 0.3])
+    d = np.array([0.3, 1.0, -0.7])
+    B = A + R * d / np.linalg.norm(d)
+    r = 4.0 * a * b / (2.0 * a + 2.0 * b)
+    ref = 2.0 * math.sqrt(r / math.pi) if R == 0 else erf(math.sqrt(r) * R) / R
+    ba, bb = ([a], [1.0]), ([b], [1.0])
+    assert oracle_lib.eri4(A, A, B, B, ba, ba, bb, bb) == pytest.approx(ref, rel=1e-13, abs=1e-15)
+    # the same pair of charges seen from the other side
+    assert oracle_lib.eri4(B, B, A, A, bb, bb, ba, ba) == pytest.approx(ref, rel=1e-13, abs=1e-15)
+
+
+def test_eri4_scaling_law(oracle_lib):
+    """Exponents times l^2 and lengths divided by l map each normalised function to
+    l^(3/2) phi(l r); the Coulomb integral then scales by l."""
+    rng = np.random.default_rng(17)
+    X = rng.uniform(-2, 2, (4, 3))
+    e, c = random_basis_rows(4, 3, 18)
+    basis = [(e[k], c[k]) for k in range(4)]
+    ref = oracle_lib.eri4(*X, *basis)
+    for lam in (0.5, 1.7, 3.0):
+        scaled = [(e[k] * lam * lam, c[k]) for k in range(4)]
+        got = oracle_lib.eri4(*(X / lam), *scaled)
+        assert got == pytest.approx(lam * ref, rel=1e-13)
+
+
+def test_eri4_eightfold_symmetry(oracle_lib):
+    """Permuting the centres together with their own contractions leaves (ij|kl) unchanged;
+    swapping only the contractions of two centres changes it."""
+    rng = np.random.default_rng(19)
+    A, B, C, D = rng.uniform(-2, 2, (4, 3))
+    e, c = random_basis_rows(4, 3, 20)
+    a, b, cc, d = [(e[k], c[k]) for k in range(4)]
+    ref = oracle_lib.eri4(A, B, C, D, a, b, cc, d)
+    for pts, bs in [((B, A, C, D), (b, a, cc, d)), ((A, B, D, C), (a, b, d, cc)), ((C, D, A, B), (cc, d, a, b)),
+                    ((D, C, B, A), (d, cc, b, a)), ((B, A, D, C), (b, a, d, cc)), ((C, D, B, A), (cc, d, b, a)),
+                    ((D, C, A, B), (d, cc, a, b))]:
+        assert oracle_lib.eri4(*pts, *bs) == pytest.approx(ref, rel=1e-14)
+    assert abs(oracle_lib.eri4(A, B, C, D, b, a, cc, d) - ref) > 1e-6 * abs(ref)
+
+
+def test_eri4_gaussian_charge_form(oracle_lib):
+    """Each primitive (ab|cd) with its own exponents on every centre is S_ab S_cd erf(sqrt(rho)
+    |P-Q|) / |P-Q|: two spherical Gaussian charges of exponents p and q at the product centres."""
+    rng = np.random.default_rng(23)
+    e, c = random_basis_rows(4, 2, 24)
+    w = c * (2 * e / math.pi) ** 0.75
+    X = rng.uniform(-1.5, 1.5, (4, 3))
+    ref = 0.0
+    for a in range(2):
+        for b in range(2):
+            p = e[0, a] + e[1, b]
+            P = (e[0, a] * X[0] + e[1, b] * X[1]) / p
+            sab = w[0, a] * w[1, b] * (math.pi / p) ** 1.5 * math.exp(-e[0, a] * e[1, b] / p * np.sum((X[0] - X[1]) ** 2))
+            for cc in range(2):
+                for d in range(2):
+                    q = e[2, cc] + e[3, d]
+                    Q = (e[2, cc] * X[2] + e[3, d] * X[3]) / q
+                    scd = w[2, cc] * w[3, d] * (math.pi / q) ** 1.5 * math.exp(-e[2, cc] * e[3, d] / q * np.sum((X[2] - X[3]) ** 2))
+                    rho = p * q / (p + q)
+                    r = np.linalg.norm(P - Q)
+                    ref += sab * scd * erf(math.sqrt(rho) * r) / r
+    got = oracle_lib.eri4(*X, *[(e[k], c[k]) for k in range(4)])
+    assert got == pytest.approx(ref, rel=1e-13)
+
+
+def _rows_cluster(n, seed, box, g=3):
+    s = random_cluster(n, seed, box=box)
+    e, c = random_basis_rows(n, g, seed + 100)
+    return s, e, c
+
+
+@pytest.mark.parametrize("n,seed,box,tau", [(1, 1, 1.0, 0.0), (2, 2, 3.0, 0.0), (4, 3, 4.0, 0.0),
+                                            (5, 4, 5.0, 0.0), (6, 5, 9.0, 1e-4), (6, 6, 12.0, 1e-6)])
+def test_fock_atoms_equals_plain_definition(oracle_lib, n, seed, box, tau):
+    s, e, c = _rows_cluster(n, seed, box)
+    Fb, Eb = oracle_lib.fock_bruteforce_atoms(s.xyz, s.dens, e, c, tau)
+    Fu, Eu, ns = oracle_lib.fock_atoms(s.xyz, s.dens, e, c, tau)
+    assert np.abs(Fu - Fb).max() <= 1e-14 * np.abs(Fb).max()
+    assert Eu == pytest.approx(Eb, rel=1e-14)
+    assert np.array_equal(Fu, Fu.T)
+    P = n * (n + 1) // 2
+    Q = oracle_lib.schwarz_atoms(s.xyz, e, c)
+    assert ns == sum(1 for a in range(P) for b in range(a + 1) if Q[a] * Q[b] >= tau)
+
+
+def test_schwarz_atoms_bounds_all_quartets(oracle_lib):
+    s, e, c = _rows_cluster(4, 31, 4.0)
+    Q = oracle_lib.schwarz_atoms(s.xyz, e, c)
+    b = [(e[k], c[k]) for k in range(4)]
+
+    def q(i, j):
+        i, j = max(i, j), min(i, j)
+        return Q[i * (i + 1) // 2 + j]
+    for i in range(4):
+        for j in range(4):
+            assert q(i, j) ** 2 == pytest.approx(oracle_lib.eri4(s.xyz[i], s.xyz[j], s.xyz[i], s.xyz[j],
+                                                                 b[i], b[j], b[i], b[j]), rel=1e-14)
+            for k in range(4):
+                for l in range(4):
+                    v = oracle_lib.eri4(s.xyz[i], s.xyz[j], s.xyz[k], s.xyz[l], b[i], b[j], b[k], b[l])
+                    assert abs(v) <= q(i, j) * q(k, l) * (1 + 1e-13)
+
+
+def test_fock_atoms_with_identical_rows_is_the_one_basis_build(oracle_lib):
+    s = random_cluster(7, 41, box=6.0)
+    e = np.tile(E3, (7, 1))
+    c = np.tile(C3, (7, 1))
+    Fa, Ea, na = oracle_lib.fock_atoms(s.xyz, s.dens, e, c, 1e-8, nthreads=1)
+    Fu, Eu, nu = oracle_lib.fock(s.xyz, s.dens, E3, C3, 1e-8, nthreads=1)
+    assert np.array_equal(Fa, Fu) and Ea == Eu and na == nu
+
+
+def test_fock_atoms_permutation_equivariance(oracle_lib):
+    """Relabelling the atoms, each keeping its own contraction, permutes G and keeps E2."""
+    s, e, c = _rows_cluster(6, 43, 6.0)
+    perm = np.array([3, 0, 5, 1, 4, 2])
+    F, E, _ = oracle_lib.fock_atoms(s.xyz, s.dens, e, c, 0.0)
+    Fp, Ep, _ = oracle_lib.fock_atoms(s.xyz[perm], s.dens[np.ix_(perm, perm)], e[perm], c[perm], 0.0)
+    assert np.abs(Fp - F[np.ix_(perm, perm)]).max() <= 1e-14 * np.abs(F).max()
+    assert Ep == pytest.approx(E, rel=1e-14)
+    # attaching the contractions to the wrong atoms changes the result
+    Fw, _, _ = oracle_lib.fock_atoms(s.xyz, s.dens, e[perm], c[perm], 0.0)
+    assert np.abs(Fw - F).max() > 1e-3 * np.abs(F).max()
+
+
+def test_fock_atoms_h_and_he_far_apart(oracle_lib):
+    """H at the origin and He 40 bohr away: on-site halves of each atom's own (ii|ii), Coulomb
+    between them as point charges S_HH S_HeHe / R, and the exchange of the screened pair."""
+    R = 40.0
+    xyz = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, R]])
+    D = np.array([[0.9, 0.2], [0.2, 1.1]])
+    e = np.stack([EH, E3])
+    c = np.stack([C3, C3])
+    F, _, _ = oracle_lib.fock_atoms(xyz, D, e, c, 1e-12)
+    jh = oracle_lib.eri(xyz[0], xyz[0], xyz[0], xyz[0], EH, C3)
+    jhe = oracle_lib.eri(xyz[1], xyz[1], xyz[1], xyz[1], E3, C3)
+    sh = oracle_lib.overlap(xyz[0], xyz[0], EH, C3)
+    she = oracle_lib.overlap(xyz[1], xyz[1], E3, C3)
+    jab = sh * she / R
+    assert F[0, 0] == pytest.approx(0.5 * D[0, 0] * jh + D[1, 1] * jab, rel=1e-13)
+    assert F[1, 1] == pytest.approx(0.5 * D[1, 1] * jhe + D[0, 0] * jab, rel=1e-13)
+    assert F[0, 1] == pytest.approx(-0.5 * D[1, 0] * jab, rel=1e-12)
+    # hydrogen is the more diffuse atom: its on-site repulsion is the smaller one
+    assert jh < jhe
+
+
+def test_grad_atoms_vs_finite_differences(oracle_lib):
+    s, e, c = _rows_cluster(4, 47, 3.5)
+    g, E, _ = oracle_lib.grad_atoms(s.xyz, s.dens, e, c, 0.0)
+    _, E2, _ = oracle_lib.fock_atoms(s.xyz, s.dens, e, c, 0.0)
+    assert E == pytest.approx(E2, rel=1e-13)
+    h = 1e-4
+    fd = np.zeros_like(g)
+    for a in range(4):
+        for x in range(3):
+            xp = s.xyz.copy(); xp[a, x] += h
+            xm = s.xyz.copy(); xm[a, x] -= h
+            fd[a, x] = (oracle_lib.fock_atoms(xp, s.dens, e, c, 0.0)[1] -
+                        oracle_lib.fock_atoms(xm, s.dens, e, c, 0.0)[1]) / (2 * h)
+    assert np.abs(g - fd).max() <= 1e-7 * max(1.0, np.abs(g).max())
+    assert np.abs(g.sum(axis=0)).max() <= 1e-12 * np.abs(g).max()
