@@ -155,3 +155,17 @@ def random_basis_rows(n: int, g: int, seed: int):
     exps = np.exp(rng.uniform(math.log(0.1), math.log(10.0), size=(n, g)))
     coefs = rng.uniform(0.1, 1.0, size=(n, g))
     return exps, coefs
+
+
+# A tight contraction whose Schwarz bounds reach above 2 (one-centre Q about 2.09), for the
+# case of a bra pair whose threshold tau / Q_s lies above every bound below 2.
+TIGHT_EXPS = np.array([40.0, 4.0, 0.6], dtype=np.float64)
+TIGHT_COEFS = np.array([0.5, 0.5, 0.5], dtype=np.float64)
+
+
+def tight_cluster() -> System:
+    """60 atoms in a 10 bohr box with the tight contraction above and tau = 1e-3."""
+    s = random_cluster(60, 2, box=10.0, tau=1e-3)
+    s.exps = TIGHT_EXPS.copy()
+    s.coefs = TIGHT_COEFS.copy()
+    return s

@@ -137,6 +137,29 @@ hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss,
                          double *d_xyz, double *d_dens, double *e2_out,
                          void *workspace, size_t workspace_bytes, void *stream);
 
+/* Per-atom bases: every atom carries a contracted s function of its own (all with ngauss
+ * primitives), for instance hydrogen and helium in one system.  The integrals are those of
+ * hfk_fock with each centre's own exponents and weights: the Gaussian product and the
+ * primitive integral of the Background section hold for any exponent on any centre, and
+ * one basis on every atom (the kernel listing) is the case of identical rows.
+ * Workspace size for hfk_fock_atoms; arguments and errors as hfk_workspace_bytes. */
+hfk_status hfk_workspace_bytes_atoms(int64_t natoms, int32_t ngauss, int32_t precision, size_t *bytes_out);
+
+/* Forward Fock build with per-atom bases.  Arguments, outputs and errors as hfk_fock except
+ *   exps_host    [natoms*ngauss] row i: the exponents of atom i, each > 0 and finite (host)
+ *   coefs_host   [natoms*ngauss] row i: the contraction coefficients of atom i, finite (host)
+ *   workspace    at least hfk_workspace_bytes_atoms(...) bytes
+ * Every row is validated on the host before any device work (HFK_EINVAL names the atom).
+ * The rows are copied into the workspace before the call returns, so the host arrays may be
+ * reused at once.  Only the hybrid form of the quartet kernel is built for this call
+ * (hfk_set_config's variant does not apply); strategy and workgroups per CU follow
+ * hfk_fock. */
+hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss,
+                          const double *exps_host, const double *coefs_host,
+                          const double *dens, double tau, int32_t precision, int32_t strategy,
+                          double *fock, double *e2,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
 /* Workspace size for hfk_fock_batched over `nmol` molecules whose atom ranges are
  * atom_off_host[m] .. atom_off_host[m+1] (CSR, host memory, nondecreasing, starting at 0).
  * with_grad != 0 adds the gradient accumulators. */

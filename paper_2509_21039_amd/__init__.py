@@ -70,6 +70,9 @@ _SIGNATURES = {
     "hfk_profile_enable": [ctypes.c_int32],
     "hfk_set_config": [ctypes.c_int32, ctypes.c_int32],
     "hfk_profile_read": [ctypes.POINTER(ctypes.c_double), _i64p],
+    "hfk_workspace_bytes_atoms": [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_sz)],
+    "hfk_fock_atoms": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
+                       ctypes.c_int32, _vp, _vp, _vp, _sz, _vp],
 }
 
 
@@ -168,6 +171,39 @@ def fock(xyz, dens, exps: Sequence[float], coefs: Sequence[float], tau: float, p
     _check(lib().hfk_fock(n, xyz.data_ptr(), len(e), _dptr(e), _dptr(c), dens.data_ptr(), float(tau), prec,
                           int(strategy), F.data_ptr(), E2.data_ptr(), workspace.data_ptr(),
                           workspace.numel(), _stream_handle(stream)))
+    return F, E2
+
+
+def workspace_bytes_atoms(natoms: int, ngauss: int = 3, precision="fp64") -> int:
+    out = _sz(0)
+    _check(lib().hfk_workspace_bytes_atoms(int(natoms), int(ngauss), _PREC[precision], ctypes.byref(out)))
+    return out.value
+
+
+def fock_atoms(xyz, dens, exps, coefs, tau: float, precision="fp64", strategy: int = STRATEGY_AUTO,
+               workspace=None, out=None, stream=None):
+    """G and E2 with per-atom bases: exps and coefs are (natoms, ngauss) host arrays, row i the
+    contraction of atom i."""
+    torch = _torch()
+    n = xyz.shape[0]
+    _dev_f64(xyz, "xyz", (n, 3))
+    _dev_f64(dens, "dens", (n, n))
+    e = _host_f64(exps)
+    c = _host_f64(coefs)
+    if e.shape != c.shape or e.ndim != 2 or e.shape[0] != n:
+        raise HfkError(HFK_EINVAL, "per-atom exps and coefs must both be (natoms, ngauss)")
+    g = e.shape[1]
+    prec = _PREC[precision]
+    if workspace is None:
+        workspace = new_workspace(workspace_bytes_atoms(n, g, prec), xyz.device)
+    if out is None:
+        F = torch.empty((n, n), dtype=torch.float64, device=xyz.device)
+        E2 = torch.empty((1,), dtype=torch.float64, device=xyz.device)
+    else:
+        F, E2 = out
+    _check(lib().hfk_fock_atoms(n, xyz.data_ptr(), g, _dptr(e), _dptr(c), dens.data_ptr(), float(tau), prec,
+                                int(strategy), F.data_ptr(), E2.data_ptr(), workspace.data_ptr(),
+                                workspace.numel(), _stream_handle(stream)))
     return F, E2
 
 

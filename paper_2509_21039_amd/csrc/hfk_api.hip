@@ -46,12 +46,13 @@ constexpr double kPrivateBudget = 16.0e9;
 // workgroups share through atomics.
 constexpr double kJcolBudget = 8.0e9;
 
-Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
+Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool atoms)
 {
     (void)prec;
     Layout L;
     memset(&L, 0, sizeof(L));
     L.n = n;
+    L.atoms = atoms;
     L.private_ok = (double)groups * (double)n * (double)n * 8.0 <= kPrivateBudget;
     L.npair = n * (n + 1) / 2;
     L.pcap = ((L.npair + 63) / 64) * 64 + 64;
@@ -78,8 +79,13 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups)
     L.pl = take(sizeof(int) * PC);
     L.pq = take(sizeof(double) * PC);
     L.pd = take(sizeof(double) * PC);
-    L.prim = take(sizeof(double) * 5 * g2 * PC);   // Px, Py, Pz, S, |P|^2
-    L.prim_f = take(sizeof(float) * 4 * g2 * PC);
+    L.prim = take(sizeof(double) * (atoms ? 6 : 5) * g2 * PC);   // Px, Py, Pz, S, |P|^2 (, 1/p)
+    L.prim_f = take(sizeof(float) * (atoms ? 5 : 4) * g2 * PC);
+    if (atoms) {
+        L.arow = take(sizeof(double) * 2 * (size_t)n * (size_t)g);
+        L.bip = take(sizeof(double) * g2 * PC);
+        L.bip_f = take(sizeof(float) * g2 * PC);
+    }
     L.bra = take(sizeof(double) * 8 * g2 * PC);
     L.bra_f = take(sizeof(float) * 8 * g2 * PC);
     L.boys_g = take(sizeof(double) * kBoysGrid * kBoysStride);
@@ -134,6 +140,20 @@ static hfk_status check_common(int64_t natoms, const double *xyz, int32_t ngauss
     if (!isfinite(tau) || tau < 0.0) return fail(HFK_EINVAL, "tau must be finite and >= 0 (got %g)", tau);
     if (precision != HFK_FP64 && precision != HFK_MIXED)
         return fail(HFK_EINVAL, "precision must be HFK_FP64 or HFK_MIXED (got %d)", (int)precision);
+    return HFK_OK;
+}
+
+// Per-atom rows: every exponent finite and > 0, every coefficient finite.
+static hfk_status check_rows(int64_t natoms, int32_t ngauss, const double *exps, const double *coefs)
+{
+    for (int64_t x = 0; x < natoms * ngauss; ++x) {
+        if (!(exps[x] > 0.0) || !isfinite(exps[x]))
+            return fail(HFK_EINVAL, "exps_host[%lld] (atom %lld) must be finite and > 0 (got %g)", (long long)x,
+                        (long long)(x / ngauss), exps[x]);
+        if (!isfinite(coefs[x]))
+            return fail(HFK_EINVAL, "coefs_host[%lld] (atom %lld) is not finite", (long long)x,
+                        (long long)(x / ngauss));
+    }
     return HFK_OK;
 }
 
@@ -325,6 +345,85 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     e = launch_fock(L, b, ws, dens, tau, precision, strat, cfg.variant, fock, e2, st);
     if (e != hipSuccess) return hip_fail(e, "fock launch");
     e = launch_header_info(ws + L.hdr, strat, L.groups, precision, cfg.variant, st);
+    if (e != hipSuccess) return hip_fail(e, "header launch");
+    return HFK_OK;
+}
+
+hfk_status hfk_workspace_bytes_atoms(int64_t natoms, int32_t ngauss, int32_t precision, size_t *bytes_out)
+{
+    g_err[0] = 0;
+    if (!bytes_out) return fail(HFK_EINVAL, "bytes_out is NULL");
+    if (natoms < 1) return fail(HFK_EINVAL, "natoms must be >= 1 (got %lld)", (long long)natoms);
+    if (ngauss < 1 || ngauss > HFK_MAX_NGAUSS)
+        return fail(HFK_EINVAL, "ngauss must be in [1, %d] (got %d)", HFK_MAX_NGAUSS, (int)ngauss);
+    if (precision != HFK_FP64 && precision != HFK_MIXED)
+        return fail(HFK_EINVAL, "precision must be HFK_FP64 or HFK_MIXED (got %d)", (int)precision);
+    if (natoms > kMaxAtoms) return fail(HFK_EUNSUPPORTED, "natoms above %lld", (long long)kMaxAtoms);
+    const Layout L = make_layout(natoms, ngauss, precision, 0, groups_cap(device_cu_count()), true);
+    *bytes_out = L.total;
+    return HFK_OK;
+}
+
+hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
+                          const double *coefs_host, const double *dens, double tau, int32_t precision,
+                          int32_t strategy, double *fock, double *e2, void *workspace, size_t workspace_bytes,
+                          void *stream)
+{
+    g_err[0] = 0;
+    hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision);
+    if (s != HFK_OK) return s;
+    s = check_rows(natoms, ngauss, exps_host, coefs_host);
+    if (s != HFK_OK) return s;
+    if (!fock) return fail(HFK_EINVAL, "fock is NULL");
+    if (!e2) return fail(HFK_EINVAL, "e2 is NULL");
+    if (!workspace) return fail(HFK_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
+    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_ATOMIC)
+        return fail(HFK_EINVAL, "unknown strategy %d", (int)strategy);
+    if (natoms > kMaxAtoms) return fail(HFK_EUNSUPPORTED, "natoms above %lld", (long long)kMaxAtoms);
+    if (ngauss > kMaxBuiltG) return fail(HFK_EUNSUPPORTED, "ngauss above %d is not built in this version", kMaxBuiltG);
+    const int cus = device_cu_count();
+    if (cus <= 0) return fail(HFK_EHIP, "no HIP device");
+    Layout L = make_layout(natoms, ngauss, precision, 0, groups_cap(cus), true);
+    if (workspace_bytes < L.total)
+        return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
+    TunedConfig cfg = pick_config(strategy, precision, natoms, ngauss);
+    cfg.variant = 1;   // per-atom bases run the hybrid form only
+    int strat = cfg.strategy;
+    if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
+    {
+        const int fit = fock_resident_groups(ngauss, precision, 1, natoms, true);
+        L.groups = cus * (fit > 0 && cfg.gpc > fit ? fit : cfg.gpc);
+    }
+    // exponents and weights of every atom, [2][n][g], copied to the workspace (pageable
+    // host memory: the copy completes before hipMemcpyAsync returns)
+    const size_t ng = (size_t)natoms * (size_t)ngauss;
+    std::vector<double> rows(2 * ng);
+    for (size_t x = 0; x < ng; ++x) {
+        rows[x] = exps_host[x];
+        rows[ng + x] = coefs_host[x] * pow(2.0 * exps_host[x] / 3.14159265358979323846, 0.75);
+    }
+    char *ws = (char *)workspace;
+    hipStream_t st = (hipStream_t)stream;
+    double *arow = (double *)(ws + L.arow);
+    hipError_t e = hipMemcpyAsync(arow, rows.data(), sizeof(double) * 2 * ng, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "basis rows copy");
+    Basis b;
+    memset(&b, 0, sizeof(b));
+    b.g = ngauss;
+    b.g2 = ngauss * ngauss;
+    for (int a = 0; a < ngauss; ++a) b.alpha[a] = 1.0;   // the one-basis tables stay finite, unused
+    b.aexp = arow;
+    b.aw = arow + ng;
+    e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (float *)(ws + L.boys_f),
+                     (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz,
+                     st);
+    if (e != hipSuccess) return hip_fail(e, "setup launch");
+    e = launch_pairs(L, b, ws, xyz, dens, tau, st);
+    if (e != hipSuccess) return hip_fail(e, "pair launch");
+    e = launch_fock(L, b, ws, dens, tau, precision, strat, 1, fock, e2, st);
+    if (e != hipSuccess) return hip_fail(e, "fock launch");
+    e = launch_header_info(ws + L.hdr, strat, L.groups, precision, 1, st);
     if (e != hipSuccess) return hip_fail(e, "header launch");
     return HFK_OK;
 }

@@ -223,9 +223,8 @@ __global__ __launch_bounds__(256) void k_b_limits(const DevHeader *__restrict__ 
         long long bend;
         if (thr <= 0.0) {
             bend = boff[(long long)(m + 1) * kNumBands];
-        } else if (thr > 2.0) {
-            bend = start;
         } else {
+            // band 0 is open-ended: a threshold above its edges still ends there
             const int bt = q_band(thr);
             bend = boff[(long long)m * kNumBands + bt + 1];
         }

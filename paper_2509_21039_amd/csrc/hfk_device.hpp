@@ -35,6 +35,27 @@ __device__ inline void pair_prims(const Basis &b, const BasisDev *__restrict__ b
     }
 }
 
+// Per-atom bases: the same for atoms i (at A) and j (at B) with exponents and weights from
+// the atom rows, plus p = alpha_a + alpha_b of every primitive pair (a on i, b on j).
+__device__ inline void pair_prims_atoms(const Basis &b, int64_t i, int64_t j, const double *A, const double *B,
+                                        double *px, double *py, double *pz, double *ps, double *pp)
+{
+    const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
+    const double ab2 = dx * dx + dy * dy + dz * dz;
+    const double *ei = b.aexp + i * b.g, *ej = b.aexp + j * b.g;
+    const double *wi = b.aw + i * b.g, *wj = b.aw + j * b.g;
+    for (int ab = 0; ab < b.g2; ++ab) {
+        const int a = ab / b.g, c = ab % b.g;
+        const double p = ei[a] + ej[c];
+        const double fa = ei[a] / p, fb = ej[c] / p;
+        px[ab] = fa * A[0] + fb * B[0];
+        py[ab] = fa * A[1] + fb * B[1];
+        pz[ab] = fa * A[2] + fb * B[2];
+        ps[ab] = wi[a] * wj[c] * exp(-(ei[a] * ej[c] / p) * ab2) * pow(kPi / p, 1.5);
+        pp[ab] = p;
+    }
+}
+
 // Reciprocal square root in FP64: the hardware estimate (relative error ~5e-8) refined by
 // one Newton step, y (1 + e/2) with e = 1 - x y^2, leaving ~1.5 e^2 ~ 4e-15.
 __device__ inline double rsqrt_fp64(double x)

@@ -39,6 +39,8 @@ struct FockArgs {
     const float *prim_f;
     const double *bra;
     const float *bra_f;
+    const double *bip;          // per-atom bases: [pcap][g2] 1/p of the bra primitive pairs
+    const float *bip_f;
     const long long *item_off;
     const long long *goff;      // [ngroups + 1] block offsets of the bra groups
     int64_t ngroups;
@@ -59,6 +61,7 @@ template <typename R> struct Prec;
 template <> struct Prec<double> {
     static __device__ const double *prim(const FockArgs &a) { return a.prim; }
     static __device__ const double *bra(const FockArgs &a) { return a.bra; }
+    static __device__ const double *bip(const FockArgs &a) { return a.bip; }
     static __device__ const double *boys(const FockArgs &a) { return a.boys; }
     static __device__ const double *rho(const BasisDev *bd) { return bd->rho; }
     static __device__ const double *srho(const BasisDev *bd) { return bd->srho; }
@@ -77,6 +80,7 @@ template <> struct Prec<double> {
 template <> struct Prec<float> {
     static __device__ const float *prim(const FockArgs &a) { return a.prim_f; }
     static __device__ const float *bra(const FockArgs &a) { return a.bra_f; }
+    static __device__ const float *bip(const FockArgs &a) { return a.bip_f; }
     static __device__ const float *boys(const FockArgs &a) { return a.boys_f; }
     static __device__ const float *rho(const BasisDev *bd) { return bd->rho_f; }
     static __device__ const float *srho(const BasisDev *bd) { return bd->srho_f; }
@@ -196,16 +200,22 @@ __device__ inline R boys_grid(R Ts, bool near, const R *__restrict__ tab)
 // FP64 forms |P-Q|^2 as |P|^2 + |Q|^2 - 2 P.Q (4 operations; with centroid-centred
 // coordinates the cancellation stays near 1e-13 bohr^2 absolute); FP32 subtracts the
 // centres directly, which its precision needs.
-template <int G, typename R>
+// Per-atom bases (kAtoms): rho = p q / (p + q) differs per quartet, so the scalar combo
+// table gives way to 1/p of the bra (uniform, bip) and of the ket (last ket component):
+// 1/rho = 1/p + 1/q, the switch test is |P-Q|^2 < kTswitch / rho, and only the near
+// branch needs sqrt(rho / h) (one reciprocal square root of 1/rho); the far field
+// S_cd / |P-Q| does not depend on rho at all.
+template <int G, typename R, bool kAtoms = false>
 __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, int64_t pcap, unsigned t,
-                                       cptr<R> rsn, const R *__restrict__ tab)
+                                       cptr<R> rsn, const R *__restrict__ tab, cptr<R> bip = nullptr)
 {
     constexpr int G2 = G * G;
     constexpr bool kExpand = sizeof(R) == 8;
+    constexpr int kPComp = kExpand ? 5 : 4;   // ket component holding 1/p (per-atom bases)
     R eri = R(0);
 #pragma unroll 1
     for (int cb = 0; cb < G; ++cb) {
-        R kx[G], ky[G], kz[G], ks[G], kq[G];
+        R kx[G], ky[G], kz[G], ks[G], kq[G], kp[G];
         // buffer loads: one resource per component (g2 * pcap values, < 4 GiB), the primitive
         // pair as a scalar offset and the ket as a 32-bit lane offset (no 64-bit address math)
         const unsigned tb = t * (unsigned)sizeof(R);
@@ -226,34 +236,59 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
             kz[d] = ld(2, cd);
             ks[d] = ld(3, cd);
             kq[d] = kExpand ? ld(4, cd) : R(0);
+            kp[d] = kAtoms ? ld(kPComp, cd) : R(0);
         }
 #pragma unroll 1
         for (int ab = 0; ab < G2; ++ab) {
             const cptr<R> bp = bra + 8 * ab;
-            const cptr<R> up = rsn + 3 * (ab * G2 + cb * G);
-            R b[8], u[3 * G];
+            R b[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) b[c] = bp[c];
-#pragma unroll
-            for (int c = 0; c < 3 * G; ++c) u[c] = up[c];
-            // keep every uniform load in one batch at the top (not sunk into the branches)
-#pragma unroll
-            for (int c = 0; c < 3 * G; ++c) asm volatile("" ::"s"(u[c]));
             R acc = R(0);
+            if constexpr (kAtoms) {
+                const R bi = bip[ab];
+                asm volatile("" ::"s"(bi));
 #pragma unroll
-            for (int d = 0; d < G; ++d) {
-                R r2;
-                if (kExpand) {
-                    r2 = fma(b[4], kx[d], fma(b[5], ky[d], fma(b[6], kz[d], kq[d] + b[7])));
-                } else {
-                    const R dx = b[0] - kx[d], dy = b[1] - ky[d], dz = b[2] - kz[d];
-                    r2 = dx * dx + dy * dy + dz * dz;
+                for (int d = 0; d < G; ++d) {
+                    R r2;
+                    if (kExpand) {
+                        r2 = fma(b[4], kx[d], fma(b[5], ky[d], fma(b[6], kz[d], kq[d] + b[7])));
+                    } else {
+                        const R dx = b[0] - kx[d], dy = b[1] - ky[d], dz = b[2] - kz[d];
+                        r2 = dx * dx + dy * dy + dz * dz;
+                    }
+                    const R irho = bi + kp[d];
+                    const bool near = r2 < R(kTswitch) * irho;
+                    if (__builtin_amdgcn_ballot_w64(near)) {
+                        const R y = rsqrt_r(irho) * R(kSqrtInvH);   // sqrt(rho / h)
+                        acc = fma(ks[d] * y, boys_grid<R>(r2 * (y * y), near, tab), acc);
+                    } else {
+                        acc = Prec<R>::far_acc(acc, ks[d], r2);
+                    }
                 }
-                const bool near = r2 < u[3 * d];
-                if (__builtin_amdgcn_ballot_w64(near)) {
-                    acc = fma(ks[d] * u[3 * d + 2], boys_grid<R>(r2 * u[3 * d + 1], near, tab), acc);
-                } else {
-                    acc = Prec<R>::far_acc(acc, ks[d], r2);
+            } else {
+                const cptr<R> up = rsn + 3 * (ab * G2 + cb * G);
+                R u[3 * G];
+#pragma unroll
+                for (int c = 0; c < 3 * G; ++c) u[c] = up[c];
+                // keep every uniform load in one batch at the top (not sunk into the branches)
+#pragma unroll
+                for (int c = 0; c < 3 * G; ++c) asm volatile("" ::"s"(u[c]));
+#pragma unroll
+                for (int d = 0; d < G; ++d) {
+                    R r2;
+                    if (kExpand) {
+                        r2 = fma(b[4], kx[d], fma(b[5], ky[d], fma(b[6], kz[d], kq[d] + b[7])));
+                    } else {
+                        const R dx = b[0] - kx[d], dy = b[1] - ky[d], dz = b[2] - kz[d];
+                        r2 = dx * dx + dy * dy + dz * dz;
+                    }
+                    const bool near = r2 < u[3 * d];
+                    if (__builtin_amdgcn_ballot_w64(near)) {
+                        acc = fma(ks[d] * u[3 * d + 2], boys_grid<R>(r2 * u[3 * d + 1], near, tab), acc);
+                    } else {
+                        acc = Prec<R>::far_acc(acc, ks[d], r2);
+                    }
                 }
             }
             eri += b[3] * acc;
@@ -273,7 +308,7 @@ template <typename R> struct FockSmem {
     }
 };
 
-template <int G, typename R, bool kSplit>
+template <int G, typename R, bool kSplit, bool kAtoms = false>
 __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
 {
     constexpr int G2 = G * G;
@@ -419,8 +454,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
         auto chunk = [&](int t, bool valid) {
             R eri;
             if (kSplit)
-                eri = quartet_eri_hybrid<G, R>((cptr<R>)(Prec<R>::bra(a) + (int64_t)s * 8 * G2), prim, a.pcap,
-                                               (unsigned)t, crs, tab);
+                eri = quartet_eri_hybrid<G, R, kAtoms>(
+                    (cptr<R>)(Prec<R>::bra(a) + (int64_t)s * 8 * G2), prim, a.pcap, (unsigned)t, crs, tab,
+                    kAtoms ? (cptr<R>)(Prec<R>::bip(a) + (int64_t)s * G2) : nullptr);
             else
                 eri = quartet_eri_direct<G, R>(lbra, prim, a.pcap, t, luni, tab);
             const int k = a.pk[t], l = a.pl[t];
@@ -549,15 +585,18 @@ __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ part,
 }
 
 template <int G, typename R>
-static hipError_t launch_fock_t(const FockArgs &a, int groups, int variant, hipStream_t st)
+static hipError_t launch_fock_t(const FockArgs &a, int groups, int variant, bool atoms, hipStream_t st)
 {
-    // the direct form keeps a bra's primitive data in LDS slots sized for g <= 4
-    const bool split = G > 4 || variant != 0;
+    // the direct form keeps a bra's primitive data in LDS slots sized for g <= 4; per-atom
+    // bases run the hybrid form only
+    const bool split = G > 4 || variant != 0 || atoms;
     const size_t smem = FockSmem<R>::total(a.n, split);
     const hipError_t ez = launch_zero_counter(a.next_block, st);
     if (ez != hipSuccess) return ez;
     profile_begin(st);
-    if constexpr (G > 4) {
+    if (atoms) {
+        hipLaunchKernelGGL((k_fock<G, R, true, true>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+    } else if constexpr (G > 4) {
         hipLaunchKernelGGL((k_fock<G, R, true>), dim3(groups), dim3(kGroupThreads), smem, st, a);
     } else {
         if (split)
@@ -570,11 +609,13 @@ static hipError_t launch_fock_t(const FockArgs &a, int groups, int variant, hipS
 }
 
 template <int G, typename R>
-static int resident_t(bool split, size_t smem)
+static int resident_t(bool split, size_t smem, bool atoms)
 {
     int nb = 0;
     hipError_t e;
-    if constexpr (G > 4) {
+    if (atoms) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fock<G, R, true, true>, kGroupThreads, smem);
+    } else if constexpr (G > 4) {
         (void)split;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fock<G, R, true>, kGroupThreads, smem);
     } else {
@@ -586,27 +627,27 @@ static int resident_t(bool split, size_t smem)
 
 // Workgroups of the quartet kernel that fit on one CU at once (registers and LDS); 0 if
 // the runtime cannot tell.  Persistent workgroups beyond this would only queue.
-int fock_resident_groups(int g, int prec, int variant, int64_t n)
+int fock_resident_groups(int g, int prec, int variant, int64_t n, bool atoms)
 {
-    const bool split = variant != 0;
-    const size_t smem = fock_smem_bytes(n, prec, variant);
+    const bool split = variant != 0 || atoms;
+    const size_t smem = fock_smem_bytes(n, prec, split ? 1 : 0);
     if (prec == HFK_MIXED) {
         switch (g) {
-        case 1: return resident_t<1, float>(split, smem);
-        case 2: return resident_t<2, float>(split, smem);
-        case 3: return resident_t<3, float>(split, smem);
-        case 4: return resident_t<4, float>(split, smem);
-        case 5: return resident_t<5, float>(true, smem);
-        default: return resident_t<6, float>(true, smem);
+        case 1: return resident_t<1, float>(split, smem, atoms);
+        case 2: return resident_t<2, float>(split, smem, atoms);
+        case 3: return resident_t<3, float>(split, smem, atoms);
+        case 4: return resident_t<4, float>(split, smem, atoms);
+        case 5: return resident_t<5, float>(true, smem, atoms);
+        default: return resident_t<6, float>(true, smem, atoms);
         }
     }
     switch (g) {
-    case 1: return resident_t<1, double>(split, smem);
-    case 2: return resident_t<2, double>(split, smem);
-    case 3: return resident_t<3, double>(split, smem);
-    case 4: return resident_t<4, double>(split, smem);
-    case 5: return resident_t<5, double>(true, smem);
-    default: return resident_t<6, double>(true, smem);
+    case 1: return resident_t<1, double>(split, smem, atoms);
+    case 2: return resident_t<2, double>(split, smem, atoms);
+    case 3: return resident_t<3, double>(split, smem, atoms);
+    case 4: return resident_t<4, double>(split, smem, atoms);
+    case 5: return resident_t<5, double>(true, smem, atoms);
+    default: return resident_t<6, double>(true, smem, atoms);
     }
 }
 
@@ -633,6 +674,8 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.prim_f = (const float *)(ws + L.prim_f);
     a.bra = (const double *)(ws + L.bra);
     a.bra_f = (const float *)(ws + L.bra_f);
+    a.bip = L.atoms ? (const double *)(ws + L.bip) : nullptr;
+    a.bip_f = L.atoms ? (const float *)(ws + L.bip_f) : nullptr;
     a.item_off = (const long long *)(ws + L.item_off);
     a.lim = (const int *)(ws + L.lim);
     a.goff = (const long long *)(ws + L.goff);
@@ -658,23 +701,24 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
         hipLaunchKernelGGL(k_fill, dim3(nb2), dim3(256), 0, st, a.fpriv, n2, 0.0);
     hipError_t err = hipSuccess;
     const int g = b.g;
+    const bool at = L.atoms;
     if (prec == HFK_MIXED) {
         switch (g) {
-        case 1: err = launch_fock_t<1, float>(a, L.groups, variant, st); break;
-        case 2: err = launch_fock_t<2, float>(a, L.groups, variant, st); break;
-        case 3: err = launch_fock_t<3, float>(a, L.groups, variant, st); break;
-        case 4: err = launch_fock_t<4, float>(a, L.groups, variant, st); break;
-        case 5: err = launch_fock_t<5, float>(a, L.groups, 1, st); break;
-        default: err = launch_fock_t<6, float>(a, L.groups, 1, st); break;
+        case 1: err = launch_fock_t<1, float>(a, L.groups, variant, at, st); break;
+        case 2: err = launch_fock_t<2, float>(a, L.groups, variant, at, st); break;
+        case 3: err = launch_fock_t<3, float>(a, L.groups, variant, at, st); break;
+        case 4: err = launch_fock_t<4, float>(a, L.groups, variant, at, st); break;
+        case 5: err = launch_fock_t<5, float>(a, L.groups, 1, at, st); break;
+        default: err = launch_fock_t<6, float>(a, L.groups, 1, at, st); break;
         }
     } else {
         switch (g) {
-        case 1: err = launch_fock_t<1, double>(a, L.groups, variant, st); break;
-        case 2: err = launch_fock_t<2, double>(a, L.groups, variant, st); break;
-        case 3: err = launch_fock_t<3, double>(a, L.groups, variant, st); break;
-        case 4: err = launch_fock_t<4, double>(a, L.groups, variant, st); break;
-        case 5: err = launch_fock_t<5, double>(a, L.groups, 1, st); break;
-        default: err = launch_fock_t<6, double>(a, L.groups, 1, st); break;
+        case 1: err = launch_fock_t<1, double>(a, L.groups, variant, at, st); break;
+        case 2: err = launch_fock_t<2, double>(a, L.groups, variant, at, st); break;
+        case 3: err = launch_fock_t<3, double>(a, L.groups, variant, at, st); break;
+        case 4: err = launch_fock_t<4, double>(a, L.groups, variant, at, st); break;
+        case 5: err = launch_fock_t<5, double>(a, L.groups, 1, at, st); break;
+        default: err = launch_fock_t<6, double>(a, L.groups, 1, at, st); break;
         }
     }
     if (err != hipSuccess) return err;

@@ -32,6 +32,7 @@ constexpr int kBoysOrder = 7;          // coefficients used (degree 6)
 constexpr int kBoysStride = 7;         // row length: odd in doubles, so rows start on 16 different LDS bank pairs
 constexpr double kBoysH = 0.125;       // grid spacing
 constexpr double kBoysInvH = 8.0;
+constexpr double kSqrtInvH = 2.82842712474619009760337744841939616;   // sqrt(1 / h)
 constexpr double kTswitch = 32.0;      // above this H(T) = T^(-1/2) to < 1e-15 relative
 constexpr int kBoysGrid = 264;         // covers [0, 33)
 
@@ -73,12 +74,16 @@ struct DevHeader {
 };
 
 // Basis constants shared by every pair, computed on the host from exps/coefs and passed
-// by value.  ab = a * g + b indexes a primitive pair.
+// by value.  ab = a * g + b indexes a primitive pair.  With per-atom bases, aexp and aw
+// point at device rows [n][g] of exponents and weights (primitive a on atom i at
+// i * g + a) and alpha/w are unused; for one basis on every atom they are NULL.
 struct Basis {
     int g;
     int g2;
     double alpha[kMaxG];
     double w[kMaxG];            // c_a (2 alpha_a / pi)^(3/4)
+    const double *aexp;
+    const double *aw;
 };
 
 // Per primitive pair / quartet constants, in device memory (written by a setup kernel).
@@ -110,8 +115,11 @@ struct Layout {
     size_t hdr, basis, boys, boys_f;
     size_t q_unsorted, bucket_of, bucket_cnt, bucket_off, bucket_cur;
     size_t pk, pl, pq, pd;                 // sorted pair tables
-    size_t prim;                           // [5][g2][pcap] doubles: Px, Py, Pz, S, |P|^2
-    size_t prim_f;                         // [4][g2][pcap] floats (mixed)
+    size_t prim;                           // [5][g2][pcap] doubles: Px, Py, Pz, S, |P|^2 (+ 1/p per-atom)
+    size_t prim_f;                         // [4][g2][pcap] floats (mixed) (+ 1/p per-atom)
+    bool atoms;                            // per-atom bases: the tables below are present
+    size_t arow;                           // [2][n][g] exponents and weights of every atom
+    size_t bip, bip_f;                     // [pcap][g2] 1/p of every bra primitive pair
     size_t bra, bra_f;                     // [pcap][g2][8] Px Py Pz S -2Px -2Py -2Pz |P|^2 (wave-uniform bra data)
     size_t boys_g, boys_g_f;               // Taylor table of g(T) = -(4/sqrt(pi)) F1(T) (gradient)
     size_t nitems, lim, item_off, scan_tmp;
@@ -128,7 +136,7 @@ struct Layout {
     size_t total;
 };
 
-Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups);
+Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool atoms = false);
 
 // Workspace layout of the batched path.
 struct BLayout {
@@ -164,7 +172,7 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
 hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *dens, double tau,
                        int prec, int strategy, int variant, double *fock, double *e2, hipStream_t st);
 size_t fock_smem_bytes(int64_t n, int prec, int variant);
-int fock_resident_groups(int g, int prec, int variant, int64_t n);
+int fock_resident_groups(int g, int prec, int variant, int64_t n, bool atoms = false);
 // Events around the quartet kernel when profiling is enabled (no-ops otherwise).
 void profile_begin(hipStream_t st);
 void profile_end(hipStream_t st);

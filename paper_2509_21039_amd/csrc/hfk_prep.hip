@@ -166,15 +166,27 @@ __global__ __launch_bounds__(256) void k_pair_q(Basis b, const BasisDev *__restr
         const double c0 = hdr->centroid[0], c1 = hdr->centroid[1], c2 = hdr->centroid[2];
         double A[3] = {xyz[3 * i] - c0, xyz[3 * i + 1] - c1, xyz[3 * i + 2] - c2};
         double B[3] = {xyz[3 * j] - c0, xyz[3 * j + 1] - c1, xyz[3 * j + 2] - c2};
-        double px[kMaxG2], py[kMaxG2], pz[kMaxG2], ps[kMaxG2];
-        pair_prims(b, bd, A, B, px, py, pz, ps);
+        double px[kMaxG2], py[kMaxG2], pz[kMaxG2], ps[kMaxG2], pp[kMaxG2];
         double s = 0.0;
-        for (int ab = 0; ab < b.g2; ++ab)
-            for (int cd = 0; cd < b.g2; ++cd) {
-                const double dx = px[ab] - px[cd], dy = py[ab] - py[cd], dz = pz[ab] - pz[cd];
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                s += ps[ab] * ps[cd] * bd->srho[ab * b.g2 + cd] * erf_over_sqrt(bd->rho[ab * b.g2 + cd] * r2);
-            }
+        if (b.aexp) {
+            // per-atom bases: rho of every primitive quartet from the pair exponents
+            pair_prims_atoms(b, i, j, A, B, px, py, pz, ps, pp);
+            for (int ab = 0; ab < b.g2; ++ab)
+                for (int cd = 0; cd < b.g2; ++cd) {
+                    const double dx = px[ab] - px[cd], dy = py[ab] - py[cd], dz = pz[ab] - pz[cd];
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    const double rho = pp[ab] * pp[cd] / (pp[ab] + pp[cd]);
+                    s += ps[ab] * ps[cd] * sqrt(rho) * erf_over_sqrt(rho * r2);
+                }
+        } else {
+            pair_prims(b, bd, A, B, px, py, pz, ps);
+            for (int ab = 0; ab < b.g2; ++ab)
+                for (int cd = 0; cd < b.g2; ++cd) {
+                    const double dx = px[ab] - px[cd], dy = py[ab] - py[cd], dz = pz[ab] - pz[cd];
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    s += ps[ab] * ps[cd] * bd->srho[ab * b.g2 + cd] * erf_over_sqrt(bd->rho[ab * b.g2 + cd] * r2);
+                }
+        }
         q = sqrt(s);
         qout[p] = q;
     }
@@ -235,7 +247,9 @@ __global__ __launch_bounds__(256) void k_bucket_cursors(const long long *__restr
 }
 
 // Writes every significant pair at its bucketed position: atoms, Q, D_kl and the SoA
-// primitive-pair table {Px, Py, Pz, S} (FP64 and FP32), centred on the centroid.
+// primitive-pair table {Px, Py, Pz, S} (FP64 and FP32), centred on the centroid.  With
+// per-atom bases (bip != NULL) the ket tables gain 1/p as their last component (FP64
+// component 5, FP32 component 4) and bip/bip_f receive it per bra primitive pair.
 __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *__restrict__ bd,
                                                       const DevHeader *__restrict__ hdr, int64_t n,
                                                       int64_t pcap, const double *__restrict__ xyz,
@@ -246,7 +260,8 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
                                                       int *__restrict__ pl, double *__restrict__ pq,
                                                       double *__restrict__ pd, double *__restrict__ prim,
                                                       float *__restrict__ prim_f, double *__restrict__ bra,
-                                                      float *__restrict__ bra_f)
+                                                      float *__restrict__ bra_f, double *__restrict__ bip,
+                                                      float *__restrict__ bip_f)
 {
     const int64_t npair = n * (n + 1) / 2;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -259,8 +274,11 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
     const double c0 = hdr->centroid[0], c1 = hdr->centroid[1], c2 = hdr->centroid[2];
     double A[3] = {xyz[3 * i] - c0, xyz[3 * i + 1] - c1, xyz[3 * i + 2] - c2};
     double B[3] = {xyz[3 * j] - c0, xyz[3 * j + 1] - c1, xyz[3 * j + 2] - c2};
-    double px[kMaxG2], py[kMaxG2], pz[kMaxG2], ps[kMaxG2];
-    pair_prims(b, bd, A, B, px, py, pz, ps);
+    double px[kMaxG2], py[kMaxG2], pz[kMaxG2], ps[kMaxG2], pp[kMaxG2];
+    if (b.aexp)
+        pair_prims_atoms(b, i, j, A, B, px, py, pz, ps, pp);
+    else
+        pair_prims(b, bd, A, B, px, py, pz, ps);
     pk[pos] = (int)i;
     pl[pos] = (int)j;
     pq[pos] = q[p];
@@ -278,19 +296,29 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
         prim_f[(3 * g2 + ab) * pcap + pos] = (float)ps[ab];
         double *ba = bra + ((int64_t)pos * g2 + ab) * 8;
         float *bf = bra_f + ((int64_t)pos * g2 + ab) * 8;
-        const double pp = px[ab] * px[ab] + py[ab] * py[ab] + pz[ab] * pz[ab];
+        const double p2 = px[ab] * px[ab] + py[ab] * py[ab] + pz[ab] * pz[ab];
         ba[0] = px[ab]; ba[1] = py[ab]; ba[2] = pz[ab]; ba[3] = ps[ab];
-        ba[4] = -2.0 * px[ab]; ba[5] = -2.0 * py[ab]; ba[6] = -2.0 * pz[ab]; ba[7] = pp;
+        ba[4] = -2.0 * px[ab]; ba[5] = -2.0 * py[ab]; ba[6] = -2.0 * pz[ab]; ba[7] = p2;
         bf[0] = (float)px[ab]; bf[1] = (float)py[ab]; bf[2] = (float)pz[ab]; bf[3] = (float)ps[ab];
         bf[4] = (float)(-2.0 * px[ab]); bf[5] = (float)(-2.0 * py[ab]); bf[6] = (float)(-2.0 * pz[ab]);
-        bf[7] = (float)pp;
+        bf[7] = (float)p2;
+    }
+    if (bip) {
+        for (int ab = 0; ab < g2; ++ab) {
+            const double ip = 1.0 / pp[ab];
+            prim[(5 * g2 + ab) * pcap + pos] = ip;
+            prim_f[(4 * g2 + ab) * pcap + pos] = (float)ip;
+            bip[(int64_t)pos * g2 + ab] = ip;
+            bip_f[(int64_t)pos * g2 + ab] = (float)ip;
+        }
     }
 }
 
 // Pads the tail chunk of the sorted tables with harmless entries (atom 0, zero weight,
 // centres 1e6 bohr away) so that lanes past the last pair, or lanes pointed at the first
 // pad entry, read defined memory and land in the far branch with a zero integral.
-// ncomp: FP64 components of the ket table (4: Px Py Pz S; 5 adds |P|^2).
+// ncomp: FP64 components of the ket table (4: Px Py Pz S; 5 adds |P|^2; 6 adds 1/p of
+// per-atom bases, which then is FP32 component 4).
 __global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int g2, int ncomp,
                            int *__restrict__ pk, int *__restrict__ pl, double *__restrict__ pq,
                            double *__restrict__ pd, double *__restrict__ prim, float *__restrict__ prim_f)
@@ -308,6 +336,10 @@ __global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int 
             prim_f[(c * g2 + ab) * pcap + pos] = c < 3 ? 1e6f : 0.0f;
         }
         if (ncomp > 4) prim[(4 * g2 + ab) * pcap + pos] = 3e12;
+        if (ncomp > 5) {
+            prim[(5 * g2 + ab) * pcap + pos] = 1.0;
+            prim_f[(4 * g2 + ab) * pcap + pos] = 1.0f;
+        }
     }
 }
 
@@ -338,8 +370,10 @@ __global__ __launch_bounds__(256) void k_limits(const DevHeader *__restrict__ hd
         if (thr <= 0.0) {
             bend = S;
         } else {
+            // band 0 is open-ended (every Q above its lower edge), so a threshold above the
+            // largest band edge still lands there; the lane-level test finishes the job
             const int bt = q_band(thr);
-            bend = (thr > 2.0) ? 0 : (bt + 1 >= kNumBands ? S : boff[(bt + 1) * kNumCells]);
+            bend = bt + 1 >= kNumBands ? S : boff[(bt + 1) * kNumCells];
         }
         const int64_t lim = bend < s + 1 ? bend : s + 1;
         ni = (lim + kItemKets - 1) / kItemKets;
@@ -504,8 +538,10 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
                        (const double *)(ws + L.q_unsorted), (const int *)(ws + L.bucket_of), cur,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f), (double *)(ws + L.bra),
-                       (float *)(ws + L.bra_f));
-    hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, L.pcap, L.g2, 5,
+                       (float *)(ws + L.bra_f), L.atoms ? (double *)(ws + L.bip) : nullptr,
+                       L.atoms ? (float *)(ws + L.bip_f) : nullptr);
+    hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, L.pcap, L.g2,
+                       L.atoms ? 6 : 5,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f));
     hipLaunchKernelGGL(k_limits, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, tau,

@@ -20,7 +20,8 @@ def _declared_symbols():
 def test_header_declares_entry_points():
     names = _declared_symbols()
     for must in ("hfk_fock", "hfk_fock_grad", "hfk_fock_batched", "hfk_workspace_bytes",
-                 "hfk_batched_workspace_bytes", "hfk_read_stats", "hfk_tune", "hfk_last_error"):
+                 "hfk_batched_workspace_bytes", "hfk_read_stats", "hfk_tune", "hfk_last_error",
+                 "hfk_fock_atoms", "hfk_workspace_bytes_atoms"):
         assert must in names
 
 
@@ -153,3 +154,53 @@ def test_batched_validation():
     off = np.array([0, 4, 9], dtype=np.int64)
     assert L.hfk_batched_workspace_bytes(2, off.ctypes.data_as(i64p), 3, 1, 1, ctypes.byref(out)) == hfk.HFK_OK
     assert out.value > 0
+
+
+def _atoms_raw(n=4, g=3, exps=None, coefs=None, xyz=1, dens=1, tau=1e-10, prec=0, strat=0, fock=1, e2=1, ws=256):
+    e = np.ascontiguousarray(np.tile([6.36242139, 1.158923, 0.31364979], (n, 1)) if exps is None else exps,
+                             dtype=np.float64)
+    c = np.ascontiguousarray(np.tile([0.15432897, 0.53532814, 0.44463454], (n, 1)) if coefs is None else coefs,
+                             dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    return hfk.lib().hfk_fock_atoms(n, xyz, g, e.ctypes.data_as(dp), c.ctypes.data_as(dp), dens, tau, prec,
+                                    strat, fock, e2, ws, 1 << 40, None)
+
+
+def _bad_row(col, value, atom=2, which="exps"):
+    a = np.tile([6.36242139, 1.158923, 0.31364979] if which == "exps" else [0.15432897, 0.53532814, 0.44463454],
+                (4, 1))
+    a[atom, col] = value
+    return {which: a}
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(n=0), "natoms"),
+    (_bad_row(1, -1.0), "atom 2"),
+    (_bad_row(0, 0.0, atom=3), "atom 3"),
+    (_bad_row(2, float("nan"), atom=1), "atom 1"),
+    (_bad_row(1, float("inf"), which="coefs"), "atom 2"),
+    (dict(tau=-1.0), "tau"),
+    (dict(prec=3), "precision"),
+    (dict(strat=9), "strategy"),
+    (dict(fock=None), "fock"),
+    (dict(ws=None), "workspace"),
+    (dict(ws=300), "aligned"),
+])
+def test_fock_atoms_rejects_invalid_arguments(kw, msg):
+    """Every atom's row is validated on the host; the message names the atom."""
+    assert _atoms_raw(**kw) == hfk.HFK_EINVAL
+    assert msg in hfk.lib().hfk_last_error().decode()
+
+
+def test_workspace_bytes_atoms_validation():
+    out = ctypes.c_size_t(0)
+    L = hfk.lib()
+    assert L.hfk_workspace_bytes_atoms(0, 3, 0, ctypes.byref(out)) == hfk.HFK_EINVAL
+    assert L.hfk_workspace_bytes_atoms(10, 9, 0, ctypes.byref(out)) == hfk.HFK_EINVAL
+    assert L.hfk_workspace_bytes_atoms(10, 3, 4, ctypes.byref(out)) == hfk.HFK_EINVAL
+    assert L.hfk_workspace_bytes_atoms(10, 3, 0, None) == hfk.HFK_EINVAL
+    assert L.hfk_workspace_bytes_atoms(100000, 3, 0, ctypes.byref(out)) == hfk.HFK_EUNSUPPORTED
+    assert L.hfk_workspace_bytes_atoms(300, 3, 0, ctypes.byref(out)) == hfk.HFK_OK
+    atoms = out.value
+    assert L.hfk_workspace_bytes(300, 3, 0, 0, ctypes.byref(out)) == hfk.HFK_OK
+    assert atoms > out.value   # the per-atom tables come on top of the one-basis layout

@@ -110,3 +110,23 @@ def test_six_primitive_batch(torch_dev):
             assert rel_fro(Fm, Fr) < tol, (precision, m)
             assert rel(E2[m], Er) < tol, (precision, m)
             assert np.linalg.norm(gm - gr) <= tol * max(np.linalg.norm(gr), 1e-6), (precision, m)
+
+
+def test_batch_with_bounds_above_two(torch_dev):
+    """A molecule whose Schwarz bounds reach above 2 inside a batch (see the single-molecule
+    regression): its bras with tau / Q_s above 2 keep their kets."""
+    from he_inputs import tight_cluster
+    t = tight_cluster()
+    others = [random_cluster(n, 300 + n, box=4.0, tau=t.tau) for n in (5, 12)]
+    for o in others:
+        o.exps, o.coefs = t.exps.copy(), t.coefs.copy()
+    systems = [others[0], t, others[1]]
+    announce("batched bounds above two")
+    off, F, E2, g = _run(torch_dev, systems, "fp64")
+    for m, s in enumerate(systems):
+        Fm, gm = _mol(off, F, g, m, s.natoms)
+        Fr, Er, _ = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+        gr, _, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+        assert rel_fro(Fm, Fr) < FP64_TOL, (m, rel_fro(Fm, Fr))
+        assert rel(E2[m], Er) < FP64_TOL, m
+        assert np.linalg.norm(gm - gr) <= FP64_TOL * max(np.linalg.norm(gr), 1e-6), m

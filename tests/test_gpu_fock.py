@@ -253,3 +253,27 @@ def test_workspace_too_small_is_rejected(torch_dev):
         hfk.fock_batched(off, torch.tensor(bx, device=dev), torch.tensor(bd, device=dev), s.exps, s.coefs, s.tau,
                          precision="fp64", with_grad=True, workspace=small)
     assert ei.value.status == hfk.HFK_ENOMEM
+
+
+def _crossing_quartets(s):
+    """Quartets kept by the screen whose bra bound Q_s is below tau / 2 (their partner Q_t
+    lies above 2)."""
+    Q = oracle.schwarz(s.xyz, s.exps, s.coefs)
+    small = Q[(Q < s.tau / 2) & (Q * Q.max() >= s.tau)]
+    return sum(int(np.sum(Q * q >= s.tau)) for q in small)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_bounds_above_two(torch_dev, variant):
+    """Schwarz bounds above 2 (a tight contraction): a bra with tau / Q_s above 2 still has
+    kets, in the open-ended top band.  Regression: such bras once got an empty ket range,
+    which dropped quartets worth ~1e-3 each here."""
+    from he_inputs import tight_cluster
+    s = tight_cluster()
+    assert _crossing_quartets(s) > 100
+    announce("bounds above two variant=%d" % variant)
+    G, E2, st = _run(torch_dev, s, variant=variant)
+    Gr, Er, nr = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+    assert st["quartets"] == nr
+    assert rel_fro(G, Gr) < FP64_TOL, rel_fro(G, Gr)
+    assert rel(E2, Er) < FP64_TOL
