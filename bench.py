@@ -91,15 +91,16 @@ def flop_per_quartet(g: int) -> int:
     return g ** 4 * FLOP_PER_PRIM_QUARTET + FLOP_SCATTER_PER_QUARTET
 
 
-def time_builds(hfk, torch, s, precision, steps, warmup, ws):
+def time_builds(hfk, torch, s, precision, steps, warmup, ws, atoms=False):
     dev = torch.device("cuda:0")
+    build = hfk.fock_atoms if atoms else hfk.fock
     xyz = torch.tensor(s.xyz, device=dev)
     D = torch.tensor(s.dens, device=dev)
     n = s.natoms
     F = torch.empty((n, n), dtype=torch.float64, device=dev)
     E2 = torch.empty((1,), dtype=torch.float64, device=dev)
     for _ in range(warmup):
-        hfk.fock(xyz, D, s.exps, s.coefs, s.tau, precision=precision, workspace=ws, out=(F, E2))
+        build(xyz, D, s.exps, s.coefs, s.tau, precision=precision, workspace=ws, out=(F, E2))
     torch.cuda.synchronize()
     stats = hfk.read_stats(ws)
     hfk.profile_read()                      # drop anything recorded so far
@@ -116,7 +117,7 @@ def time_builds(hfk, torch, s, precision, steps, warmup, ws):
     e0.record(stream)
     marks[0].record(stream)
     for k in range(steps):
-        hfk.fock(xyz, D, s.exps, s.coefs, s.tau, precision=precision, workspace=ws, out=(F, E2))
+        build(xyz, D, s.exps, s.coefs, s.tau, precision=precision, workspace=ws, out=(F, E2))
         marks[k + 1].record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
@@ -342,6 +343,29 @@ def main():
             }
         except hfk.HfkError as e:
             extras["fwd_grad_he128"] = {"error": str(e)}
+        try:
+            from he_inputs import mixed_lattice
+            s5 = mixed_lattice((8, 8, 8), seed=13, tau=1e-10)
+            log("512 H/He atoms, per-atom bases: fp64 and mixed")
+            ws5 = hfk.new_workspace(hfk.workspace_bytes_atoms(s5.natoms, g, "fp64"), dev)
+            a = time_builds(hfk, torch, s5, "fp64", 5, 1, ws5, atoms=True)
+            b = time_builds(hfk, torch, s5, "mixed", 5, 1, ws5, atoms=True)
+            qa = a["stats"]["quartets"]
+            extras["atoms_hhe512"] = {
+                "quartets": qa,
+                "fp64_ms": a["ms_per_step"], "fp64_kernel_ms": a["kernel_ms"],
+                "fp64_quartets_per_s": qa / (a["ms_per_step"] / 1e3),
+                "pct_fp64_valu_peak_nominal": 100.0 * qa * flop_per_quartet(g) / (a["kernel_ms"] / 1e3) / 1e12
+                / FP64_VALU_PEAK_TFLOPS,
+                "mixed_ms": b["ms_per_step"],
+                "mixed_quartets_per_s": b["stats"]["quartets"] / (b["ms_per_step"] / 1e3),
+                "mixed_speedup_vs_fp64": a["ms_per_step"] / b["ms_per_step"],
+                "rel_err_F_mixed_vs_fp64": float(torch.linalg.norm(b["F"] - a["F"]) / torch.linalg.norm(a["F"])),
+            }
+            del ws5, a, b
+            torch.cuda.empty_cache()
+        except hfk.HfkError as e:
+            extras["atoms_hhe512"] = {"error": str(e)}
         try:
             from he_inputs import cluster_batch
             log("2000-cluster batch: mixed + gradient, one launch")

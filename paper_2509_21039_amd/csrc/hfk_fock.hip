@@ -39,7 +39,7 @@ struct FockArgs {
     const float *prim_f;
     const double *bra;
     const float *bra_f;
-    const double *bip;          // per-atom bases: [pcap][g2] 1/p of the bra primitive pairs
+    const double *bip;          // per-atom bases: [pcap][g2] kTswitch / p of the bra primitive pairs
     const float *bip_f;
     const long long *item_off;
     const long long *goff;      // [ngroups + 1] block offsets of the bra groups
@@ -201,17 +201,17 @@ __device__ inline R boys_grid(R Ts, bool near, const R *__restrict__ tab)
 // coordinates the cancellation stays near 1e-13 bohr^2 absolute); FP32 subtracts the
 // centres directly, which its precision needs.
 // Per-atom bases (kAtoms): rho = p q / (p + q) differs per quartet, so the scalar combo
-// table gives way to 1/p of the bra (uniform, bip) and of the ket (last ket component):
-// 1/rho = 1/p + 1/q, the switch test is |P-Q|^2 < kTswitch / rho, and only the near
-// branch needs sqrt(rho / h) (one reciprocal square root of 1/rho); the far field
-// S_cd / |P-Q| does not depend on rho at all.
+// table gives way to kTswitch / p of the bra (uniform, bip) and of the ket (last ket
+// component): their sum is kTswitch / rho, the switch radius^2 itself, so the test costs
+// one add; only the near branch needs sqrt(rho / h) = sqrt(kTswitch / h) / sqrt(that sum)
+// (one reciprocal square root); the far field S_cd / |P-Q| does not depend on rho at all.
 template <int G, typename R, bool kAtoms = false>
 __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, int64_t pcap, unsigned t,
                                        cptr<R> rsn, const R *__restrict__ tab, cptr<R> bip = nullptr)
 {
     constexpr int G2 = G * G;
     constexpr bool kExpand = sizeof(R) == 8;
-    constexpr int kPComp = kExpand ? 5 : 4;   // ket component holding 1/p (per-atom bases)
+    constexpr int kPComp = kExpand ? 5 : 4;   // ket component holding kTswitch / p (per-atom bases)
     R eri = R(0);
 #pragma unroll 1
     for (int cb = 0; cb < G; ++cb) {
@@ -257,10 +257,10 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
                         const R dx = b[0] - kx[d], dy = b[1] - ky[d], dz = b[2] - kz[d];
                         r2 = dx * dx + dy * dy + dz * dz;
                     }
-                    const R irho = bi + kp[d];
-                    const bool near = r2 < R(kTswitch) * irho;
+                    const R sw = bi + kp[d];   // kTswitch / rho
+                    const bool near = r2 < sw;
                     if (__builtin_amdgcn_ballot_w64(near)) {
-                        const R y = rsqrt_r(irho) * R(kSqrtInvH);   // sqrt(rho / h)
+                        const R y = rsqrt_r(sw) * R(kSqrtSwitchInvH);   // sqrt(rho / h)
                         acc = fma(ks[d] * y, boys_grid<R>(r2 * (y * y), near, tab), acc);
                     } else {
                         acc = Prec<R>::far_acc(acc, ks[d], r2);

@@ -32,8 +32,8 @@ constexpr int kBoysOrder = 7;          // coefficients used (degree 6)
 constexpr int kBoysStride = 7;         // row length: odd in doubles, so rows start on 16 different LDS bank pairs
 constexpr double kBoysH = 0.125;       // grid spacing
 constexpr double kBoysInvH = 8.0;
-constexpr double kSqrtInvH = 2.82842712474619009760337744841939616;   // sqrt(1 / h)
 constexpr double kTswitch = 32.0;      // above this H(T) = T^(-1/2) to < 1e-15 relative
+constexpr double kSqrtSwitchInvH = 16.0;   // sqrt(kTswitch / h)
 constexpr int kBoysGrid = 264;         // covers [0, 33)
 
 constexpr int kWave = 64;
@@ -115,11 +115,11 @@ struct Layout {
     size_t hdr, basis, boys, boys_f;
     size_t q_unsorted, bucket_of, bucket_cnt, bucket_off, bucket_cur;
     size_t pk, pl, pq, pd;                 // sorted pair tables
-    size_t prim;                           // [5][g2][pcap] doubles: Px, Py, Pz, S, |P|^2 (+ 1/p per-atom)
-    size_t prim_f;                         // [4][g2][pcap] floats (mixed) (+ 1/p per-atom)
+    size_t prim;                           // [5][g2][pcap] doubles: Px, Py, Pz, S, |P|^2 (+ kTswitch/p per-atom)
+    size_t prim_f;                         // [4][g2][pcap] floats (mixed) (+ kTswitch/p per-atom)
     bool atoms;                            // per-atom bases: the tables below are present
     size_t arow;                           // [2][n][g] exponents and weights of every atom
-    size_t bip, bip_f;                     // [pcap][g2] 1/p of every bra primitive pair
+    size_t bip, bip_f;                     // [pcap][g2] kTswitch/p of every bra primitive pair
     size_t bra, bra_f;                     // [pcap][g2][8] Px Py Pz S -2Px -2Py -2Pz |P|^2 (wave-uniform bra data)
     size_t boys_g, boys_g_f;               // Taylor table of g(T) = -(4/sqrt(pi)) F1(T) (gradient)
     size_t nitems, lim, item_off, scan_tmp;

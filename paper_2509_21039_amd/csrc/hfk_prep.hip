@@ -248,8 +248,9 @@ __global__ __launch_bounds__(256) void k_bucket_cursors(const long long *__restr
 
 // Writes every significant pair at its bucketed position: atoms, Q, D_kl and the SoA
 // primitive-pair table {Px, Py, Pz, S} (FP64 and FP32), centred on the centroid.  With
-// per-atom bases (bip != NULL) the ket tables gain 1/p as their last component (FP64
-// component 5, FP32 component 4) and bip/bip_f receive it per bra primitive pair.
+// per-atom bases (bip != NULL) the ket tables gain kTswitch / p as their last component
+// (FP64 component 5, FP32 component 4) and bip/bip_f receive it per bra primitive pair:
+// the two add up to kTswitch / rho of the quartet.
 __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *__restrict__ bd,
                                                       const DevHeader *__restrict__ hdr, int64_t n,
                                                       int64_t pcap, const double *__restrict__ xyz,
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
     }
     if (bip) {
         for (int ab = 0; ab < g2; ++ab) {
-            const double ip = 1.0 / pp[ab];
+            const double ip = kTswitch / pp[ab];
             prim[(5 * g2 + ab) * pcap + pos] = ip;
             prim_f[(4 * g2 + ab) * pcap + pos] = (float)ip;
             bip[(int64_t)pos * g2 + ab] = ip;
@@ -317,8 +318,8 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
 // Pads the tail chunk of the sorted tables with harmless entries (atom 0, zero weight,
 // centres 1e6 bohr away) so that lanes past the last pair, or lanes pointed at the first
 // pad entry, read defined memory and land in the far branch with a zero integral.
-// ncomp: FP64 components of the ket table (4: Px Py Pz S; 5 adds |P|^2; 6 adds 1/p of
-// per-atom bases, which then is FP32 component 4).
+// ncomp: FP64 components of the ket table (4: Px Py Pz S; 5 adds |P|^2; 6 adds kTswitch/p
+// of per-atom bases, which then is FP32 component 4).
 __global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int g2, int ncomp,
                            int *__restrict__ pk, int *__restrict__ pl, double *__restrict__ pq,
                            double *__restrict__ pd, double *__restrict__ prim, float *__restrict__ prim_f)
