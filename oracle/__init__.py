@@ -21,6 +21,7 @@ Parity status of each function (what pins it, in ``tests/test_oracle.py``):
   *_atoms                       pinned: brute-force plain definition with per-atom bases, reduction
                                 to the one-basis build when every row is equal, atom-permutation
                                 equivariance, far-field S_ii S_kk / R, central differences of E2
+                                and of the pairing W o G (grad_pair_atoms)
 """
 from __future__ import annotations
 
@@ -93,6 +94,8 @@ def _load():
         lib.hfo_fock_element_atoms.argtypes = lib.hfo_fock_element.argtypes
         lib.hfo_fock_bruteforce_atoms.restype = ctypes.c_int
         lib.hfo_fock_bruteforce_atoms.argtypes = lib.hfo_fock_bruteforce.argtypes
+        lib.hfo_grad_pair_atoms.restype = ctypes.c_int
+        lib.hfo_grad_pair_atoms.argtypes = lib.hfo_grad_pair.argtypes
         lib.hfo_grad_atoms.restype = ctypes.c_int
         lib.hfo_grad_atoms.argtypes = lib.hfo_grad.argtypes
         lib.hfo_num_threads.restype = ctypes.c_int
@@ -301,3 +304,19 @@ def grad_atoms(xyz, dens, exps, coefs, tau, Q=None, nthreads: int = 0):
     if rc != 0:
         raise MemoryError("oracle grad_atoms: out of memory")
     return gr, e2.value, ns.value
+
+
+def grad_pair_atoms(xyz, dens, xdens, exps, coefs, tau, Q=None, nthreads: int = 0):
+    """grad_pair with per-atom bases."""
+    xyz, px, e, pe, c, pc, n, g = _atoms(xyz, exps, coefs)
+    d, pd = _c(dens)
+    x, pxd = _c(xdens)
+    gr = np.zeros((n, 3))
+    qp = None
+    if Q is not None:
+        Q, qp = _c(Q)
+    rc = _load().hfo_grad_pair_atoms(n, px, g, pe, pc, pd, pxd, float(tau), qp, int(nthreads),
+                                     gr.ctypes.data_as(_dp))
+    if rc != 0:
+        raise MemoryError("oracle grad_pair_atoms: out of memory")
+    return gr

@@ -575,16 +575,16 @@ int hfo_grad_atoms(int64_t n, const double *xyz, int g, const double *exps, cons
  * density is replaced by X:
  *   B = deg (4 (X_ij D_kl + D_ij X_kl) - (X_ik D_jl + D_ik X_jl) - (X_il D_jk + D_il X_jk)),
  * so X = W gives dL/dR, X = D / 2 gives dE2/dR, and X = W + (g/2) D gives both at once. */
-int hfo_grad_pair(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
-                  const double *dens, const double *xdens, double tau, const double *Qin, int nthreads,
-                  double *grad)
+static int grad_pair_s(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                       int64_t astride, const double *dens, const double *xdens, double tau, const double *Qin,
+                       int nthreads, double *grad)
 {
     const int64_t npair = n * (n + 1) / 2;
     int ownQ = 0;
-    double *Q = schwarz_or(Qin, n, xyz, g, exps, coefs, 0, nthreads, &ownQ);
+    double *Q = schwarz_or(Qin, n, xyz, g, exps, coefs, astride, nthreads, &ownQ);
     if (!Q) return -1;
     int64_t *pi = pair_list(n);
-    double *W = atom_weights(n, g, exps, coefs, 0);
+    double *W = atom_weights(n, g, exps, coefs, astride);
     if (!pi || !W) { free(pi); free(W); if (ownQ) free(Q); return -1; }
     memset(grad, 0, sizeof(double) * (size_t)(3 * n));
     int failed = 0;
@@ -613,7 +613,7 @@ int hfo_grad_pair(int64_t n, const double *xyz, int g, const double *exps, const
                                      (4.0 * (X[i * n + j] * D[k * n + l] + D[i * n + j] * X[k * n + l]) -
                                       (X[i * n + k] * D[j * n + l] + D[i * n + k] * X[j * n + l]) -
                                       (X[i * n + l] * D[j * n + k] + D[i * n + l] * X[j * n + k]));
-                    eri_grad_atoms(xyz, g, exps, W, 0, i, j, k, l, b, gp);
+                    eri_grad_atoms(xyz, g, exps, W, astride, i, j, k, l, b, gp);
                 }
             }
 #ifdef _OPENMP
@@ -627,6 +627,20 @@ int hfo_grad_pair(int64_t n, const double *xyz, int g, const double *exps, const
     free(W);
     if (ownQ) free(Q);
     return failed ? -1 : 0;
+}
+
+int hfo_grad_pair(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                  const double *dens, const double *xdens, double tau, const double *Qin, int nthreads,
+                  double *grad)
+{
+    return grad_pair_s(n, xyz, g, exps, coefs, 0, dens, xdens, tau, Qin, nthreads, grad);
+}
+
+int hfo_grad_pair_atoms(int64_t n, const double *xyz, int g, const double *exps, const double *coefs,
+                        const double *dens, const double *xdens, double tau, const double *Qin, int nthreads,
+                        double *grad)
+{
+    return grad_pair_s(n, xyz, g, exps, coefs, g, dens, xdens, tau, Qin, nthreads, grad);
 }
 
 int hfo_num_threads(void)
