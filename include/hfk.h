@@ -142,8 +142,10 @@ hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss,
  * hfk_fock with each centre's own exponents and weights: the Gaussian product and the
  * primitive integral of the Background section hold for any exponent on any centre, and
  * one basis on every atom (the kernel listing) is the case of identical rows.
- * Workspace size for hfk_fock_atoms; arguments and errors as hfk_workspace_bytes. */
-hfk_status hfk_workspace_bytes_atoms(int64_t natoms, int32_t ngauss, int32_t precision, size_t *bytes_out);
+ * Workspace size for hfk_fock_atoms (with_grad = 0) or hfk_fock_grad_atoms (with_grad != 0);
+ * arguments and errors as hfk_workspace_bytes. */
+hfk_status hfk_workspace_bytes_atoms(int64_t natoms, int32_t ngauss, int32_t precision, int32_t with_grad,
+                                     size_t *bytes_out);
 
 /* Forward Fock build with per-atom bases.  Arguments, outputs and errors as hfk_fock except
  *   exps_host    [natoms*ngauss] row i: the exponents of atom i, each > 0 and finite (host)
@@ -159,6 +161,16 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss,
                           const double *dens, double tau, int32_t precision, int32_t strategy,
                           double *fock, double *e2,
                           void *workspace, size_t workspace_bytes, void *stream);
+
+/* Backward of hfk_fock_atoms: arguments, outputs and errors as hfk_fock_grad, with the
+ * per-atom rows of hfk_fock_atoms; the workspace is sized by hfk_workspace_bytes_atoms with
+ * with_grad != 0.  The pull-back of g_fock is a Fock build with per-atom bases. */
+hfk_status hfk_fock_grad_atoms(int64_t natoms, const double *xyz, int32_t ngauss,
+                               const double *exps_host, const double *coefs_host,
+                               const double *dens, double tau, int32_t precision,
+                               const double *g_e2, const double *g_fock, const double *fock_in,
+                               double *d_xyz, double *d_dens, double *e2_out,
+                               void *workspace, size_t workspace_bytes, void *stream);
 
 /* Workspace size for hfk_fock_batched over `nmol` molecules whose atom ranges are
  * atom_off_host[m] .. atom_off_host[m+1] (CSR, host memory, nondecreasing, starting at 0).

@@ -70,7 +70,10 @@ _SIGNATURES = {
     "hfk_profile_enable": [ctypes.c_int32],
     "hfk_set_config": [ctypes.c_int32, ctypes.c_int32],
     "hfk_profile_read": [ctypes.POINTER(ctypes.c_double), _i64p],
-    "hfk_workspace_bytes_atoms": [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_sz)],
+    "hfk_workspace_bytes_atoms": [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.POINTER(_sz)],
+    "hfk_fock_grad_atoms": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
+                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
     "hfk_fock_atoms": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
                        ctypes.c_int32, _vp, _vp, _vp, _sz, _vp],
 }
@@ -174,10 +177,19 @@ def fock(xyz, dens, exps: Sequence[float], coefs: Sequence[float], tau: float, p
     return F, E2
 
 
-def workspace_bytes_atoms(natoms: int, ngauss: int = 3, precision="fp64") -> int:
+def workspace_bytes_atoms(natoms: int, ngauss: int = 3, precision="fp64", with_grad: bool = False) -> int:
     out = _sz(0)
-    _check(lib().hfk_workspace_bytes_atoms(int(natoms), int(ngauss), _PREC[precision], ctypes.byref(out)))
+    _check(lib().hfk_workspace_bytes_atoms(int(natoms), int(ngauss), _PREC[precision], int(bool(with_grad)),
+                                           ctypes.byref(out)))
     return out.value
+
+
+def _rows(exps, coefs, n):
+    e = _host_f64(exps)
+    c = _host_f64(coefs)
+    if e.shape != c.shape or e.ndim != 2 or e.shape[0] != n:
+        raise HfkError(HFK_EINVAL, "per-atom exps and coefs must both be (natoms, ngauss)")
+    return e, c
 
 
 def fock_atoms(xyz, dens, exps, coefs, tau: float, precision="fp64", strategy: int = STRATEGY_AUTO,
@@ -188,10 +200,7 @@ def fock_atoms(xyz, dens, exps, coefs, tau: float, precision="fp64", strategy: i
     n = xyz.shape[0]
     _dev_f64(xyz, "xyz", (n, 3))
     _dev_f64(dens, "dens", (n, n))
-    e = _host_f64(exps)
-    c = _host_f64(coefs)
-    if e.shape != c.shape or e.ndim != 2 or e.shape[0] != n:
-        raise HfkError(HFK_EINVAL, "per-atom exps and coefs must both be (natoms, ngauss)")
+    e, c = _rows(exps, coefs, n)
     g = e.shape[1]
     prec = _PREC[precision]
     if workspace is None:
@@ -216,19 +225,27 @@ def read_stats(workspace, stream=None) -> dict:
 def fock_grad(xyz, dens, exps, coefs, tau, precision="fp64", g_e2=None, fock_in=None, want_dens=True,
               workspace=None, stream=None, g_fock=None):
     """(d_xyz, d_dens or None, E2) for upstream g_e2 (device scalar tensor; 1 if None) and
-    g_fock (device [n, n] tensor dL/dG, or None)."""
+    g_fock (device [n, n] tensor dL/dG, or None).  exps/coefs: one contraction (1-D) for every
+    atom, or per-atom rows (natoms, ngauss)."""
     torch = _torch()
     n = xyz.shape[0]
     _dev_f64(xyz, "xyz", (n, 3))
     _dev_f64(dens, "dens", (n, n))
-    e = _host_f64(exps)
-    c = _host_f64(coefs)
+    atoms = np.ndim(exps) == 2
+    if atoms:
+        e, c = _rows(exps, coefs, n)
+        g = e.shape[1]
+    else:
+        e = _host_f64(exps)
+        c = _host_f64(coefs)
+        g = len(e)
     prec = _PREC[precision]
     if g_e2 is None:
         g_e2 = torch.ones((1,), dtype=torch.float64, device=xyz.device)
     _dev_f64(g_e2, "g_e2")
     if workspace is None:
-        workspace = new_workspace(workspace_bytes(n, len(e), prec, True), xyz.device)
+        nb = workspace_bytes_atoms(n, g, prec, True) if atoms else workspace_bytes(n, g, prec, True)
+        workspace = new_workspace(nb, xyz.device)
     if g_fock is not None:
         _dev_f64(g_fock, "g_fock", (n, n))
     d_xyz = torch.empty((n, 3), dtype=torch.float64, device=xyz.device)
@@ -239,11 +256,12 @@ def fock_grad(xyz, dens, exps, coefs, tau, precision="fp64", g_e2=None, fock_in=
         _dev_f64(fock_in, "fock_in", (n, n))
         d_dens = torch.empty((n, n), dtype=torch.float64, device=xyz.device)
     E2 = torch.empty((1,), dtype=torch.float64, device=xyz.device)
-    _check(lib().hfk_fock_grad(n, xyz.data_ptr(), len(e), _dptr(e), _dptr(c), dens.data_ptr(), float(tau), prec,
-                               g_e2.data_ptr(), g_fock.data_ptr() if g_fock is not None else None,
-                               fock_in.data_ptr() if fock_in is not None else None,
-                               d_xyz.data_ptr(), d_dens.data_ptr() if d_dens is not None else None,
-                               E2.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream_handle(stream)))
+    call = lib().hfk_fock_grad_atoms if atoms else lib().hfk_fock_grad
+    _check(call(n, xyz.data_ptr(), g, _dptr(e), _dptr(c), dens.data_ptr(), float(tau), prec,
+                g_e2.data_ptr(), g_fock.data_ptr() if g_fock is not None else None,
+                fock_in.data_ptr() if fock_in is not None else None,
+                d_xyz.data_ptr(), d_dens.data_ptr() if d_dens is not None else None,
+                E2.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream_handle(stream)))
     return d_xyz, d_dens, E2
 
 
@@ -255,12 +273,16 @@ def _autograd():
 
         forward(xyz, dens, exps, coefs, tau, precision) -> (G, E2); backward hands the
         upstream (gG, gE2) to the library's gradient call: dL/dxyz from the two-density
-        contraction, dL/ddens = gE2 * G + G(sym(gG))."""
+        contraction, dL/ddens = gE2 * G + G(sym(gG)).  exps/coefs: one contraction (1-D) or
+        per-atom rows (natoms, ngauss)."""
 
         @staticmethod
         def forward(ctx, xyz, dens, exps, coefs, tau, precision="fp64"):
             ctx.set_materialize_grads(False)
-            G, E2 = fock(xyz, dens, exps, coefs, tau, precision)
+            if np.ndim(exps) == 2:
+                G, E2 = fock_atoms(xyz, dens, exps, coefs, tau, precision)
+            else:
+                G, E2 = fock(xyz, dens, exps, coefs, tau, precision)
             ctx.save_for_backward(xyz, dens, G)
             ctx.basis = (np.asarray(exps, dtype=np.float64).copy(), np.asarray(coefs, dtype=np.float64).copy())
             ctx.tau = tau

@@ -85,6 +85,11 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool a
         L.arow = take(sizeof(double) * 2 * (size_t)n * (size_t)g);
         L.bip = take(sizeof(double) * g2 * PC);
         L.bip_f = take(sizeof(float) * g2 * PC);
+        if (with_grad) {
+            L.pmu = take(sizeof(double) * g2 * PC);
+            L.pfa = take(sizeof(double) * g2 * PC);
+            L.bmf = take(sizeof(double) * 2 * g2 * PC);
+        }
     }
     L.bra = take(sizeof(double) * 8 * g2 * PC);
     L.bra_f = take(sizeof(float) * 8 * g2 * PC);
@@ -349,7 +354,34 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     return HFK_OK;
 }
 
-hfk_status hfk_workspace_bytes_atoms(int64_t natoms, int32_t ngauss, int32_t precision, size_t *bytes_out)
+}  // extern "C"
+
+// Per-atom bases: exponents and weights of every atom, [2][n][g], copied to the workspace
+// (pageable host memory: the copy completes before hipMemcpyAsync returns), and the Basis
+// that points the kernels at them.
+static hipError_t upload_rows(const Layout &L, char *ws, int64_t natoms, int32_t ngauss, const double *exps,
+                              const double *coefs, hipStream_t st, Basis *b)
+{
+    const size_t ng = (size_t)natoms * (size_t)ngauss;
+    std::vector<double> rows(2 * ng);
+    for (size_t x = 0; x < ng; ++x) {
+        rows[x] = exps[x];
+        rows[ng + x] = coefs[x] * pow(2.0 * exps[x] / 3.14159265358979323846, 0.75);
+    }
+    double *arow = (double *)(ws + L.arow);
+    memset(b, 0, sizeof(*b));
+    b->g = ngauss;
+    b->g2 = ngauss * ngauss;
+    for (int a = 0; a < ngauss; ++a) b->alpha[a] = 1.0;   // the one-basis tables stay finite, unused
+    b->aexp = arow;
+    b->aw = arow + ng;
+    return hipMemcpyAsync(arow, rows.data(), sizeof(double) * 2 * ng, hipMemcpyHostToDevice, st);
+}
+
+extern "C" {
+
+hfk_status hfk_workspace_bytes_atoms(int64_t natoms, int32_t ngauss, int32_t precision, int32_t with_grad,
+                                     size_t *bytes_out)
 {
     g_err[0] = 0;
     if (!bytes_out) return fail(HFK_EINVAL, "bytes_out is NULL");
@@ -359,7 +391,9 @@ hfk_status hfk_workspace_bytes_atoms(int64_t natoms, int32_t ngauss, int32_t pre
     if (precision != HFK_FP64 && precision != HFK_MIXED)
         return fail(HFK_EINVAL, "precision must be HFK_FP64 or HFK_MIXED (got %d)", (int)precision);
     if (natoms > kMaxAtoms) return fail(HFK_EUNSUPPORTED, "natoms above %lld", (long long)kMaxAtoms);
-    const Layout L = make_layout(natoms, ngauss, precision, 0, groups_cap(device_cu_count()), true);
+    if (with_grad && natoms > kMaxGradAtoms)
+        return fail(HFK_EUNSUPPORTED, "gradient supports natoms <= %lld", (long long)kMaxGradAtoms);
+    const Layout L = make_layout(natoms, ngauss, precision, with_grad, groups_cap(device_cu_count()), true);
     *bytes_out = L.total;
     return HFK_OK;
 }
@@ -395,26 +429,11 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
         const int fit = fock_resident_groups(ngauss, precision, 1, natoms, true);
         L.groups = cus * (fit > 0 && cfg.gpc > fit ? fit : cfg.gpc);
     }
-    // exponents and weights of every atom, [2][n][g], copied to the workspace (pageable
-    // host memory: the copy completes before hipMemcpyAsync returns)
-    const size_t ng = (size_t)natoms * (size_t)ngauss;
-    std::vector<double> rows(2 * ng);
-    for (size_t x = 0; x < ng; ++x) {
-        rows[x] = exps_host[x];
-        rows[ng + x] = coefs_host[x] * pow(2.0 * exps_host[x] / 3.14159265358979323846, 0.75);
-    }
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
-    double *arow = (double *)(ws + L.arow);
-    hipError_t e = hipMemcpyAsync(arow, rows.data(), sizeof(double) * 2 * ng, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "basis rows copy");
     Basis b;
-    memset(&b, 0, sizeof(b));
-    b.g = ngauss;
-    b.g2 = ngauss * ngauss;
-    for (int a = 0; a < ngauss; ++a) b.alpha[a] = 1.0;   // the one-basis tables stay finite, unused
-    b.aexp = arow;
-    b.aw = arow + ng;
+    hipError_t e = upload_rows(L, ws, natoms, ngauss, exps_host, coefs_host, st, &b);
+    if (e != hipSuccess) return hip_fail(e, "basis rows copy");
     e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (float *)(ws + L.boys_f),
                      (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz,
                      st);
@@ -450,14 +469,20 @@ hfk_status hfk_read_stats(const void *workspace, void *stream, hfk_stats *out)
     return HFK_OK;
 }
 
-hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
-                         const double *coefs_host, const double *dens, double tau, int32_t precision,
-                         const double *g_e2, const double *g_fock, const double *fock_in, double *d_xyz,
-                         double *d_dens, double *e2_out, void *workspace, size_t workspace_bytes, void *stream)
+// hfk_fock_grad and hfk_fock_grad_atoms (atoms: exps/coefs are per-atom rows).
+static hfk_status fock_grad_impl(bool atoms, int64_t natoms, const double *xyz, int32_t ngauss,
+                                 const double *exps_host, const double *coefs_host, const double *dens, double tau,
+                                 int32_t precision, const double *g_e2, const double *g_fock, const double *fock_in,
+                                 double *d_xyz, double *d_dens, double *e2_out, void *workspace,
+                                 size_t workspace_bytes, void *stream)
 {
     g_err[0] = 0;
     hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision);
     if (s != HFK_OK) return s;
+    if (atoms) {
+        s = check_rows(natoms, ngauss, exps_host, coefs_host);
+        if (s != HFK_OK) return s;
+    }
     if (!g_e2) return fail(HFK_EINVAL, "g_e2 is NULL");
     if (!d_xyz) return fail(HFK_EINVAL, "d_xyz is NULL");
     if (d_dens && !fock_in) return fail(HFK_EINVAL, "d_dens needs fock_in");
@@ -468,13 +493,19 @@ hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss, cons
     if (ngauss > kMaxBuiltG) return fail(HFK_EUNSUPPORTED, "ngauss above %d is not built in this version", kMaxBuiltG);
     const int cus = device_cu_count();
     if (cus <= 0) return fail(HFK_EHIP, "no HIP device");
-    Layout L = make_layout(natoms, ngauss, precision, 1, groups_cap(cus));
+    Layout L = make_layout(natoms, ngauss, precision, 1, groups_cap(cus), atoms);
     if (workspace_bytes < L.total)
         return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
     L.groups = cus * kGradGroupsPerCU;
-    const Basis b = make_basis(ngauss, exps_host, coefs_host);
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
+    Basis b;
+    if (atoms) {
+        const hipError_t eu = upload_rows(L, ws, natoms, ngauss, exps_host, coefs_host, st, &b);
+        if (eu != hipSuccess) return hip_fail(eu, "basis rows copy");
+    } else {
+        b = make_basis(ngauss, exps_host, coefs_host);
+    }
     hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (float *)(ws + L.boys_f),
                                 (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr),
                                 natoms, xyz, st);
@@ -495,11 +526,12 @@ hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss, cons
         // rebuilt around W; the screen depends on the geometry only), then the axpy
         e = launch_pairs(L, b, ws, xyz, xw, tau, st);
         if (e != hipSuccess) return hip_fail(e, "pair launch (W)");
-        const TunedConfig cfg = pick_config(HFK_STRATEGY_AUTO, precision, natoms, ngauss);
+        TunedConfig cfg = pick_config(HFK_STRATEGY_AUTO, precision, natoms, ngauss);
+        if (atoms) cfg.variant = 1;   // per-atom bases run the hybrid form only
         int strat = cfg.strategy;
         if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
         Layout LF = L;
-        const int fit = fock_resident_groups(ngauss, precision, cfg.variant, natoms);
+        const int fit = fock_resident_groups(ngauss, precision, cfg.variant, natoms, atoms);
         LF.groups = cus * (fit > 0 && cfg.gpc > fit ? fit : cfg.gpc);
         e = launch_fock(LF, b, ws, xw, tau, precision, strat, cfg.variant, d_dens, (double *)(ws + L.e2tmp), st);
         if (e != hipSuccess) return hip_fail(e, "Fock launch (W)");
@@ -509,6 +541,25 @@ hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss, cons
     e = launch_header_info(ws + L.hdr, 0, L.groups, precision, -1, st);
     if (e != hipSuccess) return hip_fail(e, "header launch");
     return HFK_OK;
+}
+
+hfk_status hfk_fock_grad(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
+                         const double *coefs_host, const double *dens, double tau, int32_t precision,
+                         const double *g_e2, const double *g_fock, const double *fock_in, double *d_xyz,
+                         double *d_dens, double *e2_out, void *workspace, size_t workspace_bytes, void *stream)
+{
+    return fock_grad_impl(false, natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision, g_e2, g_fock,
+                          fock_in, d_xyz, d_dens, e2_out, workspace, workspace_bytes, stream);
+}
+
+hfk_status hfk_fock_grad_atoms(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
+                               const double *coefs_host, const double *dens, double tau, int32_t precision,
+                               const double *g_e2, const double *g_fock, const double *fock_in, double *d_xyz,
+                               double *d_dens, double *e2_out, void *workspace, size_t workspace_bytes,
+                               void *stream)
+{
+    return fock_grad_impl(true, natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision, g_e2, g_fock,
+                          fock_in, d_xyz, d_dens, e2_out, workspace, workspace_bytes, stream);
 }
 
 static hfk_status check_batch(int64_t nmol, const int64_t *atom_off)

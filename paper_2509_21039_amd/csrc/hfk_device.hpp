@@ -38,7 +38,8 @@ __device__ inline void pair_prims(const Basis &b, const BasisDev *__restrict__ b
 // Per-atom bases: the same for atoms i (at A) and j (at B) with exponents and weights from
 // the atom rows, plus p = alpha_a + alpha_b of every primitive pair (a on i, b on j).
 __device__ inline void pair_prims_atoms(const Basis &b, int64_t i, int64_t j, const double *A, const double *B,
-                                        double *px, double *py, double *pz, double *ps, double *pp)
+                                        double *px, double *py, double *pz, double *ps, double *pp,
+                                        double *pmu = nullptr, double *pfa = nullptr)
 {
     const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
     const double ab2 = dx * dx + dy * dy + dz * dz;
@@ -53,6 +54,10 @@ __device__ inline void pair_prims_atoms(const Basis &b, int64_t i, int64_t j, co
         pz[ab] = fa * A[2] + fb * B[2];
         ps[ab] = wi[a] * wj[c] * exp(-(ei[a] * ej[c] / p) * ab2) * pow(kPi / p, 1.5);
         pp[ab] = p;
+        if (pmu) {
+            pmu[ab] = ei[a] * ej[c] / p;
+            pfa[ab] = fa;
+        }
     }
 }
 

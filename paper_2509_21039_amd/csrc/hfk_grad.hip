@@ -11,6 +11,12 @@
 //   d(ab|cd)/dD = -(dA + dB + dC)            (translation invariance)
 // Beyond the switch E = 1/r and W = -1/r^3 exactly; below it both come from Taylor tables.
 //
+// Per-atom bases (kAtoms): mu, a/p and rho differ per primitive pair and quartet.  The
+// switch radius^2 kTswitch / rho is the sum of the stored kTswitch / p of bra and ket (as in
+// the forward kernel); near steps derive sqrt(rho/h), rho/h and (rho/h)^(3/2) from it with
+// one reciprocal square root; the bra's (mu, a/p) come through scalar loads and the ket's
+// from two SoA tables read once per ket primitive pair.
+//
 // Work decomposition as in the forward kernel (items of 1024 kets of one bra, blocks of
 // items fetched from a global counter in the same bra-group order, 256 kets per wave packed
 // into full 64-lane chunks after the screen).  Bra-atom gradients accumulate in
@@ -35,6 +41,11 @@ struct GradArgs {
     const float *prim_f;
     const double *bra;
     const float *bra_f;
+    const double *bip;      // per-atom bases: [pcap][g2] kTswitch / p of the bra pairs (and FP32 copy)
+    const float *bip_f;
+    const double *kmu;      // per-atom bases: [g2][pcap] mu and a/p of the ket pairs
+    const double *kfa;
+    const double *bmf;      // per-atom bases: [pcap][g2][2] (mu, a/p) of the bra pairs
     const long long *item_off;
     const long long *goff;      // [ngroups + 1] block offsets of the bra groups
     int64_t ngroups;
@@ -54,6 +65,7 @@ template <typename R> struct GPrec;
 template <> struct GPrec<double> {
     static __device__ const double *prim(const GradArgs &a) { return a.prim; }
     static __device__ const double *bra(const GradArgs &a) { return a.bra; }
+    static __device__ const double *bip(const GradArgs &a) { return a.bip; }
     static __device__ const double *tabH(const GradArgs &a) { return a.tabH; }
     static __device__ const double *tabG(const GradArgs &a) { return a.tabG; }
     static __device__ const double *rsg(const BasisDev *bd) { return bd->rsg; }
@@ -62,16 +74,18 @@ template <> struct GPrec<double> {
 template <> struct GPrec<float> {
     static __device__ const float *prim(const GradArgs &a) { return a.prim_f; }
     static __device__ const float *bra(const GradArgs &a) { return a.bra_f; }
+    static __device__ const float *bip(const GradArgs &a) { return a.bip_f; }
     static __device__ const float *tabH(const GradArgs &a) { return a.tabH_f; }
     static __device__ const float *tabG(const GradArgs &a) { return a.tabG_f; }
     static __device__ const float *rsg(const BasisDev *bd) { return bd->rsg_f; }
     static __device__ float rsqrt(float x) { return rsqrt_fp32(x); }
 };
 
-template <int G, typename R>
+template <int G, typename R, bool kAtoms = false>
 __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
 {
     constexpr int G2 = G * G;
+    constexpr int kPComp = sizeof(R) == 8 ? 5 : 4;   // ket component holding kTswitch / p
     extern __shared__ double smem[];
     const int n = a.n;
     double *lg = smem;                                   // [n*3]
@@ -170,6 +184,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                 const bool valid = c0 + lane < nvalid;
                 const long long t = valid ? perm[c0 + lane] : S;   // S: first pad entry
                 const cptr<R> bra = (cptr<R>)(GPrec<R>::bra(a) + (int64_t)s * 8 * G2);
+                const cptr<R> bipp = kAtoms ? (cptr<R>)(GPrec<R>::bip(a) + (int64_t)s * G2) : nullptr;
+                const cptr<double> bmfp = kAtoms ? (cptr<double>)(a.bmf + (int64_t)s * 2 * G2) : nullptr;
 
                 R sX = R(0), eri = R(0);
                 R sYa[3] = {R(0), R(0), R(0)}, sYb[3] = {R(0), R(0), R(0)};
@@ -180,7 +196,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                 const double CDz = a.xyz[3 * k + 2] - a.xyz[3 * l + 2];
     #pragma unroll 1
                 for (int cb = 0; cb < G; ++cb) {
-                    R kx[G], ky[G], kz[G], ks[G];
+                    R kx[G], ky[G], kz[G], ks[G], kp[G];
                     R Uc[G], Vc[G][3];
                     // buffer loads of the ket table: component base, primitive pair as a
                     // scalar offset, ket as a 32-bit lane offset
@@ -202,6 +218,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                         ky[d] = ld(1, cd);
                         kz[d] = ld(2, cd);
                         ks[d] = ld(3, cd);
+                        kp[d] = kAtoms ? ld(kPComp, cd) : R(0);
                         Uc[d] = R(0);
                         Vc[d][0] = Vc[d][1] = Vc[d][2] = R(0);
                     }
@@ -209,26 +226,47 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                     for (int ab = 0; ab < G2; ++ab) {
                         // every scalar of this bra primitive in one batch of scalar loads
                         const cptr<R> bp = bra + 8 * ab;
-                        const cptr<R> up = rsg + 4 * (ab * G2 + cb * G);
-                        R b[4], u[4 * G];
+                        R b[4], u[4 * G], bsw = R(0);
+                        double bmu = 0.0, bfa = 0.0;
 #pragma unroll
                         for (int c = 0; c < 4; ++c) b[c] = bp[c];
+                        if constexpr (kAtoms) {
+                            bsw = bipp[ab];
+                            bmu = bmfp[2 * ab];
+                            bfa = bmfp[2 * ab + 1];
+                            asm volatile("" ::"s"(bsw));
+                        } else {
+                            const cptr<R> up = rsg + 4 * (ab * G2 + cb * G);
 #pragma unroll
-                        for (int c = 0; c < 4 * G; ++c) u[c] = up[c];
+                            for (int c = 0; c < 4 * G; ++c) u[c] = up[c];
 #pragma unroll
-                        for (int c = 0; c < 4 * G; ++c) asm volatile("" ::"s"(u[c]));
+                            for (int c = 0; c < 4 * G; ++c) asm volatile("" ::"s"(u[c]));
+                        }
                         const R px = b[0], py = b[1], pz = b[2], sab = b[3];
                         R U = R(0), V0 = R(0), V1 = R(0), V2 = R(0);
 #pragma unroll
                         for (int d = 0; d < G; ++d) {
                             const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
                             const R r2 = dx * dx + dy * dy + dz * dz;
-                            const bool near = r2 < u[4 * d];
+                            // switch radius^2 kTswitch / rho (per-atom bases: sum of the stored halves)
+                            const R sw = kAtoms ? bsw + kp[d] : u[4 * d];
+                            const bool near = r2 < sw;
                             R E, W;
                             if (__builtin_amdgcn_ballot_w64(near)) {
+                                // (rho/h, sqrt(rho/h), (rho/h)^(3/2)): from the table, or from sw
+                                R q1, q2, q3;
+                                if constexpr (kAtoms) {
+                                    q2 = rsqrt_r(sw) * R(kSqrtSwitchInvH);
+                                    q1 = q2 * q2;
+                                    q3 = q1 * q2;
+                                } else {
+                                    q1 = u[4 * d + 1];
+                                    q2 = u[4 * d + 2];
+                                    q3 = u[4 * d + 3];
+                                }
                                 // T' = T / h on the table grid; sqrt(h) H and h^(3/2) g, or their
                                 // far forms T'^(-1/2) and -T'^(-3/2)
-                                const R Ts = r2 * u[4 * d + 1];
+                                const R Ts = r2 * q1;
                                 const R y = GPrec<R>::rsqrt(Ts);
                                 const R Tc = fmin(Ts, R(kBoysGrid - 4));
                                 const R kd = rint(Tc);
@@ -242,8 +280,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                                     vh = vh * dd + ch[m];
                                     vg = vg * dd + cg[m];
                                 }
-                                E = u[4 * d + 2] * (near ? vh : y);
-                                W = u[4 * d + 3] * (near ? vg : -(y * y * y));
+                                E = q2 * (near ? vh : y);
+                                W = q3 * (near ? vg : -(y * y * y));
                             } else {
                                 const R y = GPrec<R>::rsqrt(r2);
                                 E = y;
@@ -261,8 +299,16 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                         }
                         const R su = sab * U;
                         eri += su;
-                        sX += (R)cmu[ab] * su;
-                        const R fa = (R)cfa[ab] * sab, fb = (R)cfb[ab] * sab;
+                        R fa, fb;
+                        if constexpr (kAtoms) {
+                            sX += (R)bmu * su;
+                            fa = (R)bfa * sab;
+                            fb = sab - fa;
+                        } else {
+                            sX += (R)cmu[ab] * su;
+                            fa = (R)cfa[ab] * sab;
+                            fb = (R)cfb[ab] * sab;
+                        }
                         sYa[0] += fa * V0; sYa[1] += fa * V1; sYa[2] += fa * V2;
                         sYb[0] += fb * V0; sYb[1] += fb * V1; sYb[2] += fb * V2;
                     }
@@ -270,8 +316,16 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                     for (int d = 0; d < G; ++d) {
                         const int cd = cb * G + d;
                         const double sc = (double)ks[d];
-                        const double mu2 = -2.0 * cmu[cd] * sc * (double)Uc[d];
-                        const double fc = cfa[cd] * sc;
+                        double kmu, kfa;
+                        if constexpr (kAtoms) {
+                            kmu = a.kmu[(int64_t)cd * a.pcap + t];
+                            kfa = a.kfa[(int64_t)cd * a.pcap + t];
+                        } else {
+                            kmu = cmu[cd];
+                            kfa = cfa[cd];
+                        }
+                        const double mu2 = -2.0 * kmu * sc * (double)Uc[d];
+                        const double fc = kfa * sc;
                         kC[0] += mu2 * CDx - fc * (double)Vc[d][0];
                         kC[1] += mu2 * CDy - fc * (double)Vc[d][1];
                         kC[2] += mu2 * CDz - fc * (double)Vc[d][2];
@@ -402,11 +456,14 @@ size_t grad_smem_bytes(int64_t n, int prec)
 }
 
 template <int G, typename R>
-static hipError_t launch_grad_t(const GradArgs &a, int groups, size_t smem, hipStream_t st)
+static hipError_t launch_grad_t(const GradArgs &a, int groups, size_t smem, bool atoms, hipStream_t st)
 {
     const hipError_t ez = launch_zero_counter(a.next_block, st);
     if (ez != hipSuccess) return ez;
-    hipLaunchKernelGGL((k_grad<G, R>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+    if (atoms)
+        hipLaunchKernelGGL((k_grad<G, R, true>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+    else
+        hipLaunchKernelGGL((k_grad<G, R, false>), dim3(groups), dim3(kGroupThreads), smem, st, a);
     return hipGetLastError();
 }
 
@@ -429,6 +486,12 @@ hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *
     a.prim_f = (const float *)(ws + L.prim_f);
     a.bra = (const double *)(ws + L.bra);
     a.bra_f = (const float *)(ws + L.bra_f);
+    const bool at = L.atoms && L.pmu;
+    a.bip = at ? (const double *)(ws + L.bip) : nullptr;
+    a.bip_f = at ? (const float *)(ws + L.bip_f) : nullptr;
+    a.kmu = at ? (const double *)(ws + L.pmu) : nullptr;
+    a.kfa = at ? (const double *)(ws + L.pfa) : nullptr;
+    a.bmf = at ? (const double *)(ws + L.bmf) : nullptr;
     a.item_off = (const long long *)(ws + L.item_off);
     a.lim = (const int *)(ws + L.lim);
     a.goff = (const long long *)(ws + L.goff);
@@ -446,21 +509,21 @@ hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *
     hipError_t err;
     if (prec == HFK_MIXED) {
         switch (b.g) {
-        case 1: err = launch_grad_t<1, float>(a, L.groups, smem, st); break;
-        case 2: err = launch_grad_t<2, float>(a, L.groups, smem, st); break;
-        case 3: err = launch_grad_t<3, float>(a, L.groups, smem, st); break;
-        case 4: err = launch_grad_t<4, float>(a, L.groups, smem, st); break;
-        case 5: err = launch_grad_t<5, float>(a, L.groups, smem, st); break;
-        default: err = launch_grad_t<6, float>(a, L.groups, smem, st); break;
+        case 1: err = launch_grad_t<1, float>(a, L.groups, smem, at, st); break;
+        case 2: err = launch_grad_t<2, float>(a, L.groups, smem, at, st); break;
+        case 3: err = launch_grad_t<3, float>(a, L.groups, smem, at, st); break;
+        case 4: err = launch_grad_t<4, float>(a, L.groups, smem, at, st); break;
+        case 5: err = launch_grad_t<5, float>(a, L.groups, smem, at, st); break;
+        default: err = launch_grad_t<6, float>(a, L.groups, smem, at, st); break;
         }
     } else {
         switch (b.g) {
-        case 1: err = launch_grad_t<1, double>(a, L.groups, smem, st); break;
-        case 2: err = launch_grad_t<2, double>(a, L.groups, smem, st); break;
-        case 3: err = launch_grad_t<3, double>(a, L.groups, smem, st); break;
-        case 4: err = launch_grad_t<4, double>(a, L.groups, smem, st); break;
-        case 5: err = launch_grad_t<5, double>(a, L.groups, smem, st); break;
-        default: err = launch_grad_t<6, double>(a, L.groups, smem, st); break;
+        case 1: err = launch_grad_t<1, double>(a, L.groups, smem, at, st); break;
+        case 2: err = launch_grad_t<2, double>(a, L.groups, smem, at, st); break;
+        case 3: err = launch_grad_t<3, double>(a, L.groups, smem, at, st); break;
+        case 4: err = launch_grad_t<4, double>(a, L.groups, smem, at, st); break;
+        case 5: err = launch_grad_t<5, double>(a, L.groups, smem, at, st); break;
+        default: err = launch_grad_t<6, double>(a, L.groups, smem, at, st); break;
         }
     }
     if (err != hipSuccess) return err;

@@ -120,6 +120,8 @@ struct Layout {
     bool atoms;                            // per-atom bases: the tables below are present
     size_t arow;                           // [2][n][g] exponents and weights of every atom
     size_t bip, bip_f;                     // [pcap][g2] kTswitch/p of every bra primitive pair
+    size_t pmu, pfa;                       // per-atom gradient: [g2][pcap] mu and a/p of the ket pairs
+    size_t bmf;                            // per-atom gradient: [pcap][g2][2] (mu, a/p) of the bra pairs
     size_t bra, bra_f;                     // [pcap][g2][8] Px Py Pz S -2Px -2Py -2Pz |P|^2 (wave-uniform bra data)
     size_t boys_g, boys_g_f;               // Taylor table of g(T) = -(4/sqrt(pi)) F1(T) (gradient)
     size_t nitems, lim, item_off, scan_tmp;

@@ -262,7 +262,8 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
                                                       double *__restrict__ pd, double *__restrict__ prim,
                                                       float *__restrict__ prim_f, double *__restrict__ bra,
                                                       float *__restrict__ bra_f, double *__restrict__ bip,
-                                                      float *__restrict__ bip_f)
+                                                      float *__restrict__ bip_f, double *__restrict__ kmu,
+                                                      double *__restrict__ kfa, double *__restrict__ bmf)
 {
     const int64_t npair = n * (n + 1) / 2;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -275,9 +276,9 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
     const double c0 = hdr->centroid[0], c1 = hdr->centroid[1], c2 = hdr->centroid[2];
     double A[3] = {xyz[3 * i] - c0, xyz[3 * i + 1] - c1, xyz[3 * i + 2] - c2};
     double B[3] = {xyz[3 * j] - c0, xyz[3 * j + 1] - c1, xyz[3 * j + 2] - c2};
-    double px[kMaxG2], py[kMaxG2], pz[kMaxG2], ps[kMaxG2], pp[kMaxG2];
+    double px[kMaxG2], py[kMaxG2], pz[kMaxG2], ps[kMaxG2], pp[kMaxG2], mu[kMaxG2], fa[kMaxG2];
     if (b.aexp)
-        pair_prims_atoms(b, i, j, A, B, px, py, pz, ps, pp);
+        pair_prims_atoms(b, i, j, A, B, px, py, pz, ps, pp, mu, fa);
     else
         pair_prims(b, bd, A, B, px, py, pz, ps);
     pk[pos] = (int)i;
@@ -313,6 +314,15 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
             bip_f[(int64_t)pos * g2 + ab] = (float)ip;
         }
     }
+    if (kmu) {
+        // per-atom gradient: mu and a/p of every primitive pair, ket-major and bra-major
+        for (int ab = 0; ab < g2; ++ab) {
+            kmu[(int64_t)ab * pcap + pos] = mu[ab];
+            kfa[(int64_t)ab * pcap + pos] = fa[ab];
+            bmf[((int64_t)pos * g2 + ab) * 2] = mu[ab];
+            bmf[((int64_t)pos * g2 + ab) * 2 + 1] = fa[ab];
+        }
+    }
 }
 
 // Pads the tail chunk of the sorted tables with harmless entries (atom 0, zero weight,
@@ -320,9 +330,11 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
 // pad entry, read defined memory and land in the far branch with a zero integral.
 // ncomp: FP64 components of the ket table (4: Px Py Pz S; 5 adds |P|^2; 6 adds kTswitch/p
 // of per-atom bases, which then is FP32 component 4).
+// kmu/kfa (per-atom gradient tables, or NULL) are zeroed there too.
 __global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int g2, int ncomp,
                            int *__restrict__ pk, int *__restrict__ pl, double *__restrict__ pq,
-                           double *__restrict__ pd, double *__restrict__ prim, float *__restrict__ prim_f)
+                           double *__restrict__ pd, double *__restrict__ prim, float *__restrict__ prim_f,
+                           double *__restrict__ kmu, double *__restrict__ kfa)
 {
     const int64_t s = hdr->sig_pairs;
     const int64_t pos = s + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -341,6 +353,10 @@ __global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int 
             prim[(5 * g2 + ab) * pcap + pos] = 1.0;
             prim_f[(4 * g2 + ab) * pcap + pos] = 1.0f;
         }
+        if (kmu) {
+            kmu[(int64_t)ab * pcap + pos] = 0.0;
+            kfa[(int64_t)ab * pcap + pos] = 0.0;
+        }
     }
 }
 
@@ -349,7 +365,7 @@ hipError_t launch_pair_pad(const DevHeader *hdr, int64_t pcap, int g2, int *pk, 
 {
     // the batched tables hold the four-component FP64 ket table
     hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((pcap + 255) / 256)), dim3(256), 0, st, hdr, pcap, g2, 4, pk, pl,
-                       pq, pd, prim, prim_f);
+                       pq, pd, prim, prim_f, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -540,11 +556,13 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f), (double *)(ws + L.bra),
                        (float *)(ws + L.bra_f), L.atoms ? (double *)(ws + L.bip) : nullptr,
-                       L.atoms ? (float *)(ws + L.bip_f) : nullptr);
+                       L.atoms ? (float *)(ws + L.bip_f) : nullptr, L.pmu ? (double *)(ws + L.pmu) : nullptr,
+                       L.pmu ? (double *)(ws + L.pfa) : nullptr, L.pmu ? (double *)(ws + L.bmf) : nullptr);
     hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, L.pcap, L.g2,
                        L.atoms ? 6 : 5,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
-                       (double *)(ws + L.prim), (float *)(ws + L.prim_f));
+                       (double *)(ws + L.prim), (float *)(ws + L.prim_f), L.pmu ? (double *)(ws + L.pmu) : nullptr,
+                       L.pmu ? (double *)(ws + L.pfa) : nullptr);
     hipLaunchKernelGGL(k_limits, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, tau,
                        (const double *)(ws + L.pq), off, (long long *)(ws + L.nitems), (int *)(ws + L.lim),
                        L.pcap);

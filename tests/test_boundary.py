@@ -21,7 +21,7 @@ def test_header_declares_entry_points():
     names = _declared_symbols()
     for must in ("hfk_fock", "hfk_fock_grad", "hfk_fock_batched", "hfk_workspace_bytes",
                  "hfk_batched_workspace_bytes", "hfk_read_stats", "hfk_tune", "hfk_last_error",
-                 "hfk_fock_atoms", "hfk_workspace_bytes_atoms"):
+                 "hfk_fock_atoms", "hfk_workspace_bytes_atoms", "hfk_fock_grad_atoms"):
         assert must in names
 
 
@@ -195,12 +195,26 @@ def test_fock_atoms_rejects_invalid_arguments(kw, msg):
 def test_workspace_bytes_atoms_validation():
     out = ctypes.c_size_t(0)
     L = hfk.lib()
-    assert L.hfk_workspace_bytes_atoms(0, 3, 0, ctypes.byref(out)) == hfk.HFK_EINVAL
-    assert L.hfk_workspace_bytes_atoms(10, 9, 0, ctypes.byref(out)) == hfk.HFK_EINVAL
-    assert L.hfk_workspace_bytes_atoms(10, 3, 4, ctypes.byref(out)) == hfk.HFK_EINVAL
-    assert L.hfk_workspace_bytes_atoms(10, 3, 0, None) == hfk.HFK_EINVAL
-    assert L.hfk_workspace_bytes_atoms(100000, 3, 0, ctypes.byref(out)) == hfk.HFK_EUNSUPPORTED
-    assert L.hfk_workspace_bytes_atoms(300, 3, 0, ctypes.byref(out)) == hfk.HFK_OK
+    assert L.hfk_workspace_bytes_atoms(0, 3, 0, 0, ctypes.byref(out)) == hfk.HFK_EINVAL
+    assert L.hfk_workspace_bytes_atoms(10, 9, 0, 0, ctypes.byref(out)) == hfk.HFK_EINVAL
+    assert L.hfk_workspace_bytes_atoms(10, 3, 4, 0, ctypes.byref(out)) == hfk.HFK_EINVAL
+    assert L.hfk_workspace_bytes_atoms(10, 3, 0, 0, None) == hfk.HFK_EINVAL
+    assert L.hfk_workspace_bytes_atoms(100000, 3, 0, 0, ctypes.byref(out)) == hfk.HFK_EUNSUPPORTED
+    assert L.hfk_workspace_bytes_atoms(5000, 3, 0, 1, ctypes.byref(out)) == hfk.HFK_EUNSUPPORTED
+    assert L.hfk_workspace_bytes_atoms(300, 3, 0, 0, ctypes.byref(out)) == hfk.HFK_OK
     atoms = out.value
     assert L.hfk_workspace_bytes(300, 3, 0, 0, ctypes.byref(out)) == hfk.HFK_OK
     assert atoms > out.value   # the per-atom tables come on top of the one-basis layout
+    assert L.hfk_workspace_bytes_atoms(300, 3, 0, 1, ctypes.byref(out)) == hfk.HFK_OK
+    assert out.value > atoms   # and the gradient's tables on top of those
+
+
+def test_fock_grad_atoms_rejects_bad_rows():
+    e = np.tile([6.36242139, 1.158923, 0.31364979], (4, 1))
+    c = np.tile([0.15432897, 0.53532814, 0.44463454], (4, 1))
+    e[3, 2] = -0.5
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = hfk.lib().hfk_fock_grad_atoms(4, 1, 3, e.ctypes.data_as(dp), c.ctypes.data_as(dp), 1, 1e-10, 0, 1, None,
+                                       None, 1, None, None, 256, 1 << 40, None)
+    assert st == hfk.HFK_EINVAL
+    assert "atom 3" in hfk.lib().hfk_last_error().decode()
