@@ -169,3 +169,14 @@ def tight_cluster() -> System:
     s.exps = TIGHT_EXPS.copy()
     s.coefs = TIGHT_COEFS.copy()
     return s
+
+
+def hhe_rows(n: int, seed: int, frac_h: float = 0.5):
+    """(n, 3) per-atom rows for stacked atoms: one (n,) draw of U[0, 1) marks hydrogen when
+    below ``frac_h`` (STO-3G hydrogen exponents), helium otherwise; both with the STO-3G
+    coefficients."""
+    rng = _rng(seed)
+    is_h = rng.uniform(0.0, 1.0, size=n) < frac_h
+    exps = np.where(is_h[:, None], H_STO3G_EXPS[None, :], HE_STO3G_EXPS[None, :])
+    coefs = np.broadcast_to(HE_STO3G_COEFS, (n, 3)).copy()
+    return exps, coefs

@@ -195,6 +195,25 @@ hfk_status hfk_fock_batched(int64_t nmol, const int64_t *atom_off_host, const do
                             double *fock_packed, double *e2, double *d_xyz,
                             void *workspace, size_t workspace_bytes, void *stream);
 
+/* Ragged batches with per-atom bases (see hfk_fock_atoms): workspace size, arguments and
+ * errors as hfk_batched_workspace_bytes. */
+hfk_status hfk_batched_workspace_bytes_atoms(int64_t nmol, const int64_t *atom_off_host,
+                                             int32_t ngauss, int32_t precision, int32_t with_grad,
+                                             size_t *bytes_out);
+
+/* hfk_fock_batched with per-atom bases:
+ *   exps_host    [sum n * ngauss] row a: the exponents of stacked atom a (molecule m's atoms
+ *                are rows atom_off_host[m] .. atom_off_host[m+1]), each > 0 and finite
+ *   coefs_host   [sum n * ngauss] the matching contraction coefficients, finite
+ * Every row is validated on the host and copied into the workspace before the call returns.
+ * Other arguments, outputs and errors as hfk_fock_batched; the workspace is sized by
+ * hfk_batched_workspace_bytes_atoms. */
+hfk_status hfk_fock_batched_atoms(int64_t nmol, const int64_t *atom_off_host, const double *xyz,
+                                  int32_t ngauss, const double *exps_host, const double *coefs_host,
+                                  const double *dens_packed, double tau, int32_t precision,
+                                  double *fock_packed, double *e2, double *d_xyz,
+                                  void *workspace, size_t workspace_bytes, void *stream);
+
 /* Waits for `stream`, then copies the counters of the last build made with `workspace`
  * into *out.  Errors: HFK_EINVAL for NULL arguments, HFK_EHIP. */
 hfk_status hfk_read_stats(const void *workspace, void *stream, hfk_stats *out);

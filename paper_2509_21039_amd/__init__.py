@@ -72,6 +72,10 @@ _SIGNATURES = {
     "hfk_profile_read": [ctypes.POINTER(ctypes.c_double), _i64p],
     "hfk_workspace_bytes_atoms": [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.POINTER(_sz)],
+    "hfk_batched_workspace_bytes_atoms": [ctypes.c_int64, _i64p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(_sz)],
+    "hfk_fock_batched_atoms": [ctypes.c_int64, _i64p, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double,
+                               ctypes.c_int32, _vp, _vp, _vp, _vp, _sz, _vp],
     "hfk_fock_grad_atoms": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
     "hfk_fock_atoms": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
@@ -318,34 +322,43 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-def batched_workspace_bytes(atom_off, ngauss=3, precision="mixed", with_grad=True) -> int:
+def batched_workspace_bytes(atom_off, ngauss=3, precision="mixed", with_grad=True, atoms=False) -> int:
     off = np.ascontiguousarray(np.asarray(atom_off, dtype=np.int64))
     out = _sz(0)
-    _check(lib().hfk_batched_workspace_bytes(len(off) - 1, off.ctypes.data_as(_i64p), int(ngauss),
-                                             _PREC[precision], int(bool(with_grad)), ctypes.byref(out)))
+    call = lib().hfk_batched_workspace_bytes_atoms if atoms else lib().hfk_batched_workspace_bytes
+    _check(call(len(off) - 1, off.ctypes.data_as(_i64p), int(ngauss), _PREC[precision], int(bool(with_grad)),
+                ctypes.byref(out)))
     return out.value
 
 
 def fock_batched(atom_off, xyz, dens_packed, exps, coefs, tau, precision="mixed", with_grad=True,
                  workspace=None, stream=None):
-    """Ragged batch in one persistent launch: (fock_packed, e2[nmol], d_xyz or None)."""
+    """Ragged batch in one persistent launch: (fock_packed, e2[nmol], d_xyz or None).  exps/coefs:
+    one contraction (1-D) for every atom, or per-atom rows (sum n, ngauss) over the stacked atoms."""
     torch = _torch()
     off = np.ascontiguousarray(np.asarray(atom_off, dtype=np.int64))
     nmol = len(off) - 1
     _dev_f64(xyz, "xyz", (int(off[-1]), 3))
     _dev_f64(dens_packed, "dens_packed")
-    e = _host_f64(exps)
-    c = _host_f64(coefs)
+    atoms = np.ndim(exps) == 2
+    if atoms:
+        e, c = _rows(exps, coefs, int(off[-1]))
+        g = e.shape[1]
+    else:
+        e = _host_f64(exps)
+        c = _host_f64(coefs)
+        g = len(e)
     prec = _PREC[precision]
     if workspace is None:
-        workspace = new_workspace(batched_workspace_bytes(off, len(e), prec, with_grad), xyz.device)
+        workspace = new_workspace(batched_workspace_bytes(off, g, prec, with_grad, atoms), xyz.device)
     F = torch.empty_like(dens_packed)
     E2 = torch.empty((nmol,), dtype=torch.float64, device=xyz.device)
     d_xyz = torch.empty_like(xyz) if with_grad else None
-    _check(lib().hfk_fock_batched(nmol, off.ctypes.data_as(_i64p), xyz.data_ptr(), len(e), _dptr(e), _dptr(c),
-                                  dens_packed.data_ptr(), float(tau), prec, F.data_ptr(), E2.data_ptr(),
-                                  d_xyz.data_ptr() if d_xyz is not None else None, workspace.data_ptr(),
-                                  workspace.numel(), _stream_handle(stream)))
+    call = lib().hfk_fock_batched_atoms if atoms else lib().hfk_fock_batched
+    _check(call(nmol, off.ctypes.data_as(_i64p), xyz.data_ptr(), g, _dptr(e), _dptr(c),
+                dens_packed.data_ptr(), float(tau), prec, F.data_ptr(), E2.data_ptr(),
+                d_xyz.data_ptr() if d_xyz is not None else None, workspace.data_ptr(),
+                workspace.numel(), _stream_handle(stream)))
     return F, E2, d_xyz
 
 

@@ -359,7 +359,7 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
 // Per-atom bases: exponents and weights of every atom, [2][n][g], copied to the workspace
 // (pageable host memory: the copy completes before hipMemcpyAsync returns), and the Basis
 // that points the kernels at them.
-static hipError_t upload_rows(const Layout &L, char *ws, int64_t natoms, int32_t ngauss, const double *exps,
+static hipError_t upload_rows(double *arow, int64_t natoms, int32_t ngauss, const double *exps,
                               const double *coefs, hipStream_t st, Basis *b)
 {
     const size_t ng = (size_t)natoms * (size_t)ngauss;
@@ -368,7 +368,6 @@ static hipError_t upload_rows(const Layout &L, char *ws, int64_t natoms, int32_t
         rows[x] = exps[x];
         rows[ng + x] = coefs[x] * pow(2.0 * exps[x] / 3.14159265358979323846, 0.75);
     }
-    double *arow = (double *)(ws + L.arow);
     memset(b, 0, sizeof(*b));
     b->g = ngauss;
     b->g2 = ngauss * ngauss;
@@ -432,7 +431,7 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
     Basis b;
-    hipError_t e = upload_rows(L, ws, natoms, ngauss, exps_host, coefs_host, st, &b);
+    hipError_t e = upload_rows((double *)(ws + L.arow), natoms, ngauss, exps_host, coefs_host, st, &b);
     if (e != hipSuccess) return hip_fail(e, "basis rows copy");
     e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (float *)(ws + L.boys_f),
                      (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz,
@@ -501,7 +500,7 @@ static hfk_status fock_grad_impl(bool atoms, int64_t natoms, const double *xyz, 
     hipStream_t st = (hipStream_t)stream;
     Basis b;
     if (atoms) {
-        const hipError_t eu = upload_rows(L, ws, natoms, ngauss, exps_host, coefs_host, st, &b);
+        const hipError_t eu = upload_rows((double *)(ws + L.arow), natoms, ngauss, exps_host, coefs_host, st, &b);
         if (eu != hipSuccess) return hip_fail(eu, "basis rows copy");
     } else {
         b = make_basis(ngauss, exps_host, coefs_host);
@@ -577,8 +576,8 @@ static hfk_status check_batch(int64_t nmol, const int64_t *atom_off)
     return HFK_OK;
 }
 
-hfk_status hfk_batched_workspace_bytes(int64_t nmol, const int64_t *atom_off_host, int32_t ngauss,
-                                       int32_t precision, int32_t with_grad, size_t *bytes_out)
+static hfk_status batched_ws_impl(bool atoms, int64_t nmol, const int64_t *atom_off_host, int32_t ngauss,
+                                  int32_t precision, int32_t with_grad, size_t *bytes_out)
 {
     g_err[0] = 0;
     if (!bytes_out) return fail(HFK_EINVAL, "bytes_out is NULL");
@@ -588,33 +587,58 @@ hfk_status hfk_batched_workspace_bytes(int64_t nmol, const int64_t *atom_off_hos
         return fail(HFK_EINVAL, "precision must be HFK_FP64 or HFK_MIXED (got %d)", (int)precision);
     hfk_status s = check_batch(nmol, atom_off_host);
     if (s != HFK_OK) return s;
-    *bytes_out = make_blayout(nmol, atom_off_host, ngauss, with_grad).total;
+    *bytes_out = make_blayout(nmol, atom_off_host, ngauss, with_grad, atoms).total;
     return HFK_OK;
 }
 
-hfk_status hfk_fock_batched(int64_t nmol, const int64_t *atom_off_host, const double *xyz, int32_t ngauss,
-                            const double *exps_host, const double *coefs_host, const double *dens_packed,
-                            double tau, int32_t precision, double *fock_packed, double *e2, double *d_xyz,
-                            void *workspace, size_t workspace_bytes, void *stream)
+hfk_status hfk_batched_workspace_bytes(int64_t nmol, const int64_t *atom_off_host, int32_t ngauss,
+                                       int32_t precision, int32_t with_grad, size_t *bytes_out)
+{
+    return batched_ws_impl(false, nmol, atom_off_host, ngauss, precision, with_grad, bytes_out);
+}
+
+hfk_status hfk_batched_workspace_bytes_atoms(int64_t nmol, const int64_t *atom_off_host, int32_t ngauss,
+                                             int32_t precision, int32_t with_grad, size_t *bytes_out)
+{
+    return batched_ws_impl(true, nmol, atom_off_host, ngauss, precision, with_grad, bytes_out);
+}
+
+// hfk_fock_batched and hfk_fock_batched_atoms (atoms: exps/coefs are per-atom rows over the
+// stacked atoms of the batch).
+static hfk_status fock_batched_impl(bool atoms, int64_t nmol, const int64_t *atom_off_host, const double *xyz,
+                                    int32_t ngauss, const double *exps_host, const double *coefs_host,
+                                    const double *dens_packed, double tau, int32_t precision, double *fock_packed,
+                                    double *e2, double *d_xyz, void *workspace, size_t workspace_bytes, void *stream)
 {
     g_err[0] = 0;
     hfk_status s = check_batch(nmol, atom_off_host);
     if (s != HFK_OK) return s;
     s = check_common(atom_off_host[nmol], xyz, ngauss, exps_host, coefs_host, dens_packed, tau, precision);
     if (s != HFK_OK) return s;
+    if (atoms) {
+        s = check_rows(atom_off_host[nmol], ngauss, exps_host, coefs_host);
+        if (s != HFK_OK) return s;
+    }
     if (!fock_packed) return fail(HFK_EINVAL, "fock_packed is NULL");
     if (!e2) return fail(HFK_EINVAL, "e2 is NULL");
     if (!workspace) return fail(HFK_EINVAL, "workspace is NULL");
     if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
     if (ngauss > kMaxBuiltG) return fail(HFK_EUNSUPPORTED, "ngauss above %d is not built in this version", kMaxBuiltG);
-    const BLayout L = make_blayout(nmol, atom_off_host, ngauss, d_xyz != nullptr);
+    const BLayout L = make_blayout(nmol, atom_off_host, ngauss, d_xyz != nullptr, atoms);
     if (workspace_bytes < L.total)
         return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
     const int cus = device_cu_count();
     if (cus <= 0) return fail(HFK_EHIP, "no HIP device");
-    const Basis b = make_basis(ngauss, exps_host, coefs_host);
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
+    Basis b;
+    if (atoms) {
+        const hipError_t eu = upload_rows((double *)(ws + L.arow), atom_off_host[nmol], ngauss, exps_host,
+                                          coefs_host, st, &b);
+        if (eu != hipSuccess) return hip_fail(eu, "basis rows copy");
+    } else {
+        b = make_basis(ngauss, exps_host, coefs_host);
+    }
     hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (float *)(ws + L.boys_f),
                                 (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr),
                                 atom_off_host[nmol], xyz, st);
@@ -625,6 +649,24 @@ hfk_status hfk_fock_batched(int64_t nmol, const int64_t *atom_off_host, const do
     e = launch_header_info(ws + L.hdr, 0, cus * gpc, precision, -1, st);
     if (e != hipSuccess) return hip_fail(e, "header launch");
     return HFK_OK;
+}
+
+hfk_status hfk_fock_batched(int64_t nmol, const int64_t *atom_off_host, const double *xyz, int32_t ngauss,
+                            const double *exps_host, const double *coefs_host, const double *dens_packed,
+                            double tau, int32_t precision, double *fock_packed, double *e2, double *d_xyz,
+                            void *workspace, size_t workspace_bytes, void *stream)
+{
+    return fock_batched_impl(false, nmol, atom_off_host, xyz, ngauss, exps_host, coefs_host, dens_packed, tau,
+                             precision, fock_packed, e2, d_xyz, workspace, workspace_bytes, stream);
+}
+
+hfk_status hfk_fock_batched_atoms(int64_t nmol, const int64_t *atom_off_host, const double *xyz, int32_t ngauss,
+                                  const double *exps_host, const double *coefs_host, const double *dens_packed,
+                                  double tau, int32_t precision, double *fock_packed, double *e2, double *d_xyz,
+                                  void *workspace, size_t workspace_bytes, void *stream)
+{
+    return fock_batched_impl(true, nmol, atom_off_host, xyz, ngauss, exps_host, coefs_host, dens_packed, tau,
+                             precision, fock_packed, e2, d_xyz, workspace, workspace_bytes, stream);
 }
 
 // ------------------------------------------------------------------ autotuner

@@ -10,6 +10,10 @@
 // global atomics when the molecule or the block changes.  Per primitive quartet the loop forms E(r) (the integral) and
 // W(r) = E'(r)/r (its radial derivative) from the same r^2, so the forward result and the
 // gradient come out of one pass over the quartets.
+//
+// Per-atom bases (kAtoms): pair bounds and tables come from the atom rows; the ket table's
+// component 4 and a per-bra uniform array hold kTswitch / p, whose sum is the quartet's
+// switch radius^2, and near steps derive rho from it (as in the single-molecule kernels).
 #include <string.h>
 
 #include <vector>
@@ -34,6 +38,11 @@ struct BArgs {
     const float *prim_f;
     const double *bra;
     const float *bra_f;
+    const double *bip;      // per-atom bases: [pcap][g2] kTswitch / p of the bra pairs (and FP32)
+    const float *bip_f;
+    const double *kmu;      // per-atom gradient: [g2][pcap] ket mu and a/p, [pcap][g2][2] bra
+    const double *kfa;
+    const double *bmf;
     const long long *item_off;
     const int *lim;
     const int *klo;
@@ -56,6 +65,7 @@ template <typename R> struct BPrec;
 template <> struct BPrec<double> {
     static __device__ const double *prim(const BArgs &a) { return a.prim; }
     static __device__ const double *bra(const BArgs &a) { return a.bra; }
+    static __device__ const double *bip(const BArgs &a) { return a.bip; }
     static __device__ const double *tabH(const BArgs &a) { return a.tabH; }
     static __device__ const double *tabG(const BArgs &a) { return a.tabG; }
     static __device__ const double *rsg(const BasisDev *bd) { return bd->rsg; }
@@ -63,6 +73,7 @@ template <> struct BPrec<double> {
 template <> struct BPrec<float> {
     static __device__ const float *prim(const BArgs &a) { return a.prim_f; }
     static __device__ const float *bra(const BArgs &a) { return a.bra_f; }
+    static __device__ const float *bip(const BArgs &a) { return a.bip_f; }
     static __device__ const float *tabH(const BArgs &a) { return a.tabH_f; }
     static __device__ const float *tabG(const BArgs &a) { return a.tabG_f; }
     static __device__ const float *rsg(const BasisDev *bd) { return bd->rsg_f; }
@@ -110,15 +121,25 @@ __global__ __launch_bounds__(256) void k_b_pair_q(Basis b, const BasisDev *__res
     const double *xa = xyz + 3 * (aoff[m] + i), *xb = xyz + 3 * (aoff[m] + j);
     double A[3] = {xa[0] - c[0], xa[1] - c[1], xa[2] - c[2]};
     double B[3] = {xb[0] - c[0], xb[1] - c[1], xb[2] - c[2]};
-    double px[kMaxG2], py[kMaxG2], pz[kMaxG2], ps[kMaxG2];
-    pair_prims(b, bd, A, B, px, py, pz, ps);
+    double px[kMaxG2], py[kMaxG2], pz[kMaxG2], ps[kMaxG2], pp[kMaxG2];
     double s = 0.0;
-    for (int ab = 0; ab < b.g2; ++ab)
-        for (int cd = 0; cd < b.g2; ++cd) {
-            const double dx = px[ab] - px[cd], dy = py[ab] - py[cd], dz = pz[ab] - pz[cd];
-            s += ps[ab] * ps[cd] * bd->srho[ab * b.g2 + cd] *
-                 erf_over_sqrt(bd->rho[ab * b.g2 + cd] * (dx * dx + dy * dy + dz * dz));
-        }
+    if (b.aexp) {
+        pair_prims_atoms(b, aoff[m] + i, aoff[m] + j, A, B, px, py, pz, ps, pp);
+        for (int ab = 0; ab < b.g2; ++ab)
+            for (int cd = 0; cd < b.g2; ++cd) {
+                const double dx = px[ab] - px[cd], dy = py[ab] - py[cd], dz = pz[ab] - pz[cd];
+                const double rho = pp[ab] * pp[cd] / (pp[ab] + pp[cd]);
+                s += ps[ab] * ps[cd] * sqrt(rho) * erf_over_sqrt(rho * (dx * dx + dy * dy + dz * dz));
+            }
+    } else {
+        pair_prims(b, bd, A, B, px, py, pz, ps);
+        for (int ab = 0; ab < b.g2; ++ab)
+            for (int cd = 0; cd < b.g2; ++cd) {
+                const double dx = px[ab] - px[cd], dy = py[ab] - py[cd], dz = pz[ab] - pz[cd];
+                s += ps[ab] * ps[cd] * bd->srho[ab * b.g2 + cd] *
+                     erf_over_sqrt(bd->rho[ab * b.g2 + cd] * (dx * dx + dy * dy + dz * dz));
+            }
+    }
     const double q = sqrt(s);
     qout[p] = q;
     atomicMax(&qmax[m], (unsigned long long)__double_as_longlong(q));
@@ -159,7 +180,9 @@ __global__ __launch_bounds__(256) void k_b_pair_scatter(
     const double *__restrict__ cent, const double *__restrict__ xyz, const double *__restrict__ dens, long long ptot,
     int64_t pcap, const double *__restrict__ q, const int *__restrict__ bucket_of, int *__restrict__ cur,
     int *__restrict__ pk, int *__restrict__ pl, int *__restrict__ pm, double *__restrict__ pq, double *__restrict__ pd,
-    double *__restrict__ prim, float *__restrict__ prim_f, double *__restrict__ bra, float *__restrict__ bra_f)
+    double *__restrict__ prim, float *__restrict__ prim_f, double *__restrict__ bra, float *__restrict__ bra_f,
+    double *__restrict__ bip, float *__restrict__ bip_f, double *__restrict__ kmu, double *__restrict__ kfa,
+    double *__restrict__ bmf)
 {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ptot) return;
@@ -173,8 +196,11 @@ __global__ __launch_bounds__(256) void k_b_pair_scatter(
     const double *xa = xyz + 3 * (aoff[m] + i), *xb = xyz + 3 * (aoff[m] + j);
     double A[3] = {xa[0] - c[0], xa[1] - c[1], xa[2] - c[2]};
     double B[3] = {xb[0] - c[0], xb[1] - c[1], xb[2] - c[2]};
-    double px[kMaxG2], py[kMaxG2], pz[kMaxG2], ps[kMaxG2];
-    pair_prims(b, bd, A, B, px, py, pz, ps);
+    double px[kMaxG2], py[kMaxG2], pz[kMaxG2], ps[kMaxG2], pp[kMaxG2], mu[kMaxG2], fa[kMaxG2];
+    if (b.aexp)
+        pair_prims_atoms(b, aoff[m] + i, aoff[m] + j, A, B, px, py, pz, ps, pp, mu, fa);
+    else
+        pair_prims(b, bd, A, B, px, py, pz, ps);
     pk[pos] = (int)i;
     pl[pos] = (int)j;
     pm[pos] = m;
@@ -192,11 +218,28 @@ __global__ __launch_bounds__(256) void k_b_pair_scatter(
         prim_f[(3 * g2 + ab) * pcap + pos] = (float)ps[ab];
         double *ba = bra + ((int64_t)pos * g2 + ab) * 8;
         float *bf = bra_f + ((int64_t)pos * g2 + ab) * 8;
-        const double pp = px[ab] * px[ab] + py[ab] * py[ab] + pz[ab] * pz[ab];
+        const double p2 = px[ab] * px[ab] + py[ab] * py[ab] + pz[ab] * pz[ab];
         ba[0] = px[ab]; ba[1] = py[ab]; ba[2] = pz[ab]; ba[3] = ps[ab];
-        ba[4] = -2.0 * px[ab]; ba[5] = -2.0 * py[ab]; ba[6] = -2.0 * pz[ab]; ba[7] = pp;
+        ba[4] = -2.0 * px[ab]; ba[5] = -2.0 * py[ab]; ba[6] = -2.0 * pz[ab]; ba[7] = p2;
         bf[0] = (float)px[ab]; bf[1] = (float)py[ab]; bf[2] = (float)pz[ab]; bf[3] = (float)ps[ab];
-        bf[4] = (float)ba[4]; bf[5] = (float)ba[5]; bf[6] = (float)ba[6]; bf[7] = (float)pp;
+        bf[4] = (float)ba[4]; bf[5] = (float)ba[5]; bf[6] = (float)ba[6]; bf[7] = (float)p2;
+    }
+    if (bip) {
+        for (int ab = 0; ab < g2; ++ab) {
+            const double sw = kTswitch / pp[ab];
+            prim[(4 * g2 + ab) * pcap + pos] = sw;
+            prim_f[(4 * g2 + ab) * pcap + pos] = (float)sw;
+            bip[(int64_t)pos * g2 + ab] = sw;
+            bip_f[(int64_t)pos * g2 + ab] = (float)sw;
+        }
+    }
+    if (kmu) {
+        for (int ab = 0; ab < g2; ++ab) {
+            kmu[(int64_t)ab * pcap + pos] = mu[ab];
+            kfa[(int64_t)ab * pcap + pos] = fa[ab];
+            bmf[((int64_t)pos * g2 + ab) * 2] = mu[ab];
+            bmf[((int64_t)pos * g2 + ab) * 2 + 1] = fa[ab];
+        }
     }
 }
 
@@ -242,7 +285,7 @@ __global__ __launch_bounds__(256) void k_b_limits(const DevHeader *__restrict__ 
 
 // ------------------------------------------------------------------ fused quartet kernel
 
-template <int G, typename R, bool kGrad>
+template <int G, typename R, bool kGrad, bool kAtoms = false>
 __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
 {
     constexpr int G2 = G * G;
@@ -363,6 +406,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
         const bool valid = (tk < lim) && (qs * a.pq[tk] >= a.tau);
         const long long t = valid ? tk : S;   // lanes without a kept quartet read the first pad entry
         const cptr<R> bra = (cptr<R>)(BPrec<R>::bra(a) + (int64_t)s * 8 * G2);
+        const cptr<R> bipp = kAtoms ? (cptr<R>)(BPrec<R>::bip(a) + (int64_t)s * G2) : nullptr;
+        const cptr<double> bmfp = (kAtoms && kGrad) ? (cptr<double>)(a.bmf + (int64_t)s * 2 * G2) : nullptr;
         const int k = a.pk[t], l = a.pl[t];
 
         R sX = R(0), eri = R(0);
@@ -375,7 +420,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
         }
 #pragma unroll 1
         for (int cb = 0; cb < G; ++cb) {
-            R kx[G], ky[G], kz[G], ks[G];
+            R kx[G], ky[G], kz[G], ks[G], kp[G];
             R Uc[G], Vc[G][3];
             // buffer loads of the ket table: component base, primitive pair as a scalar
             // offset, ket as a 32-bit lane offset
@@ -397,6 +442,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
                 ky[d] = ld(1, cd);
                 kz[d] = ld(2, cd);
                 ks[d] = ld(3, cd);
+                kp[d] = kAtoms ? ld(4, cd) : R(0);
                 Uc[d] = R(0);
                 Vc[d][0] = Vc[d][1] = Vc[d][2] = R(0);
             }
@@ -404,26 +450,49 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
             for (int ab = 0; ab < G2; ++ab) {
                 // every scalar of this bra primitive in one batch of scalar loads
                 const cptr<R> bp = bra + 8 * ab;
-                const cptr<R> up = rsg + 4 * (ab * G2 + cb * G);
-                R b[4], u[4 * G];
+                R b[4], u[4 * G], bsw = R(0);
+                double bmu = 0.0, bfa = 0.0;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) b[c] = bp[c];
+                if constexpr (kAtoms) {
+                    bsw = bipp[ab];
+                    if constexpr (kGrad) {
+                        bmu = bmfp[2 * ab];
+                        bfa = bmfp[2 * ab + 1];
+                    }
+                    asm volatile("" ::"s"(bsw));
+                } else {
+                    const cptr<R> up = rsg + 4 * (ab * G2 + cb * G);
 #pragma unroll
-                for (int c = 0; c < 4 * G; ++c) u[c] = up[c];
+                    for (int c = 0; c < 4 * G; ++c) u[c] = up[c];
 #pragma unroll
-                for (int c = 0; c < 4 * G; ++c) asm volatile("" ::"s"(u[c]));
+                    for (int c = 0; c < 4 * G; ++c) asm volatile("" ::"s"(u[c]));
+                }
                 const R px = b[0], py = b[1], pz = b[2], sab = b[3];
                 R U = R(0), V0 = R(0), V1 = R(0), V2 = R(0);
 #pragma unroll
                 for (int d = 0; d < G; ++d) {
                     const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
                     const R r2 = dx * dx + dy * dy + dz * dz;
-                    const bool near = r2 < u[4 * d];
+                    // switch radius^2 kTswitch / rho (per-atom bases: sum of the stored halves)
+                    const R sw = kAtoms ? bsw + kp[d] : u[4 * d];
+                    const bool near = r2 < sw;
                     R E, W = R(0);
                     if (__builtin_amdgcn_ballot_w64(near)) {
+                        // (rho/h, sqrt(rho/h), (rho/h)^(3/2)) from the table, or from sw
+                        R q1, q2, q3;
+                        if constexpr (kAtoms) {
+                            q2 = rsqrt_r(sw) * R(kSqrtSwitchInvH);
+                            q1 = q2 * q2;
+                            q3 = q1 * q2;
+                        } else {
+                            q1 = u[4 * d + 1];
+                            q2 = u[4 * d + 2];
+                            q3 = u[4 * d + 3];
+                        }
                         // T' = T / h on the table grid; sqrt(h) H and h^(3/2) g, or their far
                         // forms T'^(-1/2) and -T'^(-3/2)
-                        const R Ts = r2 * u[4 * d + 1];
+                        const R Ts = r2 * q1;
                         const R y = rsqrt_r(Ts);
                         const R Tc = fmin(Ts, R(kBoysGrid - 4));
                         const R kd = rint(Tc);
@@ -433,13 +502,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
                         R vh = ch[6];
 #pragma unroll
                         for (int m = 5; m >= 0; --m) vh = vh * dd + ch[m];
-                        E = u[4 * d + 2] * (near ? vh : y);
+                        E = q2 * (near ? vh : y);
                         if (kGrad) {
                             const R *cg = (const R *)((const char *)tG + off);
                             R vg = cg[6];
 #pragma unroll
                             for (int m = 5; m >= 0; --m) vg = vg * dd + cg[m];
-                            W = u[4 * d + 3] * (near ? vg : -(y * y * y));
+                            W = q3 * (near ? vg : -(y * y * y));
                         }
                     } else {
                         const R y = rsqrt_r(r2);
@@ -461,8 +530,16 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
                 const R su = sab * U;
                 eri += su;
                 if (kGrad) {
-                    sX += (R)cmu[ab] * su;
-                    const R fa = (R)cfa[ab] * sab, fb = (R)cfb[ab] * sab;
+                    R fa, fb;
+                    if constexpr (kAtoms) {
+                        sX += (R)bmu * su;
+                        fa = (R)bfa * sab;
+                        fb = sab - fa;
+                    } else {
+                        sX += (R)cmu[ab] * su;
+                        fa = (R)cfa[ab] * sab;
+                        fb = (R)cfb[ab] * sab;
+                    }
                     sYa[0] += fa * V0; sYa[1] += fa * V1; sYa[2] += fa * V2;
                     sYb[0] += fb * V0; sYb[1] += fb * V1; sYb[2] += fb * V2;
                 }
@@ -472,8 +549,16 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
                 for (int d = 0; d < G; ++d) {
                     const int cd = cb * G + d;
                     const double sc = (double)ks[d];
-                    const double mu2 = -2.0 * cmu[cd] * sc * (double)Uc[d];
-                    const double fc = cfa[cd] * sc;
+                    double kmu, kfa;
+                    if constexpr (kAtoms) {
+                        kmu = a.kmu[(int64_t)cd * a.pcap + t];
+                        kfa = a.kfa[(int64_t)cd * a.pcap + t];
+                    } else {
+                        kmu = cmu[cd];
+                        kfa = cfa[cd];
+                    }
+                    const double mu2 = -2.0 * kmu * sc * (double)Uc[d];
+                    const double fc = kfa * sc;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) kC[c] += mu2 * CD[c] - fc * (double)Vc[d][c];
                 }
@@ -569,11 +654,12 @@ size_t batched_smem_bytes(int nmax, int prec)
            2 * (size_t)kBoysGrid * kBoysStride * (prec == HFK_MIXED ? sizeof(float) : sizeof(double));
 }
 
-BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad)
+BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad, bool atoms)
 {
     BLayout L;
     memset(&L, 0, sizeof(L));
     L.nmol = nmol;
+    L.atoms = atoms;
     L.g = g;
     L.g2 = g * g;
     long long ptot = 0, ntot = 0, tri = 0, nmax = 0;
@@ -619,8 +705,18 @@ BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad
     L.pm = take(sizeof(int) * PC);
     L.pq = take(sizeof(double) * PC);
     L.pd = take(sizeof(double) * PC);
-    L.prim = take(sizeof(double) * 4 * g2 * PC);
-    L.prim_f = take(sizeof(float) * 4 * g2 * PC);
+    L.prim = take(sizeof(double) * (atoms ? 5 : 4) * g2 * PC);   // Px, Py, Pz, S (, kTswitch/p)
+    L.prim_f = take(sizeof(float) * (atoms ? 5 : 4) * g2 * PC);
+    if (atoms) {
+        L.arow = take(sizeof(double) * 2 * (size_t)ntot * (size_t)g);
+        L.bip = take(sizeof(double) * g2 * PC);
+        L.bip_f = take(sizeof(float) * g2 * PC);
+        if (with_grad) {
+            L.kmu = take(sizeof(double) * g2 * PC);
+            L.kfa = take(sizeof(double) * g2 * PC);
+            L.bmf = take(sizeof(double) * 2 * g2 * PC);
+        }
+    }
     L.bra = take(sizeof(double) * 8 * g2 * PC);
     L.bra_f = take(sizeof(float) * 8 * g2 * PC);
     L.nitems = take(sizeof(long long) * PC);
@@ -692,10 +788,13 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
                        cent, xyz, dens, L.ptot, L.pcap, (const double *)(ws + L.q), (const int *)(ws + L.bucket_of), bcur,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (int *)(ws + L.pm), (double *)(ws + L.pq),
                        (double *)(ws + L.pd), (double *)(ws + L.prim), (float *)(ws + L.prim_f), (double *)(ws + L.bra),
-                       (float *)(ws + L.bra_f));
+                       (float *)(ws + L.bra_f), L.atoms ? (double *)(ws + L.bip) : nullptr,
+                       L.atoms ? (float *)(ws + L.bip_f) : nullptr, L.kmu ? (double *)(ws + L.kmu) : nullptr,
+                       L.kmu ? (double *)(ws + L.kfa) : nullptr, L.kmu ? (double *)(ws + L.bmf) : nullptr);
     const unsigned nbc = (unsigned)((L.pcap + 255) / 256);
-    e = launch_pair_pad(hdr, L.pcap, L.g2, (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq),
-                        (double *)(ws + L.pd), (double *)(ws + L.prim), (float *)(ws + L.prim_f), st);
+    e = launch_pair_pad(hdr, L.pcap, L.g2, L.atoms, (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq),
+                        (double *)(ws + L.pd), (double *)(ws + L.prim), (float *)(ws + L.prim_f),
+                        L.kmu ? (double *)(ws + L.kmu) : nullptr, L.kmu ? (double *)(ws + L.kfa) : nullptr, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_b_pad, dim3(nbc), dim3(256), 0, st, hdr, L.pcap, (int *)(ws + L.pm));
     hipLaunchKernelGGL(k_b_limits, dim3(nbc), dim3(256), 0, st, hdr, tau, (const double *)(ws + L.pq),
@@ -729,6 +828,11 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
     a.prim_f = (const float *)(ws + L.prim_f);
     a.bra = (const double *)(ws + L.bra);
     a.bra_f = (const float *)(ws + L.bra_f);
+    a.bip = L.atoms ? (const double *)(ws + L.bip) : nullptr;
+    a.bip_f = L.atoms ? (const float *)(ws + L.bip_f) : nullptr;
+    a.kmu = L.kmu ? (const double *)(ws + L.kmu) : nullptr;
+    a.kfa = L.kmu ? (const double *)(ws + L.kfa) : nullptr;
+    a.bmf = L.kmu ? (const double *)(ws + L.bmf) : nullptr;
     a.item_off = (const long long *)(ws + L.item_off);
     a.lim = (const int *)(ws + L.lim);
     a.klo = (const int *)(ws + L.klo);
@@ -751,8 +855,14 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
         if (ez != hipSuccess) return ez;
     }
     profile_begin(st);
-#define HFK_B_LAUNCH(GG, RR, GR) \
-    hipLaunchKernelGGL((k_batched<GG, RR, GR>), dim3(groups), dim3(kGroupThreads), smem, st, a)
+    if (grad && L.atoms && !L.kmu) return hipErrorInvalidValue;   // per-atom gradient tables missing
+#define HFK_B_LAUNCH(GG, RR, GR)                                                                         \
+    do {                                                                                                 \
+        if (L.atoms)                                                                                     \
+            hipLaunchKernelGGL((k_batched<GG, RR, GR, true>), dim3(groups), dim3(kGroupThreads), smem, st, a); \
+        else                                                                                             \
+            hipLaunchKernelGGL((k_batched<GG, RR, GR, false>), dim3(groups), dim3(kGroupThreads), smem, st, a); \
+    } while (0)
     if (prec == HFK_MIXED) {
         if (grad) {
             switch (b.g) {

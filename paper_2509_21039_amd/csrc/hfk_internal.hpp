@@ -150,17 +150,22 @@ struct BLayout {
     size_t pk, pl, pm, pq, pd, prim, prim_f, bra, bra_f;
     size_t nitems, lim, klo, item_off, scan_tmp;
     size_t facc, gacc;
+    bool atoms;                 // per-atom bases: ket component 4 is kTswitch/p, tables below
+    size_t arow;                // [2][sum n][g] exponents and weights of every atom
+    size_t bip, bip_f;          // [pcap][g2] kTswitch/p of the bra pairs
+    size_t kmu, kfa, bmf;       // gradient: [g2][pcap] ket mu, a/p; [pcap][g2][2] bra (mu, a/p)
     size_t total;
 };
 
-BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad);
+BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad, bool atoms = false);
 size_t batched_smem_bytes(int nmax, int prec);
 hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int64_t *atom_off_host, const double *xyz,
                           const double *dens, double tau, int prec, double *fock, double *e2, double *d_xyz,
                           int groups, hipStream_t st);
-// Pads the batched pair tables (four-component FP64 ket table) past the last pair.
-hipError_t launch_pair_pad(const DevHeader *hdr, int64_t pcap, int g2, int *pk, int *pl, double *pq, double *pd,
-                           double *prim, float *prim_f, hipStream_t st);
+// Pads the batched pair tables (four-component ket table, plus kTswitch/p with per-atom
+// bases; kmu/kfa: per-atom gradient tables or NULL) past the last pair.
+hipError_t launch_pair_pad(const DevHeader *hdr, int64_t pcap, int g2, bool atoms, int *pk, int *pl, double *pq,
+                           double *pd, double *prim, float *prim_f, double *kmu, double *kfa, hipStream_t st);
 
 int device_cu_count();
 

@@ -328,10 +328,11 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
 // Pads the tail chunk of the sorted tables with harmless entries (atom 0, zero weight,
 // centres 1e6 bohr away) so that lanes past the last pair, or lanes pointed at the first
 // pad entry, read defined memory and land in the far branch with a zero integral.
-// ncomp: FP64 components of the ket table (4: Px Py Pz S; 5 adds |P|^2; 6 adds kTswitch/p
-// of per-atom bases, which then is FP32 component 4).
-// kmu/kfa (per-atom gradient tables, or NULL) are zeroed there too.
-__global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int g2, int ncomp,
+// Ket table components: Px Py Pz S always; p2: FP64 component 4 holds |P|^2; swc / swc_f:
+// the FP64 / FP32 component holding kTswitch/p of per-atom bases (-1: none), padded with
+// 1 so that the switch radius stays far below the pad distance.  kmu/kfa (per-atom
+// gradient tables, or NULL) are zeroed there too.
+__global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int g2, bool p2, int swc, int swc_f,
                            int *__restrict__ pk, int *__restrict__ pl, double *__restrict__ pq,
                            double *__restrict__ pd, double *__restrict__ prim, float *__restrict__ prim_f,
                            double *__restrict__ kmu, double *__restrict__ kfa)
@@ -348,11 +349,9 @@ __global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int 
             prim[(c * g2 + ab) * pcap + pos] = c < 3 ? 1e6 : 0.0;
             prim_f[(c * g2 + ab) * pcap + pos] = c < 3 ? 1e6f : 0.0f;
         }
-        if (ncomp > 4) prim[(4 * g2 + ab) * pcap + pos] = 3e12;
-        if (ncomp > 5) {
-            prim[(5 * g2 + ab) * pcap + pos] = 1.0;
-            prim_f[(4 * g2 + ab) * pcap + pos] = 1.0f;
-        }
+        if (p2) prim[(4 * g2 + ab) * pcap + pos] = 3e12;
+        if (swc >= 0) prim[((int64_t)swc * g2 + ab) * pcap + pos] = 1.0;
+        if (swc_f >= 0) prim_f[((int64_t)swc_f * g2 + ab) * pcap + pos] = 1.0f;
         if (kmu) {
             kmu[(int64_t)ab * pcap + pos] = 0.0;
             kfa[(int64_t)ab * pcap + pos] = 0.0;
@@ -360,12 +359,13 @@ __global__ void k_pair_pad(const DevHeader *__restrict__ hdr, int64_t pcap, int 
     }
 }
 
-hipError_t launch_pair_pad(const DevHeader *hdr, int64_t pcap, int g2, int *pk, int *pl, double *pq, double *pd,
-                           double *prim, float *prim_f, hipStream_t st)
+hipError_t launch_pair_pad(const DevHeader *hdr, int64_t pcap, int g2, bool atoms, int *pk, int *pl, double *pq,
+                           double *pd, double *prim, float *prim_f, double *kmu, double *kfa, hipStream_t st)
 {
-    // the batched tables hold the four-component FP64 ket table
-    hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((pcap + 255) / 256)), dim3(256), 0, st, hdr, pcap, g2, 4, pk, pl,
-                       pq, pd, prim, prim_f, nullptr, nullptr);
+    // the batched tables hold the four-component ket table, plus kTswitch/p as component 4
+    // (FP64 and FP32) with per-atom bases
+    hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((pcap + 255) / 256)), dim3(256), 0, st, hdr, pcap, g2, false,
+                       atoms ? 4 : -1, atoms ? 4 : -1, pk, pl, pq, pd, prim, prim_f, kmu, kfa);
     return hipGetLastError();
 }
 
@@ -559,7 +559,7 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
                        L.atoms ? (float *)(ws + L.bip_f) : nullptr, L.pmu ? (double *)(ws + L.pmu) : nullptr,
                        L.pmu ? (double *)(ws + L.pfa) : nullptr, L.pmu ? (double *)(ws + L.bmf) : nullptr);
     hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, L.pcap, L.g2,
-                       L.atoms ? 6 : 5,
+                       true, L.atoms ? 5 : -1, L.atoms ? 4 : -1,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f), L.pmu ? (double *)(ws + L.pmu) : nullptr,
                        L.pmu ? (double *)(ws + L.pfa) : nullptr);

@@ -21,7 +21,8 @@ def test_header_declares_entry_points():
     names = _declared_symbols()
     for must in ("hfk_fock", "hfk_fock_grad", "hfk_fock_batched", "hfk_workspace_bytes",
                  "hfk_batched_workspace_bytes", "hfk_read_stats", "hfk_tune", "hfk_last_error",
-                 "hfk_fock_atoms", "hfk_workspace_bytes_atoms", "hfk_fock_grad_atoms"):
+                 "hfk_fock_atoms", "hfk_workspace_bytes_atoms", "hfk_fock_grad_atoms",
+                 "hfk_fock_batched_atoms", "hfk_batched_workspace_bytes_atoms"):
         assert must in names
 
 
@@ -218,3 +219,23 @@ def test_fock_grad_atoms_rejects_bad_rows():
                                        None, 1, None, None, 256, 1 << 40, None)
     assert st == hfk.HFK_EINVAL
     assert "atom 3" in hfk.lib().hfk_last_error().decode()
+
+
+def test_fock_batched_atoms_rejects_bad_rows():
+    off = np.array([0, 2, 5], dtype=np.int64)
+    e = np.tile([6.36242139, 1.158923, 0.31364979], (5, 1))
+    c = np.tile([0.15432897, 0.53532814, 0.44463454], (5, 1))
+    c[4, 0] = float("nan")
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = hfk.lib().hfk_fock_batched_atoms(2, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1, 3,
+                                          e.ctypes.data_as(dp), c.ctypes.data_as(dp), 1, 1e-10, 0, 1, 1, None,
+                                          256, 1 << 40, None)
+    assert st == hfk.HFK_EINVAL
+    assert "atom 4" in hfk.lib().hfk_last_error().decode()
+    out = ctypes.c_size_t(0)
+    L = hfk.lib()
+    p64 = ctypes.POINTER(ctypes.c_int64)
+    assert L.hfk_batched_workspace_bytes(2, off.ctypes.data_as(p64), 3, 1, 1, ctypes.byref(out)) == hfk.HFK_OK
+    one = out.value
+    assert L.hfk_batched_workspace_bytes_atoms(2, off.ctypes.data_as(p64), 3, 1, 1, ctypes.byref(out)) == hfk.HFK_OK
+    assert out.value > one

@@ -130,3 +130,80 @@ def test_batch_with_bounds_above_two(torch_dev):
         assert rel_fro(Fm, Fr) < FP64_TOL, (m, rel_fro(Fm, Fr))
         assert rel(E2[m], Er) < FP64_TOL, m
         assert np.linalg.norm(gm - gr) <= FP64_TOL * max(np.linalg.norm(gr), 1e-6), m
+
+
+# ------------------------------------------------------------------ per-atom bases
+
+def _run_atoms(torch_dev, systems, rows, precision, with_grad=True):
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    off, xyz, dens = pack_batch(systems)
+    X = torch.tensor(xyz, device=dev)
+    Dp = torch.tensor(dens, device=dev)
+    e, c = rows
+    F, E2, g = hfk.fock_batched(off, X, Dp, e, c, systems[0].tau, precision=precision, with_grad=with_grad)
+    torch.cuda.synchronize()
+    return off, F.cpu().numpy(), E2.cpu().numpy(), (g.cpu().numpy() if g is not None else None)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_small_batch_atoms_vs_oracle(torch_dev, precision, tol):
+    """Random per-atom contractions over a ragged batch: every molecule's G, E2 and gradient
+    against the oracle's per-atom functions."""
+    from he_inputs import random_basis_rows
+    systems = _small_batch(1e-10)
+    ntot = sum(s.natoms for s in systems)
+    e, c = random_basis_rows(ntot, 3, 401)
+    announce("batched per-atom small %s" % precision)
+    off, F, E2, g = _run_atoms(torch_dev, systems, (e, c), precision)
+    for m, s in enumerate(systems):
+        n = s.natoms
+        a0, a1 = int(off[m]), int(off[m + 1])
+        Fm, gm = _mol(off, F, g, m, n)
+        Fr, Er, _ = oracle.fock_atoms(s.xyz, s.dens, e[a0:a1], c[a0:a1], s.tau)
+        gr, _, _ = oracle.grad_atoms(s.xyz, s.dens, e[a0:a1], c[a0:a1], s.tau)
+        assert rel_fro(Fm, Fr) < tol, (m, n, rel_fro(Fm, Fr))
+        assert rel(E2[m], Er) < tol, (m, n)
+        assert np.linalg.norm(gm - gr) <= tol * max(np.linalg.norm(gr), 1e-6), (m, n)
+
+
+def test_batch_atoms_forward_only_and_identical_rows(torch_dev):
+    """Forward-only equals the fused forward; identical rows equal the one-basis batch."""
+    systems = _small_batch(1e-10)
+    ntot = sum(s.natoms for s in systems)
+    e = np.tile(systems[0].exps, (ntot, 1))
+    c = np.tile(systems[0].coefs, (ntot, 1))
+    announce("batched per-atom forward-only and identical rows")
+    _, F1, E1, _ = _run_atoms(torch_dev, systems, (e, c), "fp64", with_grad=False)
+    _, F2, E2, g2 = _run_atoms(torch_dev, systems, (e, c), "fp64", with_grad=True)
+    _, F0, E0, g0 = _run(torch_dev, systems, "fp64")
+    assert np.abs(F1 - F2).max() <= 1e-13 * np.abs(F2).max()
+    assert np.abs(F2 - F0).max() <= 1e-13 * np.abs(F0).max()
+    assert np.abs(E2 - E0).max() <= 1e-12 * np.abs(E0).max()
+    assert np.abs(g2 - g0).max() <= 1e-12 * np.abs(g0).max()
+
+
+def test_hhe_cluster_batch_sampled(torch_dev):
+    """500 H/He clusters (the cluster recipe with per-atom rows), mixed precision + gradient
+    in one launch; sampled molecules against the FP64 oracle, net force per molecule."""
+    from he_inputs import hhe_rows
+    systems = cluster_batch(nmol=500, seed=6)
+    ntot = sum(s.natoms for s in systems)
+    e, c = hhe_rows(ntot, 7)
+    announce("batched 500 H/He clusters mixed+grad")
+    off, F, E2, g = _run_atoms(torch_dev, systems, (e, c), "mixed")
+    counts = np.array([s.natoms for s in systems])
+    picks = [int(np.argmin(counts))] + [int(np.argmin(np.abs(counts - t))) for t in (30, 60)]
+    for m in picks:
+        s = systems[m]
+        a0, a1 = int(off[m]), int(off[m + 1])
+        Fm, gm = _mol(off, F, g, m, s.natoms)
+        Fr, Er, _ = oracle.fock_atoms(s.xyz, s.dens, e[a0:a1], c[a0:a1], s.tau)
+        gr, _, _ = oracle.grad_atoms(s.xyz, s.dens, e[a0:a1], c[a0:a1], s.tau)
+        assert rel_fro(Fm, Fr) < MIXED_TOL, (m, s.natoms)
+        assert rel(E2[m], Er) < MIXED_TOL, m
+        assert rel_fro(gm, gr) < MIXED_TOL, m
+    assert np.isfinite(F).all() and np.isfinite(E2).all() and np.isfinite(g).all()
+    for m in range(len(systems)):
+        gm = g[off[m]:off[m + 1]]
+        assert np.abs(gm.sum(axis=0)).max() < 1e-5 * max(1.0, np.abs(gm).max())
