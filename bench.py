@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -140,11 +142,15 @@ def time_grad(hfk, torch, s, steps, warmup):
     dev = torch.device("cuda:0")
     xyz = torch.tensor(s.xyz, device=dev)
     D = torch.tensor(s.dens, device=dev)
-    ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, len(s.exps), "fp64", True), dev)
+    atoms = np.ndim(s.exps) == 2
+    g = s.exps.shape[-1]
+    nb = hfk.workspace_bytes_atoms(s.natoms, g, "fp64", True) if atoms else hfk.workspace_bytes(s.natoms, g, "fp64", True)
+    ws = hfk.new_workspace(nb, dev)
     g_e2 = torch.ones((1,), dtype=torch.float64, device=dev)
+    build = hfk.fock_atoms if atoms else hfk.fock
 
     def step():
-        G, E2 = hfk.fock(xyz, D, s.exps, s.coefs, s.tau, workspace=ws)
+        G, E2 = build(xyz, D, s.exps, s.coefs, s.tau, workspace=ws)
         return hfk.fock_grad(xyz, D, s.exps, s.coefs, s.tau, g_e2=g_e2, fock_in=G, workspace=ws)
 
     for _ in range(warmup):
@@ -351,6 +357,14 @@ def main():
             a = time_builds(hfk, torch, s5, "fp64", 5, 1, ws5, atoms=True)
             b = time_builds(hfk, torch, s5, "mixed", 5, 1, ws5, atoms=True)
             qa = a["stats"]["quartets"]
+            s6 = mixed_lattice((8, 4, 4), seed=14, tau=1e-10)
+            ws6 = hfk.new_workspace(hfk.workspace_bytes_atoms(s6.natoms, g, "fp64"), dev)
+            f6 = time_builds(hfk, torch, s6, "fp64", 10, 2, ws6, atoms=True)
+            fg6 = time_grad(hfk, torch, s6, 10, 2)
+            extras["atoms_hhe128_fwd_grad"] = {
+                "quartets": f6["stats"]["quartets"], "fwd_ms": f6["ms_per_step"], "fwd_grad_ms": fg6,
+                "fwd_grad_over_fwd_time": fg6 / f6["ms_per_step"],
+            }
             extras["atoms_hhe512"] = {
                 "quartets": qa,
                 "fp64_ms": a["ms_per_step"], "fp64_kernel_ms": a["kernel_ms"],
