@@ -56,7 +56,13 @@ typedef enum hfk_precision {
 typedef enum hfk_strategy {
     HFK_STRATEGY_AUTO = 0,     /* library default, or the tuned choice once hfk_tune ran */
     HFK_STRATEGY_PRIVATE = 1,  /* each workgroup owns an FP64 copy of F; summed at the end */
-    HFK_STRATEGY_ATOMIC = 2    /* workgroups flush their LDS rows into one F with atomics */
+    HFK_STRATEGY_ATOMIC = 2,   /* workgroups flush their LDS rows into one F with atomics */
+    HFK_STRATEGY_DETERMINISTIC = 3   /* every sum in a fixed order: repeated builds with the same
+                                        inputs on the same device agree bit for bit.  Static
+                                        block schedule, private copies of F and of the ket
+                                        vectors, per-wave LDS rows.  Up to 1024 atoms (hfk_fock and
+                                        hfk_fock_atoms; HFK_EUNSUPPORTED above); slower than the
+                                        other strategies and never chosen by the tuner */
 } hfk_strategy;
 
 /* Arguments accept up to HFK_MAX_NGAUSS primitives per function; the kernels are built for

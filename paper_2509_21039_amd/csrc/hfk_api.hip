@@ -180,6 +180,17 @@ constexpr int64_t kMaxAtoms = 6144;
 // n above which the gradient kernel's LDS copy of dE2/dR (n x 3) and its two tables no longer fit
 constexpr int64_t kMaxGradAtoms = 4096;
 constexpr int kGradGroupsPerCU = 2;
+// Largest system of the deterministic strategy: every workgroup needs its own copies of F
+// and of the ket vector within the workspace budgets, and four wave copies of rows i, j in LDS.
+constexpr int64_t kMaxDetAtoms = 1024;
+
+// Deterministic strategy: every workgroup must own a copy of F and of the ket vector.
+static hfk_status det_groups(Layout &L)
+{
+    if (!L.private_ok) return fail(HFK_EUNSUPPORTED, "private copies of F do not fit for the deterministic strategy");
+    if (L.jcopies < L.groups) L.groups = L.jcopies;
+    return HFK_OK;
+}
 // Largest molecule of a batch (its triangle of F and its gradient stay in LDS).
 constexpr int kMaxBatchAtomsApi = 128;
 static int g_cfg_batch_gpc = 0;
@@ -209,6 +220,10 @@ static TunedConfig pick_config(int32_t strategy, int32_t precision, int64_t n, i
     if (g_cfg_variant >= 0) c.variant = g_cfg_variant;
     if (g_cfg_gpc > 0) c.gpc = g_cfg_gpc;
     if (ngauss > 4) c.variant = 1;   // the direct form is built for g <= 4 only
+    if (strategy == HFK_STRATEGY_DETERMINISTIC) {
+        // a fixed configuration, independent of tuning and overrides (capped at residency)
+        c = TunedConfig{HFK_STRATEGY_DETERMINISTIC, 1, kMaxGroupsPerCU};
+    }
     return c;
 }
 
@@ -321,8 +336,10 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     if (!e2) return fail(HFK_EINVAL, "e2 is NULL");
     if (!workspace) return fail(HFK_EINVAL, "workspace is NULL");
     if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
-    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_ATOMIC)
+    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_DETERMINISTIC)
         return fail(HFK_EINVAL, "unknown strategy %d", (int)strategy);
+    if (strategy == HFK_STRATEGY_DETERMINISTIC && natoms > kMaxDetAtoms)
+        return fail(HFK_EUNSUPPORTED, "the deterministic strategy supports natoms <= %lld", (long long)kMaxDetAtoms);
     if (natoms > kMaxAtoms) return fail(HFK_EUNSUPPORTED, "natoms above %lld", (long long)kMaxAtoms);
     if (ngauss > kMaxBuiltG) return fail(HFK_EUNSUPPORTED, "ngauss above %d is not built in this version", kMaxBuiltG);
     const int cus = device_cu_count();
@@ -335,8 +352,13 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
     {
         // no more persistent workgroups than fit on a CU at once
-        const int fit = fock_resident_groups(ngauss, precision, cfg.variant, natoms);
+        const bool det = strat == HFK_STRATEGY_DETERMINISTIC;
+        const int fit = fock_resident_groups(ngauss, precision, cfg.variant, natoms, false, det);
         L.groups = cus * (fit > 0 && cfg.gpc > fit ? fit : cfg.gpc);
+        if (det) {
+            hfk_status sd = det_groups(L);
+            if (sd != HFK_OK) return sd;
+        }
     }
     const Basis b = make_basis(ngauss, exps_host, coefs_host);
     char *ws = (char *)workspace;
@@ -345,7 +367,10 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
                                 (float *)(ws + L.boys_f), (double *)(ws + L.boys_g),
                                 (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz, st);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
-    e = launch_pairs(L, b, ws, xyz, dens, tau, st);
+    e = launch_pairs(L, b, ws, xyz, dens, tau, st, strat == HFK_STRATEGY_DETERMINISTIC);
+    if (e == hipErrorNotSupported && strat == HFK_STRATEGY_DETERMINISTIC)
+        return fail(HFK_EUNSUPPORTED, "deterministic strategy: more than %d pairs share one (Q band, cell) bucket",
+                    kMaxFixedBucket);
     if (e != hipSuccess) return hip_fail(e, "pair launch");
     e = launch_fock(L, b, ws, dens, tau, precision, strat, cfg.variant, fock, e2, st);
     if (e != hipSuccess) return hip_fail(e, "fock launch");
@@ -411,8 +436,10 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
     if (!e2) return fail(HFK_EINVAL, "e2 is NULL");
     if (!workspace) return fail(HFK_EINVAL, "workspace is NULL");
     if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
-    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_ATOMIC)
+    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_DETERMINISTIC)
         return fail(HFK_EINVAL, "unknown strategy %d", (int)strategy);
+    if (strategy == HFK_STRATEGY_DETERMINISTIC && natoms > kMaxDetAtoms)
+        return fail(HFK_EUNSUPPORTED, "the deterministic strategy supports natoms <= %lld", (long long)kMaxDetAtoms);
     if (natoms > kMaxAtoms) return fail(HFK_EUNSUPPORTED, "natoms above %lld", (long long)kMaxAtoms);
     if (ngauss > kMaxBuiltG) return fail(HFK_EUNSUPPORTED, "ngauss above %d is not built in this version", kMaxBuiltG);
     const int cus = device_cu_count();
@@ -425,8 +452,13 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
     int strat = cfg.strategy;
     if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
     {
-        const int fit = fock_resident_groups(ngauss, precision, 1, natoms, true);
+        const bool det = strat == HFK_STRATEGY_DETERMINISTIC;
+        const int fit = fock_resident_groups(ngauss, precision, 1, natoms, true, det);
         L.groups = cus * (fit > 0 && cfg.gpc > fit ? fit : cfg.gpc);
+        if (det) {
+            hfk_status sd = det_groups(L);
+            if (sd != HFK_OK) return sd;
+        }
     }
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
@@ -437,7 +469,10 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
                      (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz,
                      st);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
-    e = launch_pairs(L, b, ws, xyz, dens, tau, st);
+    e = launch_pairs(L, b, ws, xyz, dens, tau, st, strat == HFK_STRATEGY_DETERMINISTIC);
+    if (e == hipErrorNotSupported && strat == HFK_STRATEGY_DETERMINISTIC)
+        return fail(HFK_EUNSUPPORTED, "deterministic strategy: more than %d pairs share one (Q band, cell) bucket",
+                    kMaxFixedBucket);
     if (e != hipSuccess) return hip_fail(e, "pair launch");
     e = launch_fock(L, b, ws, dens, tau, precision, strat, 1, fock, e2, st);
     if (e != hipSuccess) return hip_fail(e, "fock launch");

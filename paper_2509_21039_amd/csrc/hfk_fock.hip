@@ -22,6 +22,15 @@
 //   F_ik, F_il, F_jk, F_jl -= ...   LDS atomics into copies of rows i and j of F, flushed
 //                      to a per-workgroup copy of F (or with global atomics) once per bra
 // and a final kernel sums the copies, symmetrises and forms E2.
+//
+// Deterministic strategy (kDet): the same arithmetic with every sum taken in a fixed order,
+// so repeated builds agree bit for bit.  Blocks are dealt out by a static grid stride
+// instead of the global counter and every workgroup owns its copy of F and of the ket
+// vector.  Within a workgroup each wave stages its exchange updates (k, l, v) in LDS; at the
+// end of every item the waves apply them to rows i and j one wave after the other (a wave's
+// atomic adds within one instruction are applied by the LDS in a fixed lane order), and the
+// F_ij partial sums of the four waves are added in wave order.  The final kernels sum the
+// workgroup copies in workgroup order.
 #include "hfk_device.hpp"
 
 namespace hfk {
@@ -302,13 +311,15 @@ template <typename R> struct FockSmem {
     static constexpr int kCombos = kMaxG2 * kMaxG2 / 16;                    // g <= 4 here: 256 combos
     static constexpr size_t tab_bytes = sizeof(R) * kBoysGrid * kBoysStride;
     static constexpr size_t uni_bytes = 4 * sizeof(R) * 16 + 2 * sizeof(R) * kCombos;   // bra, (rho, srho)
-    static size_t total(int n, bool split)
+    // deterministic strategy: per wave, kWaveKets staged updates (v, then k and l)
+    static constexpr size_t stage_bytes = kWavesPerGroup * kWaveKets * (sizeof(double) + 2 * sizeof(int));
+    static size_t total(int n, bool split, bool det = false)
     {
-        return sizeof(double) * 2 * (size_t)n + tab_bytes + (split ? 0 : uni_bytes);
+        return sizeof(double) * 2 * (size_t)n + tab_bytes + (split ? 0 : uni_bytes) + (det ? stage_bytes : 0);
     }
 };
 
-template <int G, typename R, bool kSplit, bool kAtoms = false>
+template <int G, typename R, bool kSplit, bool kAtoms = false, bool kDet = false>
 __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
 {
     constexpr int G2 = G * G;
@@ -323,6 +334,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     sp += sizeof(double) * 2 * (size_t)n;
     R *lbra = (R *)sp;                      // direct form: [G2][4] Px, Py, Pz, S of the current bra
     R *luni = lbra + 4 * 16;                // direct form: (rho, sqrt rho) per primitive quartet
+    // deterministic strategy: staged exchange updates of each wave (the hybrid form has no
+    // direct-form slots, so they start at the same place)
+    double *stv = (double *)sp;                                   // [waves][kWaveKets] v
+    int *stk = (int *)(stv + kWavesPerGroup * kWaveKets);         // [waves][kWaveKets] k
+    int *stl = stk + kWavesPerGroup * kWaveKets;                  // [waves][kWaveKets] l
+    __shared__ double jbs[kWavesPerGroup];
     __shared__ int bra_at[2];
     __shared__ double bra_qd[2];
     __shared__ int wperm[kWavesPerGroup][kWaveKets];
@@ -356,8 +373,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     const cptr<R> crs = (cptr<R>)Prec<R>::rsn(bd);
     const bool jshared = a.jcopies < ng;
     double *jcol = a.jcol + (int64_t)(gid % a.jcopies) * a.pcap;
-    double *fp = a.strategy == HFK_STRATEGY_PRIVATE ? a.fpriv + (int64_t)gid * n * n : a.fpriv;
-    if (a.strategy == HFK_STRATEGY_PRIVATE) {
+    const bool priv = kDet || a.strategy == HFK_STRATEGY_PRIVATE;
+    double *fp = priv ? a.fpriv + (int64_t)gid * n * n : a.fpriv;
+    if (priv) {
         for (int64_t x = tid; x < (int64_t)n * n; x += kGroupThreads) fp[x] = 0.0;
     }
     if (!jshared) {
@@ -369,11 +387,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     __shared__ long long blk_at;
     const long long NB = a.hdr->blocks;
     (void)M;
-    // blocks (bra group, ket block K, bra) fetched from a global counter until exhausted
-    for (;;) {
-    if (tid == 0) blk_at = (long long)atomicAdd(a.next_block, 1ULL);
+    // blocks (bra group, ket block K, bra) fetched from a global counter until exhausted, or
+    // dealt out by a static grid stride (deterministic strategy)
+    for (long long it = 0;; ++it) {
+    if (!kDet && tid == 0) blk_at = (long long)atomicAdd(a.next_block, 1ULL);
     __syncthreads();
-    const long long blk = blk_at;
+    const long long blk = kDet ? (long long)gid + it * ng : blk_at;
     __syncthreads();
     if (blk >= NB) break;
     int s;
@@ -405,11 +424,23 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
             if (cur >= 0) {
                 // flush the finished bra: F_ij from the wave partial sums, then rows i, j
                 const double w = wave_sum(jb);
-                if (lane == 0 && w != 0.0) atomicAdd(&rowi[bj], 4.0 * w);
+                if constexpr (kDet) {
+                    // the four wave sums in wave order
+                    if (lane == 0) jbs[wave] = w;
+                    __syncthreads();
+                    if (tid == 0) {
+                        double sw = jbs[0];
+#pragma unroll
+                        for (int wv = 1; wv < kWavesPerGroup; ++wv) sw += jbs[wv];
+                        if (sw != 0.0) rowi[bj] += 4.0 * sw;
+                    }
+                } else {
+                    if (lane == 0 && w != 0.0) atomicAdd(&rowi[bj], 4.0 * w);
+                }
                 jb = 0.0;
                 __syncthreads();
                 double *fi = fp + (int64_t)bi * n, *fj = fp + (int64_t)bj * n;
-                if (a.strategy == HFK_STRATEGY_PRIVATE) {
+                if (priv) {
                     if (bi == bj) {
                         for (int c = tid; c < n; c += kGroupThreads) fi[c] += rowi[c] + rowj[c];
                     } else {
@@ -449,9 +480,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
             lim = a.lim[s];
         }
         const long long wbase = (m - a.item_off[s]) * kItemKets + (long long)wave * kWaveKets;
-        if (wbase >= lim) continue;
+        if constexpr (!kDet) {
+            if (wbase >= lim) continue;
+        }
         // one 64-lane chunk: ket t per lane (valid: kept by the screen), scatter of v
-        auto chunk = [&](int t, bool valid) {
+        // (deterministic strategy: the exchange updates are staged at position `slot`)
+        auto chunk = [&](int t, bool valid, int slot) {
             R eri;
             if (kSplit)
                 eri = quartet_eri_hybrid<G, R, kAtoms>(
@@ -472,15 +506,48 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
                     atomicAdd(&jcol[t], 4.0 * ds * v);
                 else
                     jcol[t] += 4.0 * ds * v;
-                const double *Di = a.dens + (int64_t)bi * n;
-                const double *Dj = a.dens + (int64_t)bj * n;
-                atomicAdd(&rowi[k], -Dj[l] * v);
-                atomicAdd(&rowi[l], -Dj[k] * v);
-                atomicAdd(&rowj[k], -Di[l] * v);
-                atomicAdd(&rowj[l], -Di[k] * v);
+                if constexpr (kDet) {
+                    stv[wave * kWaveKets + slot] = v;
+                    stk[wave * kWaveKets + slot] = k;
+                    stl[wave * kWaveKets + slot] = l;
+                } else {
+                    const double *Di = a.dens + (int64_t)bi * n;
+                    const double *Dj = a.dens + (int64_t)bj * n;
+                    atomicAdd(&rowi[k], -Dj[l] * v);
+                    atomicAdd(&rowi[l], -Dj[k] * v);
+                    atomicAdd(&rowj[k], -Di[l] * v);
+                    atomicAdd(&rowj[l], -Di[k] * v);
+                }
             }
         };
-        if (kSplit) {
+        if constexpr (kDet) {
+            int nvalid = 0;
+            if (wbase < lim) {
+                int *perm = wperm[wave];
+                nvalid = pack_kets(wbase, lane, perm, [&](long long t) { return t < lim && qs * a.pq[t] >= a.tau; });
+                for (int c0 = 0; c0 < nvalid; c0 += kWave) {
+                    const bool valid = c0 + lane < nvalid;
+                    chunk(valid ? perm[c0 + lane] : S, valid, c0 + lane);
+                }
+            }
+            // every wave's updates are staged; apply them wave after wave
+            __syncthreads();
+            const double *Di = a.dens + (int64_t)bi * n;
+            const double *Dj = a.dens + (int64_t)bj * n;
+            for (int wv = 0; wv < kWavesPerGroup; ++wv) {
+                if (wave == wv) {
+                    for (int e = lane; e < nvalid; e += kWave) {
+                        const double v = stv[wave * kWaveKets + e];
+                        const int k = stk[wave * kWaveKets + e], l = stl[wave * kWaveKets + e];
+                        atomicAdd(&rowi[k], -Dj[l] * v);
+                        atomicAdd(&rowi[l], -Dj[k] * v);
+                        atomicAdd(&rowj[k], -Di[l] * v);
+                        atomicAdd(&rowj[l], -Di[k] * v);
+                    }
+                }
+                __syncthreads();
+            }
+        } else if (kSplit) {
             // keep the screened kets of this wave's 256, in order, packed into full chunks
             int *perm = wperm[wave];
             const int nvalid = pack_kets(wbase, lane, perm,
@@ -488,7 +555,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
             if (nvalid == 0) continue;
             for (int c0 = 0; c0 < nvalid; c0 += kWave) {
                 const bool valid = c0 + lane < nvalid;
-                chunk(valid ? perm[c0 + lane] : S, valid);   // S: first pad entry
+                chunk(valid ? perm[c0 + lane] : S, valid, 0);   // S: first pad entry
             }
             __builtin_amdgcn_wave_barrier();
         } else {
@@ -496,7 +563,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
                 const long long t0 = wbase + c * kWave;
                 if (t0 >= lim) break;
                 const long long t = t0 + lane;   // < S + 64 <= pcap: padded tables
-                chunk((int)t, t < lim && qs * a.pq[t] >= a.tau);
+                chunk((int)t, t < lim && qs * a.pq[t] >= a.tau, 0);
             }
         }
     }
@@ -588,13 +655,19 @@ template <int G, typename R>
 static hipError_t launch_fock_t(const FockArgs &a, int groups, int variant, bool atoms, hipStream_t st)
 {
     // the direct form keeps a bra's primitive data in LDS slots sized for g <= 4; per-atom
-    // bases run the hybrid form only
-    const bool split = G > 4 || variant != 0 || atoms;
-    const size_t smem = FockSmem<R>::total(a.n, split);
+    // bases and the deterministic strategy run the hybrid form only
+    const bool det = a.strategy == HFK_STRATEGY_DETERMINISTIC;
+    const bool split = G > 4 || variant != 0 || atoms || det;
+    const size_t smem = FockSmem<R>::total(a.n, split, det);
     const hipError_t ez = launch_zero_counter(a.next_block, st);
     if (ez != hipSuccess) return ez;
     profile_begin(st);
-    if (atoms) {
+    if (det) {
+        if (atoms)
+            hipLaunchKernelGGL((k_fock<G, R, true, true, true>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+        else
+            hipLaunchKernelGGL((k_fock<G, R, true, false, true>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+    } else if (atoms) {
         hipLaunchKernelGGL((k_fock<G, R, true, true>), dim3(groups), dim3(kGroupThreads), smem, st, a);
     } else if constexpr (G > 4) {
         hipLaunchKernelGGL((k_fock<G, R, true>), dim3(groups), dim3(kGroupThreads), smem, st, a);
@@ -609,11 +682,16 @@ static hipError_t launch_fock_t(const FockArgs &a, int groups, int variant, bool
 }
 
 template <int G, typename R>
-static int resident_t(bool split, size_t smem, bool atoms)
+static int resident_t(bool split, size_t smem, bool atoms, bool det)
 {
     int nb = 0;
     hipError_t e;
-    if (atoms) {
+    if (det) {
+        e = atoms ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fock<G, R, true, true, true>, kGroupThreads,
+                                                                 smem)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fock<G, R, true, false, true>, kGroupThreads,
+                                                                 smem);
+    } else if (atoms) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fock<G, R, true, true>, kGroupThreads, smem);
     } else if constexpr (G > 4) {
         (void)split;
@@ -627,27 +705,28 @@ static int resident_t(bool split, size_t smem, bool atoms)
 
 // Workgroups of the quartet kernel that fit on one CU at once (registers and LDS); 0 if
 // the runtime cannot tell.  Persistent workgroups beyond this would only queue.
-int fock_resident_groups(int g, int prec, int variant, int64_t n, bool atoms)
+int fock_resident_groups(int g, int prec, int variant, int64_t n, bool atoms, bool det)
 {
-    const bool split = variant != 0 || atoms;
-    const size_t smem = fock_smem_bytes(n, prec, split ? 1 : 0);
+    const bool split = variant != 0 || atoms || det;
+    const size_t smem = prec == HFK_MIXED ? FockSmem<float>::total((int)n, split, det)
+                                          : FockSmem<double>::total((int)n, split, det);
     if (prec == HFK_MIXED) {
         switch (g) {
-        case 1: return resident_t<1, float>(split, smem, atoms);
-        case 2: return resident_t<2, float>(split, smem, atoms);
-        case 3: return resident_t<3, float>(split, smem, atoms);
-        case 4: return resident_t<4, float>(split, smem, atoms);
-        case 5: return resident_t<5, float>(true, smem, atoms);
-        default: return resident_t<6, float>(true, smem, atoms);
+        case 1: return resident_t<1, float>(split, smem, atoms, det);
+        case 2: return resident_t<2, float>(split, smem, atoms, det);
+        case 3: return resident_t<3, float>(split, smem, atoms, det);
+        case 4: return resident_t<4, float>(split, smem, atoms, det);
+        case 5: return resident_t<5, float>(true, smem, atoms, det);
+        default: return resident_t<6, float>(true, smem, atoms, det);
         }
     }
     switch (g) {
-    case 1: return resident_t<1, double>(split, smem, atoms);
-    case 2: return resident_t<2, double>(split, smem, atoms);
-    case 3: return resident_t<3, double>(split, smem, atoms);
-    case 4: return resident_t<4, double>(split, smem, atoms);
-    case 5: return resident_t<5, double>(true, smem, atoms);
-    default: return resident_t<6, double>(true, smem, atoms);
+    case 1: return resident_t<1, double>(split, smem, atoms, det);
+    case 2: return resident_t<2, double>(split, smem, atoms, det);
+    case 3: return resident_t<3, double>(split, smem, atoms, det);
+    case 4: return resident_t<4, double>(split, smem, atoms, det);
+    case 5: return resident_t<5, double>(true, smem, atoms, det);
+    default: return resident_t<6, double>(true, smem, atoms, det);
     }
 }
 
@@ -723,7 +802,7 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     }
     if (err != hipSuccess) return err;
     double *fsum = (double *)(ws + L.fsum);
-    if (strategy == HFK_STRATEGY_PRIVATE)
+    if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_DETERMINISTIC)
         hipLaunchKernelGGL(k_sum_private, dim3(nb2), dim3(256), 0, st, a.fpriv, L.groups, n2, fsum);
     else
         hipLaunchKernelGGL(k_copy, dim3(nb2), dim3(256), 0, st, a.fpriv, n2, fsum);

@@ -68,7 +68,7 @@ struct DevHeader {
     int precision;
     int natoms;
     int variant;
-    int pad1;
+    int max_bucket;                 // most pairs in one (band, cell) bucket (fixed pair order only)
     unsigned long long next_block;  // work counter of the quartet kernels (blocks of items)
     long long blocks;               // blocks of the single-molecule kernels (empty ones included)
 };
@@ -174,12 +174,17 @@ int device_cu_count();
 hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, double *boys_g,
                         float *boys_g_f, DevHeader *hdr, int64_t n, const double *xyz, hipStream_t st);
 hipError_t launch_zero_counter(unsigned long long *p, hipStream_t st);
+// fixed_order: pairs within a (band, cell) bucket by pair index (deterministic strategy)
+// instead of the order an atomic cursor hands out.  That mode waits for the stream once to
+// read the largest bucket and returns hipErrorNotSupported, before sorting, when it holds
+// more than kMaxFixedBucket pairs.
+constexpr int kMaxFixedBucket = 4096;
 hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
-                        double tau, hipStream_t st);
+                        double tau, hipStream_t st, bool fixed_order = false);
 hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *dens, double tau,
                        int prec, int strategy, int variant, double *fock, double *e2, hipStream_t st);
 size_t fock_smem_bytes(int64_t n, int prec, int variant);
-int fock_resident_groups(int g, int prec, int variant, int64_t n, bool atoms = false);
+int fock_resident_groups(int g, int prec, int variant, int64_t n, bool atoms = false, bool det = false);
 // Events around the quartet kernel when profiling is enabled (no-ops otherwise).
 void profile_begin(hipStream_t st);
 void profile_end(hipStream_t st);

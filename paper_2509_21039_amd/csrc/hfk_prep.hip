@@ -95,6 +95,7 @@ __global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ b
         hdr->sig_pairs = 0;
         hdr->items = 0;
         hdr->quartets = 0;
+        hdr->max_bucket = 0;
         hdr->centroid[0] = red[0][0] / (double)n;
         hdr->centroid[1] = red[1][0] / (double)n;
         hdr->centroid[2] = red[2][0] / (double)n;
@@ -263,14 +264,26 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
                                                       float *__restrict__ prim_f, double *__restrict__ bra,
                                                       float *__restrict__ bra_f, double *__restrict__ bip,
                                                       float *__restrict__ bip_f, double *__restrict__ kmu,
-                                                      double *__restrict__ kfa, double *__restrict__ bmf)
+                                                      double *__restrict__ kfa, double *__restrict__ bmf,
+                                                      const int *__restrict__ slot)
 {
     const int64_t npair = n * (n + 1) / 2;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npair) return;
-    const int bk = bucket_of[p];
-    if (bk < 0) return;
-    const int pos = atomicAdd(&cur[bk], 1);
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p;
+    int pos;
+    if (slot) {
+        // fixed order: thread x writes position x, holding pair slot[x]
+        if (x >= hdr->sig_pairs) return;
+        pos = (int)x;
+        p = slot[x];
+    } else {
+        // order within a bucket as the atomic cursor hands out places
+        p = x;
+        if (p >= npair) return;
+        const int bk = bucket_of[p];
+        if (bk < 0) return;
+        pos = atomicAdd(&cur[bk], 1);
+    }
     int64_t i, j;
     pair_of_index(p, i, j);
     const double c0 = hdr->centroid[0], c1 = hdr->centroid[1], c2 = hdr->centroid[2];
@@ -322,6 +335,48 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
             bmf[((int64_t)pos * g2 + ab) * 2] = mu[ab];
             bmf[((int64_t)pos * g2 + ab) * 2 + 1] = fa[ab];
         }
+    }
+}
+
+// Fixed pair order (deterministic strategy): every significant pair's index into its
+// bucket's range (in any order), then each bucket's range sorted by pair index, so the
+// bucketed order is a function of the inputs alone.
+__global__ __launch_bounds__(256) void k_slot_fill(int64_t npair, const int *__restrict__ bucket_of,
+                                                   int *__restrict__ cur, int *__restrict__ slot)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npair) return;
+    const int bk = bucket_of[p];
+    if (bk >= 0) slot[atomicAdd(&cur[bk], 1)] = (int)p;
+}
+
+__global__ __launch_bounds__(256) void k_bucket_max(const long long *__restrict__ off, DevHeader *__restrict__ hdr)
+{
+    __shared__ int red[256];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    red[threadIdx.x] = b < kNumBuckets ? (int)(off[b + 1] - off[b]) : 0;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(&hdr->max_bucket, red[0]);
+}
+
+__global__ __launch_bounds__(256) void k_slot_sort(const long long *__restrict__ off, int *__restrict__ slot)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= kNumBuckets) return;
+    const long long lo = off[b], hi = off[b + 1];
+    // insertion sort of one bucket (buckets hold tens of pairs)
+    for (long long x = lo + 1; x < hi; ++x) {
+        const int v = slot[x];
+        long long y = x - 1;
+        while (y >= lo && slot[y] > v) {
+            slot[y + 1] = slot[y];
+            --y;
+        }
+        slot[y + 1] = v;
     }
 }
 
@@ -534,7 +589,7 @@ __global__ void k_group_blocks(const DevHeader *__restrict__ hdr, const long lon
 }
 
 hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
-                        double tau, hipStream_t st)
+                        double tau, hipStream_t st, bool fixed_order)
 {
     DevHeader *hdr = (DevHeader *)(ws + L.hdr);
     const BasisDev *bd = (const BasisDev *)(ws + L.basis);
@@ -551,13 +606,26 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
     hipError_t e = launch_scan(cnt, kNumBuckets, off, (long long *)(ws + L.scan_tmp), nullptr, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bucket_cursors, dim3((kNumBuckets + 255) / 256), dim3(256), 0, st, off, cur, hdr);
+    // fixed order: the pair of every position first (the item counts' storage is free until
+    // the limits are computed below)
+    int *slot = fixed_order ? (int *)(ws + L.nitems) : nullptr;
+    if (fixed_order) {
+        hipLaunchKernelGGL(k_bucket_max, dim3((kNumBuckets + 255) / 256), dim3(256), 0, st, off, hdr);
+        int hmax = 0;
+        e = hipMemcpyAsync(&hmax, &hdr->max_bucket, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        if (hmax > kMaxFixedBucket) return hipErrorNotSupported;
+        hipLaunchKernelGGL(k_slot_fill, dim3(nbp), dim3(bs), 0, st, np, (const int *)(ws + L.bucket_of), cur, slot);
+        hipLaunchKernelGGL(k_slot_sort, dim3((kNumBuckets + 255) / 256), dim3(256), 0, st, off, slot);
+    }
     hipLaunchKernelGGL(k_pair_scatter, dim3(nbp), dim3(bs), 0, st, b, bd, hdr, L.n, L.pcap, xyz, dens,
                        (const double *)(ws + L.q_unsorted), (const int *)(ws + L.bucket_of), cur,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f), (double *)(ws + L.bra),
                        (float *)(ws + L.bra_f), L.atoms ? (double *)(ws + L.bip) : nullptr,
                        L.atoms ? (float *)(ws + L.bip_f) : nullptr, L.pmu ? (double *)(ws + L.pmu) : nullptr,
-                       L.pmu ? (double *)(ws + L.pfa) : nullptr, L.pmu ? (double *)(ws + L.bmf) : nullptr);
+                       L.pmu ? (double *)(ws + L.pfa) : nullptr, L.pmu ? (double *)(ws + L.bmf) : nullptr, slot);
     hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, L.pcap, L.g2,
                        true, L.atoms ? 5 : -1, L.atoms ? 4 : -1,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),

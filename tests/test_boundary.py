@@ -239,3 +239,12 @@ def test_fock_batched_atoms_rejects_bad_rows():
     one = out.value
     assert L.hfk_batched_workspace_bytes_atoms(2, off.ctypes.data_as(p64), 3, 1, 1, ctypes.byref(out)) == hfk.HFK_OK
     assert out.value > one
+
+
+def test_deterministic_strategy_size_limit():
+    """The deterministic strategy is refused above 1024 atoms before any device work; strategy
+    values past it are invalid."""
+    assert _fock_raw(n=1025, strat=3) == hfk.HFK_EUNSUPPORTED
+    assert "deterministic" in hfk.lib().hfk_last_error().decode()
+    assert _fock_raw(strat=4) == hfk.HFK_EINVAL
+    assert _atoms_raw(n=1100, strat=3) == hfk.HFK_EUNSUPPORTED

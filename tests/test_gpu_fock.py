@@ -277,3 +277,91 @@ def test_bounds_above_two(torch_dev, variant):
     assert st["quartets"] == nr
     assert rel_fro(G, Gr) < FP64_TOL, rel_fro(G, Gr)
     assert rel(E2, Er) < FP64_TOL
+
+
+# ------------------------------------------------------------------ deterministic strategy
+
+def _det_builds(torch_dev, s, precision="fp64", reps=3, atoms=False):
+    """reps builds with the deterministic strategy, each on a freshly allocated workspace."""
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    xyz = torch.tensor(s.xyz, device=dev)
+    D = torch.tensor(s.dens, device=dev)
+    g = s.exps.shape[-1]
+    out = []
+    for r in range(reps):
+        nb = hfk.workspace_bytes_atoms(s.natoms, g, precision) if atoms else hfk.workspace_bytes(s.natoms, g, precision)
+        ws = hfk.new_workspace(nb, dev)
+        ws.fill_(r * 37 % 251)   # contents on entry must not matter
+        build = hfk.fock_atoms if atoms else hfk.fock
+        G, E2 = build(xyz, D, s.exps, s.coefs, s.tau, precision=precision, strategy=hfk.STRATEGY_DETERMINISTIC,
+                      workspace=ws)
+        st = hfk.read_stats(ws)
+        assert st["strategy"] == hfk.STRATEGY_DETERMINISTIC
+        out.append((G.cpu().numpy(), float(E2.item()), st["quartets"]))
+        del ws
+    return out
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_deterministic_repeats_bitwise_he64(torch_dev, precision, tol):
+    s = config_system("he64_fp64")
+    announce("deterministic he64 %s" % precision)
+    runs = _det_builds(torch_dev, s, precision)
+    G0, E0, n0 = runs[0]
+    for G, E, nq in runs[1:]:
+        assert np.array_equal(G, G0) and E == E0 and nq == n0
+    Gr, Er, nr = load_golden("he64_fp64")
+    assert rel_fro(G0, Gr) < tol and rel(E0, Er) < tol
+    assert np.array_equal(G0, G0.T)
+
+
+def test_deterministic_repeats_bitwise_ragged_and_atoms(torch_dev):
+    """A ragged random cluster (one basis) and an H/He lattice (per-atom bases)."""
+    from he_inputs import mixed_lattice
+    s = random_cluster(70, 8, box=9.0, tau=1e-9)
+    announce("deterministic ragged 70")
+    runs = _det_builds(torch_dev, s)
+    for G, E, _ in runs[1:]:
+        assert np.array_equal(G, runs[0][0]) and E == runs[0][1]
+    Gr, Er, _ = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
+    assert rel_fro(runs[0][0], Gr) < FP64_TOL
+    m = mixed_lattice((4, 4, 4), seed=12, tau=1e-12)
+    announce("deterministic H/He 64 per-atom")
+    runs = _det_builds(torch_dev, m, atoms=True)
+    for G, E, _ in runs[1:]:
+        assert np.array_equal(G, runs[0][0]) and E == runs[0][1]
+    Gr, Er, _ = oracle.fock_atoms(m.xyz, m.dens, m.exps, m.coefs, m.tau)
+    assert rel_fro(runs[0][0], Gr) < FP64_TOL and rel(runs[0][1], Er) < FP64_TOL
+
+
+def test_deterministic_he512_full_size(torch_dev):
+    """The 512-atom workload with the deterministic strategy: two builds agree bit for bit,
+    and E2, survivors and the stored sample match the oracle."""
+    s = config_system("he512_fp64")
+    announce("deterministic he512")
+    rows, e2_ref, ns_ref = load_golden("he512_fp64_sample")
+    runs = _det_builds(torch_dev, s, reps=2)
+    assert np.array_equal(runs[0][0], runs[1][0]) and runs[0][1] == runs[1][1]
+    G, E2, nq = runs[0]
+    assert nq == ns_ref
+    assert rel(E2, e2_ref) < FP64_TOL
+    scale = np.abs(rows[:, 2]).max()
+    for i, j, v in rows:
+        assert abs(G[int(i), int(j)] - v) <= FP64_TOL * scale, (i, j)
+
+
+def test_deterministic_refuses_a_crowded_bucket(torch_dev):
+    """100 coincident atoms put all 5050 pairs in one (Q band, cell) bucket: the deterministic
+    strategy refuses (its per-bucket sort is sized for realistic buckets), before any sort."""
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    s = random_cluster(100, 3, box=1.0, tau=1e-10)
+    s.xyz[:] = 0.0
+    announce("deterministic crowded bucket")
+    xyz = torch.tensor(s.xyz, device=dev)
+    D = torch.tensor(s.dens, device=dev)
+    with pytest.raises(hfk.HfkError) as ei:
+        hfk.fock(xyz, D, s.exps, s.coefs, s.tau, strategy=hfk.STRATEGY_DETERMINISTIC)
+    assert ei.value.status == hfk.HFK_EUNSUPPORTED
+    assert "bucket" in str(ei.value)
