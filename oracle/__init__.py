@@ -18,6 +18,12 @@ Parity status of each function (what pins it, in ``tests/test_oracle.py``):
   eri4                          pinned (per-centre contractions): two-centre Gaussian-charge closed
                                 form with unequal exponents, coincident-centre value, scaling law
                                 (exponents x l^2, lengths / l gives x l), 8-fold symmetry
+  one_electron_atoms            pinned: 1-D quadrature of overlap and kinetic energy (the latter as
+                                1/2 <g_a'|g_b'>), nucleus-on-centre closed form 2 sqrt(2a/pi), each
+                                Gaussian product as a charge cloud erf(sqrt(p) R)/R away from a nucleus
+  scf (scf.py)                  pinned: one-function closed form 2h/S + J/S^2, D S D = 2 D, the
+                                commutator F D S - S D F at convergence, energy as a trace, orbitals
+                                orthonormal, rotation invariance, the filled-shell case D = 2 S^-1
   *_atoms                       pinned: brute-force plain definition with per-atom bases, reduction
                                 to the one-basis build when every row is equal, atom-permutation
                                 equivariance, far-field S_ii S_kk / R, central differences of E2
@@ -98,6 +104,8 @@ def _load():
         lib.hfo_grad_pair_atoms.argtypes = lib.hfo_grad_pair.argtypes
         lib.hfo_grad_atoms.restype = ctypes.c_int
         lib.hfo_grad_atoms.argtypes = lib.hfo_grad.argtypes
+        lib.hfo_one_electron_atoms.restype = ctypes.c_int
+        lib.hfo_one_electron_atoms.argtypes = [ctypes.c_int64, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
         lib.hfo_num_threads.restype = ctypes.c_int
         lib.hfo_num_threads.argtypes = []
         _lib = lib
@@ -320,3 +328,14 @@ def grad_pair_atoms(xyz, dens, xdens, exps, coefs, tau, Q=None, nthreads: int = 
     if rc != 0:
         raise MemoryError("oracle grad_pair_atoms: out of memory")
     return gr
+
+
+def one_electron_atoms(xyz, charges, exps, coefs):
+    """(S, T, V), each (n, n), for per-atom rows and nuclear charges Z (n,)."""
+    xyz, px, e, pe, c, pc, n, g = _atoms(xyz, exps, coefs)
+    Z, pz = _c(charges)
+    S = np.zeros((n, n)); T = np.zeros((n, n)); V = np.zeros((n, n))
+    if _load().hfo_one_electron_atoms(n, px, pz, g, pe, pc, S.ctypes.data_as(_dp), T.ctypes.data_as(_dp),
+                                      V.ctypes.data_as(_dp)) != 0:
+        raise MemoryError("oracle one_electron_atoms: out of memory")
+    return S, T, V

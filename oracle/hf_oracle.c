@@ -643,6 +643,51 @@ int hfo_grad_pair_atoms(int64_t n, const double *xyz, int g, const double *exps,
     return grad_pair_s(n, xyz, g, exps, coefs, g, dens, xdens, tau, Qin, nthreads, grad);
 }
 
+/* ---------------------------------------------------------------- one-electron integrals */
+
+/* For the self-consistent field around the two-electron build (not part of the paper's
+ * kernel, which computes the electron-repulsion term only): overlap S, kinetic energy T and
+ * nuclear attraction V of contracted s functions, from the standard closed forms of s
+ * Gaussians (p = a + b, mu = a b / p, P = (a A + b B) / p, R = |A - B|):
+ *   S_ab = w_a w_b (pi / p)^(3/2) exp(-mu R^2)
+ *   T_ab = mu (3 - 2 mu R^2) S_ab
+ *   V_ab = - sum_C Z_C w_a w_b (2 pi / p) exp(-mu R^2) F0(p |P - C|^2)
+ * Per-atom rows (astride = g) as the *_atoms functions.  S, T, V are n x n, symmetric. */
+int hfo_one_electron_atoms(int64_t n, const double *xyz, const double *Z, int g, const double *exps,
+                           const double *coefs, double *S, double *T, double *V)
+{
+    double *W = atom_weights(n, g, exps, coefs, g);
+    if (!W) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j <= i; ++j) {
+            const double *A = xyz + 3 * i, *B = xyz + 3 * j;
+            const double *ea = exps + i * g, *eb = exps + j * g, *wa = W + i * g, *wb = W + j * g;
+            double r2 = 0.0;
+            for (int x = 0; x < 3; ++x) r2 += (A[x] - B[x]) * (A[x] - B[x]);
+            double s = 0.0, t = 0.0, v = 0.0;
+            for (int a = 0; a < g; ++a)
+                for (int b = 0; b < g; ++b) {
+                    double p = ea[a] + eb[b], mu = ea[a] * eb[b] / p;
+                    double K = wa[a] * wb[b] * exp(-mu * r2);
+                    double sab = K * pow(HFO_PI / p, 1.5);
+                    s += sab;
+                    t += mu * (3.0 - 2.0 * mu * r2) * sab;
+                    double P[3];
+                    for (int x = 0; x < 3; ++x) P[x] = (ea[a] * A[x] + eb[b] * B[x]) / p;
+                    for (int64_t c = 0; c < n; ++c) {
+                        double pc2 = 0.0;
+                        for (int x = 0; x < 3; ++x) pc2 += (P[x] - xyz[3 * c + x]) * (P[x] - xyz[3 * c + x]);
+                        v -= Z[c] * K * (2.0 * HFO_PI / p) * hfo_boys0(p * pc2);
+                    }
+                }
+            S[i * n + j] = S[j * n + i] = s;
+            T[i * n + j] = T[j * n + i] = t;
+            V[i * n + j] = V[j * n + i] = v;
+        }
+    free(W);
+    return 0;
+}
+
 int hfo_num_threads(void)
 {
 #ifdef _OPENMP

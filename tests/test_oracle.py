@@ -623,3 +623,136 @@ def test_grad_pair_atoms_vs_finite_differences(oracle_lib):
     ge, _, _ = oracle_lib.grad_atoms(s.xyz, s.dens, e, c, 0.0)
     gh = oracle_lib.grad_pair_atoms(s.xyz, s.dens, 0.5 * s.dens, e, c, 0.0)
     assert np.abs(gh - ge).max() <= 1e-12 * np.abs(ge).max()
+
+
+# ------------------------------------------------------------------ one-electron integrals and SCF
+
+def _quad1(f, lo=-40.0, hi=40.0, pts=None):
+    v, _ = integrate.quad(f, lo, hi, epsabs=0, epsrel=1e-13, limit=400, points=pts)
+    return v
+
+
+def test_one_electron_overlap_and_kinetic_by_quadrature(oracle_lib):
+    """S and T of two contracted functions with their own exponents, as sums of products of
+    1-D integrals: S = prod_x <g|g>_x and T = sum_x 1/2 <g'|g'>_x prod_{y != x} <g|g>_y."""
+    rng = np.random.default_rng(61)
+    xyz = rng.uniform(-1.0, 1.0, (2, 3))
+    e, c = random_basis_rows(2, 2, 62)
+    S, T, V = oracle_lib.one_electron_atoms(xyz, [1.0, 2.0], e, c)
+    w = c * (2 * e / math.pi) ** 0.75
+    Sref = Tref = 0.0
+    for a in range(2):
+        for b in range(2):
+            A, B, al, be = xyz[0], xyz[1], e[0, a], e[1, b]
+            ov, ki = [], []
+            for x in range(3):
+                g1 = lambda s, x=x: math.exp(-al * (s - A[x]) ** 2)
+                g2 = lambda s, x=x: math.exp(-be * (s - B[x]) ** 2)
+                ov.append(_quad1(lambda s: g1(s) * g2(s), pts=[A[x], B[x]]))
+                ki.append(0.5 * _quad1(lambda s: (-2 * al * (s - A[x]) * g1(s)) * (-2 * be * (s - B[x]) * g2(s)),
+                                       pts=[A[x], B[x]]))
+            pref = w[0, a] * w[1, b]
+            Sref += pref * ov[0] * ov[1] * ov[2]
+            Tref += pref * (ki[0] * ov[1] * ov[2] + ov[0] * ki[1] * ov[2] + ov[0] * ov[1] * ki[2])
+    assert S[0, 1] == pytest.approx(Sref, rel=1e-12)
+    assert T[0, 1] == pytest.approx(Tref, rel=1e-11)
+    assert S[1, 0] == S[0, 1] and T[1, 0] == T[0, 1]
+
+
+@pytest.mark.parametrize("alpha,Z", [(0.4, 1.0), (3.0, 2.0)])
+def test_nuclear_attraction_on_centre(oracle_lib, alpha, Z):
+    """|g|^2 of a normalised primitive is a unit Gaussian charge of exponent 2a; a nucleus at its
+    centre feels -Z 2 sqrt(2a/pi)."""
+    S, T, V = oracle_lib.one_electron_atoms(np.zeros((1, 3)), [Z], [[alpha]], [[1.0]])
+    assert S[0, 0] == pytest.approx(1.0, rel=1e-14)
+    assert V[0, 0] == pytest.approx(-Z * 2.0 * math.sqrt(2 * alpha / math.pi), rel=1e-13)
+    # kinetic energy of a normalised s Gaussian: 3a/2 (virial of the harmonic form)
+    assert T[0, 0] == pytest.approx(1.5 * alpha, rel=1e-13)
+
+
+def test_nuclear_attraction_as_charge_cloud(oracle_lib):
+    """Each primitive product is a Gaussian charge S_ab of exponent p at P: a nucleus C away
+    adds -Z_C S_ab erf(sqrt(p) |P - C|) / |P - C| (the charge-cloud route, not F0)."""
+    xyz = np.array([[0.0, 0.0, 0.0], [0.9, -0.3, 0.4], [2.5, 1.0, -1.5]])
+    Zs = [0.0, 0.0, 1.7]      # only the third atom carries a nucleus
+    e = np.array([[1.3], [0.6], [2.0]])
+    c = np.ones((3, 1))
+    S, T, V = oracle_lib.one_electron_atoms(xyz, Zs, e, c)
+    a, b = 1.3, 0.6
+    p = a + b
+    P = (a * xyz[0] + b * xyz[1]) / p
+    r = np.linalg.norm(P - xyz[2])
+    ref = -1.7 * S[0, 1] * erf(math.sqrt(p) * r) / r
+    assert V[0, 1] == pytest.approx(ref, rel=1e-13)
+    # far away the cloud is a point charge
+    xyz_far = xyz.copy()
+    xyz_far[2] = [0.0, 0.0, 80.0]
+    S2, _, V2 = oracle_lib.one_electron_atoms(xyz_far, Zs, e, c)
+    assert V2[0, 0] == pytest.approx(-1.7 * S2[0, 0] / np.linalg.norm(xyz_far[2]), rel=1e-12)
+
+
+def _scf_system(shape, seed, tau=1e-12):
+    from he_inputs import mixed_lattice
+    s = mixed_lattice(shape, seed=seed, tau=tau)
+    Z = np.where(s.exps[:, 0] < 5.0, 1.0, 2.0)
+    return s, Z, int(Z.sum()) // 2
+
+
+def test_scf_single_function_closed_form(oracle_lib):
+    """One He atom, one basis function: D = 2/S, and E = 2 h / S + J / S^2 with h = T + V and
+    J = (11|11), each pinned on its own above."""
+    from oracle.scf import scf
+    xyz = np.zeros((1, 3))
+    r = scf(xyz, [2.0], [E3], [C3], 1, 0.0)
+    S, T, V = oracle_lib.one_electron_atoms(xyz, [2.0], [E3], [C3])
+    h = T[0, 0] + V[0, 0]
+    J = oracle_lib.eri(xyz[0], xyz[0], xyz[0], xyz[0], E3, C3)
+    assert r["converged"]
+    assert r["D"][0, 0] == pytest.approx(2.0 / S[0, 0], rel=1e-14)
+    assert r["E"] == pytest.approx(2 * h / S[0, 0] + J / S[0, 0] ** 2, rel=1e-13)
+    assert r["E"] == pytest.approx(-2.807783957, abs=2e-9)   # minimal-basis helium
+
+
+def test_scf_filled_shell_is_inverse_overlap(oracle_lib):
+    """Every orbital occupied (He only): D = 2 S^-1 whatever F is."""
+    from oracle.scf import scf
+    s = random_cluster(6, 71, box=5.0)
+    r = scf(s.xyz, np.full(6, 2.0), np.tile(E3, (6, 1)), np.tile(C3, (6, 1)), 6, 1e-12)
+    assert r["converged"] and r["iterations"] <= 3
+    assert np.abs(r["D"] @ r["S"] - 2 * np.eye(6)).max() < 1e-10
+
+
+def test_scf_converged_properties(oracle_lib):
+    """H/He 32: converged; D S D = 2 D, tr(D S) = 2 nocc, the commutator vanishes, orbitals are
+    S-orthonormal and ascending, and E is the trace formula for the returned D."""
+    from oracle.scf import scf
+    s, Z, nocc = _scf_system((4, 4, 2), 16)
+    r = scf(s.xyz, Z, s.exps, s.coefs, nocc, s.tau)
+    assert r["converged"]
+    D, S, F, H = r["D"], r["S"], r["F"], r["H"]
+    assert np.abs(D @ S @ D - 2 * D).max() < 1e-7
+    assert np.trace(D @ S) == pytest.approx(2 * nocc, rel=1e-10)
+    assert np.abs(F @ D @ S - S @ D @ F).max() < 1e-6
+    C = r["C"]
+    assert np.abs(C.T @ S @ C - np.eye(len(Z))).max() < 1e-10
+    assert np.all(np.diff(r["eps"]) >= 0)
+    G = oracle_lib.fock_atoms(s.xyz, D, s.exps, s.coefs, s.tau)[0]
+    Eref = 0.5 * np.sum(D * (2 * H + G)) + r["enn"]
+    assert r["E"] == pytest.approx(Eref, rel=1e-13)
+
+
+def test_scf_rotation_invariance_and_variational(oracle_lib):
+    """E is unchanged by a rigid rotation, and lies below the energy of the core-Hamiltonian
+    guess density (both idempotent, the SCF one variationally optimal)."""
+    from oracle.scf import scf, density_from, orthogonaliser, nuclear_repulsion
+    s, Z, nocc = _scf_system((4, 2, 2), 18)
+    r = scf(s.xyz, Z, s.exps, s.coefs, nocc, s.tau)
+    R = _rot(3)
+    r2 = scf(s.xyz @ R.T, Z, s.exps, s.coefs, nocc, s.tau)
+    assert r2["E"] == pytest.approx(r["E"], rel=1e-11)
+    S, T, V = oracle_lib.one_electron_atoms(s.xyz, Z, s.exps, s.coefs)
+    H = T + V
+    D0, _, _ = density_from(H, orthogonaliser(S), nocc)
+    G0 = oracle_lib.fock_atoms(s.xyz, D0, s.exps, s.coefs, s.tau)[0]
+    E0 = 0.5 * np.sum(D0 * (2 * H + G0)) + nuclear_repulsion(s.xyz, Z)
+    assert r["E"] < E0
