@@ -178,6 +178,40 @@ hfk_status hfk_fock_grad_atoms(int64_t natoms, const double *xyz, int32_t ngauss
                                double *d_xyz, double *d_dens, double *e2_out,
                                void *workspace, size_t workspace_bytes, void *stream);
 
+/* Self-consistent field around the two-electron build (closed shell).  The paper's kernel
+ * is the electron-repulsion term of the Fock operator; this is the loop on either side of
+ * it: core Hamiltonian H = T + V of contracted s functions with nuclear charges, symmetric
+ * orthogonalisation X = S^(-1/2), F = H + G(D) with G from the screened build (per-atom
+ * bases), energy E = 1/2 sum D o (H + F) + E_nn, orbitals of X F X, D = 2 C_occ C_occ^T
+ * (the nocc lowest orbitals), DIIS on X (F D S - S D F) X over the last 8 iterations, until
+ * |E - E_prev| < e_tol and max |X (F D S - S D F) X| < d_tol, or max_iter Fock builds.
+ * Workspace size for hfk_scf; arguments and errors as hfk_workspace_bytes_atoms. */
+hfk_status hfk_scf_workspace_bytes(int64_t natoms, int32_t ngauss, int32_t precision, size_t *bytes_out);
+
+/*   natoms .. coefs_host   as hfk_fock_atoms (device xyz, host per-atom rows)
+ *   charges_host     [natoms] nuclear charges Z, finite and >= 0 (host)
+ *   nocc             doubly occupied orbitals, 0 .. natoms
+ *   tau, precision   of the two-electron builds; strategy as hfk_fock (DETERMINISTIC makes
+ *                    the whole loop repeat bit for bit)
+ *   max_iter         >= 1; e_tol, d_tol > 0
+ *   dens             [n*n] device: the starting density when use_guess != 0 (else the core
+ *                    Hamiltonian's orbitals start), and on return the density of the last
+ *                    build, whose energy is *energy_host
+ *   orb_energies     [n] device or NULL: orbital energies of the final F, ascending
+ *   energy_host, iterations_host, converged_host   host outputs (Fock builds taken; 1 when
+ *                    both tolerances were met)
+ *   workspace        hfk_scf_workspace_bytes(...) bytes, 256-byte aligned
+ * The call waits for `stream` whenever the loop needs a number on the host and returns when
+ * the loop has ended.  Dense products and eigenproblems run in rocBLAS and rocSOLVER with
+ * their scratch taken from the workspace (HFK_ENOMEM if their own query asks for more).
+ * Errors as hfk_fock_atoms; HFK_EUNSUPPORTED for a (nearly) singular overlap matrix. */
+hfk_status hfk_scf(int64_t natoms, const double *xyz, const double *charges_host, int32_t ngauss,
+                   const double *exps_host, const double *coefs_host, int32_t nocc, double tau,
+                   int32_t precision, int32_t strategy, int32_t max_iter, double e_tol, double d_tol,
+                   double *dens, int32_t use_guess, double *orb_energies, double *energy_host,
+                   int32_t *iterations_host, int32_t *converged_host,
+                   void *workspace, size_t workspace_bytes, void *stream);
+
 /* Workspace size for hfk_fock_batched over `nmol` molecules whose atom ranges are
  * atom_off_host[m] .. atom_off_host[m+1] (CSR, host memory, nondecreasing, starting at 0).
  * with_grad != 0 adds the gradient accumulators. */

@@ -76,6 +76,11 @@ _SIGNATURES = {
                                           ctypes.POINTER(_sz)],
     "hfk_fock_batched_atoms": [ctypes.c_int64, _i64p, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double,
                                ctypes.c_int32, _vp, _vp, _vp, _vp, _sz, _vp],
+    "hfk_scf_workspace_bytes": [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_sz)],
+    "hfk_scf": [ctypes.c_int64, _vp, _dp, ctypes.c_int32, _dp, _dp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _vp, ctypes.c_int32, _vp,
+                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                _vp, _sz, _vp],
     "hfk_fock_grad_atoms": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
     "hfk_fock_atoms": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
@@ -218,6 +223,44 @@ def fock_atoms(xyz, dens, exps, coefs, tau: float, precision="fp64", strategy: i
                                 int(strategy), F.data_ptr(), E2.data_ptr(), workspace.data_ptr(),
                                 workspace.numel(), _stream_handle(stream)))
     return F, E2
+
+
+def scf_workspace_bytes(natoms: int, ngauss: int = 3, precision="fp64") -> int:
+    out = _sz(0)
+    _check(lib().hfk_scf_workspace_bytes(int(natoms), int(ngauss), _PREC[precision], ctypes.byref(out)))
+    return out.value
+
+
+def scf(xyz, charges, exps, coefs, nocc: int, tau: float, precision="fp64", strategy: int = STRATEGY_AUTO,
+        max_iter: int = 100, e_tol: float = 1e-10, d_tol: float = 1e-7, dens0=None, workspace=None, stream=None):
+    """Closed-shell SCF around the two-electron build.  charges: (natoms,) nuclear charges
+    (host); exps/coefs: per-atom rows (natoms, ngauss); dens0: optional device (n, n) start.
+    Returns dict(E, D (device), eps (device), iterations, converged)."""
+    torch = _torch()
+    n = xyz.shape[0]
+    _dev_f64(xyz, "xyz", (n, 3))
+    e, c = _rows(exps, coefs, n)
+    g = e.shape[1]
+    Z = _host_f64(charges)
+    if Z.shape != (n,):
+        raise HfkError(HFK_EINVAL, "charges must be (natoms,)")
+    prec = _PREC[precision]
+    if workspace is None:
+        workspace = new_workspace(scf_workspace_bytes(n, g, prec), xyz.device)
+    if dens0 is not None:
+        _dev_f64(dens0, "dens0", (n, n))
+        D = dens0.clone()
+    else:
+        D = torch.empty((n, n), dtype=torch.float64, device=xyz.device)
+    eps = torch.empty((n,), dtype=torch.float64, device=xyz.device)
+    E = ctypes.c_double(0.0)
+    its = ctypes.c_int32(0)
+    conv = ctypes.c_int32(0)
+    _check(lib().hfk_scf(n, xyz.data_ptr(), _dptr(Z), g, _dptr(e), _dptr(c), int(nocc), float(tau), prec,
+                         int(strategy), int(max_iter), float(e_tol), float(d_tol), D.data_ptr(),
+                         int(dens0 is not None), eps.data_ptr(), ctypes.byref(E), ctypes.byref(its),
+                         ctypes.byref(conv), workspace.data_ptr(), workspace.numel(), _stream_handle(stream)))
+    return {"E": E.value, "D": D, "eps": eps, "iterations": its.value, "converged": bool(conv.value)}
 
 
 def read_stats(workspace, stream=None) -> dict:

@@ -31,7 +31,9 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 
-SOURCES = ["hfk_api.hip", "hfk_prep.hip", "hfk_fock.hip", "hfk_grad.hip", "hfk_batched.hip"]
+SOURCES = ["hfk_api.hip", "hfk_prep.hip", "hfk_fock.hip", "hfk_grad.hip", "hfk_batched.hip", "hfk_scf.hip"]
+# dense products and symmetric eigenproblems of the SCF loop
+LIBS = ["-L/opt/rocm/lib", "-lrocblas", "-lrocsolver", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def _compile(src: str) -> str:
@@ -54,7 +56,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, *LIBS]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))

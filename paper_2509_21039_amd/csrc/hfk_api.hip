@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "hfk_internal.hpp"
+#include "hfk_scf.hpp"
 
 namespace hfk {
 
@@ -478,6 +479,91 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
     if (e != hipSuccess) return hip_fail(e, "fock launch");
     e = launch_header_info(ws + L.hdr, strat, L.groups, precision, 1, st);
     if (e != hipSuccess) return hip_fail(e, "header launch");
+    return HFK_OK;
+}
+
+hfk_status hfk_scf_workspace_bytes(int64_t natoms, int32_t ngauss, int32_t precision, size_t *bytes_out)
+{
+    g_err[0] = 0;
+    if (!bytes_out) return fail(HFK_EINVAL, "bytes_out is NULL");
+    if (natoms < 1) return fail(HFK_EINVAL, "natoms must be >= 1 (got %lld)", (long long)natoms);
+    if (ngauss < 1 || ngauss > HFK_MAX_NGAUSS)
+        return fail(HFK_EINVAL, "ngauss must be in [1, %d] (got %d)", HFK_MAX_NGAUSS, (int)ngauss);
+    if (precision != HFK_FP64 && precision != HFK_MIXED)
+        return fail(HFK_EINVAL, "precision must be HFK_FP64 or HFK_MIXED (got %d)", (int)precision);
+    if (natoms > kMaxAtoms) return fail(HFK_EUNSUPPORTED, "natoms above %lld", (long long)kMaxAtoms);
+    const Layout L = make_layout(natoms, ngauss, precision, 0, groups_cap(device_cu_count()), true);
+    *bytes_out = make_scf_layout(L.total, natoms).total;
+    return HFK_OK;
+}
+
+hfk_status hfk_scf(int64_t natoms, const double *xyz, const double *charges_host, int32_t ngauss,
+                   const double *exps_host, const double *coefs_host, int32_t nocc, double tau, int32_t precision,
+                   int32_t strategy, int32_t max_iter, double e_tol, double d_tol, double *dens, int32_t use_guess,
+                   double *orb_energies, double *energy_host, int32_t *iterations_host, int32_t *converged_host,
+                   void *workspace, size_t workspace_bytes, void *stream)
+{
+    g_err[0] = 0;
+    hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, xyz, tau, precision);
+    if (s != HFK_OK) return s;
+    s = check_rows(natoms, ngauss, exps_host, coefs_host);
+    if (s != HFK_OK) return s;
+    if (!charges_host) return fail(HFK_EINVAL, "charges_host is NULL");
+    for (int64_t a = 0; a < natoms; ++a)
+        if (!isfinite(charges_host[a]) || charges_host[a] < 0.0)
+            return fail(HFK_EINVAL, "charges_host[%lld] must be finite and >= 0", (long long)a);
+    if (nocc < 0 || nocc > natoms) return fail(HFK_EINVAL, "nocc must be in [0, natoms] (got %d)", (int)nocc);
+    if (max_iter < 1) return fail(HFK_EINVAL, "max_iter must be >= 1 (got %d)", (int)max_iter);
+    if (!(e_tol > 0.0) || !(d_tol > 0.0) || !isfinite(e_tol) || !isfinite(d_tol))
+        return fail(HFK_EINVAL, "e_tol and d_tol must be finite and > 0");
+    if (!dens) return fail(HFK_EINVAL, "dens is NULL");
+    if (!energy_host || !iterations_host || !converged_host)
+        return fail(HFK_EINVAL, "energy_host, iterations_host and converged_host must not be NULL");
+    if (!workspace) return fail(HFK_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
+    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_DETERMINISTIC)
+        return fail(HFK_EINVAL, "unknown strategy %d", (int)strategy);
+    if (strategy == HFK_STRATEGY_DETERMINISTIC && natoms > kMaxDetAtoms)
+        return fail(HFK_EUNSUPPORTED, "the deterministic strategy supports natoms <= %lld", (long long)kMaxDetAtoms);
+    if (natoms > kMaxAtoms) return fail(HFK_EUNSUPPORTED, "natoms above %lld", (long long)kMaxAtoms);
+    if (ngauss > kMaxBuiltG) return fail(HFK_EUNSUPPORTED, "ngauss above %d is not built in this version", kMaxBuiltG);
+    const int cus = device_cu_count();
+    if (cus <= 0) return fail(HFK_EHIP, "no HIP device");
+    Layout L = make_layout(natoms, ngauss, precision, 0, groups_cap(cus), true);
+    const ScfLayout SL = make_scf_layout(L.total, natoms);
+    if (workspace_bytes < SL.total)
+        return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, SL.total);
+    TunedConfig cfg = pick_config(strategy, precision, natoms, ngauss);
+    cfg.variant = 1;
+    int strat = cfg.strategy;
+    if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
+    {
+        const bool det = strat == HFK_STRATEGY_DETERMINISTIC;
+        const int fit = fock_resident_groups(ngauss, precision, 1, natoms, true, det);
+        L.groups = cus * (fit > 0 && cfg.gpc > fit ? fit : cfg.gpc);
+        if (det) {
+            hfk_status sd = det_groups(L);
+            if (sd != HFK_OK) return sd;
+        }
+    }
+    char *ws = (char *)workspace;
+    hipStream_t st = (hipStream_t)stream;
+    Basis b;
+    hipError_t e = upload_rows((double *)(ws + L.arow), natoms, ngauss, exps_host, coefs_host, st, &b);
+    if (e != hipSuccess) return hip_fail(e, "basis rows copy");
+    e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (float *)(ws + L.boys_f),
+                     (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz,
+                     st);
+    if (e != hipSuccess) return hip_fail(e, "setup launch");
+    ScfResult r;
+    char msg[256];
+    msg[0] = 0;
+    s = run_scf(L, b, ws, SL, xyz, charges_host, nocc, tau, precision, strat, max_iter, e_tol, d_tol, dens,
+                use_guess != 0, orb_energies, &r, st, msg, sizeof(msg));
+    if (s != HFK_OK) return fail(s, "scf: %s", msg);
+    *energy_host = r.energy;
+    *iterations_host = r.iterations;
+    *converged_host = r.converged;
     return HFK_OK;
 }
 

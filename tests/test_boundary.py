@@ -22,7 +22,8 @@ def test_header_declares_entry_points():
     for must in ("hfk_fock", "hfk_fock_grad", "hfk_fock_batched", "hfk_workspace_bytes",
                  "hfk_batched_workspace_bytes", "hfk_read_stats", "hfk_tune", "hfk_last_error",
                  "hfk_fock_atoms", "hfk_workspace_bytes_atoms", "hfk_fock_grad_atoms",
-                 "hfk_fock_batched_atoms", "hfk_batched_workspace_bytes_atoms"):
+                 "hfk_fock_batched_atoms", "hfk_batched_workspace_bytes_atoms", "hfk_scf",
+                 "hfk_scf_workspace_bytes"):
         assert must in names
 
 
@@ -248,3 +249,42 @@ def test_deterministic_strategy_size_limit():
     assert "deterministic" in hfk.lib().hfk_last_error().decode()
     assert _fock_raw(strat=4) == hfk.HFK_EINVAL
     assert _atoms_raw(n=1100, strat=3) == hfk.HFK_EUNSUPPORTED
+
+
+def _scf_raw(n=4, charges=None, nocc=2, max_iter=50, e_tol=1e-10, d_tol=1e-7, dens=1, strat=0, e=None):
+    ee = np.ascontiguousarray(np.tile([6.36242139, 1.158923, 0.31364979], (n, 1)) if e is None else e)
+    cc = np.ascontiguousarray(np.tile([0.15432897, 0.53532814, 0.44463454], (n, 1)))
+    Z = np.ascontiguousarray(np.full(n, 2.0) if charges is None else charges, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    E = ctypes.c_double(0.0)
+    it = ctypes.c_int32(0)
+    cv = ctypes.c_int32(0)
+    return hfk.lib().hfk_scf(n, 1, Z.ctypes.data_as(dp), 3, ee.ctypes.data_as(dp), cc.ctypes.data_as(dp), nocc,
+                             1e-10, 0, strat, max_iter, e_tol, d_tol, dens, 0, None, ctypes.byref(E),
+                             ctypes.byref(it), ctypes.byref(cv), 256, 1 << 40, None)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(charges=[2.0, -1.0, 2.0, 2.0]), "charges"),
+    (dict(charges=[2.0, float("nan"), 2.0, 2.0]), "charges"),
+    (dict(nocc=5), "nocc"),
+    (dict(nocc=-1), "nocc"),
+    (dict(max_iter=0), "max_iter"),
+    (dict(e_tol=0.0), "e_tol"),
+    (dict(d_tol=float("inf")), "d_tol"),
+    (dict(dens=None), "dens"),
+    (dict(strat=7), "strategy"),
+])
+def test_scf_rejects_invalid_arguments(kw, msg):
+    assert _scf_raw(**kw) == hfk.HFK_EINVAL
+    assert msg in hfk.lib().hfk_last_error().decode()
+
+
+def test_scf_workspace_bytes():
+    out = ctypes.c_size_t(0)
+    L = hfk.lib()
+    assert L.hfk_scf_workspace_bytes(0, 3, 0, ctypes.byref(out)) == hfk.HFK_EINVAL
+    assert L.hfk_scf_workspace_bytes(100, 3, 0, ctypes.byref(out)) == hfk.HFK_OK
+    small = out.value
+    assert L.hfk_workspace_bytes_atoms(100, 3, 0, 0, ctypes.byref(out)) == hfk.HFK_OK
+    assert small > out.value + 10 * 100 * 100 * 8   # the SCF matrices come on top of the Fock layout
