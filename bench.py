@@ -381,6 +381,32 @@ def main():
         except hfk.HfkError as e:
             extras["atoms_hhe512"] = {"error": str(e)}
         try:
+            from he_inputs import mixed_lattice
+            s7 = mixed_lattice((4, 4, 8), seed=17, tau=1e-12)
+            Z7 = np.where(s7.exps[:, 0] < 5.0, 1.0, 2.0)
+            nocc7 = int(Z7.sum()) // 2
+            log("SCF, 128 H/He atoms (per-atom bases)")
+            x7 = torch.tensor(s7.xyz, device=dev)
+            ws7 = hfk.new_workspace(hfk.scf_workspace_bytes(s7.natoms, g, "fp64"), dev)
+            hfk.scf(x7, Z7, s7.exps, s7.coefs, nocc7, s7.tau, max_iter=3, workspace=ws7)   # warm-up
+            torch.cuda.synchronize()
+            hfk.profile_read()
+            hfk.profile_enable(True)
+            t0 = time.time()
+            r7 = hfk.scf(x7, Z7, s7.exps, s7.coefs, nocc7, s7.tau, workspace=ws7)
+            torch.cuda.synchronize()
+            wall7 = (time.time() - t0) * 1e3
+            hfk.profile_enable(False)
+            k7, _ = hfk.profile_read()
+            extras["scf_hhe128"] = {
+                "energy": r7["E"], "iterations": r7["iterations"], "converged": r7["converged"],
+                "total_ms": wall7, "ms_per_iteration": wall7 / max(r7["iterations"], 1),
+                "quartet_kernel_share": k7 / wall7,
+            }
+            del ws7, x7
+        except hfk.HfkError as e:
+            extras["scf_hhe128"] = {"error": str(e)}
+        try:
             from he_inputs import cluster_batch
             log("2000-cluster batch: mixed + gradient, one launch")
             extras["batched_2000_mixed_grad"] = time_batched(hfk, torch, cluster_batch(), 5, 1)
