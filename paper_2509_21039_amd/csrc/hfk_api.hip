@@ -128,14 +128,16 @@ static int g_cfg_gpc = 0;
 // Workgroups the buffers are sized for (the most any configuration launches).
 static int groups_cap(int cus) { return (cus > 0 ? cus : 256) * kMaxGroupsPerCU; }
 
+// need_dens: the call reads a density (every build does; the SCF makes its own)
 static hfk_status check_common(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps,
-                               const double *coefs, const double *dens, double tau, int32_t precision)
+                               const double *coefs, const double *dens, double tau, int32_t precision,
+                               bool need_dens = true)
 {
     if (natoms < 1) return fail(HFK_EINVAL, "natoms must be >= 1 (got %lld)", (long long)natoms);
     if (ngauss < 1 || ngauss > HFK_MAX_NGAUSS)
         return fail(HFK_EINVAL, "ngauss must be in [1, %d] (got %d)", HFK_MAX_NGAUSS, (int)ngauss);
     if (!xyz) return fail(HFK_EINVAL, "xyz is NULL");
-    if (!dens) return fail(HFK_EINVAL, "dens is NULL");
+    if (need_dens && !dens) return fail(HFK_EINVAL, "dens is NULL");
     if (!exps) return fail(HFK_EINVAL, "exps_host is NULL");
     if (!coefs) return fail(HFK_EINVAL, "coefs_host is NULL");
     for (int a = 0; a < ngauss; ++a) {
@@ -504,7 +506,7 @@ hfk_status hfk_scf(int64_t natoms, const double *xyz, const double *charges_host
                    void *workspace, size_t workspace_bytes, void *stream)
 {
     g_err[0] = 0;
-    hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, xyz, tau, precision);
+    hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, nullptr, tau, precision, false);
     if (s != HFK_OK) return s;
     s = check_rows(natoms, ngauss, exps_host, coefs_host);
     if (s != HFK_OK) return s;

@@ -422,7 +422,6 @@ hfk_status run_scf(const Layout &L, const Basis &b, char *ws, const ScfLayout &S
     if (eps_out && hipMemcpyAsync(eps_out, eps, sizeof(double) * n, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return say(c, HFK_EHIP, "eigenvalue copy failed");
     if (hipStreamSynchronize(st) != hipSuccess) return say(c, HFK_EHIP, "stream sync failed");
-    (void)A;
     res->energy = E;
     res->iterations = it;
     res->converged = conv ? 1 : 0;
