@@ -49,8 +49,11 @@ constexpr int kBlockItems = 16;  // items per dynamically fetched block of the q
 // Single-molecule blocks: kTileItems items of one bra.  Bras are taken kGroupBras at a time
 // and their blocks are numbered ket-block-major (block K of every bra of the group, then
 // block K+1), so the workgroups running at the same moment read the same few thousand
-// kets and the ket table is served from L2 instead of streaming past it.
-constexpr int kTileItems = 8;
+// kets and the ket table is served from L2 instead of streaming past it.  Four items
+// (4096 kets, 1.5 MB of FP64 ket data) fit next to the rest in an XCD's 4 MB L2: fabric
+// reads per launch at 512 atoms are 30 GB against 105 GB with eight items and 220 GB with
+// sixteen; two or three items cut reads further but flush rows more often and run slower.
+constexpr int kTileItems = 4;
 constexpr int kGroupBras = 1024;
 
 // Device-side counters written by the build and read back by hfk_read_stats.
