@@ -49,11 +49,11 @@ constexpr double kJcolBudget = 8.0e9;
 
 Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool atoms)
 {
-    (void)prec;
     Layout L;
     memset(&L, 0, sizeof(L));
     L.n = n;
     L.atoms = atoms;
+    L.tile = prec == HFK_MIXED ? 2 * kTileItems : kTileItems;
     L.private_ok = (double)groups * (double)n * (double)n * 8.0 <= kPrivateBudget;
     L.npair = n * (n + 1) / 2;
     L.pcap = ((L.npair + 63) / 64) * 64 + 64;

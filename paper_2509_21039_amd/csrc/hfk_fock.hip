@@ -53,6 +53,7 @@ struct FockArgs {
     const long long *item_off;
     const long long *goff;      // [ngroups + 1] block offsets of the bra groups
     int64_t ngroups;
+    int tile;                   // items per block
     const int *lim;
     const double *dens;
     double *fpriv;
@@ -408,9 +409,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
         s = (int)(lo * kGroupBras + local % kGroupBras);
         if (s >= S) continue;
         const long long i1 = a.item_off[s + 1];
-        m0 = a.item_off[s] + (local / kGroupBras) * kTileItems;
+        m0 = a.item_off[s] + (local / kGroupBras) * a.tile;
         if (m0 >= i1) continue;   // this bra has fewer blocks than the group's longest
-        m1 = m0 + kTileItems < i1 ? m0 + kTileItems : i1;
+        m1 = m0 + a.tile < i1 ? m0 + a.tile : i1;
     }
     int cur = -1, bi = 0, bj = 0;
     double qs = 0.0, ds = 0.0, jb = 0.0;
@@ -759,6 +760,7 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.lim = (const int *)(ws + L.lim);
     a.goff = (const long long *)(ws + L.goff);
     a.ngroups = L.ngroups;
+    a.tile = L.tile;
     a.dens = dens;
     a.fpriv = (double *)(ws + L.fpriv);
     a.jcol = (double *)(ws + L.jcol);

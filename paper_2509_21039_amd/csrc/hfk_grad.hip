@@ -49,6 +49,7 @@ struct GradArgs {
     const long long *item_off;
     const long long *goff;      // [ngroups + 1] block offsets of the bra groups
     int64_t ngroups;
+    int tile;               // items per block
     const int *lim;
     const double *dens;
     const double *xdens;    // X of the two-density contraction, or NULL (Gamma from D alone)
@@ -134,9 +135,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
             s = (int)(lo * kGroupBras + local % kGroupBras);
             if (s >= S) continue;
             const long long i1 = a.item_off[s + 1];
-            m0 = a.item_off[s] + (local / kGroupBras) * kTileItems;
+            m0 = a.item_off[s] + (local / kGroupBras) * a.tile;
             if (m0 >= i1) continue;
-            m1 = m0 + kTileItems < i1 ? m0 + kTileItems : i1;
+            m1 = m0 + a.tile < i1 ? m0 + a.tile : i1;
         }
         const R *prim = GPrec<R>::prim(a);
         const cptr<R> rsg = (cptr<R>)GPrec<R>::rsg(bd);
@@ -496,6 +497,7 @@ hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *
     a.lim = (const int *)(ws + L.lim);
     a.goff = (const long long *)(ws + L.goff);
     a.ngroups = L.ngroups;
+    a.tile = L.tile;
     a.dens = dens;
     a.xdens = xdens;
     a.xyz = xyz;

@@ -46,13 +46,15 @@ constexpr int kSubChunks = 4;
 constexpr int kWaveKets = kWave * kSubChunks;
 constexpr int kItemKets = kWavesPerGroup * kWaveKets;
 constexpr int kBlockItems = 16;  // items per dynamically fetched block of the quartet kernels
-// Single-molecule blocks: kTileItems items of one bra.  Bras are taken kGroupBras at a time
-// and their blocks are numbered ket-block-major (block K of every bra of the group, then
-// block K+1), so the workgroups running at the same moment read the same few thousand
-// kets and the ket table is served from L2 instead of streaming past it.  Four items
-// (4096 kets, 1.5 MB of FP64 ket data) fit next to the rest in an XCD's 4 MB L2: fabric
-// reads per launch at 512 atoms are 30 GB against 105 GB with eight items and 220 GB with
-// sixteen; two or three items cut reads further but flush rows more often and run slower.
+// Single-molecule blocks: kTileItems items of one bra (twice as many with FP32 ket data).
+// Bras are taken kGroupBras at a time and their blocks are numbered ket-block-major (block
+// K of every bra of the group, then block K+1), so the workgroups running at the same
+// moment read the same few thousand kets and the ket table is served from L2 instead of
+// streaming past it.  Four FP64 items (4096 kets, 1.5 MB of ket data) fit next to the rest
+// in an XCD's 4 MB L2: fabric reads per launch at 512 atoms are 30 GB against 105 GB with
+// eight items and 220 GB with sixteen; two or three items cut reads further but flush rows
+// more often and run slower.  The FP32 ket table is half the size, and eight items are the
+// faster choice there.
 constexpr int kTileItems = 4;
 constexpr int kGroupBras = 1024;
 
@@ -114,6 +116,7 @@ struct BasisDev {
 struct Layout {
     int64_t n, npair, pcap;     // pcap = npair rounded up to 64, plus one spare chunk
     int g, g2, groups;          // groups: persistent workgroups the buffers are sized for
+    int tile;                   // items per block (kTileItems, doubled for FP32 ket data)
     bool private_ok;            // per-workgroup copies of F fit the memory budget
     size_t hdr, basis, boys, boys_f;
     size_t q_unsorted, bucket_of, bucket_cnt, bucket_off, bucket_cur;

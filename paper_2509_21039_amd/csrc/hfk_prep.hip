@@ -575,14 +575,14 @@ __global__ void k_fill_i64(long long *__restrict__ p, int64_t m)
 // Blocks of every bra group: kGroupBras x the largest block count of its bras (bras with
 // fewer blocks leave empty slots, skipped by the kernels).
 __global__ void k_group_blocks(const DevHeader *__restrict__ hdr, const long long *__restrict__ nitems,
-                               int64_t ngroups, long long *__restrict__ gcnt)
+                               int64_t ngroups, int tile, long long *__restrict__ gcnt)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ngroups) return;
     const int64_t S = hdr->sig_pairs;
     long long nb = 0;
     for (int64_t s = g * kGroupBras; s < (g + 1) * kGroupBras && s < S; ++s) {
-        const long long b = (nitems[s] + kTileItems - 1) / kTileItems;
+        const long long b = (nitems[s] + tile - 1) / tile;
         nb = b > nb ? b : nb;
     }
     gcnt[g] = nb * kGroupBras;
@@ -638,7 +638,7 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
                     (long long *)(ws + L.scan_tmp), &hdr->items, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_group_blocks, dim3((unsigned)((L.ngroups + 255) / 256)), dim3(256), 0, st, hdr,
-                       (const long long *)(ws + L.nitems), L.ngroups, (long long *)(ws + L.gcnt));
+                       (const long long *)(ws + L.nitems), L.ngroups, L.tile, (long long *)(ws + L.gcnt));
     return launch_scan((const long long *)(ws + L.gcnt), L.ngroups, (long long *)(ws + L.goff),
                        (long long *)(ws + L.scan_tmp), &hdr->blocks, st);
 }
