@@ -310,14 +310,19 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
     }
     unsigned long long kept = 0;
     __shared__ long long blk_at;
-    // blocks of kBlockItems consecutive items, fetched from a global counter until exhausted
+    // blocks of bsz consecutive items, fetched from a global counter until exhausted: at least
+    // kBlockItems, and up to four times that while every workgroup still gets eight blocks
+    // or more (fewer fetches and molecule switches; 2000 clusters: 751 ms against 766 ms
+    // with blocks of 16)
+    long long bsz = M / (8LL * (long long)gridDim.x);
+    bsz = bsz < kBlockItems ? kBlockItems : (bsz > 4 * kBlockItems ? 4 * kBlockItems : bsz);
     for (;;) {
     __syncthreads();
     if (tid == 0) blk_at = (long long)atomicAdd(a.next_block, 1ULL);
     __syncthreads();
-    const long long m0 = blk_at * kBlockItems;
+    const long long m0 = blk_at * bsz;
     if (m0 >= M) break;
-    const long long m1 = m0 + kBlockItems < M ? m0 + kBlockItems : M;
+    const long long m1 = m0 + bsz < M ? m0 + bsz : M;
     int s;
     {
         int lo = 0, hi = S - 1;
