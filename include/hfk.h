@@ -42,7 +42,7 @@ typedef enum hfk_status {
     HFK_EINVAL = 1,        /* an argument is out of range or a required pointer is NULL */
     HFK_ENOMEM = 2,        /* the workspace is smaller than *_workspace_bytes asked for */
     HFK_EHIP = 3,          /* a HIP runtime call failed (message holds the HIP error) */
-    HFK_EUNSUPPORTED = 4   /* valid but outside what this build supports (sizes, device) */
+    HFK_EUNSUPPORTED = 4   /* valid but outside what this library version supports (sizes, device) */
 } hfk_status;
 
 typedef enum hfk_precision {
