@@ -204,7 +204,8 @@ hfk_status hfk_scf_workspace_bytes(int64_t natoms, int32_t ngauss, int32_t preci
  * The call waits for `stream` whenever the loop needs a number on the host and returns when
  * the loop has ended.  Dense products and eigenproblems run in rocBLAS and rocSOLVER with
  * their scratch taken from the workspace (HFK_ENOMEM if their own query asks for more).
- * Errors as hfk_fock_atoms; HFK_EUNSUPPORTED for a (nearly) singular overlap matrix. */
+ * Errors as hfk_fock_atoms; HFK_EUNSUPPORTED for a (nearly) singular overlap matrix; HFK_EHIP
+ * also when an eigensolve does not converge (a Fock matrix or guess density with NaN or Inf). */
 hfk_status hfk_scf(int64_t natoms, const double *xyz, const double *charges_host, int32_t ngauss,
                    const double *exps_host, const double *coefs_host, int32_t nocc, double tau,
                    int32_t precision, int32_t strategy, int32_t max_iter, double e_tol, double d_tol,

@@ -247,6 +247,21 @@ hfk_status diagonalise(Ctx &c, const ScfLayout &SL, char *ws, const double *Fx, 
     return HFK_OK;
 }
 
+// The status the last symmetric eigensolve left in the workspace (waits for the stream):
+// a positive value means it did not converge, as with a matrix that holds NaN or Inf.
+hfk_status solver_info(Ctx &c, char *ws, const ScfLayout &SL)
+{
+    int info = 0;
+    if (hipMemcpyAsync(&info, ws + SL.info, sizeof(int), hipMemcpyDeviceToHost, c.st) != hipSuccess ||
+        hipStreamSynchronize(c.st) != hipSuccess)
+        return say(c, HFK_EHIP, "eigensolver status copy failed");
+    if (info != 0) {
+        snprintf(c.msg, c.msglen, "dsyevd did not converge (info = %d)", info);
+        return HFK_EHIP;
+    }
+    return HFK_OK;
+}
+
 // Solves the (m+1) x (m+1) DIIS system by Gaussian elimination with partial pivoting;
 // false if it is singular.
 bool diis_solve(const std::vector<double> &B, int m, std::vector<double> &coef)
@@ -326,6 +341,7 @@ hfk_status run_scf(const Layout &L, const Basis &b, char *ws, const ScfLayout &S
         return say(c, HFK_EHIP, "nuclear repulsion copy failed");
 
     // X = S^(-1/2) = U s^(-1/2) U^T
+    hfk_status s_ok = HFK_OK;
     if (hipMemcpyAsync(A, S, sizeof(double) * n2, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return say(c, HFK_EHIP, "copy failed");
     if (rocsolver_dsyevd(c.h, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n, A, (rocblas_int)n, eps,
@@ -336,12 +352,12 @@ hfk_status run_scf(const Layout &L, const Basis &b, char *ws, const ScfLayout &S
         if (hipMemcpyAsync(s.data(), eps, sizeof(double) * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return say(c, HFK_EHIP, "eigenvalue copy failed");
+        if ((s_ok = solver_info(c, ws, SL)) != HFK_OK) return s_ok;
         if (!(s[0] > 1e-12 * s[n - 1])) return say(c, HFK_EUNSUPPORTED, "overlap matrix is (nearly) singular");
     }
     hipLaunchKernelGGL(k_scale_cols, dim3(blocks(n2)), dim3(256), 0, st, n, A, eps, T1);
     if (!gemm(c, false, true, (rocblas_int)n, T1, A, X)) return say(c, HFK_EHIP, "dgemm failed");
 
-    hfk_status s_ok = HFK_OK;
     if (!use_guess && (s_ok = diagonalise(c, SL, ws, H, nocc, dens)) != HFK_OK) return s_ok;
 
     std::vector<double> B((size_t)kDiisMax * kDiisMax, 0.0);
@@ -379,6 +395,8 @@ hfk_status run_scf(const Layout &L, const Basis &b, char *ws, const ScfLayout &S
         if (hipMemcpyAsync(&emax, scal + 2, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return say(c, HFK_EHIP, "error copy failed");
+        // the status of the last eigensolve: the one whose orbitals gave this density
+        if ((s_ok = solver_info(c, ws, SL)) != HFK_OK) return s_ok;
         for (int k = 0; k < kDiisMax; ++k) {
             if (age[k] < 0) continue;
             double v = 0.0;
@@ -422,6 +440,7 @@ hfk_status run_scf(const Layout &L, const Basis &b, char *ws, const ScfLayout &S
     if (eps_out && hipMemcpyAsync(eps_out, eps, sizeof(double) * n, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return say(c, HFK_EHIP, "eigenvalue copy failed");
     if (hipStreamSynchronize(st) != hipSuccess) return say(c, HFK_EHIP, "stream sync failed");
+    if ((s_ok = solver_info(c, ws, SL)) != HFK_OK) return s_ok;
     res->energy = E;
     res->iterations = it;
     res->converged = conv ? 1 : 0;
