@@ -388,9 +388,10 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
 
 }  // extern "C"
 
-// Per-atom bases: exponents and weights of every atom, [2][n][g], copied to the workspace
-// (pageable host memory: the copy completes before hipMemcpyAsync returns), and the Basis
-// that points the kernels at them.
+// Per-atom bases: exponents and weights of every atom, [2][n][g], copied to the workspace,
+// and the Basis that points the kernels at them.  The staging vector is pageable host memory
+// that ends with this call, so the copy is waited for here rather than trusting the runtime
+// to have read it when hipMemcpyAsync returns (the wait also covers work queued before it).
 static hipError_t upload_rows(double *arow, int64_t natoms, int32_t ngauss, const double *exps,
                               const double *coefs, hipStream_t st, Basis *b)
 {
@@ -406,7 +407,8 @@ static hipError_t upload_rows(double *arow, int64_t natoms, int32_t ngauss, cons
     for (int a = 0; a < ngauss; ++a) b->alpha[a] = 1.0;   // the one-basis tables stay finite, unused
     b->aexp = arow;
     b->aw = arow + ng;
-    return hipMemcpyAsync(arow, rows.data(), sizeof(double) * 2 * ng, hipMemcpyHostToDevice, st);
+    const hipError_t e = hipMemcpyAsync(arow, rows.data(), sizeof(double) * 2 * ng, hipMemcpyHostToDevice, st);
+    return e != hipSuccess ? e : hipStreamSynchronize(st);
 }
 
 extern "C" {
