@@ -713,6 +713,46 @@ def test_scf_single_function_closed_form(oracle_lib):
     assert r["E"] == pytest.approx(-2.807783957, abs=2e-9)   # minimal-basis helium
 
 
+# STO-3G fit of a 1s Slater function of unit exponent; a Slater exponent zeta scales the
+# Gaussian exponents by zeta^2 (the coefficients are C3).
+STO3G_UNIT_EXPS = np.array([2.227660, 0.405771, 0.109818])
+
+
+def test_scf_textbook_h2():
+    """H2 at R = 1.4 bohr in STO-3G (zeta 1.24): the minimal-basis example of Szabo and Ostlund,
+    Modern Quantum Chemistry (section 3.5), whose electronic energy is -1.8310 hartree
+    (total -1.1167).  Pins the two-centre overlap, kinetic, nuclear-attraction and
+    two-electron integrals and the SCF loop against numbers computed elsewhere."""
+    from he_inputs import H_STO3G_EXPS
+    from oracle.scf import scf
+    R = 1.4
+    xyz = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, R]])
+    r = scf(xyz, [1.0, 1.0], np.tile(H_STO3G_EXPS, (2, 1)), np.tile(C3, (2, 1)), 1, 0.0)
+    assert r["converged"]
+    assert r["E"] - 1.0 / R == pytest.approx(-1.8310, abs=5e-5)
+    assert r["E"] == pytest.approx(-1.1167, abs=5e-5)
+    # the same exponents from the unit-exponent fit
+    assert np.allclose(STO3G_UNIT_EXPS * 1.24 ** 2, H_STO3G_EXPS, rtol=5e-6)
+
+
+def test_scf_textbook_heh_cation():
+    """HeH+ at R = 1.4632 bohr, STO-3G with zeta 2.0925 (He) and 1.24 (H): the worked example of
+    Szabo and Ostlund (section 3.5 and the SCF program of their appendix B): electronic energy
+    -4.227529, total -2.860662 hartree, orbital energies -1.5974 and -0.0617.  Two different
+    nuclei, per-atom bases and an asymmetric density."""
+    from he_inputs import H_STO3G_EXPS
+    from oracle.scf import scf
+    R = 1.4632
+    xyz = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, R]])
+    exps = np.stack([STO3G_UNIT_EXPS * 2.0925 ** 2, H_STO3G_EXPS])
+    r = scf(xyz, [2.0, 1.0], exps, np.tile(C3, (2, 1)), 1, 0.0)
+    assert r["converged"]
+    # the printed exponents carry six digits: 1e-5 hartree covers their rounding
+    assert r["E"] - 2.0 / R == pytest.approx(-4.227529, abs=1e-5)
+    assert r["E"] == pytest.approx(-2.860662, abs=1e-5)
+    assert r["eps"] == pytest.approx([-1.5974, -0.0617], abs=1e-4)
+
+
 def test_scf_filled_shell_is_inverse_overlap(oracle_lib):
     """Every orbital occupied (He only): D = 2 S^-1 whatever F is."""
     from oracle.scf import scf
