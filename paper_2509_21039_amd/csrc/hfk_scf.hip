@@ -121,19 +121,34 @@ __global__ __launch_bounds__(256) void k_antisym(int64_t n, const double *__rest
     out[x] = A[x] - A[r * n + c];
 }
 
-// out[0] = max |a| (one block).
-__global__ __launch_bounds__(256) void k_absmax(int64_t m, const double *__restrict__ a, double *__restrict__ out)
+// The numbers the host needs after each build, in one launch of 3 + kDiisMax blocks, each a
+// fixed-order block reduction (so repeated runs agree bit for bit):
+//   out[0] = <D, H>, out[1] = <D, F>, out[2] = max |e|,
+//   out[3 + k] = <e, e_k> for every history slot k set in `filled` (0 for the others).
+__global__ __launch_bounds__(256) void k_scf_scalars(int64_t n2, const double *__restrict__ D,
+                                                     const double *__restrict__ H, const double *__restrict__ F,
+                                                     const double *__restrict__ e, const double *__restrict__ hist,
+                                                     unsigned filled, double *__restrict__ out)
 {
     __shared__ double red[256];
+    const int q = blockIdx.x;   // uniform over the block: an early return keeps every barrier whole
+    const bool mx = q == 2;
+    const double *a = q < 2 ? D : e;
+    const double *b = q == 0 ? H : (q == 1 ? F : (q == 2 ? e : hist + (int64_t)(q - 3) * n2));
+    if (q >= 3 && !((filled >> (q - 3)) & 1u)) {
+        if (threadIdx.x == 0) out[q] = 0.0;
+        return;
+    }
     double v = 0.0;
-    for (int64_t x = threadIdx.x; x < m; x += 256) v = fmax(v, fabs(a[x]));
+    for (int64_t x = threadIdx.x; x < n2; x += 256) v = mx ? fmax(v, fabs(a[x])) : fma(a[x], b[x], v);
     red[threadIdx.x] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        if (threadIdx.x < w)
+            red[threadIdx.x] = mx ? fmax(red[threadIdx.x], red[threadIdx.x + w]) : red[threadIdx.x] + red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = red[0];
+    if (threadIdx.x == 0) out[q] = red[0];
 }
 
 struct Coefs {
@@ -178,7 +193,7 @@ ScfLayout make_scf_layout(size_t base, int64_t n)
     L.eps = take(sizeof(double) * (size_t)n);
     L.evw = take(sizeof(double) * (size_t)n);
     L.info = take(sizeof(int));
-    L.scal = take(sizeof(double) * 8);
+    L.scal = take(sizeof(double) * 32);
     L.Z = take(sizeof(double) * (size_t)n);
     L.diisF = take(n2 * kDiisMax);
     L.diisE = take(n2 * kDiisMax);
@@ -249,17 +264,20 @@ hfk_status diagonalise(Ctx &c, const ScfLayout &SL, char *ws, const double *Fx, 
 
 // The status the last symmetric eigensolve left in the workspace (waits for the stream):
 // a positive value means it did not converge, as with a matrix that holds NaN or Inf.
+hfk_status info_status(Ctx &c, int info)
+{
+    if (info == 0) return HFK_OK;
+    snprintf(c.msg, c.msglen, "dsyevd did not converge (info = %d)", info);
+    return HFK_EHIP;
+}
+
 hfk_status solver_info(Ctx &c, char *ws, const ScfLayout &SL)
 {
     int info = 0;
     if (hipMemcpyAsync(&info, ws + SL.info, sizeof(int), hipMemcpyDeviceToHost, c.st) != hipSuccess ||
         hipStreamSynchronize(c.st) != hipSuccess)
         return say(c, HFK_EHIP, "eigensolver status copy failed");
-    if (info != 0) {
-        snprintf(c.msg, c.msglen, "dsyevd did not converge (info = %d)", info);
-        return HFK_EHIP;
-    }
-    return HFK_OK;
+    return info_status(c, info);
 }
 
 // Solves the (m+1) x (m+1) DIIS system by Gaussian elimination with partial pivoting;
@@ -372,11 +390,6 @@ hfk_status run_scf(const Layout &L, const Basis &b, char *ws, const ScfLayout &S
         if (ef == hipSuccess) ef = launch_fock(L, b, ws, dens, tau, prec, strat, 1, G, e2tmp, st);
         if (ef != hipSuccess) return say(c, HFK_EHIP, "Fock build failed");
         hipLaunchKernelGGL(k_add, dim3(blocks(n2)), dim3(256), 0, st, n2, H, G, F);
-        double dh = 0.0, df = 0.0;
-        if (rocblas_ddot(c.h, (rocblas_int)n2, dens, 1, H, 1, &dh) != rocblas_status_success ||
-            rocblas_ddot(c.h, (rocblas_int)n2, dens, 1, F, 1, &df) != rocblas_status_success)
-            return say(c, HFK_EHIP, "ddot failed");
-        E = 0.5 * (dh + df) + enn;
         // e = X (F D S - S D F) X into the history slot of the oldest entry
         int slot = 0;
         for (int k = 0; k < kDiisMax; ++k)
@@ -390,20 +403,26 @@ hfk_status run_scf(const Layout &L, const Basis &b, char *ws, const ScfLayout &S
         if (hipMemcpyAsync(hF + (int64_t)slot * n2, F, sizeof(double) * n2, hipMemcpyDeviceToDevice, st) != hipSuccess)
             return say(c, HFK_EHIP, "copy failed");
         age[slot] = it;
-        hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, st, n2, ek, scal + 2);
-        double emax = 0.0;
-        if (hipMemcpyAsync(&emax, scal + 2, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        // E = 1/2 (<D, H> + <D, F>) + E_nn, max |e| and the new row of the DIIS matrix, read
+        // back with one wait
+        unsigned filled = 0;
+        for (int k = 0; k < kDiisMax; ++k)
+            if (age[k] >= 0) filled |= 1u << k;
+        hipLaunchKernelGGL(k_scf_scalars, dim3(3 + kDiisMax), dim3(256), 0, st, n2, dens, H, F, ek, hE, filled,
+                           scal + 8);
+        // with the status of the last eigensolve: the one whose orbitals gave this density
+        double sc[3 + kDiisMax];
+        int info = 0;
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(sc, scal + 8, sizeof(sc), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(&info, ws + SL.info, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
-            return say(c, HFK_EHIP, "error copy failed");
-        // the status of the last eigensolve: the one whose orbitals gave this density
-        if ((s_ok = solver_info(c, ws, SL)) != HFK_OK) return s_ok;
-        for (int k = 0; k < kDiisMax; ++k) {
-            if (age[k] < 0) continue;
-            double v = 0.0;
-            if (rocblas_ddot(c.h, (rocblas_int)n2, ek, 1, hE + (int64_t)k * n2, 1, &v) != rocblas_status_success)
-                return say(c, HFK_EHIP, "ddot failed");
-            B[slot * kDiisMax + k] = B[k * kDiisMax + slot] = v;
-        }
+            return say(c, HFK_EHIP, "scalar copy failed");
+        if ((s_ok = info_status(c, info)) != HFK_OK) return s_ok;
+        E = 0.5 * (sc[0] + sc[1]) + enn;
+        const double emax = sc[2];
+        for (int k = 0; k < kDiisMax; ++k)
+            if (age[k] >= 0) B[slot * kDiisMax + k] = B[k * kDiisMax + slot] = sc[3 + k];
         if (have_old && fabs(E - e_old) < e_tol && emax < d_tol) {
             conv = true;
             break;

@@ -41,6 +41,31 @@ def test_scf_single_helium(torch_dev):
     assert abs(D[0, 0] - ref["D"][0, 0]) < 1e-12
 
 
+@pytest.mark.parametrize("name", ["H2", "HeH+"])
+def test_scf_textbook_diatomics(torch_dev, name):
+    """The minimal-basis H2 (R = 1.4 bohr) and HeH+ (R = 1.4632 bohr, helium zeta 2.0925) of
+    Szabo and Ostlund (section 3.5): total energies -1.1167 and -2.860662 hartree, and the
+    oracle's energy, density and orbital energies."""
+    from he_inputs import H_STO3G_EXPS
+    announce("scf textbook %s" % name)
+    if name == "H2":
+        R, Z, expect, tol = 1.4, [1.0, 1.0], -1.1167, 5e-5
+        e = np.tile(H_STO3G_EXPS, (2, 1))
+    else:
+        R, Z, expect, tol = 1.4632, [2.0, 1.0], -2.860662, 1e-5
+        e = np.stack([np.array([2.227660, 0.405771, 0.109818]) * 2.0925 ** 2, H_STO3G_EXPS])
+    xyz = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, R]])
+    c = np.tile(C3, (2, 1))
+    r, D, eps = _gpu_scf(torch_dev, xyz, Z, e, c, 1, 0.0)
+    ref = oracle_scf(xyz, Z, e, c, 1, 0.0)
+    assert r["converged"]
+    assert r["E"] == pytest.approx(expect, abs=tol)
+    # both loops stop at |dE| < 1e-10 and max |FDS - SDF| < 1e-7
+    assert rel(r["E"], ref["E"]) < 1e-10
+    assert np.abs(D - ref["D"]).max() < 1e-6
+    assert np.abs(eps - ref["eps"]).max() < 1e-6
+
+
 @pytest.mark.parametrize("shape,seed", [((4, 4, 2), 16), ((4, 4, 4), 15)])
 def test_scf_hhe_vs_oracle(torch_dev, shape, seed):
     """H/He lattices (32 and 64 atoms; the 64-atom one is a cation): converged energy, density
