@@ -215,6 +215,16 @@ struct TunedConfig {
 };
 static TunedConfig g_tuned_cfg[2][4];
 
+// The configuration before any tuning.  Timed over whole calls (side kernels included) on
+// MI355X for He 64 to 1024 and H/He 128, FP64 and mixed: ATOMIC was the faster strategy at
+// every size (the per-workgroup copies of F and their summation cost more than the atomics
+// they save), and small systems ran fastest with fewer workgroups per CU (2 at 64 atoms,
+// 4 at 128, the most that fit above).
+static TunedConfig default_config(int64_t n)
+{
+    return TunedConfig{HFK_STRATEGY_ATOMIC, 1, n <= 64 ? 2 : (n <= 128 ? 4 : 6)};
+}
+
 static TunedConfig pick_config(int32_t strategy, int32_t precision, int64_t n, int32_t ngauss)
 {
     TunedConfig c;
@@ -222,7 +232,7 @@ static TunedConfig pick_config(int32_t strategy, int32_t precision, int64_t n, i
         std::lock_guard<std::mutex> lk(g_tune_mu);
         c = g_tuned_cfg[precision][size_class(n)];
     }
-    if (c.strategy == 0) c = TunedConfig{HFK_STRATEGY_PRIVATE, 1, 6};
+    if (c.strategy == 0) c = default_config(n);
     if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_ATOMIC) c.strategy = strategy;
     if (g_cfg_variant >= 0) c.variant = g_cfg_variant;
     if (g_cfg_gpc > 0) c.gpc = g_cfg_gpc;
