@@ -58,9 +58,62 @@ def measured_traffic(stats):
         return None
     for e in t.get("entries", []):
         cfg = e.get("config", {})
-        if (cfg.get("strategy") == stats["strategy"] and cfg.get("variant") == stats["variant"]
-                and cfg.get("groups") == stats["groups"]):
+        if all(cfg.get(k) == stats.get(k) for k in ("strategy", "variant", "groups", "tile_items", "group_bras",
+                                                   "ket_copies")):
             return e.get("bytes_per_launch")
+    return None
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+# Nominal flops of the forward + gradient contraction per kept quartet: 31 (integral) + 45
+# (F1, nine derivative components, Gamma contraction) per primitive quartet, plus 14.
+FLOP_GRAD_PER_PRIM_QUARTET = 31 + 45
+# FP32 vector rates: the published 157.3 TFLOP/s counts packed FP32 (two lanes per
+# instruction); packed FP32 instructions are disabled in this build, so 78.6 TFLOP/s
+# (256 CU x 64 lanes x 2 flop x 2.4 GHz, one FP32 FMA per lane per cycle) is its ceiling.
+FP32_VALU_NONPACKED_TFLOPS = 78.6
+
+
+def stored_oracle(name):
+    """A whole matrix written by tests/golden/make_golden.py (oracle only): (G, E2, survivors)."""
+    with np.load(os.path.join(GOLDEN, name + ".npz"), allow_pickle=False) as z:
+        tri = z["tri"]
+        n = int(round((math.sqrt(8 * tri.size + 1) - 1) / 2))
+        G = np.zeros((n, n))
+        G[np.tril_indices(n)] = tri
+        return G + np.tril(G, -1).T, float(z["e2"]), int(z["survivors"])
+
+
+def stored_grad(name="he128_grad"):
+    path = os.path.join(GOLDEN, name + ".txt")
+    return np.loadtxt(path)
+
+
+def err_vs(x, ref):
+    """Errors of a result against the FP64 oracle: element-wise (max |dx| / max |ref|) and Frobenius."""
+    x = np.asarray(x); ref = np.asarray(ref)
+    return {"max_abs_over_max_ref": float(np.abs(x - ref).max() / np.abs(ref).max()),
+            "fro_rel": float(np.linalg.norm(x - ref) / np.linalg.norm(ref))}
+
+
+# Counter-based FP64 flops of the quartet kernel (rocprofv3 VALU instruction counts), used
+# only while the kernel sources and the launch configuration match the counted run.
+VALU_FILE = os.path.join(ROOT, "profiles", "k_fock_he512_fp64_valu.json")
+
+
+def counted_fp64_flop(stats):
+    try:
+        with open(VALU_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    for e in t.get("entries", []):
+        cfg = e.get("config", {})
+        if all(cfg.get(k) == stats.get(k) for k in ("strategy", "variant", "groups", "tile_items", "group_bras",
+                                                   "ket_copies")):
+            return e.get("fp64_flop_per_launch")
     return None
 
 
@@ -137,36 +190,51 @@ def time_builds(hfk, torch, s, precision, steps, warmup, ws, atoms=False):
             "sclk_mhz": clock.get("sclk_mhz")}
 
 
-def time_grad(hfk, torch, s, steps, warmup):
-    """Forward build followed by the backward (dE2/dR, dE2/dD) per step."""
+def time_grad(hfk, torch, s, steps, warmup, precision="fp64"):
+    """Forward build followed by the backward (dE2/dR, dE2/dD) per step; the gradient
+    kernel's own duration from the library's HIP events around it."""
     dev = torch.device("cuda:0")
     xyz = torch.tensor(s.xyz, device=dev)
     D = torch.tensor(s.dens, device=dev)
     atoms = np.ndim(s.exps) == 2
     g = s.exps.shape[-1]
-    nb = hfk.workspace_bytes_atoms(s.natoms, g, "fp64", True) if atoms else hfk.workspace_bytes(s.natoms, g, "fp64", True)
+    nb = (hfk.workspace_bytes_atoms(s.natoms, g, precision, True) if atoms
+          else hfk.workspace_bytes(s.natoms, g, precision, True))
     ws = hfk.new_workspace(nb, dev)
     g_e2 = torch.ones((1,), dtype=torch.float64, device=dev)
     build = hfk.fock_atoms if atoms else hfk.fock
+    grad = hfk.fock_grad_atoms if atoms else hfk.fock_grad
+    out = {}
 
-    def step():
-        G, E2 = build(xyz, D, s.exps, s.coefs, s.tau, workspace=ws)
-        return hfk.fock_grad(xyz, D, s.exps, s.coefs, s.tau, g_e2=g_e2, fock_in=G, workspace=ws)
+    def step(prof):
+        G, E2 = build(xyz, D, s.exps, s.coefs, s.tau, precision=precision, workspace=ws)
+        if prof:
+            hfk.profile_enable(True)     # events are recorded when the launch is enqueued
+        r = grad(xyz, D, s.exps, s.coefs, s.tau, precision=precision, g_e2=g_e2, fock_in=G, workspace=ws)
+        if prof:
+            hfk.profile_enable(False)
+        out["d_xyz"] = r[0]
+        return r
 
     for _ in range(warmup):
-        step()
+        step(False)
     torch.cuda.synchronize()
+    hfk.profile_read()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        step()
+        step(True)
     e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps
+    kms, nl = hfk.profile_read()
+    return {"ms_per_step": e0.elapsed_time(e1) / steps, "grad_kernel_ms": kms / max(nl, 1),
+            "d_xyz": out["d_xyz"].cpu().numpy(), "quartets": hfk.read_stats(ws)["quartets"]}
 
 
 def time_batched(hfk, torch, systems, steps, warmup):
+    """The ragged batch, mixed + gradient in one launch, tuned first; errors of the sampled
+    clusters against the stored oracle results."""
     from he_inputs import pack_batch
     dev = torch.device("cuda:0")
     off, xyz, dens = pack_batch(systems)
@@ -185,15 +253,53 @@ def time_batched(hfk, torch, systems, steps, warmup):
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        hfk.fock_batched(off, X, Dp, s0.exps, s0.coefs, s0.tau, precision="mixed", with_grad=True, workspace=ws)
+        F, E2, g = hfk.fock_batched(off, X, Dp, s0.exps, s0.coefs, s0.tau, precision="mixed", with_grad=True,
+                                    workspace=ws)
     e1.record()
     torch.cuda.synchronize()
     hfk.profile_enable(False)
     kms, nl = hfk.profile_read()
     ms = e0.elapsed_time(e1) / steps
-    return {"molecules": len(systems), "atoms": int(off[-1]), "quartets": stats["quartets"],
-            "ms_per_batch": ms, "kernel_ms": kms / max(nl, 1), "quartets_per_s": stats["quartets"] / (ms / 1e3),
-            "groups_per_cu": gpc}
+    kernel_ms = kms / max(nl, 1)
+    q = stats["quartets"]
+    g_ = len(s0.exps)
+    achieved = q * (g_ ** 4 * FLOP_GRAD_PER_PRIM_QUARTET + FLOP_SCATTER_PER_QUARTET) / (kernel_ms / 1e3) / 1e12
+    res = {"molecules": len(systems), "atoms": int(off[-1]), "quartets": q,
+           "ms_per_batch": ms, "kernel_ms": kernel_ms, "quartets_per_s": q / (ms / 1e3),
+           "config": {"groups_per_cu": gpc, "workgroups": stats["groups"], "items_per_block": stats["tile_items"]},
+           "roofline": {"bound": "alu", "kernel": "k_batched<3,float,grad>", "achieved": achieved,
+                        "unit": "TFLOP/s", "flop_per_quartet": g_ ** 4 * FLOP_GRAD_PER_PRIM_QUARTET
+                        + FLOP_SCATTER_PER_QUARTET,
+                        "peak_fp32_packed": FP32_VALU_PEAK_TFLOPS, "frac_fp32_packed": achieved / FP32_VALU_PEAK_TFLOPS,
+                        "peak_fp32_nonpacked": FP32_VALU_NONPACKED_TFLOPS,
+                        "frac_fp32_nonpacked": achieved / FP32_VALU_NONPACKED_TFLOPS}}
+    try:
+        with np.load(os.path.join(GOLDEN, "batched_2000_sample.npz"), allow_pickle=False) as z:
+            counts = np.array([s.natoms for s in systems], dtype=np.int64)
+            doff = np.concatenate([[0], np.cumsum(counts ** 2)])
+            Fh, Eh, gh = F.cpu().numpy(), E2.cpu().numpy(), g.cpu().numpy()
+            worst = {"G_max_abs_over_max_ref": 0.0, "E2_rel": 0.0, "grad_max_abs_over_max_ref": 0.0}
+            t0 = g0 = 0
+            for m, n, e2r in zip(z["mol"], z["natoms"], z["e2"]):
+                n = int(n)
+                nt = n * (n + 1) // 2
+                Gr = np.zeros((n, n))
+                Gr[np.tril_indices(n)] = z["tri"][t0:t0 + nt]
+                Gr = Gr + np.tril(Gr, -1).T
+                gr = z["grad"][g0:g0 + n]
+                t0 += nt
+                g0 += n
+                Fm = Fh[doff[m]:doff[m] + n * n].reshape(n, n)
+                worst["G_max_abs_over_max_ref"] = max(worst["G_max_abs_over_max_ref"],
+                                                      err_vs(Fm, Gr)["max_abs_over_max_ref"])
+                worst["E2_rel"] = max(worst["E2_rel"], abs(Eh[m] - e2r) / abs(e2r))
+                worst["grad_max_abs_over_max_ref"] = max(worst["grad_max_abs_over_max_ref"],
+                                                         err_vs(gh[off[m]:off[m + 1]], gr)["max_abs_over_max_ref"])
+            res["errors_vs_oracle"] = dict(worst, clusters=int(len(z["mol"])),
+                                           note="largest over the stored 50 clusters (the ten largest and 40 drawn)")
+    except OSError:
+        res["errors_vs_oracle"] = None
+    return res
 
 
 def cpu_baseline(s, target_s=12.0):
@@ -235,6 +341,51 @@ def cpu_baseline(s, target_s=12.0):
             "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
+def plain_copy(torch, dev, nbytes=512 << 20):
+    """A device copy of known size: the reference that scales the traffic counters."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    return nbytes
+
+
+def run_probe(hfk, torch, dev, which):
+    """One warm-up and one timed call of the batched or gradient workload in the untuned
+    default configuration, then a plain copy; prints what ran."""
+    from he_inputs import cluster_batch, config_system, pack_batch
+    info = {"probe": which}
+    if which == "batched":
+        systems = cluster_batch()
+        off, xyz, dens = pack_batch(systems)
+        X = torch.tensor(xyz, device=dev)
+        Dp = torch.tensor(dens, device=dev)
+        s0 = systems[0]
+        ws = hfk.new_workspace(hfk.batched_workspace_bytes(off, len(s0.exps), "mixed", True), dev)
+        for _ in range(2):
+            t0 = time.perf_counter()
+            hfk.fock_batched(off, X, Dp, s0.exps, s0.coefs, s0.tau, precision="mixed", with_grad=True, workspace=ws)
+            torch.cuda.synchronize()
+            info.setdefault("call_ms", []).append((time.perf_counter() - t0) * 1e3)
+        st = hfk.read_stats(ws)
+    else:
+        s = config_system("he128_grad")
+        X = torch.tensor(s.xyz, device=dev)
+        D = torch.tensor(s.dens, device=dev)
+        ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, len(s.exps), "fp64", True), dev)
+        g_e2 = torch.ones((1,), dtype=torch.float64, device=dev)
+        for _ in range(2):
+            t0 = time.perf_counter()
+            G, _ = hfk.fock(X, D, s.exps, s.coefs, s.tau, workspace=ws)
+            hfk.fock_grad(X, D, s.exps, s.coefs, s.tau, g_e2=g_e2, fock_in=G, workspace=ws)
+            torch.cuda.synchronize()
+            info.setdefault("call_ms", []).append((time.perf_counter() - t0) * 1e3)
+        st = hfk.read_stats(ws)
+    info.update({"quartets": st["quartets"], "groups": st["groups"], "tile_items": st.get("tile_items"),
+                 "copy_bytes": plain_copy(torch, dev)})
+    print(json.dumps(info), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +398,15 @@ def main():
                          "512 MiB device copy, for hardware-counter runs; prints the configuration")
     ap.add_argument("--probe-strategy", type=int, default=2, choices=[1, 2],
                     help="accumulation strategy of the traffic probe (1 private copies, 2 atomics)")
+    ap.add_argument("--probe-shape", default="",
+                    help="launch shape of the traffic probe: gpc,tile_items,group_bras,ket_copies "
+                         "(default: the untuned default)")
+    ap.add_argument("--batched-probe", action="store_true",
+                    help="one warm-up and one timed call of the 2000-cluster batch (mixed + gradient, default "
+                         "configuration, no tuning) and one plain 512 MiB device copy, for counter runs")
+    ap.add_argument("--grad-probe", action="store_true",
+                    help="one warm-up and one timed forward + backward of the 128-atom lattice (FP64, default "
+                         "configuration) and one plain 512 MiB device copy, for counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the Fock build here is single-GPU (the multi-GPU "
@@ -262,22 +422,26 @@ def main():
     dev = torch.device("cuda:0")
     s = config_system("he512_fp64")
     g = len(s.exps)
+    if args.batched_probe or args.grad_probe:
+        return run_probe(hfk, torch, dev, "batched" if args.batched_probe else "grad")
     if args.traffic_probe:
         # one build in a fixed configuration (hybrid kernel, default workgroups), then a copy
         ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, g, "fp64"), dev)
         xyz_t = torch.tensor(s.xyz, device=dev)
         D_t = torch.tensor(s.dens, device=dev)
-        hfk.set_config(1, 0)
+        if args.probe_shape:
+            gpc, tile, gbras, kcop = (int(v) for v in args.probe_shape.split(","))
+            hfk.set_config(1, gpc)
+            hfk.set_shape(tile, gbras, kcop)
+        else:
+            hfk.set_config(1, 0)
         hfk.fock(xyz_t, D_t, s.exps, s.coefs, s.tau, strategy=args.probe_strategy, workspace=ws)
         torch.cuda.synchronize()
         st = hfk.read_stats(ws)
-        nbytes = 512 << 20
-        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
+        nbytes = plain_copy(torch, dev)
         print(json.dumps({"copy_bytes": nbytes, "strategy": st["strategy"], "variant": st["variant"],
-                          "groups": st["groups"], "source_sha256": kernel_source_hash()}), flush=True)
+                          "groups": st["groups"], "tile_items": st["tile_items"], "group_bras": st["group_bras"],
+                          "ket_copies": st["ket_copies"], "source_sha256": kernel_source_hash()}), flush=True)
         return
     ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, g, "fp64"), dev)
     log("he512 fp64: autotune")
@@ -322,6 +486,18 @@ def main():
                      "flop_per_quartet": flop_per_quartet(g)},
         "e2": r["e2"],
     }
+    try:
+        Gr, Er, nr = stored_oracle("he512_fp64")
+        out["errors_vs_oracle"] = {"G": err_vs(r["F"].cpu().numpy(), Gr), "E2_rel": abs(r["e2"] - Er) / abs(Er),
+                                   "quartets_equal": q == nr, "oracle": "tests/golden/he512_fp64.npz"}
+    except OSError:
+        out["errors_vs_oracle"] = None
+    counted = counted_fp64_flop(r["stats"])
+    if counted is not None:
+        out["roofline"]["counted_flop_per_launch"] = counted
+        out["roofline"]["counted_frac"] = counted / (r["kernel_ms"] / 1e3) / 1e12 / FP64_VALU_PEAK_TFLOPS
+    else:
+        out["roofline"]["counted_frac"] = None
     del r
     if not args.no_extras:
         extras = {}
@@ -338,16 +514,29 @@ def main():
             b = time_builds(hfk, torch, s3, "mixed", 3, 1, ws3)
             qa = a["stats"]["quartets"]
             Fa, Fb = a["F"], b["F"]
+            mixed_tflops = b["stats"]["quartets"] * flop_per_quartet(g) / (b["kernel_ms"] / 1e3) / 1e12
             extras["mixed_he1024"] = {
                 "quartets": qa,
                 "fp64_quartets_per_s": qa / (a["ms_per_step"] / 1e3),
                 "mixed_quartets_per_s": b["stats"]["quartets"] / (b["ms_per_step"] / 1e3),
                 "speedup_vs_fp64": a["ms_per_step"] / b["ms_per_step"],
+                "fp64_kernel_ms": a["kernel_ms"], "mixed_kernel_ms": b["kernel_ms"],
                 "rel_err_F_vs_fp64": float(torch.linalg.norm(Fb - Fa) / torch.linalg.norm(Fa)),
                 "rel_err_E2_vs_fp64": abs(b["e2"] - a["e2"]) / abs(a["e2"]),
-                "pct_fp32_valu_peak_nominal": 100.0 * b["stats"]["quartets"] * flop_per_quartet(g)
-                / (b["kernel_ms"] / 1e3) / 1e12 / FP32_VALU_PEAK_TFLOPS,
+                "mixed_tflops_nominal": mixed_tflops,
+                "pct_fp32_packed_peak_nominal": 100.0 * mixed_tflops / FP32_VALU_PEAK_TFLOPS,
+                "pct_fp32_nonpacked_peak_nominal": 100.0 * mixed_tflops / FP32_VALU_NONPACKED_TFLOPS,
+                "fp32_peaks_tflops": {"packed": FP32_VALU_PEAK_TFLOPS, "nonpacked": FP32_VALU_NONPACKED_TFLOPS,
+                                      "note": "packed FP32 is disabled in this build"},
             }
+            try:
+                Gr3, Er3, nr3 = stored_oracle("he1024_fp64")
+                extras["mixed_he1024"]["errors_vs_oracle"] = {
+                    "fp64": {"G": err_vs(Fa.cpu().numpy(), Gr3), "E2_rel": abs(a["e2"] - Er3) / abs(Er3)},
+                    "mixed": {"G": err_vs(Fb.cpu().numpy(), Gr3), "E2_rel": abs(b["e2"] - Er3) / abs(Er3)},
+                    "quartets_equal": qa == nr3 and b["stats"]["quartets"] == nr3}
+            except OSError:
+                extras["mixed_he1024"]["errors_vs_oracle"] = None
             del ws3, a, b, Fa, Fb
             torch.cuda.empty_cache()
         except hfk.HfkError as e:
@@ -358,14 +547,27 @@ def main():
             ws4 = hfk.new_workspace(hfk.workspace_bytes(s4.natoms, g, "fp64"), dev)
             f4 = time_builds(hfk, torch, s4, "fp64", 10, 2, ws4)
             fg = time_grad(hfk, torch, s4, 10, 2)
+            fgm = time_grad(hfk, torch, s4, 10, 2, precision="mixed")
             q4 = f4["stats"]["quartets"]
+            gtf = q4 * (g ** 4 * FLOP_GRAD_PER_PRIM_QUARTET + FLOP_SCATTER_PER_QUARTET) / (fg["grad_kernel_ms"] / 1e3) / 1e12
             extras["fwd_grad_he128"] = {
                 "quartets": q4,
-                "fwd_ms": f4["ms_per_step"], "fwd_grad_ms": fg,
+                "fwd_ms": f4["ms_per_step"], "fwd_grad_ms": fg["ms_per_step"],
                 "fwd_quartets_per_s": q4 / (f4["ms_per_step"] / 1e3),
-                "fwd_grad_quartets_per_s": q4 / (fg / 1e3),
-                "fwd_grad_over_fwd_time": fg / f4["ms_per_step"],
+                "fwd_grad_quartets_per_s": q4 / (fg["ms_per_step"] / 1e3),
+                "fwd_grad_over_fwd_time": fg["ms_per_step"] / f4["ms_per_step"],
+                "mixed_fwd_grad_ms": fgm["ms_per_step"],
+                "grad_kernel_ms": fg["grad_kernel_ms"], "mixed_grad_kernel_ms": fgm["grad_kernel_ms"],
+                "grad_roofline": {"bound": "alu", "kernel": "k_grad<3,double>", "achieved": gtf, "unit": "TFLOP/s",
+                                  "peak": FP64_VALU_PEAK_TFLOPS, "frac": gtf / FP64_VALU_PEAK_TFLOPS,
+                                  "flop_per_quartet": g ** 4 * FLOP_GRAD_PER_PRIM_QUARTET + FLOP_SCATTER_PER_QUARTET},
             }
+            try:
+                gr = stored_grad("he128_grad")
+                extras["fwd_grad_he128"]["errors_vs_oracle"] = {"fp64": err_vs(fg["d_xyz"], gr),
+                                                                "mixed": err_vs(fgm["d_xyz"], gr)}
+            except OSError:
+                extras["fwd_grad_he128"]["errors_vs_oracle"] = None
         except hfk.HfkError as e:
             extras["fwd_grad_he128"] = {"error": str(e)}
         try:
@@ -381,8 +583,8 @@ def main():
             f6 = time_builds(hfk, torch, s6, "fp64", 10, 2, ws6, atoms=True)
             fg6 = time_grad(hfk, torch, s6, 10, 2)
             extras["atoms_hhe128_fwd_grad"] = {
-                "quartets": f6["stats"]["quartets"], "fwd_ms": f6["ms_per_step"], "fwd_grad_ms": fg6,
-                "fwd_grad_over_fwd_time": fg6 / f6["ms_per_step"],
+                "quartets": f6["stats"]["quartets"], "fwd_ms": f6["ms_per_step"], "fwd_grad_ms": fg6["ms_per_step"],
+                "fwd_grad_over_fwd_time": fg6["ms_per_step"] / f6["ms_per_step"],
             }
             extras["atoms_hhe512"] = {
                 "quartets": qa,

@@ -24,7 +24,11 @@
  *   - Arguments are validated on the host before any HIP call; an invalid call enqueues
  *     nothing.  A non-zero hfk_status is returned on failure and hfk_last_error() gives a
  *     thread-local message.  No C++ exception crosses this interface.
- *   - The density must be symmetric; the library does not check it.
+ *   - The density must be symmetric (the kernel listing reads dens as a symmetric matrix:
+ *     the Coulomb scatter uses D_kl for both orders of k and l, the exchange reads D_ik,
+ *     D_jl, D_il and D_jk for one order each).  The library does not check it unless debug
+ *     mode is on (hfk_set_debug), in which case a density that is not symmetric is refused
+ *     with HFK_ENOTSYM before any build work.
  *   - Calls that share a workspace must not overlap in time (same stream, or ordered).
  */
 #ifndef HFK_H
@@ -42,7 +46,8 @@ typedef enum hfk_status {
     HFK_EINVAL = 1,        /* an argument is out of range or a required pointer is NULL */
     HFK_ENOMEM = 2,        /* the workspace is smaller than *_workspace_bytes asked for */
     HFK_EHIP = 3,          /* a HIP runtime call failed (message holds the HIP error) */
-    HFK_EUNSUPPORTED = 4   /* valid but outside what this library version supports (sizes, device) */
+    HFK_EUNSUPPORTED = 4,  /* valid but outside what this library version supports (sizes, device) */
+    HFK_ENOTSYM = 5        /* debug mode only: a density is not symmetric within the debug tolerance */
 } hfk_status;
 
 typedef enum hfk_precision {
@@ -80,6 +85,12 @@ typedef struct hfk_stats {
     int32_t groups;          /* persistent workgroups launched */
     int32_t precision;       /* hfk_precision used */
     int32_t variant;         /* quartet-kernel variant used (hfk_set_config) */
+    int32_t tile_items;      /* items (1024 kets each) per block of the single-molecule
+                                kernels, or items (256 kets) per block of the batched one */
+    int32_t group_bras;      /* bras per group whose blocks are numbered ket-block-major */
+    int32_t ket_copies;      /* copies of the ket-side Coulomb vector (= groups: one per
+                                workgroup, plain read-modify-writes; fewer: shared, atomics) */
+    int32_t reserved;
 } hfk_stats;
 
 /* Workspace size (bytes) for hfk_fock / hfk_fock_grad on `natoms` atoms with `ngauss`
@@ -259,22 +270,49 @@ hfk_status hfk_fock_batched_atoms(int64_t nmol, const int64_t *atom_off_host, co
  * into *out.  Errors: HFK_EINVAL for NULL arguments, HFK_EHIP. */
 hfk_status hfk_read_stats(const void *workspace, void *stream, hfk_stats *out);
 
-/* Autotuner: times the forward build of the given system under every candidate
- * (accumulation strategy x quartet-kernel variant x persistent workgroups per compute
- * unit) on `stream`, keeps the fastest for this (precision, size class) for the rest of the
- * process, and writes the table to cache_path as JSON when cache_path is not NULL.
- * best_out (may be NULL) receives the chosen hfk_strategy.  Inputs and workspace as
- * hfk_fock (fock and e2 are overwritten).  Waits for `stream`.  Errors as hfk_fock. */
+/* The counters of the last successful build call made on this thread (hfk_fock*,
+ * hfk_fock_grad*, hfk_fock_batched*): waits for that call's stream and reads its workspace,
+ * which must still be allocated.  Errors: HFK_EINVAL for NULL out or when this thread has
+ * made no build call, HFK_EHIP. */
+hfk_status hfk_last_stats(hfk_stats *out);
+
+/* Debug mode, process-wide, off by default.  While it is on, every call that takes a
+ * density (hfk_fock*, hfk_fock_grad* for dens and g_fock, hfk_fock_batched* per molecule,
+ * hfk_scf for a guess density) first checks it on the device, waits for `stream`, and
+ * refuses it before any build work:
+ *   HFK_EINVAL    an entry is NaN or infinite;
+ *   HFK_ENOTSYM   some |D_ij - D_ji| > sym_tol * max_ij |D_ij| (per molecule for batches;
+ *                 the message names the largest difference, and the first molecule).
+ * sym_tol must be finite and >= 0 (0 asks for exact symmetry).  Errors: HFK_EINVAL. */
+hfk_status hfk_set_debug(int32_t on, double sym_tol);
+
+/* Autotuner of the forward build.  Times hfk_fock on the given system on `stream` and
+ * searches the launch configuration one dimension at a time, starting from the untuned
+ * default and keeping a candidate only when it beats the best so far:
+ *   persistent workgroups per compute unit 1..6 (capped at what fits on a CU),
+ *   quartet-tile shape: items per block {1, 2, 4, 8, 16} x bras per group {256 .. 4096},
+ *   ket-side Coulomb vectors {one per workgroup, 8 shared, 32 shared},
+ *   accumulation strategy {ATOMIC, PRIVATE}, quartet-kernel variant {hybrid, direct}.
+ * The result is kept for the rest of the process under (device architecture, precision,
+ * size bucket ceil(log2 natoms)) and written to cache_path as JSON when cache_path is not
+ * NULL (with every other tuned entry of the process).  best_out (may be NULL) receives the
+ * chosen hfk_strategy.  Inputs and workspace as hfk_fock (fock and e2 are overwritten).
+ * Waits for `stream`.  Errors as hfk_fock. */
 hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss,
                     const double *exps_host, const double *coefs_host,
                     const double *dens, double tau, int32_t precision,
                     double *fock, double *e2, void *workspace, size_t workspace_bytes,
                     void *stream, const char *cache_path, int32_t *best_out);
 
-/* Autotuner of the batched path: times hfk_fock_batched on the given batch for 1..3
- * persistent workgroups per compute unit, keeps the fastest for the rest of the process
- * (written to cache_path with the hfk_tune table when cache_path is not NULL) and returns it
- * in best_gpc_out (may be NULL).  Arguments as hfk_fock_batched (outputs overwritten). */
+/* Autotuner of the batched path: times hfk_fock_batched on the given batch, one dimension
+ * at a time from the untuned default: waves per workgroup {8, 4}, persistent workgroups per
+ * compute unit 1..4, items (256 kets) per block {auto, 8, 16, 32, 64, 128}, and the
+ * accumulation strategy {shared: blocks of a molecule added to G with atomics; owned:
+ * molecules up to a work bound run whole in one workgroup and are stored without atomics,
+ * bound {2^14, 2^16, 2^18} quartets}.  Keeps the fastest for the rest of the process under (device
+ * architecture, precision), writes the table to cache_path when it is not NULL, and
+ * returns the chosen workgroups per CU in best_gpc_out (may be NULL).  Arguments as
+ * hfk_fock_batched (outputs overwritten). */
 hfk_status hfk_tune_batched(int64_t nmol, const int64_t *atom_off_host, const double *xyz,
                             int32_t ngauss, const double *exps_host, const double *coefs_host,
                             const double *dens_packed, double tau, int32_t precision,
@@ -282,9 +320,13 @@ hfk_status hfk_tune_batched(int64_t nmol, const int64_t *atom_off_host, const do
                             void *workspace, size_t workspace_bytes, void *stream,
                             const char *cache_path, int32_t *best_gpc_out);
 
-/* Loads a table written by hfk_tune / hfk_tune_batched (JSON).  Errors: HFK_EINVAL (NULL,
- * unreadable, or not such a table). */
+/* Loads a table written by hfk_tune / hfk_tune_batched (JSON); entries for another device
+ * architecture are kept but not used on this one.  Errors: HFK_EINVAL (NULL, unreadable,
+ * not such a table, or an entry out of range). */
 hfk_status hfk_load_tuning(const char *cache_path);
+
+/* Forgets every tuned entry of the process (the untuned defaults apply again). */
+hfk_status hfk_clear_tuning(void);
 
 /* Process-wide override of the launch configuration of hfk_fock, for tuning and tests:
  *   variant          0 = every primitive quartet evaluates the Boys function in place,
@@ -294,8 +336,36 @@ hfk_status hfk_load_tuning(const char *cache_path);
  * Errors: HFK_EINVAL for values outside these sets. */
 hfk_status hfk_set_config(int32_t variant, int32_t groups_per_cu);
 
-/* Kernel timing for measurement tools: while enabled, every build records a pair of HIP
- * events on its stream around its quartet kernel (the dominant kernel).  hfk_profile_read
+/* Process-wide override of the quartet-tile shape of hfk_fock and hfk_fock_atoms (and of
+ * the pull-back build of hfk_fock_grad; not of the deterministic strategy), for tuning and
+ * tests:
+ *   tile_items     items of 1024 kets per block of one bra, 1..16 (0: library choice)
+ *   group_bras     bras per group whose blocks are numbered ket-block-major: 256, 512,
+ *                  1024, 2048 or 4096 (0: library choice)
+ *   ket_copies     copies of the ket-side Coulomb vector: 1..1024 shared copies updated
+ *                  with atomics (workgroup w uses copy w mod ket_copies), 0 for one per
+ *                  workgroup with plain updates (fewer, shared, when they exceed the memory
+ *                  budget), or -1 for the library's choice
+ * hfk_set_shape(0, 0, -1) returns to the library's choices.  Errors: HFK_EINVAL for values
+ * outside these sets. */
+hfk_status hfk_set_shape(int32_t tile_items, int32_t group_bras, int32_t ket_copies);
+
+/* Process-wide override of the batched launch, for tuning and tests; 0 keeps the library's
+ * choice:
+ *   groups_per_cu  persistent workgroups per compute unit, 1..4 (capped at what fits)
+ *   block_items    items of 256 kets per fetched block of a shared molecule, 1..1024
+ *   owned_bound    -1: every molecule is split into blocks (shared accumulation);
+ *                  k > 0: molecules with at most k unique quartets before screening run
+ *                  whole in one workgroup and store G and the gradient without atomics
+ *   waves          waves per workgroup, 4 or 8
+ * hfk_set_batched_config(0, 0, 0, 0) returns to the library's choices.  Errors: HFK_EINVAL
+ * for values outside these sets. */
+hfk_status hfk_set_batched_config(int32_t groups_per_cu, int32_t block_items, int64_t owned_bound, int32_t waves);
+
+/* Kernel timing for measurement tools: while enabled, every call records a pair of HIP
+ * events on its stream around each launch of its quartet kernel (the dominant kernel: the
+ * forward, gradient or batched kernel; a gradient call with g_fock records its pull-back
+ * build too).  hfk_profile_read
  * waits for the recorded events, returns the summed duration in milliseconds and the
  * number of launches timed, and clears the record.  Process-wide; not thread-safe against
  * concurrent builds.  Errors: HFK_EINVAL (NULL outputs), HFK_EHIP. */

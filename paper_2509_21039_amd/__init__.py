@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhfk.so")
 
-HFK_OK, HFK_EINVAL, HFK_ENOMEM, HFK_EHIP, HFK_EUNSUPPORTED = 0, 1, 2, 3, 4
+HFK_OK, HFK_EINVAL, HFK_ENOMEM, HFK_EHIP, HFK_EUNSUPPORTED, HFK_ENOTSYM = 0, 1, 2, 3, 4, 5
 FP64, MIXED = 0, 1
 STRATEGY_AUTO, STRATEGY_PRIVATE, STRATEGY_ATOMIC, STRATEGY_DETERMINISTIC = 0, 1, 2, 3
 MAX_NGAUSS = 8
@@ -24,7 +24,7 @@ MAX_NGAUSS = 8
 _PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
 
 _STATUS_NAMES = {HFK_OK: "HFK_OK", HFK_EINVAL: "HFK_EINVAL", HFK_ENOMEM: "HFK_ENOMEM",
-                 HFK_EHIP: "HFK_EHIP", HFK_EUNSUPPORTED: "HFK_EUNSUPPORTED"}
+                 HFK_EHIP: "HFK_EHIP", HFK_EUNSUPPORTED: "HFK_EUNSUPPORTED", HFK_ENOTSYM: "HFK_ENOTSYM"}
 
 
 class HfkError(RuntimeError):
@@ -40,7 +40,9 @@ class HfkStats(ctypes.Structure):
     _fields_ = [("natoms", ctypes.c_int64), ("pairs", ctypes.c_int64), ("sig_pairs", ctypes.c_int64),
                 ("quartets", ctypes.c_int64), ("work_items", ctypes.c_int64),
                 ("strategy", ctypes.c_int32), ("groups", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("tile_items", ctypes.c_int32), ("group_bras", ctypes.c_int32),
+                ("ket_copies", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -69,6 +71,11 @@ _SIGNATURES = {
                          ctypes.POINTER(ctypes.c_int32)],
     "hfk_profile_enable": [ctypes.c_int32],
     "hfk_set_config": [ctypes.c_int32, ctypes.c_int32],
+    "hfk_set_shape": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "hfk_set_batched_config": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32],
+    "hfk_set_debug": [ctypes.c_int32, ctypes.c_double],
+    "hfk_last_stats": [ctypes.POINTER(HfkStats)],
+    "hfk_clear_tuning": [],
     "hfk_profile_read": [ctypes.POINTER(ctypes.c_double), _i64p],
     "hfk_workspace_bytes_atoms": [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.POINTER(_sz)],
@@ -465,3 +472,30 @@ def tune_batched(atom_off, xyz, dens_packed, exps, coefs, tau, precision="mixed"
 
 def load_tuning(cache_path: str):
     _check(lib().hfk_load_tuning(cache_path.encode()))
+
+
+def clear_tuning():
+    """Forget every tuned configuration of the process (hfk_clear_tuning)."""
+    _check(lib().hfk_clear_tuning())
+
+
+def set_shape(tile_items: int = 0, group_bras: int = 0, ket_copies: int = -1):
+    """Override the quartet-tile shape (hfk_set_shape); the defaults restore the library's choice."""
+    _check(lib().hfk_set_shape(int(tile_items), int(group_bras), int(ket_copies)))
+
+
+def set_batched_config(groups_per_cu: int = 0, block_items: int = 0, owned_bound: int = 0, waves: int = 0):
+    """Override the batched launch (hfk_set_batched_config); the defaults restore the library's choice."""
+    _check(lib().hfk_set_batched_config(int(groups_per_cu), int(block_items), int(owned_bound), int(waves)))
+
+
+def set_debug(on: bool = True, sym_tol: float = 0.0):
+    """Debug mode (hfk_set_debug): densities are checked on the device before every build."""
+    _check(lib().hfk_set_debug(1 if on else 0, float(sym_tol)))
+
+
+def last_stats() -> dict:
+    """Counters of this thread's last build call (hfk_last_stats; waits for its stream)."""
+    st = HfkStats()
+    _check(lib().hfk_last_stats(ctypes.byref(st)))
+    return st.as_dict()

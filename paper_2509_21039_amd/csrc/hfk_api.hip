@@ -32,6 +32,13 @@ static hfk_status hip_fail(hipError_t e, const char *where)
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+static double bits_to_double(unsigned long long b)
+{
+    double d;
+    memcpy(&d, &b, sizeof(d));
+    return d;
+}
+
 int device_cu_count()
 {
     int dev = 0;
@@ -54,6 +61,8 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool a
     L.n = n;
     L.atoms = atoms;
     L.tile = prec == HFK_MIXED ? 2 * kTileItems : kTileItems;
+    L.gshift = 10;   // kGroupBras
+    L.kcopies = 0;
     L.private_ok = (double)groups * (double)n * (double)n * 8.0 <= kPrivateBudget;
     L.npair = n * (n + 1) / 2;
     L.pcap = ((L.npair + 63) / 64) * 64 + 64;
@@ -89,8 +98,11 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool a
         if (with_grad) {
             L.pmu = take(sizeof(double) * g2 * PC);
             L.pfa = take(sizeof(double) * g2 * PC);
-            L.bmf = take(sizeof(double) * 2 * g2 * PC);
         }
+    }
+    if (with_grad) {
+        L.bgw = take(sizeof(double) * kGW * g2 * PC);
+        L.bgw_f = take(sizeof(float) * kGW * g2 * PC);
     }
     L.bra = take(sizeof(double) * 8 * g2 * PC);
     L.bra_f = take(sizeof(float) * 8 * g2 * PC);
@@ -100,8 +112,9 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool a
     L.lim = take(sizeof(int) * PC);
     L.item_off = take(sizeof(long long) * (PC + 1));
     L.ngroups = (L.pcap + kGroupBras - 1) / kGroupBras;
-    L.gcnt = take(sizeof(long long) * (size_t)(L.ngroups + 1));
-    L.goff = take(sizeof(long long) * (size_t)(L.ngroups + 1));
+    L.ngroups_cap = (L.pcap + kMinGroupBras - 1) / kMinGroupBras;
+    L.gcnt = take(sizeof(long long) * (size_t)(L.ngroups_cap + 1));
+    L.goff = take(sizeof(long long) * (size_t)(L.ngroups_cap + 1));
     L.scan_tmp = take(sizeof(long long) * (((PC > (size_t)kNumBuckets ? PC : (size_t)kNumBuckets) + 1023) / 1024 + 1));
     const size_t n2 = (size_t)(n * n);
     L.fpriv = take(sizeof(double) * n2 * (size_t)(L.private_ok ? groups : 1));
@@ -117,6 +130,16 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool a
     L.e2tmp = take(sizeof(double));
     L.total = o;
     return L;
+}
+
+void set_shape(Layout &L, int tile, int group_bras, int ket_copies)
+{
+    L.tile = tile;
+    int sh = 0;
+    while ((1 << sh) < group_bras) ++sh;
+    L.gshift = sh;
+    L.ngroups = (L.pcap + (1LL << sh) - 1) >> sh;
+    L.kcopies = ket_copies;
 }
 
 constexpr int kMaxGroupsPerCU = 6;
@@ -182,7 +205,7 @@ static Basis make_basis(int32_t ngauss, const double *exps, const double *coefs)
 constexpr int64_t kMaxAtoms = 6144;
 // n above which the gradient kernel's LDS copy of dE2/dR (n x 3) and its two tables no longer fit
 constexpr int64_t kMaxGradAtoms = 4096;
-constexpr int kGradGroupsPerCU = 2;
+constexpr int kGradGroupsPerCU = 4;
 // Items per block of the gradient kernel: eight (he512 FP64 184 ms against 191 with four;
 // its per-item work is about 2.4 times the forward's, so fewer row flushes matter more
 // than the smaller ket working set).
@@ -200,48 +223,181 @@ static hfk_status det_groups(Layout &L)
 }
 // Largest molecule of a batch (its triangle of F and its gradient stay in LDS).
 constexpr int kMaxBatchAtomsApi = 128;
-static int g_cfg_batch_gpc = 0;
-static int g_tuned_batch_gpc = 0;
+// Pairs of all molecules of a batch: the ket table's buffer resources cover G rows of
+// pcap values (G <= 6 FP64: 48 bytes per pair), which must stay below 2^31 bytes.
+constexpr int64_t kMaxBatchPairs = 40000000;
+constexpr int kMaxBatchGroupsPerCU = 4;
 
-// Tuned strategy per (precision, size class); 0 = not tuned.
-static std::mutex g_tune_mu;
+// ------------------------------------------------------------------ launch configuration
 
-static int size_class(int64_t n) { return n <= 128 ? 0 : n <= 384 ? 1 : n <= 768 ? 2 : 3; }
-
+// One launch configuration of the single-molecule forward build.
 struct TunedConfig {
-    int strategy;      // 0 = not tuned
+    int strategy;      // 0 = not set
     int variant;
-    int gpc;
+    int gpc;           // persistent workgroups per CU
+    int tile;          // items per block
+    int gbras;         // bras per group
+    int kcopies;       // ket-side Coulomb vectors (0: one per workgroup)
 };
-static TunedConfig g_tuned_cfg[2][4];
+
+// One launch configuration of the batched path.
+struct BatchedConfig {
+    int gpc;                // 0 = not set
+    int block_items;        // 0 = automatic
+    long long owned_bound;  // -1 = no owned molecules
+    int waves;              // waves per workgroup: 4 or 8
+};
+
+// Size bucket of the tuning table: ceil(log2 n).
+static int size_bucket(int64_t n)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+// Architecture name of the current device (gcnArchName up to the first ':'), cached per device.
+static std::string device_arch()
+{
+    static std::mutex mu;
+    static std::vector<std::string> names;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)names.size() <= dev) names.resize(dev + 1);
+    if (names[dev].empty()) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+        std::string a(prop.gcnArchName);
+        const size_t c = a.find(':');
+        names[dev] = c == std::string::npos ? a : a.substr(0, c);
+    }
+    return names[dev];
+}
+
+struct TuneEntry {
+    std::string arch;
+    int precision;
+    int bucket;
+    TunedConfig cfg;
+};
+struct BatchedEntry {
+    std::string arch;
+    int precision;
+    BatchedConfig cfg;
+};
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tuned;
+static std::vector<BatchedEntry> g_tuned_b;
+
+// Process-wide overrides (hfk_set_config, hfk_set_shape, hfk_set_batched_config).
+static int g_cfg_tile = 0, g_cfg_gbras = 0, g_cfg_kcopies = -1;
+static BatchedConfig g_cfg_b{0, 0, 0, 0};
+// The candidate being timed by a tuner on this thread (takes precedence over everything).
+static thread_local const TunedConfig *g_force = nullptr;
+static thread_local const BatchedConfig *g_force_b = nullptr;
 
 // The configuration before any tuning.  Timed over whole calls (side kernels included) on
 // MI355X for He 64 to 1024 and H/He 128, FP64 and mixed: ATOMIC was the faster strategy at
 // every size (the per-workgroup copies of F and their summation cost more than the atomics
 // they save), and small systems ran fastest with fewer workgroups per CU (2 at 64 atoms,
-// 4 at 128, the most that fit above).
-static TunedConfig default_config(int64_t n)
+// 4 at 128, the most that fit above).  Blocks of four items of 1024 kets (eight with the
+// FP32 ket table, half the size), groups of 1024 bras, one ket vector per workgroup.
+static TunedConfig default_config(int64_t n, int precision)
 {
-    return TunedConfig{HFK_STRATEGY_ATOMIC, 1, n <= 64 ? 2 : (n <= 128 ? 4 : 6)};
+    return TunedConfig{HFK_STRATEGY_ATOMIC, 1, n <= 64 ? 2 : (n <= 128 ? 4 : 6),
+                       precision == HFK_MIXED ? 2 * kTileItems : kTileItems, kGroupBras, 0};
+}
+
+// Before tuning: eight-wave workgroups, two per CU (the LDS holds two molecules' triangles
+// up to 96 atoms), automatic block size, every molecule in shared blocks.
+static BatchedConfig default_batched_config() { return BatchedConfig{2, 0, -1, 8}; }
+
+static bool lookup_tuned(const std::string &arch, int precision, int bucket, TunedConfig *out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const TuneEntry &e : g_tuned)
+        if (e.arch == arch && e.precision == precision && e.bucket == bucket) {
+            *out = e.cfg;
+            return true;
+        }
+    return false;
 }
 
 static TunedConfig pick_config(int32_t strategy, int32_t precision, int64_t n, int32_t ngauss)
 {
-    TunedConfig c;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        c = g_tuned_cfg[precision][size_class(n)];
+    TunedConfig c = default_config(n, precision);
+    if (g_force) {
+        c = *g_force;
+    } else {
+        TunedConfig t;
+        if (lookup_tuned(device_arch(), precision, size_bucket(n), &t)) c = t;
+        if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_ATOMIC) c.strategy = strategy;
+        if (g_cfg_variant >= 0) c.variant = g_cfg_variant;
+        if (g_cfg_gpc > 0) c.gpc = g_cfg_gpc;
+        if (g_cfg_tile > 0) c.tile = g_cfg_tile;
+        if (g_cfg_gbras > 0) c.gbras = g_cfg_gbras;
+        if (g_cfg_kcopies >= 0) c.kcopies = g_cfg_kcopies;
     }
-    if (c.strategy == 0) c = default_config(n);
-    if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_ATOMIC) c.strategy = strategy;
-    if (g_cfg_variant >= 0) c.variant = g_cfg_variant;
-    if (g_cfg_gpc > 0) c.gpc = g_cfg_gpc;
     if (ngauss > 4) c.variant = 1;   // the direct form is built for g <= 4 only
     if (strategy == HFK_STRATEGY_DETERMINISTIC) {
         // a fixed configuration, independent of tuning and overrides (capped at residency)
-        c = TunedConfig{HFK_STRATEGY_DETERMINISTIC, 1, kMaxGroupsPerCU};
+        c = TunedConfig{HFK_STRATEGY_DETERMINISTIC, 1, kMaxGroupsPerCU,
+                        precision == HFK_MIXED ? 2 * kTileItems : kTileItems, kGroupBras, 0};
     }
     return c;
+}
+
+static BatchedConfig pick_batched_config(int32_t precision)
+{
+    BatchedConfig c = default_batched_config();
+    if (g_force_b) return *g_force_b;
+    {
+        const std::string arch = device_arch();
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const BatchedEntry &e : g_tuned_b)
+            if (e.arch == arch && e.precision == precision) c = e.cfg;
+    }
+    if (g_cfg_b.gpc > 0) c.gpc = g_cfg_b.gpc;
+    if (g_cfg_b.block_items > 0) c.block_items = g_cfg_b.block_items;
+    if (g_cfg_b.owned_bound != 0) c.owned_bound = g_cfg_b.owned_bound;
+    if (g_cfg_b.waves > 0) c.waves = g_cfg_b.waves;
+    return c;
+}
+
+// ------------------------------------------------------------------ debug mode
+
+static bool g_debug = false;
+static double g_debug_tol = 0.0;
+
+// Debug check of one n x n density (hfk_set_debug): waits for the stream.
+static hfk_status debug_check(char *ws_hdr, int64_t n, const double *dens, hipStream_t st, const char *what)
+{
+    if (!g_debug) return HFK_OK;
+    DevHeader *hdr = (DevHeader *)ws_hdr;
+    hipError_t e = launch_dens_check(hdr, n, dens, st);
+    DevHeader h;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "density check");
+    if (h.dchk_bad) return fail(HFK_EINVAL, "%s has %llu non-finite entries", what, (unsigned long long)h.dchk_bad);
+    const double asym = bits_to_double(h.dchk_asym);
+    const double mx = bits_to_double(h.dchk_max);
+    if (asym > g_debug_tol * mx)
+        return fail(HFK_ENOTSYM, "%s is not symmetric: max |D_ij - D_ji| = %.3e, max |D_ij| = %.3e, tolerance %.3e",
+                    what, asym, mx, g_debug_tol);
+    return HFK_OK;
+}
+
+// ------------------------------------------------------------------ last build of this thread
+
+static thread_local const void *g_last_ws = nullptr;
+static thread_local void *g_last_stream = nullptr;
+
+static void note_last(const void *ws, void *stream)
+{
+    g_last_ws = ws;
+    g_last_stream = stream;
 }
 
 // ------------------------------------------------------------------ kernel timing
@@ -341,10 +497,13 @@ hfk_status hfk_workspace_bytes(int64_t natoms, int32_t ngauss, int32_t precision
     return HFK_OK;
 }
 
-hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
-                    const double *coefs_host, const double *dens, double tau, int32_t precision,
-                    int32_t strategy, double *fock, double *e2, void *workspace, size_t workspace_bytes,
-                    void *stream)
+}  // extern "C"
+
+// hfk_fock.
+static hfk_status fock_one_basis(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
+                                 const double *coefs_host, const double *dens, double tau, int32_t precision,
+                                 int32_t strategy, double *fock, double *e2, void *workspace, size_t workspace_bytes,
+                                 void *stream)
 {
     g_err[0] = 0;
     hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision);
@@ -367,6 +526,7 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     const TunedConfig cfg = pick_config(strategy, precision, natoms, ngauss);
     int strat = cfg.strategy;
     if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
+    set_shape(L, cfg.tile, cfg.gbras, cfg.kcopies);
     {
         // no more persistent workgroups than fit on a CU at once
         const bool det = strat == HFK_STRATEGY_DETERMINISTIC;
@@ -380,6 +540,8 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     const Basis b = make_basis(ngauss, exps_host, coefs_host);
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
+    s = debug_check(ws + L.hdr, natoms, dens, st, "dens");
+    if (s != HFK_OK) return s;
     hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys),
                                 (float *)(ws + L.boys_f), (double *)(ws + L.boys_g),
                                 (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz, st);
@@ -391,9 +553,22 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     if (e != hipSuccess) return hip_fail(e, "pair launch");
     e = launch_fock(L, b, ws, dens, tau, precision, strat, cfg.variant, fock, e2, st);
     if (e != hipSuccess) return hip_fail(e, "fock launch");
-    e = launch_header_info(ws + L.hdr, strat, L.groups, precision, cfg.variant, st);
+    e = launch_header_info(ws + L.hdr, strat, L.groups, precision, cfg.variant, st, L.tile, 1 << L.gshift,
+                           effective_copies(L));
     if (e != hipSuccess) return hip_fail(e, "header launch");
+    note_last(workspace, stream);
     return HFK_OK;
+}
+
+extern "C" {
+
+hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
+                    const double *coefs_host, const double *dens, double tau, int32_t precision,
+                    int32_t strategy, double *fock, double *e2, void *workspace, size_t workspace_bytes,
+                    void *stream)
+{
+    return fock_one_basis(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision, strategy, fock, e2,
+                          workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"
@@ -470,6 +645,7 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
     cfg.variant = 1;   // per-atom bases run the hybrid form only
     int strat = cfg.strategy;
     if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
+    set_shape(L, cfg.tile, cfg.gbras, cfg.kcopies);
     {
         const bool det = strat == HFK_STRATEGY_DETERMINISTIC;
         const int fit = fock_resident_groups(ngauss, precision, 1, natoms, true, det);
@@ -481,6 +657,8 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
     }
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
+    s = debug_check(ws + L.hdr, natoms, dens, st, "dens");
+    if (s != HFK_OK) return s;
     Basis b;
     hipError_t e = upload_rows((double *)(ws + L.arow), natoms, ngauss, exps_host, coefs_host, st, &b);
     if (e != hipSuccess) return hip_fail(e, "basis rows copy");
@@ -495,8 +673,10 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
     if (e != hipSuccess) return hip_fail(e, "pair launch");
     e = launch_fock(L, b, ws, dens, tau, precision, strat, 1, fock, e2, st);
     if (e != hipSuccess) return hip_fail(e, "fock launch");
-    e = launch_header_info(ws + L.hdr, strat, L.groups, precision, 1, st);
+    e = launch_header_info(ws + L.hdr, strat, L.groups, precision, 1, st, L.tile, 1 << L.gshift,
+                           effective_copies(L));
     if (e != hipSuccess) return hip_fail(e, "header launch");
+    note_last(workspace, stream);
     return HFK_OK;
 }
 
@@ -555,6 +735,7 @@ hfk_status hfk_scf(int64_t natoms, const double *xyz, const double *charges_host
     cfg.variant = 1;
     int strat = cfg.strategy;
     if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
+    set_shape(L, cfg.tile, cfg.gbras, cfg.kcopies);
     {
         const bool det = strat == HFK_STRATEGY_DETERMINISTIC;
         const int fit = fock_resident_groups(ngauss, precision, 1, natoms, true, det);
@@ -566,6 +747,10 @@ hfk_status hfk_scf(int64_t natoms, const double *xyz, const double *charges_host
     }
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
+    if (use_guess) {
+        s = debug_check(ws + L.hdr, natoms, dens, st, "guess density");
+        if (s != HFK_OK) return s;
+    }
     Basis b;
     hipError_t e = upload_rows((double *)(ws + L.arow), natoms, ngauss, exps_host, coefs_host, st, &b);
     if (e != hipSuccess) return hip_fail(e, "basis rows copy");
@@ -604,6 +789,26 @@ hfk_status hfk_read_stats(const void *workspace, void *stream, hfk_stats *out)
     out->groups = h.groups;
     out->precision = h.precision;
     out->variant = h.variant;
+    out->tile_items = h.tile;
+    out->group_bras = h.group_bras;
+    out->ket_copies = h.ket_copies;
+    return HFK_OK;
+}
+
+hfk_status hfk_last_stats(hfk_stats *out)
+{
+    if (!out) return fail(HFK_EINVAL, "out is NULL");
+    if (!g_last_ws) return fail(HFK_EINVAL, "no build call has been made on this thread");
+    return hfk_read_stats(g_last_ws, g_last_stream, out);
+}
+
+hfk_status hfk_set_debug(int32_t on, double sym_tol)
+{
+    g_err[0] = 0;
+    if (!isfinite(sym_tol) || sym_tol < 0.0)
+        return fail(HFK_EINVAL, "sym_tol must be finite and >= 0 (got %g)", sym_tol);
+    g_debug = on != 0;
+    g_debug_tol = sym_tol;
     return HFK_OK;
 }
 
@@ -634,11 +839,18 @@ static hfk_status fock_grad_impl(bool atoms, int64_t natoms, const double *xyz, 
     Layout L = make_layout(natoms, ngauss, precision, 1, groups_cap(cus), atoms);
     if (workspace_bytes < L.total)
         return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
-    L.groups = cus * kGradGroupsPerCU;
-    const int fwd_tile = L.tile;
-    L.tile = kGradTileItems;   // the gradient kernel's blocks (the pull-back build below uses fwd_tile)
+    {
+        // as many persistent workgroups as fit on a CU, up to kGradGroupsPerCU
+        const int fit = grad_resident_groups(ngauss, precision, natoms, atoms);
+        L.groups = cus * (fit > 0 && fit < kGradGroupsPerCU ? fit : kGradGroupsPerCU);
+    }
+    // the gradient kernel's blocks: eight items, groups of 1024 bras (the pull-back build
+    // below takes the forward's shape)
+    set_shape(L, kGradTileItems, kGroupBras, 0);
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
+    s = debug_check(ws + L.hdr, natoms, dens, st, "dens");
+    if (s != HFK_OK) return s;
     Basis b;
     if (atoms) {
         const hipError_t eu = upload_rows((double *)(ws + L.arow), natoms, ngauss, exps_host, coefs_host, st, &b);
@@ -664,14 +876,14 @@ static hfk_status fock_grad_impl(bool atoms, int64_t natoms, const double *xyz, 
     if (g_fock && d_dens) {
         // d_dens = G(W) + g_e2 G: a Fock build with W as the density (the pair tables are
         // rebuilt around W; the screen depends on the geometry only), then the axpy
-        Layout LW = L;
-        LW.tile = fwd_tile;
-        e = launch_pairs(LW, b, ws, xyz, xw, tau, st);
-        if (e != hipSuccess) return hip_fail(e, "pair launch (W)");
         TunedConfig cfg = pick_config(HFK_STRATEGY_AUTO, precision, natoms, ngauss);
         if (atoms) cfg.variant = 1;   // per-atom bases run the hybrid form only
         int strat = cfg.strategy;
         if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
+        Layout LW = L;
+        set_shape(LW, cfg.tile, cfg.gbras, cfg.kcopies);
+        e = launch_pairs(LW, b, ws, xyz, xw, tau, st);
+        if (e != hipSuccess) return hip_fail(e, "pair launch (W)");
         Layout LF = LW;
         const int fit = fock_resident_groups(ngauss, precision, cfg.variant, natoms, atoms);
         LF.groups = cus * (fit > 0 && cfg.gpc > fit ? fit : cfg.gpc);
@@ -680,8 +892,9 @@ static hfk_status fock_grad_impl(bool atoms, int64_t natoms, const double *xyz, 
         e = launch_axpy_dev(n2, g_e2, fock_in, d_dens, st);
         if (e != hipSuccess) return hip_fail(e, "axpy launch");
     }
-    e = launch_header_info(ws + L.hdr, 0, L.groups, precision, -1, st);
+    e = launch_header_info(ws + L.hdr, 0, L.groups, precision, -1, st, kGradTileItems, kGroupBras, 0);
     if (e != hipSuccess) return hip_fail(e, "header launch");
+    note_last(workspace, stream);
     return HFK_OK;
 }
 
@@ -716,6 +929,14 @@ static hfk_status check_batch(int64_t nmol, const int64_t *atom_off)
             return fail(HFK_EUNSUPPORTED, "molecule %lld has %lld atoms; the batched path holds at most %d",
                         (long long)m, (long long)n, kMaxBatchAtomsApi);
     }
+    int64_t pairs = 0;
+    for (int64_t m = 0; m < nmol; ++m) {
+        const int64_t n = atom_off[m + 1] - atom_off[m];
+        pairs += n * (n + 1) / 2;
+    }
+    if (pairs > kMaxBatchPairs)
+        return fail(HFK_EUNSUPPORTED, "the batch has %lld atom pairs; one call holds at most %lld",
+                    (long long)pairs, (long long)kMaxBatchPairs);
     return HFK_OK;
 }
 
@@ -786,11 +1007,38 @@ static hfk_status fock_batched_impl(bool atoms, int64_t nmol, const int64_t *ato
                                 (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr),
                                 atom_off_host[nmol], xyz, st);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
-    const int gpc = g_cfg_batch_gpc > 0 ? g_cfg_batch_gpc : g_tuned_batch_gpc > 0 ? g_tuned_batch_gpc : 2;
-    e = launch_batched(L, b, ws, atom_off_host, xyz, dens_packed, tau, precision, fock_packed, e2, d_xyz, cus * gpc, st);
+    e = upload_batch_tables(L, ws, atom_off_host, st);
+    if (e != hipSuccess) return hip_fail(e, "batch tables copy");
+    if (g_debug) {
+        DevHeader *hdr = (DevHeader *)(ws + L.hdr);
+        e = launch_dens_check_batched(hdr, nmol, (const long long *)(ws + L.mol_doff), (const int *)(ws + L.mol_n),
+                                      dens_packed, g_debug_tol, st);
+        DevHeader h;
+        if (e == hipSuccess) e = hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "density check");
+        if (h.dchk_bad)
+            return fail(HFK_EINVAL, "dens_packed has %llu non-finite entries (first in molecule %d)",
+                        (unsigned long long)h.dchk_bad, h.dchk_badmol);
+        if (h.dchk_mol != 0x7fffffff)
+            return fail(HFK_ENOTSYM,
+                        "the density of molecule %d is not symmetric (largest max |D_ij - D_ji| / max |D_ij| over "
+                        "the molecules outside the tolerance: %.3e, tolerance %.3e)",
+                        h.dchk_mol, bits_to_double(h.dchk_ratio), g_debug_tol);
+    }
+    const BatchedConfig bc = pick_batched_config(precision);
+    int gpc = bc.gpc;
+    {
+        const int fit = batched_resident_groups(ngauss, precision, d_xyz != nullptr, atoms, L.nmax, bc.waves);
+        if (fit > 0 && gpc > fit) gpc = fit;
+    }
+    const BatchedShape shape{gpc, bc.block_items, bc.owned_bound, bc.waves};
+    e = launch_batched(L, b, ws, atom_off_host, xyz, dens_packed, tau, precision, fock_packed, e2, d_xyz, cus * gpc,
+                       shape, st);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
-    e = launch_header_info(ws + L.hdr, 0, cus * gpc, precision, -1, st);
+    e = launch_header_info(ws + L.hdr, 0, cus * gpc, precision, -1, st, -1, 0, 0);
     if (e != hipSuccess) return hip_fail(e, "header launch");
+    note_last(workspace, stream);
     return HFK_OK;
 }
 
@@ -812,11 +1060,13 @@ hfk_status hfk_fock_batched_atoms(int64_t nmol, const int64_t *atom_off_host, co
                              precision, fock_packed, e2, d_xyz, workspace, workspace_bytes, stream);
 }
 
+}  // extern "C"
+
 // ------------------------------------------------------------------ autotuner
 
-static double time_fock_ms(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps,
-                           const double *coefs, const double *dens, double tau, int32_t precision, int32_t strategy,
-                           double *fock, double *e2, void *ws, size_t wsb, hipStream_t st, int reps, hfk_status *err)
+// Best of `reps` timed calls after one untimed call (HIP events on the stream).
+template <typename Call>
+static double time_call_ms(Call call, hipStream_t st, int reps, hfk_status *err)
 {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -826,7 +1076,7 @@ static double time_fock_ms(int64_t natoms, const double *xyz, int32_t ngauss, co
     double best = 1e300;
     for (int r = 0; r <= reps; ++r) {
         (void)hipEventRecord(e0, st);
-        hfk_status s = hfk_fock(natoms, xyz, ngauss, exps, coefs, dens, tau, precision, strategy, fock, e2, ws, wsb, st);
+        const hfk_status s = call();
         (void)hipEventRecord(e1, st);
         if (s != HFK_OK) {
             *err = s;
@@ -837,31 +1087,68 @@ static double time_fock_ms(int64_t natoms, const double *xyz, int32_t ngauss, co
             *err = fail(HFK_EHIP, "event timing");
             break;
         }
-        if (r > 0 && ms < best) best = ms;     // the first run warms up
+        if (r > 0 && ms < best) best = ms;     // the first call warms up
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return best;
 }
 
+// A candidate replaces the best so far only when it is faster by more than this fraction
+// (back-to-back timings of one configuration agree to about 0.3%).
+constexpr double kTuneMargin = 0.005;
+
 static hfk_status write_tuning(const char *path)
 {
     FILE *f = fopen(path, "w");
     if (!f) return fail(HFK_EINVAL, "cannot write %s", path);
-    fprintf(f, "{\n  \"format\": \"hfk-tuning-1\",\n  \"entries\": [\n");
-    bool first = true;
-    for (int p = 0; p < 2; ++p)
-        for (int c = 0; c < 4; ++c) {
-            const TunedConfig &t = g_tuned_cfg[p][c];
-            if (!t.strategy) continue;
-            fprintf(f, "%s    {\"precision\": %d, \"size_class\": %d, \"strategy\": %d, \"variant\": %d, \"gpc\": %d}",
-                    first ? "" : ",\n", p, c, t.strategy, t.variant, t.gpc);
-            first = false;
-        }
-    fprintf(f, "\n  ],\n  \"batched_gpc\": %d\n}\n", g_tuned_batch_gpc);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    fprintf(f, "{\n  \"format\": \"hfk-tuning-2\",\n  \"entries\": [\n");
+    for (size_t x = 0; x < g_tuned.size(); ++x) {
+        const TuneEntry &t = g_tuned[x];
+        fprintf(f,
+                "    {\"arch\": \"%s\", \"precision\": %d, \"size_bucket\": %d, \"strategy\": %d, \"variant\": %d, "
+                "\"gpc\": %d, \"tile_items\": %d, \"group_bras\": %d, \"ket_copies\": %d}%s\n",
+                t.arch.c_str(), t.precision, t.bucket, t.cfg.strategy, t.cfg.variant, t.cfg.gpc, t.cfg.tile,
+                t.cfg.gbras, t.cfg.kcopies, x + 1 < g_tuned.size() ? "," : "");
+    }
+    fprintf(f, "  ],\n  \"batched\": [\n");
+    for (size_t x = 0; x < g_tuned_b.size(); ++x) {
+        const BatchedEntry &t = g_tuned_b[x];
+        fprintf(f,
+                "    {\"arch\": \"%s\", \"precision\": %d, \"gpc\": %d, \"block_items\": %d, \"owned_bound\": %lld, "
+                "\"waves\": %d}%s\n",
+                t.arch.c_str(), t.precision, t.cfg.gpc, t.cfg.block_items, t.cfg.owned_bound, t.cfg.waves,
+                x + 1 < g_tuned_b.size() ? "," : "");
+    }
+    fprintf(f, "  ]\n}\n");
     fclose(f);
     return HFK_OK;
 }
+
+static void store_tuned(const std::string &arch, int precision, int bucket, const TunedConfig &c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (TuneEntry &e : g_tuned)
+        if (e.arch == arch && e.precision == precision && e.bucket == bucket) {
+            e.cfg = c;
+            return;
+        }
+    g_tuned.push_back(TuneEntry{arch, precision, bucket, c});
+}
+
+static void store_tuned_b(const std::string &arch, int precision, const BatchedConfig &c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (BatchedEntry &e : g_tuned_b)
+        if (e.arch == arch && e.precision == precision) {
+            e.cfg = c;
+            return;
+        }
+    g_tuned_b.push_back(BatchedEntry{arch, precision, c});
+}
+
+extern "C" {
 
 hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
                     const double *coefs_host, const double *dens, double tau, int32_t precision, double *fock,
@@ -871,33 +1158,61 @@ hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss, const dou
     g_err[0] = 0;
     hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision);
     if (s != HFK_OK) return s;
-    const int save_var = g_cfg_variant, save_gpc = g_cfg_gpc;
-    const int strategies[2] = {HFK_STRATEGY_PRIVATE, HFK_STRATEGY_ATOMIC};
-    const int variants[2] = {1, 0};
-    const int gpcs[4] = {3, 4, 5, 6};
-    TunedConfig best{0, 1, 2};
-    double best_ms = 1e300;
+    if (natoms > kMaxAtoms) return fail(HFK_EUNSUPPORTED, "natoms above %lld", (long long)kMaxAtoms);
+    hipStream_t st = (hipStream_t)stream;
+    const int cus = device_cu_count();
+    if (cus <= 0) return fail(HFK_EHIP, "no HIP device");
+    const Layout L0 = make_layout(natoms, ngauss, precision, 0, groups_cap(cus));
     hfk_status err = HFK_OK;
-    for (int si = 0; si < 2 && err == HFK_OK; ++si)
-        for (int vi = 0; vi < (ngauss > 4 ? 1 : 2) && err == HFK_OK; ++vi)
-            for (int gi = 0; gi < 4 && err == HFK_OK; ++gi) {
-                g_cfg_variant = variants[vi];
-                g_cfg_gpc = gpcs[gi];
-                const double ms = time_fock_ms(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision,
-                                               strategies[si], fock, e2, workspace, workspace_bytes,
-                                               (hipStream_t)stream, 2, &err);
-                if (err == HFK_OK && ms < best_ms) {
-                    best_ms = ms;
-                    best = TunedConfig{strategies[si], variants[vi], gpcs[gi]};
-                }
+    TunedConfig best = default_config(natoms, precision);
+    if (ngauss > 4) best.variant = 1;
+    TunedConfig cand;
+    auto run = [&]() {
+        return hfk_fock(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision, HFK_STRATEGY_AUTO, fock,
+                        e2, workspace, workspace_bytes, stream);
+    };
+    auto timed = [&](const TunedConfig &c) {
+        cand = c;
+        g_force = &cand;
+        const double ms = time_call_ms(run, st, 2, &err);
+        g_force = nullptr;
+        return ms;
+    };
+    double best_ms = timed(best);
+    // one dimension at a time, each candidate against the best so far
+    auto try_dim = [&](auto set, const int *vals, int nv) {
+        for (int x = 0; x < nv && err == HFK_OK; ++x) {
+            TunedConfig c = best;
+            set(c, vals[x]);
+            if (memcmp(&c, &best, sizeof(c)) == 0) continue;
+            const double ms = timed(c);
+            if (err == HFK_OK && ms < best_ms * (1.0 - kTuneMargin)) {
+                best_ms = ms;
+                best = c;
             }
-    g_cfg_variant = save_var;
-    g_cfg_gpc = save_gpc;
-    if (err != HFK_OK) return err;
+        }
+    };
+    const int strategies[2] = {HFK_STRATEGY_ATOMIC, HFK_STRATEGY_PRIVATE};
+    const int variants[2] = {1, 0};
+    const int gpcs[6] = {1, 2, 3, 4, 5, 6};
+    const int tiles[5] = {1, 2, 4, 8, 16};
+    const int gbras[5] = {256, 512, 1024, 2048, 4096};
+    const int kcopies[3] = {0, 8, 32};
+    try_dim([](TunedConfig &c, int v) { c.strategy = v; }, strategies, L0.private_ok ? 2 : 1);
+    if (ngauss <= 4) try_dim([](TunedConfig &c, int v) { c.variant = v; }, variants, 2);
     {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned_cfg[precision][size_class(natoms)] = best;
+        // workgroups per CU up to what fits on a CU (more would only queue)
+        const int fit = fock_resident_groups(ngauss, precision, best.variant, natoms, false, false);
+        try_dim([](TunedConfig &c, int v) { c.gpc = v; }, gpcs, fit > 0 && fit < 6 ? fit : 6);
     }
+    try_dim([](TunedConfig &c, int v) { c.tile = v; }, tiles, 5);
+    try_dim([](TunedConfig &c, int v) { c.gbras = v; }, gbras, 5);
+    try_dim([](TunedConfig &c, int v) { c.kcopies = v; }, kcopies, 3);
+    // the first dimensions again, against the final shape
+    try_dim([](TunedConfig &c, int v) { c.gpc = v; }, gpcs, 6);
+    try_dim([](TunedConfig &c, int v) { c.tile = v; }, tiles, 5);
+    if (err != HFK_OK) return err;
+    store_tuned(device_arch(), precision, size_bucket(natoms), best);
     if (best_out) *best_out = best.strategy;
     if (cache_path) return write_tuning(cache_path);
     return HFK_OK;
@@ -909,41 +1224,55 @@ hfk_status hfk_tune_batched(int64_t nmol, const int64_t *atom_off_host, const do
                             size_t workspace_bytes, void *stream, const char *cache_path, int32_t *best_gpc_out)
 {
     g_err[0] = 0;
+    if (precision != HFK_FP64 && precision != HFK_MIXED)
+        return fail(HFK_EINVAL, "precision must be HFK_FP64 or HFK_MIXED (got %d)", (int)precision);
     hipStream_t st = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(HFK_EHIP, "event create");
-    const int save = g_cfg_batch_gpc;
-    int best = 2;
-    double best_ms = 1e300;
     hfk_status err = HFK_OK;
-    for (int gpc = 1; gpc <= 3 && err == HFK_OK; ++gpc) {
-        g_cfg_batch_gpc = gpc;
-        for (int r = 0; r < 3 && err == HFK_OK; ++r) {
-            (void)hipEventRecord(e0, st);
-            err = hfk_fock_batched(nmol, atom_off_host, xyz, ngauss, exps_host, coefs_host, dens_packed, tau,
-                                   precision, fock_packed, e2, d_xyz, workspace, workspace_bytes, stream);
-            (void)hipEventRecord(e1, st);
-            float ms = 0.f;
-            if (err == HFK_OK && (hipEventSynchronize(e1) != hipSuccess ||
-                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-                err = fail(HFK_EHIP, "event timing");
-            if (err == HFK_OK && r > 0 && ms < best_ms) {
+    BatchedConfig best = default_batched_config();
+    BatchedConfig cand;
+    auto run = [&]() {
+        return hfk_fock_batched(nmol, atom_off_host, xyz, ngauss, exps_host, coefs_host, dens_packed, tau, precision,
+                                fock_packed, e2, d_xyz, workspace, workspace_bytes, stream);
+    };
+    auto timed = [&](const BatchedConfig &c) {
+        cand = c;
+        g_force_b = &cand;
+        const double ms = time_call_ms(run, st, 2, &err);
+        g_force_b = nullptr;
+        return ms;
+    };
+    double best_ms = timed(best);
+    auto try_dim = [&](auto set, const long long *vals, int nv) {
+        for (int x = 0; x < nv && err == HFK_OK; ++x) {
+            BatchedConfig c = best;
+            set(c, vals[x]);
+            if (memcmp(&c, &best, sizeof(c)) == 0) continue;
+            const double ms = timed(c);
+            if (err == HFK_OK && ms < best_ms * (1.0 - kTuneMargin)) {
                 best_ms = ms;
-                best = gpc;
+                best = c;
             }
         }
-    }
-    g_cfg_batch_gpc = save;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    };
+    const long long gpcs[4] = {1, 2, 3, 4};
+    const long long items[6] = {0, 8, 16, 32, 64, 128};
+    const long long owned[4] = {-1, 1LL << 14, 1LL << 16, 1LL << 18};
+    const long long waves[2] = {8, 4};
+    try_dim([](BatchedConfig &c, long long v) { c.waves = (int)v; }, waves, 2);
+    try_dim([](BatchedConfig &c, long long v) { c.gpc = (int)v; }, gpcs, 4);
+    try_dim([](BatchedConfig &c, long long v) { c.block_items = (int)v; }, items, 6);
+    try_dim([](BatchedConfig &c, long long v) { c.owned_bound = v; }, owned, 4);
+    try_dim([](BatchedConfig &c, long long v) { c.gpc = (int)v; }, gpcs, 4);
     if (err != HFK_OK) return err;
-    g_tuned_batch_gpc = best;
-    if (best_gpc_out) *best_gpc_out = best;
+    store_tuned_b(device_arch(), precision, best);
+    if (best_gpc_out) *best_gpc_out = best.gpc;
     if (cache_path) return write_tuning(cache_path);
     return HFK_OK;
 }
 
-static bool json_int(const char *obj, const char *key, int *out)
+}  // extern "C"
+
+static bool json_ll(const char *obj, const char *key, long long *out)
 {
     char pat[64];
     snprintf(pat, sizeof(pat), "\"%s\"", key);
@@ -951,8 +1280,31 @@ static bool json_int(const char *obj, const char *key, int *out)
     if (!p) return false;
     p = strchr(p + strlen(pat), ':');
     if (!p) return false;
-    return sscanf(p + 1, " %d", out) == 1;
+    return sscanf(p + 1, " %lld", out) == 1;
 }
+
+static bool json_str(const char *obj, const char *key, std::string *out)
+{
+    char pat[64];
+    snprintf(pat, sizeof(pat), "\"%s\"", key);
+    const char *p = strstr(obj, pat);
+    if (!p) return false;
+    p = strchr(p + strlen(pat), ':');
+    if (!p) return false;
+    p = strchr(p, '"');
+    if (!p) return false;
+    const char *q = strchr(p + 1, '"');
+    if (!q) return false;
+    out->assign(p + 1, q - p - 1);
+    return true;
+}
+
+static bool is_pow2_in(long long v, long long lo, long long hi)
+{
+    return v >= lo && v <= hi && (v & (v - 1)) == 0;
+}
+
+extern "C" {
 
 hfk_status hfk_load_tuning(const char *cache_path)
 {
@@ -967,24 +1319,79 @@ hfk_status hfk_load_tuning(const char *cache_path)
     fclose(f);
     buf.push_back(0);
     const char *txt = buf.data();
-    if (!strstr(txt, "\"hfk-tuning-1\"")) return fail(HFK_EINVAL, "%s is not an hfk tuning table", cache_path);
-    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!strstr(txt, "\"hfk-tuning-2\"")) return fail(HFK_EINVAL, "%s is not an hfk tuning table", cache_path);
+    const char *bat = strstr(txt, "\"batched\"");
+    std::vector<TuneEntry> single;
+    std::vector<BatchedEntry> batched;
     for (const char *p = strchr(txt, '{'); p; p = strchr(p + 1, '{')) {
+        if (p == txt) continue;   // the outer object
         const char *end = strchr(p, '}');
         if (!end) break;
-        std::string obj(p, end - p + 1);
-        int prec, cls, strat, var, gpc;
-        if (json_int(obj.c_str(), "precision", &prec) && json_int(obj.c_str(), "size_class", &cls) &&
-            json_int(obj.c_str(), "strategy", &strat) && json_int(obj.c_str(), "variant", &var) &&
-            json_int(obj.c_str(), "gpc", &gpc)) {
-            if (prec < 0 || prec > 1 || cls < 0 || cls > 3 || strat < 1 || strat > 2 || var < 0 || var > 1 ||
-                gpc < 1 || gpc > kMaxGroupsPerCU)
+        const std::string obj(p, end - p + 1);
+        const char *o = obj.c_str();
+        std::string arch;
+        long long prec, v[6];
+        if (!json_str(o, "arch", &arch) || !json_ll(o, "precision", &prec) || prec < 0 || prec > 1)
+            return fail(HFK_EINVAL, "bad entry in %s", cache_path);
+        if (bat && p > bat) {
+            if (!json_ll(o, "gpc", &v[0]) || !json_ll(o, "block_items", &v[1]) || !json_ll(o, "owned_bound", &v[2]) ||
+                !json_ll(o, "waves", &v[3]) || v[0] < 1 || v[0] > kMaxBatchGroupsPerCU || v[1] < 0 || v[1] > 1024 ||
+                v[2] == 0 || v[2] < -1 || (v[3] != 4 && v[3] != 8))
+                return fail(HFK_EINVAL, "bad batched entry in %s", cache_path);
+            batched.push_back(BatchedEntry{arch, (int)prec, BatchedConfig{(int)v[0], (int)v[1], v[2], (int)v[3]}});
+        } else {
+            long long bucket;
+            if (!json_ll(o, "size_bucket", &bucket) || !json_ll(o, "strategy", &v[0]) || !json_ll(o, "variant", &v[1]) ||
+                !json_ll(o, "gpc", &v[2]) || !json_ll(o, "tile_items", &v[3]) || !json_ll(o, "group_bras", &v[4]) ||
+                !json_ll(o, "ket_copies", &v[5]) || bucket < 0 || bucket > 62 || v[0] < 1 || v[0] > 2 || v[1] < 0 ||
+                v[1] > 1 || v[2] < 1 || v[2] > kMaxGroupsPerCU || v[3] < 1 || v[3] > kMaxTileItems ||
+                !is_pow2_in(v[4], kMinGroupBras, kMaxGroupBras) || v[5] < 0 || v[5] > 1024)
                 return fail(HFK_EINVAL, "bad entry in %s", cache_path);
-            g_tuned_cfg[prec][cls] = TunedConfig{strat, var, gpc};
+            single.push_back(TuneEntry{arch, (int)prec, (int)bucket,
+                                       TunedConfig{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5]}});
         }
     }
-    int bg = 0;
-    if (json_int(txt, "batched_gpc", &bg) && bg >= 1 && bg <= 3) g_tuned_batch_gpc = bg;
+    for (const TuneEntry &e : single) store_tuned(e.arch, e.precision, e.bucket, e.cfg);
+    for (const BatchedEntry &e : batched) store_tuned_b(e.arch, e.precision, e.cfg);
+    return HFK_OK;
+}
+
+hfk_status hfk_clear_tuning(void)
+{
+    g_err[0] = 0;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+    g_tuned_b.clear();
+    return HFK_OK;
+}
+
+hfk_status hfk_set_shape(int32_t tile_items, int32_t group_bras, int32_t ket_copies)
+{
+    g_err[0] = 0;
+    if (tile_items < 0 || tile_items > kMaxTileItems)
+        return fail(HFK_EINVAL, "tile_items must be in [0, %d] (got %d)", kMaxTileItems, (int)tile_items);
+    if (group_bras != 0 && !is_pow2_in(group_bras, kMinGroupBras, kMaxGroupBras))
+        return fail(HFK_EINVAL, "group_bras must be 0 or a power of two in [%d, %d] (got %d)", kMinGroupBras,
+                    kMaxGroupBras, (int)group_bras);
+    if (ket_copies < -1 || ket_copies > 1024)
+        return fail(HFK_EINVAL, "ket_copies must be in [-1, 1024] (got %d)", (int)ket_copies);
+    g_cfg_tile = tile_items;
+    g_cfg_gbras = group_bras;
+    g_cfg_kcopies = ket_copies;
+    return HFK_OK;
+}
+
+hfk_status hfk_set_batched_config(int32_t groups_per_cu, int32_t block_items, int64_t owned_bound, int32_t waves)
+{
+    g_err[0] = 0;
+    if (waves != 0 && waves != 4 && waves != 8)
+        return fail(HFK_EINVAL, "waves must be 0, 4 or 8 (got %d)", (int)waves);
+    if (groups_per_cu < 0 || groups_per_cu > kMaxBatchGroupsPerCU)
+        return fail(HFK_EINVAL, "groups_per_cu must be in [0, %d] (got %d)", kMaxBatchGroupsPerCU, (int)groups_per_cu);
+    if (block_items < 0 || block_items > 1024)
+        return fail(HFK_EINVAL, "block_items must be in [0, 1024] (got %d)", (int)block_items);
+    if (owned_bound < -1) return fail(HFK_EINVAL, "owned_bound must be -1, 0 or > 0 (got %lld)", (long long)owned_bound);
+    g_cfg_b = BatchedConfig{groups_per_cu, block_items, (long long)owned_bound, waves};
     return HFK_OK;
 }
 

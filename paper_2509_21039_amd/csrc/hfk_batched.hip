@@ -3,11 +3,15 @@
 //
 // Pairs of every molecule are prepared in one pass and stored in (molecule, Q band) order;
 // a bra's kets are the molecule's pairs up to its screen limit (t <= s keeps each quartet
-// once).  Items of 256 kets are numbered molecule by molecule; workgroups fetch blocks of
-// consecutive items from a global counter.  A workgroup keeps the current molecule's whole
-// two-electron matrix in LDS (lower triangle, the symmetrisation G = (F + F^T)/2 folded in:
-// F_xy and F_yx land in the same slot) and its n x 3 gradient, and flushes both with
-// global atomics when the molecule or the block changes.  Per primitive quartet the loop forms E(r) (the integral) and
+// once).  Items of 256 kets are numbered molecule by molecule.  Workgroups fetch blocks from
+// a global counter through a block table with two kinds of blocks:
+//   owned:  all items of one molecule (molecules up to a tuned work bound), fetched first;
+//   shared: up to bsz consecutive items of one molecule.
+// A workgroup keeps the current molecule's whole two-electron matrix in LDS (lower
+// triangle, the symmetrisation G = (F + F^T)/2 folded in: F_xy and F_yx land in the same
+// slot) and its n x 3 gradient.  At the end of an owned block they are stored as they are
+// (no other workgroup touches that molecule); at the end of a shared block they are added
+// to the global accumulators with atomics.  Per primitive quartet the loop forms E(r) (the integral) and
 // W(r) = E'(r)/r (its radial derivative) from the same r^2, so the forward result and the
 // gradient come out of one pass over the quartets.
 //
@@ -40,9 +44,8 @@ struct BArgs {
     const float *bra_f;
     const double *bip;      // per-atom bases: [pcap][g2] kTswitch / p of the bra pairs (and FP32)
     const float *bip_f;
-    const double *kmu;      // per-atom gradient: [g2][pcap] ket mu and a/p, [pcap][g2][2] bra
+    const double *kmu;      // per-atom gradient: [g2][pcap] ket mu and a/p
     const double *kfa;
-    const double *bmf;
     const long long *item_off;
     const int *lim;
     const int *klo;
@@ -54,6 +57,11 @@ struct BArgs {
     const double *dens;
     double *facc;        // packed lower triangles, molecule m at mol_toff[m]
     double *gacc;        // [sum n][3]
+    const long long *off_own;   // [nmol + 1] exclusive prefix of owned blocks per molecule
+    const long long *off_sh;    // [nmol + 1] exclusive prefix of shared blocks per molecule
+    const long long *mol_i0;    // [nmol] first item of each molecule
+    const long long *mol_i1;    // [nmol] end of its items
+    int nmol;
     unsigned long long *quartets;
     unsigned long long *next_block;
     int64_t pcap;
@@ -81,6 +89,8 @@ template <> struct BPrec<float> {
 
 __device__ inline int tri(int a, int b) { return a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a; }
 
+// Last m in [0, nmol) with off[m] <= p: the molecule whose range of a prefix sum holds p
+// (molecules with an empty range share their offset with the next one and are skipped).
 __device__ inline int mol_of(const long long *__restrict__ off, int nmol, long long p)
 {
     int lo = 0, hi = nmol - 1;
@@ -181,8 +191,7 @@ __global__ __launch_bounds__(256) void k_b_pair_scatter(
     int64_t pcap, const double *__restrict__ q, const int *__restrict__ bucket_of, int *__restrict__ cur,
     int *__restrict__ pk, int *__restrict__ pl, int *__restrict__ pm, double *__restrict__ pq, double *__restrict__ pd,
     double *__restrict__ prim, float *__restrict__ prim_f, double *__restrict__ bra, float *__restrict__ bra_f,
-    double *__restrict__ bip, float *__restrict__ bip_f, double *__restrict__ kmu, double *__restrict__ kfa,
-    double *__restrict__ bmf)
+    double *__restrict__ bip, float *__restrict__ bip_f, double *__restrict__ kmu, double *__restrict__ kfa)
 {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ptot) return;
@@ -216,13 +225,19 @@ __global__ __launch_bounds__(256) void k_b_pair_scatter(
         prim_f[(1 * g2 + ab) * pcap + pos] = (float)py[ab];
         prim_f[(2 * g2 + ab) * pcap + pos] = (float)pz[ab];
         prim_f[(3 * g2 + ab) * pcap + pos] = (float)ps[ab];
-        double *ba = bra + ((int64_t)pos * g2 + ab) * 8;
-        float *bf = bra_f + ((int64_t)pos * g2 + ab) * 8;
-        const double p2 = px[ab] * px[ab] + py[ab] * py[ab] + pz[ab] * pz[ab];
-        ba[0] = px[ab]; ba[1] = py[ab]; ba[2] = pz[ab]; ba[3] = ps[ab];
-        ba[4] = -2.0 * px[ab]; ba[5] = -2.0 * py[ab]; ba[6] = -2.0 * pz[ab]; ba[7] = p2;
-        bf[0] = (float)px[ab]; bf[1] = (float)py[ab]; bf[2] = (float)pz[ab]; bf[3] = (float)ps[ab];
-        bf[4] = (float)ba[4]; bf[5] = (float)ba[5]; bf[6] = (float)ba[6]; bf[7] = (float)p2;
+        // bra row: centre, charge and the charge weighted by mu and by the fractions
+        // fa = a/p, fb = b/p of the primitive pair (the gradient's bra weights)
+        double *ba = bra + ((int64_t)pos * g2 + ab) * kBBra;
+        float *bf = bra_f + ((int64_t)pos * g2 + ab) * kBBra;
+        const double m_ab = b.aexp ? mu[ab] : bd->mu[ab];
+        const double fa_ab = b.aexp ? fa[ab] : bd->fa[ab];
+        const double fb_ab = b.aexp ? 1.0 - fa[ab] : bd->fb[ab];
+        const double row[kBBra] = {px[ab], py[ab], pz[ab], ps[ab], m_ab * ps[ab], fa_ab * ps[ab], fb_ab * ps[ab],
+                                   fa_ab * fb_ab * ps[ab], fb_ab * fb_ab * ps[ab], 0.0, 0.0, 0.0};
+        for (int c = 0; c < kBBra; ++c) {
+            ba[c] = row[c];
+            bf[c] = (float)row[c];
+        }
     }
     if (bip) {
         for (int ab = 0; ab < g2; ++ab) {
@@ -237,8 +252,6 @@ __global__ __launch_bounds__(256) void k_b_pair_scatter(
         for (int ab = 0; ab < g2; ++ab) {
             kmu[(int64_t)ab * pcap + pos] = mu[ab];
             kfa[(int64_t)ab * pcap + pos] = fa[ab];
-            bmf[((int64_t)pos * g2 + ab) * 2] = mu[ab];
-            bmf[((int64_t)pos * g2 + ab) * 2 + 1] = fa[ab];
         }
     }
 }
@@ -283,10 +296,63 @@ __global__ __launch_bounds__(256) void k_b_limits(const DevHeader *__restrict__ 
     nitems[s] = ni;
 }
 
+// Block table of the quartet kernel.  Per molecule: its item range, and either one owned
+// block (all its items; molecules with at most owned_bound unique quartets before the
+// screen, P (P + 1) / 2 with P = n (n + 1) / 2) or ceil(items / bsz) shared blocks.
+// bsz = block_items, or (0: automatic) total items / (8 x workgroups) clamped to
+// [kBlockItems, 4 kBlockItems]: big batches get fewer fetches and molecule switches, small
+// ones keep enough blocks to spread.
+__global__ __launch_bounds__(256) void k_b_blocks(DevHeader *__restrict__ hdr, int64_t nmol,
+                                                  const int *__restrict__ nm, const long long *__restrict__ boff,
+                                                  const long long *__restrict__ item_off, int block_items,
+                                                  long long owned_bound, int groups, long long *__restrict__ mi0,
+                                                  long long *__restrict__ mi1, long long *__restrict__ cnt_own,
+                                                  long long *__restrict__ cnt_sh)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    long long bsz = block_items;
+    if (bsz <= 0) {
+        bsz = hdr->items / (8LL * (long long)groups);
+        bsz = bsz < kBlockItems ? kBlockItems : (bsz > 4 * kBlockItems ? 4 * kBlockItems : bsz);
+    }
+    if (m == 0) hdr->bsz = bsz;
+    if (m >= nmol) return;
+    const long long i0 = item_off[boff[m * kNumBands]], i1 = item_off[boff[(m + 1) * kNumBands]];
+    mi0[m] = i0;
+    mi1[m] = i1;
+    const long long n = nm[m], P = n * (n + 1) / 2;
+    const bool own = owned_bound > 0 && P * (P + 1) / 2 <= owned_bound;
+    cnt_own[m] = own && i1 > i0 ? 1 : 0;
+    cnt_sh[m] = own ? 0 : (i1 - i0 + bsz - 1) / bsz;
+}
+
 // ------------------------------------------------------------------ fused quartet kernel
 
+// Work within a block.  A block is a range of items of one molecule (all of them for an
+// owned block).  Each item (bra s, 256 kets) is cut into four units of 64 kets, and the
+// waves of the workgroup take the block's units round-robin, each on its own: a wave walks
+// its units in item order, keeps its bra's data while the bra stays the same, and folds its
+// bra-side sums into LDS when the bra changes.  The waves meet only at the start and the
+// end of a block (LDS cleared, then the molecule's accumulators written out), so a bra with
+// few kets occupies one wave, not the workgroup.  The wave count per workgroup is set at
+// launch (blockDim.x / 64): with a large molecule's triangle in LDS few workgroups fit on a
+// CU, and wider ones keep the SIMDs supplied.
+//
+// Gradient contraction.  With P_ab = A + fb (B - A) and Q_cd = C + fd (D - C) (fa = a/p,
+// fb = b/p, fc = c/q, fd = d/q), the separation splits into atom vectors,
+//     P - Q = R_AC + fb R_BA - fd R_DC,   R_AC = A - C, R_BA = B - A, R_DC = D - C,
+// so the W terms of the derivatives need only scalar sums of w = S_ab S_cd W(r) weighted by
+// the fractions: per primitive quartet the lane adds S_cd E, mu_cd S_cd E, S_cd W, fd S_cd W,
+// fc S_cd W and fc fd S_cd W (one FMA each), and once per bra primitive pair these are
+// folded with the bra's weights (S, mu S, fa S, fb S, fa fb S, fb^2 S from the bra table).
+// Every weighted sum is accumulated directly (no difference of two sums), so FP32 partial
+// sums keep their relative accuracy.  Per kept quartet, with Gamma the density factor:
+//   dA = Gamma [ -2 AB sum mu S S E + R_AC sum fa w + R_BA sum fa fb w - R_DC sum fa fd w ]
+//   dB = Gamma [ +2 AB sum mu S S E + R_AC sum fb w + R_BA sum fb^2 w - R_DC sum fb fd w ]
+//   dC = Gamma [ -2 CD sum mu_cd S S E - R_AC sum fc w - R_BA sum fc fb w + R_DC sum fc fd w ]
+//   dD = -(dA + dB + dC)
 template <int G, typename R, bool kGrad, bool kAtoms = false>
-__global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
+__global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
 {
     constexpr int G2 = G * G;
     extern __shared__ double smem[];
@@ -295,13 +361,16 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
     double *lg = Lt + nmax * (nmax + 1) / 2;                   // [3 nmax]
     R *tH = (R *)(lg + 3 * nmax);
     R *tG = tH + kBoysGrid * kBoysStride;
-    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    const long long M = a.hdr->items;
+    const int nthr = (int)blockDim.x, tid = threadIdx.x, lane = tid % kWave;
+    // the wave index through readfirstlane, so that everything derived from it (the unit
+    // loop, the bra walk) is known to be wave-uniform and stays in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int nwaves = nthr / kWave;
     const int S = a.hdr->sig_pairs;
     const BasisDev *bd = a.bd;
     // grid-scaled rows (argument T' = T / h): coefficient m of H times h^m sqrt(h), of g times
     // h^m h^(3/2), built from the FP64 rows
-    for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) {
+    for (int x = tid; x < kBoysGrid * kBoysStride; x += nthr) {
         const int m = x % kBoysStride;
         double sc = sqrt(kBoysH);
         for (int e = 0; e < m; ++e) sc *= kBoysH;
@@ -310,90 +379,70 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
     }
     unsigned long long kept = 0;
     __shared__ long long blk_at;
-    // blocks of bsz consecutive items, fetched from a global counter until exhausted: at least
-    // kBlockItems, and up to four times that while every workgroup still gets eight blocks
-    // or more (fewer fetches and molecule switches; 2000 clusters: 751 ms against 766 ms
-    // with blocks of 16)
-    long long bsz = M / (8LL * (long long)gridDim.x);
-    bsz = bsz < kBlockItems ? kBlockItems : (bsz > 4 * kBlockItems ? 4 * kBlockItems : bsz);
-    for (;;) {
-    __syncthreads();
-    if (tid == 0) blk_at = (long long)atomicAdd(a.next_block, 1ULL);
-    __syncthreads();
-    const long long m0 = blk_at * bsz;
-    if (m0 >= M) break;
-    const long long m1 = m0 + bsz < M ? m0 + bsz : M;
-    int s;
-    {
-        int lo = 0, hi = S - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.item_off[mid] <= m0) lo = mid; else hi = mid - 1;
-        }
-        s = lo;
-    }
+    __shared__ int s_first;
+    // blocks from a global counter through the block table: owned blocks first (whole
+    // molecules), then shared blocks of bsz items, until both kinds are exhausted
+    const long long bt_own = a.hdr->bt_own, bt_all = bt_own + a.hdr->bt_sh, bsz = a.hdr->bsz;
     const R *prim = BPrec<R>::prim(a);
     const cptr<R> rsg = (cptr<R>)BPrec<R>::rsg(bd);
     const cptr<double> cmu = (cptr<double>)bd->mu;
     const cptr<double> cfa = (cptr<double>)bd->fa;
     const cptr<double> cfb = (cptr<double>)bd->fb;
-    int curmol = -1, curbra = -1;
-    int nm = 0;
-    long long aoff = 0, doff = 0, toff = 0;
+    for (;;) {
+    __syncthreads();
+    if (tid == 0) blk_at = (long long)atomicAdd(a.next_block, 1ULL);
+    __syncthreads();
+    const long long blk = blk_at;
+    if (blk >= bt_all) break;
+    const bool owned = blk < bt_own;
+    const int mol = owned ? mol_of(a.off_own, a.nmol, blk) : mol_of(a.off_sh, a.nmol, blk - bt_own);
+    long long m0 = a.mol_i0[mol];
+    if (!owned) m0 += (blk - bt_own - a.off_sh[mol]) * bsz;
+    const long long m1 = owned || m0 + bsz > a.mol_i1[mol] ? a.mol_i1[mol] : m0 + bsz;
+    const int nm = a.mol_n[mol];
+    const long long aoff = a.mol_aoff[mol], doff = a.mol_doff[mol], toff = a.mol_toff[mol];
+    const int ntri = nm * (nm + 1) / 2;
+    for (int x = tid; x < ntri; x += nthr) Lt[x] = 0.0;
+    if (kGrad)
+        for (int x = tid; x < 3 * nm; x += nthr) lg[x] = 0.0;
+    if (tid == 0) {
+        // the bra of item m0: the last s with item_off[s] <= m0
+        int lo = 0, hi = S - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.item_off[mid] <= m0) lo = mid; else hi = mid - 1;
+        }
+        s_first = lo;
+    }
+    __syncthreads();
+    {
+    int s = s_first, curbra = -1;
     int bi = 0, bj = 0, lim = 0, klo = 0;
-    double qs = 0.0, ds = 0.0, ABx = 0.0, ABy = 0.0, ABz = 0.0;
+    double qs = 0.0, ds = 0.0, Ax = 0.0, Ay = 0.0, Az = 0.0, Bx = 0.0, By = 0.0, Bz = 0.0;
     double jb = 0.0, gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
-
-    for (long long m = m0; m <= m1; ++m) {
-        if (m < m1) {
-            while (a.item_off[s + 1] <= m) ++s;
-        }
-        const int mol = m < m1 ? a.pm[s] : -1;
-        const bool newbra = (m == m1) || (s != curbra);
-        if (newbra && curbra >= 0) {
-            const double w = wave_sum(jb);
-            if (lane == 0 && w != 0.0) atomicAdd(&Lt[tri(bi, bj)], 4.0 * w);
-            jb = 0.0;
-            if (kGrad) {
+    // folds this wave's bra-side sums into the LDS accumulators
+    auto flush_bra = [&]() {
+        const double w = wave_sum(jb);
+        if (lane == 0 && w != 0.0) atomicAdd(&Lt[tri(bi, bj)], 4.0 * w);
+        jb = 0.0;
+        if (kGrad) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double wa = wave_sum(gA[c]), wb = wave_sum(gB[c]);
-                    if (lane == 0) {
-                        atomicAdd(&lg[3 * bi + c], wa);
-                        atomicAdd(&lg[3 * bj + c], wb);
-                    }
-                    gA[c] = gB[c] = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double wa = wave_sum(gA[c]), wb = wave_sum(gB[c]);
+                if (lane == 0) {
+                    atomicAdd(&lg[3 * bi + c], wa);
+                    atomicAdd(&lg[3 * bj + c], wb);
                 }
+                gA[c] = gB[c] = 0.0;
             }
-            curbra = -1;
         }
-        if (m == m1 || mol != curmol) {
-            __syncthreads();
-            if (curmol >= 0) {
-                const int nt = nm * (nm + 1) / 2;
-                for (int x = tid; x < nt; x += kGroupThreads) {
-                    const double v = Lt[x];
-                    if (v != 0.0) atomicAdd(&a.facc[toff + x], v);
-                }
-                if (kGrad) {
-                    for (int x = tid; x < 3 * nm; x += kGroupThreads) {
-                        const double v = lg[x];
-                        if (v != 0.0) atomicAdd(&a.gacc[3 * aoff + x], v);
-                    }
-                }
-            }
-            __syncthreads();
-            if (m == m1) break;
-            curmol = mol;
-            nm = a.mol_n[mol];
-            aoff = a.mol_aoff[mol];
-            doff = a.mol_doff[mol];
-            toff = a.mol_toff[mol];
-            for (int x = tid; x < nm * (nm + 1) / 2; x += kGroupThreads) Lt[x] = 0.0;
-            for (int x = tid; x < 3 * nm; x += kGroupThreads) lg[x] = 0.0;
-            __syncthreads();
-        }
-        if (curbra != s) {
+    };
+    const long long nunits = (m1 - m0) * kUnitsPerItem;
+    for (long long u = wave; u < nunits; u += nwaves) {
+        const long long m = m0 + u / kUnitsPerItem;
+        while (a.item_off[s + 1] <= m) ++s;
+        if (s != curbra) {
+            if (curbra >= 0) flush_bra();
             curbra = s;
             bi = a.pk[s];
             bj = a.pl[s];
@@ -401,70 +450,71 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
             ds = a.pd[s];
             lim = a.lim[s];
             klo = a.klo[s];
-            ABx = a.xyz[3 * (aoff + bi)] - a.xyz[3 * (aoff + bj)];
-            ABy = a.xyz[3 * (aoff + bi) + 1] - a.xyz[3 * (aoff + bj) + 1];
-            ABz = a.xyz[3 * (aoff + bi) + 2] - a.xyz[3 * (aoff + bj) + 2];
+            const double *xa = a.xyz + 3 * (aoff + bi), *xb = a.xyz + 3 * (aoff + bj);
+            Ax = xa[0]; Ay = xa[1]; Az = xa[2];
+            Bx = xb[0]; By = xb[1]; Bz = xb[2];
         }
-        const long long t0 = klo + (m - a.item_off[s]) * kKetsPerItem + (long long)wave * kWave;
+        const long long t0 = klo + (m - a.item_off[s]) * kKetsPerItem + (u % kUnitsPerItem) * kWave;
         if (t0 >= lim) continue;
         const long long tk = t0 + lane;
         const bool valid = (tk < lim) && (qs * a.pq[tk] >= a.tau);
         const long long t = valid ? tk : S;   // lanes without a kept quartet read the first pad entry
-        const cptr<R> bra = (cptr<R>)(BPrec<R>::bra(a) + (int64_t)s * 8 * G2);
+        const cptr<R> bra = (cptr<R>)(BPrec<R>::bra(a) + (int64_t)s * kBBra * G2);
         const cptr<R> bipp = kAtoms ? (cptr<R>)(BPrec<R>::bip(a) + (int64_t)s * G2) : nullptr;
-        const cptr<double> bmfp = (kAtoms && kGrad) ? (cptr<double>)(a.bmf + (int64_t)s * 2 * G2) : nullptr;
         const int k = a.pk[t], l = a.pl[t];
 
-        R sX = R(0), eri = R(0);
-        R sYa[3] = {R(0), R(0), R(0)}, sYb[3] = {R(0), R(0), R(0)};
-        double kC[3] = {0.0, 0.0, 0.0};
-        double CD[3] = {0.0, 0.0, 0.0};
-        if (kGrad) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) CD[c] = a.xyz[3 * (aoff + k) + c] - a.xyz[3 * (aoff + l) + c];
-        }
+        // forward: eri; gradient: sX = sum mu_ab S S E, sZ = sum mu_cd S S E and the
+        // fraction-weighted sums of w (names: weights of bra, then ket)
+        R eri = R(0), sX = R(0), sZ = R(0);
+        R wA = R(0), wAB = R(0), wB = R(0), wBB = R(0), wAD = R(0), wBD = R(0), wC = R(0), wCB = R(0), wCD = R(0);
 #pragma unroll 1
         for (int cb = 0; cb < G; ++cb) {
             R kx[G], ky[G], kz[G], ks[G], kp[G];
-            R Uc[G], Vc[G][3];
-            // buffer loads of the ket table: component base, primitive pair as a scalar
-            // offset, ket as a 32-bit lane offset
+            R kms[G], kds[G], kcs[G], kcds[G];   // S_cd times mu_cd, fd, fc, fc fd
+            // buffer loads of the ket table: component and this cb's rows in the resource,
+            // the row as a scalar offset, the ket as a 32-bit lane offset
             const unsigned tb = (unsigned)t * (unsigned)sizeof(R);
-            auto ld = [&](int c, int cd) {
-                const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
-                    (void *)(prim + (int64_t)c * G2 * a.pcap), (short)0, (int)(G2 * a.pcap * (int64_t)sizeof(R)),
-                    0x00020000);
-                const int so = (int)((int64_t)cd * a.pcap * (int64_t)sizeof(R));
-                if constexpr (sizeof(R) == 8)
-                    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rc, (int)tb, so, 0));
-                else
-                    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)tb, so, 0));
+            auto ld = [&](int c, int d) {
+                return ket_load<R>(ket_rows(prim, (int64_t)c * G2 + cb * G, a.pcap, G), tb,
+                                  (int)((int64_t)d * a.pcap * (int64_t)sizeof(R)));
             };
 #pragma unroll
             for (int d = 0; d < G; ++d) {
-                const int cd = cb * G + d;
-                kx[d] = ld(0, cd);
-                ky[d] = ld(1, cd);
-                kz[d] = ld(2, cd);
-                ks[d] = ld(3, cd);
-                kp[d] = kAtoms ? ld(4, cd) : R(0);
-                Uc[d] = R(0);
-                Vc[d][0] = Vc[d][1] = Vc[d][2] = R(0);
+                kx[d] = ld(0, d);
+                ky[d] = ld(1, d);
+                kz[d] = ld(2, d);
+                ks[d] = ld(3, d);
+                kp[d] = kAtoms ? ld(4, d) : R(0);
+            }
+            if (kGrad) {
+#pragma unroll
+                for (int d = 0; d < G; ++d) {
+                    const int cd = cb * G + d;
+                    double mu, fc;
+                    if constexpr (kAtoms) {
+                        mu = a.kmu[(int64_t)cd * a.pcap + t];
+                        fc = a.kfa[(int64_t)cd * a.pcap + t];
+                    } else {
+                        mu = cmu[cd];
+                        fc = cfa[cd];
+                    }
+                    const double fd = kAtoms ? 1.0 - fc : cfb[cd];
+                    kms[d] = (R)mu * ks[d];
+                    kcs[d] = (R)fc * ks[d];
+                    kds[d] = (R)fd * ks[d];
+                    kcds[d] = (R)(fc * fd) * ks[d];
+                }
             }
 #pragma unroll 1
             for (int ab = 0; ab < G2; ++ab) {
-                // every scalar of this bra primitive in one batch of scalar loads
-                const cptr<R> bp = bra + 8 * ab;
-                R b[4], u[4 * G], bsw = R(0);
-                double bmu = 0.0, bfa = 0.0;
+                // every scalar of this bra primitive in one batch of scalar loads:
+                // Px Py Pz S mu*S fa*S fb*S fa*fb*S fb^2*S, and the switch data
+                const cptr<R> bp = bra + kBBra * ab;
+                R b[kGrad ? 9 : 4], u[4 * G], bsw = R(0);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) b[c] = bp[c];
+                for (int c = 0; c < (kGrad ? 9 : 4); ++c) b[c] = bp[c];
                 if constexpr (kAtoms) {
                     bsw = bipp[ab];
-                    if constexpr (kGrad) {
-                        bmu = bmfp[2 * ab];
-                        bfa = bmfp[2 * ab + 1];
-                    }
                     asm volatile("" ::"s"(bsw));
                 } else {
                     const cptr<R> up = rsg + 4 * (ab * G2 + cb * G);
@@ -473,8 +523,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
 #pragma unroll
                     for (int c = 0; c < 4 * G; ++c) asm volatile("" ::"s"(u[c]));
                 }
-                const R px = b[0], py = b[1], pz = b[2], sab = b[3];
-                R U = R(0), V0 = R(0), V1 = R(0), V2 = R(0);
+                const R px = b[0], py = b[1], pz = b[2];
+                R U = R(0), Y = R(0), X0 = R(0), X1 = R(0), Xc = R(0), Xcd = R(0);
 #pragma unroll
                 for (int d = 0; d < G; ++d) {
                     const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
@@ -520,52 +570,28 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
                         E = y;
                         if (kGrad) W = -(y * y * y);
                     }
-                    U += ks[d] * E;
+                    U = fma(ks[d], E, U);
                     if (kGrad) {
-                        const R wk = ks[d] * W, wb = sab * W;
-                        V0 += wk * dx;
-                        V1 += wk * dy;
-                        V2 += wk * dz;
-                        Uc[d] += sab * E;
-                        Vc[d][0] += wb * dx;
-                        Vc[d][1] += wb * dy;
-                        Vc[d][2] += wb * dz;
+                        Y = fma(kms[d], E, Y);
+                        X0 = fma(ks[d], W, X0);
+                        X1 = fma(kds[d], W, X1);
+                        Xc = fma(kcs[d], W, Xc);
+                        Xcd = fma(kcds[d], W, Xcd);
                     }
                 }
-                const R su = sab * U;
-                eri += su;
+                eri = fma(b[3], U, eri);
                 if (kGrad) {
-                    R fa, fb;
-                    if constexpr (kAtoms) {
-                        sX += (R)bmu * su;
-                        fa = (R)bfa * sab;
-                        fb = sab - fa;
-                    } else {
-                        sX += (R)cmu[ab] * su;
-                        fa = (R)cfa[ab] * sab;
-                        fb = (R)cfb[ab] * sab;
-                    }
-                    sYa[0] += fa * V0; sYa[1] += fa * V1; sYa[2] += fa * V2;
-                    sYb[0] += fb * V0; sYb[1] += fb * V1; sYb[2] += fb * V2;
-                }
-            }
-            if (kGrad) {
-#pragma unroll
-                for (int d = 0; d < G; ++d) {
-                    const int cd = cb * G + d;
-                    const double sc = (double)ks[d];
-                    double kmu, kfa;
-                    if constexpr (kAtoms) {
-                        kmu = a.kmu[(int64_t)cd * a.pcap + t];
-                        kfa = a.kfa[(int64_t)cd * a.pcap + t];
-                    } else {
-                        kmu = cmu[cd];
-                        kfa = cfa[cd];
-                    }
-                    const double mu2 = -2.0 * kmu * sc * (double)Uc[d];
-                    const double fc = kfa * sc;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) kC[c] += mu2 * CD[c] - fc * (double)Vc[d][c];
+                    sX = fma(b[4], U, sX);
+                    sZ = fma(b[3], Y, sZ);
+                    wA = fma(b[5], X0, wA);
+                    wAB = fma(b[7], X0, wAB);
+                    wB = fma(b[6], X0, wB);
+                    wBB = fma(b[8], X0, wBB);
+                    wAD = fma(b[5], X1, wAD);
+                    wBD = fma(b[6], X1, wBD);
+                    wC = fma(b[3], Xc, wC);
+                    wCB = fma(b[6], Xc, wCB);
+                    wCD = fma(b[3], Xcd, wCD);
                 }
             }
         }
@@ -588,17 +614,42 @@ __global__ __launch_bounds__(kGroupThreads) void k_batched(BArgs a)
             atomicAdd(&Lt[tri(bj, l)], -Dik * v);
             if (kGrad) {
                 const double gam = deg * (4.0 * ds * dt - Dik * Djl - Dil * Djk);
-                const double AB[3] = {ABx, ABy, ABz};
+                const double *xc = a.xyz + 3 * (aoff + k), *xd = a.xyz + 3 * (aoff + l);
+                const double A[3] = {Ax, Ay, Az}, B[3] = {Bx, By, Bz};
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const double GA = gam * (-2.0 * AB[c] * (double)sX + (double)sYa[c]);
-                    const double GB = gam * (2.0 * AB[c] * (double)sX + (double)sYb[c]);
-                    const double GC = gam * kC[c];
+                    const double rac = A[c] - xc[c], rba = B[c] - A[c], rdc = xd[c] - xc[c];
+                    const double GA = gam * (2.0 * rba * (double)sX + rac * (double)wA + rba * (double)wAB -
+                                             rdc * (double)wAD);
+                    const double GB = gam * (-2.0 * rba * (double)sX + rac * (double)wB + rba * (double)wBB -
+                                             rdc * (double)wBD);
+                    const double GC = gam * (2.0 * rdc * (double)sZ - rac * (double)wC - rba * (double)wCB +
+                                             rdc * (double)wCD);
                     gA[c] += GA;
                     gB[c] += GB;
                     atomicAdd(&lg[3 * k + c], GC);
                     atomicAdd(&lg[3 * l + c], -(GA + GB + GC));
                 }
+            }
+        }
+    }
+    if (curbra >= 0) flush_bra();
+    }
+    __syncthreads();
+    if (owned) {
+        // the molecule's only block: store the accumulators as they are
+        for (int x = tid; x < ntri; x += nthr) a.facc[toff + x] = Lt[x];
+        if (kGrad)
+            for (int x = tid; x < 3 * nm; x += nthr) a.gacc[3 * aoff + x] = lg[x];
+    } else {
+        for (int x = tid; x < ntri; x += nthr) {
+            const double v = Lt[x];
+            if (v != 0.0) atomicAdd(&a.facc[toff + x], v);
+        }
+        if (kGrad) {
+            for (int x = tid; x < 3 * nm; x += nthr) {
+                const double v = lg[x];
+                if (v != 0.0) atomicAdd(&a.gacc[3 * aoff + x], v);
             }
         }
     }
@@ -653,6 +704,42 @@ __global__ void k_b_copy(const double *__restrict__ s, int64_t m, double *__rest
 
 // ------------------------------------------------------------------ host side
 
+template <int G, typename R, bool GR, bool AT>
+static int bres(size_t smem, int threads)
+{
+    int nb = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched<G, R, GR, AT>, threads, smem) == hipSuccess
+               ? nb
+               : 0;
+}
+
+template <typename R, bool GR, bool AT>
+static int bres_g(int g, size_t smem, int threads)
+{
+    switch (g) {
+    case 1: return bres<1, R, GR, AT>(smem, threads);
+    case 2: return bres<2, R, GR, AT>(smem, threads);
+    case 3: return bres<3, R, GR, AT>(smem, threads);
+    case 4: return bres<4, R, GR, AT>(smem, threads);
+    case 5: return bres<5, R, GR, AT>(smem, threads);
+    default: return bres<6, R, GR, AT>(smem, threads);
+    }
+}
+
+// Workgroups of the batched kernel (`waves` waves each) that fit on one CU at once (0 if the
+// runtime cannot tell).
+int batched_resident_groups(int g, int prec, bool grad, bool atoms, int nmax, int waves)
+{
+    const size_t smem = batched_smem_bytes(nmax, prec);
+    const int th = waves * kWave;
+    if (prec == HFK_MIXED) {
+        if (grad) return atoms ? bres_g<float, true, true>(g, smem, th) : bres_g<float, true, false>(g, smem, th);
+        return atoms ? bres_g<float, false, true>(g, smem, th) : bres_g<float, false, false>(g, smem, th);
+    }
+    if (grad) return atoms ? bres_g<double, true, true>(g, smem, th) : bres_g<double, true, false>(g, smem, th);
+    return atoms ? bres_g<double, false, true>(g, smem, th) : bres_g<double, false, false>(g, smem, th);
+}
+
 size_t batched_smem_bytes(int nmax, int prec)
 {
     return sizeof(double) * ((size_t)nmax * (nmax + 1) / 2 + 3 * (size_t)nmax) +
@@ -677,6 +764,7 @@ BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad
     }
     L.ptot = ptot;
     L.ntot = ntot;
+    L.tri = tri;
     L.nmax = (int)nmax;
     L.pcap = ((ptot + 63) / 64) * 64 + 64;
     size_t o = 0;
@@ -719,11 +807,10 @@ BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad
         if (with_grad) {
             L.kmu = take(sizeof(double) * g2 * PC);
             L.kfa = take(sizeof(double) * g2 * PC);
-            L.bmf = take(sizeof(double) * 2 * g2 * PC);
         }
     }
-    L.bra = take(sizeof(double) * 8 * g2 * PC);
-    L.bra_f = take(sizeof(float) * 8 * g2 * PC);
+    L.bra = take(sizeof(double) * kBBra * g2 * PC);
+    L.bra_f = take(sizeof(float) * kBBra * g2 * PC);
     L.nitems = take(sizeof(long long) * PC);
     L.lim = take(sizeof(int) * PC);
     L.klo = take(sizeof(int) * PC);
@@ -732,13 +819,17 @@ BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad
     L.scan_tmp = take(sizeof(long long) * ((scan_n + 1023) / 1024 + 1));
     L.facc = take(sizeof(double) * (size_t)tri);
     L.gacc = with_grad ? take(sizeof(double) * 3 * (size_t)ntot) : 0;
+    L.mol_i0 = take(sizeof(long long) * NM);
+    L.mol_i1 = take(sizeof(long long) * NM);
+    L.cnt_own = take(sizeof(long long) * NM);
+    L.cnt_sh = take(sizeof(long long) * NM);
+    L.off_own = take(sizeof(long long) * (NM + 1));
+    L.off_sh = take(sizeof(long long) * (NM + 1));
     L.total = o;
     return L;
 }
 
-hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int64_t *atom_off_host, const double *xyz,
-                          const double *dens, double tau, int prec, double *fock, double *e2, double *d_xyz,
-                          int groups, hipStream_t st)
+hipError_t upload_batch_tables(const BLayout &L, char *ws, const int64_t *atom_off_host, hipStream_t st)
 {
     const int64_t nmol = L.nmol;
     std::vector<int> nm(nmol);
@@ -763,8 +854,16 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
         e = hipMemcpyAsync(ws + L.mol_toff, toff.data(), sizeof(long long) * (nmol + 1), hipMemcpyHostToDevice, st);
     // the host vectors end with this call: wait until the copies have consumed them
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
+    return e;
+}
 
+hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int64_t *atom_off_host, const double *xyz,
+                          const double *dens, double tau, int prec, double *fock, double *e2, double *d_xyz,
+                          int groups, const BatchedShape &shape, hipStream_t st)
+{
+    (void)atom_off_host;
+    const int64_t nmol = L.nmol;
+    hipError_t e = hipSuccess;
     DevHeader *hdr = (DevHeader *)(ws + L.hdr);
     const BasisDev *bd = (const BasisDev *)(ws + L.basis);
     const int *d_n = (const int *)(ws + L.mol_n);
@@ -795,7 +894,7 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
                        (double *)(ws + L.pd), (double *)(ws + L.prim), (float *)(ws + L.prim_f), (double *)(ws + L.bra),
                        (float *)(ws + L.bra_f), L.atoms ? (double *)(ws + L.bip) : nullptr,
                        L.atoms ? (float *)(ws + L.bip_f) : nullptr, L.kmu ? (double *)(ws + L.kmu) : nullptr,
-                       L.kmu ? (double *)(ws + L.kfa) : nullptr, L.kmu ? (double *)(ws + L.bmf) : nullptr);
+                       L.kmu ? (double *)(ws + L.kfa) : nullptr);
     const unsigned nbc = (unsigned)((L.pcap + 255) / 256);
     e = launch_pair_pad(hdr, L.pcap, L.g2, L.atoms, (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq),
                         (double *)(ws + L.pd), (double *)(ws + L.prim), (float *)(ws + L.prim_f),
@@ -808,9 +907,18 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
     e = launch_scan((const long long *)(ws + L.nitems), L.pcap, (long long *)(ws + L.item_off),
                     (long long *)(ws + L.scan_tmp), &hdr->items, st);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_b_blocks, dim3((unsigned)((nmol + 255) / 256)), dim3(256), 0, st, hdr, (int64_t)nmol, d_n,
+                       (const long long *)boff, (const long long *)(ws + L.item_off), shape.block_items,
+                       shape.owned_bound, groups, (long long *)(ws + L.mol_i0), (long long *)(ws + L.mol_i1),
+                       (long long *)(ws + L.cnt_own), (long long *)(ws + L.cnt_sh));
+    e = launch_scan((const long long *)(ws + L.cnt_own), nmol, (long long *)(ws + L.off_own),
+                    (long long *)(ws + L.scan_tmp), &hdr->bt_own, st);
+    if (e == hipSuccess)
+        e = launch_scan((const long long *)(ws + L.cnt_sh), nmol, (long long *)(ws + L.off_sh),
+                        (long long *)(ws + L.scan_tmp), &hdr->bt_sh, st);
+    if (e != hipSuccess) return e;
 
-    long long tri = 0;
-    for (int64_t m = 0; m < nmol; ++m) tri += (long long)nm[m] * (nm[m] + 1) / 2;
+    const long long tri = L.tri;
     hipLaunchKernelGGL(k_b_fill, dim3((unsigned)((tri + 255) / 256)), dim3(256), 0, st, (double *)(ws + L.facc),
                        (int64_t)tri);
     const bool grad = d_xyz != nullptr;
@@ -837,7 +945,6 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
     a.bip_f = L.atoms ? (const float *)(ws + L.bip_f) : nullptr;
     a.kmu = L.kmu ? (const double *)(ws + L.kmu) : nullptr;
     a.kfa = L.kmu ? (const double *)(ws + L.kfa) : nullptr;
-    a.bmf = L.kmu ? (const double *)(ws + L.bmf) : nullptr;
     a.item_off = (const long long *)(ws + L.item_off);
     a.lim = (const int *)(ws + L.lim);
     a.klo = (const int *)(ws + L.klo);
@@ -851,10 +958,16 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
     a.gacc = grad ? (double *)(ws + L.gacc) : nullptr;
     a.quartets = &hdr->quartets;
     a.next_block = &hdr->next_block;
+    a.off_own = (const long long *)(ws + L.off_own);
+    a.off_sh = (const long long *)(ws + L.off_sh);
+    a.mol_i0 = (const long long *)(ws + L.mol_i0);
+    a.mol_i1 = (const long long *)(ws + L.mol_i1);
+    a.nmol = (int)nmol;
     a.pcap = L.pcap;
     a.tau = tau;
     a.nmax = L.nmax;
     const size_t smem = batched_smem_bytes(L.nmax, prec);
+    const int threads = (shape.waves == 8 ? 8 : 4) * kWave;
     {
         const hipError_t ez = launch_zero_counter(a.next_block, st);
         if (ez != hipSuccess) return ez;
@@ -864,9 +977,9 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
 #define HFK_B_LAUNCH(GG, RR, GR)                                                                         \
     do {                                                                                                 \
         if (L.atoms)                                                                                     \
-            hipLaunchKernelGGL((k_batched<GG, RR, GR, true>), dim3(groups), dim3(kGroupThreads), smem, st, a); \
+            hipLaunchKernelGGL((k_batched<GG, RR, GR, true>), dim3(groups), dim3(threads), smem, st, a); \
         else                                                                                             \
-            hipLaunchKernelGGL((k_batched<GG, RR, GR, false>), dim3(groups), dim3(kGroupThreads), smem, st, a); \
+            hipLaunchKernelGGL((k_batched<GG, RR, GR, false>), dim3(groups), dim3(threads), smem, st, a); \
     } while (0)
     if (prec == HFK_MIXED) {
         if (grad) {

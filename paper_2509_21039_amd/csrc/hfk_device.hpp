@@ -79,6 +79,28 @@ __device__ inline float rsqrt_r(float x) { return rsqrt_fp32(x); }
 // loads (they are never written while a kernel runs).
 template <typename T> using cptr = const __attribute__((address_space(4))) T *;
 
+// Buffer loads from an SoA table [C][g2][pcap] with the ket t as a 32-bit lane offset.  A
+// resource covers `rows` consecutive primitive-pair rows of one component starting at row
+// first_row (the 64-bit part of the address lives in the resource base), and the row within
+// it is the scalar offset d * pcap * sizeof(R): every offset and the record count stay below
+// 2^31 for tables of up to 2^31 / (rows * sizeof(R)) pairs, whatever the number of
+// components and primitive pairs in front.
+template <typename R>
+__device__ inline __amdgpu_buffer_rsrc_t ket_rows(const R *tab, int64_t first_row, int64_t pcap, int rows)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(tab + first_row * pcap), (short)0,
+                                             (int)((int64_t)rows * pcap * (int64_t)sizeof(R)), 0x00020000);
+}
+
+template <typename R>
+__device__ inline R ket_load(__amdgpu_buffer_rsrc_t rc, unsigned voff, int soff)
+{
+    if constexpr (sizeof(R) == 8)
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rc, (int)voff, soff, 0));
+    else
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)voff, soff, 0));
+}
+
 // Pair index p = i(i+1)/2 + j (i >= j) back to (i, j).
 __device__ inline void pair_of_index(int64_t p, int64_t &i, int64_t &j)
 {

@@ -8,7 +8,7 @@
 // An item is (bra s, 1024 consecutive kets).  Persistent workgroups fetch blocks of up to
 // kTileItems items of one bra from a global counter (the cost per item varies with the
 // bra's surroundings, and static ranges left a long tail of slow workgroups).  Blocks are
-// numbered ket-block-major within groups of kGroupBras bras, so the workgroups running
+// numbered ket-block-major within groups of bras (1024 unless tuned), so the workgroups running
 // together read the same kets, which then come from L2.  Each of a workgroup's four waves
 // takes 256 kets of an item and runs them as 64-lane chunks, one ket per lane; the bra's
 // primitive data are wave-uniform.  In the hybrid form the wave first packs the kets that
@@ -53,6 +53,7 @@ struct FockArgs {
     const long long *item_off;
     const long long *goff;      // [ngroups + 1] block offsets of the bra groups
     int64_t ngroups;
+    int gshift;                 // log2 of the bras per group
     int tile;                   // items per block
     const int *lim;
     const double *dens;
@@ -226,27 +227,21 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
 #pragma unroll 1
     for (int cb = 0; cb < G; ++cb) {
         R kx[G], ky[G], kz[G], ks[G], kq[G], kp[G];
-        // buffer loads: one resource per component (g2 * pcap values, < 4 GiB), the primitive
-        // pair as a scalar offset and the ket as a 32-bit lane offset (no 64-bit address math)
+        // buffer loads: one resource per component over the G rows of this cb, the row as a
+        // scalar offset and the ket as a 32-bit lane offset (no 64-bit address math per lane)
         const unsigned tb = t * (unsigned)sizeof(R);
-        auto ld = [&](int c, int cd) {
-            const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
-                (void *)(prim + (int64_t)c * G2 * pcap), (short)0, (int)(G2 * pcap * (int64_t)sizeof(R)), 0x00020000);
-            const int so = (int)((int64_t)cd * pcap * (int64_t)sizeof(R));
-            if constexpr (sizeof(R) == 8)
-                return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rc, (int)tb, so, 0));
-            else
-                return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)tb, so, 0));
+        auto ld = [&](int c, int d) {
+            return ket_load<R>(ket_rows(prim, (int64_t)c * G2 + cb * G, pcap, G), tb,
+                               (int)((int64_t)d * pcap * (int64_t)sizeof(R)));
         };
 #pragma unroll
         for (int d = 0; d < G; ++d) {
-            const int cd = cb * G + d;
-            kx[d] = ld(0, cd);
-            ky[d] = ld(1, cd);
-            kz[d] = ld(2, cd);
-            ks[d] = ld(3, cd);
-            kq[d] = kExpand ? ld(4, cd) : R(0);
-            kp[d] = kAtoms ? ld(kPComp, cd) : R(0);
+            kx[d] = ld(0, d);
+            ky[d] = ld(1, d);
+            kz[d] = ld(2, d);
+            ks[d] = ld(3, d);
+            kq[d] = kExpand ? ld(4, d) : R(0);
+            kp[d] = kAtoms ? ld(kPComp, d) : R(0);
         }
 #pragma unroll 1
         for (int ab = 0; ab < G2; ++ab) {
@@ -406,10 +401,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
             if (a.goff[mid] <= blk) lo = mid; else hi = mid - 1;
         }
         const long long local = blk - a.goff[lo];
-        s = (int)(lo * kGroupBras + local % kGroupBras);
+        s = (int)((lo << a.gshift) + (local & ((1LL << a.gshift) - 1)));
         if (s >= S) continue;
         const long long i1 = a.item_off[s + 1];
-        m0 = a.item_off[s] + (local / kGroupBras) * a.tile;
+        m0 = a.item_off[s] + (local >> a.gshift) * a.tile;
         if (m0 >= i1) continue;   // this bra has fewer blocks than the group's longest
         m1 = m0 + a.tile < i1 ? m0 + a.tile : i1;
     }
@@ -760,6 +755,7 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.lim = (const int *)(ws + L.lim);
     a.goff = (const long long *)(ws + L.goff);
     a.ngroups = L.ngroups;
+    a.gshift = L.gshift;
     a.tile = L.tile;
     a.dens = dens;
     a.fpriv = (double *)(ws + L.fpriv);
@@ -770,7 +766,7 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.tau = tau;
     a.n = (int)L.n;
     a.strategy = strategy;
-    a.jcopies = L.jcopies < L.groups ? L.jcopies : L.groups;
+    a.jcopies = effective_copies(L);
     if (a.jcopies < L.groups) {
         // shared ket vectors are cleared before the launch (workgroups clear private ones)
         const int64_t nj = (int64_t)a.jcopies * L.pcap;

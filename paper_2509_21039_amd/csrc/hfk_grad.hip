@@ -10,6 +10,13 @@
 //   d(ab|cd)/dC = S_ab S_cd [ -2 mu_cd (C-D) E - (c/q) (P-Q) W ]
 //   d(ab|cd)/dD = -(dA + dB + dC)            (translation invariance)
 // Beyond the switch E = 1/r and W = -1/r^3 exactly; below it both come from Taylor tables.
+// With P = A + fb (B - A) and Q = C + fd (D - C) (fa = a/p, fb = b/p, fc = c/q, fd = d/q) the
+// separation is P - Q = R_AC + fb R_BA - fd R_DC, so the W terms need only scalar sums of
+// w = S_ab S_cd W weighted by the fractions (sum fa w, fa fb w, fa fd w, fb w, fb^2 w,
+// fb fd w, fc w, fc fb w, fc fd w), each accumulated directly: the lane adds S_cd E,
+// mu_cd S_cd E, S_cd W, fd S_cd W, fc S_cd W and fc fd S_cd W per primitive quartet and folds
+// them once per bra primitive pair with the bra's weights (mu S, fa S, fb S, fa fb S, fb^2 S,
+// stored per pair), and the atom vectors enter once per quartet in FP64.
 //
 // Per-atom bases (kAtoms): mu, a/p and rho differ per primitive pair and quartet.  The
 // switch radius^2 kTswitch / rho is the sum of the stored kTswitch / p of bra and ket (as in
@@ -45,10 +52,12 @@ struct GradArgs {
     const float *bip_f;
     const double *kmu;      // per-atom bases: [g2][pcap] mu and a/p of the ket pairs
     const double *kfa;
-    const double *bmf;      // per-atom bases: [pcap][g2][2] (mu, a/p) of the bra pairs
+    const double *bgw;      // [pcap][g2][kGW] bra weights mu S, fa S, fb S, fa fb S, fb^2 S (and FP32 copy)
+    const float *bgw_f;
     const long long *item_off;
     const long long *goff;      // [ngroups + 1] block offsets of the bra groups
     int64_t ngroups;
+    int gshift;                 // log2 of the bras per group
     int tile;               // items per block
     const int *lim;
     const double *dens;
@@ -67,6 +76,7 @@ template <> struct GPrec<double> {
     static __device__ const double *prim(const GradArgs &a) { return a.prim; }
     static __device__ const double *bra(const GradArgs &a) { return a.bra; }
     static __device__ const double *bip(const GradArgs &a) { return a.bip; }
+    static __device__ const double *bgw(const GradArgs &a) { return a.bgw; }
     static __device__ const double *tabH(const GradArgs &a) { return a.tabH; }
     static __device__ const double *tabG(const GradArgs &a) { return a.tabG; }
     static __device__ const double *rsg(const BasisDev *bd) { return bd->rsg; }
@@ -76,6 +86,7 @@ template <> struct GPrec<float> {
     static __device__ const float *prim(const GradArgs &a) { return a.prim_f; }
     static __device__ const float *bra(const GradArgs &a) { return a.bra_f; }
     static __device__ const float *bip(const GradArgs &a) { return a.bip_f; }
+    static __device__ const float *bgw(const GradArgs &a) { return a.bgw_f; }
     static __device__ const float *tabH(const GradArgs &a) { return a.tabH_f; }
     static __device__ const float *tabG(const GradArgs &a) { return a.tabG_f; }
     static __device__ const float *rsg(const BasisDev *bd) { return bd->rsg_f; }
@@ -132,10 +143,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                 if (a.goff[mid] <= blk) lo = mid; else hi = mid - 1;
             }
             const long long local = blk - a.goff[lo];
-            s = (int)(lo * kGroupBras + local % kGroupBras);
+            s = (int)((lo << a.gshift) + (local & ((1LL << a.gshift) - 1)));
             if (s >= S) continue;
             const long long i1 = a.item_off[s + 1];
-            m0 = a.item_off[s] + (local / kGroupBras) * a.tile;
+            m0 = a.item_off[s] + (local >> a.gshift) * a.tile;
             if (m0 >= i1) continue;
             m1 = m0 + a.tile < i1 ? m0 + a.tile : i1;
         }
@@ -146,7 +157,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
         const cptr<double> cfb = (cptr<double>)bd->fb;
         int cur = -1, bi = 0, bj = 0, lim = 0;
         double qs = 0.0, ds = 0.0;
-        double ABx = 0.0, ABy = 0.0, ABz = 0.0;
         double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
         for (long long m = m0; m <= m1; ++m) {
             if (m < m1) {
@@ -171,9 +181,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                 qs = a.pq[s];
                 ds = a.pd[s];
                 lim = a.lim[s];
-                ABx = a.xyz[3 * bi] - a.xyz[3 * bj];
-                ABy = a.xyz[3 * bi + 1] - a.xyz[3 * bj + 1];
-                ABz = a.xyz[3 * bi + 2] - a.xyz[3 * bj + 2];
             }
             const long long wbase = (m - a.item_off[s]) * kItemKets + (long long)wave * kWaveKets;
             if (wbase >= lim) continue;
@@ -186,55 +193,64 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                 const long long t = valid ? perm[c0 + lane] : S;   // S: first pad entry
                 const cptr<R> bra = (cptr<R>)(GPrec<R>::bra(a) + (int64_t)s * 8 * G2);
                 const cptr<R> bipp = kAtoms ? (cptr<R>)(GPrec<R>::bip(a) + (int64_t)s * G2) : nullptr;
-                const cptr<double> bmfp = kAtoms ? (cptr<double>)(a.bmf + (int64_t)s * 2 * G2) : nullptr;
+                const cptr<R> bwp = (cptr<R>)(GPrec<R>::bgw(a) + (int64_t)s * kGW * G2);
 
-                R sX = R(0), eri = R(0);
-                R sYa[3] = {R(0), R(0), R(0)}, sYb[3] = {R(0), R(0), R(0)};
-                double kC[3] = {0.0, 0.0, 0.0};
+                // eri; sX = sum mu_ab S S E, sZ = sum mu_cd S S E; fraction-weighted sums of
+                // w = S S W (names: weights of bra, then ket)
+                R eri = R(0), sX = R(0), sZ = R(0);
+                R wA = R(0), wAB = R(0), wB = R(0), wBB = R(0), wAD = R(0), wBD = R(0), wC = R(0), wCB = R(0),
+                  wCD = R(0);
                 const int k = a.pk[t], l = a.pl[t];
-                const double CDx = a.xyz[3 * k] - a.xyz[3 * l];
-                const double CDy = a.xyz[3 * k + 1] - a.xyz[3 * l + 1];
-                const double CDz = a.xyz[3 * k + 2] - a.xyz[3 * l + 2];
     #pragma unroll 1
                 for (int cb = 0; cb < G; ++cb) {
                     R kx[G], ky[G], kz[G], ks[G], kp[G];
-                    R Uc[G], Vc[G][3];
-                    // buffer loads of the ket table: component base, primitive pair as a
-                    // scalar offset, ket as a 32-bit lane offset
+                    R kms[G], kds[G], kcs[G], kcds[G];   // S_cd times mu_cd, fd, fc, fc fd
+                    // buffer loads of the ket table: component and this cb's rows in the
+                    // resource, the row as a scalar offset, the ket as a 32-bit lane offset
                     const unsigned tb = (unsigned)t * (unsigned)sizeof(R);
-                    auto ld = [&](int c, int cd) {
-                        const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
-                            (void *)(prim + (int64_t)c * G2 * a.pcap), (short)0,
-                            (int)(G2 * a.pcap * (int64_t)sizeof(R)), 0x00020000);
-                        const int so = (int)((int64_t)cd * a.pcap * (int64_t)sizeof(R));
-                        if constexpr (sizeof(R) == 8)
-                            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rc, (int)tb, so, 0));
-                        else
-                            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)tb, so, 0));
+                    auto ld = [&](int c, int d) {
+                        return ket_load<R>(ket_rows(prim, (int64_t)c * G2 + cb * G, a.pcap, G), tb,
+                                          (int)((int64_t)d * a.pcap * (int64_t)sizeof(R)));
                     };
 #pragma unroll
                     for (int d = 0; d < G; ++d) {
+                        kx[d] = ld(0, d);
+                        ky[d] = ld(1, d);
+                        kz[d] = ld(2, d);
+                        ks[d] = ld(3, d);
+                        kp[d] = kAtoms ? ld(kPComp, d) : R(0);
+                    }
+#pragma unroll
+                    for (int d = 0; d < G; ++d) {
                         const int cd = cb * G + d;
-                        kx[d] = ld(0, cd);
-                        ky[d] = ld(1, cd);
-                        kz[d] = ld(2, cd);
-                        ks[d] = ld(3, cd);
-                        kp[d] = kAtoms ? ld(kPComp, cd) : R(0);
-                        Uc[d] = R(0);
-                        Vc[d][0] = Vc[d][1] = Vc[d][2] = R(0);
+                        double mu, fc;
+                        if constexpr (kAtoms) {
+                            mu = a.kmu[(int64_t)cd * a.pcap + t];
+                            fc = a.kfa[(int64_t)cd * a.pcap + t];
+                        } else {
+                            mu = cmu[cd];
+                            fc = cfa[cd];
+                        }
+                        const double fd = kAtoms ? 1.0 - fc : cfb[cd];
+                        kms[d] = (R)mu * ks[d];
+                        kcs[d] = (R)fc * ks[d];
+                        kds[d] = (R)fd * ks[d];
+                        kcds[d] = (R)(fc * fd) * ks[d];
                     }
 #pragma unroll 1
                     for (int ab = 0; ab < G2; ++ab) {
-                        // every scalar of this bra primitive in one batch of scalar loads
+                        // every scalar of this bra primitive in one batch of scalar loads: the
+                        // centre and charge, the weights mu S, fa S, fb S, fa fb S, fb^2 S, and
+                        // the switch data
                         const cptr<R> bp = bra + 8 * ab;
-                        R b[4], u[4 * G], bsw = R(0);
-                        double bmu = 0.0, bfa = 0.0;
+                        const cptr<R> wp = bwp + kGW * ab;
+                        R b[4], bw[5], u[4 * G], bsw = R(0);
 #pragma unroll
                         for (int c = 0; c < 4; ++c) b[c] = bp[c];
+#pragma unroll
+                        for (int c = 0; c < 5; ++c) bw[c] = wp[c];
                         if constexpr (kAtoms) {
                             bsw = bipp[ab];
-                            bmu = bmfp[2 * ab];
-                            bfa = bmfp[2 * ab + 1];
                             asm volatile("" ::"s"(bsw));
                         } else {
                             const cptr<R> up = rsg + 4 * (ab * G2 + cb * G);
@@ -244,7 +260,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                             for (int c = 0; c < 4 * G; ++c) asm volatile("" ::"s"(u[c]));
                         }
                         const R px = b[0], py = b[1], pz = b[2], sab = b[3];
-                        R U = R(0), V0 = R(0), V1 = R(0), V2 = R(0);
+                        R U = R(0), Y = R(0), X0 = R(0), X1 = R(0), Xc = R(0), Xcd = R(0);
 #pragma unroll
                         for (int d = 0; d < G; ++d) {
                             const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
@@ -288,48 +304,25 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                                 E = y;
                                 W = -(y * y * y);
                             }
-                            const R wk = ks[d] * W, wb = sab * W;
-                            U += ks[d] * E;
-                            V0 += wk * dx;
-                            V1 += wk * dy;
-                            V2 += wk * dz;
-                            Uc[d] += sab * E;
-                            Vc[d][0] += wb * dx;
-                            Vc[d][1] += wb * dy;
-                            Vc[d][2] += wb * dz;
+                            U = fma(ks[d], E, U);
+                            Y = fma(kms[d], E, Y);
+                            X0 = fma(ks[d], W, X0);
+                            X1 = fma(kds[d], W, X1);
+                            Xc = fma(kcs[d], W, Xc);
+                            Xcd = fma(kcds[d], W, Xcd);
                         }
-                        const R su = sab * U;
-                        eri += su;
-                        R fa, fb;
-                        if constexpr (kAtoms) {
-                            sX += (R)bmu * su;
-                            fa = (R)bfa * sab;
-                            fb = sab - fa;
-                        } else {
-                            sX += (R)cmu[ab] * su;
-                            fa = (R)cfa[ab] * sab;
-                            fb = (R)cfb[ab] * sab;
-                        }
-                        sYa[0] += fa * V0; sYa[1] += fa * V1; sYa[2] += fa * V2;
-                        sYb[0] += fb * V0; sYb[1] += fb * V1; sYb[2] += fb * V2;
-                    }
-#pragma unroll
-                    for (int d = 0; d < G; ++d) {
-                        const int cd = cb * G + d;
-                        const double sc = (double)ks[d];
-                        double kmu, kfa;
-                        if constexpr (kAtoms) {
-                            kmu = a.kmu[(int64_t)cd * a.pcap + t];
-                            kfa = a.kfa[(int64_t)cd * a.pcap + t];
-                        } else {
-                            kmu = cmu[cd];
-                            kfa = cfa[cd];
-                        }
-                        const double mu2 = -2.0 * kmu * sc * (double)Uc[d];
-                        const double fc = kfa * sc;
-                        kC[0] += mu2 * CDx - fc * (double)Vc[d][0];
-                        kC[1] += mu2 * CDy - fc * (double)Vc[d][1];
-                        kC[2] += mu2 * CDz - fc * (double)Vc[d][2];
+                        eri = fma(sab, U, eri);
+                        sX = fma(bw[0], U, sX);
+                        sZ = fma(sab, Y, sZ);
+                        wA = fma(bw[1], X0, wA);
+                        wAB = fma(bw[3], X0, wAB);
+                        wB = fma(bw[2], X0, wB);
+                        wBB = fma(bw[4], X0, wBB);
+                        wAD = fma(bw[1], X1, wAD);
+                        wBD = fma(bw[2], X1, wBD);
+                        wC = fma(sab, Xc, wC);
+                        wCB = fma(bw[2], Xc, wCB);
+                        wCD = fma(sab, Xcd, wCD);
                     }
                 }
                 if (valid) {
@@ -348,17 +341,22 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                         gam = deg * (4.0 * (xs * dt + ds * xt) - (Xi[k] * Dj[l] + Di[k] * Xj[l]) -
                                      (Xi[l] * Dj[k] + Di[l] * Xj[k]));
                     }
-                    const double AB[3] = {ABx, ABy, ABz};
-                    double GA[3], GB[3], GC[3];
+                    const double *xa = a.xyz + 3 * bi, *xb = a.xyz + 3 * bj;
+                    const double *xc = a.xyz + 3 * k, *xd = a.xyz + 3 * l;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        GA[c] = gam * (-2.0 * AB[c] * (double)sX + (double)sYa[c]);
-                        GB[c] = gam * (2.0 * AB[c] * (double)sX + (double)sYb[c]);
-                        GC[c] = gam * kC[c];
-                        gA[c] += GA[c];
-                        gB[c] += GB[c];
-                        atomicAdd(&lg[3 * k + c], GC[c]);
-                        atomicAdd(&lg[3 * l + c], -(GA[c] + GB[c] + GC[c]));
+                        // P - Q = R_AC + fb R_BA - fd R_DC
+                        const double rac = xa[c] - xc[c], rba = xb[c] - xa[c], rdc = xd[c] - xc[c];
+                        const double GA = gam * (2.0 * rba * (double)sX + rac * (double)wA + rba * (double)wAB -
+                                                 rdc * (double)wAD);
+                        const double GB = gam * (-2.0 * rba * (double)sX + rac * (double)wB + rba * (double)wBB -
+                                                 rdc * (double)wBD);
+                        const double GC = gam * (2.0 * rdc * (double)sZ - rac * (double)wC - rba * (double)wCB +
+                                                 rdc * (double)wCD);
+                        gA[c] += GA;
+                        gB[c] += GB;
+                        atomicAdd(&lg[3 * k + c], GC);
+                        atomicAdd(&lg[3 * l + c], -(GA + GB + GC));
                     }
                     eacc += gE * (double)eri;
                 }
@@ -457,14 +455,50 @@ size_t grad_smem_bytes(int64_t n, int prec)
 }
 
 template <int G, typename R>
+static int grad_res(bool atoms, size_t smem)
+{
+    int nb = 0;
+    const hipError_t e = atoms ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grad<G, R, true>, kGroupThreads, smem)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grad<G, R, false>, kGroupThreads, smem);
+    return e == hipSuccess ? nb : 0;
+}
+
+// Workgroups of the gradient kernel that fit on one CU at once (registers and LDS); 0 if the
+// runtime cannot tell.
+int grad_resident_groups(int g, int prec, int64_t n, bool atoms)
+{
+    const size_t smem = grad_smem_bytes(n, prec);
+    if (prec == HFK_MIXED) {
+        switch (g) {
+        case 1: return grad_res<1, float>(atoms, smem);
+        case 2: return grad_res<2, float>(atoms, smem);
+        case 3: return grad_res<3, float>(atoms, smem);
+        case 4: return grad_res<4, float>(atoms, smem);
+        case 5: return grad_res<5, float>(atoms, smem);
+        default: return grad_res<6, float>(atoms, smem);
+        }
+    }
+    switch (g) {
+    case 1: return grad_res<1, double>(atoms, smem);
+    case 2: return grad_res<2, double>(atoms, smem);
+    case 3: return grad_res<3, double>(atoms, smem);
+    case 4: return grad_res<4, double>(atoms, smem);
+    case 5: return grad_res<5, double>(atoms, smem);
+    default: return grad_res<6, double>(atoms, smem);
+    }
+}
+
+template <int G, typename R>
 static hipError_t launch_grad_t(const GradArgs &a, int groups, size_t smem, bool atoms, hipStream_t st)
 {
     const hipError_t ez = launch_zero_counter(a.next_block, st);
     if (ez != hipSuccess) return ez;
+    profile_begin(st);
     if (atoms)
         hipLaunchKernelGGL((k_grad<G, R, true>), dim3(groups), dim3(kGroupThreads), smem, st, a);
     else
         hipLaunchKernelGGL((k_grad<G, R, false>), dim3(groups), dim3(kGroupThreads), smem, st, a);
+    profile_end(st);
     return hipGetLastError();
 }
 
@@ -492,11 +526,13 @@ hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *
     a.bip_f = at ? (const float *)(ws + L.bip_f) : nullptr;
     a.kmu = at ? (const double *)(ws + L.pmu) : nullptr;
     a.kfa = at ? (const double *)(ws + L.pfa) : nullptr;
-    a.bmf = at ? (const double *)(ws + L.bmf) : nullptr;
+    a.bgw = (const double *)(ws + L.bgw);
+    a.bgw_f = (const float *)(ws + L.bgw_f);
     a.item_off = (const long long *)(ws + L.item_off);
     a.lim = (const int *)(ws + L.lim);
     a.goff = (const long long *)(ws + L.goff);
     a.ngroups = L.ngroups;
+    a.gshift = L.gshift;
     a.tile = L.tile;
     a.dens = dens;
     a.xdens = xdens;

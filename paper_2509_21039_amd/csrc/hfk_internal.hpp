@@ -46,6 +46,14 @@ constexpr int kSubChunks = 4;
 constexpr int kWaveKets = kWave * kSubChunks;
 constexpr int kItemKets = kWavesPerGroup * kWaveKets;
 constexpr int kBlockItems = 16;  // items per dynamically fetched block of the quartet kernels
+// Batched kernel: items of kKetsPerItem kets are cut into units of one wave's 64 kets; the
+// workgroup has 4 or 8 waves (set at launch, at most kBatchMaxThreads threads); the bra table
+// holds kBBra values per primitive pair (Px Py Pz S, mu S, fa S, fb S, fa fb S, fb^2 S, pad).
+constexpr int kUnitsPerItem = kKetsPerItem / kWave;
+constexpr int kBatchMaxThreads = 512;
+constexpr int kBBra = 12;
+// Gradient bra weights per primitive pair of the single-molecule tables.
+constexpr int kGW = 8;
 // Single-molecule blocks: kTileItems items of one bra (twice as many with FP32 ket data).
 // Bras are taken kGroupBras at a time and their blocks are numbered ket-block-major (block
 // K of every bra of the group, then block K+1), so the workgroups running at the same
@@ -57,6 +65,11 @@ constexpr int kBlockItems = 16;  // items per dynamically fetched block of the q
 // faster choice there.
 constexpr int kTileItems = 4;
 constexpr int kGroupBras = 1024;
+// Bras per group are a power of two in [kMinGroupBras, kMaxGroupBras] (tuned); the group
+// tables are sized for the smallest.
+constexpr int kMinGroupBras = 256;
+constexpr int kMaxGroupBras = 4096;
+constexpr int kMaxTileItems = 16;
 
 // Device-side counters written by the build and read back by hfk_read_stats.
 struct DevHeader {
@@ -76,6 +89,21 @@ struct DevHeader {
     int max_bucket;                 // most pairs in one (band, cell) bucket (fixed pair order only)
     unsigned long long next_block;  // work counter of the quartet kernels (blocks of items)
     long long blocks;               // blocks of the single-molecule kernels (empty ones included)
+    int tile;                       // launch shape of the last build (for the stats)
+    int group_bras;
+    int ket_copies;
+    int pad1;
+    // batched block table: owned-molecule blocks, shared blocks, items per shared block
+    long long bt_own;
+    long long bt_sh;
+    long long bsz;
+    // debug check of the density (hfk_set_debug): bit patterns of non-negative doubles
+    unsigned long long dchk_asym;   // max |D_ij - D_ji| (single molecule)
+    unsigned long long dchk_max;    // max |D_ij| (single molecule)
+    unsigned long long dchk_ratio;  // max over molecules of max|D_ij - D_ji| / max|D_ij| (batched)
+    unsigned long long dchk_bad;    // non-finite entries
+    int dchk_mol;                   // first molecule over the tolerance (batched), or INT_MAX
+    int dchk_badmol;                // first molecule with a non-finite entry (batched), or INT_MAX
 };
 
 // Basis constants shared by every pair, computed on the host from exps/coefs and passed
@@ -116,7 +144,9 @@ struct BasisDev {
 struct Layout {
     int64_t n, npair, pcap;     // pcap = npair rounded up to 64, plus one spare chunk
     int g, g2, groups;          // groups: persistent workgroups the buffers are sized for
-    int tile;                   // items per block (kTileItems, doubled for FP32 ket data)
+    int tile;                   // items per block (kTileItems, doubled for FP32 ket data; tuned)
+    int gshift;                 // log2 of the bras per group (tuned)
+    int kcopies;                // ket-side Coulomb vectors requested (0: one per workgroup)
     bool private_ok;            // per-workgroup copies of F fit the memory budget
     size_t hdr, basis, boys, boys_f;
     size_t q_unsorted, bucket_of, bucket_cnt, bucket_off, bucket_cur;
@@ -127,12 +157,13 @@ struct Layout {
     size_t arow;                           // [2][n][g] exponents and weights of every atom
     size_t bip, bip_f;                     // [pcap][g2] kTswitch/p of every bra primitive pair
     size_t pmu, pfa;                       // per-atom gradient: [g2][pcap] mu and a/p of the ket pairs
-    size_t bmf;                            // per-atom gradient: [pcap][g2][2] (mu, a/p) of the bra pairs
+    size_t bgw, bgw_f;                     // gradient: [pcap][g2][kGW] bra weights mu S, fa S, fb S, fa fb S, fb^2 S
     size_t bra, bra_f;                     // [pcap][g2][8] Px Py Pz S -2Px -2Py -2Pz |P|^2 (wave-uniform bra data)
     size_t boys_g, boys_g_f;               // Taylor table of g(T) = -(4/sqrt(pi)) F1(T) (gradient)
     size_t nitems, lim, item_off, scan_tmp;
     size_t gcnt, goff;                     // per bra group: blocks, and their exclusive prefix
-    int64_t ngroups;                       // bra groups of kGroupBras
+    int64_t ngroups;                       // bra groups of 2^gshift bras
+    int64_t ngroups_cap;                   // groups the tables hold (groups of kMinGroupBras)
     size_t fpriv;                          // [groups][n*n] or [n*n]
     size_t jcol;                           // [jcopies][pcap] ket-side Coulomb vectors
     int jcopies;                           // copies of the ket vector (one per workgroup while they fit)
@@ -145,10 +176,23 @@ struct Layout {
 };
 
 Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool atoms = false);
+// Ket-side Coulomb vectors a build uses: one per workgroup within the memory budget, or the
+// requested number of shared copies when that is smaller.
+inline int effective_copies(const Layout &L)
+{
+    int c = L.jcopies < L.groups ? L.jcopies : L.groups;
+    if (L.kcopies > 0 && L.kcopies < c) c = L.kcopies;
+    return c;
+}
+
+// Sets the quartet-tile shape of a layout: items per block, bras per group (a power of two
+// in [kMinGroupBras, kMaxGroupBras]) and the requested ket-side Coulomb vector copies.
+void set_shape(Layout &L, int tile, int group_bras, int ket_copies);
 
 // Workspace layout of the batched path.
 struct BLayout {
     int64_t nmol, ptot, ntot, pcap;
+    int64_t tri;                // sum of n (n + 1) / 2: entries of the packed triangles
     int g, g2, nmax;
     size_t hdr, basis, boys, boys_f, boys_g, boys_g_f;
     size_t mol_n, mol_aoff, mol_poff, mol_doff, mol_toff, cent, qmax;
@@ -156,18 +200,39 @@ struct BLayout {
     size_t pk, pl, pm, pq, pd, prim, prim_f, bra, bra_f;
     size_t nitems, lim, klo, item_off, scan_tmp;
     size_t facc, gacc;
+    size_t mol_i0, mol_i1;              // per molecule: first and end item
+    size_t cnt_own, cnt_sh, off_own, off_sh;   // per molecule: blocks of each kind and their prefix
     bool atoms;                 // per-atom bases: ket component 4 is kTswitch/p, tables below
     size_t arow;                // [2][sum n][g] exponents and weights of every atom
     size_t bip, bip_f;          // [pcap][g2] kTswitch/p of the bra pairs
-    size_t kmu, kfa, bmf;       // gradient: [g2][pcap] ket mu, a/p; [pcap][g2][2] bra (mu, a/p)
+    size_t kmu, kfa;            // per-atom gradient: [g2][pcap] ket mu and a/p
     size_t total;
 };
 
 BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad, bool atoms = false);
 size_t batched_smem_bytes(int nmax, int prec);
+// Launch configuration of the batched kernel: block_items 0 = automatic (total items /
+// (8 x workgroups), clamped to [16, 64]); owned_bound > 0: molecules with at most that many
+// unique quartets before screening run whole in one workgroup (plain stores), -1: none.
+struct BatchedShape {
+    int gpc;
+    int block_items;
+    long long owned_bound;
+    int waves;                  // waves per workgroup (4 or 8)
+};
+// Copies the per-molecule tables (atom counts, offsets) into the workspace and waits for
+// the copies (their host staging ends with the call).
+hipError_t upload_batch_tables(const BLayout &L, char *ws, const int64_t *atom_off_host, hipStream_t st);
 hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int64_t *atom_off_host, const double *xyz,
                           const double *dens, double tau, int prec, double *fock, double *e2, double *d_xyz,
-                          int groups, hipStream_t st);
+                          int groups, const BatchedShape &shape, hipStream_t st);
+int batched_resident_groups(int g, int prec, bool grad, bool atoms, int nmax, int waves);
+// Debug check of densities on the device (results in the header's dchk fields, which the
+// first launch clears): one row-major n x n matrix, or nmol matrices at mol_doff with sizes
+// mol_n (device arrays), each compared against tol times its own largest entry.
+hipError_t launch_dens_check(DevHeader *hdr, int64_t n, const double *dens, hipStream_t st);
+hipError_t launch_dens_check_batched(DevHeader *hdr, int64_t nmol, const long long *mol_doff, const int *mol_n,
+                                     const double *dens, double tol, hipStream_t st);
 // Pads the batched pair tables (four-component ket table, plus kTswitch/p with per-atom
 // bases; kmu/kfa: per-atom gradient tables or NULL) past the last pair.
 hipError_t launch_pair_pad(const DevHeader *hdr, int64_t pcap, int g2, bool atoms, int *pk, int *pl, double *pq,
@@ -196,7 +261,7 @@ void profile_begin(hipStream_t st);
 void profile_end(hipStream_t st);
 
 hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision, int variant,
-                              hipStream_t st);
+                              hipStream_t st, int tile = 0, int group_bras = 0, int ket_copies = 0);
 hipError_t launch_scan(const long long *in, int64_t m, long long *out, long long *tmp, long long *total,
                        hipStream_t st);
 // Gradient kernel and its reductions.  xdens: X of the two-density contraction (see
@@ -211,5 +276,6 @@ hipError_t launch_make_xw(int64_t n, const double *dens, const double *g_fock, c
 // y += g_e2 * x over m values.
 hipError_t launch_axpy_dev(int64_t m, const double *g_e2, const double *x, double *y, hipStream_t st);
 size_t grad_smem_bytes(int64_t n, int prec);
+int grad_resident_groups(int g, int prec, int64_t n, bool atoms);
 
 }  // namespace hfk

@@ -264,7 +264,8 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
                                                       float *__restrict__ prim_f, double *__restrict__ bra,
                                                       float *__restrict__ bra_f, double *__restrict__ bip,
                                                       float *__restrict__ bip_f, double *__restrict__ kmu,
-                                                      double *__restrict__ kfa, double *__restrict__ bmf,
+                                                      double *__restrict__ kfa, double *__restrict__ bgw,
+                                                      float *__restrict__ bgw_f,
                                                       const int *__restrict__ slot)
 {
     const int64_t npair = n * (n + 1) / 2;
@@ -328,12 +329,26 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Basis b, const BasisDev *_
         }
     }
     if (kmu) {
-        // per-atom gradient: mu and a/p of every primitive pair, ket-major and bra-major
+        // per-atom gradient: mu and a/p of every ket primitive pair
         for (int ab = 0; ab < g2; ++ab) {
             kmu[(int64_t)ab * pcap + pos] = mu[ab];
             kfa[(int64_t)ab * pcap + pos] = fa[ab];
-            bmf[((int64_t)pos * g2 + ab) * 2] = mu[ab];
-            bmf[((int64_t)pos * g2 + ab) * 2 + 1] = fa[ab];
+        }
+    }
+    if (bgw) {
+        // gradient: the bra weights mu S, fa S, fb S, fa fb S, fb^2 S of every primitive pair
+        for (int ab = 0; ab < g2; ++ab) {
+            const double m_ab = b.aexp ? mu[ab] : bd->mu[ab];
+            const double fa_ab = b.aexp ? fa[ab] : bd->fa[ab];
+            const double fb_ab = b.aexp ? 1.0 - fa[ab] : bd->fb[ab];
+            const double row[kGW] = {m_ab * ps[ab], fa_ab * ps[ab], fb_ab * ps[ab], fa_ab * fb_ab * ps[ab],
+                                     fb_ab * fb_ab * ps[ab], 0.0, 0.0, 0.0};
+            double *w = bgw + ((int64_t)pos * g2 + ab) * kGW;
+            float *wf = bgw_f + ((int64_t)pos * g2 + ab) * kGW;
+            for (int c = 0; c < kGW; ++c) {
+                w[c] = row[c];
+                wf[c] = (float)row[c];
+            }
         }
     }
 }
@@ -539,18 +554,149 @@ hipError_t launch_scan(const long long *in, int64_t m, long long *out, long long
     return hipGetLastError();
 }
 
-__global__ void k_header_info(DevHeader *hdr, int strategy, int groups, int precision, int variant)
+__global__ void k_header_info(DevHeader *hdr, int strategy, int groups, int precision, int variant, int tile,
+                              int group_bras, int ket_copies)
 {
     hdr->strategy = strategy;
     hdr->groups = groups;
     hdr->precision = precision;
     hdr->variant = variant;
+    hdr->tile = tile >= 0 ? tile : (int)hdr->bsz;   // batched: the block size its table used
+    hdr->group_bras = group_bras;
+    hdr->ket_copies = ket_copies;
 }
 
-hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision, int variant, hipStream_t st)
+hipError_t launch_header_info(char *hdr, int strategy, int groups, int precision, int variant, hipStream_t st,
+                              int tile, int group_bras, int ket_copies)
 {
     hipLaunchKernelGGL(k_header_info, dim3(1), dim3(1), 0, st, (DevHeader *)hdr, strategy, groups, precision,
-                       variant);
+                       variant, tile, group_bras, ket_copies);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ debug check of the density
+
+__global__ void k_dchk_reset(DevHeader *hdr)
+{
+    hdr->dchk_asym = 0;
+    hdr->dchk_max = 0;
+    hdr->dchk_ratio = 0;
+    hdr->dchk_bad = 0;
+    hdr->dchk_mol = 0x7fffffff;
+    hdr->dchk_badmol = 0x7fffffff;
+}
+
+// Non-negative doubles order like their bit patterns, so atomicMax on the patterns is a max.
+__device__ inline void atomic_max_nonneg(unsigned long long *p, double v)
+{
+    atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+
+// One matrix, any size: grid-stride over its entries, block maxima, then atomics.
+__global__ __launch_bounds__(256) void k_dens_check(int64_t n, const double *__restrict__ D,
+                                                    DevHeader *__restrict__ hdr)
+{
+    __shared__ double ra[256], rm[256];
+    __shared__ unsigned long long rb[256];
+    double asym = 0.0, mx = 0.0;
+    unsigned long long bad = 0;
+    const int64_t n2 = n * n;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n2; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = x / n, j = x - i * n;
+        const double v = D[x];
+        if (!isfinite(v)) {
+            ++bad;
+            continue;
+        }
+        mx = fmax(mx, fabs(v));
+        const double w = D[j * n + i];
+        if (isfinite(w)) asym = fmax(asym, fabs(v - w));
+    }
+    ra[threadIdx.x] = asym;
+    rm[threadIdx.x] = mx;
+    rb[threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            ra[threadIdx.x] = fmax(ra[threadIdx.x], ra[threadIdx.x + w]);
+            rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + w]);
+            rb[threadIdx.x] += rb[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomic_max_nonneg(&hdr->dchk_asym, ra[0]);
+        atomic_max_nonneg(&hdr->dchk_max, rm[0]);
+        if (rb[0]) atomicAdd(&hdr->dchk_bad, rb[0]);
+    }
+}
+
+// Many small matrices: one block per molecule (grid-stride over molecules), each judged
+// against tol times its own largest entry.
+__global__ __launch_bounds__(256) void k_dens_check_batched(int64_t nmol, const long long *__restrict__ doff,
+                                                            const int *__restrict__ nmv,
+                                                            const double *__restrict__ D, double tol,
+                                                            DevHeader *__restrict__ hdr)
+{
+    __shared__ double ra[256], rm[256];
+    __shared__ unsigned long long rb[256];
+    for (int64_t m = blockIdx.x; m < nmol; m += gridDim.x) {
+        const int64_t n = nmv[m];
+        const double *Dm = D + doff[m];
+        double asym = 0.0, mx = 0.0;
+        unsigned long long bad = 0;
+        for (int64_t x = threadIdx.x; x < n * n; x += blockDim.x) {
+            const int64_t i = x / n, j = x - i * n;
+            const double v = Dm[x];
+            if (!isfinite(v)) {
+                ++bad;
+                continue;
+            }
+            mx = fmax(mx, fabs(v));
+            const double w = Dm[j * n + i];
+            if (isfinite(w)) asym = fmax(asym, fabs(v - w));
+        }
+        ra[threadIdx.x] = asym;
+        rm[threadIdx.x] = mx;
+        rb[threadIdx.x] = bad;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                ra[threadIdx.x] = fmax(ra[threadIdx.x], ra[threadIdx.x + w]);
+                rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + w]);
+                rb[threadIdx.x] += rb[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (rb[0]) {
+                atomicAdd(&hdr->dchk_bad, rb[0]);
+                atomicMin(&hdr->dchk_badmol, (int)m);
+            }
+            const double a = ra[0], b = rm[0];
+            if (a > tol * b) {
+                atomicMin(&hdr->dchk_mol, (int)m);
+                atomic_max_nonneg(&hdr->dchk_ratio, b > 0.0 ? a / b : a);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_dens_check(DevHeader *hdr, int64_t n, const double *dens, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dchk_reset, dim3(1), dim3(1), 0, st, hdr);
+    const int64_t nb = (n * n + 255) / 256;
+    hipLaunchKernelGGL(k_dens_check, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, st, n, dens, hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_dens_check_batched(DevHeader *hdr, int64_t nmol, const long long *mol_doff, const int *mol_n,
+                                     const double *dens, double tol, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dchk_reset, dim3(1), dim3(1), 0, st, hdr);
+    hipLaunchKernelGGL(k_dens_check_batched, dim3((unsigned)(nmol < 4096 ? nmol : 4096)), dim3(256), 0, st, nmol,
+                       mol_doff, mol_n, dens, tol, hdr);
     return hipGetLastError();
 }
 
@@ -572,20 +718,21 @@ __global__ void k_fill_i64(long long *__restrict__ p, int64_t m)
     if (i < m) p[i] = 0;
 }
 
-// Blocks of every bra group: kGroupBras x the largest block count of its bras (bras with
+// Blocks of every bra group: 2^gshift x the largest block count of its bras (bras with
 // fewer blocks leave empty slots, skipped by the kernels).
 __global__ void k_group_blocks(const DevHeader *__restrict__ hdr, const long long *__restrict__ nitems,
-                               int64_t ngroups, int tile, long long *__restrict__ gcnt)
+                               int64_t ngroups, int gshift, int tile, long long *__restrict__ gcnt)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ngroups) return;
     const int64_t S = hdr->sig_pairs;
+    const int64_t gb = (int64_t)1 << gshift;
     long long nb = 0;
-    for (int64_t s = g * kGroupBras; s < (g + 1) * kGroupBras && s < S; ++s) {
+    for (int64_t s = g * gb; s < (g + 1) * gb && s < S; ++s) {
         const long long b = (nitems[s] + tile - 1) / tile;
         nb = b > nb ? b : nb;
     }
-    gcnt[g] = nb * kGroupBras;
+    gcnt[g] = nb * gb;
 }
 
 hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
@@ -625,7 +772,8 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
                        (double *)(ws + L.prim), (float *)(ws + L.prim_f), (double *)(ws + L.bra),
                        (float *)(ws + L.bra_f), L.atoms ? (double *)(ws + L.bip) : nullptr,
                        L.atoms ? (float *)(ws + L.bip_f) : nullptr, L.pmu ? (double *)(ws + L.pmu) : nullptr,
-                       L.pmu ? (double *)(ws + L.pfa) : nullptr, L.pmu ? (double *)(ws + L.bmf) : nullptr, slot);
+                       L.pmu ? (double *)(ws + L.pfa) : nullptr, L.bgw ? (double *)(ws + L.bgw) : nullptr,
+                       L.bgw ? (float *)(ws + L.bgw_f) : nullptr, slot);
     hipLaunchKernelGGL(k_pair_pad, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, L.pcap, L.g2,
                        true, L.atoms ? 5 : -1, L.atoms ? 4 : -1,
                        (int *)(ws + L.pk), (int *)(ws + L.pl), (double *)(ws + L.pq), (double *)(ws + L.pd),
@@ -638,7 +786,7 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
                     (long long *)(ws + L.scan_tmp), &hdr->items, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_group_blocks, dim3((unsigned)((L.ngroups + 255) / 256)), dim3(256), 0, st, hdr,
-                       (const long long *)(ws + L.nitems), L.ngroups, L.tile, (long long *)(ws + L.gcnt));
+                       (const long long *)(ws + L.nitems), L.ngroups, L.gshift, L.tile, (long long *)(ws + L.gcnt));
     return launch_scan((const long long *)(ws + L.gcnt), L.ngroups, (long long *)(ws + L.goff),
                        (long long *)(ws + L.scan_tmp), &hdr->blocks, st);
 }

@@ -121,18 +121,39 @@ def test_load_tuning_rejects_missing_and_foreign_files(tmp_path):
     bad.write_text('{"something": 1}')
     with pytest.raises(hfk.HfkError):
         hfk.load_tuning(str(bad))
-    worse = tmp_path / "worse.json"
-    worse.write_text('{"format": "hfk-tuning-1", "entries": [{"precision": 0, "size_class": 1, "strategy": 7, '
-                     '"variant": 1, "gpc": 4}]}')
+    # the previous format, keyed by a size class, is not read
+    old = tmp_path / "old.json"
+    old.write_text('{"format": "hfk-tuning-1", "entries": [{"precision": 0, "size_class": 1, "strategy": 1, '
+                   '"variant": 1, "gpc": 4}]}')
     with pytest.raises(hfk.HfkError):
-        hfk.load_tuning(str(worse))
+        hfk.load_tuning(str(old))
+    entry = ('{"arch": "gfx950", "precision": 0, "size_bucket": 9, "strategy": %d, "variant": 1, "gpc": 4, '
+             '"tile_items": %d, "group_bras": %d, "ket_copies": 0}')
+    for strat, tile, gb in ((7, 4, 1024), (2, 0, 1024), (2, 17, 1024), (2, 4, 1000), (2, 4, 8192)):
+        worse = tmp_path / "worse.json"
+        worse.write_text('{"format": "hfk-tuning-2", "entries": [%s], "batched": []}' % (entry % (strat, tile, gb)))
+        with pytest.raises(hfk.HfkError):
+            hfk.load_tuning(str(worse))
+    for gpc, items, owned, w in ((0, 0, -1, 8), (5, 0, -1, 8), (2, 2000, -1, 8), (2, 0, 0, 8), (2, 0, -5, 8),
+                                 (2, 0, -1, 6)):
+        worse = tmp_path / "worse_b.json"
+        worse.write_text('{"format": "hfk-tuning-2", "entries": [], "batched": [{"arch": "gfx950", "precision": 1, '
+                         '"gpc": %d, "block_items": %d, "owned_bound": %d, "waves": %d}]}' % (gpc, items, owned, w))
+        with pytest.raises(hfk.HfkError):
+            hfk.load_tuning(str(worse))
 
 
 def test_load_tuning_accepts_its_format(tmp_path):
     good = tmp_path / "good.json"
-    good.write_text('{\n  "format": "hfk-tuning-1",\n  "entries": [\n    {"precision": 0, "size_class": 2, '
-                    '"strategy": 1, "variant": 1, "gpc": 4}\n  ],\n  "batched_gpc": 2\n}\n')
+    good.write_text('{\n  "format": "hfk-tuning-2",\n  "entries": [\n'
+                    '    {"arch": "gfx950", "precision": 0, "size_bucket": 9, "strategy": 2, "variant": 1, "gpc": 4, '
+                    '"tile_items": 8, "group_bras": 2048, "ket_copies": 8},\n'
+                    '    {"arch": "gfx942", "precision": 1, "size_bucket": 10, "strategy": 1, "variant": 0, "gpc": 6, '
+                    '"tile_items": 4, "group_bras": 256, "ket_copies": 0}\n  ],\n'
+                    '  "batched": [\n    {"arch": "gfx950", "precision": 1, "gpc": 3, "block_items": 32, '
+                    '"owned_bound": 65536, "waves": 4}\n  ]\n}\n')
     hfk.load_tuning(str(good))
+    hfk.clear_tuning()
 
 
 def test_set_config_validation():
@@ -140,6 +161,66 @@ def test_set_config_validation():
     assert L.hfk_set_config(2, 0) == hfk.HFK_EINVAL
     assert L.hfk_set_config(-1, 9) == hfk.HFK_EINVAL
     assert L.hfk_set_config(-1, 0) == hfk.HFK_OK
+
+
+def test_set_shape_validation():
+    L = hfk.lib()
+    for tile, gb, kc in ((17, 0, -1), (-1, 0, -1), (4, 1000, -1), (4, 128, -1), (4, 8192, -1), (4, 1024, -2),
+                         (4, 1024, 1025)):
+        assert L.hfk_set_shape(tile, gb, kc) == hfk.HFK_EINVAL, (tile, gb, kc)
+    for tile, gb, kc in ((1, 256, 0), (16, 4096, 1024), (8, 512, 8)):
+        assert L.hfk_set_shape(tile, gb, kc) == hfk.HFK_OK
+    assert L.hfk_set_shape(0, 0, -1) == hfk.HFK_OK
+
+
+def test_set_batched_config_validation():
+    L = hfk.lib()
+    for gpc, items, owned, w in ((5, 0, 0, 0), (-1, 0, 0, 0), (2, 1025, 0, 0), (2, -1, 0, 0), (2, 0, -2, 0),
+                                 (2, 0, 0, 2), (2, 0, 0, 16)):
+        assert L.hfk_set_batched_config(gpc, items, owned, w) == hfk.HFK_EINVAL, (gpc, items, owned, w)
+    for gpc, items, owned, w in ((4, 1024, 1 << 18, 8), (1, 8, -1, 4)):
+        assert L.hfk_set_batched_config(gpc, items, owned, w) == hfk.HFK_OK
+    assert L.hfk_set_batched_config(0, 0, 0, 0) == hfk.HFK_OK
+
+
+def test_set_debug_validation():
+    L = hfk.lib()
+    for tol in (-1e-12, float("nan"), float("inf")):
+        assert L.hfk_set_debug(1, tol) == hfk.HFK_EINVAL, tol
+    assert L.hfk_set_debug(1, 0.0) == hfk.HFK_OK
+    assert L.hfk_set_debug(0, 1e-12) == hfk.HFK_OK
+
+
+def test_last_stats_needs_a_build_on_this_thread():
+    """No build call has run on a fresh thread: hfk_last_stats refuses (host check, no HIP call)."""
+    import threading
+    out = {}
+
+    def probe():
+        st = hfk.HfkStats()
+        out["status"] = hfk.lib().hfk_last_stats(ctypes.byref(st))
+        out["null"] = hfk.lib().hfk_last_stats(None)
+
+    t = threading.Thread(target=probe)
+    t.start()
+    t.join()
+    assert out["status"] == hfk.HFK_EINVAL and out["null"] == hfk.HFK_EINVAL
+
+
+def test_batched_pair_limit():
+    """A batch above the pair limit of one call (its ket-table buffer offsets stay below
+    2^31) is refused on the host: 2501 molecules of 128 atoms hold 20.6M pairs, 5000 hold
+    41.3M."""
+    import numpy as np
+    L = hfk.lib()
+    out = ctypes.c_size_t(0)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    ok = np.arange(0, 128 * 2502, 128, dtype=np.int64)
+    assert L.hfk_batched_workspace_bytes(len(ok) - 1, ok.ctypes.data_as(i64p), 6, 0, 1, ctypes.byref(out)) == hfk.HFK_OK
+    big = np.arange(0, 128 * 5001, 128, dtype=np.int64)
+    assert (L.hfk_batched_workspace_bytes(len(big) - 1, big.ctypes.data_as(i64p), 6, 0, 1, ctypes.byref(out))
+            == hfk.HFK_EUNSUPPORTED)
+    assert "pairs" in hfk.lib().hfk_last_error().decode()
 
 
 def test_batched_validation():

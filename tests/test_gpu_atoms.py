@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from he_inputs import mixed_lattice, random_basis_rows, random_cluster, config_system
-from gpu_util import announce, rel, rel_fro
+from gpu_util import announce, assert_close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -48,7 +48,7 @@ def test_atoms_tiny_vs_bruteforce(torch_dev, n, seed, box, tau):
     announce("atoms tiny n=%d seed=%d tau=%g" % (n, seed, tau))
     G, E2, _ = _run(torch_dev, s.xyz, s.dens, e, c, tau)
     Gb, Eb = oracle.fock_bruteforce_atoms(s.xyz, s.dens, e, c, tau)
-    assert rel_fro(G, Gb) < FP64_TOL
+    assert_close(G, Gb, FP64_TOL)
     assert rel(E2, Eb) < FP64_TOL
     assert np.array_equal(G, G.T)
 
@@ -66,7 +66,7 @@ def test_atoms_hhe64_fp64_vs_oracle(torch_dev, hhe64, strategy):
     assert 0 < int(np.sum(s.exps[:, 0] < 5.0)) < s.natoms   # both elements present
     announce("atoms H/He 64 fp64 strategy=%d" % strategy)
     G, E2, st = _run(torch_dev, s.xyz, s.dens, s.exps, s.coefs, s.tau, strategy=strategy)
-    assert rel_fro(G, Gr) < FP64_TOL, rel_fro(G, Gr)
+    assert_close(G, Gr, FP64_TOL)
     assert rel(E2, Er) < FP64_TOL
     assert np.abs(G - Gr).max() < FP64_TOL * np.abs(Gr).max()
     assert abs(st["quartets"] - nr) <= 4
@@ -77,7 +77,7 @@ def test_atoms_hhe64_mixed_vs_oracle(torch_dev, hhe64):
     s, Gr, Er, nr = hhe64
     announce("atoms H/He 64 mixed")
     G, E2, st = _run(torch_dev, s.xyz, s.dens, s.exps, s.coefs, s.tau, precision="mixed")
-    assert rel_fro(G, Gr) < MIXED_TOL, rel_fro(G, Gr)
+    assert_close(G, Gr, MIXED_TOL)
     assert rel(E2, Er) < MIXED_TOL
     assert abs(st["quartets"] - nr) <= 4
 
@@ -92,11 +92,11 @@ def test_atoms_random_contractions(torch_dev, g):
     announce("atoms random contractions g=%d" % g)
     Gr, Er, nr = oracle.fock_atoms(s.xyz, s.dens, e, c, tau)
     G, E2, st = _run(torch_dev, s.xyz, s.dens, e, c, tau)
-    assert rel_fro(G, Gr) < FP64_TOL, rel_fro(G, Gr)
+    assert_close(G, Gr, FP64_TOL)
     assert rel(E2, Er) < FP64_TOL
     assert abs(st["quartets"] - nr) <= 4
     Gm, Em, _ = _run(torch_dev, s.xyz, s.dens, e, c, tau, precision="mixed")
-    assert rel_fro(Gm, Gr) < MIXED_TOL, rel_fro(Gm, Gr)
+    assert_close(Gm, Gr, MIXED_TOL)
     assert rel(Em, Er) < MIXED_TOL
 
 
@@ -108,7 +108,7 @@ def test_atoms_ragged_sizes(torch_dev, n, seed):
     announce("atoms ragged n=%d" % n)
     Gr, Er, _ = oracle.fock_atoms(s.xyz, s.dens, e, c, 1e-9)
     G, E2, _ = _run(torch_dev, s.xyz, s.dens, e, c, 1e-9)
-    assert rel_fro(G, Gr) < FP64_TOL
+    assert_close(G, Gr, FP64_TOL)
     assert rel(E2, Er) < FP64_TOL
 
 
@@ -126,7 +126,7 @@ def test_atoms_identical_rows_match_one_basis_build(torch_dev):
     D = torch.tensor(s.dens, device=dev)
     G1, E1 = hfk.fock(X, D, s.exps, s.coefs, s.tau)
     G1 = G1.cpu().numpy()
-    assert rel_fro(G, G1) < 1e-13
+    assert_close(G, G1, 1e-13)
     assert rel(E2, float(E1.item())) < 1e-13
 
 
@@ -137,7 +137,7 @@ def test_atoms_permutation_equivariance(torch_dev):
     announce("atoms permutation")
     G, E2, _ = _run(torch_dev, s.xyz, s.dens, e, c, 1e-10)
     Gp, Ep, _ = _run(torch_dev, s.xyz[perm], s.dens[np.ix_(perm, perm)], e[perm], c[perm], 1e-10)
-    assert rel_fro(Gp, G[np.ix_(perm, perm)]) < 1e-12
+    assert_close(Gp, G[np.ix_(perm, perm)], 1e-12)
     assert rel(Ep, E2) < 1e-12
 
 
@@ -171,7 +171,7 @@ def test_atoms_hhe512_sampled(torch_dev):
         assert abs(Gm[i, j] - r) <= MIXED_TOL * scale, (i, j)
     assert rel(E2, 0.5 * float(np.sum(s.dens * G))) < 1e-12
     assert rel(Em, E2) < MIXED_TOL
-    assert rel_fro(Gm, G) < MIXED_TOL
+    assert_close(Gm, G, MIXED_TOL)
 
 
 def test_atoms_workspace_too_small_is_rejected(torch_dev):
@@ -206,7 +206,7 @@ def test_atoms_bounds_above_two(torch_dev):
     G, E2, st = _run(torch_dev, s.xyz, s.dens, e, c, s.tau)
     Gr, Er, nr = oracle.fock_atoms(s.xyz, s.dens, e, c, s.tau)
     assert st["quartets"] == nr
-    assert rel_fro(G, Gr) < FP64_TOL, rel_fro(G, Gr)
+    assert_close(G, Gr, FP64_TOL)
     assert rel(E2, Er) < FP64_TOL
 
 
@@ -234,7 +234,7 @@ def test_atoms_grad_vs_oracle(torch_dev, g):
     announce("atoms grad g=%d" % g)
     dx, dd, E2g, G = _grad_atoms(torch_dev, s.xyz, s.dens, e, c, tau)
     gr, Er, _ = oracle.grad_atoms(s.xyz, s.dens, e, c, tau)
-    assert rel_fro(dx, gr) < FP64_TOL, rel_fro(dx, gr)
+    assert_close(dx, gr, FP64_TOL)
     assert rel(E2g, Er) < FP64_TOL
     assert np.array_equal(dd, G)
 
@@ -245,10 +245,10 @@ def test_atoms_grad_hhe128(torch_dev):
     announce("atoms grad H/He 128 fp64 + mixed")
     gr, Er, _ = oracle.grad_atoms(s.xyz, s.dens, s.exps, s.coefs, s.tau)
     dx, _, E2g, _ = _grad_atoms(torch_dev, s.xyz, s.dens, s.exps, s.coefs, s.tau)
-    assert rel_fro(dx, gr) < FP64_TOL, rel_fro(dx, gr)
+    assert_close(dx, gr, FP64_TOL)
     assert rel(E2g, Er) < FP64_TOL
     dm, _, Em, _ = _grad_atoms(torch_dev, s.xyz, s.dens, s.exps, s.coefs, s.tau, precision="mixed")
-    assert rel_fro(dm, gr) < MIXED_TOL, rel_fro(dm, gr)
+    assert_close(dm, gr, MIXED_TOL)
     assert rel(Em, Er) < MIXED_TOL
 
 
@@ -266,8 +266,8 @@ def test_atoms_vjp_through_G(torch_dev, n, seed, ge2):
     gx = oracle.grad_pair_atoms(s.xyz, s.dens, W + 0.5 * ge2 * s.dens, e, c, tau)
     G = oracle.fock_atoms(s.xyz, s.dens, e, c, tau)[0]
     GW = oracle.fock_atoms(s.xyz, W, e, c, tau)[0]
-    assert rel_fro(dx, gx) < FP64_TOL, rel_fro(dx, gx)
-    assert rel_fro(dd, ge2 * G + GW) < FP64_TOL
+    assert_close(dx, gx, FP64_TOL)
+    assert_close(dd, ge2 * G + GW, FP64_TOL)
 
 
 def test_atoms_gradcheck(torch_dev):

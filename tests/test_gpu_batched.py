@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 from he_inputs import cluster_batch, pack_batch, random_cluster
-from gpu_util import announce, rel, rel_fro
+from gpu_util import announce, assert_close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +53,7 @@ def test_small_batch_vs_oracle(torch_dev, precision, tol):
         Fm, gm = _mol(off, F, g, m, n)
         Fr, Er, _ = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
         gr, _, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
-        assert rel_fro(Fm, Fr) < tol, (m, n, rel_fro(Fm, Fr))
+        assert_close(Fm, Fr, tol, str((m, n)))
         assert rel(E2[m], Er) < tol, (m, n)
         # a one-atom molecule has zero gradient (translation invariance): absolute floor
         assert np.linalg.norm(gm - gr) <= tol * max(np.linalg.norm(gr), 1e-6), (m, n)
@@ -84,9 +84,9 @@ def test_cluster_batch_2000_sampled(torch_dev):
         Fm, gm = _mol(off, F, g, m, n)
         Fr, Er, _ = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
         gr, _, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
-        assert rel_fro(Fm, Fr) < MIXED_TOL, (m, n)
+        assert_close(Fm, Fr, MIXED_TOL, str((m, n)))
         assert rel(E2[m], Er) < MIXED_TOL, (m, n)
-        assert rel_fro(gm, gr) < MIXED_TOL, (m, n)
+        assert_close(gm, gr, MIXED_TOL, str((m, n)))
     # properties over the whole batch: finite results, zero net force per molecule
     assert np.isfinite(F).all() and np.isfinite(E2).all() and np.isfinite(g).all()
     for m in range(len(systems)):
@@ -107,7 +107,7 @@ def test_six_primitive_batch(torch_dev):
             Fm, gm = _mol(off, F, g, m, s.natoms)
             Fr, Er, _ = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
             gr, _, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
-            assert rel_fro(Fm, Fr) < tol, (precision, m)
+            assert_close(Fm, Fr, tol, str((precision, m)))
             assert rel(E2[m], Er) < tol, (precision, m)
             assert np.linalg.norm(gm - gr) <= tol * max(np.linalg.norm(gr), 1e-6), (precision, m)
 
@@ -127,7 +127,7 @@ def test_batch_with_bounds_above_two(torch_dev):
         Fm, gm = _mol(off, F, g, m, s.natoms)
         Fr, Er, _ = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
         gr, _, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
-        assert rel_fro(Fm, Fr) < FP64_TOL, (m, rel_fro(Fm, Fr))
+        assert_close(Fm, Fr, FP64_TOL, str(m))
         assert rel(E2[m], Er) < FP64_TOL, m
         assert np.linalg.norm(gm - gr) <= FP64_TOL * max(np.linalg.norm(gr), 1e-6), m
 
@@ -162,7 +162,7 @@ def test_small_batch_atoms_vs_oracle(torch_dev, precision, tol):
         Fm, gm = _mol(off, F, g, m, n)
         Fr, Er, _ = oracle.fock_atoms(s.xyz, s.dens, e[a0:a1], c[a0:a1], s.tau)
         gr, _, _ = oracle.grad_atoms(s.xyz, s.dens, e[a0:a1], c[a0:a1], s.tau)
-        assert rel_fro(Fm, Fr) < tol, (m, n, rel_fro(Fm, Fr))
+        assert_close(Fm, Fr, tol, str((m, n)))
         assert rel(E2[m], Er) < tol, (m, n)
         assert np.linalg.norm(gm - gr) <= tol * max(np.linalg.norm(gr), 1e-6), (m, n)
 
@@ -200,9 +200,9 @@ def test_hhe_cluster_batch_sampled(torch_dev):
         Fm, gm = _mol(off, F, g, m, s.natoms)
         Fr, Er, _ = oracle.fock_atoms(s.xyz, s.dens, e[a0:a1], c[a0:a1], s.tau)
         gr, _, _ = oracle.grad_atoms(s.xyz, s.dens, e[a0:a1], c[a0:a1], s.tau)
-        assert rel_fro(Fm, Fr) < MIXED_TOL, (m, s.natoms)
+        assert_close(Fm, Fr, MIXED_TOL, str((m, s.natoms)))
         assert rel(E2[m], Er) < MIXED_TOL, m
-        assert rel_fro(gm, gr) < MIXED_TOL, m
+        assert_close(gm, gr, MIXED_TOL, str(m))
     assert np.isfinite(F).all() and np.isfinite(E2).all() and np.isfinite(g).all()
     for m in range(len(systems)):
         gm = g[off[m]:off[m + 1]]

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from he_inputs import config_system, random_cluster
-from gpu_util import announce, load_golden, rel, rel_fro
+from gpu_util import announce, assert_close, load_golden, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +38,7 @@ def test_grad_vs_oracle(torch_dev, n, seed, box, tau):
     announce("grad n=%d seed=%d tau=%g" % (n, seed, tau))
     g, dD, E2g, G, E2 = _grad(torch_dev, s)
     gr, Er, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, tau)
-    assert rel_fro(g, gr) < FP64_TOL, rel_fro(g, gr)
+    assert_close(g, gr, FP64_TOL)
     assert rel(E2g, Er) < FP64_TOL
     assert rel(E2, Er) < FP64_TOL
     assert np.abs(dD - G).max() == 0.0        # g_e2 = 1: dE2/dD is G itself
@@ -50,7 +50,7 @@ def test_he128_grad_vs_oracle(torch_dev):
     announce("he128 grad fp64")
     g, _, E2g, _, E2 = _grad(torch_dev, s)
     gr, Er, _ = load_golden("he128_grad")
-    assert rel_fro(g, gr) < FP64_TOL, rel_fro(g, gr)
+    assert_close(g, gr, FP64_TOL)
     assert rel(E2g, Er) < FP64_TOL
     assert rel(E2, Er) < FP64_TOL
 
@@ -60,7 +60,7 @@ def test_he128_grad_mixed(torch_dev):
     announce("he128 grad mixed")
     g, _, E2g, _, _ = _grad(torch_dev, s, precision="mixed")
     gr, Er, _ = load_golden("he128_grad")
-    assert rel_fro(g, gr) < MIXED_TOL, rel_fro(g, gr)
+    assert_close(g, gr, MIXED_TOL)
     assert rel(E2g, Er) < MIXED_TOL
 
 
@@ -94,7 +94,7 @@ def test_autograd_function(torch_dev):
     G, E2 = hfk.FockEnergy.apply(xyz, D, s.exps, s.coefs, s.tau, "fp64")
     (3.0 * E2.sum()).backward()
     gr, _, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
-    assert rel_fro(xyz.grad.cpu().numpy(), 3.0 * gr) < FP64_TOL
+    assert_close(xyz.grad.cpu().numpy(), 3.0 * gr, FP64_TOL)
     assert np.abs(D.grad.cpu().numpy() - 3.0 * G.detach().cpu().numpy()).max() < 1e-13 * np.abs(G.detach().cpu().numpy()).max()
 
 
@@ -123,8 +123,8 @@ def test_fock_output_vjp_vs_oracle(torch_dev, n, seed, box, tau, ge2):
     d_xyz, d_dens, _ = hfk.fock_grad(xyz, D, s.exps, s.coefs, s.tau, g_e2=g_e2, fock_in=G,
                                      g_fock=torch.tensor(GF, device=dev))
     gx, gd = _vjp_reference(s, GF, ge2)
-    assert rel_fro(d_xyz.cpu().numpy(), gx) < FP64_TOL, rel_fro(d_xyz.cpu().numpy(), gx)
-    assert rel_fro(d_dens.cpu().numpy(), gd) < FP64_TOL, rel_fro(d_dens.cpu().numpy(), gd)
+    assert_close(d_xyz.cpu().numpy(), gx, FP64_TOL)
+    assert_close(d_dens.cpu().numpy(), gd, FP64_TOL)
 
 
 def test_fock_output_vjp_mixed(torch_dev):
@@ -140,8 +140,8 @@ def test_fock_output_vjp_mixed(torch_dev):
     d_xyz, d_dens, _ = hfk.fock_grad(xyz, D, s.exps, s.coefs, s.tau, precision="mixed", g_e2=g_e2, fock_in=G,
                                      g_fock=torch.tensor(GF, device=dev))
     gx, gd = _vjp_reference(s, GF, 0.5)
-    assert rel_fro(d_xyz.cpu().numpy(), gx) < MIXED_TOL
-    assert rel_fro(d_dens.cpu().numpy(), gd) < MIXED_TOL
+    assert_close(d_xyz.cpu().numpy(), gx, MIXED_TOL)
+    assert_close(d_dens.cpu().numpy(), gd, MIXED_TOL)
 
 
 def test_autograd_through_both_outputs(torch_dev):
@@ -156,8 +156,8 @@ def test_autograd_through_both_outputs(torch_dev):
     G, E2 = hfk.FockEnergy.apply(xyz, D, s.exps, s.coefs, s.tau, "fp64")
     ((G * torch.tensor(M, device=dev)).sum() + 2.5 * E2.sum()).backward()
     gx, gd = _vjp_reference(s, M, 2.5)
-    assert rel_fro(xyz.grad.cpu().numpy(), gx) < FP64_TOL
-    assert rel_fro(D.grad.cpu().numpy(), gd) < FP64_TOL
+    assert_close(xyz.grad.cpu().numpy(), gx, FP64_TOL)
+    assert_close(D.grad.cpu().numpy(), gd, FP64_TOL)
 
 
 def test_gradcheck_small(torch_dev):
@@ -188,7 +188,7 @@ def test_grad_other_basis_sizes(torch_dev, exps, coefs):
     announce("grad ngauss=%d" % len(exps))
     g, _, E2g, _, _ = _grad(torch_dev, s)
     gr, Er, _ = oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau)
-    assert rel_fro(g, gr) < FP64_TOL
+    assert_close(g, gr, FP64_TOL)
     assert rel(E2g, Er) < FP64_TOL
 
 

@@ -1,6 +1,7 @@
 """Performance gate of the headline workload: the 512-atom FP64 build, tuned, must keep at
-least 45% of the FP64 vector peak in nominal flops (2,525 per kept quartet) in its quartet
-kernel.  The measured figure is about 53%; the margin covers box-to-box spread."""
+least 50% of the FP64 vector peak in nominal flops (2,525 per kept quartet) in its quartet
+kernel, the target the build is held to.  Measured: 52-55% across boxes (the shader clock
+under load varies by about 8% between them)."""
 import pytest
 
 from he_inputs import config_system
@@ -35,4 +36,4 @@ def test_he512_fp64_peak_fraction():
     q = hfk.read_stats(ws)["quartets"]
     frac = q * FLOP_PER_QUARTET / (kms / launches * 1e-3) / (FP64_PEAK_TFLOPS * 1e12)
     print("he512 fp64 nominal peak fraction %.3f" % frac)
-    assert frac >= 0.45, frac
+    assert frac >= 0.50, frac

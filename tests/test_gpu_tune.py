@@ -1,45 +1,187 @@
-"""The autotuners run, keep a valid choice and round-trip their cache file."""
+"""The autotuners: every candidate they may pick gives the oracle's result, the tuned choice is
+never slower than the untuned default on the timed system, and the cache file round-trips."""
 import json
 
 import numpy as np
 import pytest
 
-from he_inputs import cluster_batch, config_system, pack_batch
-from gpu_util import announce, rel
+import oracle
+from he_inputs import cluster_batch, config_system, pack_batch, random_cluster
+from gpu_util import announce, assert_close, rel
 
 pytestmark = pytest.mark.gpu
 
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-6
 
-def test_tune_single_molecule(tmp_path):
+
+@pytest.fixture(scope="module")
+def torch_dev():
     import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda:0")
+
+
+def test_every_single_molecule_candidate_matches_the_oracle(torch_dev):
+    """Each value of each tuned dimension (strategy, variant, workgroups per CU, items per
+    block, bras per group, ket-vector copies) on a ragged 150-atom cluster, FP64 and mixed."""
     import paper_2509_21039_amd as hfk
-    dev = torch.device("cuda:0")
-    s = config_system("he64_fp64")
+    torch, dev = torch_dev
+    s = random_cluster(150, 91, box=14.0, tau=1e-10)
+    Gr, Er, nr = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
     xyz = torch.tensor(s.xyz, device=dev)
     D = torch.tensor(s.dens, device=dev)
-    announce("tune he64")
+    cands = [dict(strategy=st) for st in (1, 2)] + [dict(variant=v) for v in (0, 1)] + \
+            [dict(gpc=g) for g in (1, 3, 6)] + [dict(tile=t) for t in (1, 2, 8, 16)] + \
+            [dict(gbras=b) for b in (256, 512, 2048, 4096)] + [dict(kcopies=k) for k in (0, 1, 8, 32)]
+    try:
+        for c in cands:
+            hfk.set_config(c.get("variant", -1), c.get("gpc", 0))
+            hfk.set_shape(c.get("tile", 0), c.get("gbras", 0), c.get("kcopies", -1))
+            for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+                announce("candidate %s %s" % (c, precision))
+                ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, 3, precision), dev)
+                G, E2 = hfk.fock(xyz, D, s.exps, s.coefs, s.tau, precision=precision,
+                                 strategy=c.get("strategy", 0), workspace=ws)
+                st = hfk.read_stats(ws)
+                assert st["quartets"] == nr, c
+                assert_close(G.cpu().numpy(), Gr, tol, str(c))
+                assert rel(E2.item(), Er) < tol, c
+    finally:
+        hfk.set_config(-1, 0)
+        hfk.set_shape(0, 0, -1)
+
+
+def _time_builds(hfk, torch, xyz, D, s, reps=5):
+    ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, 3, "fp64"), xyz.device)
+    hfk.fock(xyz, D, s.exps, s.coefs, s.tau, workspace=ws)
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        hfk.fock(xyz, D, s.exps, s.coefs, s.tau, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def test_tune_single_molecule_not_slower_and_round_trips(torch_dev, tmp_path):
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    s = config_system("he128_grad")
+    xyz = torch.tensor(s.xyz, device=dev)
+    D = torch.tensor(s.dens, device=dev)
+    hfk.clear_tuning()
+    announce("tune he128: default timing")
+    t_default = _time_builds(hfk, torch, xyz, D, s)
     G0, E0 = hfk.fock(xyz, D, s.exps, s.coefs, s.tau)
     path = str(tmp_path / "tune.json")
+    announce("tune he128: tuner")
     best = hfk.tune(xyz, D, s.exps, s.coefs, s.tau, cache_path=path)
     assert best in (hfk.STRATEGY_PRIVATE, hfk.STRATEGY_ATOMIC)
+    t_tuned = _time_builds(hfk, torch, xyz, D, s)
+    print("he128 default %.3f ms, tuned %.3f ms" % (t_default, t_tuned))
+    assert t_tuned <= 1.05 * t_default, (t_tuned, t_default)
     table = json.load(open(path))
-    assert table["format"] == "hfk-tuning-1" and len(table["entries"]) >= 1
+    assert table["format"] == "hfk-tuning-2"
+    e = [x for x in table["entries"] if x["precision"] == 0 and x["size_bucket"] == 7]
+    assert len(e) == 1 and e[0]["arch"].startswith("gfx")
+    # the table read back gives the same choice, and the same result
+    hfk.clear_tuning()
     hfk.load_tuning(path)
-    G1, E1 = hfk.fock(xyz, D, s.exps, s.coefs, s.tau)
+    ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, 3, "fp64"), dev)
+    G1, E1 = hfk.fock(xyz, D, s.exps, s.coefs, s.tau, workspace=ws)
+    st = hfk.read_stats(ws)
+    assert (st["strategy"], st["tile_items"], st["group_bras"]) == (e[0]["strategy"], e[0]["tile_items"],
+                                                                     e[0]["group_bras"])
     assert rel(E1.item(), E0.item()) < 1e-12
+    hfk.clear_tuning()
 
 
-def test_tune_batched(tmp_path):
-    import torch
-    import paper_2509_21039_amd as hfk
-    dev = torch.device("cuda:0")
-    systems = cluster_batch(nmol=60, seed=9)
+def _batch_run(hfk, torch, dev, systems, precision, with_grad=True):
     off, xyz, dens = pack_batch(systems)
     X = torch.tensor(xyz, device=dev)
     Dp = torch.tensor(dens, device=dev)
-    announce("tune batched 60")
-    gpc = hfk.tune_batched(off, X, Dp, systems[0].exps, systems[0].coefs, systems[0].tau,
-                           cache_path=str(tmp_path / "tb.json"))
-    assert 1 <= gpc <= 3
-    F, E2, g = hfk.fock_batched(off, X, Dp, systems[0].exps, systems[0].coefs, systems[0].tau)
+    F, E2, g = hfk.fock_batched(off, X, Dp, systems[0].exps, systems[0].coefs, systems[0].tau,
+                                precision=precision, with_grad=with_grad)
+    torch.cuda.synchronize()
+    return off, F.cpu().numpy(), E2.cpu().numpy(), (g.cpu().numpy() if with_grad else None)
+
+
+def test_every_batched_candidate_matches_the_oracle(torch_dev):
+    """Each value of each tuned batched dimension (workgroups per CU, items per block, owned
+    molecules up to a work bound) on a ragged batch, mixed + gradient and FP64 + gradient."""
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    sizes = [1, 30, 5, 17, 3, 40, 9, 2, 24, 12, 60, 7, 33]
+    systems = [random_cluster(n, 500 + i, box=1.2 * n ** (1 / 3) * 2.0, tau=1e-10) for i, n in enumerate(sizes)]
+    refs = [(oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau), oracle.grad(s.xyz, s.dens, s.exps, s.coefs, s.tau))
+            for s in systems]
+    cands = [dict(gpc=g) for g in (1, 2, 3, 4)] + [dict(items=b) for b in (1, 8, 16, 64, 128)] + \
+            [dict(owned=o) for o in (-1, 1 << 10, 1 << 14, 1 << 16, 1 << 18, 1 << 40)] + \
+            [dict(waves=w) for w in (4, 8)] + [dict(waves=4, owned=1 << 14, items=8)]
+    try:
+        for c in cands:
+            hfk.set_batched_config(c.get("gpc", 0), c.get("items", 0), c.get("owned", 0), c.get("waves", 0))
+            for precision, tol in (("mixed", MIXED_TOL), ("fp64", FP64_TOL)):
+                announce("batched candidate %s %s" % (c, precision))
+                off, F, E2, g = _batch_run(hfk, torch, dev, systems, precision)
+                d0 = 0
+                for m, s in enumerate(systems):
+                    n = s.natoms
+                    (Fr, Er, _), (gr, _, _) = refs[m]
+                    assert_close(F[d0:d0 + n * n].reshape(n, n), Fr, tol, "%s m=%d" % (c, m))
+                    assert rel(E2[m], Er) < tol, (c, m)
+                    gm = g[off[m]:off[m + 1]]
+                    assert np.linalg.norm(gm - gr) <= tol * max(np.linalg.norm(gr), 1e-6), (c, m)
+                    d0 += n * n
+    finally:
+        hfk.set_batched_config(0, 0, 0, 0)
+
+
+def test_tune_batched_not_slower_and_round_trips(torch_dev, tmp_path):
+    import paper_2509_21039_amd as hfk
+    torch, dev = torch_dev
+    systems = cluster_batch(nmol=300, seed=9)
+    off, xyz, dens = pack_batch(systems)
+    X = torch.tensor(xyz, device=dev)
+    Dp = torch.tensor(dens, device=dev)
+    s0 = systems[0]
+    hfk.clear_tuning()
+
+    def timed():
+        ws = hfk.new_workspace(hfk.batched_workspace_bytes(off, 3, "mixed", True), dev)
+        g = torch.empty_like(X)
+        best = 1e30
+        for r in range(4):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            hfk.fock_batched(off, X, Dp, s0.exps, s0.coefs, s0.tau, precision="mixed", with_grad=True, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                best = min(best, e0.elapsed_time(e1))
+        del g
+        return best
+
+    announce("tune batched 300: default timing")
+    t_default = timed()
+    path = str(tmp_path / "tb.json")
+    announce("tune batched 300: tuner")
+    gpc = hfk.tune_batched(off, X, Dp, s0.exps, s0.coefs, s0.tau, cache_path=path)
+    assert 1 <= gpc <= 4
+    t_tuned = timed()
+    print("batched 300 default %.3f ms, tuned %.3f ms" % (t_default, t_tuned))
+    assert t_tuned <= 1.05 * t_default, (t_tuned, t_default)
+    table = json.load(open(path))
+    assert table["format"] == "hfk-tuning-2" and len(table["batched"]) == 1
+    assert table["batched"][0]["gpc"] == gpc
+    hfk.clear_tuning()
+    hfk.load_tuning(path)
+    F, E2, g = hfk.fock_batched(off, X, Dp, s0.exps, s0.coefs, s0.tau)
     assert np.isfinite(E2.cpu().numpy()).all()
+    hfk.clear_tuning()

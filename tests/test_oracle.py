@@ -415,17 +415,22 @@ def test_config_he64_matches_fixture(oracle_lib):
 
 
 def test_he512_fixture_elements_match_element_definition(oracle_lib):
-    """Sampled entries of the stored 512-atom build (written by the unique-quartet oracle)
-    against the element-wise plain definition, a separate code path."""
+    """Entries of the stored 512-atom build (written by the unique-quartet oracle) against
+    the element-wise plain definition, a separate code path; the stored matrix is symmetric
+    and its energy is 1/2 sum D o G."""
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "he512_fp64_sample.txt")
-    rows = np.loadtxt(path)
+    from gpu_util import load_full
+    G, e2, _ = load_full("he512_fp64")
     s = config_system("he512_fp64")
+    assert G.shape == (512, 512) and np.array_equal(G, G.T)
+    assert 0.5 * float(np.sum(s.dens * G)) == pytest.approx(e2, rel=1e-13)
     Q = oracle_lib.schwarz(s.xyz, E3, C3)
-    scale = np.abs(rows[:, 2]).max()
-    for i, j, v in rows[:8]:
-        e = oracle_lib.fock_element(s.xyz, s.dens, E3, C3, s.tau, Q, int(i), int(j))
-        assert abs(e - v) <= 1e-12 * scale, (i, j)
+    scale = np.abs(G).max()
+    rng = np.random.default_rng(5120)
+    idx = [(0, 0), (511, 0), (511, 511)] + [tuple(int(v) for v in p) for p in rng.integers(0, 512, (5, 2))]
+    for i, j in idx:
+        e = oracle_lib.fock_element(s.xyz, s.dens, E3, C3, s.tau, Q, i, j)
+        assert abs(e - G[i, j]) <= 1e-12 * scale, (i, j)
 
 
 # ------------------------------------------------------------------ per-atom bases
