@@ -203,7 +203,7 @@ def time_grad(hfk, torch, s, steps, warmup, precision="fp64"):
     ws = hfk.new_workspace(nb, dev)
     g_e2 = torch.ones((1,), dtype=torch.float64, device=dev)
     build = hfk.fock_atoms if atoms else hfk.fock
-    grad = hfk.fock_grad_atoms if atoms else hfk.fock_grad
+    grad = hfk.fock_grad
     out = {}
 
     def step(prof):
@@ -473,7 +473,9 @@ def main():
                    "natoms": s.natoms, "ngauss": g, "tau": s.tau, "quartets": q,
                    "primitive_quartets": q * g ** 4, "sig_pairs": r["stats"]["sig_pairs"],
                    "kernel_variant": r["stats"]["variant"], "accumulation": r["stats"]["strategy"],
-                   "workgroups": r["stats"]["groups"], "parallelism": "single GPU"},
+                   "workgroups": r["stats"]["groups"], "tile_items": r["stats"]["tile_items"],
+                   "group_bras": r["stats"]["group_bras"], "ket_copies": r["stats"]["ket_copies"],
+                   "parallelism": "single GPU"},
         "pct_fp64_valu_peak_nominal": 100.0 * achieved / FP64_VALU_PEAK_TFLOPS,
         "step_ms": r["step_ms"],
         "sclk_mhz_sampled": r["sclk_mhz"],

@@ -374,8 +374,8 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
         const int m = x % kBoysStride;
         double sc = sqrt(kBoysH);
         for (int e = 0; e < m; ++e) sc *= kBoysH;
-        tH[x] = (R)(a.tabH[x] * sc);
-        tG[x] = (R)(a.tabG[x] * sc * kBoysH);
+        tH[x] = (R)(a.tabH[x] * sc * (double)GradScale<R>::kE);
+        tG[x] = (R)(a.tabG[x] * sc * kBoysH * (double)GradScale<R>::kW);
     }
     unsigned long long kept = 0;
     __shared__ long long blk_at;
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
                         // T' = T / h on the table grid; sqrt(h) H and h^(3/2) g, or their far
                         // forms T'^(-1/2) and -T'^(-3/2)
                         const R Ts = r2 * q1;
-                        const R y = rsqrt_r(Ts);
+                        const R y = GradScale<R>::e_far(Ts);
                         const R Tc = fmin(Ts, R(kBoysGrid - 4));
                         const R kd = rint(Tc);
                         const R dd = Tc - kd;
@@ -563,12 +563,12 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
                             R vg = cg[6];
 #pragma unroll
                             for (int m = 5; m >= 0; --m) vg = vg * dd + cg[m];
-                            W = q3 * (near ? vg : -(y * y * y));
+                            W = q3 * (near ? vg : GradScale<R>::w_far(y));
                         }
                     } else {
-                        const R y = rsqrt_r(r2);
+                        const R y = GradScale<R>::e_far(r2);
                         E = y;
-                        if (kGrad) W = -(y * y * y);
+                        if (kGrad) W = GradScale<R>::w_far(y);
                     }
                     U = fma(ks[d], E, U);
                     if (kGrad) {
@@ -593,6 +593,15 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
                     wCB = fma(b[6], Xc, wCB);
                     wCD = fma(b[3], Xcd, wCD);
                 }
+            }
+        }
+        {
+            // back from the accumulators' scales (E times kE, W times kW)
+            constexpr R iE = R(1) / GradScale<R>::kE, iW = R(1) / GradScale<R>::kW;
+            eri *= iE;
+            if (kGrad) {
+                sX *= iE; sZ *= iE;
+                wA *= iW; wAB *= iW; wB *= iW; wBB *= iW; wAD *= iW; wBD *= iW; wC *= iW; wCB *= iW; wCD *= iW;
             }
         }
         if (valid) {

@@ -75,6 +75,27 @@ __device__ inline float rsqrt_fp32(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double rsqrt_r(double x) { return rsqrt_fp64(x); }
 __device__ inline float rsqrt_r(float x) { return rsqrt_fp32(x); }
 
+// Far field of the gradient kernels: E(r) = 1/r and W(r) = E'(r)/r = -1/r^3 from x = r^2,
+// scaled for the kernels' accumulators.  FP64: the estimate y of x^(-1/2) takes one Newton
+// step folded into the product, e = y (x y^2 - 3) = -2 y1 (error ~1.5 (5e-8)^2), so E is carried
+// times kE = -2 and W = e^3 = -8 y1^3 times kW = 8; the near-branch tables are scaled to match
+// and the sums scaled back once per quartet.  FP32 has no Newton step: E = y, W = -y^3.
+template <typename R> struct GradScale;
+template <> struct GradScale<double> {
+    static constexpr double kE = -2.0, kW = 8.0;
+    static __device__ double e_far(double x)
+    {
+        const double y = __builtin_amdgcn_rsq(x);
+        return y * fma(x, y * y, -3.0);
+    }
+    static __device__ double w_far(double e) { return e * e * e; }
+};
+template <> struct GradScale<float> {
+    static constexpr float kE = 1.0f, kW = 1.0f;
+    static __device__ float e_far(float x) { return rsqrt_fp32(x); }
+    static __device__ float w_far(float e) { return -(e * e * e); }
+};
+
 // Wave-uniform tables read through the constant address space are fetched with scalar
 // loads (they are never written while a kernel runs).
 template <typename T> using cptr = const __attribute__((address_space(4))) T *;

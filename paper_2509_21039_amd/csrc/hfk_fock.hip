@@ -80,12 +80,14 @@ template <> struct Prec<double> {
     static __device__ const double *rs(const BasisDev *bd) { return bd->rs; }
     static __device__ const double *rsn(const BasisDev *bd) { return bd->rsn; }
     static __device__ double rsqrt(double x) { return rsqrt_fp64(x); }
-    // acc + s / sqrt(x): hardware estimate y, one Newton step folded into the product
+    // The hybrid kernel's FP64 accumulator carries -2 times the sum, which lets the Newton
+    // step of the reciprocal square root fold into the product: with the hardware estimate
+    // y, y1 = y (3 - x y^2) / 2 and -2 s y1 = (s y) (x y^2 - 3): four operations after rsq.
+    static constexpr double kAccScale = -2.0;
     static __device__ double far_acc(double acc, double s, double x)
     {
         const double y = __builtin_amdgcn_rsq(x);
-        const double e = fma(-x * y, y, 1.0);
-        return fma(s * y, fma(e, 0.5, 1.0), acc);
+        return fma(s * y, fma(x, y * y, -3.0), acc);
     }
 };
 template <> struct Prec<float> {
@@ -99,6 +101,7 @@ template <> struct Prec<float> {
     static __device__ const float *rs(const BasisDev *bd) { return bd->rs_f; }
     static __device__ const float *rsn(const BasisDev *bd) { return bd->rsn_f; }
     static __device__ float rsqrt(float x) { return rsqrt_fp32(x); }
+    static constexpr float kAccScale = 1.0f;   // no Newton step in FP32
     static __device__ float far_acc(float acc, float s, float x) { return fmaf(s, rsqrt_fp32(x), acc); }
 };
 
@@ -170,18 +173,19 @@ __device__ inline R quartet_eri_direct(const R *__restrict__ lbra, const R *__re
     return eri;
 }
 
-// sqrt(h) H(T) from T' = T / h, the argument on the table grid (rows at integers): the
-// Taylor row nearest T' with coefficients pre-multiplied by h^m sqrt(h) where the lane
-// is near, T'^(-1/2) where it is not (T = 0 is always near, so needs no guard).
+// kAccScale sqrt(h) H(T) from T' = T / h, the argument on the table grid (rows at
+// integers): the Taylor row nearest T' with coefficients pre-multiplied by
+// kAccScale h^m sqrt(h) where the lane is near, kAccScale T'^(-1/2) where it is not (T = 0
+// is always near, so needs no guard).
 template <typename R>
 __device__ inline R boys_grid(R Ts, bool near, const R *__restrict__ tab)
 {
-    // one Newton step in FP64, y (1 + e/2) with e = 1 - Ts y^2 (error ~1.5 e^2 ~ 4e-15)
+    // one Newton step in FP64 (error ~1.5 e^2 ~ 4e-15 for the estimate's e ~ 5e-8):
+    // -2 y1 = y (Ts y^2 - 3)
     R far;
     if constexpr (sizeof(R) == 8) {
         const double y = __builtin_amdgcn_rsq(Ts);
-        const double e = fma(-Ts * y, y, 1.0);
-        far = fma(y * e, 0.5, y);
+        far = y * fma(Ts, y * y, -3.0);
     } else {
         far = Prec<R>::rsqrt(Ts);
     }
@@ -210,7 +214,9 @@ __device__ inline R boys_grid(R Ts, bool near, const R *__restrict__ tab)
 // primitive quartet, (switch radius^2, rho/h, sqrt(rho/h)).
 // FP64 forms |P-Q|^2 as |P|^2 + |Q|^2 - 2 P.Q (4 operations; with centroid-centred
 // coordinates the cancellation stays near 1e-13 bohr^2 absolute); FP32 subtracts the
-// centres directly, which its precision needs.
+// centres directly, which its precision needs.  The FP64 accumulator holds -2 times the sum
+// (kAccScale; the near-branch table is scaled to match), which saves one operation in each
+// Newton step of the reciprocal square root; the result is scaled back once per quartet.
 // Per-atom bases (kAtoms): rho = p q / (p + q) differs per quartet, so the scalar combo
 // table gives way to kTswitch / p of the bra (uniform, bip) and of the ket (last ket
 // component): their sum is kTswitch / rho, the switch radius^2 itself, so the test costs
@@ -299,7 +305,7 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
             eri += b[3] * acc;
         }
     }
-    return eri;
+    return eri * (R(1) / Prec<R>::kAccScale);
 }
 
 // LDS carve-up of the quartet kernel (bytes, 16-byte aligned pieces).
@@ -350,10 +356,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
 
     const R *gtab = Prec<R>::boys(a);
     if (kSplit) {
-        // grid-scaled rows: coefficient m times h^m sqrt(h)
+        // grid-scaled rows: coefficient m times h^m sqrt(h), and the accumulator's scale
         for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) {
             const int m = x % kBoysStride;
-            double sc = sqrt(kBoysH);
+            double sc = sqrt(kBoysH) * (double)Prec<R>::kAccScale;
             for (int e = 0; e < m; ++e) sc *= kBoysH;
             tab[x] = (R)(a.boys[x] * sc);   // from the FP64 rows: one rounding for FP32
         }

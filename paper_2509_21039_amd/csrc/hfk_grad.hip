@@ -117,8 +117,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
         const int m = x % kBoysStride;
         double sc = sqrt(kBoysH);
         for (int e = 0; e < m; ++e) sc *= kBoysH;
-        tH[x] = (R)(a.tabH[x] * sc);
-        tG[x] = (R)(a.tabG[x] * sc * kBoysH);
+        tH[x] = (R)(a.tabH[x] * sc * (double)GradScale<R>::kE);
+        tG[x] = (R)(a.tabG[x] * sc * kBoysH * (double)GradScale<R>::kW);
     }
     __syncthreads();
 
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                                 // T' = T / h on the table grid; sqrt(h) H and h^(3/2) g, or their
                                 // far forms T'^(-1/2) and -T'^(-3/2)
                                 const R Ts = r2 * q1;
-                                const R y = GPrec<R>::rsqrt(Ts);
+                                const R y = GradScale<R>::e_far(Ts);
                                 const R Tc = fmin(Ts, R(kBoysGrid - 4));
                                 const R kd = rint(Tc);
                                 const R dd = Tc - kd;
@@ -298,11 +298,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                                     vg = vg * dd + cg[m];
                                 }
                                 E = q2 * (near ? vh : y);
-                                W = q3 * (near ? vg : -(y * y * y));
+                                W = q3 * (near ? vg : GradScale<R>::w_far(y));
                             } else {
-                                const R y = GPrec<R>::rsqrt(r2);
+                                const R y = GradScale<R>::e_far(r2);
                                 E = y;
-                                W = -(y * y * y);
+                                W = GradScale<R>::w_far(y);
                             }
                             U = fma(ks[d], E, U);
                             Y = fma(kms[d], E, Y);
@@ -324,6 +324,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                         wCB = fma(bw[2], Xc, wCB);
                         wCD = fma(sab, Xcd, wCD);
                     }
+                }
+                {
+                    // back from the accumulators' scales (E times kE, W times kW)
+                    constexpr R iE = R(1) / GradScale<R>::kE, iW = R(1) / GradScale<R>::kW;
+                    eri *= iE; sX *= iE; sZ *= iE;
+                    wA *= iW; wAB *= iW; wB *= iW; wBB *= iW; wAD *= iW; wBD *= iW; wC *= iW; wCB *= iW; wCD *= iW;
                 }
                 if (valid) {
                     double deg = 1.0;

@@ -427,6 +427,9 @@ hfk_status run_scf(const Layout &L, const Basis &b, char *ws, const ScfLayout &S
             conv = true;
             break;
         }
+        // the last build allowed: its density is the one whose energy is E (no further
+        // eigensolve, which could also leave a failed solve behind the returned density)
+        if (it == max_iter) break;
         // DIIS over the filled slots (oldest first), else F itself
         std::vector<int> order;
         for (int k = 0; k < kDiisMax; ++k)

@@ -129,3 +129,23 @@ def test_scf_singular_overlap_is_refused(torch_dev):
     with pytest.raises(hfk.HfkError) as ei:
         _gpu_scf(torch_dev, xyz, [2.0, 2.0], np.tile(E3, (2, 1)), np.tile(C3, (2, 1)), 2, 0.0)
     assert ei.value.status == hfk.HFK_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("max_iter", [1, 3])
+def test_scf_unconverged_returns_the_density_of_its_energy(torch_dev, max_iter):
+    """A loop cut off by max_iter returns the density whose Fock matrix gave the returned
+    energy: E = 1/2 sum D o (2H + G(D)) + E_nn recomputed from the oracle (one-electron
+    integrals, the two-electron build and the nuclear repulsion) for the returned D.
+    Regression: the last iteration once diagonalised again and returned the next density."""
+    s, Z, nocc = _system((4, 4, 2), 16)
+    announce("scf unconverged max_iter=%d" % max_iter)
+    r, D, eps = _gpu_scf(torch_dev, s.xyz, Z, s.exps, s.coefs, nocc, s.tau, max_iter=max_iter)
+    assert not r["converged"] and r["iterations"] == max_iter
+    S, T, V = oracle.one_electron_atoms(s.xyz, Z, s.exps, s.coefs)
+    H = T + V
+    G, _, _ = oracle.fock_atoms(s.xyz, D, s.exps, s.coefs, s.tau)
+    n = len(Z)
+    enn = sum(Z[a] * Z[b] / np.linalg.norm(s.xyz[a] - s.xyz[b]) for a in range(n) for b in range(a))
+    E = 0.5 * float(np.sum(D * (2.0 * H + G))) + enn
+    assert rel(r["E"], E) < 1e-10, (r["E"], E)
+    assert np.isfinite(D).all() and np.isfinite(eps).all()
