@@ -126,6 +126,21 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss,
                     double *fock, double *e2,
                     void *workspace, size_t workspace_bytes, void *stream);
 
+/* hfk_fock for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same build with the atomics
+ * strategy, whose scratch is a static device array of 64 MiB inside the library instead
+ * of a caller workspace.  The call allocates nothing (no hipMalloc, no library routine that
+ * allocates).  Every GPU the library runs on holds its own copy of that array until the
+ * process ends; every call on a GPU shares that GPU's copy, so calls that overlap in time on
+ * one GPU race (serialise them, e.g. on one stream).  Each call clears what it needs.
+ *   Arguments and outputs as hfk_fock, without strategy and workspace.
+ * Errors as hfk_fock; HFK_EUNSUPPORTED when the system needs more scratch than the array
+ * holds (about 256 atoms with 3 primitives per function, fewer with more primitives). */
+hfk_status hfk_fock_noalloc(int64_t natoms, const double *xyz, int32_t ngauss,
+                            const double *exps_host, const double *coefs_host,
+                            const double *dens, double tau, int32_t precision,
+                            double *fock, double *e2, void *stream);
+
 /* Backward of the forward outputs (G, E2) for upstream (g_fock, g_e2).  The paper has no
  * gradient; this is the derivative of what the forward defines, with the screening
  * decisions held fixed.  With W = (g_fock + g_fock^T)/2 (0 if g_fock is NULL) and

@@ -92,6 +92,8 @@ _SIGNATURES = {
                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
     "hfk_fock_atoms": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
                        ctypes.c_int32, _vp, _vp, _vp, _sz, _vp],
+    "hfk_fock_noalloc": [ctypes.c_int64, _vp, ctypes.c_int32, _dp, _dp, _vp, ctypes.c_double, ctypes.c_int32,
+                         _vp, _vp, _vp],
 }
 
 
@@ -190,6 +192,28 @@ def fock(xyz, dens, exps: Sequence[float], coefs: Sequence[float], tau: float, p
     _check(lib().hfk_fock(n, xyz.data_ptr(), len(e), _dptr(e), _dptr(c), dens.data_ptr(), float(tau), prec,
                           int(strategy), F.data_ptr(), E2.data_ptr(), workspace.data_ptr(),
                           workspace.numel(), _stream_handle(stream)))
+    return F, E2
+
+
+def fock_noalloc(xyz, dens, exps: Sequence[float], coefs: Sequence[float], tau: float, precision="fp64",
+                 out=None, stream=None):
+    """hfk_fock_noalloc: the forward build with the library's static scratch (no workspace);
+    `out` = (F, E2) preallocated by the caller, or None to allocate them here."""
+    torch = _torch()
+    n = xyz.shape[0]
+    _dev_f64(xyz, "xyz", (n, 3))
+    _dev_f64(dens, "dens", (n, n))
+    e = _host_f64(exps)
+    c = _host_f64(coefs)
+    if e.shape != c.shape or e.ndim != 1:
+        raise HfkError(HFK_EINVAL, "exps and coefs must be 1-D of equal length")
+    if out is None:
+        F = torch.empty((n, n), dtype=torch.float64, device=xyz.device)
+        E2 = torch.empty((1,), dtype=torch.float64, device=xyz.device)
+    else:
+        F, E2 = out
+    _check(lib().hfk_fock_noalloc(n, xyz.data_ptr(), len(e), _dptr(e), _dptr(c), dens.data_ptr(), float(tau),
+                                  _PREC[precision], F.data_ptr(), E2.data_ptr(), _stream_handle(stream)))
     return F, E2
 
 

@@ -54,7 +54,7 @@ constexpr double kPrivateBudget = 16.0e9;
 // workgroups share through atomics.
 constexpr double kJcolBudget = 8.0e9;
 
-Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool atoms)
+Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool atoms, bool compact)
 {
     Layout L;
     memset(&L, 0, sizeof(L));
@@ -63,7 +63,7 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool a
     L.tile = prec == HFK_MIXED ? 2 * kTileItems : kTileItems;
     L.gshift = 10;   // kGroupBras
     L.kcopies = 0;
-    L.private_ok = (double)groups * (double)n * (double)n * 8.0 <= kPrivateBudget;
+    L.private_ok = !compact && (double)groups * (double)n * (double)n * 8.0 <= kPrivateBudget;
     L.npair = n * (n + 1) / 2;
     L.pcap = ((L.npair + 63) / 64) * 64 + 64;
     L.g = g;
@@ -121,6 +121,7 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool a
     {
         const double fit = kJcolBudget / (8.0 * (double)PC);
         L.jcopies = fit >= (double)groups ? groups : (fit >= 1.0 ? (int)fit : 1);
+        if (compact && L.jcopies > kCompactKetCopies) L.jcopies = kCompactKetCopies;
     }
     L.jcol = take(sizeof(double) * PC * (size_t)L.jcopies);
     L.fsum = take(sizeof(double) * n2);
@@ -389,6 +390,38 @@ static hfk_status debug_check(char *ws_hdr, int64_t n, const double *dens, hipSt
     return HFK_OK;
 }
 
+// ------------------------------------------------------------------ static scratch
+
+// Scratch of the allocation-free entry point (hfk_fock_noalloc): device memory that every
+// GPU the library runs on holds from module load until the process ends.  In host code the
+// array's name is only a stand-in; its device address comes from hipGetSymbolAddress, once
+// per device with that device current, and only that address is ever passed to kernels or
+// copies.  Every call on a GPU shares that GPU's copy: calls that overlap in time on one GPU
+// race, and each call clears what it needs (counters, accumulators) before use.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<void *> g_scratch_ptr;   // per device
+
+static hfk_status static_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || (uintptr_t)p % 256 != 0) return fail(HFK_EHIP, "static scratch has no aligned device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HFK_OK;
+}
+
 // ------------------------------------------------------------------ last build of this thread
 
 static thread_local const void *g_last_ws = nullptr;
@@ -499,18 +532,19 @@ hfk_status hfk_workspace_bytes(int64_t natoms, int32_t ngauss, int32_t precision
 
 }  // extern "C"
 
-// hfk_fock.
+// hfk_fock, and (compact) hfk_fock_noalloc: the workspace is then the static scratch, laid
+// out for the atomics strategy with a few shared ket vectors.
 static hfk_status fock_one_basis(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
                                  const double *coefs_host, const double *dens, double tau, int32_t precision,
                                  int32_t strategy, double *fock, double *e2, void *workspace, size_t workspace_bytes,
-                                 void *stream)
+                                 void *stream, bool compact)
 {
     g_err[0] = 0;
     hfk_status s = check_common(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision);
     if (s != HFK_OK) return s;
     if (!fock) return fail(HFK_EINVAL, "fock is NULL");
     if (!e2) return fail(HFK_EINVAL, "e2 is NULL");
-    if (!workspace) return fail(HFK_EINVAL, "workspace is NULL");
+    if (!compact && !workspace) return fail(HFK_EINVAL, "workspace is NULL");
     if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
     if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_DETERMINISTIC)
         return fail(HFK_EINVAL, "unknown strategy %d", (int)strategy);
@@ -520,10 +554,25 @@ static hfk_status fock_one_basis(int64_t natoms, const double *xyz, int32_t ngau
     if (ngauss > kMaxBuiltG) return fail(HFK_EUNSUPPORTED, "ngauss above %d is not built in this version", kMaxBuiltG);
     const int cus = device_cu_count();
     if (cus <= 0) return fail(HFK_EHIP, "no HIP device");
-    Layout L = make_layout(natoms, ngauss, precision, 0, groups_cap(cus));
+    Layout L = make_layout(natoms, ngauss, precision, 0, groups_cap(cus), false, compact);
+    if (compact) {
+        if (L.total > kStaticScratchBytes)
+            return fail(HFK_EUNSUPPORTED,
+                        "this system needs %zu bytes of scratch; the allocation-free call holds %zu (about 256 atoms "
+                        "with 3 primitives per function)",
+                        L.total, kStaticScratchBytes);
+        s = static_scratch(&workspace);
+        if (s != HFK_OK) return s;
+        workspace_bytes = kStaticScratchBytes;
+    }
     if (workspace_bytes < L.total)
         return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
-    const TunedConfig cfg = pick_config(strategy, precision, natoms, ngauss);
+    TunedConfig cfg = pick_config(strategy, precision, natoms, ngauss);
+    if (compact) {
+        // the scratch is laid out for atomics and the layout's shared ket vectors
+        cfg.strategy = HFK_STRATEGY_ATOMIC;
+        cfg.kcopies = 0;
+    }
     int strat = cfg.strategy;
     if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
     set_shape(L, cfg.tile, cfg.gbras, cfg.kcopies);
@@ -568,7 +617,15 @@ hfk_status hfk_fock(int64_t natoms, const double *xyz, int32_t ngauss, const dou
                     void *stream)
 {
     return fock_one_basis(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision, strategy, fock, e2,
-                          workspace, workspace_bytes, stream);
+                          workspace, workspace_bytes, stream, false);
+}
+
+hfk_status hfk_fock_noalloc(int64_t natoms, const double *xyz, int32_t ngauss, const double *exps_host,
+                            const double *coefs_host, const double *dens, double tau, int32_t precision,
+                            double *fock, double *e2, void *stream)
+{
+    return fock_one_basis(natoms, xyz, ngauss, exps_host, coefs_host, dens, tau, precision, HFK_STRATEGY_ATOMIC,
+                          fock, e2, nullptr, 0, stream, true);
 }
 
 }  // extern "C"

@@ -175,7 +175,10 @@ struct Layout {
     size_t total;
 };
 
-Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool atoms = false);
+// compact: the layout of the allocation-free call (one F for the atomics strategy, at most
+// kCompactKetCopies shared ket vectors).
+constexpr int kCompactKetCopies = 8;
+Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool atoms = false, bool compact = false);
 // Ket-side Coulomb vectors a build uses: one per workgroup within the memory budget, or the
 // requested number of shared copies when that is smaller.
 inline int effective_copies(const Layout &L)
