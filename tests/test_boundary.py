@@ -129,7 +129,7 @@ def test_load_tuning_rejects_missing_and_foreign_files(tmp_path):
         hfk.load_tuning(str(old))
     entry = ('{"arch": "gfx950", "precision": 0, "size_bucket": 9, "strategy": %d, "variant": 1, "gpc": 4, '
              '"tile_items": %d, "group_bras": %d, "ket_copies": 0}')
-    for strat, tile, gb in ((7, 4, 1024), (2, 0, 1024), (2, 17, 1024), (2, 4, 1000), (2, 4, 8192)):
+    for strat, tile, gb in ((7, 4, 1024), (3, 4, 1024), (2, 0, 1024), (2, 17, 1024), (2, 4, 1000), (2, 4, 8192)):
         worse = tmp_path / "worse.json"
         worse.write_text('{"format": "hfk-tuning-2", "entries": [%s], "batched": []}' % (entry % (strat, tile, gb)))
         with pytest.raises(hfk.HfkError):
@@ -328,7 +328,7 @@ def test_deterministic_strategy_size_limit():
     values past it are invalid."""
     assert _fock_raw(n=1025, strat=3) == hfk.HFK_EUNSUPPORTED
     assert "deterministic" in hfk.lib().hfk_last_error().decode()
-    assert _fock_raw(strat=4) == hfk.HFK_EINVAL
+    assert _fock_raw(strat=5) == hfk.HFK_EINVAL
     assert _atoms_raw(n=1100, strat=3) == hfk.HFK_EUNSUPPORTED
 
 
