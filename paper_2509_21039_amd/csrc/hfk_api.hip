@@ -79,7 +79,7 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool a
     L.hdr = take(sizeof(DevHeader));
     L.basis = take(sizeof(BasisDev));
     L.boys = take(sizeof(double) * kBoysGrid * kBoysStride);
-    L.boys_f = take(sizeof(float) * kBoysGrid * kBoysStride);
+    L.boys_f = take(sizeof(double) * kBoysGridF * kBoysStrideF);
     L.q_unsorted = take(sizeof(double) * P);
     L.bucket_of = take(sizeof(int) * P);
     L.bucket_cnt = take(sizeof(long long) * kNumBuckets);
@@ -107,7 +107,7 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool a
     L.bra = take(sizeof(double) * 8 * g2 * PC);
     L.bra_f = take(sizeof(float) * 8 * g2 * PC);
     L.boys_g = take(sizeof(double) * kBoysGrid * kBoysStride);
-    L.boys_g_f = take(sizeof(float) * kBoysGrid * kBoysStride);
+    L.boys_g_f = take(sizeof(double) * kBoysGridF * kBoysStrideF);
     L.nitems = take(sizeof(long long) * PC);
     L.lim = take(sizeof(int) * PC);
     L.item_off = take(sizeof(long long) * (PC + 1));
@@ -602,8 +602,8 @@ static hfk_status fock_one_basis(int64_t natoms, const double *xyz, int32_t ngau
     s = debug_check(ws + L.hdr, natoms, dens, st, "dens");
     if (s != HFK_OK) return s;
     hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys),
-                                (float *)(ws + L.boys_f), (double *)(ws + L.boys_g),
-                                (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz, st);
+                                (double *)(ws + L.boys_f), (double *)(ws + L.boys_g),
+                                (double *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz, st);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
     e = launch_pairs(L, b, ws, xyz, dens, tau, st, strat == HFK_STRATEGY_DETERMINISTIC);
     if (e == hipErrorNotSupported && strat == HFK_STRATEGY_DETERMINISTIC)
@@ -729,8 +729,8 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
     Basis b;
     hipError_t e = upload_rows((double *)(ws + L.arow), natoms, ngauss, exps_host, coefs_host, st, &b);
     if (e != hipSuccess) return hip_fail(e, "basis rows copy");
-    e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (float *)(ws + L.boys_f),
-                     (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz,
+    e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (double *)(ws + L.boys_f),
+                     (double *)(ws + L.boys_g), (double *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz,
                      st);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
     e = launch_pairs(L, b, ws, xyz, dens, tau, st, strat == HFK_STRATEGY_DETERMINISTIC);
@@ -821,8 +821,8 @@ hfk_status hfk_scf(int64_t natoms, const double *xyz, const double *charges_host
     Basis b;
     hipError_t e = upload_rows((double *)(ws + L.arow), natoms, ngauss, exps_host, coefs_host, st, &b);
     if (e != hipSuccess) return hip_fail(e, "basis rows copy");
-    e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (float *)(ws + L.boys_f),
-                     (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz,
+    e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (double *)(ws + L.boys_f),
+                     (double *)(ws + L.boys_g), (double *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr), natoms, xyz,
                      st);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
     ScfResult r;
@@ -925,8 +925,8 @@ static hfk_status fock_grad_impl(bool atoms, int64_t natoms, const double *xyz, 
     } else {
         b = make_basis(ngauss, exps_host, coefs_host);
     }
-    hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (float *)(ws + L.boys_f),
-                                (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr),
+    hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (double *)(ws + L.boys_f),
+                                (double *)(ws + L.boys_g), (double *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr),
                                 natoms, xyz, st);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
     e = launch_pairs(L, b, ws, xyz, dens, tau, st);
@@ -1070,8 +1070,8 @@ static hfk_status fock_batched_impl(bool atoms, int64_t nmol, const int64_t *ato
     } else {
         b = make_basis(ngauss, exps_host, coefs_host);
     }
-    hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (float *)(ws + L.boys_f),
-                                (double *)(ws + L.boys_g), (float *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr),
+    hipError_t e = launch_setup(b, (BasisDev *)(ws + L.basis), (double *)(ws + L.boys), (double *)(ws + L.boys_f),
+                                (double *)(ws + L.boys_g), (double *)(ws + L.boys_g_f), (DevHeader *)(ws + L.hdr),
                                 atom_off_host[nmol], xyz, st);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
     e = upload_batch_tables(L, ws, atom_off_host, st);

@@ -30,9 +30,9 @@ struct BArgs {
     const DevHeader *hdr;
     const BasisDev *bd;
     const double *tabH;
-    const float *tabH_f;
+    const double *tabH_f;   // rows of the FP32 grid (FP64 values)
     const double *tabG;
-    const float *tabG_f;
+    const double *tabG_f;
     const int *pk;
     const int *pl;
     const int *pm;
@@ -74,16 +74,12 @@ template <> struct BPrec<double> {
     static __device__ const double *prim(const BArgs &a) { return a.prim; }
     static __device__ const double *bra(const BArgs &a) { return a.bra; }
     static __device__ const double *bip(const BArgs &a) { return a.bip; }
-    static __device__ const double *tabH(const BArgs &a) { return a.tabH; }
-    static __device__ const double *tabG(const BArgs &a) { return a.tabG; }
     static __device__ const double *rsg(const BasisDev *bd) { return bd->rsg; }
 };
 template <> struct BPrec<float> {
     static __device__ const float *prim(const BArgs &a) { return a.prim_f; }
     static __device__ const float *bra(const BArgs &a) { return a.bra_f; }
     static __device__ const float *bip(const BArgs &a) { return a.bip_f; }
-    static __device__ const float *tabH(const BArgs &a) { return a.tabH_f; }
-    static __device__ const float *tabG(const BArgs &a) { return a.tabG_f; }
     static __device__ const float *rsg(const BasisDev *bd) { return bd->rsg_f; }
 };
 
@@ -355,12 +351,14 @@ template <int G, typename R, bool kGrad, bool kAtoms = false>
 __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
 {
     constexpr int G2 = G * G;
-    extern __shared__ double smem[];
+    extern __shared__ __attribute__((aligned(16))) double smem[];
     const int nmax = a.nmax;
-    double *Lt = smem;                                         // [nmax (nmax+1) / 2]
+    using BG = BoysGrid<R>;
+    // the tables first (16-byte aligned rows), then the molecule's accumulators
+    R *tH = (R *)smem;
+    R *tG = tH + BG::rows * BG::stride;
+    double *Lt = (double *)(tG + BG::rows * BG::stride);       // [nmax (nmax+1) / 2]
     double *lg = Lt + nmax * (nmax + 1) / 2;                   // [3 nmax]
-    R *tH = (R *)(lg + 3 * nmax);
-    R *tG = tH + kBoysGrid * kBoysStride;
     const int nthr = (int)blockDim.x, tid = threadIdx.x, lane = tid % kWave;
     // the wave index through readfirstlane, so that everything derived from it (the unit
     // loop, the bra walk) is known to be wave-uniform and stays in scalar registers
@@ -368,14 +366,17 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
     const int nwaves = nthr / kWave;
     const int S = a.hdr->sig_pairs;
     const BasisDev *bd = a.bd;
-    // grid-scaled rows (argument T' = T / h): coefficient m of H times h^m sqrt(h), of g times
-    // h^m h^(3/2), built from the FP64 rows
-    for (int x = tid; x < kBoysGrid * kBoysStride; x += nthr) {
-        const int m = x % kBoysStride;
-        double sc = sqrt(kBoysH);
-        for (int e = 0; e < m; ++e) sc *= kBoysH;
-        tH[x] = (R)(a.tabH[x] * sc * (double)GradScale<R>::kE);
-        tG[x] = (R)(a.tabG[x] * sc * kBoysH * (double)GradScale<R>::kW);
+    // grid-scaled rows of this precision's grid (argument T' = T / h): coefficient m of H
+    // times h^m sqrt(h), of g times h^m h^(3/2), from the FP64 rows (one rounding for FP32)
+    {
+        const double *gH = sizeof(R) == 8 ? a.tabH : a.tabH_f, *gG = sizeof(R) == 8 ? a.tabG : a.tabG_f;
+        for (int x = tid; x < BG::rows * BG::stride; x += nthr) {
+            const int m = x % BG::stride;
+            double sc = sqrt(BG::h);
+            for (int e = 0; e < m; ++e) sc *= BG::h;
+            tH[x] = (R)(gH[x] * sc * (double)GradScale<R>::kE);
+            tG[x] = (R)(gG[x] * sc * BG::h * (double)GradScale<R>::kW);
+        }
     }
     unsigned long long kept = 0;
     __shared__ long long blk_at;
@@ -531,13 +532,14 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
                     const R r2 = dx * dx + dy * dy + dz * dz;
                     // switch radius^2 kTswitch / rho (per-atom bases: sum of the stored halves)
                     const R sw = kAtoms ? bsw + kp[d] : u[4 * d];
-                    const bool near = r2 < sw;
+                    // lanes below the switch radius take the table, the others the far
+                    // field, under exec masks (a wave with no near lane skips the table part)
                     R E, W = R(0);
-                    if (__builtin_amdgcn_ballot_w64(near)) {
+                    if (r2 < sw) {
                         // (rho/h, sqrt(rho/h), (rho/h)^(3/2)) from the table, or from sw
                         R q1, q2, q3;
                         if constexpr (kAtoms) {
-                            q2 = rsqrt_r(sw) * R(kSqrtSwitchInvH);
+                            q2 = rsqrt_r(sw) * R(BG::sqrt_sw_inv_h);
                             q1 = q2 * q2;
                             q3 = q1 * q2;
                         } else {
@@ -545,26 +547,11 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
                             q2 = u[4 * d + 2];
                             q3 = u[4 * d + 3];
                         }
-                        // T' = T / h on the table grid; sqrt(h) H and h^(3/2) g, or their far
-                        // forms T'^(-1/2) and -T'^(-3/2)
-                        const R Ts = r2 * q1;
-                        const R y = GradScale<R>::e_far(Ts);
-                        const R Tc = fmin(Ts, R(kBoysGrid - 4));
-                        const R kd = rint(Tc);
-                        const R dd = Tc - kd;
-                        const unsigned off = __umul24((unsigned)(int)kd, (unsigned)(kBoysStride * sizeof(R)));
-                        const R *ch = (const R *)((const char *)tH + off);
-                        R vh = ch[6];
-#pragma unroll
-                        for (int m = 5; m >= 0; --m) vh = vh * dd + ch[m];
-                        E = q2 * (near ? vh : y);
-                        if (kGrad) {
-                            const R *cg = (const R *)((const char *)tG + off);
-                            R vg = cg[6];
-#pragma unroll
-                            for (int m = 5; m >= 0; --m) vg = vg * dd + cg[m];
-                            W = q3 * (near ? vg : GradScale<R>::w_far(y));
-                        }
+                        // sqrt(h) H and h^(3/2) g at T' = T / h on the table grid
+                        R dd;
+                        const unsigned off = boys_row<R>(r2, q1, dd);
+                        E = q2 * boys_eval<R>(tH, off, dd);
+                        if (kGrad) W = q3 * boys_eval<R>(tG, off, dd);
                     } else {
                         const R y = GradScale<R>::e_far(r2);
                         E = y;
@@ -752,7 +739,8 @@ int batched_resident_groups(int g, int prec, bool grad, bool atoms, int nmax, in
 size_t batched_smem_bytes(int nmax, int prec)
 {
     return sizeof(double) * ((size_t)nmax * (nmax + 1) / 2 + 3 * (size_t)nmax) +
-           2 * (size_t)kBoysGrid * kBoysStride * (prec == HFK_MIXED ? sizeof(float) : sizeof(double));
+           (prec == HFK_MIXED ? 2 * sizeof(float) * BoysGrid<float>::rows * BoysGrid<float>::stride
+                              : 2 * sizeof(double) * BoysGrid<double>::rows * BoysGrid<double>::stride);
 }
 
 BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad, bool atoms)
@@ -787,9 +775,9 @@ BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad
     L.hdr = take(sizeof(DevHeader));
     L.basis = take(sizeof(BasisDev));
     L.boys = take(sizeof(double) * kBoysGrid * kBoysStride);
-    L.boys_f = take(sizeof(float) * kBoysGrid * kBoysStride);
+    L.boys_f = take(sizeof(double) * kBoysGridF * kBoysStrideF);
     L.boys_g = take(sizeof(double) * kBoysGrid * kBoysStride);
-    L.boys_g_f = take(sizeof(float) * kBoysGrid * kBoysStride);
+    L.boys_g_f = take(sizeof(double) * kBoysGridF * kBoysStrideF);
     L.mol_n = take(sizeof(int) * NM);
     L.mol_aoff = take(sizeof(long long) * (NM + 1));
     L.mol_poff = take(sizeof(long long) * (NM + 1));
@@ -938,9 +926,9 @@ hipError_t launch_batched(const BLayout &L, const Basis &b, char *ws, const int6
     a.hdr = hdr;
     a.bd = bd;
     a.tabH = (const double *)(ws + L.boys);
-    a.tabH_f = (const float *)(ws + L.boys_f);
+    a.tabH_f = (const double *)(ws + L.boys_f);
     a.tabG = (const double *)(ws + L.boys_g);
-    a.tabG_f = (const float *)(ws + L.boys_g_f);
+    a.tabG_f = (const double *)(ws + L.boys_g_f);
     a.pk = (const int *)(ws + L.pk);
     a.pl = (const int *)(ws + L.pl);
     a.pm = (const int *)(ws + L.pm);

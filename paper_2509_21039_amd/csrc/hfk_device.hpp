@@ -96,6 +96,55 @@ template <> struct GradScale<float> {
     static __device__ float w_far(float e) { return -(e * e * e); }
 };
 
+// Table row of a lane below the switch radius, from r2 = |P-Q|^2 and rsh = rho/h:
+// T' = r2 rsh on the grid of this precision (below kTswitch / h for such a lane).  Adding the
+// rounding constant 1.5 2^52 (FP32: 1.5 2^23) in the FMA that forms T' rounds it to the
+// nearest row, whose index is then the low bits of the sum (no separate round and convert);
+// the index is still clamped to the table as a guard.  Returns the row's byte offset and
+// d = T' - row from one more FMA.
+template <typename R>
+__device__ inline unsigned boys_row(R r2, R rsh, R &d)
+{
+    using BG = BoysGrid<R>;
+    unsigned k;
+    if constexpr (sizeof(R) == 8) {
+        constexpr double kRound = 6755399441055744.0;   // 1.5 * 2^52
+        const double sum = fma(r2, rsh, kRound);
+        d = fma(r2, rsh, -(sum - kRound));
+        k = (unsigned)__double_as_longlong(sum);
+    } else {
+        constexpr float kRound = 12582912.0f;           // 1.5 * 2^23
+        const float sum = fmaf(r2, rsh, kRound);
+        d = fmaf(r2, rsh, -(sum - kRound));
+        k = __float_as_uint(sum) & 0x3fffffu;
+    }
+    k = min(k, (unsigned)(BG::rows - 8));
+    return __umul24(k, (unsigned)(BG::stride * sizeof(R)));
+}
+
+// The row's Taylor polynomial at d (Horner).  FP32 rows are 16 bytes on 16-byte boundaries:
+// one LDS read.
+template <typename R>
+__device__ inline R boys_eval(const R *__restrict__ tab, unsigned off, R d)
+{
+    const R *c = (const R *)((const char *)tab + off);
+    if constexpr (sizeof(R) == 8) {
+        static_assert(BoysGrid<double>::order == 7, "degree-6 rows");
+        R v = c[6];
+        v = v * d + c[5];
+        v = v * d + c[4];
+        v = v * d + c[3];
+        v = v * d + c[2];
+        v = v * d + c[1];
+        v = v * d + c[0];
+        return v;
+    } else {
+        static_assert(BoysGrid<float>::order == 4 && BoysGrid<float>::stride == 4, "degree-3 rows of 16 bytes");
+        const float4 r = *(const float4 *)c;
+        return fmaf(fmaf(fmaf(r.w, d, r.z), d, r.y), d, r.x);
+    }
+}
+
 // Id of the accelerator complex die (XCD) that runs this wave: hardware register XCC_ID
 // (gfx940 and later), bits [3:0].  Workgroups never move between dies, so the die's L2 is the
 // coherence point for every update one workgroup makes.

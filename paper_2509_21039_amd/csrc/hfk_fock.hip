@@ -39,7 +39,7 @@ struct FockArgs {
     const DevHeader *hdr;
     const BasisDev *bd;
     const double *boys;
-    const float *boys_f;
+    const double *boys_f;   // rows of the FP32 grid (FP64 values, rounded once into LDS)
     const int *pk;
     const int *pl;
     const double *pq;
@@ -94,7 +94,7 @@ template <> struct Prec<float> {
     static __device__ const float *prim(const FockArgs &a) { return a.prim_f; }
     static __device__ const float *bra(const FockArgs &a) { return a.bra_f; }
     static __device__ const float *bip(const FockArgs &a) { return a.bip_f; }
-    static __device__ const float *boys(const FockArgs &a) { return a.boys_f; }
+    static __device__ const double *boys(const FockArgs &a) { return a.boys_f; }
     static __device__ const float *rho(const BasisDev *bd) { return bd->rho_f; }
     static __device__ const float *srho(const BasisDev *bd) { return bd->srho_f; }
     static __device__ const float *r2sw(const BasisDev *bd) { return bd->r2sw_f; }
@@ -109,16 +109,13 @@ template <> struct Prec<float> {
 template <typename R>
 __device__ inline R boys_taylor(R T, const R *__restrict__ tab)
 {
-    const int k = (int)(T * R(kBoysInvH) + R(0.5));
-    const R d = T - (R)k * R(kBoysH);
-    const R *c = tab + k * kBoysStride;
-    R v = c[6];
-    v = v * d + c[5];
-    v = v * d + c[4];
-    v = v * d + c[3];
-    v = v * d + c[2];
-    v = v * d + c[1];
-    v = v * d + c[0];
+    using BG = BoysGrid<R>;
+    const int k = (int)(T * R(BG::inv_h) + R(0.5));
+    const R d = T - (R)k * R(BG::h);
+    const R *c = tab + k * BG::stride;
+    R v = c[BG::order - 1];
+#pragma unroll
+    for (int m = BG::order - 2; m >= 0; --m) v = v * d + c[m];
     return v;
 }
 
@@ -173,42 +170,20 @@ __device__ inline R quartet_eri_direct(const R *__restrict__ lbra, const R *__re
     return eri;
 }
 
-// kAccScale sqrt(h) H(T) from T' = T / h, the argument on the table grid (rows at
-// integers): the Taylor row nearest T' with coefficients pre-multiplied by
-// kAccScale h^m sqrt(h) where the lane is near, kAccScale T'^(-1/2) where it is not (T = 0
-// is always near, so needs no guard).
+// kAccScale sqrt(h) H(T) for a lane below the switch radius (the table is scaled to match).
 template <typename R>
-__device__ inline R boys_grid(R Ts, bool near, const R *__restrict__ tab)
+__device__ inline R boys_near(R r2, R rsh, const R *__restrict__ tab)
 {
-    // one Newton step in FP64 (error ~1.5 e^2 ~ 4e-15 for the estimate's e ~ 5e-8):
-    // -2 y1 = y (Ts y^2 - 3)
-    R far;
-    if constexpr (sizeof(R) == 8) {
-        const double y = __builtin_amdgcn_rsq(Ts);
-        far = y * fma(Ts, y * y, -3.0);
-    } else {
-        far = Prec<R>::rsqrt(Ts);
-    }
-    const R Tc = fmin(Ts, R(kBoysGrid - 4));
-    const R kd = rint(Tc);
-    const R d = Tc - kd;
-    // 24-bit multiply (full rate) for the row address
-    const R *c = (const R *)((const char *)tab + __umul24((unsigned)(int)kd, (unsigned)(kBoysStride * sizeof(R))));
-    R v = c[6];
-    v = v * d + c[5];
-    v = v * d + c[4];
-    v = v * d + c[3];
-    v = v * d + c[2];
-    v = v * d + c[1];
-    v = v * d + c[0];
-    return near ? v : far;
+    R d;
+    const unsigned off = boys_row<R>(r2, rsh, d);
+    return boys_eval<R>(tab, off, d);
 }
 
-// Contracted (bra | ket) with a wave-uniform near/far branch per primitive quartet: when
-// no lane of the wave has |P-Q|^2 below the switch radius (the common case once kets are
-// spatially sorted), the lanes add the far-field value S_cd / |P-Q| (exact beyond the
-// switch); otherwise every lane evaluates S_cd sqrt(rho/h) * sqrt(h) H(T) through the
-// grid table or its far-field form.  Lanes without a kept quartet point at a pad entry
+// Contracted (bra | ket) with a near/far branch per primitive quartet under exec masks:
+// lanes with |P-Q|^2 beyond the switch radius add the far-field value S_cd / |P-Q| (exact
+// there), the others S_cd sqrt(rho/h) * sqrt(h) H(T) from the grid table; a wave with no
+// near lane (the common case once kets are spatially sorted) skips the table part, and only
+// near lanes read the table from LDS.  Lanes without a kept quartet point at a pad entry
 // (centres 1e6 bohr away, zero weight), so they are never near and add nothing.  Uniform data come through scalar loads issued together
 // at the top of each bra primitive: (Px, Py, Pz, S, -2Px, -2Py, -2Pz, |P|^2) and, per
 // primitive quartet, (switch radius^2, rho/h, sqrt(rho/h)).
@@ -269,10 +244,9 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
                         r2 = dx * dx + dy * dy + dz * dz;
                     }
                     const R sw = bi + kp[d];   // kTswitch / rho
-                    const bool near = r2 < sw;
-                    if (__builtin_amdgcn_ballot_w64(near)) {
-                        const R y = rsqrt_r(sw) * R(kSqrtSwitchInvH);   // sqrt(rho / h)
-                        acc = fma(ks[d] * y, boys_grid<R>(r2 * (y * y), near, tab), acc);
+                    if (r2 < sw) {
+                        const R y = rsqrt_r(sw) * R(BoysGrid<R>::sqrt_sw_inv_h);   // sqrt(rho / h)
+                        acc = fma(ks[d] * y, boys_near<R>(r2, y * y, tab), acc);
                     } else {
                         acc = Prec<R>::far_acc(acc, ks[d], r2);
                     }
@@ -294,9 +268,8 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
                         const R dx = b[0] - kx[d], dy = b[1] - ky[d], dz = b[2] - kz[d];
                         r2 = dx * dx + dy * dy + dz * dz;
                     }
-                    const bool near = r2 < u[3 * d];
-                    if (__builtin_amdgcn_ballot_w64(near)) {
-                        acc = fma(ks[d] * u[3 * d + 2], boys_grid<R>(r2 * u[3 * d + 1], near, tab), acc);
+                    if (r2 < u[3 * d]) {
+                        acc = fma(ks[d] * u[3 * d + 2], boys_near<R>(r2, u[3 * d + 1], tab), acc);
                     } else {
                         acc = Prec<R>::far_acc(acc, ks[d], r2);
                     }
@@ -311,7 +284,7 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
 // LDS carve-up of the quartet kernel (bytes, 16-byte aligned pieces).
 template <typename R> struct FockSmem {
     static constexpr int kCombos = kMaxG2 * kMaxG2 / 16;                    // g <= 4 here: 256 combos
-    static constexpr size_t tab_bytes = sizeof(R) * kBoysGrid * kBoysStride;
+    static constexpr size_t tab_bytes = sizeof(R) * BoysGrid<R>::rows * BoysGrid<R>::stride;
     static constexpr size_t uni_bytes = 4 * sizeof(R) * 16 + 2 * sizeof(R) * kCombos;   // bra, (rho, srho)
     // deterministic strategy: per wave, kWaveKets staged updates (v, then k and l)
     static constexpr size_t stage_bytes = kWavesPerGroup * kWaveKets * (sizeof(double) + 2 * sizeof(int));
@@ -325,7 +298,7 @@ template <int G, typename R, bool kSplit, bool kAtoms = false, bool kDet = false
 __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
 {
     constexpr int G2 = G * G;
-    extern __shared__ double smem[];
+    extern __shared__ __attribute__((aligned(16))) double smem[];
     const int n = a.n;
     // the table first, so its row addresses need no base register
     char *sp = (char *)smem;
@@ -354,17 +327,20 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
     const int S = a.hdr->sig_pairs;
     const BasisDev *bd = a.bd;
 
-    const R *gtab = Prec<R>::boys(a);
-    if (kSplit) {
-        // grid-scaled rows: coefficient m times h^m sqrt(h), and the accumulator's scale
-        for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) {
-            const int m = x % kBoysStride;
-            double sc = sqrt(kBoysH) * (double)Prec<R>::kAccScale;
-            for (int e = 0; e < m; ++e) sc *= kBoysH;
-            tab[x] = (R)(a.boys[x] * sc);   // from the FP64 rows: one rounding for FP32
+    {
+        // the rows of this precision's grid, from FP64 values (one rounding for FP32); the
+        // hybrid form scales coefficient m by h^m sqrt(h) and the accumulator's scale
+        using BG = BoysGrid<R>;
+        const double *gtab = Prec<R>::boys(a);
+        for (int x = tid; x < BG::rows * BG::stride; x += kGroupThreads) {
+            const int m = x % BG::stride;
+            double sc = 1.0;
+            if (kSplit) {
+                sc = sqrt(BG::h) * (double)Prec<R>::kAccScale;
+                for (int e = 0; e < m; ++e) sc *= BG::h;
+            }
+            tab[x] = (R)(gtab[x] * sc);
         }
-    } else {
-        for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) tab[x] = gtab[x];
     }
     if (!kSplit) {
         for (int x = tid; x < G2 * G2; x += kGroupThreads) {
@@ -758,7 +734,7 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.hdr = hdr;
     a.bd = (const BasisDev *)(ws + L.basis);
     a.boys = (const double *)(ws + L.boys);
-    a.boys_f = (const float *)(ws + L.boys_f);
+    a.boys_f = (const double *)(ws + L.boys_f);
     a.pk = (const int *)(ws + L.pk);
     a.pl = (const int *)(ws + L.pl);
     a.pq = (const double *)(ws + L.pq);

@@ -37,9 +37,9 @@ struct GradArgs {
     const DevHeader *hdr;
     const BasisDev *bd;
     const double *tabH;
-    const float *tabH_f;
+    const double *tabH_f;   // rows of the FP32 grid (FP64 values)
     const double *tabG;
-    const float *tabG_f;
+    const double *tabG_f;
     const int *pk;
     const int *pl;
     const double *pq;
@@ -77,8 +77,6 @@ template <> struct GPrec<double> {
     static __device__ const double *bra(const GradArgs &a) { return a.bra; }
     static __device__ const double *bip(const GradArgs &a) { return a.bip; }
     static __device__ const double *bgw(const GradArgs &a) { return a.bgw; }
-    static __device__ const double *tabH(const GradArgs &a) { return a.tabH; }
-    static __device__ const double *tabG(const GradArgs &a) { return a.tabG; }
     static __device__ const double *rsg(const BasisDev *bd) { return bd->rsg; }
     static __device__ double rsqrt(double x) { return rsqrt_fp64(x); }
 };
@@ -87,8 +85,6 @@ template <> struct GPrec<float> {
     static __device__ const float *bra(const GradArgs &a) { return a.bra_f; }
     static __device__ const float *bip(const GradArgs &a) { return a.bip_f; }
     static __device__ const float *bgw(const GradArgs &a) { return a.bgw_f; }
-    static __device__ const float *tabH(const GradArgs &a) { return a.tabH_f; }
-    static __device__ const float *tabG(const GradArgs &a) { return a.tabG_f; }
     static __device__ const float *rsg(const BasisDev *bd) { return bd->rsg_f; }
     static __device__ float rsqrt(float x) { return rsqrt_fp32(x); }
 };
@@ -98,11 +94,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
 {
     constexpr int G2 = G * G;
     constexpr int kPComp = sizeof(R) == 8 ? 5 : 4;   // ket component holding kTswitch / p
-    extern __shared__ double smem[];
+    extern __shared__ __attribute__((aligned(16))) double smem[];
     const int n = a.n;
-    double *lg = smem;                                   // [n*3]
-    R *tH = (R *)(smem + 3 * n);
-    R *tG = tH + kBoysGrid * kBoysStride;
+    using BG = BoysGrid<R>;
+    // the tables first (16-byte aligned rows), then the gradient partials
+    R *tH = (R *)smem;
+    R *tG = tH + BG::rows * BG::stride;
+    double *lg = (double *)(tG + BG::rows * BG::stride);   // [n*3]
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int gid = blockIdx.x;
     const long long M = a.hdr->items;
@@ -111,14 +109,17 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
     __shared__ int wperm[kWavesPerGroup][kWaveKets];
     __shared__ long long blk_at;
     for (int x = tid; x < 3 * n; x += kGroupThreads) lg[x] = 0.0;
-    // grid-scaled rows (argument T' = T / h): coefficient m of H times h^m sqrt(h), of g times
-    // h^m h^(3/2), built from the FP64 rows
-    for (int x = tid; x < kBoysGrid * kBoysStride; x += kGroupThreads) {
-        const int m = x % kBoysStride;
-        double sc = sqrt(kBoysH);
-        for (int e = 0; e < m; ++e) sc *= kBoysH;
-        tH[x] = (R)(a.tabH[x] * sc * (double)GradScale<R>::kE);
-        tG[x] = (R)(a.tabG[x] * sc * kBoysH * (double)GradScale<R>::kW);
+    // grid-scaled rows of this precision's grid (argument T' = T / h): coefficient m of H
+    // times h^m sqrt(h), of g times h^m h^(3/2), from the FP64 rows (one rounding for FP32)
+    {
+        const double *gH = sizeof(R) == 8 ? a.tabH : a.tabH_f, *gG = sizeof(R) == 8 ? a.tabG : a.tabG_f;
+        for (int x = tid; x < BG::rows * BG::stride; x += kGroupThreads) {
+            const int m = x % BG::stride;
+            double sc = sqrt(BG::h);
+            for (int e = 0; e < m; ++e) sc *= BG::h;
+            tH[x] = (R)(gH[x] * sc * (double)GradScale<R>::kE);
+            tG[x] = (R)(gG[x] * sc * BG::h * (double)GradScale<R>::kW);
+        }
     }
     __syncthreads();
 
@@ -267,13 +268,15 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                             const R r2 = dx * dx + dy * dy + dz * dz;
                             // switch radius^2 kTswitch / rho (per-atom bases: sum of the stored halves)
                             const R sw = kAtoms ? bsw + kp[d] : u[4 * d];
-                            const bool near = r2 < sw;
+                            // lanes below the switch radius take the table, the others the
+                            // far field, under exec masks (a wave with no near lane skips
+                            // the table part)
                             R E, W;
-                            if (__builtin_amdgcn_ballot_w64(near)) {
+                            if (r2 < sw) {
                                 // (rho/h, sqrt(rho/h), (rho/h)^(3/2)): from the table, or from sw
                                 R q1, q2, q3;
                                 if constexpr (kAtoms) {
-                                    q2 = rsqrt_r(sw) * R(kSqrtSwitchInvH);
+                                    q2 = rsqrt_r(sw) * R(BG::sqrt_sw_inv_h);
                                     q1 = q2 * q2;
                                     q3 = q1 * q2;
                                 } else {
@@ -281,24 +284,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                                     q2 = u[4 * d + 2];
                                     q3 = u[4 * d + 3];
                                 }
-                                // T' = T / h on the table grid; sqrt(h) H and h^(3/2) g, or their
-                                // far forms T'^(-1/2) and -T'^(-3/2)
-                                const R Ts = r2 * q1;
-                                const R y = GradScale<R>::e_far(Ts);
-                                const R Tc = fmin(Ts, R(kBoysGrid - 4));
-                                const R kd = rint(Tc);
-                                const R dd = Tc - kd;
-                                const unsigned off = __umul24((unsigned)(int)kd, (unsigned)(kBoysStride * sizeof(R)));
-                                const R *ch = (const R *)((const char *)tH + off);
-                                const R *cg = (const R *)((const char *)tG + off);
-                                R vh = ch[6], vg = cg[6];
-#pragma unroll
-                                for (int m = 5; m >= 0; --m) {
-                                    vh = vh * dd + ch[m];
-                                    vg = vg * dd + cg[m];
-                                }
-                                E = q2 * (near ? vh : y);
-                                W = q3 * (near ? vg : GradScale<R>::w_far(y));
+                                // sqrt(h) H and h^(3/2) g at T' = T / h on the table grid
+                                R dd;
+                                const unsigned off = boys_row<R>(r2, q1, dd);
+                                E = q2 * boys_eval<R>(tH, off, dd);
+                                W = q3 * boys_eval<R>(tG, off, dd);
                             } else {
                                 const R y = GradScale<R>::e_far(r2);
                                 E = y;
@@ -457,7 +447,8 @@ __global__ __launch_bounds__(256) void k_scale_copy(const double *__restrict__ s
 size_t grad_smem_bytes(int64_t n, int prec)
 {
     return sizeof(double) * 3 * (size_t)n +
-           2 * (size_t)kBoysGrid * kBoysStride * (prec == HFK_MIXED ? sizeof(float) : sizeof(double));
+           (prec == HFK_MIXED ? 2 * sizeof(float) * BoysGrid<float>::rows * BoysGrid<float>::stride
+                              : 2 * sizeof(double) * BoysGrid<double>::rows * BoysGrid<double>::stride);
 }
 
 template <int G, typename R>
@@ -516,9 +507,9 @@ hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *
     a.hdr = (const DevHeader *)(ws + L.hdr);
     a.bd = (const BasisDev *)(ws + L.basis);
     a.tabH = (const double *)(ws + L.boys);
-    a.tabH_f = (const float *)(ws + L.boys_f);
+    a.tabH_f = (const double *)(ws + L.boys_f);
     a.tabG = (const double *)(ws + L.boys_g);
-    a.tabG_f = (const float *)(ws + L.boys_g_f);
+    a.tabG_f = (const double *)(ws + L.boys_g_f);
     a.pk = (const int *)(ws + L.pk);
     a.pl = (const int *)(ws + L.pl);
     a.pq = (const double *)(ws + L.pq);

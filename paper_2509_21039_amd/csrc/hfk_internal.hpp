@@ -35,6 +35,26 @@ constexpr double kBoysInvH = 8.0;
 constexpr double kTswitch = 32.0;      // above this H(T) = T^(-1/2) to < 1e-15 relative
 constexpr double kSqrtSwitchInvH = 16.0;   // sqrt(kTswitch / h)
 constexpr int kBoysGrid = 264;         // covers [0, 33)
+// The FP32 paths use a finer grid with a shorter expansion: degree 3 at h = 1/16 leaves a
+// Taylor remainder below 1e-8 relative (under FP32 rounding), and a row of four
+// coefficients is one 16-byte LDS read.  The rows are computed in FP64 and rounded once.
+constexpr int kBoysOrderF = 4;
+constexpr int kBoysStrideF = 4;
+constexpr double kBoysHF = 0.0625;
+constexpr double kBoysInvHF = 16.0;
+constexpr double kSqrtSwitchInvHF = 22.627416997969522;   // sqrt(kTswitch / hF) = sqrt(512)
+constexpr int kBoysGridF = 536;        // covers [0, 33.5)
+
+// Table geometry of each precision (rows, coefficients per row, grid spacing).
+template <typename R> struct BoysGrid;
+template <> struct BoysGrid<double> {
+    static constexpr int rows = kBoysGrid, stride = kBoysStride, order = kBoysOrder;
+    static constexpr double h = kBoysH, inv_h = kBoysInvH, sqrt_sw_inv_h = kSqrtSwitchInvH;
+};
+template <> struct BoysGrid<float> {
+    static constexpr int rows = kBoysGridF, stride = kBoysStrideF, order = kBoysOrderF;
+    static constexpr double h = kBoysHF, inv_h = kBoysInvHF, sqrt_sw_inv_h = kSqrtSwitchInvHF;
+};
 
 constexpr int kWave = 64;
 constexpr int kWavesPerGroup = 4;
@@ -135,9 +155,9 @@ struct BasisDev {
     double rs[3 * kMaxG2 * kMaxG2];     // (rho, sqrt(rho), kTswitch / rho) interleaved
     float rs_f[3 * kMaxG2 * kMaxG2];
     double rsn[3 * kMaxG2 * kMaxG2];    // (kTswitch / rho, rho / h, sqrt(rho / h)): T on the table grid
-    float rsn_f[3 * kMaxG2 * kMaxG2];
+    float rsn_f[3 * kMaxG2 * kMaxG2];   // the same on the FP32 grid (h = kBoysHF)
     double rsg[4 * kMaxG2 * kMaxG2];    // (kTswitch / rho, rho / h, sqrt(rho / h), (rho / h)^(3/2))
-    float rsg_f[4 * kMaxG2 * kMaxG2];
+    float rsg_f[4 * kMaxG2 * kMaxG2];   // the same on the FP32 grid
     float rho_f[kMaxG2 * kMaxG2];
     float srho_f[kMaxG2 * kMaxG2];
     float r2sw_f[kMaxG2 * kMaxG2];
@@ -248,8 +268,8 @@ int device_cu_count();
 
 // ------------------------------------------------------------------ launchers
 // Each returns hipSuccess or the launch error; all enqueue on `st`.
-hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, double *boys_g,
-                        float *boys_g_f, DevHeader *hdr, int64_t n, const double *xyz, hipStream_t st);
+hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, double *boys_f, double *boys_g,
+                        double *boys_g_f, DevHeader *hdr, int64_t n, const double *xyz, hipStream_t st);
 hipError_t launch_zero_counter(unsigned long long *p, hipStream_t st);
 // fixed_order: pairs within a (band, cell) bucket by pair index (deterministic strategy)
 // instead of the order an atomic cursor hands out.  That mode waits for the stream once to

@@ -41,18 +41,19 @@ __global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ b
         bd->rsn[3 * x + 1] = rho * kBoysInvH;
         bd->rsn[3 * x + 2] = sqrt(rho * kBoysInvH);
         bd->rsn_f[3 * x] = (float)(kTswitch / rho);
-        bd->rsn_f[3 * x + 1] = (float)(rho * kBoysInvH);
-        bd->rsn_f[3 * x + 2] = (float)sqrt(rho * kBoysInvH);
+        bd->rsn_f[3 * x + 1] = (float)(rho * kBoysInvHF);
+        bd->rsn_f[3 * x + 2] = (float)sqrt(rho * kBoysInvHF);
         {
             const double r = rho * kBoysInvH, sr = sqrt(r);
             bd->rsg[4 * x] = kTswitch / rho;
             bd->rsg[4 * x + 1] = r;
             bd->rsg[4 * x + 2] = sr;
             bd->rsg[4 * x + 3] = r * sr;
+            const double rf = rho * kBoysInvHF, srf = sqrt(rf);
             bd->rsg_f[4 * x] = (float)(kTswitch / rho);
-            bd->rsg_f[4 * x + 1] = (float)r;
-            bd->rsg_f[4 * x + 2] = (float)sr;
-            bd->rsg_f[4 * x + 3] = (float)(r * sr);
+            bd->rsg_f[4 * x + 1] = (float)rf;
+            bd->rsg_f[4 * x + 2] = (float)srf;
+            bd->rsg_f[4 * x + 3] = (float)(rf * srf);
         }
         bd->srho_f[x] = (float)sqrt(rho);
         bd->r2sw_f[x] = (float)(kTswitch / rho);
@@ -106,16 +107,13 @@ __global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ b
 // Boys tables.  Row k of `tab` holds (2/sqrt(pi)) (-1)^m F_m(k h) / m!, m = 0..kBoysOrder-1
 // (Taylor coefficients of H(T) = erf(sqrt T)/sqrt T about T_k), and row k of `tg` holds
 // -(4/sqrt(pi)) (-1)^m F_{m+1}(k h) / m! (Taylor coefficients of g(T) = -(4/sqrt(pi)) F1(T),
-// the radial derivative factor of the gradient).  F_m comes from its positive Kummer
-// series (no cancellation).
-__global__ void k_boys_table(double *__restrict__ tab, float *__restrict__ tab_f, double *__restrict__ tg,
-                             float *__restrict__ tg_f)
+// the radial derivative factor of the gradient).  `tab_f` and `tg_f` hold the same on the
+// FP32 grid (spacing kBoysHF, kBoysOrderF coefficients), still in FP64.  F_m comes from its
+// positive Kummer series (no cancellation).
+__device__ inline void boys_rows(double T, int order, int stride, double *v, double *w)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= kBoysGrid) return;
-    const double T = k * kBoysH;
     double fm[kBoysOrder + 1];
-    for (int m = 0; m <= kBoysOrder; ++m) {
+    for (int m = 0; m <= order; ++m) {
         double term = 1.0 / (2.0 * m + 1.0), sum = term;
         for (int i = 1; i < 400; ++i) {
             term *= 2.0 * T / (2.0 * m + 2.0 * i + 1.0);
@@ -125,26 +123,32 @@ __global__ void k_boys_table(double *__restrict__ tab, float *__restrict__ tab_f
         fm[m] = exp(-T) * sum;
     }
     double fact = 1.0;
-    for (int m = 0; m < kBoysStride; ++m) {
-        double v = 0.0, w = 0.0;
-        if (m < kBoysOrder) {
+    for (int m = 0; m < stride; ++m) {
+        v[m] = w[m] = 0.0;
+        if (m < order) {
             if (m > 0) fact *= (double)m;
             const double sgn = (m & 1) ? -1.0 : 1.0;
-            v = kTwoOverSqrtPi * sgn * fm[m] / fact;
-            w = -2.0 * kTwoOverSqrtPi * sgn * fm[m + 1] / fact;
+            v[m] = kTwoOverSqrtPi * sgn * fm[m] / fact;
+            w[m] = -2.0 * kTwoOverSqrtPi * sgn * fm[m + 1] / fact;
         }
-        tab[k * kBoysStride + m] = v;
-        tab_f[k * kBoysStride + m] = (float)v;
-        tg[k * kBoysStride + m] = w;
-        tg_f[k * kBoysStride + m] = (float)w;
     }
 }
 
-hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, float *boys_f, double *boys_g,
-                        float *boys_g_f, DevHeader *hdr, int64_t n, const double *xyz, hipStream_t st)
+__global__ void k_boys_table(double *__restrict__ tab, double *__restrict__ tab_f, double *__restrict__ tg,
+                             double *__restrict__ tg_f)
 {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < kBoysGrid) boys_rows(k * kBoysH, kBoysOrder, kBoysStride, tab + k * kBoysStride, tg + k * kBoysStride);
+    if (k < kBoysGridF)
+        boys_rows(k * kBoysHF, kBoysOrderF, kBoysStrideF, tab_f + k * kBoysStrideF, tg_f + k * kBoysStrideF);
+}
+
+hipError_t launch_setup(const Basis &b, BasisDev *bd, double *boys, double *boys_f, double *boys_g,
+                        double *boys_g_f, DevHeader *hdr, int64_t n, const double *xyz, hipStream_t st)
+{
+    static_assert(kBoysGridF >= kBoysGrid, "one thread per row of the longer table");
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, b, bd, hdr, n, xyz);
-    hipLaunchKernelGGL(k_boys_table, dim3((kBoysGrid + 63) / 64), dim3(64), 0, st, boys, boys_f, boys_g,
+    hipLaunchKernelGGL(k_boys_table, dim3((kBoysGridF + 63) / 64), dim3(64), 0, st, boys, boys_f, boys_g,
                        boys_g_f);
     return hipGetLastError();
 }
