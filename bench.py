@@ -405,6 +405,8 @@ def main():
     ap.add_argument("--batched-probe", action="store_true",
                     help="one warm-up and one timed call of the 2000-cluster batch (mixed + gradient, default "
                          "configuration, no tuning) and one plain 512 MiB device copy, for counter runs")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="run the VALU throughput probe (built next to the library) and print its JSON line")
     ap.add_argument("--grad-probe", action="store_true",
                     help="one warm-up and one timed forward + backward of the 128-atom lattice (FP64, default "
                          "configuration) and one plain 512 MiB device copy, for counter runs")
@@ -414,6 +416,13 @@ def main():
               "design is an all-reduce of F over a cost-balanced split of the tile list, not built). "
               "Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.valu_probe:
+        import subprocess
+        probe = os.path.join(ROOT, "paper_2509_21039_amd", "valu_probe")
+        if not os.path.exists(probe):
+            sys.exit("valu_probe is not built: run python -m paper_2509_21039_amd.build")
+        sys.exit(subprocess.run([probe]).returncode)
 
     import torch
     import paper_2509_21039_amd as hfk

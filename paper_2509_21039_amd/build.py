@@ -18,6 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libhfk.so")
+PROBE = os.path.join(HERE, "valu_probe")
 OBJDIR = os.path.join(HERE, "_build")
 
 ARCH = os.environ.get("HFK_OFFLOAD_ARCH", "gfx950")
@@ -61,8 +62,15 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, OUT)
+    # the VALU throughput probe: a stand-alone measurement program (bench.py --valu-probe)
+    probe_tmp = PROBE + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, *FLAGS, os.path.join(CSRC, "valu_probe.hip"), "-o", probe_tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for valu_probe.hip:\n%s\n%s" % (" ".join(cmd), r.stderr))
+    os.replace(probe_tmp, PROBE)
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", PROBE)
     return OUT
 
 
