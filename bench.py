@@ -396,9 +396,8 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one he512 FP64 build (hybrid kernel, default workgroups, --probe-strategy) and one plain "
                          "512 MiB device copy, for hardware-counter runs; prints the configuration")
-    ap.add_argument("--probe-strategy", type=int, default=2, choices=[1, 2, 4],
-                    help="accumulation strategy of the traffic probe (1 private copies, 2 atomics, 4 per-XCD "
-                         "copies)")
+    ap.add_argument("--probe-strategy", type=int, default=2, choices=[1, 2],
+                    help="accumulation strategy of the traffic probe (1 private copies, 2 atomics)")
     ap.add_argument("--probe-shape", default="",
                     help="launch shape of the traffic probe: gpc,tile_items,group_bras,ket_copies "
                          "(default: the untuned default)")

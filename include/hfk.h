@@ -62,16 +62,12 @@ typedef enum hfk_strategy {
     HFK_STRATEGY_AUTO = 0,     /* library default, or the tuned choice once hfk_tune ran */
     HFK_STRATEGY_PRIVATE = 1,  /* each workgroup owns an FP64 copy of F; summed at the end */
     HFK_STRATEGY_ATOMIC = 2,   /* workgroups flush their LDS rows into one F with atomics */
-    HFK_STRATEGY_DETERMINISTIC = 3,  /* every sum in a fixed order: repeated builds with the same
+    HFK_STRATEGY_DETERMINISTIC = 3   /* every sum in a fixed order: repeated builds with the same
                                         inputs on the same device agree bit for bit.  Static
                                         block schedule, private copies of F and of the ket
                                         vectors, per-wave LDS rows.  Up to 1024 atoms (hfk_fock and
                                         hfk_fock_atoms; HFK_EUNSUPPORTED above); slower than the
                                         other strategies and never chosen by the tuner */
-    HFK_STRATEGY_XCD = 4       /* one copy of F and of the ket-side Coulomb vector per XCD
-                                  (accelerator complex die, each with its own L2): a workgroup
-                                  updates its die's copies with atomics that complete in that L2
-                                  instead of in memory, and a final kernel sums the copies */
 } hfk_strategy;
 
 /* Arguments accept up to HFK_MAX_NGAUSS primitives per function; the kernels are built for

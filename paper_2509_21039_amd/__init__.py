@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhfk.so")
 
 HFK_OK, HFK_EINVAL, HFK_ENOMEM, HFK_EHIP, HFK_EUNSUPPORTED, HFK_ENOTSYM = 0, 1, 2, 3, 4, 5
 FP64, MIXED = 0, 1
-STRATEGY_AUTO, STRATEGY_PRIVATE, STRATEGY_ATOMIC, STRATEGY_DETERMINISTIC, STRATEGY_XCD = 0, 1, 2, 3, 4
+STRATEGY_AUTO, STRATEGY_PRIVATE, STRATEGY_ATOMIC, STRATEGY_DETERMINISTIC = 0, 1, 2, 3
 MAX_NGAUSS = 8
 
 _PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}

@@ -215,15 +215,6 @@ constexpr int kGradTileItems = 8;
 // and of the ket vector within the workspace budgets, and four wave copies of rows i, j in LDS.
 constexpr int64_t kMaxDetAtoms = 1024;
 
-// The strategy a layout can run: PRIVATE needs a copy of F per workgroup and XCD one per die
-// (both within the private-copy budget, and a ket vector per die); otherwise ATOMIC.
-static int usable_strategy(int strat, const Layout &L)
-{
-    if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) return HFK_STRATEGY_ATOMIC;
-    if (strat == HFK_STRATEGY_XCD && (!L.private_ok || L.jcopies < kXcdCopies)) return HFK_STRATEGY_ATOMIC;
-    return strat;
-}
-
 // Deterministic strategy: every workgroup must own a copy of F and of the ket vector.
 static hfk_status det_groups(Layout &L)
 {
@@ -342,8 +333,7 @@ static TunedConfig pick_config(int32_t strategy, int32_t precision, int64_t n, i
     } else {
         TunedConfig t;
         if (lookup_tuned(device_arch(), precision, size_bucket(n), &t)) c = t;
-        if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_ATOMIC || strategy == HFK_STRATEGY_XCD)
-            c.strategy = strategy;
+        if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_ATOMIC) c.strategy = strategy;
         if (g_cfg_variant >= 0) c.variant = g_cfg_variant;
         if (g_cfg_gpc > 0) c.gpc = g_cfg_gpc;
         if (g_cfg_tile > 0) c.tile = g_cfg_tile;
@@ -556,7 +546,7 @@ static hfk_status fock_one_basis(int64_t natoms, const double *xyz, int32_t ngau
     if (!e2) return fail(HFK_EINVAL, "e2 is NULL");
     if (!compact && !workspace) return fail(HFK_EINVAL, "workspace is NULL");
     if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
-    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_XCD)
+    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_DETERMINISTIC)
         return fail(HFK_EINVAL, "unknown strategy %d", (int)strategy);
     if (strategy == HFK_STRATEGY_DETERMINISTIC && natoms > kMaxDetAtoms)
         return fail(HFK_EUNSUPPORTED, "the deterministic strategy supports natoms <= %lld", (long long)kMaxDetAtoms);
@@ -584,7 +574,7 @@ static hfk_status fock_one_basis(int64_t natoms, const double *xyz, int32_t ngau
         cfg.kcopies = 0;
     }
     int strat = cfg.strategy;
-    strat = usable_strategy(strat, L);
+    if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
     set_shape(L, cfg.tile, cfg.gbras, cfg.kcopies);
     {
         // no more persistent workgroups than fit on a CU at once
@@ -613,7 +603,7 @@ static hfk_status fock_one_basis(int64_t natoms, const double *xyz, int32_t ngau
     e = launch_fock(L, b, ws, dens, tau, precision, strat, cfg.variant, fock, e2, st);
     if (e != hipSuccess) return hip_fail(e, "fock launch");
     e = launch_header_info(ws + L.hdr, strat, L.groups, precision, cfg.variant, st, L.tile, 1 << L.gshift,
-                           strat == HFK_STRATEGY_XCD ? kXcdCopies : effective_copies(L));
+                           effective_copies(L));
     if (e != hipSuccess) return hip_fail(e, "header launch");
     note_last(workspace, stream);
     return HFK_OK;
@@ -697,7 +687,7 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
     if (!e2) return fail(HFK_EINVAL, "e2 is NULL");
     if (!workspace) return fail(HFK_EINVAL, "workspace is NULL");
     if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
-    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_XCD)
+    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_DETERMINISTIC)
         return fail(HFK_EINVAL, "unknown strategy %d", (int)strategy);
     if (strategy == HFK_STRATEGY_DETERMINISTIC && natoms > kMaxDetAtoms)
         return fail(HFK_EUNSUPPORTED, "the deterministic strategy supports natoms <= %lld", (long long)kMaxDetAtoms);
@@ -711,7 +701,7 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
     TunedConfig cfg = pick_config(strategy, precision, natoms, ngauss);
     cfg.variant = 1;   // per-atom bases run the hybrid form only
     int strat = cfg.strategy;
-    strat = usable_strategy(strat, L);
+    if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
     set_shape(L, cfg.tile, cfg.gbras, cfg.kcopies);
     {
         const bool det = strat == HFK_STRATEGY_DETERMINISTIC;
@@ -741,7 +731,7 @@ hfk_status hfk_fock_atoms(int64_t natoms, const double *xyz, int32_t ngauss, con
     e = launch_fock(L, b, ws, dens, tau, precision, strat, 1, fock, e2, st);
     if (e != hipSuccess) return hip_fail(e, "fock launch");
     e = launch_header_info(ws + L.hdr, strat, L.groups, precision, 1, st, L.tile, 1 << L.gshift,
-                           strat == HFK_STRATEGY_XCD ? kXcdCopies : effective_copies(L));
+                           effective_copies(L));
     if (e != hipSuccess) return hip_fail(e, "header launch");
     note_last(workspace, stream);
     return HFK_OK;
@@ -786,7 +776,7 @@ hfk_status hfk_scf(int64_t natoms, const double *xyz, const double *charges_host
         return fail(HFK_EINVAL, "energy_host, iterations_host and converged_host must not be NULL");
     if (!workspace) return fail(HFK_EINVAL, "workspace is NULL");
     if ((uintptr_t)workspace % 256 != 0) return fail(HFK_EINVAL, "workspace must be 256-byte aligned");
-    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_XCD)
+    if (strategy < HFK_STRATEGY_AUTO || strategy > HFK_STRATEGY_DETERMINISTIC)
         return fail(HFK_EINVAL, "unknown strategy %d", (int)strategy);
     if (strategy == HFK_STRATEGY_DETERMINISTIC && natoms > kMaxDetAtoms)
         return fail(HFK_EUNSUPPORTED, "the deterministic strategy supports natoms <= %lld", (long long)kMaxDetAtoms);
@@ -801,7 +791,7 @@ hfk_status hfk_scf(int64_t natoms, const double *xyz, const double *charges_host
     TunedConfig cfg = pick_config(strategy, precision, natoms, ngauss);
     cfg.variant = 1;
     int strat = cfg.strategy;
-    strat = usable_strategy(strat, L);
+    if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
     set_shape(L, cfg.tile, cfg.gbras, cfg.kcopies);
     {
         const bool det = strat == HFK_STRATEGY_DETERMINISTIC;
@@ -946,7 +936,7 @@ static hfk_status fock_grad_impl(bool atoms, int64_t natoms, const double *xyz, 
         TunedConfig cfg = pick_config(HFK_STRATEGY_AUTO, precision, natoms, ngauss);
         if (atoms) cfg.variant = 1;   // per-atom bases run the hybrid form only
         int strat = cfg.strategy;
-        strat = usable_strategy(strat, L);
+        if (strat == HFK_STRATEGY_PRIVATE && !L.private_ok) strat = HFK_STRATEGY_ATOMIC;
         Layout LW = L;
         set_shape(LW, cfg.tile, cfg.gbras, cfg.kcopies);
         e = launch_pairs(LW, b, ws, xyz, xw, tau, st);
@@ -1259,13 +1249,13 @@ hfk_status hfk_tune(int64_t natoms, const double *xyz, int32_t ngauss, const dou
             }
         }
     };
-    const int strategies[3] = {HFK_STRATEGY_ATOMIC, HFK_STRATEGY_PRIVATE, HFK_STRATEGY_XCD};
+    const int strategies[2] = {HFK_STRATEGY_ATOMIC, HFK_STRATEGY_PRIVATE};
     const int variants[2] = {1, 0};
     const int gpcs[6] = {1, 2, 3, 4, 5, 6};
     const int tiles[5] = {1, 2, 4, 8, 16};
     const int gbras[5] = {256, 512, 1024, 2048, 4096};
     const int kcopies[3] = {0, 8, 32};
-    try_dim([](TunedConfig &c, int v) { c.strategy = v; }, strategies, L0.private_ok ? 3 : 1);
+    try_dim([](TunedConfig &c, int v) { c.strategy = v; }, strategies, L0.private_ok ? 2 : 1);
     if (ngauss <= 4) try_dim([](TunedConfig &c, int v) { c.variant = v; }, variants, 2);
     {
         // workgroups per CU up to what fits on a CU (more would only queue)
@@ -1410,7 +1400,7 @@ hfk_status hfk_load_tuning(const char *cache_path)
             long long bucket;
             if (!json_ll(o, "size_bucket", &bucket) || !json_ll(o, "strategy", &v[0]) || !json_ll(o, "variant", &v[1]) ||
                 !json_ll(o, "gpc", &v[2]) || !json_ll(o, "tile_items", &v[3]) || !json_ll(o, "group_bras", &v[4]) ||
-                !json_ll(o, "ket_copies", &v[5]) || bucket < 0 || bucket > 62 || v[0] < 1 || v[0] > 4 || v[0] == 3 || v[1] < 0 ||
+                !json_ll(o, "ket_copies", &v[5]) || bucket < 0 || bucket > 62 || v[0] < 1 || v[0] > 2 || v[1] < 0 ||
                 v[1] > 1 || v[2] < 1 || v[2] > kMaxGroupsPerCU || v[3] < 1 || v[3] > kMaxTileItems ||
                 !is_pow2_in(v[4], kMinGroupBras, kMaxGroupBras) || v[5] < 0 || v[5] > 1024)
                 return fail(HFK_EINVAL, "bad entry in %s", cache_path);

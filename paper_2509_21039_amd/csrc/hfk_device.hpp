@@ -145,23 +145,6 @@ __device__ inline R boys_eval(const R *__restrict__ tab, unsigned off, R d)
     }
 }
 
-// Id of the accelerator complex die (XCD) that runs this wave: hardware register XCC_ID
-// (gfx940 and later), bits [3:0].  Workgroups never move between dies, so the die's L2 is the
-// coherence point for every update one workgroup makes.
-__device__ inline int xcd_id()
-{
-    unsigned v;
-    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
-    return (int)(v & 15u);
-}
-
-// atomic add performed in the L2 of the die that issues it (workgroup scope: no forwarding to
-// memory); correct when every workgroup that updates *p runs on the same die
-__device__ inline void atomic_add_die(double *p, double v)
-{
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 // Wave-uniform tables read through the constant address space are fetched with scalar
 // loads (they are never written while a kernel runs).
 template <typename T> using cptr = const __attribute__((address_space(4))) T *;

@@ -349,18 +349,14 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
         }
     }
     const cptr<R> crs = (cptr<R>)Prec<R>::rsn(bd);
-    // XCD strategy: this die's copies of the ket vector and of F, updated with atomics that
-    // complete in the die's L2
-    const bool xcd = !kDet && a.strategy == HFK_STRATEGY_XCD;
-    const int die = xcd ? xcd_id() : 0;
-    const bool jshared = !xcd && a.jcopies < ng;
-    double *jcol = a.jcol + (int64_t)(xcd ? die : gid % a.jcopies) * a.pcap;
+    const bool jshared = a.jcopies < ng;
+    double *jcol = a.jcol + (int64_t)(gid % a.jcopies) * a.pcap;
     const bool priv = kDet || a.strategy == HFK_STRATEGY_PRIVATE;
-    double *fp = priv ? a.fpriv + (int64_t)gid * n * n : a.fpriv + (xcd ? (int64_t)die * n * n : 0);
+    double *fp = priv ? a.fpriv + (int64_t)gid * n * n : a.fpriv;
     if (priv) {
         for (int64_t x = tid; x < (int64_t)n * n; x += kGroupThreads) fp[x] = 0.0;
     }
-    if (!jshared && !xcd) {
+    if (!jshared) {
         for (int64_t x = tid; x < S; x += kGroupThreads) jcol[x] = 0.0;
     }
     __syncthreads();
@@ -431,12 +427,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
                             fj[c] += rowj[c];
                         }
                     }
-                } else if (xcd) {
-                    for (int c = tid; c < n; c += kGroupThreads) {
-                        const double vi = rowi[c], vj = rowj[c];
-                        if (vi != 0.0) atomic_add_die(&fi[c], vi);
-                        if (vj != 0.0) atomic_add_die(&fj[c], vj);
-                    }
                 } else {
                     for (int c = tid; c < n; c += kGroupThreads) {
                         const double vi = rowi[c], vj = rowj[c];
@@ -490,9 +480,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_fock(FockArgs a)
             jb = fma(a.pd[t], v, jb);
             if (valid) {
                 ++kept;
-                if (xcd)
-                    atomic_add_die(&jcol[t], 4.0 * ds * v);
-                else if (jshared)
+                if (jshared)
                     atomicAdd(&jcol[t], 4.0 * ds * v);
                 else
                     jcol[t] += 4.0 * ds * v;
@@ -760,19 +748,16 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     a.tau = tau;
     a.n = (int)L.n;
     a.strategy = strategy;
-    const bool xcd = strategy == HFK_STRATEGY_XCD;
-    a.jcopies = xcd ? kXcdCopies : effective_copies(L);
-    if (xcd || a.jcopies < L.groups) {
+    a.jcopies = effective_copies(L);
+    if (a.jcopies < L.groups) {
         // shared ket vectors are cleared before the launch (workgroups clear private ones)
         const int64_t nj = (int64_t)a.jcopies * L.pcap;
         hipLaunchKernelGGL(k_fill, dim3((unsigned)((nj + 255) / 256)), dim3(256), 0, st, a.jcol, nj, 0.0);
     }
     const int64_t n2 = L.n * L.n;
     const unsigned nb2 = (unsigned)((n2 + 255) / 256);
-    if (strategy == HFK_STRATEGY_ATOMIC || xcd) {
-        const int64_t nf = xcd ? kXcdCopies * n2 : n2;
-        hipLaunchKernelGGL(k_fill, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, a.fpriv, nf, 0.0);
-    }
+    if (strategy == HFK_STRATEGY_ATOMIC)
+        hipLaunchKernelGGL(k_fill, dim3(nb2), dim3(256), 0, st, a.fpriv, n2, 0.0);
     hipError_t err = hipSuccess;
     const int g = b.g;
     const bool at = L.atoms;
@@ -797,9 +782,8 @@ hipError_t launch_fock(const Layout &L, const Basis &b, char *ws, const double *
     }
     if (err != hipSuccess) return err;
     double *fsum = (double *)(ws + L.fsum);
-    if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_DETERMINISTIC || xcd)
-        hipLaunchKernelGGL(k_sum_private, dim3(nb2), dim3(256), 0, st, a.fpriv, xcd ? kXcdCopies : L.groups, n2,
-                           fsum);
+    if (strategy == HFK_STRATEGY_PRIVATE || strategy == HFK_STRATEGY_DETERMINISTIC)
+        hipLaunchKernelGGL(k_sum_private, dim3(nb2), dim3(256), 0, st, a.fpriv, L.groups, n2, fsum);
     else
         hipLaunchKernelGGL(k_copy, dim3(nb2), dim3(256), 0, st, a.fpriv, n2, fsum);
     hipLaunchKernelGGL(k_jcol_scatter, dim3((unsigned)((L.pcap + 255) / 256)), dim3(256), 0, st, hdr, a.jcol,

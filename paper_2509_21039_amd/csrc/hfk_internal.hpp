@@ -74,9 +74,6 @@ constexpr int kBatchMaxThreads = 512;
 constexpr int kBBra = 12;
 // Gradient bra weights per primitive pair of the single-molecule tables.
 constexpr int kGW = 8;
-// XCD-local accumulation: copies indexed by the die id (XCC_ID, 4 bits), so any device with
-// up to 16 dies gets one copy per die.
-constexpr int kXcdCopies = 16;
 // Single-molecule blocks: kTileItems items of one bra (twice as many with FP32 ket data).
 // Bras are taken kGroupBras at a time and their blocks are numbered ket-block-major (block
 // K of every bra of the group, then block K+1), so the workgroups running at the same

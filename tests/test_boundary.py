@@ -328,7 +328,7 @@ def test_deterministic_strategy_size_limit():
     values past it are invalid."""
     assert _fock_raw(n=1025, strat=3) == hfk.HFK_EUNSUPPORTED
     assert "deterministic" in hfk.lib().hfk_last_error().decode()
-    assert _fock_raw(strat=5) == hfk.HFK_EINVAL
+    assert _fock_raw(strat=4) == hfk.HFK_EINVAL
     assert _atoms_raw(n=1100, strat=3) == hfk.HFK_EUNSUPPORTED
 
 

@@ -60,7 +60,7 @@ def hhe64():
     return s, Gr, Er, nr
 
 
-@pytest.mark.parametrize("strategy", [1, 2, 4])
+@pytest.mark.parametrize("strategy", [1, 2])
 def test_atoms_hhe64_fp64_vs_oracle(torch_dev, hhe64, strategy):
     s, Gr, Er, nr = hhe64
     assert 0 < int(np.sum(s.exps[:, 0] < 5.0)) < s.natoms   # both elements present

@@ -48,7 +48,7 @@ def test_tiny_vs_bruteforce(torch_dev, n, seed, box, tau, variant):
 
 
 @pytest.mark.parametrize("variant", [0, 1])
-@pytest.mark.parametrize("strategy", [1, 2, 4])
+@pytest.mark.parametrize("strategy", [1, 2])
 def test_he64_fp64_vs_oracle(torch_dev, strategy, variant):
     s = config_system("he64_fp64")
     announce("he64 fp64 strategy=%d variant=%d" % (strategy, variant))

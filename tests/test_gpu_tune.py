@@ -31,7 +31,7 @@ def test_every_single_molecule_candidate_matches_the_oracle(torch_dev):
     Gr, Er, nr = oracle.fock(s.xyz, s.dens, s.exps, s.coefs, s.tau)
     xyz = torch.tensor(s.xyz, device=dev)
     D = torch.tensor(s.dens, device=dev)
-    cands = [dict(strategy=st) for st in (1, 2, 4)] + [dict(variant=v) for v in (0, 1)] + \
+    cands = [dict(strategy=st) for st in (1, 2)] + [dict(variant=v) for v in (0, 1)] + \
             [dict(gpc=g) for g in (1, 3, 6)] + [dict(tile=t) for t in (1, 2, 8, 16)] + \
             [dict(gbras=b) for b in (256, 512, 2048, 4096)] + [dict(kcopies=k) for k in (0, 1, 8, 32)]
     try:
