@@ -348,12 +348,13 @@ hfk_status hfk_clear_tuning(void);
  *                    1 = near/far split with per-wave compaction of near-field quartets,
  *                   -1 = library choice (default: tuned value, else 1)
  *   groups_per_cu    persistent workgroups per compute unit, 1..6, or 0 for the default
+ *                    (also the gradient kernel's count of hfk_fock_grad, capped at what fits)
  * Errors: HFK_EINVAL for values outside these sets. */
 hfk_status hfk_set_config(int32_t variant, int32_t groups_per_cu);
 
 /* Process-wide override of the quartet-tile shape of hfk_fock and hfk_fock_atoms (and of
- * the pull-back build of hfk_fock_grad; not of the deterministic strategy), for tuning and
- * tests:
+ * the gradient kernel and pull-back build of hfk_fock_grad; not of the deterministic
+ * strategy), for tuning and tests:
  *   tile_items     items of 1024 kets per block of one bra, 1..16 (0: library choice)
  *   group_bras     bras per group whose blocks are numbered ket-block-major: 256, 512,
  *                  1024, 2048 or 4096 (0: library choice)

@@ -106,7 +106,7 @@ Layout make_layout(int64_t n, int g, int prec, int with_grad, int groups, bool a
     }
     L.bra = take(sizeof(double) * 8 * g2 * PC);
     L.bra_f = take(sizeof(float) * 8 * g2 * PC);
-    L.boys_g = take(sizeof(double) * kBoysGrid * kBoysStride);
+    L.boys_g = take(sizeof(double) * kBoysGrid * kBoysStrideG);
     L.boys_g_f = take(sizeof(double) * kBoysGridF * kBoysStrideF);
     L.nitems = take(sizeof(long long) * PC);
     L.lim = take(sizeof(int) * PC);
@@ -897,13 +897,15 @@ static hfk_status fock_grad_impl(bool atoms, int64_t natoms, const double *xyz, 
     if (workspace_bytes < L.total)
         return fail(HFK_ENOMEM, "workspace holds %zu bytes, %zu needed", workspace_bytes, L.total);
     {
-        // as many persistent workgroups as fit on a CU, up to kGradGroupsPerCU
+        // as many persistent workgroups as fit on a CU, up to kGradGroupsPerCU (or the count
+        // hfk_set_config asks for)
         const int fit = grad_resident_groups(ngauss, precision, natoms, atoms);
-        L.groups = cus * (fit > 0 && fit < kGradGroupsPerCU ? fit : kGradGroupsPerCU);
+        const int want = g_cfg_gpc > 0 ? g_cfg_gpc : kGradGroupsPerCU;
+        L.groups = cus * (fit > 0 && fit < want ? fit : want);
     }
-    // the gradient kernel's blocks: eight items, groups of 1024 bras (the pull-back build
-    // below takes the forward's shape)
-    set_shape(L, kGradTileItems, kGroupBras, 0);
+    // the gradient kernel's blocks: eight items, groups of 1024 bras, unless hfk_set_shape
+    // asks for another shape (the pull-back build below takes the forward's shape)
+    set_shape(L, g_cfg_tile > 0 ? g_cfg_tile : kGradTileItems, g_cfg_gbras > 0 ? g_cfg_gbras : kGroupBras, 0);
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
     s = debug_check(ws + L.hdr, natoms, dens, st, "dens");
@@ -949,7 +951,7 @@ static hfk_status fock_grad_impl(bool atoms, int64_t natoms, const double *xyz, 
         e = launch_axpy_dev(n2, g_e2, fock_in, d_dens, st);
         if (e != hipSuccess) return hip_fail(e, "axpy launch");
     }
-    e = launch_header_info(ws + L.hdr, 0, L.groups, precision, -1, st, kGradTileItems, kGroupBras, 0);
+    e = launch_header_info(ws + L.hdr, 0, L.groups, precision, -1, st, L.tile, 1 << L.gshift, 0);
     if (e != hipSuccess) return hip_fail(e, "header launch");
     note_last(workspace, stream);
     return HFK_OK;

@@ -354,10 +354,9 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
     extern __shared__ __attribute__((aligned(16))) double smem[];
     const int nmax = a.nmax;
     using BG = BoysGrid<R>;
-    // the tables first (16-byte aligned rows), then the molecule's accumulators
-    R *tH = (R *)smem;
-    R *tG = tH + BG::rows * BG::stride;
-    double *Lt = (double *)(tG + BG::rows * BG::stride);       // [nmax (nmax+1) / 2]
+    // the Boys table first (16-byte aligned rows), then the molecule's accumulators
+    R *tHG = (R *)smem;
+    double *Lt = (double *)(tHG + BG::table_len);  // [nmax (nmax+1) / 2]
     double *lg = Lt + nmax * (nmax + 1) / 2;                   // [3 nmax]
     const int nthr = (int)blockDim.x, tid = threadIdx.x, lane = tid % kWave;
     // the wave index through readfirstlane, so that everything derived from it (the unit
@@ -366,16 +365,35 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
     const int nwaves = nthr / kWave;
     const int S = a.hdr->sig_pairs;
     const BasisDev *bd = a.bd;
-    // grid-scaled rows of this precision's grid (argument T' = T / h): coefficient m of H
-    // times h^m sqrt(h), of g times h^m h^(3/2), from the FP64 rows (one rounding for FP32)
+    // grid-scaled rows (argument T' = T / h) from the FP64 rows (one rounding for FP32):
+    // coefficient m of H times h^m sqrt(h) kE, of g times h^m h^(3/2) kW (FP32 only; FP64
+    // takes g from the derivative of H's degree-7 row)
     {
-        const double *gH = sizeof(R) == 8 ? a.tabH : a.tabH_f, *gG = sizeof(R) == 8 ? a.tabG : a.tabG_f;
-        for (int x = tid; x < BG::rows * BG::stride; x += nthr) {
-            const int m = x % BG::stride;
-            double sc = sqrt(BG::h);
-            for (int e = 0; e < m; ++e) sc *= BG::h;
-            tH[x] = (R)(gH[x] * sc * (double)GradScale<R>::kE);
-            tG[x] = (R)(gG[x] * sc * BG::h * (double)GradScale<R>::kW);
+        // FP64: the degree-7 rows of H (tabG); FP32: H's and g's rows on the FP32 grid
+        const double *gH = sizeof(R) == 8 ? a.tabG : a.tabH_f, *gG = a.tabG_f;
+        for (int x = tid; x < BG::table_len; x += nthr) {
+            int k, c;
+            bool isg;
+            if constexpr (sizeof(R) == 8) {   // H's rows of degree 7, padded
+                k = x / BG::pair_stride;
+                c = x % BG::pair_stride;
+                isg = false;
+            } else {                          // H's rows, then g's
+                isg = x >= BG::g_off;
+                const int y = isg ? x - BG::g_off : x;
+                k = y / BG::stride;
+                c = y % BG::stride;
+            }
+            const int order = sizeof(R) == 8 ? kBoysOrderG : BG::stride;
+            const int rowlen = sizeof(R) == 8 ? kBoysStrideG : BG::stride;
+            double v = 0.0;   // the pad
+            if (c < order) {
+                double sc = sqrt(BG::h);
+                for (int e = 0; e < c; ++e) sc *= BG::h;
+                v = isg ? gG[k * rowlen + c] * sc * BG::h * (double)GradScale<R>::kW
+                        : gH[k * rowlen + c] * sc * (double)GradScale<R>::kE;
+            }
+            tHG[x] = (R)v;
         }
     }
     unsigned long long kept = 0;
@@ -549,9 +567,16 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
                         }
                         // sqrt(h) H and h^(3/2) g at T' = T / h on the table grid
                         R dd;
-                        const unsigned off = boys_row<R>(r2, q1, dd);
-                        E = q2 * boys_eval<R>(tH, off, dd);
-                        if (kGrad) W = q3 * boys_eval<R>(tG, off, dd);
+                        const unsigned off = boys_row<R, BG::pair_stride>(r2, q1, dd);
+                        if constexpr (sizeof(R) == 8) {
+                            // degree-7 rows of H; g = 2 H': W on the grid is (2 kW / kE) dE/dd
+                            double de;
+                            E = q2 * boys_eval_d(tHG, off, dd, de);
+                            if (kGrad) W = q3 * (R(2.0 * GradScale<R>::kW / GradScale<R>::kE) * de);
+                        } else {
+                            E = q2 * boys_eval<R>(tHG, off, dd);
+                            if (kGrad) W = q3 * boys_eval<R>(tHG + BG::g_off, off, dd);
+                        }
                     } else {
                         const R y = GradScale<R>::e_far(r2);
                         E = y;
@@ -739,8 +764,8 @@ int batched_resident_groups(int g, int prec, bool grad, bool atoms, int nmax, in
 size_t batched_smem_bytes(int nmax, int prec)
 {
     return sizeof(double) * ((size_t)nmax * (nmax + 1) / 2 + 3 * (size_t)nmax) +
-           (prec == HFK_MIXED ? 2 * sizeof(float) * BoysGrid<float>::rows * BoysGrid<float>::stride
-                              : 2 * sizeof(double) * BoysGrid<double>::rows * BoysGrid<double>::stride);
+           (prec == HFK_MIXED ? sizeof(float) * BoysGrid<float>::table_len
+                              : sizeof(double) * BoysGrid<double>::table_len);
 }
 
 BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad, bool atoms)
@@ -776,7 +801,7 @@ BLayout make_blayout(int64_t nmol, const int64_t *atom_off, int g, int with_grad
     L.basis = take(sizeof(BasisDev));
     L.boys = take(sizeof(double) * kBoysGrid * kBoysStride);
     L.boys_f = take(sizeof(double) * kBoysGridF * kBoysStrideF);
-    L.boys_g = take(sizeof(double) * kBoysGrid * kBoysStride);
+    L.boys_g = take(sizeof(double) * kBoysGrid * kBoysStrideG);
     L.boys_g_f = take(sizeof(double) * kBoysGridF * kBoysStrideF);
     L.mol_n = take(sizeof(int) * NM);
     L.mol_aoff = take(sizeof(long long) * (NM + 1));

@@ -100,9 +100,9 @@ template <> struct GradScale<float> {
 // T' = r2 rsh on the grid of this precision (below kTswitch / h for such a lane).  Adding the
 // rounding constant 1.5 2^52 (FP32: 1.5 2^23) in the FMA that forms T' rounds it to the
 // nearest row, whose index is then the low bits of the sum (no separate round and convert);
-// the index is still clamped to the table as a guard.  Returns the row's byte offset and
-// d = T' - row from one more FMA.
-template <typename R>
+// the index is still clamped to the table as a guard.  Returns the row's byte offset (rows of
+// kRowLen values) and d = T' - row from one more FMA.
+template <typename R, int kRowLen = BoysGrid<R>::stride>
 __device__ inline unsigned boys_row(R r2, R rsh, R &d)
 {
     using BG = BoysGrid<R>;
@@ -119,7 +119,7 @@ __device__ inline unsigned boys_row(R r2, R rsh, R &d)
         k = __float_as_uint(sum) & 0x3fffffu;
     }
     k = min(k, (unsigned)(BG::rows - 8));
-    return __umul24(k, (unsigned)(BG::stride * sizeof(R)));
+    return __umul24(k, (unsigned)(kRowLen * sizeof(R)));
 }
 
 // The row's Taylor polynomial at d (Horner).  FP32 rows are 16 bytes on 16-byte boundaries:
@@ -143,6 +143,30 @@ __device__ inline R boys_eval(const R *__restrict__ tab, unsigned off, R d)
         const float4 r = *(const float4 *)c;
         return fmaf(fmaf(fmaf(r.w, d, r.z), d, r.y), d, r.x);
     }
+}
+
+// Value and derivative in d of a degree-7 FP64 row (kBoysOrderG coefficients) by joint
+// Horner steps: p = p d + c_m, q = q d + p.
+__device__ inline double boys_eval_d(const double *__restrict__ tab, unsigned off, double d, double &dp)
+{
+    static_assert(kBoysOrderG == 8, "degree-7 rows");
+    const double *c = (const double *)((const char *)tab + off);
+    double p = c[7], q = p;
+    p = fma(p, d, c[6]);
+    q = fma(q, d, p);
+    p = fma(p, d, c[5]);
+    q = fma(q, d, p);
+    p = fma(p, d, c[4]);
+    q = fma(q, d, p);
+    p = fma(p, d, c[3]);
+    q = fma(q, d, p);
+    p = fma(p, d, c[2]);
+    q = fma(q, d, p);
+    p = fma(p, d, c[1]);
+    q = fma(q, d, p);
+    p = fma(p, d, c[0]);
+    dp = q;
+    return p;
 }
 
 // Wave-uniform tables read through the constant address space are fetched with scalar

@@ -90,17 +90,23 @@ template <> struct GPrec<float> {
 };
 
 template <int G, typename R, bool kAtoms = false>
-__global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
+// One-basis FP64 kernels with up to three primitives are held to 128 VGPRs (four waves per
+// SIMD); the compiler then spills a few registers outside the quartet loop only.  The others
+// keep the register count they need.
+__global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu((kAtoms || G > 3) ? 1 : 4)))
+void k_grad(GradArgs a)
 {
     constexpr int G2 = G * G;
     constexpr int kPComp = sizeof(R) == 8 ? 5 : 4;   // ket component holding kTswitch / p
+    // FP64 forms |P-Q|^2 from the expanded table entries (4 operations, centroid-centred
+    // coordinates keep the cancellation near 1e-13 bohr^2); FP32 subtracts the centres
+    constexpr bool kExpand = sizeof(R) == 8;
     extern __shared__ __attribute__((aligned(16))) double smem[];
     const int n = a.n;
     using BG = BoysGrid<R>;
-    // the tables first (16-byte aligned rows), then the gradient partials
-    R *tH = (R *)smem;
-    R *tG = tH + BG::rows * BG::stride;
-    double *lg = (double *)(tG + BG::rows * BG::stride);   // [n*3]
+    // the Boys table first (16-byte aligned rows), then the gradient partials
+    R *tHG = (R *)smem;
+    double *lg = (double *)(tHG + BG::table_len);   // [n*3]
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int gid = blockIdx.x;
     const long long M = a.hdr->items;
@@ -109,16 +115,35 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
     __shared__ int wperm[kWavesPerGroup][kWaveKets];
     __shared__ long long blk_at;
     for (int x = tid; x < 3 * n; x += kGroupThreads) lg[x] = 0.0;
-    // grid-scaled rows of this precision's grid (argument T' = T / h): coefficient m of H
-    // times h^m sqrt(h), of g times h^m h^(3/2), from the FP64 rows (one rounding for FP32)
+    // grid-scaled rows (argument T' = T / h) from the FP64 rows (one rounding for FP32):
+    // coefficient m of H times h^m sqrt(h) kE, of g times h^m h^(3/2) kW (FP32 only; FP64
+    // takes g from the derivative of H's degree-7 row)
     {
-        const double *gH = sizeof(R) == 8 ? a.tabH : a.tabH_f, *gG = sizeof(R) == 8 ? a.tabG : a.tabG_f;
-        for (int x = tid; x < BG::rows * BG::stride; x += kGroupThreads) {
-            const int m = x % BG::stride;
-            double sc = sqrt(BG::h);
-            for (int e = 0; e < m; ++e) sc *= BG::h;
-            tH[x] = (R)(gH[x] * sc * (double)GradScale<R>::kE);
-            tG[x] = (R)(gG[x] * sc * BG::h * (double)GradScale<R>::kW);
+        // FP64: the degree-7 rows of H (tabG); FP32: H's and g's rows on the FP32 grid
+        const double *gH = sizeof(R) == 8 ? a.tabG : a.tabH_f, *gG = a.tabG_f;
+        for (int x = tid; x < BG::table_len; x += kGroupThreads) {
+            int k, c;
+            bool isg;
+            if constexpr (sizeof(R) == 8) {   // H's rows of degree 7, padded
+                k = x / BG::pair_stride;
+                c = x % BG::pair_stride;
+                isg = false;
+            } else {                          // H's rows, then g's
+                isg = x >= BG::g_off;
+                const int y = isg ? x - BG::g_off : x;
+                k = y / BG::stride;
+                c = y % BG::stride;
+            }
+            const int order = sizeof(R) == 8 ? kBoysOrderG : BG::stride;
+            const int rowlen = sizeof(R) == 8 ? kBoysStrideG : BG::stride;
+            double v = 0.0;   // the pad
+            if (c < order) {
+                double sc = sqrt(BG::h);
+                for (int e = 0; e < c; ++e) sc *= BG::h;
+                v = isg ? gG[k * rowlen + c] * sc * BG::h * (double)GradScale<R>::kW
+                        : gH[k * rowlen + c] * sc * (double)GradScale<R>::kE;
+            }
+            tHG[x] = (R)v;
         }
     }
     __syncthreads();
@@ -204,7 +229,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                 const int k = a.pk[t], l = a.pl[t];
     #pragma unroll 1
                 for (int cb = 0; cb < G; ++cb) {
-                    R kx[G], ky[G], kz[G], ks[G], kp[G];
+                    R kx[G], ky[G], kz[G], ks[G], kp[G], kq[G];
                     R kms[G], kds[G], kcs[G], kcds[G];   // S_cd times mu_cd, fd, fc, fc fd
                     // buffer loads of the ket table: component and this cb's rows in the
                     // resource, the row as a scalar offset, the ket as a 32-bit lane offset
@@ -220,23 +245,29 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                         kz[d] = ld(2, d);
                         ks[d] = ld(3, d);
                         kp[d] = kAtoms ? ld(kPComp, d) : R(0);
+                        kq[d] = kExpand ? ld(4, d) : R(0);
                     }
+                    // ket weights (mu_cd, fd, fc, fc fd): per lane for per-atom bases, else
+                    // uniform scalars
+                    R kw[4 * G];
 #pragma unroll
                     for (int d = 0; d < G; ++d) {
                         const int cd = cb * G + d;
-                        double mu, fc;
                         if constexpr (kAtoms) {
-                            mu = a.kmu[(int64_t)cd * a.pcap + t];
-                            fc = a.kfa[(int64_t)cd * a.pcap + t];
+                            const double mu = a.kmu[(int64_t)cd * a.pcap + t];
+                            const double fc = a.kfa[(int64_t)cd * a.pcap + t];
+                            const double fd = 1.0 - fc;
+                            kms[d] = (R)mu * ks[d];
+                            kcs[d] = (R)fc * ks[d];
+                            kds[d] = (R)fd * ks[d];
+                            kcds[d] = (R)(fc * fd) * ks[d];
                         } else {
-                            mu = cmu[cd];
-                            fc = cfa[cd];
+                            const double mu = cmu[cd], fc = cfa[cd], fd = cfb[cd];
+                            kw[4 * d] = (R)mu;
+                            kw[4 * d + 1] = (R)fd;
+                            kw[4 * d + 2] = (R)fc;
+                            kw[4 * d + 3] = (R)(fc * fd);
                         }
-                        const double fd = kAtoms ? 1.0 - fc : cfb[cd];
-                        kms[d] = (R)mu * ks[d];
-                        kcs[d] = (R)fc * ks[d];
-                        kds[d] = (R)fd * ks[d];
-                        kcds[d] = (R)(fc * fd) * ks[d];
                     }
 #pragma unroll 1
                     for (int ab = 0; ab < G2; ++ab) {
@@ -245,9 +276,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                         // the switch data
                         const cptr<R> bp = bra + 8 * ab;
                         const cptr<R> wp = bwp + kGW * ab;
-                        R b[4], bw[5], u[4 * G], bsw = R(0);
+                        R b[8], bw[5], u[4 * G], bsw = R(0);
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) b[c] = bp[c];
+                        for (int c = 0; c < (kExpand ? 8 : 4); ++c) b[c] = bp[c];
 #pragma unroll
                         for (int c = 0; c < 5; ++c) bw[c] = wp[c];
                         if constexpr (kAtoms) {
@@ -264,8 +295,14 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                         R U = R(0), Y = R(0), X0 = R(0), X1 = R(0), Xc = R(0), Xcd = R(0);
 #pragma unroll
                         for (int d = 0; d < G; ++d) {
-                            const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
-                            const R r2 = dx * dx + dy * dy + dz * dz;
+                            R r2;
+                            if (kExpand) {
+                                // |P|^2 + |Q|^2 - 2 P.Q with the bra's -2P and |P|^2 (as the forward)
+                                r2 = fma(b[4], kx[d], fma(b[5], ky[d], fma(b[6], kz[d], kq[d] + b[7])));
+                            } else {
+                                const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
+                                r2 = dx * dx + dy * dy + dz * dz;
+                            }
                             // switch radius^2 kTswitch / rho (per-atom bases: sum of the stored halves)
                             const R sw = kAtoms ? bsw + kp[d] : u[4 * d];
                             // lanes below the switch radius take the table, the others the
@@ -286,20 +323,40 @@ __global__ __launch_bounds__(kGroupThreads) void k_grad(GradArgs a)
                                 }
                                 // sqrt(h) H and h^(3/2) g at T' = T / h on the table grid
                                 R dd;
-                                const unsigned off = boys_row<R>(r2, q1, dd);
-                                E = q2 * boys_eval<R>(tH, off, dd);
-                                W = q3 * boys_eval<R>(tG, off, dd);
+                                const unsigned off = boys_row<R, BG::pair_stride>(r2, q1, dd);
+                                if constexpr (sizeof(R) == 8) {
+                                    // g = 2 H': W on the grid is (2 kW / kE) times dE/dd
+                                    double de;
+                                    E = q2 * boys_eval_d(tHG, off, dd, de);
+                                    W = q3 * (R(2.0 * GradScale<R>::kW / GradScale<R>::kE) * de);
+                                } else {
+                                    E = q2 * boys_eval<R>(tHG, off, dd);
+                                    W = q3 * boys_eval<R>(tHG + BG::g_off, off, dd);
+                                }
                             } else {
                                 const R y = GradScale<R>::e_far(r2);
                                 E = y;
                                 W = GradScale<R>::w_far(y);
                             }
-                            U = fma(ks[d], E, U);
-                            Y = fma(kms[d], E, Y);
-                            X0 = fma(ks[d], W, X0);
-                            X1 = fma(kds[d], W, X1);
-                            Xc = fma(kcs[d], W, Xc);
-                            Xcd = fma(kcds[d], W, Xcd);
+                            if constexpr (kAtoms) {
+                                U = fma(ks[d], E, U);
+                                Y = fma(kms[d], E, Y);
+                                X0 = fma(ks[d], W, X0);
+                                X1 = fma(kds[d], W, X1);
+                                Xc = fma(kcs[d], W, Xc);
+                                Xcd = fma(kcds[d], W, Xcd);
+                            } else {
+                                // one basis: the ket fractions are uniform scalars, so the lane
+                                // keeps only S_cd and weights S_cd E and S_cd W by them here
+                                // (two more operations, 24 fewer registers per lane)
+                                const R T = ks[d] * E, V = ks[d] * W;
+                                U += T;
+                                Y = fma(kw[4 * d], T, Y);
+                                X0 += V;
+                                X1 = fma(kw[4 * d + 1], V, X1);
+                                Xc = fma(kw[4 * d + 2], V, Xc);
+                                Xcd = fma(kw[4 * d + 3], V, Xcd);
+                            }
                         }
                         eri = fma(sab, U, eri);
                         sX = fma(bw[0], U, sX);
@@ -447,8 +504,8 @@ __global__ __launch_bounds__(256) void k_scale_copy(const double *__restrict__ s
 size_t grad_smem_bytes(int64_t n, int prec)
 {
     return sizeof(double) * 3 * (size_t)n +
-           (prec == HFK_MIXED ? 2 * sizeof(float) * BoysGrid<float>::rows * BoysGrid<float>::stride
-                              : 2 * sizeof(double) * BoysGrid<double>::rows * BoysGrid<double>::stride);
+           (prec == HFK_MIXED ? sizeof(float) * BoysGrid<float>::table_len
+                              : sizeof(double) * BoysGrid<double>::table_len);
 }
 
 template <int G, typename R>

@@ -47,12 +47,24 @@ constexpr int kBoysGridF = 536;        // covers [0, 33.5)
 
 // Table geometry of each precision (rows, coefficients per row, grid spacing).
 template <typename R> struct BoysGrid;
+// Gradient tables.  FP64: since g(T) = -(4/sqrt(pi)) F1(T) = 2 H'(T), one row of H of
+// degree 7 (kBoysOrderG coefficients) gives both: its value, and its derivative, which is
+// exactly the degree-6 Taylor expansion of g about the same point; rows of kBoysStrideG
+// values (a pad: 72-byte rows of 18 dwords start on 32 different banks).  FP32: H's and g's
+// rows of degree 3 in two tables of 16-byte rows (g's at a constant offset, within
+// ds_read_b128's 16-bit offset), since the derivative of a degree-3 row would leave g at
+// degree 2, short of FP32 accuracy.  pair_stride: values per row step; g_off: g's row after
+// H's (-1: derived); table_len: values in all.
+constexpr int kBoysOrderG = 8;
+constexpr int kBoysStrideG = 9;
 template <> struct BoysGrid<double> {
-    static constexpr int rows = kBoysGrid, stride = kBoysStride, order = kBoysOrder;
+    static constexpr int rows = kBoysGrid, stride = kBoysStride, order = kBoysOrder, pair_stride = kBoysStrideG;
+    static constexpr int g_off = -1, table_len = rows * pair_stride;
     static constexpr double h = kBoysH, inv_h = kBoysInvH, sqrt_sw_inv_h = kSqrtSwitchInvH;
 };
 template <> struct BoysGrid<float> {
-    static constexpr int rows = kBoysGridF, stride = kBoysStrideF, order = kBoysOrderF;
+    static constexpr int rows = kBoysGridF, stride = kBoysStrideF, order = kBoysOrderF, pair_stride = 4;
+    static constexpr int g_off = rows * stride, table_len = 2 * rows * stride;
     static constexpr double h = kBoysHF, inv_h = kBoysInvHF, sqrt_sw_inv_h = kSqrtSwitchInvHF;
 };
 
@@ -179,7 +191,7 @@ struct Layout {
     size_t pmu, pfa;                       // per-atom gradient: [g2][pcap] mu and a/p of the ket pairs
     size_t bgw, bgw_f;                     // gradient: [pcap][g2][kGW] bra weights mu S, fa S, fb S, fa fb S, fb^2 S
     size_t bra, bra_f;                     // [pcap][g2][8] Px Py Pz S -2Px -2Py -2Pz |P|^2 (wave-uniform bra data)
-    size_t boys_g, boys_g_f;               // Taylor table of g(T) = -(4/sqrt(pi)) F1(T) (gradient)
+    size_t boys_g, boys_g_f;               // gradient tables: H of degree 7 (FP64), g(T) = -(4/sqrt(pi)) F1(T) (FP32 grid)
     size_t nitems, lim, item_off, scan_tmp;
     size_t gcnt, goff;                     // per bra group: blocks, and their exclusive prefix
     int64_t ngroups;                       // bra groups of 2^gshift bras

@@ -105,14 +105,15 @@ __global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ b
 }
 
 // Boys tables.  Row k of `tab` holds (2/sqrt(pi)) (-1)^m F_m(k h) / m!, m = 0..kBoysOrder-1
-// (Taylor coefficients of H(T) = erf(sqrt T)/sqrt T about T_k), and row k of `tg` holds
-// -(4/sqrt(pi)) (-1)^m F_{m+1}(k h) / m! (Taylor coefficients of g(T) = -(4/sqrt(pi)) F1(T),
-// the radial derivative factor of the gradient).  `tab_f` and `tg_f` hold the same on the
-// FP32 grid (spacing kBoysHF, kBoysOrderF coefficients), still in FP64.  F_m comes from its
-// positive Kummer series (no cancellation).
+// (Taylor coefficients of H(T) = erf(sqrt T)/sqrt T about T_k); row k of `tg` holds the same
+// to degree 7 (kBoysOrderG coefficients, rows of kBoysStrideG: the FP64 gradient kernels take
+// g(T) = -(4/sqrt(pi)) F1(T) = 2 H'(T) from its derivative).  On the FP32 grid (spacing
+// kBoysHF, kBoysOrderF coefficients, still in FP64) `tab_f` holds H's rows and `tg_f` g's,
+// -(4/sqrt(pi)) (-1)^m F_{m+1}(k h) / m!.  F_m comes from its positive Kummer series (no
+// cancellation).
 __device__ inline void boys_rows(double T, int order, int stride, double *v, double *w)
 {
-    double fm[kBoysOrder + 1];
+    double fm[kBoysOrderG + 1];
     for (int m = 0; m <= order; ++m) {
         double term = 1.0 / (2.0 * m + 1.0), sum = term;
         for (int i = 1; i < 400; ++i) {
@@ -124,12 +125,13 @@ __device__ inline void boys_rows(double T, int order, int stride, double *v, dou
     }
     double fact = 1.0;
     for (int m = 0; m < stride; ++m) {
-        v[m] = w[m] = 0.0;
+        v[m] = 0.0;
+        if (w) w[m] = 0.0;
         if (m < order) {
             if (m > 0) fact *= (double)m;
             const double sgn = (m & 1) ? -1.0 : 1.0;
             v[m] = kTwoOverSqrtPi * sgn * fm[m] / fact;
-            w[m] = -2.0 * kTwoOverSqrtPi * sgn * fm[m + 1] / fact;
+            if (w) w[m] = -2.0 * kTwoOverSqrtPi * sgn * fm[m + 1] / fact;
         }
     }
 }
@@ -138,7 +140,10 @@ __global__ void k_boys_table(double *__restrict__ tab, double *__restrict__ tab_
                              double *__restrict__ tg_f)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < kBoysGrid) boys_rows(k * kBoysH, kBoysOrder, kBoysStride, tab + k * kBoysStride, tg + k * kBoysStride);
+    if (k < kBoysGrid) {
+        boys_rows(k * kBoysH, kBoysOrder, kBoysStride, tab + k * kBoysStride, nullptr);
+        boys_rows(k * kBoysH, kBoysOrderG, kBoysStrideG, tg + k * kBoysStrideG, nullptr);
+    }
     if (k < kBoysGridF)
         boys_rows(k * kBoysHF, kBoysOrderF, kBoysStrideF, tab_f + k * kBoysStrideF, tg_f + k * kBoysStrideF);
 }
