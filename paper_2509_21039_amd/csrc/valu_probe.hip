@@ -2,8 +2,9 @@
 // quartet kernels are built from (FP64 FMA and multiply, FP32 FMA, v_rsq_f64, v_rsq_f32
 // between conversions, and the far step's reciprocal square root with its folded Newton
 // step).  Every mode runs eight independent dependency chains per lane, 8 waves per SIMD, and
-// is timed with HIP events; cycles are reported at the 2.4 GHz engine clock.  Each thread
-// writes one output element at its global index (grid sized to the buffer).
+// is timed with HIP events; cycles are reported at the 2.4 GHz engine clock and at the clock
+// measured during the launch (thread 0's shader-clock ticks over its constant-rate ticks).
+// Each thread writes one output element at its global index (grid sized to the buffer).
 //
 //     valu_probe            prints one JSON line
 #include <hip/hip_runtime.h>
@@ -16,10 +17,15 @@ constexpr int kIters = 4096;
 constexpr int kChains = 8;
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_probe(double *out, double a, double b)
+__global__ __launch_bounds__(256) void k_probe(double *out, double a, double b, unsigned long long *clk)
 {
     double v[kChains];
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long c0 = 0, w0 = 0;
+    if (gid == 0) {
+        c0 = clock64();        // shader clock counter
+        w0 = wall_clock64();   // constant-rate counter
+    }
 #pragma unroll
     for (int c = 0; c < kChains; ++c) v[c] = 1.0 + 1e-3 * (gid + c);
     for (int it = 0; it < kIters; ++it) {
@@ -49,17 +55,21 @@ __global__ __launch_bounds__(256) void k_probe(double *out, double a, double b)
 #pragma unroll
     for (int c = 0; c < kChains; ++c) s += v[c];
     out[gid] = s;
+    if (gid == 0) {
+        clk[0] = clock64() - c0;
+        clk[1] = wall_clock64() - w0;
+    }
 }
 
 template <int MODE>
-float run(double *out, int blocks)
+float run(double *out, int blocks, unsigned long long *clk)
 {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0f;
-    hipLaunchKernelGGL(k_probe<MODE>, dim3(blocks), dim3(256), 0, 0, out, 0.999999, 1e-9);
+    hipLaunchKernelGGL(k_probe<MODE>, dim3(blocks), dim3(256), 0, 0, out, 0.999999, 1e-9, clk);
     float ms = -1.0f;
     if (hipEventRecord(e0) == hipSuccess) {
-        hipLaunchKernelGGL(k_probe<MODE>, dim3(blocks), dim3(256), 0, 0, out, 0.999999, 1e-9);
+        hipLaunchKernelGGL(k_probe<MODE>, dim3(blocks), dim3(256), 0, 0, out, 0.999999, 1e-9, clk);
         if (hipEventRecord(e1) == hipSuccess && hipEventSynchronize(e1) == hipSuccess)
             (void)hipEventElapsedTime(&ms, e0, e1);
     }
@@ -77,22 +87,40 @@ int main()
     const int cus = p.multiProcessorCount;
     const int blocks = cus * 8;   // 8 workgroups of 4 waves per CU: 8 waves per SIMD
     double *out = nullptr;
+    unsigned long long *clk = nullptr;
     if (hipMalloc(&out, sizeof(double) * blocks * 256) != hipSuccess) return 1;
+    if (hipMalloc(&clk, 2 * sizeof(unsigned long long)) != hipSuccess) return 1;
+    int wall_khz = 0;
+    if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, 0) != hipSuccess) wall_khz = 0;
     const char *names[] = {"fma_f64", "mul_f64", "fma_f32", "rsq_f64", "4fma_f64+rsq_f64", "rsq_f64+newton",
                            "cvt+rsq_f32+cvt+newton"};
     float t[7];
-    t[0] = run<0>(out, blocks);
-    t[1] = run<1>(out, blocks);
-    t[2] = run<2>(out, blocks);
-    t[3] = run<3>(out, blocks);
-    t[4] = run<4>(out, blocks);
-    t[5] = run<5>(out, blocks);
-    t[6] = run<6>(out, blocks);
+    double mhz[7];
+    unsigned long long c[2];
+    auto clock_mhz = [&]() {
+        // engine clock during the last launch: shader-clock ticks over constant-rate ticks
+        if (hipMemcpy(c, clk, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess || c[1] == 0 || wall_khz <= 0)
+            return 0.0;
+        return (double)c[0] / ((double)c[1] / (wall_khz * 1e3)) / 1e6;
+    };
+    t[0] = run<0>(out, blocks, clk); mhz[0] = clock_mhz();
+    t[1] = run<1>(out, blocks, clk); mhz[1] = clock_mhz();
+    t[2] = run<2>(out, blocks, clk); mhz[2] = clock_mhz();
+    t[3] = run<3>(out, blocks, clk); mhz[3] = clock_mhz();
+    t[4] = run<4>(out, blocks, clk); mhz[4] = clock_mhz();
+    t[5] = run<5>(out, blocks, clk); mhz[5] = clock_mhz();
+    t[6] = run<6>(out, blocks, clk); mhz[6] = clock_mhz();
     const double steps = (double)kIters * kChains * (blocks * 4.0) / (cus * 4.0);   // per SIMD
     printf("{\"probe\": \"valu\", \"cus\": %d, \"cycles_per_step_at_2400MHz\": {", cus);
     for (int m = 0; m < 7; ++m)
         printf("%s\"%s\": %.2f", m ? ", " : "", names[m], t[m] * 1e-3 * 2.4e9 / steps);
-    printf("}}\n");
+    printf("}, \"cycles_per_step_at_measured_clock\": {");
+    for (int m = 0; m < 7; ++m)
+        printf("%s\"%s\": %.2f", m ? ", " : "", names[m], t[m] * 1e-3 * mhz[m] * 1e6 / steps);
+    printf("}, \"measured_clock_mhz\": [");
+    for (int m = 0; m < 7; ++m) printf("%s%.0f", m ? ", " : "", mhz[m]);
+    printf("]}\n");
+    (void)hipFree(clk);
     (void)hipFree(out);
     for (int m = 0; m < 7; ++m)
         if (t[m] < 0) return 1;
