@@ -207,6 +207,7 @@ constexpr int64_t kMaxAtoms = 6144;
 // n above which the gradient kernel's LDS copy of dE2/dR (n x 3) and its two tables no longer fit
 constexpr int64_t kMaxGradAtoms = 4096;
 constexpr int kGradGroupsPerCU = 4;
+constexpr int kDefaultKetCopies = 8;   // untuned default: shared ket-side Coulomb vectors
 // Items per block of the gradient kernel: eight (he512 FP64 184 ms against 191 with four;
 // its per-item work is about 2.4 times the forward's, so fewer row flushes matter more
 // than the smaller ket working set).
@@ -306,8 +307,11 @@ static thread_local const BatchedConfig *g_force_b = nullptr;
 // FP32 ket table, half the size), groups of 1024 bras, one ket vector per workgroup.
 static TunedConfig default_config(int64_t n, int precision)
 {
+    // eight shared ket-side Coulomb vectors: they stay cached where one per workgroup does
+    // not (he512 FP64 68.0 against 69.2 ms, he1024 mixed 210.0 against 221.2 ms, he128 2.12
+    // against 2.19 ms)
     return TunedConfig{HFK_STRATEGY_ATOMIC, 1, n <= 64 ? 2 : (n <= 128 ? 4 : 6),
-                       precision == HFK_MIXED ? 2 * kTileItems : kTileItems, kGroupBras, 0};
+                       precision == HFK_MIXED ? 2 * kTileItems : kTileItems, kGroupBras, kDefaultKetCopies};
 }
 
 // Before tuning: eight-wave workgroups, two per CU (the LDS holds two molecules' triangles
