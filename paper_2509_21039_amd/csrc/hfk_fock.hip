@@ -204,25 +204,41 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
     constexpr int G2 = G * G;
     constexpr bool kExpand = sizeof(R) == 8;
     constexpr int kPComp = kExpand ? 5 : 4;   // ket component holding kTswitch / p (per-atom bases)
+    // FP32 with up to three primitives loads the next cb's ket data while it works on this one
+    // (the kernel has registers to spare: he1024 mixed 209.6 -> 203.2 ms); FP64 would drop from
+    // five to four waves per SIMD for it and run slower (he512 67.9 -> 73.5 ms), so it loads
+    // each cb at its start
+    constexpr bool kPrefetch = sizeof(R) == 4 && G <= 3;
+    constexpr int kSlots = kPrefetch ? 2 : 1;
     R eri = R(0);
-#pragma unroll 1
-    for (int cb = 0; cb < G; ++cb) {
-        R kx[G], ky[G], kz[G], ks[G], kq[G], kp[G];
-        // buffer loads: one resource per component over the G rows of this cb, the row as a
-        // scalar offset and the ket as a 32-bit lane offset (no 64-bit address math per lane)
-        const unsigned tb = t * (unsigned)sizeof(R);
+    R kx[kSlots][G], ky[kSlots][G], kz[kSlots][G], ks[kSlots][G], kq[kSlots][G], kp[kSlots][G];
+    // buffer loads: one resource per component over the G rows of a cb, the row as a scalar
+    // offset and the ket as a 32-bit lane offset (no 64-bit address math per lane)
+    const unsigned tb = t * (unsigned)sizeof(R);
+    auto load_cb = [&](int cbl, int slot) {
         auto ld = [&](int c, int d) {
-            return ket_load<R>(ket_rows(prim, (int64_t)c * G2 + cb * G, pcap, G), tb,
+            return ket_load<R>(ket_rows(prim, (int64_t)c * G2 + cbl * G, pcap, G), tb,
                                (int)((int64_t)d * pcap * (int64_t)sizeof(R)));
         };
 #pragma unroll
         for (int d = 0; d < G; ++d) {
-            kx[d] = ld(0, d);
-            ky[d] = ld(1, d);
-            kz[d] = ld(2, d);
-            ks[d] = ld(3, d);
-            kq[d] = kExpand ? ld(4, d) : R(0);
-            kp[d] = kAtoms ? ld(kPComp, d) : R(0);
+            kx[slot][d] = ld(0, d);
+            ky[slot][d] = ld(1, d);
+            kz[slot][d] = ld(2, d);
+            ks[slot][d] = ld(3, d);
+            kq[slot][d] = kExpand ? ld(4, d) : R(0);
+            kp[slot][d] = kAtoms ? ld(kPComp, d) : R(0);
+        }
+    };
+    constexpr int kCbUnroll = kPrefetch ? G : 1;   // the slots must be compile-time indices
+    if constexpr (kPrefetch) load_cb(0, 0);
+#pragma unroll kCbUnroll
+    for (int cb = 0; cb < G; ++cb) {
+        const int cur = kPrefetch ? (cb & 1) : 0;
+        if constexpr (kPrefetch) {
+            if (cb + 1 < G) load_cb(cb + 1, cur ^ 1);
+        } else {
+            load_cb(cb, 0);
         }
 #pragma unroll 1
         for (int ab = 0; ab < G2; ++ab) {
@@ -238,17 +254,17 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
                 for (int d = 0; d < G; ++d) {
                     R r2;
                     if (kExpand) {
-                        r2 = fma(b[4], kx[d], fma(b[5], ky[d], fma(b[6], kz[d], kq[d] + b[7])));
+                        r2 = fma(b[4], kx[cur][d], fma(b[5], ky[cur][d], fma(b[6], kz[cur][d], kq[cur][d] + b[7])));
                     } else {
-                        const R dx = b[0] - kx[d], dy = b[1] - ky[d], dz = b[2] - kz[d];
+                        const R dx = b[0] - kx[cur][d], dy = b[1] - ky[cur][d], dz = b[2] - kz[cur][d];
                         r2 = dx * dx + dy * dy + dz * dz;
                     }
-                    const R sw = bi + kp[d];   // kTswitch / rho
+                    const R sw = bi + kp[cur][d];   // kTswitch / rho
                     if (r2 < sw) {
                         const R y = rsqrt_r(sw) * R(BoysGrid<R>::sqrt_sw_inv_h);   // sqrt(rho / h)
-                        acc = fma(ks[d] * y, boys_near<R>(r2, y * y, tab), acc);
+                        acc = fma(ks[cur][d] * y, boys_near<R>(r2, y * y, tab), acc);
                     } else {
-                        acc = Prec<R>::far_acc(acc, ks[d], r2);
+                        acc = Prec<R>::far_acc(acc, ks[cur][d], r2);
                     }
                 }
             } else {
@@ -263,15 +279,15 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
                 for (int d = 0; d < G; ++d) {
                     R r2;
                     if (kExpand) {
-                        r2 = fma(b[4], kx[d], fma(b[5], ky[d], fma(b[6], kz[d], kq[d] + b[7])));
+                        r2 = fma(b[4], kx[cur][d], fma(b[5], ky[cur][d], fma(b[6], kz[cur][d], kq[cur][d] + b[7])));
                     } else {
-                        const R dx = b[0] - kx[d], dy = b[1] - ky[d], dz = b[2] - kz[d];
+                        const R dx = b[0] - kx[cur][d], dy = b[1] - ky[cur][d], dz = b[2] - kz[cur][d];
                         r2 = dx * dx + dy * dy + dz * dz;
                     }
                     if (r2 < u[3 * d]) {
-                        acc = fma(ks[d] * u[3 * d + 2], boys_near<R>(r2, u[3 * d + 1], tab), acc);
+                        acc = fma(ks[cur][d] * u[3 * d + 2], boys_near<R>(r2, u[3 * d + 1], tab), acc);
                     } else {
-                        acc = Prec<R>::far_acc(acc, ks[d], r2);
+                        acc = Prec<R>::far_acc(acc, ks[cur][d], r2);
                     }
                 }
             }

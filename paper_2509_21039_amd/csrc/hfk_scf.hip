@@ -209,16 +209,26 @@ ScfLayout make_scf_layout(size_t base, int64_t n)
 namespace {
 
 struct Ctx {
-    rocblas_handle h = nullptr;
+    rocblas_handle h = nullptr;   // the calling thread's handle for the current device
     hipStream_t st = nullptr;
     int64_t n = 0;
     char *msg = nullptr;
     size_t msglen = 0;
-    ~Ctx()
-    {
-        if (h) (void)rocblas_destroy_handle(h);
-    }
 };
+
+// One rocBLAS handle per calling thread and device, created on the first SCF call and kept
+// for the life of the thread: creating one per call cost time on every call, and handles are
+// not shared between threads.  Each call sets its stream and its workspace before any use.
+// The handles are never destroyed (so teardown order at process exit does not matter).
+rocblas_handle thread_handle()
+{
+    thread_local std::vector<rocblas_handle> handles;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+    if ((int)handles.size() <= dev) handles.resize(dev + 1, nullptr);
+    if (!handles[dev] && rocblas_create_handle(&handles[dev]) != rocblas_status_success) handles[dev] = nullptr;
+    return handles[dev];
+}
 
 hfk_status say(Ctx &c, hfk_status s, const char *what)
 {
@@ -321,7 +331,8 @@ hfk_status run_scf(const Layout &L, const Basis &b, char *ws, const ScfLayout &S
     c.msg = msg;
     c.msglen = msglen;
     const int64_t n = L.n, n2 = n * n;
-    if (rocblas_create_handle(&c.h) != rocblas_status_success) return say(c, HFK_EHIP, "rocblas_create_handle failed");
+    c.h = thread_handle();
+    if (!c.h) return say(c, HFK_EHIP, "rocblas_create_handle failed");
     if (rocblas_set_stream(c.h, st) != rocblas_status_success) return say(c, HFK_EHIP, "rocblas_set_stream failed");
     (void)rocblas_set_pointer_mode(c.h, rocblas_pointer_mode_host);
     {
