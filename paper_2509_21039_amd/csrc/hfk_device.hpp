@@ -122,21 +122,22 @@ __device__ inline unsigned boys_row(R r2, R rsh, R &d)
     return __umul24(k, (unsigned)(kRowLen * sizeof(R)));
 }
 
-// The row's Taylor polynomial at d (Horner).  FP32 rows are 16 bytes on 16-byte boundaries:
-// one LDS read.
+// The row's polynomial at d (Horner).  FP64 rows are 48 bytes and FP32 rows 16 bytes, on
+// 16-byte boundaries: three LDS reads and one.
 template <typename R>
 __device__ inline R boys_eval(const R *__restrict__ tab, unsigned off, R d)
 {
     const R *c = (const R *)((const char *)tab + off);
     if constexpr (sizeof(R) == 8) {
-        static_assert(BoysGrid<double>::order == 7, "degree-6 rows");
-        R v = c[6];
-        v = v * d + c[5];
-        v = v * d + c[4];
-        v = v * d + c[3];
-        v = v * d + c[2];
-        v = v * d + c[1];
-        v = v * d + c[0];
+        // degree-5 rows of 48 bytes on 16-byte boundaries: three LDS reads
+        static_assert(BoysGrid<double>::order == 6 && BoysGrid<double>::stride == 6, "degree-5 rows");
+        const double2 c01 = ((const double2 *)c)[0], c23 = ((const double2 *)c)[1], c45 = ((const double2 *)c)[2];
+        R v = c45.y;
+        v = v * d + c45.x;
+        v = v * d + c23.y;
+        v = v * d + c23.x;
+        v = v * d + c01.y;
+        v = v * d + c01.x;
         return v;
     } else {
         static_assert(BoysGrid<float>::order == 4 && BoysGrid<float>::stride == 4, "degree-3 rows of 16 bytes");

@@ -24,17 +24,20 @@ constexpr int kCellBits = 4;
 constexpr int kNumCells = 1 << (3 * kCellBits);
 constexpr int kNumBuckets = kNumBands * kNumCells;
 
-// Boys function table: F0 Taylor expansion about T_k = k h, k = 0 .. kBoysGrid-1.
-// Coefficient n of row k is (2/sqrt(pi)) (-1)^n F_n(T_k) / n!, so that
-// H(T) = erf(sqrt T)/sqrt T = sum_n c_n (T - T_k)^n near T_k.  A second table holds the
-// expansion of g(T) = -(4/sqrt(pi)) F1(T) for the gradient.
-constexpr int kBoysOrder = 7;          // coefficients used (degree 6)
-constexpr int kBoysStride = 7;         // row length: odd in doubles, so rows start on 16 different LDS bank pairs
-constexpr double kBoysH = 0.125;       // grid spacing
-constexpr double kBoysInvH = 8.0;
+// Boys function table of H(T) = erf(sqrt T)/sqrt T = (2/sqrt(pi)) F0(T) about T_k = k h,
+// k = 0 .. kBoysGrid-1: row k holds c_n with H(T) ~ sum_n c_n (T - T_k)^n for |T - T_k| <= h/2.
+// FP64 rows are of degree 5, the Chebyshev economisation of the degree-7 Taylor row (whose
+// coefficients are (2/sqrt(pi)) (-1)^n F_n(T_k) / n!): on the interval the dropped degree-6
+// and degree-7 terms are replaced by their lower-degree Chebyshev parts, which leaves an
+// error near 2e-14 where the degree-5 Taylor row would leave 5e-13.  Six coefficients are 48
+// bytes, three 16-byte LDS reads.
+constexpr int kBoysOrder = 6;          // coefficients used (degree 5)
+constexpr int kBoysStride = 6;         // row length (48 bytes: 16-byte aligned rows)
+constexpr double kBoysH = 1.0 / 12.0;  // grid spacing
+constexpr double kBoysInvH = 12.0;
 constexpr double kTswitch = 32.0;      // above this H(T) = T^(-1/2) to < 1e-15 relative
-constexpr double kSqrtSwitchInvH = 16.0;   // sqrt(kTswitch / h)
-constexpr int kBoysGrid = 264;         // covers [0, 33)
+constexpr double kSqrtSwitchInvH = 19.595917942265423;   // sqrt(kTswitch / h) = sqrt(384)
+constexpr int kBoysGrid = 393;         // covers [0, 32.75): rows up to kTswitch / h plus the guard
 // The FP32 paths use a finer grid with a shorter expansion: degree 3 at h = 1/16 leaves a
 // Taylor remainder below 1e-8 relative (under FP32 rounding), and a row of four
 // coefficients is one 16-byte LDS read.  The rows are computed in FP64 and rounded once.

@@ -104,13 +104,13 @@ __global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ b
     }
 }
 
-// Boys tables.  Row k of `tab` holds (2/sqrt(pi)) (-1)^m F_m(k h) / m!, m = 0..kBoysOrder-1
-// (Taylor coefficients of H(T) = erf(sqrt T)/sqrt T about T_k); row k of `tg` holds the same
-// to degree 7 (kBoysOrderG coefficients, rows of kBoysStrideG: the FP64 gradient kernels take
-// g(T) = -(4/sqrt(pi)) F1(T) = 2 H'(T) from its derivative).  On the FP32 grid (spacing
-// kBoysHF, kBoysOrderF coefficients, still in FP64) `tab_f` holds H's rows and `tg_f` g's,
-// -(4/sqrt(pi)) (-1)^m F_{m+1}(k h) / m!.  F_m comes from its positive Kummer series (no
-// cancellation).
+// Boys tables.  Row k of `tg` holds (2/sqrt(pi)) (-1)^m F_m(k h) / m!, m = 0..7 (Taylor
+// coefficients of H(T) = erf(sqrt T)/sqrt T about T_k, rows of kBoysStrideG: the FP64 gradient
+// kernels take g(T) = -(4/sqrt(pi)) F1(T) = 2 H'(T) from its derivative); row k of `tab` is its
+// degree-5 Chebyshev economisation on [T_k - h/2, T_k + h/2] (the forward kernels' rows).  On
+// the FP32 grid (spacing kBoysHF, kBoysOrderF coefficients, still in FP64) `tab_f` holds H's
+// Taylor rows and `tg_f` g's, -(4/sqrt(pi)) (-1)^m F_{m+1}(k h) / m!.  F_m comes from its
+// positive Kummer series (no cancellation).
 __device__ inline void boys_rows(double T, int order, int stride, double *v, double *w)
 {
     double fm[kBoysOrderG + 1];
@@ -141,8 +141,29 @@ __global__ void k_boys_table(double *__restrict__ tab, double *__restrict__ tab_
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < kBoysGrid) {
-        boys_rows(k * kBoysH, kBoysOrder, kBoysStride, tab + k * kBoysStride, nullptr);
-        boys_rows(k * kBoysH, kBoysOrderG, kBoysStrideG, tg + k * kBoysStrideG, nullptr);
+        double *t7 = tg + k * kBoysStrideG;
+        boys_rows(k * kBoysH, kBoysOrderG, kBoysStrideG, t7, nullptr);
+        // economise to degree 5 in u = (T - T_k) / r, r = h/2 (b_m = c_m r^m): drop T7(u)/64
+        // and T6(u)/32 from the expansion, keeping the lower-degree parts of u^7 and u^6
+        //   u^7 = (T7 + 112 u^5 - 56 u^3 + 7 u) / 64,   u^6 = (T6 + 48 u^4 - 18 u^2 + 1) / 32
+        static_assert(kBoysOrder == 6 && kBoysOrderG == 8, "degree-7 rows economised to degree 5");
+        const double r = 0.5 * kBoysH;
+        double b[8], rm = 1.0;
+        for (int m = 0; m < 8; ++m) {
+            b[m] = t7[m] * rm;
+            rm *= r;
+        }
+        b[5] += b[7] * (112.0 / 64.0);
+        b[3] -= b[7] * (56.0 / 64.0);
+        b[1] += b[7] * (7.0 / 64.0);
+        b[4] += b[6] * (48.0 / 32.0);
+        b[2] -= b[6] * (18.0 / 32.0);
+        b[0] += b[6] * (1.0 / 32.0);
+        rm = 1.0;
+        for (int m = 0; m < kBoysStride; ++m) {
+            tab[k * kBoysStride + m] = b[m] / rm;
+            rm *= r;
+        }
     }
     if (k < kBoysGridF)
         boys_rows(k * kBoysHF, kBoysOrderF, kBoysStrideF, tab_f + k * kBoysStrideF, tg_f + k * kBoysStrideF);
