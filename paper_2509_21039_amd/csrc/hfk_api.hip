@@ -204,7 +204,7 @@ static Basis make_basis(int32_t ngauss, const double *exps, const double *coefs)
 
 // n above which rows i and j of F no longer fit in one workgroup's LDS next to the Boys table
 constexpr int64_t kMaxAtoms = 6144;
-// n above which the gradient kernel's LDS copy of dE2/dR (n x 3) and its two tables no longer fit
+// n above which the gradient kernel's LDS copy of dE2/dR (n x 3) and its Boys tables no longer fit
 constexpr int64_t kMaxGradAtoms = 4096;
 constexpr int kGradGroupsPerCU = 4;
 constexpr int kDefaultKetCopies = 8;   // untuned default: shared ket-side Coulomb vectors
