@@ -293,24 +293,26 @@ void k_grad(GradArgs a)
                         }
                         const R px = b[0], py = b[1], pz = b[2], sab = b[3];
                         R U = R(0), Y = R(0), X0 = R(0), X1 = R(0), Xc = R(0), Xcd = R(0);
+                        // every lane's separation and far-field E, W first (independent across
+                        // d, so their reciprocal square roots overlap), then the near lanes
+                        // overwrite theirs from the table under exec masks
+                        R r2[G], E[G], W[G];
 #pragma unroll
                         for (int d = 0; d < G; ++d) {
-                            R r2;
                             if (kExpand) {
-                                // |P|^2 + |Q|^2 - 2 P.Q with the bra's -2P and |P|^2 (as the forward)
-                                r2 = fma(b[4], kx[d], fma(b[5], ky[d], fma(b[6], kz[d], kq[d] + b[7])));
+                                r2[d] = fma(b[4], kx[d], fma(b[5], ky[d], fma(b[6], kz[d], kq[d] + b[7])));
                             } else {
                                 const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
-                                r2 = dx * dx + dy * dy + dz * dz;
+                                r2[d] = dx * dx + dy * dy + dz * dz;
                             }
-                            // switch radius^2 kTswitch / rho (per-atom bases: sum of the stored halves)
+                            const R y = GradScale<R>::e_far(r2[d]);
+                            E[d] = y;
+                            W[d] = GradScale<R>::w_far(y);
+                        }
+#pragma unroll
+                        for (int d = 0; d < G; ++d) {
                             const R sw = kAtoms ? bsw + kp[d] : u[4 * d];
-                            // lanes below the switch radius take the table, the others the
-                            // far field, under exec masks (a wave with no near lane skips
-                            // the table part)
-                            R E, W;
-                            if (r2 < sw) {
-                                // (rho/h, sqrt(rho/h), (rho/h)^(3/2)): from the table, or from sw
+                            if (r2[d] < sw) {
                                 R q1, q2, q3;
                                 if constexpr (kAtoms) {
                                     q2 = rsqrt_r(sw) * R(BG::sqrt_sw_inv_h);
@@ -321,35 +323,29 @@ void k_grad(GradArgs a)
                                     q2 = u[4 * d + 2];
                                     q3 = u[4 * d + 3];
                                 }
-                                // sqrt(h) H and h^(3/2) g at T' = T / h on the table grid
                                 R dd;
-                                const unsigned off = boys_row<R, BG::pair_stride>(r2, q1, dd);
+                                const unsigned off = boys_row<R, BG::pair_stride>(r2[d], q1, dd);
                                 if constexpr (sizeof(R) == 8) {
-                                    // g = 2 H': W on the grid is (2 kW / kE) times dE/dd
                                     double de;
-                                    E = q2 * boys_eval_d(tHG, off, dd, de);
-                                    W = q3 * (R(2.0 * GradScale<R>::kW / GradScale<R>::kE) * de);
+                                    E[d] = q2 * boys_eval_d(tHG, off, dd, de);
+                                    W[d] = q3 * (R(2.0 * GradScale<R>::kW / GradScale<R>::kE) * de);
                                 } else {
-                                    E = q2 * boys_eval<R>(tHG, off, dd);
-                                    W = q3 * boys_eval<R>(tHG + BG::g_off, off, dd);
+                                    E[d] = q2 * boys_eval<R>(tHG, off, dd);
+                                    W[d] = q3 * boys_eval<R>(tHG + BG::g_off, off, dd);
                                 }
-                            } else {
-                                const R y = GradScale<R>::e_far(r2);
-                                E = y;
-                                W = GradScale<R>::w_far(y);
                             }
+                        }
+#pragma unroll
+                        for (int d = 0; d < G; ++d) {
                             if constexpr (kAtoms) {
-                                U = fma(ks[d], E, U);
-                                Y = fma(kms[d], E, Y);
-                                X0 = fma(ks[d], W, X0);
-                                X1 = fma(kds[d], W, X1);
-                                Xc = fma(kcs[d], W, Xc);
-                                Xcd = fma(kcds[d], W, Xcd);
+                                U = fma(ks[d], E[d], U);
+                                Y = fma(kms[d], E[d], Y);
+                                X0 = fma(ks[d], W[d], X0);
+                                X1 = fma(kds[d], W[d], X1);
+                                Xc = fma(kcs[d], W[d], Xc);
+                                Xcd = fma(kcds[d], W[d], Xcd);
                             } else {
-                                // one basis: the ket fractions are uniform scalars, so the lane
-                                // keeps only S_cd and weights S_cd E and S_cd W by them here
-                                // (two more operations, 24 fewer registers per lane)
-                                const R T = ks[d] * E, V = ks[d] * W;
+                                const R T = ks[d] * E[d], V = ks[d] * W[d];
                                 U += T;
                                 Y = fma(kw[4 * d], T, Y);
                                 X0 += V;
