@@ -544,16 +544,23 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
                 }
                 const R px = b[0], py = b[1], pz = b[2];
                 R U = R(0), Y = R(0), X0 = R(0), X1 = R(0), Xc = R(0), Xcd = R(0);
+                // every lane's separation and far-field E, W first (independent across d, so
+                // their reciprocal square roots overlap), then the near lanes overwrite theirs
+                // from the table under exec masks
+                R r2[G], E[G], W[G];
 #pragma unroll
                 for (int d = 0; d < G; ++d) {
                     const R dx = px - kx[d], dy = py - ky[d], dz = pz - kz[d];
-                    const R r2 = dx * dx + dy * dy + dz * dz;
+                    r2[d] = dx * dx + dy * dy + dz * dz;
+                    const R y = GradScale<R>::e_far(r2[d]);
+                    E[d] = y;
+                    W[d] = kGrad ? GradScale<R>::w_far(y) : R(0);
+                }
+#pragma unroll
+                for (int d = 0; d < G; ++d) {
                     // switch radius^2 kTswitch / rho (per-atom bases: sum of the stored halves)
                     const R sw = kAtoms ? bsw + kp[d] : u[4 * d];
-                    // lanes below the switch radius take the table, the others the far
-                    // field, under exec masks (a wave with no near lane skips the table part)
-                    R E, W = R(0);
-                    if (r2 < sw) {
+                    if (r2[d] < sw) {
                         // (rho/h, sqrt(rho/h), (rho/h)^(3/2)) from the table, or from sw
                         R q1, q2, q3;
                         if constexpr (kAtoms) {
@@ -567,28 +574,27 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
                         }
                         // sqrt(h) H and h^(3/2) g at T' = T / h on the table grid
                         R dd;
-                        const unsigned off = boys_row<R, BG::pair_stride>(r2, q1, dd);
+                        const unsigned off = boys_row<R, BG::pair_stride>(r2[d], q1, dd);
                         if constexpr (sizeof(R) == 8) {
                             // degree-7 rows of H; g = 2 H': W on the grid is (2 kW / kE) dE/dd
                             double de;
-                            E = q2 * boys_eval_d(tHG, off, dd, de);
-                            if (kGrad) W = q3 * (R(2.0 * GradScale<R>::kW / GradScale<R>::kE) * de);
+                            E[d] = q2 * boys_eval_d(tHG, off, dd, de);
+                            if (kGrad) W[d] = q3 * (R(2.0 * GradScale<R>::kW / GradScale<R>::kE) * de);
                         } else {
-                            E = q2 * boys_eval<R>(tHG, off, dd);
-                            if (kGrad) W = q3 * boys_eval<R>(tHG + BG::g_off, off, dd);
+                            E[d] = q2 * boys_eval<R>(tHG, off, dd);
+                            if (kGrad) W[d] = q3 * boys_eval<R>(tHG + BG::g_off, off, dd);
                         }
-                    } else {
-                        const R y = GradScale<R>::e_far(r2);
-                        E = y;
-                        if (kGrad) W = GradScale<R>::w_far(y);
                     }
-                    U = fma(ks[d], E, U);
+                }
+#pragma unroll
+                for (int d = 0; d < G; ++d) {
+                    U = fma(ks[d], E[d], U);
                     if (kGrad) {
-                        Y = fma(kms[d], E, Y);
-                        X0 = fma(ks[d], W, X0);
-                        X1 = fma(kds[d], W, X1);
-                        Xc = fma(kcs[d], W, Xc);
-                        Xcd = fma(kcds[d], W, Xcd);
+                        Y = fma(kms[d], E[d], Y);
+                        X0 = fma(ks[d], W[d], X0);
+                        X1 = fma(kds[d], W[d], X1);
+                        Xc = fma(kcs[d], W[d], Xc);
+                        Xcd = fma(kcds[d], W[d], Xcd);
                     }
                 }
                 eri = fma(b[3], U, eri);
