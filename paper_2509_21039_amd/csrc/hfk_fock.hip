@@ -82,12 +82,16 @@ template <> struct Prec<double> {
     static __device__ double rsqrt(double x) { return rsqrt_fp64(x); }
     // The hybrid kernel's FP64 accumulator carries -2 times the sum, which lets the Newton
     // step of the reciprocal square root fold into the product: with the hardware estimate
-    // y, y1 = y (3 - x y^2) / 2 and -2 s y1 = (s y) (x y^2 - 3): four operations after rsq.
+    // y, y1 = y (3 - x y^2) / 2 and -2 s y1 = (s y) (x y^2 - 3).  The far-field term of a
+    // primitive quartet is returned as the two factors a = s y and b = x y^2 - 3 (three
+    // operations after rsq; the accumulating FMA makes four), so that near lanes can replace
+    // both before the one FMA that adds the term.
     static constexpr double kAccScale = -2.0;
-    static __device__ double far_acc(double acc, double s, double x)
+    static __device__ void far_split(double s, double x, double &a, double &b)
     {
         const double y = __builtin_amdgcn_rsq(x);
-        return fma(s * y, fma(x, y * y, -3.0), acc);
+        a = s * y;
+        b = fma(x, y * y, -3.0);
     }
 };
 template <> struct Prec<float> {
@@ -102,12 +106,12 @@ template <> struct Prec<float> {
     static __device__ const float *rsn(const BasisDev *bd) { return bd->rsn_f; }
     static __device__ float rsqrt(float x) { return rsqrt_fp32(x); }
     static constexpr float kAccScale = 1.0f;   // no Newton step in FP32
-    static __device__ float far_acc(float acc, float s, float x) { return fmaf(s, rsqrt_fp32(x), acc); }
+    static __device__ void far_split(float s, float x, float &a, float &b) { a = s; b = rsqrt_fp32(x); }
 };
 
-// Taylor expansion of the table row nearest to T (T below the switch, so the row exists).
+// Polynomial of the table row nearest to T (T below the switch, so the row exists).
 template <typename R>
-__device__ inline R boys_taylor(R T, const R *__restrict__ tab)
+__device__ inline R boys_nearest_row(R T, const R *__restrict__ tab)
 {
     using BG = BoysGrid<R>;
     const int k = (int)(T * R(BG::inv_h) + R(0.5));
@@ -119,14 +123,14 @@ __device__ inline R boys_taylor(R T, const R *__restrict__ tab)
     return v;
 }
 
-// H(T) = erf(sqrt T)/sqrt T: Taylor row below the switch, T^(-1/2) above it (both
+// H(T) = erf(sqrt T)/sqrt T: table row below the switch, T^(-1/2) above it (both
 // evaluated, one selected).
 template <typename R>
 __device__ inline R boys_h(R T, const R *__restrict__ tab)
 {
     const R far = Prec<R>::rsqrt(fmax(T, R(1e-30)));
     const R Tc = fmin(T, R(kTswitch + 0.5));
-    const R v = boys_taylor<R>(Tc, tab);
+    const R v = boys_nearest_row<R>(Tc, tab);
     return T < R(kTswitch) ? v : far;
 }
 
@@ -179,11 +183,14 @@ __device__ inline R boys_near(R r2, R rsh, const R *__restrict__ tab)
     return boys_eval<R>(tab, off, d);
 }
 
-// Contracted (bra | ket) with a near/far branch per primitive quartet under exec masks:
-// lanes with |P-Q|^2 beyond the switch radius add the far-field value S_cd / |P-Q| (exact
-// there), the others S_cd sqrt(rho/h) * sqrt(h) H(T) from the grid table; a wave with no
-// near lane (the common case once kets are spatially sorted) skips the table part, and only
-// near lanes read the table from LDS.  Lanes without a kept quartet point at a pad entry
+// Contracted (bra | ket), far field first: for one bra primitive pair a lane forms |P-Q|^2
+// of its G ket primitive pairs and their far-field terms S_cd / |P-Q| (exact beyond the
+// switch radius; the G reciprocal square roots issue back to back); then, under exec masks,
+// lanes below the switch radius replace a term by S_cd sqrt(rho/h) * sqrt(h) H(T) from the
+// grid table (a wave with no near lane, the common case once kets are spatially sorted, skips
+// the table part, and only near lanes read the table from LDS); the terms are added last, in
+// one branch-free run of FMAs.  Far values of near lanes (|P-Q|^2 may be zero or round
+// below it) are discarded, never added.  Lanes without a kept quartet point at a pad entry
 // (centres 1e6 bohr away, zero weight), so they are never near and add nothing.  Uniform data come through scalar loads issued together
 // at the top of each bra primitive: (Px, Py, Pz, S, -2Px, -2Py, -2Pz, |P|^2) and, per
 // primitive quartet, (switch radius^2, rho/h, sqrt(rho/h)).
@@ -250,23 +257,28 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
             if constexpr (kAtoms) {
                 const R bi = bip[ab];
                 asm volatile("" ::"s"(bi));
+                R r2[G], fa[G], fb[G];
 #pragma unroll
                 for (int d = 0; d < G; ++d) {
-                    R r2;
                     if (kExpand) {
-                        r2 = fma(b[4], kx[cur][d], fma(b[5], ky[cur][d], fma(b[6], kz[cur][d], kq[cur][d] + b[7])));
+                        r2[d] = fma(b[4], kx[cur][d], fma(b[5], ky[cur][d], fma(b[6], kz[cur][d], kq[cur][d] + b[7])));
                     } else {
                         const R dx = b[0] - kx[cur][d], dy = b[1] - ky[cur][d], dz = b[2] - kz[cur][d];
-                        r2 = dx * dx + dy * dy + dz * dz;
+                        r2[d] = dx * dx + dy * dy + dz * dz;
                     }
+                    Prec<R>::far_split(ks[cur][d], r2[d], fa[d], fb[d]);
+                }
+#pragma unroll
+                for (int d = 0; d < G; ++d) {
                     const R sw = bi + kp[cur][d];   // kTswitch / rho
-                    if (r2 < sw) {
+                    if (r2[d] < sw) {
                         const R y = rsqrt_r(sw) * R(BoysGrid<R>::sqrt_sw_inv_h);   // sqrt(rho / h)
-                        acc = fma(ks[cur][d] * y, boys_near<R>(r2, y * y, tab), acc);
-                    } else {
-                        acc = Prec<R>::far_acc(acc, ks[cur][d], r2);
+                        fa[d] = ks[cur][d] * y;
+                        fb[d] = boys_near<R>(r2[d], y * y, tab);
                     }
                 }
+#pragma unroll
+                for (int d = 0; d < G; ++d) acc = fma(fa[d], fb[d], acc);
             } else {
                 const cptr<R> up = rsn + 3 * (ab * G2 + cb * G);
                 R u[3 * G];
@@ -275,21 +287,26 @@ __device__ inline R quartet_eri_hybrid(cptr<R> bra, const R *__restrict__ prim, 
                 // keep every uniform load in one batch at the top (not sunk into the branches)
 #pragma unroll
                 for (int c = 0; c < 3 * G; ++c) asm volatile("" ::"s"(u[c]));
+                R r2[G], fa[G], fb[G];
 #pragma unroll
                 for (int d = 0; d < G; ++d) {
-                    R r2;
                     if (kExpand) {
-                        r2 = fma(b[4], kx[cur][d], fma(b[5], ky[cur][d], fma(b[6], kz[cur][d], kq[cur][d] + b[7])));
+                        r2[d] = fma(b[4], kx[cur][d], fma(b[5], ky[cur][d], fma(b[6], kz[cur][d], kq[cur][d] + b[7])));
                     } else {
                         const R dx = b[0] - kx[cur][d], dy = b[1] - ky[cur][d], dz = b[2] - kz[cur][d];
-                        r2 = dx * dx + dy * dy + dz * dz;
+                        r2[d] = dx * dx + dy * dy + dz * dz;
                     }
-                    if (r2 < u[3 * d]) {
-                        acc = fma(ks[cur][d] * u[3 * d + 2], boys_near<R>(r2, u[3 * d + 1], tab), acc);
-                    } else {
-                        acc = Prec<R>::far_acc(acc, ks[cur][d], r2);
+                    Prec<R>::far_split(ks[cur][d], r2[d], fa[d], fb[d]);
+                }
+#pragma unroll
+                for (int d = 0; d < G; ++d) {
+                    if (r2[d] < u[3 * d]) {
+                        fa[d] = ks[cur][d] * u[3 * d + 2];
+                        fb[d] = boys_near<R>(r2[d], u[3 * d + 1], tab);
                     }
                 }
+#pragma unroll
+                for (int d = 0; d < G; ++d) acc = fma(fa[d], fb[d], acc);
             }
             eri += b[3] * acc;
         }
