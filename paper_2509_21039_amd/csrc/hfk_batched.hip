@@ -544,9 +544,9 @@ __global__ __launch_bounds__(kBatchMaxThreads) void k_batched(BArgs a)
                 }
                 const R px = b[0], py = b[1], pz = b[2];
                 R U = R(0), Y = R(0), X0 = R(0), X1 = R(0), Xc = R(0), Xcd = R(0);
-                // every lane's separation and far-field E, W first (independent across d, so
-                // their reciprocal square roots overlap), then the near lanes overwrite theirs
-                // from the table under exec masks
+                // every lane's separation and far-field E, W first (independent across d:
+                // their reciprocal square roots issue back to back), then the near lanes
+                // overwrite theirs from the table under exec masks
                 R r2[G], E[G], W[G];
 #pragma unroll
                 for (int d = 0; d < G; ++d) {

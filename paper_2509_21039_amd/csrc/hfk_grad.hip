@@ -294,7 +294,7 @@ void k_grad(GradArgs a)
                         const R px = b[0], py = b[1], pz = b[2], sab = b[3];
                         R U = R(0), Y = R(0), X0 = R(0), X1 = R(0), Xc = R(0), Xcd = R(0);
                         // every lane's separation and far-field E, W first (independent across
-                        // d, so their reciprocal square roots overlap), then the near lanes
+                        // d: their reciprocal square roots issue back to back), then the near lanes
                         // overwrite theirs from the table under exec masks
                         R r2[G], E[G], W[G];
 #pragma unroll
