@@ -97,29 +97,34 @@ template <> struct GradScale<float> {
 };
 
 // Table row of a lane below the switch radius, from r2 = |P-Q|^2 and rsh = rho/h:
-// T' = r2 rsh on the grid of this precision (below kTswitch / h for such a lane).  Adding the
-// rounding constant 1.5 2^52 (FP32: 1.5 2^23) in the FMA that forms T' rounds it to the
-// nearest row, whose index is then the low bits of the sum (no separate round and convert);
-// the index is still clamped to the table as a guard.  Returns the row's byte offset (rows of
-// kRowLen values) and d = T' - row from one more FMA.
+// T' = r2 rsh on the grid of this precision.  Adding the rounding constant 1.5 2^52 (FP32:
+// 1.5 2^23) in the FMA that forms T' rounds it to the nearest row, whose index is then read
+// off the sum's encoding (no separate round and convert).  Returns the row's byte offset (rows
+// of kRowLen values) and d = T' - row from one more FMA.
+// The row needs no clamp: a caller takes this branch only for r2 < sw, where the switch
+// radius^2 sw = kTswitch / rho and rsh come from the same rho (per-atom bases derive rsh
+// from sw itself), so T' < kTswitch / h up to a few roundings and the row is at most
+// kTswitch / h = 384 (FP32: 512), below the table's rows; r2 is a sum of squares, or in the
+// expanded FP64 form below zero by rounding only (~1e-12 bohr^2), so the row is at least 0.
 template <typename R, int kRowLen = BoysGrid<R>::stride>
 __device__ inline unsigned boys_row(R r2, R rsh, R &d)
 {
     using BG = BoysGrid<R>;
-    unsigned k;
+    constexpr unsigned kRowBytes = kRowLen * sizeof(R);
+    static_assert(BG::rows > kTswitch * BG::inv_h, "rows up to kTswitch / h");
     if constexpr (sizeof(R) == 8) {
         constexpr double kRound = 6755399441055744.0;   // 1.5 * 2^52
         const double sum = fma(r2, rsh, kRound);
         d = fma(r2, rsh, -(sum - kRound));
-        k = (unsigned)__double_as_longlong(sum);
+        // the low 32 bits of the sum's encoding are the row
+        return __umul24((unsigned)__double_as_longlong(sum), kRowBytes);
     } else {
         constexpr float kRound = 12582912.0f;           // 1.5 * 2^23
         const float sum = fmaf(r2, rsh, kRound);
         d = fmaf(r2, rsh, -(sum - kRound));
-        k = __float_as_uint(sum) & 0x3fffffu;
+        // the sum is 1.5 2^23 + row, whose encoding is 0x4B400000 + row
+        return (__float_as_uint(sum) - 0x4B400000u) * kRowBytes;
     }
-    k = min(k, (unsigned)(BG::rows - 8));
-    return __umul24(k, (unsigned)(kRowLen * sizeof(R)));
 }
 
 // The row's polynomial at d (Horner).  FP64 rows are 48 bytes and FP32 rows 16 bytes, on

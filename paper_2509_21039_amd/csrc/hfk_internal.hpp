@@ -37,7 +37,7 @@ constexpr double kBoysH = 1.0 / 12.0;  // grid spacing
 constexpr double kBoysInvH = 12.0;
 constexpr double kTswitch = 32.0;      // above this H(T) = T^(-1/2) to < 1e-15 relative
 constexpr double kSqrtSwitchInvH = 19.595917942265423;   // sqrt(kTswitch / h) = sqrt(384)
-constexpr int kBoysGrid = 393;         // covers [0, 32.75): rows up to kTswitch / h plus the guard
+constexpr int kBoysGrid = 393;         // covers [0, 32.75): rows up to kTswitch / h and 8 more
 // The FP32 paths use a finer grid with a shorter expansion: degree 3 at h = 1/16 leaves a
 // Taylor remainder below 1e-8 relative (under FP32 rounding), and a row of four
 // coefficients is one 16-byte LDS read.  The rows are computed in FP64 and rounded once.
