@@ -401,6 +401,8 @@ def main():
     ap.add_argument("--probe-shape", default="",
                     help="launch shape of the traffic probe: gpc,tile_items,group_bras,ket_copies "
                          "(default: the untuned default)")
+    ap.add_argument("--probe-mixed", action="store_true",
+                    help="the traffic probe on the 1024-atom lattice in mixed precision instead of he512 FP64")
     ap.add_argument("--batched-probe", action="store_true",
                     help="one warm-up and one timed call of the 2000-cluster batch (mixed + gradient, default "
                          "configuration, no tuning) and one plain 512 MiB device copy, for counter runs")
@@ -435,7 +437,10 @@ def main():
         return run_probe(hfk, torch, dev, "batched" if args.batched_probe else "grad")
     if args.traffic_probe:
         # one build in a fixed configuration (hybrid kernel, default workgroups), then a copy
-        ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, g, "fp64"), dev)
+        prec = "mixed" if args.probe_mixed else "fp64"
+        if args.probe_mixed:
+            s = config_system("he1024_mixed")
+        ws = hfk.new_workspace(hfk.workspace_bytes(s.natoms, g, prec), dev)
         xyz_t = torch.tensor(s.xyz, device=dev)
         D_t = torch.tensor(s.dens, device=dev)
         if args.probe_shape:
@@ -444,11 +449,12 @@ def main():
             hfk.set_shape(tile, gbras, kcop)
         else:
             hfk.set_config(1, 0)
-        hfk.fock(xyz_t, D_t, s.exps, s.coefs, s.tau, strategy=args.probe_strategy, workspace=ws)
+        hfk.fock(xyz_t, D_t, s.exps, s.coefs, s.tau, precision=prec, strategy=args.probe_strategy, workspace=ws)
         torch.cuda.synchronize()
         st = hfk.read_stats(ws)
         nbytes = plain_copy(torch, dev)
-        print(json.dumps({"copy_bytes": nbytes, "strategy": st["strategy"], "variant": st["variant"],
+        print(json.dumps({"copy_bytes": nbytes, "precision": prec, "natoms": s.natoms, "quartets": st["quartets"],
+                          "strategy": st["strategy"], "variant": st["variant"],
                           "groups": st["groups"], "tile_items": st["tile_items"], "group_bras": st["group_bras"],
                           "ket_copies": st["ket_copies"], "source_sha256": kernel_source_hash()}), flush=True)
         return
