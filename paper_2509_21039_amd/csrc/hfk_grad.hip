@@ -436,14 +436,28 @@ void k_grad(GradArgs a)
 // d_xyz = g_e2 * sum over workgroups; E2 = sum of partials (fixed order); d_dens = g_e2 * G.
 // d_xyz = scale * sum of the workgroup partials; scale = g_e2[0], or 1 when g_e2 is NULL
 // (the two-density contraction already carries it).
+// Sum of the workgroups' gradient copies: a workgroup takes kRedOut consecutive outputs, each
+// in kRedSlices interleaved slices of the copies (coalesced rows, many loads in flight), and
+// adds the slices in a fixed order.
+constexpr int kRedOut = 16, kRedSlices = 16;
+static_assert(kRedOut * kRedSlices == 256, "one 256-thread workgroup");
 __global__ __launch_bounds__(256) void k_grad_reduce(const double *__restrict__ gpriv, int groups, int64_t m,
                                                      const double *__restrict__ g_e2, double *__restrict__ d_xyz)
 {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= m) return;
+    __shared__ double part[kRedSlices][kRedOut];
+    const int o = threadIdx.x % kRedOut, sl = threadIdx.x / kRedOut;
+    const int64_t x = (int64_t)blockIdx.x * kRedOut + o;
     double s = 0.0;
-    for (int gph = 0; gph < groups; ++gph) s += gpriv[(int64_t)gph * m + x];
-    d_xyz[x] = g_e2 ? g_e2[0] * s : s;
+    if (x < m) {
+        for (int gph = sl; gph < groups; gph += kRedSlices) s += gpriv[(int64_t)gph * m + x];
+    }
+    part[sl][o] = s;
+    __syncthreads();
+    if (sl == 0 && x < m) {
+        double t = part[0][o];
+        for (int k = 1; k < kRedSlices; ++k) t += part[k][o];
+        d_xyz[x] = g_e2 ? g_e2[0] * t : t;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_make_xw(int64_t n, const double *__restrict__ dens,
@@ -621,8 +635,8 @@ hipError_t launch_grad(const Layout &L, const Basis &b, char *ws, const double *
     }
     if (err != hipSuccess) return err;
     const int64_t m = 3 * L.n;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, a.gpriv, L.groups, m,
-                       xdens ? nullptr : g_e2, d_xyz);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((m + kRedOut - 1) / kRedOut)), dim3(256), 0, st, a.gpriv,
+                       L.groups, m, xdens ? nullptr : g_e2, d_xyz);
     if (e2_out) hipLaunchKernelGGL(k_grad_energy, dim3(1), dim3(256), 0, st, a.epart, L.groups, e2_out);
     if (d_dens) {
         const int64_t n2 = L.n * L.n;

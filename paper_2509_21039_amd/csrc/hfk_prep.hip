@@ -109,20 +109,25 @@ __global__ __launch_bounds__(256) void k_setup(Basis b, BasisDev *__restrict__ b
 // kernels take g(T) = -(4/sqrt(pi)) F1(T) = 2 H'(T) from its derivative); row k of `tab` is its
 // degree-5 Chebyshev economisation on [T_k - h/2, T_k + h/2] (the forward kernels' rows).  On
 // the FP32 grid (spacing kBoysHF, kBoysOrderF coefficients, still in FP64) `tab_f` holds H's
-// Taylor rows and `tg_f` g's, -(4/sqrt(pi)) (-1)^m F_{m+1}(k h) / m!.  F_m comes from its
-// positive Kummer series (no cancellation).
+// Taylor rows and `tg_f` g's, -(4/sqrt(pi)) (-1)^m F_{m+1}(k h) / m!.  The highest order
+// comes from its positive Kummer series (no cancellation), the lower ones from the downward
+// recursion F_m = (2T F_{m+1} + e^-T) / (2m + 1), which is stable in that direction (one
+// series per row instead of one per order: each term of a series is a division).
 __device__ inline void boys_rows(double T, int order, int stride, double *v, double *w)
 {
     double fm[kBoysOrderG + 1];
-    for (int m = 0; m <= order; ++m) {
+    const double et = exp(-T);
+    {
+        const int m = order;
         double term = 1.0 / (2.0 * m + 1.0), sum = term;
         for (int i = 1; i < 400; ++i) {
             term *= 2.0 * T / (2.0 * m + 2.0 * i + 1.0);
             sum += term;
             if (term < 1e-18 * sum) break;
         }
-        fm[m] = exp(-T) * sum;
+        fm[m] = et * sum;
     }
+    for (int m = order - 1; m >= 0; --m) fm[m] = (2.0 * T * fm[m + 1] + et) / (2.0 * m + 1.0);
     double fact = 1.0;
     for (int m = 0; m < stride; ++m) {
         v[m] = 0.0;
@@ -750,19 +755,28 @@ __global__ void k_fill_i64(long long *__restrict__ p, int64_t m)
 
 // Blocks of every bra group: 2^gshift x the largest block count of its bras (bras with
 // fewer blocks leave empty slots, skipped by the kernels).
-__global__ void k_group_blocks(const DevHeader *__restrict__ hdr, const long long *__restrict__ nitems,
-                               int64_t ngroups, int gshift, int tile, long long *__restrict__ gcnt)
+// One workgroup per group of bras: the largest block count of its bras (a block-wide max).
+__global__ __launch_bounds__(256) void k_group_blocks(const DevHeader *__restrict__ hdr,
+                                                      const long long *__restrict__ nitems, int64_t ngroups,
+                                                      int gshift, int tile, long long *__restrict__ gcnt)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ngroups) return;
+    __shared__ long long red[256];
+    const int64_t g = blockIdx.x;   // the grid is exactly ngroups workgroups
+    const int tid = threadIdx.x;
     const int64_t S = hdr->sig_pairs;
     const int64_t gb = (int64_t)1 << gshift;
     long long nb = 0;
-    for (int64_t s = g * gb; s < (g + 1) * gb && s < S; ++s) {
+    for (int64_t s = g * gb + tid; s < (g + 1) * gb && s < S; s += blockDim.x) {
         const long long b = (nitems[s] + tile - 1) / tile;
         nb = b > nb ? b : nb;
     }
-    gcnt[g] = nb * gb;
+    red[tid] = nb;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] = red[tid + w] > red[tid] ? red[tid + w] : red[tid];
+        __syncthreads();
+    }
+    if (tid == 0) gcnt[g] = red[0] * gb;
 }
 
 hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double *xyz, const double *dens,
@@ -815,7 +829,7 @@ hipError_t launch_pairs(const Layout &L, const Basis &b, char *ws, const double 
     e = launch_scan((const long long *)(ws + L.nitems), L.pcap, (long long *)(ws + L.item_off),
                     (long long *)(ws + L.scan_tmp), &hdr->items, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_group_blocks, dim3((unsigned)((L.ngroups + 255) / 256)), dim3(256), 0, st, hdr,
+    hipLaunchKernelGGL(k_group_blocks, dim3((unsigned)L.ngroups), dim3(256), 0, st, hdr,
                        (const long long *)(ws + L.nitems), L.ngroups, L.gshift, L.tile, (long long *)(ws + L.gcnt));
     return launch_scan((const long long *)(ws + L.gcnt), L.ngroups, (long long *)(ws + L.goff),
                        (long long *)(ws + L.scan_tmp), &hdr->blocks, st);
